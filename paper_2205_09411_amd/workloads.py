@@ -1,0 +1,203 @@
+"""Seeded synthetic workloads: geometry descriptions, right-hand sides and
+boundary data for the multigrid solver and for its FP64 CPU checker.
+
+This module holds inputs only.  It contains none of the solver's arithmetic
+(no stencils, no line search, no transfers): it turns seeds and closed-form
+fields into the arrays both sides are fed.  Every generator is deterministic
+(NumPy PCG64 ``default_rng``).
+
+Workload shapes follow the paper's test problems (Sec. 4) and the scaled
+workloads of this package:
+
+* ``mms2d``   2D unit square, circle r=0.25 at (0.5,0.5), manufactured
+              phi = sin(2 pi x) cos(3 pi y) + x^2, 8x8-cell blocks.
+* ``mms3d``   3D unit cube, sphere r=0.3 at the centre, manufactured
+              phi = exp(x) sin(pi y) cos(pi z), 16^3-cell blocks.
+* ``spheres`` 3D union of seeded spheres (centres U[0.2,0.8]^3, radii
+              U[0.03,0.1]), phi=1 on the spheres, 0 on the cube, g ~ N(0,1).
+* ``cylinder``3D cylinder r=0.2 along z through (0.5,0.5), phi=0 on it and on
+              the cube; right-hand sides are sums of seeded Gaussian sources.
+* ``sphere_f1`` the convergence test of Sec. 4.1: domain of unit size centred
+              at the origin, sphere of radius R, exact solutions of
+              eq. (solution-sphere) imposed on the domain boundary.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# level-set kinds understood by both the library and the checker
+LSF_NONE = 0
+LSF_SPHERES = 1      # union of spheres/circles: params [cx, cy, cz, r] * n
+LSF_CYLINDER_Z = 2   # infinite cylinder along z: params [cx, cy, r]
+
+REFINE_UNIFORM = 0
+REFINE_NEAR_INTERFACE = 1
+
+
+@dataclass
+class Geometry:
+    """Plain description of a block octree and its level set."""
+    dim: int
+    block_n: int
+    max_level: int
+    lsf_kind: int
+    lsf_params: np.ndarray
+    lo: tuple = (0.0, 0.0, 0.0)
+    refine_kind: int = REFINE_UNIFORM
+    refine_width: float = 0.0
+    eps_tol: float = 1e-8
+    mask_factor: float = 1.5
+    w_min: float = 0.0
+    coarse_n: int = 8
+    name: str = ""
+
+    @property
+    def lsf_n(self) -> int:
+        if self.lsf_kind == LSF_SPHERES:
+            return len(self.lsf_params) // 4
+        if self.lsf_kind == LSF_CYLINDER_Z:
+            return 1
+        return 0
+
+    def finest_cells_per_dim(self) -> int:
+        return self.block_n * (1 << (self.max_level - 1))
+
+
+@dataclass
+class Workload:
+    geom: Geometry
+    rhs: callable            # xyz[n,3] -> g[n]
+    iface_value: callable    # xyz[n,3] -> phi_b[n]
+    domain_value: callable   # xyz[n,3] -> phi_b[n]
+    exact: callable = None   # xyz[n,3] -> phi[n] (closed form), if any
+    notes: str = ""
+    extra: dict = field(default_factory=dict)
+
+
+# ---------------------------------------------------------------- closed forms
+def _mms2d_phi(x):
+    return np.sin(2 * np.pi * x[:, 0]) * np.cos(3 * np.pi * x[:, 1]) + x[:, 0] ** 2
+
+
+def _mms2d_g(x):
+    # Laplacian of _mms2d_phi, written out analytically
+    return (-13.0 * np.pi ** 2 * np.sin(2 * np.pi * x[:, 0]) * np.cos(3 * np.pi * x[:, 1])
+            + 2.0)
+
+
+def _mms3d_phi(x):
+    return np.exp(x[:, 0]) * np.sin(np.pi * x[:, 1]) * np.cos(np.pi * x[:, 2])
+
+
+def _mms3d_g(x):
+    return (1.0 - 2.0 * np.pi ** 2) * _mms3d_phi(x)
+
+
+def mms2d(max_level: int = 4, block_n: int = 8, w_min: float = 4e-3) -> Workload:
+    """2D manufactured problem: 64^2 cells (max_level 4) in 8^2 blocks."""
+    g = Geometry(dim=2, block_n=block_n, max_level=max_level, lsf_kind=LSF_SPHERES,
+                 lsf_params=np.array([0.5, 0.5, 0.0, 0.25]), w_min=w_min,
+                 name=f"mms2d_{block_n * (1 << (max_level - 1))}")
+    return Workload(g, _mms2d_g, _mms2d_phi, _mms2d_phi, exact=_mms2d_phi)
+
+
+def mms3d(max_level: int = 5, block_n: int = 16, w_min: float = 8e-3) -> Workload:
+    """3D manufactured problem: 256^3 cells (max_level 5) in 16^3 blocks."""
+    g = Geometry(dim=3, block_n=block_n, max_level=max_level, lsf_kind=LSF_SPHERES,
+                 lsf_params=np.array([0.5, 0.5, 0.5, 0.3]), w_min=w_min,
+                 name=f"mms3d_{block_n * (1 << (max_level - 1))}")
+    return Workload(g, _mms3d_g, _mms3d_phi, _mms3d_phi, exact=_mms3d_phi)
+
+
+def sphere_params(n: int, seed: int) -> np.ndarray:
+    """n spheres, centres U[0.2,0.8]^3, radii U[0.03,0.1] (seeded)."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.2, 0.8, size=(n, 3))
+    r = rng.uniform(0.03, 0.1, size=(n, 1))
+    return np.concatenate([c, r], axis=1).reshape(-1)
+
+
+def spheres(n_spheres: int = 20, max_level: int = 6, block_n: int = 16, seed: int = 3,
+            g_seed: int = 31, adaptive: bool = True, refine_width: float = 2.0 + math.sqrt(3) / 2,
+            w_min: float = 8e-3) -> Workload:
+    """Union of seeded spheres; phi=1 on the spheres, 0 on the cube; g ~ N(0,1)."""
+    geom = Geometry(dim=3, block_n=block_n, max_level=max_level, lsf_kind=LSF_SPHERES,
+                    lsf_params=sphere_params(n_spheres, seed),
+                    refine_kind=REFINE_NEAR_INTERFACE if adaptive else REFINE_UNIFORM,
+                    refine_width=refine_width, w_min=w_min,
+                    name=f"spheres{n_spheres}_L{max_level}_{'amr' if adaptive else 'uni'}")
+
+    def rhs(x, _seed=g_seed):
+        return np.random.default_rng(_seed).standard_normal(x.shape[0])
+
+    return Workload(geom, rhs, lambda x: np.ones(x.shape[0]), lambda x: np.zeros(x.shape[0]))
+
+
+def gaussian_sources(x: np.ndarray, seed: int, n_src: int = 8) -> np.ndarray:
+    """Sum of n_src Gaussians: amplitude U[-1,1], width U[0.02,0.05],
+    centres U[0.1,0.9]^3, g = sum A exp(-|x-c|^2 / (2 w^2))."""
+    rng = np.random.default_rng(seed)
+    amp = rng.uniform(-1.0, 1.0, n_src)
+    wid = rng.uniform(0.02, 0.05, n_src)
+    cen = rng.uniform(0.1, 0.9, size=(n_src, 3))
+    out = np.zeros(x.shape[0])
+    for a, w, c in zip(amp, wid, cen):
+        d2 = ((x[:, :3] - c) ** 2).sum(axis=1)
+        out += a * np.exp(-d2 / (2.0 * w * w))
+    return out
+
+
+def cylinder(max_level: int = 4, block_n: int = 16, n_rhs: int = 64, seed0: int = 400,
+             w_min: float = 8e-3) -> Workload:
+    """Cylinder r=0.2 along z through (0.5,0.5); phi=0 on it and on the cube;
+    n_rhs right-hand sides of 8 Gaussian sources each (seeds seed0+i)."""
+    geom = Geometry(dim=3, block_n=block_n, max_level=max_level, lsf_kind=LSF_CYLINDER_Z,
+                    lsf_params=np.array([0.5, 0.5, 0.2]), w_min=w_min,
+                    name=f"cylinder_{block_n * (1 << (max_level - 1))}")
+
+    def rhs(x, i=0):
+        return gaussian_sources(x, seed0 + i)
+
+    z = lambda x: np.zeros(x.shape[0])
+    return Workload(geom, rhs, z, z, extra={"n_rhs": n_rhs, "seed0": seed0})
+
+
+def sphere_f1(dim: int = 3, max_level: int = 4, R: float = 0.25, block_n: int = 8,
+              phi_b: float = 0.0, a: float = 1.0) -> Workload:
+    """Sec. 4.1 convergence test: Laplace equation, f = |x| - R on a domain of
+    unit size centred at the origin; the exact solution of eq.
+    (solution-sphere) is imposed on the domain boundary, phi_b on the sphere."""
+    geom = Geometry(dim=dim, block_n=block_n, max_level=max_level, lsf_kind=LSF_SPHERES,
+                    lsf_params=np.array([0.0, 0.0, 0.0, R]), lo=(-0.5, -0.5, -0.5),
+                    w_min=4e-3 if dim == 2 else 8e-3,
+                    name=f"sphere_f1_{dim}d_{block_n * (1 << (max_level - 1))}")
+
+    def exact(x):
+        r = np.sqrt((x[:, :dim] ** 2).sum(axis=1))
+        if dim == 2:
+            return phi_b + a * np.log(r / R)
+        return phi_b + a * (1.0 - R / r)
+
+    return Workload(geom, lambda x: np.zeros(x.shape[0]), lambda x: np.full(x.shape[0], phi_b),
+                    exact, exact=exact)
+
+
+def serving_geometries(seed0: int = 500, counts=(1, 5, 10, 20)):
+    """The four pre-built level sets of the serving stream: unions of
+    {1, 5, 10, 20} seeded spheres."""
+    return [sphere_params(n, seed0 + i) for i, n in enumerate(counts)]
+
+
+def serving_stream(n_requests: int, rate_hz: float, seed: int = 510):
+    """Poisson arrivals at a fixed rate: (arrival_time_s, size_level, geom_id,
+    rhs_seed) per request; sizes uniform over 64^3, 128^3, 256^3 (max_level
+    3, 4, 5 with 16^3 blocks)."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_hz, n_requests)
+    t = np.cumsum(gaps) - gaps[0]
+    lv = rng.integers(3, 6, n_requests)
+    gid = rng.integers(0, 4, n_requests)
+    return [(float(t[i]), int(lv[i]), int(gid[i]), 10000 + i) for i in range(n_requests)]
