@@ -1,0 +1,192 @@
+/*
+ * octmg.h -- C ABI of the octree geometric multigrid solver for Poisson's
+ * equation with level-set-defined irregular Dirichlet boundaries, after
+ * Teunissen & Schiavello, "Geometric multigrid method for solving Poisson's
+ * equation on octree grids with irregular boundaries".
+ *
+ * Conventions for every entry point:
+ *   - Every call returns octmg_status: 0 = OK, < 0 = error.  Nothing throws
+ *     across the ABI.  The message of the last error on the calling thread is
+ *     returned by octmg_last_error().
+ *   - Handles are owned by the library and released by the matching
+ *     *_destroy call.  Buffers passed in are borrowed for the duration of the
+ *     call (host buffers) or until the given stream has passed the call
+ *     (device buffers; on_device != 0).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device work of a call is ordered on that stream.
+ *   - A geometry is immutable after creation and may be shared by several
+ *     states.  A state is used by one host thread at a time.
+ *   - Leaf order ("canonical"): levels from coarse to fine, blocks of a level
+ *     in Morton order (x bit lowest), cells of a block x-fastest.  Level
+ *     order: the same without the leaf filter.
+ *   - Levels are numbered 0 .. n_levels-1 from the coarsest grid (8^D cells,
+ *     solved directly) to the finest.  Tree level l (root = 1 in the paper's
+ *     numbering) is level index l - 1 + n_sub, where n_sub single-block
+ *     levels sit below the root when block_n > coarse_n.
+ *
+ * Errors: OCTMG_ERR_INVALID for bad arguments (null handles, sizes out of
+ * range, unsupported dim/block size); OCTMG_ERR_OOM when a device allocation
+ * fails; OCTMG_ERR_HIP for any other HIP runtime failure (including no
+ * device); OCTMG_ERR_NONFINITE when the rhs or boundary data holds NaN/Inf;
+ * OCTMG_ERR_NOT_CONVERGED when a solve stops before rtol (the report is
+ * filled); OCTMG_ERR_GEOMETRY for a tree the method cannot handle.
+ */
+#ifndef OCTMG_H
+#define OCTMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OCTMG_OK = 0,
+    OCTMG_ERR_INVALID = -1,
+    OCTMG_ERR_OOM = -2,
+    OCTMG_ERR_HIP = -3,
+    OCTMG_ERR_NOT_CONVERGED = -4,
+    OCTMG_ERR_NONFINITE = -5,
+    OCTMG_ERR_GEOMETRY = -6,
+    OCTMG_ERR_BUDGET = -7
+} octmg_status;
+
+/* level-set kinds (Sec. 3.1, eq. lsf-example) */
+enum { OCTMG_LSF_NONE = 0,       /* no interface */
+       OCTMG_LSF_SPHERES = 1,    /* union: f = min_m |x - c_m| - r_m; params [cx,cy,cz,r]*n */
+       OCTMG_LSF_CYLINDER_Z = 2  /* f = |(x,y) - (cx,cy)| - r; params [cx,cy,r] */ };
+enum { OCTMG_REFINE_UNIFORM = 0, OCTMG_REFINE_NEAR_INTERFACE = 1 };
+enum { OCTMG_FP64 = 0, OCTMG_MIXED = 1 };
+enum { OCTMG_CYCLE_V = 0, OCTMG_CYCLE_FMG = 1 };
+/* fields for the debug accessors */
+enum { OCTMG_FIELD_PHI = 0, OCTMG_FIELD_G = 1, OCTMG_FIELD_OLD = 2 };
+/* single method steps for kernel-level checks (octmg_debug_step) */
+enum { OCTMG_STEP_HALF_SWEEP = 0,   /* arg = colour (0 red, 1 black) */
+       OCTMG_STEP_SMOOTH = 1,       /* arg = number of red+black steps */
+       OCTMG_STEP_RESTRICT_FAS = 2, /* level -> level-1 */
+       OCTMG_STEP_PROLONG = 3,      /* level-1 -> level; arg = 1: solution mode */
+       OCTMG_STEP_COARSE_SOLVE = 4, /* level ignored */
+       OCTMG_STEP_RESTRICT_RHS = 5  /* level -> level-1, nested-iteration start */ };
+
+/* Geometry description.  The domain is the cube [lo, lo+1]^D.
+ * dim 2 or 3; block_n 8 or 16 cells per block edge; max_level >= 1 finest
+ * tree level (root block = level 1, Sec. 2.1); refine_kind UNIFORM or
+ * NEAR_INTERFACE (refine a block when |f(block centre)| < refine_width *
+ * block width, then 2:1 balance over faces, edges and corners); eps_tol the
+ * relative tolerance of the line search (Sec. 3.2, 1e-8 in the paper);
+ * mask_factor the factor in L = mask_factor * sqrt(D) * dx of eq.
+ * boundary-mask (1.5 in the paper); w_min the smallest width resolved on
+ * coarse grids (Sec. 3.6.3; <= 0 disables); coarse_n the cells per edge of the
+ * directly solved coarsest grid (8).  lsf_params is a host array read during
+ * octmg_geom_create only. */
+typedef struct octmg_geom_desc {
+    int dim, block_n, max_level, refine_kind;
+    int lsf_kind, lsf_n, coarse_n, reserved;
+    double refine_width, eps_tol, mask_factor, w_min;
+    double lo[3];
+    const double *lsf_params;
+} octmg_geom_desc;
+
+typedef struct octmg_geom_s *octmg_geom;
+typedef struct octmg_state_s *octmg_state;
+
+/* Solve options (Sec. 2.2: V-cycle or FMG, N_down = N_up = 2). rtol is
+ * relative to the max-norm residual of phi = 0 over the leaf cells.  The
+ * solve stops with OCTMG_ERR_NOT_CONVERGED after max_cycles, or when the
+ * residual ratio of successive cycles stays above 0.95 for 3 cycles. */
+typedef struct octmg_solve_opts {
+    int cycle_kind, max_cycles, zero_start, reserved;
+    double rtol;
+} octmg_solve_opts;
+
+/* Solve report (worst right-hand side of the state). */
+typedef struct octmg_solve_report {
+    int cycles, status;
+    double r0, r_final;
+    double history[64]; /* max-norm residual after each cycle */
+} octmg_solve_report;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *octmg_last_error(void);
+int octmg_version(void);
+
+/* Host-only tree planning (Sec. 2.1), no device needed: per level
+ * [n cells per edge, block edge, blocks, leaf blocks] into level_info
+ * (caller provides 4 * 24 int64).  Same tree as octmg_geom_create. */
+octmg_status octmg_plan_levels(const octmg_geom_desc *d, int *n_levels, int64_t *level_info);
+/* Host-only: block positions and leaf flags of one level of the plan. */
+octmg_status octmg_plan_blocks(const octmg_geom_desc *d, int level, int *pos, int *leaf);
+
+/* Build the tree, run the FP64 interface setup on device `hip_device`
+ * (boundary mask eq. boundary-mask, line search Sec. 3.2, unresolved
+ * boundaries Sec. 3.6.3, stencils eq. lpl-2d-lsf, Sec. 3.6.2) and factor the
+ * coarsest grid.  *out receives a new handle. */
+octmg_status octmg_geom_create(const octmg_geom_desc *d, int hip_device, octmg_geom *out);
+void octmg_geom_destroy(octmg_geom g);
+/* info[0..7] = n_levels, n_leaf cells, n_interface points, n_domain face
+ * points, custom-cell records (all levels), device bytes, tree blocks,
+ * interface blocks. */
+octmg_status octmg_geom_info(octmg_geom g, int64_t *info);
+/* out[0..7] = n, block edge, blocks, leaf blocks, records, interface points,
+ * face points per face, interface blocks of one level. */
+octmg_status octmg_geom_level_info(octmg_geom g, int level, int64_t *out);
+/* Host buffers: cell centres [n_leaf][3] and level index per leaf cell. */
+octmg_status octmg_geom_leaf_coords(octmg_geom g, double *xyz, int *level);
+/* Host buffer [n_interface][3]: the roots x0 of every cut link, ordered by
+ * level, record (canonical cell order), link (x-,x+,y-,y+,z-,z+). */
+octmg_status octmg_geom_iface_points(octmg_geom g, double *xyz);
+/* Host buffer [n_domain][3]: domain face centres, ordered by level, face
+ * (x-,x+,y-,y+,z-,z+), tangential cell index (lower axis fastest). */
+octmg_status octmg_geom_domain_points(octmg_geom g, double *xyz);
+/* Host buffers for one level: ids [nrec][3] = block, cell (canonical local
+ * index), cut mask; d [nrec][6] relative distances (eq. relative-distance);
+ * coef [nrec][8] = link coefficients (cut links included), diagonal, 0. */
+octmg_status octmg_geom_records(octmg_geom g, int level, int *ids, double *d, double *coef);
+octmg_status octmg_geom_block_positions(octmg_geom g, int level, int *pos, int *leaf);
+
+/* Fields for n_rhs right-hand sides on geometry g (kept alive by the state).
+ * precision OCTMG_FP64, or OCTMG_MIXED: FP32 smoothing, transfers and ghost
+ * fill inside an FP64 defect correction (FP64 residual, update, setup and
+ * coarse solve). Solution and rhs start at zero; boundary data at zero. */
+octmg_status octmg_state_create(octmg_geom g, int n_rhs, int precision, octmg_state *out);
+void octmg_state_destroy(octmg_state s);
+/* Smoothing steps per level visit (default 2 and 2). */
+octmg_status octmg_state_set_smoothing(octmg_state s, int n_down, int n_up);
+/* Dirichlet data shared by all right-hand sides: phi_b at every interface
+ * point (octmg_geom_iface_points order; NULL = all zero) and at every domain
+ * face point (octmg_geom_domain_points order; NULL = all zero).  The
+ * interface term b_i = sum over cut links of c * phi_b is formed on the
+ * device (Sec. 3.6.2: the value imposed at the boundary can change without
+ * redoing the setup). */
+octmg_status octmg_set_boundary(octmg_state s, const double *iface_vals, const double *domain_vals,
+                                int on_device, void *stream);
+/* rhs g at leaf cells, [n_rhs][n_leaf] in canonical leaf order. */
+octmg_status octmg_set_rhs(octmg_state s, const double *g, int on_device, void *stream);
+/* Initial guess / solution at leaf cells, [n_rhs][n_leaf]. */
+octmg_status octmg_set_solution(octmg_state s, const double *phi, int on_device, void *stream);
+octmg_status octmg_get_solution(octmg_state s, double *phi, int on_device, void *stream);
+octmg_status octmg_zero_solution(octmg_state s, void *stream);
+/* Exactly one cycle: OCTMG_CYCLE_V (FAS V-cycle, Sec. 2.2) or
+ * OCTMG_CYCLE_FMG (have_guess = 0 starts by restricting the rhs). In MIXED
+ * precision one call is one outer defect-correction step around an FP32
+ * cycle of that kind. */
+octmg_status octmg_cycle(octmg_state s, int kind, int have_guess, void *stream);
+/* Max-norm of r = g - L phi (eq. residual) over the leaf cells, per rhs,
+ * into the host array out[n_rhs] (synchronises the stream). phi_zero != 0:
+ * residual of phi = 0. */
+octmg_status octmg_residual_norm(octmg_state s, int phi_zero, double *out, void *stream);
+/* Cycles until max|r| <= rtol * max|r(phi=0)| for every rhs. */
+octmg_status octmg_solve(octmg_state s, const octmg_solve_opts *opts, void *stream, octmg_solve_report *rep);
+
+/* Kernel-level access for parity checks: one level's field of one rhs in
+ * canonical level order (host buffers, synchronous), and single steps of
+ * the method on `level` (see OCTMG_STEP_*). FP64 fields of the state. */
+octmg_status octmg_debug_get_field(octmg_state s, int level, int field, int rhs, double *out);
+octmg_status octmg_debug_set_field(octmg_state s, int level, int field, int rhs, const double *in);
+octmg_status octmg_debug_step(octmg_state s, int step, int level, int arg, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OCTMG_H */

@@ -1,0 +1,1031 @@
+// C ABI of the octree multigrid solver: geometry (tree + FP64 interface
+// setup + coarse inverse, device resident), states (fields per right-hand
+// side), and the FAS V-cycle / FMG engine that drives the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "octmg_internal.hpp"
+
+using namespace octmg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+octmg_status fail(octmg_status st, const std::string &msg) {
+    g_last_error = msg;
+    return st;
+}
+
+#define HIPCK(call)                                                                                   \
+    do {                                                                                              \
+        hipError_t e_ = (call);                                                                       \
+        if (e_ != hipSuccess) {                                                                       \
+            return fail(e_ == hipErrorOutOfMemory ? OCTMG_ERR_OOM : OCTMG_ERR_HIP,                   \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                           \
+        }                                                                                             \
+    } while (0)
+
+#define STCK(call)                        \
+    do {                                  \
+        octmg_status s_ = (call);         \
+        if (s_ != OCTMG_OK) return s_;    \
+    } while (0)
+
+// device allocation owned by a geometry or state
+struct DevPool {
+    std::vector<void *> ptrs;
+    size_t bytes = 0;
+    ~DevPool() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <typename T>
+    hipError_t alloc(T **p, size_t n) {
+        *p = nullptr;
+        if (n == 0) return hipSuccess;
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, n * sizeof(T));
+        if (e != hipSuccess) return e;
+        ptrs.push_back(q);
+        bytes += n * sizeof(T);
+        *p = (T *)q;
+        return hipSuccess;
+    }
+};
+
+struct GeomLevel {
+    int n = 0, Nb = 0, nb = 0, nblocks = 0, nleaf = 0, cpb = 0, nface = 0;
+    double dx = 0;
+    std::vector<int> leaf_blocks;
+    long long leaf_base = 0;   // canonical offset of the level's first leaf cell
+    int nrec = 0, n_iface_blocks = 0;
+    long long npts = 0, pt_base = 0;
+    int4 *d_pos = nullptr;
+    int *d_lut = nullptr, *d_leaf = nullptr, *d_map_off = nullptr, *d_map = nullptr;
+    int *d_leaf_blocks = nullptr, *d_meta = nullptr;
+    double *d_rec8 = nullptr, *d_d6 = nullptr, *d_cfull = nullptr, *d_pts = nullptr;
+    float *d_rec8f = nullptr;
+};
+
+}  // namespace
+
+struct octmg_geom_s {
+    octmg_geom_desc desc{};
+    std::vector<double> params;
+    int device = 0;
+    Tree tree;
+    std::vector<GeomLevel> L;
+    long long n_leaf = 0, n_pts = 0, n_dom = 0, n_rec = 0, n_iface_blocks = 0;
+    double *d_M = nullptr, *d_S = nullptr;
+    DevPool pool;
+    int refs = 1;
+};
+
+namespace {
+
+struct Fields64 {
+    double *phi = nullptr, *g = nullptr, *old = nullptr, *b = nullptr, *bcv = nullptr;
+};
+struct Fields32 {
+    float *phi = nullptr, *g = nullptr, *old = nullptr;
+};
+
+}  // namespace
+
+struct octmg_state_s {
+    octmg_geom geom = nullptr;
+    int nrhs = 1, precision = OCTMG_FP64, n_down = 2, n_up = 2;
+    std::vector<Fields64> f64;
+    std::vector<Fields32> f32;
+    std::vector<long long> stride;  // per level: cells per rhs
+    unsigned long long *d_norm = nullptr;
+    int *d_flag = nullptr;
+    int *d_active = nullptr;  // [nrhs], 1 while a right-hand side iterates
+    DevPool pool;
+};
+
+namespace {
+
+int cells_per_block(int D, int Nb) { return D == 3 ? Nb * Nb * Nb : Nb * Nb; }
+
+void release_geom(octmg_geom g) {
+    if (!g) return;
+    if (--g->refs == 0) {
+        (void)hipSetDevice(g->device);
+        delete g;
+    }
+}
+
+// ------------------------------------------------------------ level views
+LV<double> lv64(const octmg_state_s *s, int il) {
+    LV<double> v{};
+    if (il < 0) return v;
+    const GeomLevel &G = s->geom->L[il];
+    v.n = G.n;
+    v.nb = G.nb;
+    v.nblocks = G.nblocks;
+    v.nface = G.nface;
+    v.dx2 = G.dx * G.dx;
+    v.inv_dx2 = 1.0 / (G.dx * G.dx);
+    v.lut = G.d_lut;
+    v.pos = G.d_pos;
+    v.leaf = G.d_leaf;
+    v.map_off = G.nrec ? G.d_map_off : nullptr;
+    v.map = G.d_map;
+    v.rec = G.d_rec8;
+    v.b = s->f64[il].b;
+    v.bcv = s->f64[il].bcv;
+    v.phi = s->f64[il].phi;
+    v.g = s->f64[il].g;
+    v.old = s->f64[il].old;
+    v.fstride = s->stride[il];
+    v.active = s->d_active;
+    return v;
+}
+
+LV<float> lv32(const octmg_state_s *s, int il) {
+    LV<float> v{};
+    if (il < 0) return v;
+    const GeomLevel &G = s->geom->L[il];
+    v.n = G.n;
+    v.nb = G.nb;
+    v.nblocks = G.nblocks;
+    v.nface = G.nface;
+    v.dx2 = (float)(G.dx * G.dx);
+    v.inv_dx2 = (float)(1.0 / (G.dx * G.dx));
+    v.lut = G.d_lut;
+    v.pos = G.d_pos;
+    v.leaf = G.d_leaf;
+    v.map_off = G.nrec ? G.d_map_off : nullptr;
+    v.map = G.d_map;
+    v.rec = G.d_rec8f;
+    v.b = nullptr;    // the correction equation has homogeneous boundary data
+    v.bcv = nullptr;
+    v.phi = s->f32[il].phi;
+    v.g = s->f32[il].g;
+    v.old = s->f32[il].old;
+    v.fstride = s->stride[il];
+    v.active = s->d_active;
+    return v;
+}
+
+template <typename T>
+LV<T> lvT(const octmg_state_s *s, int il);
+template <>
+LV<double> lvT<double>(const octmg_state_s *s, int il) { return lv64(s, il); }
+template <>
+LV<float> lvT<float>(const octmg_state_s *s, int il) { return lv32(s, il); }
+
+// ---------------------------------------------------------- cycle engine
+template <typename T>
+struct Engine {
+    const octmg_state_s *s;
+    hipStream_t st;
+    int D() const { return s->geom->tree.D; }
+    int Nb(int il) const { return s->geom->L[il].Nb; }
+
+    octmg_status smooth(int il, int steps) {
+        for (int k = 0; k < steps; k++)
+            for (int color = 0; color < 2; color++)
+                HIPCK(launch_gs_half<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1), color, s->nrhs, st));
+        return OCTMG_OK;
+    }
+    octmg_status half_sweep(int il, int color) {
+        HIPCK(launch_gs_half<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1), color, s->nrhs, st));
+        return OCTMG_OK;
+    }
+    // FAS restriction il -> il-1, then g_c = L_c phi_c + r_c, old_c = phi_c
+    octmg_status restrict_fas(int il) {
+        const int adaptive = s->geom->tree.adaptive ? 1 : 0;
+        HIPCK(launch_restrict_fas<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), adaptive, s->nrhs, st));
+        if (adaptive) HIPCK(launch_copy_parents<T>(D(), Nb(il - 1), lvT<T>(s, il - 1), s->nrhs, st));
+        HIPCK(launch_fas_rhs<T>(D(), Nb(il - 1), lvT<T>(s, il - 1), lvT<T>(s, il - 2), 1, s->nrhs, st));
+        return OCTMG_OK;
+    }
+    octmg_status restrict_rhs(int il) {
+        LV<T> c = lvT<T>(s, il - 1);
+        const long long n = s->stride[il - 1] * s->nrhs;
+        HIPCK(fill(c.phi, n));
+        HIPCK(fill(c.old, n));
+        HIPCK(launch_restrict_rhs<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), c, s->nrhs, st));
+        return OCTMG_OK;
+    }
+    octmg_status prolong(int il, int solution_mode) {
+        HIPCK(launch_prolong<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), solution_mode, s->nrhs, st));
+        return OCTMG_OK;
+    }
+    octmg_status coarse_solve() {
+        HIPCK(launch_coarse_solve<T>(D(), lvT<T>(s, 0), s->geom->d_M, s->geom->d_S, s->nrhs, st));
+        return OCTMG_OK;
+    }
+    hipError_t fill(T *p, long long n);
+    octmg_status sync_down() {
+        if (!s->geom->tree.adaptive) return OCTMG_OK;
+        for (int il = (int)s->geom->L.size() - 1; il > 0; il--)
+            HIPCK(launch_restrict_phi<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), s->nrhs, st));
+        return OCTMG_OK;
+    }
+    // FAS V-cycle with top level `top` (Sec. 2.2)
+    octmg_status vcycle(int top) {
+        for (int il = top; il > 0; il--) {
+            STCK(smooth(il, s->n_down));
+            STCK(restrict_fas(il));
+        }
+        STCK(coarse_solve());
+        for (int il = 1; il <= top; il++) {
+            STCK(prolong(il, 0));
+            STCK(smooth(il, s->n_up));
+        }
+        return OCTMG_OK;
+    }
+    // FMG (Sec. 2.2): restrict to the coarsest grid, solve, then a V-cycle on
+    // each finer level after prolongating its correction.
+    octmg_status fmg(int have_guess) {
+        const int top = (int)s->geom->L.size() - 1;
+        for (int il = top; il > 0; il--) STCK(have_guess ? restrict_fas(il) : restrict_rhs(il));
+        STCK(coarse_solve());
+        for (int il = 1; il <= top; il++) {
+            STCK(prolong(il, have_guess ? 0 : 1));
+            STCK(vcycle(il));
+        }
+        return OCTMG_OK;
+    }
+    octmg_status cycle(int kind, int have_guess) {
+        const int top = (int)s->geom->L.size() - 1;
+        STCK(kind == OCTMG_CYCLE_FMG ? fmg(have_guess) : vcycle(top));
+        return sync_down();
+    }
+};
+
+template <>
+hipError_t Engine<double>::fill(double *p, long long n) { return launch_fill(p, n, 0.0, st); }
+template <>
+hipError_t Engine<float>::fill(float *p, long long n) { return launch_fillf(p, n, 0.0f, st); }
+
+octmg_status residual_norm_dev(octmg_state s, int phi_zero, hipStream_t st) {
+    HIPCK(launch_fill_u64(s->d_norm, s->nrhs, 0ull, st));
+    if (!phi_zero) {
+        Engine<double> e{s, st};
+        STCK(e.sync_down());
+    }
+    const int D = s->geom->tree.D;
+    for (int il = 0; il < (int)s->geom->L.size(); il++) {
+        const GeomLevel &G = s->geom->L[il];
+        if (G.nleaf == 0) continue;
+        HIPCK(launch_residual_max<double>(D, G.Nb, lv64(s, il), lv64(s, il - 1), phi_zero, s->d_norm, s->nrhs, st));
+    }
+    return OCTMG_OK;
+}
+
+octmg_status read_norms(octmg_state s, double *out, hipStream_t st) {
+    std::vector<unsigned long long> h(s->nrhs);
+    HIPCK(hipMemcpyAsync(h.data(), s->d_norm, sizeof(unsigned long long) * s->nrhs, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    for (int r = 0; r < s->nrhs; r++) std::memcpy(&out[r], &h[r], sizeof(double));
+    return OCTMG_OK;
+}
+
+// one outer step of the mixed-precision defect correction: FP64 defect on
+// the leaves (norm into d_norm), FP32 cycle on the correction, FP64 update
+octmg_status mixed_defect(octmg_state s, hipStream_t st) {
+    Engine<double> e64{s, st};
+    STCK(e64.sync_down());
+    HIPCK(launch_fill_u64(s->d_norm, s->nrhs, 0ull, st));
+    const int D = s->geom->tree.D;
+    for (int il = 0; il < (int)s->geom->L.size(); il++) {
+        const long long n = s->stride[il] * s->nrhs;
+        HIPCK(launch_fillf(s->f32[il].phi, n, 0.0f, st));
+    }
+    for (int il = 0; il < (int)s->geom->L.size(); il++) {
+        const GeomLevel &G = s->geom->L[il];
+        if (G.nleaf == 0) continue;
+        HIPCK(launch_defect(D, G.Nb, lv64(s, il), lv64(s, il - 1), lv32(s, il), G.d_leaf_blocks, G.nleaf, s->d_norm,
+                            s->nrhs, st));
+    }
+    return OCTMG_OK;
+}
+
+octmg_status mixed_correct(octmg_state s, int kind, hipStream_t st) {
+    Engine<float> e32{s, st};
+    STCK(e32.cycle(kind, kind == OCTMG_CYCLE_FMG ? 0 : 1));
+    const int D = s->geom->tree.D;
+    for (int il = 0; il < (int)s->geom->L.size(); il++) {
+        const GeomLevel &G = s->geom->L[il];
+        if (G.nleaf == 0) continue;
+        HIPCK(launch_update(D, G.Nb, lv64(s, il), lv32(s, il), G.d_leaf_blocks, G.nleaf, s->nrhs, st));
+    }
+    return OCTMG_OK;
+}
+
+octmg_status check_level(octmg_state s, int level) {
+    if (!s) return fail(OCTMG_ERR_INVALID, "null state");
+    if (level < 0 || level >= (int)s->geom->L.size()) return fail(OCTMG_ERR_INVALID, "level out of range");
+    return OCTMG_OK;
+}
+
+octmg_status validate_desc(const octmg_geom_desc *d) {
+    if (!d) return fail(OCTMG_ERR_INVALID, "null descriptor");
+    if (!(d->eps_tol > 0.0 && d->eps_tol < 0.5)) return fail(OCTMG_ERR_INVALID, "eps_tol must be in (0, 0.5)");
+    if (!(d->mask_factor > 0.0)) return fail(OCTMG_ERR_INVALID, "mask_factor must be > 0");
+    if (d->lsf_kind == OCTMG_LSF_SPHERES && (d->lsf_n < 1 || d->lsf_n > 100000))
+        return fail(OCTMG_ERR_INVALID, "lsf_n out of range");
+    return OCTMG_OK;
+}
+
+std::vector<double> copy_params(const octmg_geom_desc &d) {
+    int np = d.lsf_kind == OCTMG_LSF_SPHERES ? 4 * d.lsf_n : (d.lsf_kind == OCTMG_LSF_CYLINDER_Z ? 3 : 0);
+    std::vector<double> p(np + 1, 0.0);
+    if (np && d.lsf_params) std::memcpy(p.data(), d.lsf_params, np * sizeof(double));
+    return p;
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+const char *octmg_last_error(void) { return g_last_error.c_str(); }
+int octmg_version(void) { return 1; }
+
+octmg_status octmg_plan_levels(const octmg_geom_desc *d, int *n_levels, int64_t *info) {
+    STCK(validate_desc(d));
+    if (!n_levels || !info) return fail(OCTMG_ERR_INVALID, "null output");
+    octmg_geom_desc dd = *d;
+    std::vector<double> p = copy_params(dd);
+    dd.lsf_params = p.data();
+    Tree t;
+    std::string err;
+    if (!build_tree(dd, &t, &err)) return fail(OCTMG_ERR_INVALID, err);
+    *n_levels = (int)t.lv.size();
+    for (size_t il = 0; il < t.lv.size(); il++) {
+        const TreeLevel &L = t.lv[il];
+        int nl = 0;
+        for (auto f : L.leaf) nl += f;
+        info[4 * il + 0] = L.n;
+        info[4 * il + 1] = L.Nb;
+        info[4 * il + 2] = L.nblocks();
+        info[4 * il + 3] = nl;
+    }
+    return OCTMG_OK;
+}
+
+octmg_status octmg_plan_blocks(const octmg_geom_desc *d, int level, int *pos, int *leaf) {
+    STCK(validate_desc(d));
+    octmg_geom_desc dd = *d;
+    std::vector<double> p = copy_params(dd);
+    dd.lsf_params = p.data();
+    Tree t;
+    std::string err;
+    if (!build_tree(dd, &t, &err)) return fail(OCTMG_ERR_INVALID, err);
+    if (level < 0 || level >= (int)t.lv.size()) return fail(OCTMG_ERR_INVALID, "level out of range");
+    const TreeLevel &L = t.lv[level];
+    std::memcpy(pos, L.pos.data(), L.pos.size() * sizeof(int));
+    for (int b = 0; b < L.nblocks(); b++) leaf[b] = L.leaf[b];
+    return OCTMG_OK;
+}
+
+octmg_status octmg_geom_create(const octmg_geom_desc *d, int hip_device, octmg_geom *out) {
+    STCK(validate_desc(d));
+    if (!out) return fail(OCTMG_ERR_INVALID, "null output");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(OCTMG_ERR_HIP, "no HIP device");
+    if (hip_device < 0 || hip_device >= ndev) return fail(OCTMG_ERR_INVALID, "bad device index");
+    HIPCK(hipSetDevice(hip_device));
+    std::unique_ptr<octmg_geom_s> G(new octmg_geom_s());
+    G->desc = *d;
+    G->params = copy_params(*d);
+    G->desc.lsf_params = G->params.data();
+    G->device = hip_device;
+    std::string err;
+    if (!build_tree(G->desc, &G->tree, &err)) return fail(OCTMG_ERR_INVALID, err);
+    const int D = G->tree.D;
+    const int nlev = (int)G->tree.lv.size();
+    G->L.resize(nlev);
+
+    double *d_params = nullptr;
+    HIPCK(G->pool.alloc(&d_params, G->params.size()));
+    HIPCK(hipMemcpy(d_params, G->params.data(), G->params.size() * sizeof(double), hipMemcpyHostToDevice));
+    const int nbisect = (int)std::ceil(-std::log(d->eps_tol) / std::log(2.0));
+    const int ngolden = (int)std::ceil(std::log(d->eps_tol) / std::log(0.5 * (std::sqrt(5.0) - 1.0)));
+
+    long long leaf_base = 0, pt_base = 0;
+    for (int il = 0; il < nlev; il++) {
+        const TreeLevel &T = G->tree.lv[il];
+        GeomLevel &L = G->L[il];
+        L.n = T.n;
+        L.Nb = T.Nb;
+        L.nb = T.nb;
+        L.nblocks = T.nblocks();
+        L.cpb = cells_per_block(D, T.Nb);
+        L.nface = D == 3 ? T.n * T.n : T.n;
+        L.dx = 1.0 / (double)T.n;
+        std::vector<int4> pos4(L.nblocks);
+        std::vector<int> leaf(L.nblocks);
+        for (int b = 0; b < L.nblocks; b++) {
+            pos4[b] = make_int4(T.pos[3 * b], T.pos[3 * b + 1], T.pos[3 * b + 2], 0);
+            leaf[b] = T.leaf[b];
+            if (T.leaf[b]) L.leaf_blocks.push_back(b);
+        }
+        L.nleaf = (int)L.leaf_blocks.size();
+        L.leaf_base = leaf_base;
+        leaf_base += (long long)L.nleaf * L.cpb;
+        HIPCK(G->pool.alloc(&L.d_pos, L.nblocks));
+        HIPCK(G->pool.alloc(&L.d_lut, T.lut.size()));
+        HIPCK(G->pool.alloc(&L.d_leaf, L.nblocks));
+        HIPCK(G->pool.alloc(&L.d_map_off, L.nblocks));
+        HIPCK(G->pool.alloc(&L.d_leaf_blocks, std::max(1, L.nleaf)));
+        HIPCK(hipMemcpy(L.d_pos, pos4.data(), L.nblocks * sizeof(int4), hipMemcpyHostToDevice));
+        HIPCK(hipMemcpy(L.d_lut, T.lut.data(), T.lut.size() * sizeof(int), hipMemcpyHostToDevice));
+        HIPCK(hipMemcpy(L.d_leaf, leaf.data(), L.nblocks * sizeof(int), hipMemcpyHostToDevice));
+        if (L.nleaf)
+            HIPCK(hipMemcpy(L.d_leaf_blocks, L.leaf_blocks.data(), L.nleaf * sizeof(int), hipMemcpyHostToDevice));
+
+        // ---- FP64 interface setup of this level (two passes)
+        SetupLevel S{};
+        S.D = D;
+        S.n = L.n;
+        S.Nb = L.Nb;
+        S.nblocks = L.nblocks;
+        S.nb = L.nb;
+        S.dx = L.dx;
+        for (int a = 0; a < 3; a++) S.lo[a] = d->lo[a];
+        S.pos = L.d_pos;
+        S.lut = L.d_lut;
+        S.leaf = L.d_leaf;
+        S.lsf_kind = d->lsf_kind;
+        S.lsf_n = d->lsf_n;
+        S.lsf_params = d_params;
+        S.mask_L = d->mask_factor * std::sqrt((double)D) * L.dx;
+        S.w_min = d->w_min;
+        S.nbisect = nbisect;
+        S.ngolden = ngolden;
+        int *d_counts = nullptr;
+        HIPCK(hipMalloc(&d_counts, sizeof(int) * 2 * L.nblocks));
+        std::unique_ptr<int, void (*)(int *)> counts_guard(d_counts, [](int *p) { (void)hipFree(p); });
+        HIPCK(launch_setup_count(S, d_counts, nullptr));
+        std::vector<int> counts(2 * L.nblocks);
+        HIPCK(hipMemcpy(counts.data(), d_counts, sizeof(int) * 2 * L.nblocks, hipMemcpyDeviceToHost));
+        std::vector<int> rec_off(L.nblocks), pt_off(L.nblocks), map_off(L.nblocks, -1);
+        int nrec = 0, nib = 0;
+        long long npt = 0;
+        for (int b = 0; b < L.nblocks; b++) {
+            rec_off[b] = nrec;
+            pt_off[b] = (int)npt;
+            if (counts[2 * b] > 0) map_off[b] = (nib++) * L.cpb;
+            nrec += counts[2 * b];
+            npt += counts[2 * b + 1];
+        }
+        L.nrec = nrec;
+        L.npts = npt;
+        L.n_iface_blocks = nib;
+        L.pt_base = pt_base;
+        pt_base += npt;
+        HIPCK(hipMemcpy(L.d_map_off, map_off.data(), sizeof(int) * L.nblocks, hipMemcpyHostToDevice));
+        if (nrec) {
+            int *d_roff = nullptr, *d_poff = nullptr;
+            HIPCK(hipMalloc(&d_roff, sizeof(int) * L.nblocks));
+            std::unique_ptr<int, void (*)(int *)> g1(d_roff, [](int *p) { (void)hipFree(p); });
+            HIPCK(hipMalloc(&d_poff, sizeof(int) * L.nblocks));
+            std::unique_ptr<int, void (*)(int *)> g2(d_poff, [](int *p) { (void)hipFree(p); });
+            HIPCK(hipMemcpy(d_roff, rec_off.data(), sizeof(int) * L.nblocks, hipMemcpyHostToDevice));
+            HIPCK(hipMemcpy(d_poff, pt_off.data(), sizeof(int) * L.nblocks, hipMemcpyHostToDevice));
+            HIPCK(G->pool.alloc(&L.d_map, (size_t)nib * L.cpb));
+            HIPCK(hipMemset(L.d_map, 0xFF, sizeof(int) * (size_t)nib * L.cpb));
+            HIPCK(G->pool.alloc(&L.d_meta, (size_t)4 * nrec));
+            HIPCK(G->pool.alloc(&L.d_d6, (size_t)6 * nrec));
+            HIPCK(G->pool.alloc(&L.d_cfull, (size_t)6 * nrec));
+            HIPCK(G->pool.alloc(&L.d_rec8, (size_t)8 * nrec));
+            HIPCK(G->pool.alloc(&L.d_rec8f, (size_t)8 * nrec));
+            HIPCK(G->pool.alloc(&L.d_pts, (size_t)3 * std::max<long long>(1, npt)));
+            HIPCK(launch_setup_emit(S, d_roff, d_poff, L.d_map_off, L.d_map, L.d_meta, L.d_d6, L.d_cfull, L.d_rec8,
+                                    L.d_rec8f, L.d_pts, nullptr));
+            HIPCK(hipDeviceSynchronize());
+        }
+        G->n_rec += nrec;
+        G->n_iface_blocks += nib;
+        G->n_dom += 2LL * D * L.nface;
+    }
+    G->n_leaf = leaf_base;
+    G->n_pts = pt_base;
+
+    // ---- coarsest grid: dense operator and row-equilibrated inverse
+    {
+        const GeomLevel &L0 = G->L[0];
+        if (L0.nblocks != 1 || L0.Nb != 8) return fail(OCTMG_ERR_GEOMETRY, "coarsest level must be one 8^D block");
+        const int n0 = L0.cpb;
+        double *d_A = nullptr;
+        int *d_fail = nullptr;
+        HIPCK(hipMalloc(&d_A, sizeof(double) * n0 * n0));
+        std::unique_ptr<double, void (*)(double *)> ga(d_A, [](double *p) { (void)hipFree(p); });
+        HIPCK(hipMalloc(&d_fail, sizeof(int)));
+        std::unique_ptr<int, void (*)(int *)> gf(d_fail, [](int *p) { (void)hipFree(p); });
+        HIPCK(hipMemset(d_fail, 0, sizeof(int)));
+        HIPCK(G->pool.alloc(&G->d_M, (size_t)n0 * n0));
+        HIPCK(G->pool.alloc(&G->d_S, (size_t)n0));
+        int mo = -1;
+        HIPCK(hipMemcpy(&mo, L0.d_map_off, sizeof(int), hipMemcpyDeviceToHost));
+        HIPCK(launch_coarse_assemble(D, L0.Nb, L0.dx, mo >= 0 ? L0.d_map + mo : nullptr, L0.d_rec8, d_A, nullptr));
+        HIPCK(launch_gauss_jordan(n0, d_A, G->d_M, G->d_S, d_fail, nullptr));
+        int hf = 0;
+        HIPCK(hipMemcpy(&hf, d_fail, sizeof(int), hipMemcpyDeviceToHost));
+        if (hf) return fail(OCTMG_ERR_GEOMETRY, "coarse-grid operator is singular");
+    }
+    HIPCK(hipDeviceSynchronize());
+    *out = G.release();
+    return OCTMG_OK;
+}
+
+void octmg_geom_destroy(octmg_geom g) { release_geom(g); }
+
+octmg_status octmg_geom_info(octmg_geom g, int64_t *info) {
+    if (!g || !info) return fail(OCTMG_ERR_INVALID, "null argument");
+    long long blocks = 0;
+    for (auto &L : g->L) blocks += L.nblocks;
+    info[0] = (int64_t)g->L.size();
+    info[1] = g->n_leaf;
+    info[2] = g->n_pts;
+    info[3] = g->n_dom;
+    info[4] = g->n_rec;
+    info[5] = (int64_t)g->pool.bytes;
+    info[6] = blocks;
+    info[7] = g->n_iface_blocks;
+    return OCTMG_OK;
+}
+
+octmg_status octmg_geom_level_info(octmg_geom g, int level, int64_t *out) {
+    if (!g || !out) return fail(OCTMG_ERR_INVALID, "null argument");
+    if (level < 0 || level >= (int)g->L.size()) return fail(OCTMG_ERR_INVALID, "level out of range");
+    const GeomLevel &L = g->L[level];
+    out[0] = L.n;
+    out[1] = L.Nb;
+    out[2] = L.nblocks;
+    out[3] = L.nleaf;
+    out[4] = L.nrec;
+    out[5] = L.npts;
+    out[6] = L.nface;
+    out[7] = L.n_iface_blocks;
+    return OCTMG_OK;
+}
+
+octmg_status octmg_geom_leaf_coords(octmg_geom g, double *xyz, int *level) {
+    if (!g) return fail(OCTMG_ERR_INVALID, "null geometry");
+    const int D = g->tree.D;
+    long long n = 0;
+    for (size_t il = 0; il < g->L.size(); il++) {
+        const GeomLevel &L = g->L[il];
+        const TreeLevel &T = g->tree.lv[il];
+        for (int b : L.leaf_blocks)
+            for (int c = 0; c < L.cpb; c++, n++) {
+                const int l[3] = {c % L.Nb, (c / L.Nb) % L.Nb, D == 3 ? c / (L.Nb * L.Nb) : 0};
+                for (int a = 0; a < 3; a++) {
+                    double v = 0.0;
+                    if (a < D) v = g->desc.lo[a] + ((double)(T.pos[3 * b + a] * L.Nb + l[a]) + 0.5) * L.dx;
+                    if (xyz) xyz[3 * n + a] = v;
+                }
+                if (level) level[n] = (int)il;
+            }
+    }
+    return OCTMG_OK;
+}
+
+octmg_status octmg_geom_iface_points(octmg_geom g, double *xyz) {
+    if (!g || !xyz) return fail(OCTMG_ERR_INVALID, "null argument");
+    HIPCK(hipSetDevice(g->device));
+    for (auto &L : g->L)
+        if (L.npts) HIPCK(hipMemcpy(xyz + 3 * L.pt_base, L.d_pts, sizeof(double) * 3 * L.npts, hipMemcpyDeviceToHost));
+    return OCTMG_OK;
+}
+
+octmg_status octmg_geom_domain_points(octmg_geom g, double *xyz) {
+    if (!g || !xyz) return fail(OCTMG_ERR_INVALID, "null argument");
+    const int D = g->tree.D;
+    long long n = 0;
+    for (auto &L : g->L)
+        for (int f = 0; f < 2 * D; f++) {
+            const int ax = f / 2;
+            for (int t = 0; t < L.nface; t++, n++) {
+                const int tg[2] = {t % L.n, t / L.n};
+                int m = 0;
+                for (int a = 0; a < 3; a++) {
+                    double v = 0.0;
+                    if (a < D) {
+                        if (a == ax) v = (f & 1) ? g->desc.lo[a] + 1.0 : g->desc.lo[a];
+                        else v = g->desc.lo[a] + ((double)tg[m++] + 0.5) * L.dx;
+                    }
+                    xyz[3 * n + a] = v;
+                }
+            }
+        }
+    return OCTMG_OK;
+}
+
+octmg_status octmg_geom_records(octmg_geom g, int level, int *ids, double *d, double *coef) {
+    if (!g || level < 0 || level >= (int)g->L.size()) return fail(OCTMG_ERR_INVALID, "bad argument");
+    HIPCK(hipSetDevice(g->device));
+    const GeomLevel &L = g->L[level];
+    if (!L.nrec) return OCTMG_OK;
+    const int D = g->tree.D;
+    std::vector<int> meta(4 * L.nrec);
+    std::vector<double> d6(6 * L.nrec), cf(6 * L.nrec), r8(8 * L.nrec);
+    HIPCK(hipMemcpy(meta.data(), L.d_meta, sizeof(int) * meta.size(), hipMemcpyDeviceToHost));
+    HIPCK(hipMemcpy(d6.data(), L.d_d6, sizeof(double) * d6.size(), hipMemcpyDeviceToHost));
+    HIPCK(hipMemcpy(cf.data(), L.d_cfull, sizeof(double) * cf.size(), hipMemcpyDeviceToHost));
+    HIPCK(hipMemcpy(r8.data(), L.d_rec8, sizeof(double) * r8.size(), hipMemcpyDeviceToHost));
+    const int N = L.Nb, half = L.cpb / 2, nh = N / 2;
+    for (int r = 0; r < L.nrec; r++) {
+        // split index -> canonical local index
+        const int si = meta[4 * r + 1], col = si / half, q = si % half;
+        const int h = q % nh, j = (q / nh) % N, k = D == 3 ? q / (nh * N) : 0;
+        const int i = 2 * h + ((col + j + k) & 1);
+        if (ids) {
+            ids[3 * r] = meta[4 * r];
+            ids[3 * r + 1] = D == 3 ? (k * N + j) * N + i : j * N + i;
+            ids[3 * r + 2] = meta[4 * r + 2];
+        }
+        for (int kk = 0; kk < 6; kk++) {
+            if (d) d[6 * r + kk] = d6[6 * r + kk];
+            if (coef) coef[8 * r + kk] = cf[6 * r + kk];
+        }
+        if (coef) {
+            coef[8 * r + 6] = r8[8 * r + 6];
+            coef[8 * r + 7] = 0.0;
+        }
+    }
+    return OCTMG_OK;
+}
+
+octmg_status octmg_geom_block_positions(octmg_geom g, int level, int *pos, int *leaf) {
+    if (!g || level < 0 || level >= (int)g->L.size()) return fail(OCTMG_ERR_INVALID, "bad argument");
+    const TreeLevel &T = g->tree.lv[level];
+    if (pos) std::memcpy(pos, T.pos.data(), T.pos.size() * sizeof(int));
+    if (leaf)
+        for (int b = 0; b < T.nblocks(); b++) leaf[b] = T.leaf[b];
+    return OCTMG_OK;
+}
+
+octmg_status octmg_state_create(octmg_geom g, int n_rhs, int precision, octmg_state *out) {
+    if (!g || !out) return fail(OCTMG_ERR_INVALID, "null argument");
+    if (n_rhs < 1 || n_rhs > 4096) return fail(OCTMG_ERR_INVALID, "n_rhs out of range");
+    if (precision != OCTMG_FP64 && precision != OCTMG_MIXED) return fail(OCTMG_ERR_INVALID, "bad precision");
+    HIPCK(hipSetDevice(g->device));
+    std::unique_ptr<octmg_state_s> s(new octmg_state_s());
+    s->geom = g;
+    s->nrhs = n_rhs;
+    s->precision = precision;
+    const int nlev = (int)g->L.size(), D = g->tree.D;
+    s->f64.resize(nlev);
+    s->f32.resize(nlev);
+    s->stride.resize(nlev);
+    for (int il = 0; il < nlev; il++) {
+        const GeomLevel &L = g->L[il];
+        const long long cells = (long long)L.nblocks * L.cpb;
+        s->stride[il] = cells;
+        const size_t n = (size_t)cells * n_rhs;
+        Fields64 &F = s->f64[il];
+        HIPCK(s->pool.alloc(&F.phi, n));
+        HIPCK(s->pool.alloc(&F.g, n));
+        HIPCK(s->pool.alloc(&F.old, n));
+        HIPCK(s->pool.alloc(&F.b, std::max(1, L.nrec)));
+        HIPCK(s->pool.alloc(&F.bcv, (size_t)2 * D * L.nface));
+        HIPCK(launch_fill(F.phi, n, 0.0, nullptr));
+        HIPCK(launch_fill(F.g, n, 0.0, nullptr));
+        HIPCK(launch_fill(F.old, n, 0.0, nullptr));
+        HIPCK(launch_fill(F.b, std::max(1, L.nrec), 0.0, nullptr));
+        HIPCK(launch_fill(F.bcv, (long long)2 * D * L.nface, 0.0, nullptr));
+        if (precision == OCTMG_MIXED) {
+            Fields32 &H = s->f32[il];
+            HIPCK(s->pool.alloc(&H.phi, n));
+            HIPCK(s->pool.alloc(&H.g, n));
+            HIPCK(s->pool.alloc(&H.old, n));
+            HIPCK(launch_fillf(H.phi, n, 0.0f, nullptr));
+            HIPCK(launch_fillf(H.g, n, 0.0f, nullptr));
+            HIPCK(launch_fillf(H.old, n, 0.0f, nullptr));
+        }
+    }
+    HIPCK(s->pool.alloc(&s->d_norm, n_rhs));
+    HIPCK(s->pool.alloc(&s->d_flag, 1));
+    HIPCK(s->pool.alloc(&s->d_active, n_rhs));
+    {
+        std::vector<int> ones(n_rhs, 1);
+        HIPCK(hipMemcpy(s->d_active, ones.data(), sizeof(int) * n_rhs, hipMemcpyHostToDevice));
+    }
+    HIPCK(hipDeviceSynchronize());
+    g->refs++;
+    *out = s.release();
+    return OCTMG_OK;
+}
+
+void octmg_state_destroy(octmg_state s) {
+    if (!s) return;
+    (void)hipSetDevice(s->geom->device);
+    (void)hipDeviceSynchronize();
+    octmg_geom g = s->geom;
+    delete s;
+    release_geom(g);
+}
+
+octmg_status octmg_state_set_smoothing(octmg_state s, int n_down, int n_up) {
+    if (!s || n_down < 0 || n_up < 0 || n_down > 16 || n_up > 16) return fail(OCTMG_ERR_INVALID, "bad argument");
+    s->n_down = n_down;
+    s->n_up = n_up;
+    return OCTMG_OK;
+}
+
+static octmg_status stage_in(const double *src, size_t n, int on_device, hipStream_t st, double **dev,
+                             DevPool *tmp) {
+    if (on_device) {
+        *dev = (double *)src;
+        return OCTMG_OK;
+    }
+    HIPCK(tmp->alloc(dev, n));
+    HIPCK(hipMemcpyAsync(*dev, src, n * sizeof(double), hipMemcpyHostToDevice, st));
+    return OCTMG_OK;
+}
+
+static octmg_status check_finite(octmg_state s, const double *dptr, long long n, hipStream_t st) {
+    HIPCK(hipMemsetAsync(s->d_flag, 0, sizeof(int), st));
+    HIPCK(launch_check_finite(dptr, n, s->d_flag, st));
+    int h = 0;
+    HIPCK(hipMemcpyAsync(&h, s->d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (h) return fail(OCTMG_ERR_NONFINITE, "input holds NaN or Inf");
+    return OCTMG_OK;
+}
+
+octmg_status octmg_set_boundary(octmg_state s, const double *iface_vals, const double *domain_vals, int on_device,
+                                void *stream) {
+    if (!s) return fail(OCTMG_ERR_INVALID, "null state");
+    hipStream_t st = (hipStream_t)stream;
+    octmg_geom g = s->geom;
+    HIPCK(hipSetDevice(g->device));
+    const int D = g->tree.D;
+    DevPool tmp;
+    double *dv_iface = nullptr, *dv_dom = nullptr;
+    if (iface_vals && g->n_pts) {
+        STCK(stage_in(iface_vals, g->n_pts, on_device, st, &dv_iface, &tmp));
+        STCK(check_finite(s, dv_iface, g->n_pts, st));
+    }
+    if (domain_vals) {
+        STCK(stage_in(domain_vals, g->n_dom, on_device, st, &dv_dom, &tmp));
+        STCK(check_finite(s, dv_dom, g->n_dom, st));
+    }
+    long long dom_off = 0;
+    for (size_t il = 0; il < g->L.size(); il++) {
+        const GeomLevel &L = g->L[il];
+        Fields64 &F = s->f64[il];
+        HIPCK(launch_boundary_terms(D, L.d_meta, L.d_cfull, L.nrec, dv_iface ? dv_iface + L.pt_base : nullptr, F.b,
+                                    nullptr, st));
+        const long long nf = 2LL * D * L.nface;
+        if (dv_dom) HIPCK(hipMemcpyAsync(F.bcv, dv_dom + dom_off, nf * sizeof(double), hipMemcpyDeviceToDevice, st));
+        else HIPCK(launch_fill(F.bcv, nf, 0.0, st));
+        dom_off += nf;
+    }
+    HIPCK(hipStreamSynchronize(st));
+    return OCTMG_OK;
+}
+
+static octmg_status set_leaf_field(octmg_state s, const double *src, int on_device, hipStream_t st, int field) {
+    octmg_geom g = s->geom;
+    HIPCK(hipSetDevice(g->device));
+    DevPool tmp;
+    double *dv = nullptr;
+    const size_t n = (size_t)g->n_leaf * s->nrhs;
+    STCK(stage_in(src, n, on_device, st, &dv, &tmp));
+    STCK(check_finite(s, dv, (long long)n, st));
+    for (size_t il = 0; il < g->L.size(); il++) {
+        const GeomLevel &L = g->L[il];
+        HIPCK(launch_scatter_leaf(g->tree.D, L.Nb, lv64(s, (int)il), L.d_leaf_blocks, L.nleaf, dv, g->n_leaf,
+                                  L.leaf_base, field, s->nrhs, st));
+    }
+    HIPCK(hipStreamSynchronize(st));
+    return OCTMG_OK;
+}
+
+octmg_status octmg_set_rhs(octmg_state s, const double *gv, int on_device, void *stream) {
+    if (!s || !gv) return fail(OCTMG_ERR_INVALID, "null argument");
+    return set_leaf_field(s, gv, on_device, (hipStream_t)stream, 1);
+}
+
+octmg_status octmg_set_solution(octmg_state s, const double *phi, int on_device, void *stream) {
+    if (!s || !phi) return fail(OCTMG_ERR_INVALID, "null argument");
+    return set_leaf_field(s, phi, on_device, (hipStream_t)stream, 0);
+}
+
+octmg_status octmg_get_solution(octmg_state s, double *phi, int on_device, void *stream) {
+    if (!s || !phi) return fail(OCTMG_ERR_INVALID, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    octmg_geom g = s->geom;
+    HIPCK(hipSetDevice(g->device));
+    const size_t n = (size_t)g->n_leaf * s->nrhs;
+    DevPool tmp;
+    double *dv = phi;
+    if (!on_device) HIPCK(tmp.alloc(&dv, n));
+    for (size_t il = 0; il < g->L.size(); il++) {
+        const GeomLevel &L = g->L[il];
+        HIPCK(launch_gather_leaf(g->tree.D, L.Nb, lv64(s, (int)il), L.d_leaf_blocks, L.nleaf, dv, g->n_leaf,
+                                 L.leaf_base, s->nrhs, st));
+    }
+    if (!on_device) HIPCK(hipMemcpyAsync(phi, dv, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    return OCTMG_OK;
+}
+
+octmg_status octmg_zero_solution(octmg_state s, void *stream) {
+    if (!s) return fail(OCTMG_ERR_INVALID, "null state");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCK(hipSetDevice(s->geom->device));
+    for (size_t il = 0; il < s->f64.size(); il++) {
+        const long long n = s->stride[il] * s->nrhs;
+        HIPCK(launch_fill(s->f64[il].phi, n, 0.0, st));
+        HIPCK(launch_fill(s->f64[il].old, n, 0.0, st));
+    }
+    return OCTMG_OK;
+}
+
+octmg_status octmg_cycle(octmg_state s, int kind, int have_guess, void *stream) {
+    if (!s) return fail(OCTMG_ERR_INVALID, "null state");
+    if (kind != OCTMG_CYCLE_V && kind != OCTMG_CYCLE_FMG) return fail(OCTMG_ERR_INVALID, "bad cycle kind");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCK(hipSetDevice(s->geom->device));
+    if (s->precision == OCTMG_MIXED) {
+        STCK(mixed_defect(s, st));
+        return mixed_correct(s, kind, st);
+    }
+    Engine<double> e{s, st};
+    return e.cycle(kind, have_guess);
+}
+
+octmg_status octmg_residual_norm(octmg_state s, int phi_zero, double *out, void *stream) {
+    if (!s || !out) return fail(OCTMG_ERR_INVALID, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCK(hipSetDevice(s->geom->device));
+    STCK(residual_norm_dev(s, phi_zero, st));
+    return read_norms(s, out, st);
+}
+
+static octmg_status set_active(octmg_state s, const std::vector<int> &act, hipStream_t st) {
+    HIPCK(hipMemcpyAsync(s->d_active, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice, st));
+    HIPCK(hipStreamSynchronize(st));
+    return OCTMG_OK;
+}
+
+// Cycles until every right-hand side satisfies max|r| <= rtol * max|r(0)|.
+// A right-hand side that has converged is frozen (its kernels exit early),
+// so each one receives exactly the cycles a solve of it alone would.
+static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStream_t st, octmg_solve_report *rp) {
+    const int R = s->nrhs;
+    std::vector<double> r0(R), rk(R), cur(R, 0.0), prev(R, 0.0);
+    std::vector<int> act(R, 1);
+    STCK(set_active(s, act, st));
+    STCK(residual_norm_dev(s, 1, st));
+    STCK(read_norms(s, r0.data(), st));
+    if (o->zero_start) STCK(octmg_zero_solution(s, st));
+    std::memset(rp, 0, sizeof(*rp));
+    for (double v : r0) rp->r0 = std::max(rp->r0, v);
+    int stall = 0;
+    bool have_guess = !o->zero_start;
+    for (int k = 0; k <= o->max_cycles; k++) {
+        if (s->precision == OCTMG_MIXED) STCK(mixed_defect(s, st));
+        else STCK(residual_norm_dev(s, 0, st));
+        STCK(read_norms(s, rk.data(), st));
+        bool all_done = true, nonfinite = false, changed = false;
+        double rmax = 0.0;
+        for (int r = 0; r < R; r++) {
+            if (act[r]) cur[r] = rk[r];
+            if (!std::isfinite(cur[r])) nonfinite = true;
+            rmax = std::max(rmax, cur[r]);
+            if (act[r] && cur[r] <= o->rtol * r0[r]) {
+                act[r] = 0;
+                changed = true;
+            }
+            if (act[r]) all_done = false;
+        }
+        if (k > 0 && k <= 64) rp->history[k - 1] = rmax;
+        rp->cycles = k;
+        rp->r_final = rmax;
+        if (nonfinite) {
+            rp->status = OCTMG_ERR_NONFINITE;
+            return fail(OCTMG_ERR_NONFINITE, "residual became non-finite");
+        }
+        if (all_done) {
+            rp->status = OCTMG_OK;
+            return OCTMG_OK;
+        }
+        if (k == o->max_cycles) break;
+        if (k > 0) {
+            bool slow = true;
+            for (int r = 0; r < R; r++)
+                if (act[r] && !(cur[r] > 0.95 * prev[r])) slow = false;
+            stall = slow ? stall + 1 : 0;
+            if (stall >= 3) break;
+        }
+        prev = cur;
+        if (changed) STCK(set_active(s, act, st));
+        if (s->precision == OCTMG_MIXED) {
+            STCK(mixed_correct(s, o->cycle_kind, st));
+        } else {
+            Engine<double> e{s, st};
+            STCK(e.cycle(o->cycle_kind, have_guess ? 1 : 0));
+        }
+        have_guess = true;
+    }
+    rp->status = OCTMG_ERR_NOT_CONVERGED;
+    return fail(OCTMG_ERR_NOT_CONVERGED, "rtol not reached");
+}
+
+octmg_status octmg_solve(octmg_state s, const octmg_solve_opts *o, void *stream, octmg_solve_report *rep) {
+    if (!s || !o) return fail(OCTMG_ERR_INVALID, "null argument");
+    if (!(o->rtol > 0.0) || o->max_cycles < 1 || o->max_cycles > 64) return fail(OCTMG_ERR_INVALID, "bad options");
+    if (o->cycle_kind != OCTMG_CYCLE_V && o->cycle_kind != OCTMG_CYCLE_FMG) return fail(OCTMG_ERR_INVALID, "bad cycle kind");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCK(hipSetDevice(s->geom->device));
+    octmg_solve_report local{};
+    octmg_status res = solve_impl(s, o, st, rep ? rep : &local);
+    std::string msg = g_last_error;
+    std::vector<int> all(s->nrhs, 1);
+    STCK(set_active(s, all, st));
+    if (res != OCTMG_OK) return fail(res, msg);
+    return OCTMG_OK;
+}
+
+octmg_status octmg_debug_get_field(octmg_state s, int level, int field, int rhs, double *out) {
+    STCK(check_level(s, level));
+    if (rhs < 0 || rhs >= s->nrhs || !out || field < 0 || field > 2) return fail(OCTMG_ERR_INVALID, "bad argument");
+    HIPCK(hipSetDevice(s->geom->device));
+    const GeomLevel &L = s->geom->L[level];
+    const Fields64 &F = s->f64[level];
+    double *src = (field == 0 ? F.phi : field == 1 ? F.g : F.old) + s->stride[level] * rhs;
+    const size_t n = (size_t)L.nblocks * L.cpb;
+    DevPool tmp;
+    double *canon = nullptr;
+    HIPCK(tmp.alloc(&canon, n));
+    HIPCK(launch_level_copy(s->geom->tree.D, L.Nb, src, canon, L.nblocks, 0, nullptr));
+    HIPCK(hipMemcpy(out, canon, n * sizeof(double), hipMemcpyDeviceToHost));
+    return OCTMG_OK;
+}
+
+octmg_status octmg_debug_set_field(octmg_state s, int level, int field, int rhs, const double *in) {
+    STCK(check_level(s, level));
+    if (rhs < 0 || rhs >= s->nrhs || !in || field < 0 || field > 2) return fail(OCTMG_ERR_INVALID, "bad argument");
+    HIPCK(hipSetDevice(s->geom->device));
+    const GeomLevel &L = s->geom->L[level];
+    const Fields64 &F = s->f64[level];
+    double *dst = (field == 0 ? F.phi : field == 1 ? F.g : F.old) + s->stride[level] * rhs;
+    const size_t n = (size_t)L.nblocks * L.cpb;
+    DevPool tmp;
+    double *canon = nullptr;
+    HIPCK(tmp.alloc(&canon, n));
+    HIPCK(hipMemcpy(canon, in, n * sizeof(double), hipMemcpyHostToDevice));
+    HIPCK(launch_level_copy(s->geom->tree.D, L.Nb, dst, canon, L.nblocks, 1, nullptr));
+    HIPCK(hipDeviceSynchronize());
+    return OCTMG_OK;
+}
+
+octmg_status octmg_debug_step(octmg_state s, int step, int level, int arg, void *stream) {
+    if (!s) return fail(OCTMG_ERR_INVALID, "null state");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCK(hipSetDevice(s->geom->device));
+    Engine<double> e{s, st};
+    const int nlev = (int)s->geom->L.size();
+    if (step != OCTMG_STEP_COARSE_SOLVE) STCK(check_level(s, level));
+    switch (step) {
+        case OCTMG_STEP_HALF_SWEEP:
+            if (arg != 0 && arg != 1) return fail(OCTMG_ERR_INVALID, "colour must be 0 or 1");
+            STCK(e.half_sweep(level, arg));
+            break;
+        case OCTMG_STEP_SMOOTH:
+            STCK(e.smooth(level, arg));
+            break;
+        case OCTMG_STEP_RESTRICT_FAS:
+            if (level < 1) return fail(OCTMG_ERR_INVALID, "level must be >= 1");
+            STCK(e.restrict_fas(level));
+            break;
+        case OCTMG_STEP_PROLONG:
+            if (level < 1) return fail(OCTMG_ERR_INVALID, "level must be >= 1");
+            STCK(e.prolong(level, arg));
+            break;
+        case OCTMG_STEP_COARSE_SOLVE:
+            STCK(e.coarse_solve());
+            break;
+        case OCTMG_STEP_RESTRICT_RHS:
+            if (level < 1) return fail(OCTMG_ERR_INVALID, "level must be >= 1");
+            STCK(e.restrict_rhs(level));
+            break;
+        default:
+            return fail(OCTMG_ERR_INVALID, "unknown step");
+    }
+    (void)nlev;
+    HIPCK(hipStreamSynchronize(st));
+    return OCTMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,903 @@
+// HIP kernels of the multigrid cycle for gfx950 (CDNA4, wave64).
+//
+// One workgroup owns one block of N^D cells (N = 8 or 16).  Fields use the
+// colour-split block-major layout described in octmg_internal.hpp, so a
+// red-black half-sweep touches each HBM byte once: the other colour's phi
+// (read), this colour's g (read) and this colour's phi (written).  Ghost
+// values are never stored; they are formed where a neighbour is read:
+//   same level      -> the neighbour block's cell (level lookup table)
+//   domain face     -> 2 phi_b(face centre) - phi_inside (Dirichlet)
+//   refinement edge -> 1/2 C_k + 3/4 f1 - 1/4 f2, C_k = C + sum_t s_t
+//                      (C_t+ - C_t-)/8 from the next coarser level, which
+//                      makes the coarse flux equal the averaged fine flux.
+// Cells near the interface carry their own stencil (record index per cell,
+// Sec. 3.6.2); every other cell uses the constant 2D+1 point Laplacian.
+#include <hip/hip_runtime.h>
+
+#include "octmg_internal.hpp"
+
+namespace octmg {
+namespace {
+
+template <int D, int N>
+struct Blk {
+    static constexpr int NH = N / 2;
+    static constexpr int CPB = D == 3 ? N * N * N : N * N;
+    static constexpr int HALF = CPB / 2;
+    static constexpr int THREADS = HALF >= 256 ? 256 : (HALF >= 64 ? HALF : 64);
+};
+
+template <int D, int N>
+__device__ __forceinline__ int split_of(int i, int j, int k) {
+    return ((i + j + k) & 1) * Blk<D, N>::HALF + (k * N + j) * Blk<D, N>::NH + (i >> 1);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ int block_at(const LV<T> &L, int bx, int by, int bz) {
+    if (bx < 0 || by < 0 || bx >= L.nb || by >= L.nb) return -2;
+    if (D == 3 && (bz < 0 || bz >= L.nb)) return -2;
+    return L.lut[D == 3 ? (bz * L.nb + by) * L.nb + bx : by * L.nb + bx];
+}
+
+template <int D>
+__device__ __forceinline__ int face_slot(int ax, int s, int gi, int gj, int gk, int n, int nface) {
+    int t;
+    if (D == 3) t = ax == 0 ? gk * n + gj : (ax == 1 ? gk * n + gi : gj * n + gi);
+    else t = ax == 0 ? gj : gi;
+    return (2 * ax + (s > 0)) * nface + t;
+}
+
+// value at global cell Q of a level (block edge NB); Q inside the domain
+template <typename T, int D, int NB>
+__device__ __forceinline__ T level_value(const LV<T> &L, const T *f, int qi, int qj, int qk) {
+    const int b = block_at<T, D>(L, qi / NB, qj / NB, D == 3 ? qk / NB : 0);
+    if (b < 0) return T(0);  // excluded by 2:1 balance
+    return f[(long long)b * Blk<D, NB>::CPB + split_of<D, NB>(qi % NB, qj % NB, D == 3 ? qk % NB : 0)];
+}
+
+// refinement-boundary ghost for fine cell G in direction (ax, s)
+template <typename T, int D, int N>
+__device__ __noinline__ T cf_ghost(const LV<T> &Lc, const T *phic, int gi, int gj, int gk, int ax, int s, T f1,
+                                   T f2) {
+    int ng[3] = {gi, gj, gk};
+    ng[ax] += s;
+    const int C[3] = {ng[0] >> 1, ng[1] >> 1, D == 3 ? ng[2] >> 1 : 0};
+    const T Cv = level_value<T, D, N>(Lc, phic, C[0], C[1], C[2]);
+    T Ck = Cv;
+    for (int t = 0; t < D; t++) {
+        if (t == ax) continue;
+        const T st = (ng[t] & 1) ? T(1) : T(-1);
+        int P[3] = {C[0], C[1], C[2]}, M[3] = {C[0], C[1], C[2]};
+        P[t] += 1;
+        M[t] -= 1;
+        T cp, cm;
+        if (P[t] >= Lc.n) {
+            T bv = Lc.bcv ? Lc.bcv[face_slot<D>(t, 1, C[0], C[1], C[2], Lc.n, Lc.nface)] : T(0);
+            cp = T(2) * bv - Cv;
+        } else {
+            cp = level_value<T, D, N>(Lc, phic, P[0], P[1], P[2]);
+        }
+        if (M[t] < 0) {
+            T bv = Lc.bcv ? Lc.bcv[face_slot<D>(t, -1, C[0], C[1], C[2], Lc.n, Lc.nface)] : T(0);
+            cm = T(2) * bv - Cv;
+        } else {
+            cm = level_value<T, D, N>(Lc, phic, M[0], M[1], M[2]);
+        }
+        Ck = Ck + st * (cp - cm) / T(8);
+    }
+    return T(0.5) * Ck + T(0.75) * f1 - T(0.25) * f2;
+}
+
+// The 2D neighbour values (ghosts included) of local cell (i,j,k) of block
+// `blk`.  `own` is the cell's current value (needed only by ghosts).
+template <typename T, int D, int N, bool ZERO>
+__device__ __forceinline__ void gather(const LV<T> &L, const LV<T> &Lc, const T *phi, const T *phic,
+                                       long long base, const int *snb, int4 P, int i, int j, int k, T own,
+                                       T v[2 * D]) {
+    int pending = 0;
+#pragma unroll
+    for (int d = 0; d < 2 * D; d++) {
+        const int ax = d >> 1, s = (d & 1) ? 1 : -1;
+        int c[3] = {i, j, k};
+        c[ax] += s;
+        if (ZERO) {
+            v[d] = T(0);
+            if (c[ax] < 0 || c[ax] >= N) {
+                const int nbk = snb[d];
+                if (nbk == -2) {
+                    const int gi = P.x * N + i, gj = P.y * N + j, gk = D == 3 ? P.z * N + k : 0;
+                    v[d] = L.bcv ? T(2) * L.bcv[face_slot<D>(ax, s, gi, gj, gk, L.n, L.nface)] : T(0);
+                }
+            }
+            continue;
+        }
+        if (c[ax] >= 0 && c[ax] < N) {
+            v[d] = phi[base + split_of<D, N>(c[0], c[1], c[2])];
+        } else {
+            const int nbk = snb[d];
+            c[ax] = c[ax] < 0 ? N - 1 : 0;
+            if (nbk >= 0) {
+                v[d] = phi[(long long)nbk * Blk<D, N>::CPB + split_of<D, N>(c[0], c[1], c[2])];
+            } else if (nbk == -2) {
+                const int gi = P.x * N + i, gj = P.y * N + j, gk = D == 3 ? P.z * N + k : 0;
+                const T bv = L.bcv ? L.bcv[face_slot<D>(ax, s, gi, gj, gk, L.n, L.nface)] : T(0);
+                v[d] = T(2) * bv - own;
+            } else {
+                pending |= 1 << d;
+                v[d] = T(0);
+            }
+        }
+    }
+    if (pending) {
+#pragma unroll
+        for (int d = 0; d < 2 * D; d++) {
+            if (!(pending >> d & 1)) continue;
+            const int ax = d >> 1, s = (d & 1) ? 1 : -1;
+            const int gi = P.x * N + i, gj = P.y * N + j, gk = D == 3 ? P.z * N + k : 0;
+            v[d] = cf_ghost<T, D, N>(Lc, phic, gi, gj, gk, ax, s, own, v[d ^ 1]);
+        }
+    }
+}
+
+template <typename T, int D, int N>
+__device__ __forceinline__ bool on_block_face(int i, int j, int k) {
+    return i == 0 || i == N - 1 || j == 0 || j == N - 1 || (D == 3 && (k == 0 || k == N - 1));
+}
+
+template <typename T>
+__device__ __forceinline__ bool inactive(const LV<T> &L) {
+    return L.active && !L.active[blockIdx.y];
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void load_neighbours(const LV<T> &L, int4 P, int *snb, int *smo, int b) {
+    if ((int)threadIdx.x < 2 * D) {
+        const int d = threadIdx.x, ax = d >> 1, s = (d & 1) ? 1 : -1;
+        int q[3] = {P.x, P.y, P.z};
+        q[ax] += s;
+        snb[d] = block_at<T, D>(L, q[0], q[1], q[2]);
+    }
+    if (threadIdx.x == 0) *smo = L.map_off ? L.map_off[b] : -1;
+}
+
+// ------------------------------------------------------ red-black sweep
+// One colour of Gauss-Seidel (Sec. 2.2): phi_i <- (g_i - b_i - sum_uncut
+// c_ij phi_j) / c_ii, all cells of `color` of the level.
+template <typename T, int D, int N>
+__global__ __launch_bounds__((Blk<D, N>::THREADS)) void k_gs_half(LV<T> L, LV<T> Lc, int color) {
+    if (inactive(L)) return;
+    using B = Blk<D, N>;
+    const int blk = blockIdx.x;
+    __shared__ int snb[2 * D];
+    __shared__ int smo;
+    const int4 P = L.pos[blk];
+    load_neighbours<T, D>(L, P, snb, &smo, blk);
+    __syncthreads();
+    T *phi = L.phi + (long long)blockIdx.y * L.fstride;
+    const T *g = L.g + (long long)blockIdx.y * L.fstride;
+    const T *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
+    const long long base = (long long)blk * B::CPB;
+    const int mo = smo;
+    const T inv2d = T(1) / T(2 * D);
+    for (int q = threadIdx.x; q < B::HALF; q += B::THREADS) {
+        const int h = q % B::NH, j = (q / B::NH) % N, k = D == 3 ? q / (B::NH * N) : 0;
+        const int i = 2 * h + ((color + j + k) & 1);
+        const long long me = base + color * B::HALF + q;
+        const T own = on_block_face<T, D, N>(i, j, k) ? phi[me] : T(0);
+        T v[2 * D];
+        gather<T, D, N, false>(L, Lc, phi, phic, base, snb, P, i, j, k, own, v);
+        const int ri = mo >= 0 ? L.map[mo + color * B::HALF + q] : -1;
+        T nv;
+        if (ri < 0) {
+            T s = v[0];
+#pragma unroll
+            for (int d = 1; d < 2 * D; d++) s += v[d];
+            nv = (s - L.dx2 * g[me]) * inv2d;
+        } else {
+            const T *r = L.rec + 8 * (long long)ri;
+            T s = T(0);
+#pragma unroll
+            for (int d = 0; d < 2 * D; d++) s += r[d] * v[d];
+            const T bt = L.b ? L.b[ri] : T(0);
+            nv = (g[me] - bt - s) * r[7];
+        }
+        phi[me] = nv;
+    }
+}
+
+// L phi at a cell (Sec. 3.3): sum c_j phi_j + c_ii phi_i + b_i
+template <typename T, int D, int N, bool ZERO>
+__device__ __forceinline__ T apply_op(const LV<T> &L, const LV<T> &Lc, const T *phi, const T *phic, long long base,
+                                      const int *snb, int4 P, int mo, int i, int j, int k, T own) {
+    T v[2 * D];
+    gather<T, D, N, ZERO>(L, Lc, phi, phic, base, snb, P, i, j, k, own, v);
+    const int si = split_of<D, N>(i, j, k);
+    const int ri = mo >= 0 ? L.map[mo + si] : -1;
+    if (ri < 0) {
+        T s = v[0];
+#pragma unroll
+        for (int d = 1; d < 2 * D; d++) s += v[d];
+        return L.inv_dx2 * (s - T(2 * D) * own);
+    }
+    const T *r = L.rec + 8 * (long long)ri;
+    T s = T(0);
+#pragma unroll
+    for (int d = 0; d < 2 * D; d++) s += r[d] * v[d];
+    const T bt = L.b ? L.b[ri] : T(0);
+    return s + r[6] * own + bt;
+}
+
+// ------------------------------------------------------- restriction
+// FAS restriction (Sec. 2.2): phi_c = mean of the 2^D children, and the
+// coarse g holds the mean of the children's residuals until k_fas_rhs adds
+// L_c phi_c.  One workgroup per fine block; thread per coarse cell.
+template <typename T, int D, int N, int NC>
+__global__ __launch_bounds__(256) void k_restrict_fas(LV<T> L, LV<T> Lc, int into_old) {
+    if (inactive(L)) return;
+    constexpr int H = N / 2, NCELL = D == 3 ? H * H * H : H * H;
+    const int blk = blockIdx.x;
+    __shared__ int snb[2 * D];
+    __shared__ int smo;
+    const int4 P = L.pos[blk];
+    load_neighbours<T, D>(L, P, snb, &smo, blk);
+    __syncthreads();
+    const T *phi = L.phi + (long long)blockIdx.y * L.fstride;
+    const T *g = L.g + (long long)blockIdx.y * L.fstride;
+    const T *phic = Lc.phi + (long long)blockIdx.y * Lc.fstride;
+    T *phiw = (into_old ? Lc.old : Lc.phi) + (long long)blockIdx.y * Lc.fstride;
+    T *gw = Lc.g + (long long)blockIdx.y * Lc.fstride;
+    const long long base = (long long)blk * Blk<D, N>::CPB;
+    const int C0[3] = {P.x * H, P.y * H, D == 3 ? P.z * H : 0};
+    const int pb = block_at<T, D>(Lc, C0[0] / NC, C0[1] / NC, D == 3 ? C0[2] / NC : 0);
+    const T inv = T(1) / T(1 << D);
+    for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
+        const int ci = c % H, cj = (c / H) % H, ck = D == 3 ? c / (H * H) : 0;
+        T sp = T(0), sr = T(0);
+#pragma unroll
+        for (int ch = 0; ch < (1 << D); ch++) {
+            const int i = 2 * ci + (ch & 1), j = 2 * cj + ((ch >> 1) & 1), k = D == 3 ? 2 * ck + ((ch >> 2) & 1) : 0;
+            const T own = phi[base + split_of<D, N>(i, j, k)];
+            const T lphi = apply_op<T, D, N, false>(L, Lc, phi, phic, base, snb, P, smo, i, j, k, own);
+            sp += own;
+            sr += g[base + split_of<D, N>(i, j, k)] - lphi;
+        }
+        const int gi = C0[0] + ci, gj = C0[1] + cj, gk = C0[2] + ck;
+        const long long o = (long long)pb * Blk<D, NC>::CPB + split_of<D, NC>(gi % NC, gj % NC, D == 3 ? gk % NC : 0);
+        phiw[o] = sp * inv;
+        gw[o] = sr * inv;
+    }
+}
+
+template <typename T, int D, int N>
+__global__ __launch_bounds__(256) void k_copy_parents(LV<T> L) {
+    if (inactive(L)) return;
+    const int blk = blockIdx.x;
+    if (L.leaf[blk]) return;
+    const long long o = (long long)blockIdx.y * L.fstride + (long long)blk * Blk<D, N>::CPB;
+    for (int c = threadIdx.x; c < Blk<D, N>::CPB; c += blockDim.x) L.phi[o + c] = L.old[o + c];
+}
+
+// restriction of the rhs for a first FMG without initial guess
+template <typename T, int D, int N, int NC>
+__global__ __launch_bounds__(256) void k_restrict_rhs(LV<T> L, LV<T> Lc) {
+    if (inactive(L)) return;
+    constexpr int H = N / 2, NCELL = D == 3 ? H * H * H : H * H;
+    const int blk = blockIdx.x;
+    const int4 P = L.pos[blk];
+    const T *g = L.g + (long long)blockIdx.y * L.fstride;
+    T *gw = Lc.g + (long long)blockIdx.y * Lc.fstride;
+    const long long base = (long long)blk * Blk<D, N>::CPB;
+    const int C0[3] = {P.x * H, P.y * H, D == 3 ? P.z * H : 0};
+    const int pb = block_at<T, D>(Lc, C0[0] / NC, C0[1] / NC, D == 3 ? C0[2] / NC : 0);
+    const T inv = T(1) / T(1 << D);
+    for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
+        const int ci = c % H, cj = (c / H) % H, ck = D == 3 ? c / (H * H) : 0;
+        T s = T(0);
+#pragma unroll
+        for (int ch = 0; ch < (1 << D); ch++) {
+            const int i = 2 * ci + (ch & 1), j = 2 * cj + ((ch >> 1) & 1), k = D == 3 ? 2 * ck + ((ch >> 2) & 1) : 0;
+            s += g[base + split_of<D, N>(i, j, k)];
+        }
+        const int gi = C0[0] + ci, gj = C0[1] + cj, gk = C0[2] + ck;
+        gw[(long long)pb * Blk<D, NC>::CPB + split_of<D, NC>(gi % NC, gj % NC, D == 3 ? gk % NC : 0)] = s * inv;
+    }
+}
+
+// phi_c = mean of children only (composite-grid synchronisation)
+template <typename T, int D, int N, int NC>
+__global__ __launch_bounds__(256) void k_restrict_phi(LV<T> L, LV<T> Lc) {
+    if (inactive(L)) return;
+    constexpr int H = N / 2, NCELL = D == 3 ? H * H * H : H * H;
+    const int blk = blockIdx.x;
+    const int4 P = L.pos[blk];
+    const T *phi = L.phi + (long long)blockIdx.y * L.fstride;
+    T *pw = Lc.phi + (long long)blockIdx.y * Lc.fstride;
+    const long long base = (long long)blk * Blk<D, N>::CPB;
+    const int C0[3] = {P.x * H, P.y * H, D == 3 ? P.z * H : 0};
+    const int pb = block_at<T, D>(Lc, C0[0] / NC, C0[1] / NC, D == 3 ? C0[2] / NC : 0);
+    const T inv = T(1) / T(1 << D);
+    for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
+        const int ci = c % H, cj = (c / H) % H, ck = D == 3 ? c / (H * H) : 0;
+        T s = T(0);
+#pragma unroll
+        for (int ch = 0; ch < (1 << D); ch++) {
+            const int i = 2 * ci + (ch & 1), j = 2 * cj + ((ch >> 1) & 1), k = D == 3 ? 2 * ck + ((ch >> 2) & 1) : 0;
+            s += phi[base + split_of<D, N>(i, j, k)];
+        }
+        const int gi = C0[0] + ci, gj = C0[1] + cj, gk = C0[2] + ck;
+        pw[(long long)pb * Blk<D, NC>::CPB + split_of<D, NC>(gi % NC, gj % NC, D == 3 ? gk % NC : 0)] = s * inv;
+    }
+}
+
+// FAS right-hand side on parent blocks: g = L phi + (restricted residual);
+// old = phi on every block of the level.  Coarse ghosts must be current,
+// hence a launch of its own after the restriction.
+template <typename T, int D, int N>
+__global__ __launch_bounds__((Blk<D, N>::THREADS)) void k_fas_rhs(LV<T> L, LV<T> Lc, int do_rhs) {
+    if (inactive(L)) return;
+    using B = Blk<D, N>;
+    const int blk = blockIdx.x;
+    __shared__ int snb[2 * D];
+    __shared__ int smo;
+    const int4 P = L.pos[blk];
+    load_neighbours<T, D>(L, P, snb, &smo, blk);
+    __syncthreads();
+    T *phi = L.phi + (long long)blockIdx.y * L.fstride;
+    T *g = L.g + (long long)blockIdx.y * L.fstride;
+    T *old = L.old + (long long)blockIdx.y * L.fstride;
+    const T *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
+    const long long base = (long long)blk * B::CPB;
+    const bool parent = !L.leaf[blk];
+    for (int c = threadIdx.x; c < B::CPB; c += B::THREADS) {
+        const int i = c % N, j = (c / N) % N, k = D == 3 ? c / (N * N) : 0;
+        const long long me = base + split_of<D, N>(i, j, k);
+        const T own = phi[me];
+        if (parent && do_rhs) {
+            const T lphi = apply_op<T, D, N, false>(L, Lc, phi, phic, base, snb, P, smo, i, j, k, own);
+            g[me] = lphi + g[me];
+        }
+        old[me] = own;
+    }
+}
+
+// ------------------------------------------------------ prolongation
+// phi_f += sum over the 2^D nearest coarse cells of prod_a (3/4 | 1/4) e_c,
+// e_c = phi_c - old_c (Sec. 2.2, 3.4); outside the domain e_c is reflected
+// with a sign flip per axis.  Solution mode (first FMG without guess): e_c =
+// phi_c with Dirichlet ghosts, linear extrapolation at edges/corners.
+template <typename T, int D, int NC>
+__device__ T coarse_e(const LV<T> &Lc, const T *phic, const T *oldc, int x0, int x1, int x2, int solution) {
+    int q[3] = {x0, x1, x2};
+    int out = -1, nout = 0;
+    for (int a = 0; a < D; a++)
+        if (q[a] < 0 || q[a] >= Lc.n) {
+            nout++;
+            if (out < 0) out = a;
+        }
+    if (!solution) {
+        T sign = T(1);
+        for (int a = 0; a < D; a++) {
+            if (q[a] < 0) { q[a] = 0; sign = -sign; }
+            else if (q[a] >= Lc.n) { q[a] = Lc.n - 1; sign = -sign; }
+        }
+        const int b = block_at<T, D>(Lc, q[0] / NC, q[1] / NC, D == 3 ? q[2] / NC : 0);
+        if (b < 0) return T(0);
+        const long long o = (long long)b * Blk<D, NC>::CPB + split_of<D, NC>(q[0] % NC, q[1] % NC, D == 3 ? q[2] % NC : 0);
+        return sign * (phic[o] - oldc[o]);
+    }
+    if (nout == 0) return level_value<T, D, NC>(Lc, phic, q[0], q[1], q[2]);
+    // solution mode: extrapolate along the first outside axis until one face
+    // ghost remains: value(q) = 2 value(q - s e) - value(q - 2 s e)
+    const int s = q[out] < 0 ? -1 : 1;
+    if (nout == 1) {
+        int qi[3] = {q[0], q[1], q[2]};
+        qi[out] -= s;
+        const T bv = Lc.bcv ? Lc.bcv[face_slot<D>(out, s, qi[0], qi[1], qi[2], Lc.n, Lc.nface)] : T(0);
+        return T(2) * bv - level_value<T, D, NC>(Lc, phic, qi[0], qi[1], qi[2]);
+    }
+    // nout >= 2: both shifted points remain outside in the other axes
+    T acc = T(0);
+    // expand 2 v(q1) - v(q2) with v evaluated recursively (depth <= 2 more)
+    int q1[3] = {q[0], q[1], q[2]}, q2[3] = {q[0], q[1], q[2]};
+    q1[out] -= s;
+    q2[out] -= 2 * s;
+    T v1, v2;
+    {
+        // second outside axis
+        int o2 = -1, n2 = 0;
+        for (int a = 0; a < D; a++)
+            if (q1[a] < 0 || q1[a] >= Lc.n) {
+                n2++;
+                if (o2 < 0) o2 = a;
+            }
+        auto face1 = [&](const int *p, int ax) -> T {
+            const int ss = p[ax] < 0 ? -1 : 1;
+            int pi[3] = {p[0], p[1], p[2]};
+            pi[ax] -= ss;
+            const T bv = Lc.bcv ? Lc.bcv[face_slot<D>(ax, ss, pi[0], pi[1], pi[2], Lc.n, Lc.nface)] : T(0);
+            return T(2) * bv - level_value<T, D, NC>(Lc, phic, pi[0], pi[1], pi[2]);
+        };
+        auto eval = [&](const int *p) -> T {
+            int oo = -1, nn = 0;
+            for (int a = 0; a < D; a++)
+                if (p[a] < 0 || p[a] >= Lc.n) {
+                    nn++;
+                    if (oo < 0) oo = a;
+                }
+            if (nn == 1) return face1(p, oo);
+            // nn == 2 (3D corner after one shift)
+            const int ss = p[oo] < 0 ? -1 : 1;
+            int p1[3] = {p[0], p[1], p[2]}, p2[3] = {p[0], p[1], p[2]};
+            p1[oo] -= ss;
+            p2[oo] -= 2 * ss;
+            int o3 = -1;
+            for (int a = 0; a < D; a++)
+                if (p1[a] < 0 || p1[a] >= Lc.n) { o3 = a; break; }
+            return T(2) * face1(p1, o3) - face1(p2, o3);
+        };
+        (void)n2;
+        (void)o2;
+        v1 = eval(q1);
+        v2 = eval(q2);
+    }
+    acc = T(2) * v1 - v2;
+    return acc;
+}
+
+template <typename T, int D, int N, int NC>
+__global__ __launch_bounds__(256) void k_prolong(LV<T> L, LV<T> Lc, int solution) {
+    if (inactive(L)) return;
+    constexpr int H = N / 2, NCELL = D == 3 ? H * H * H : H * H;
+    const int blk = blockIdx.x;
+    const int4 P = L.pos[blk];
+    T *phi = L.phi + (long long)blockIdx.y * L.fstride;
+    const T *phic = Lc.phi + (long long)blockIdx.y * Lc.fstride;
+    const T *oldc = Lc.old + (long long)blockIdx.y * Lc.fstride;
+    const long long base = (long long)blk * Blk<D, N>::CPB;
+    const int C0[3] = {P.x * H, P.y * H, D == 3 ? P.z * H : 0};
+    for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
+        const int ci = c % H, cj = (c / H) % H, ck = D == 3 ? c / (H * H) : 0;
+        const int G[3] = {C0[0] + ci, C0[1] + cj, C0[2] + ck};
+        T E[D == 3 ? 27 : 9];
+#pragma unroll
+        for (int z = 0; z < (D == 3 ? 3 : 1); z++)
+#pragma unroll
+            for (int y = 0; y < 3; y++)
+#pragma unroll
+                for (int x = 0; x < 3; x++)
+                    E[(z * 3 + y) * 3 + x] =
+                        coarse_e<T, D, NC>(Lc, phic, oldc, G[0] + x - 1, G[1] + y - 1, D == 3 ? G[2] + z - 1 : 0, solution);
+#pragma unroll
+        for (int ch = 0; ch < (1 << D); ch++) {
+            const int a = ch & 1, bb = (ch >> 1) & 1, cc = (ch >> 2) & 1;
+            const int o[3] = {a ? 1 : -1, bb ? 1 : -1, cc ? 1 : -1};
+            T e = T(0);
+#pragma unroll
+            for (int dl = 0; dl < (1 << D); dl++) {
+                T w = T(1);
+                int idx[3] = {1, 1, 1};
+#pragma unroll
+                for (int ax = 0; ax < D; ax++) {
+                    const int on = (dl >> ax) & 1;
+                    w = w * (on ? T(0.25) : T(0.75));
+                    if (on) idx[ax] += o[ax];
+                }
+                e = e + w * E[((D == 3 ? idx[2] : 0) * 3 + idx[1]) * 3 + idx[0]];
+            }
+            const int i = 2 * ci + a, j = 2 * cj + bb, k = D == 3 ? 2 * ck + cc : 0;
+            phi[base + split_of<D, N>(i, j, k)] += e;
+        }
+    }
+}
+
+// ------------------------------------------------------ coarse solve
+// Exact solve on the single-block coarsest grid (8^D cells): rhs_i = S_i (g_i
+// - b_i - sum over uncut domain links 2 c phi_b), phi = M rhs, where M is the
+// inverse of the row-equilibrated operator.  Grid: x = row tiles, y = rhs.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_coarse_solve(LV<T> L0, const double *M, const double *S) {
+    if (inactive(L0)) return;
+    constexpr int NB = 8, NCELL = D == 3 ? 512 : 64;
+    constexpr int ROWS_PER_WG = D == 3 ? 32 : 16;
+    __shared__ double rhs[NCELL];
+    const T *g = L0.g + (long long)blockIdx.y * L0.fstride;
+    T *phi = L0.phi + (long long)blockIdx.y * L0.fstride;
+    const int mo = L0.map_off ? L0.map_off[0] : -1;
+    const double inv = 1.0 / ((double)L0.dx2);
+    for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
+        const int i = c % NB, j = (c / NB) % NB, k = D == 3 ? c / (NB * NB) : 0;
+        const int si = split_of<D, NB>(i, j, k);
+        const int ri = mo >= 0 ? L0.map[mo + si] : -1;
+        double r = (double)g[si];
+        if (ri >= 0 && L0.b) r -= (double)L0.b[ri];
+        for (int d = 0; d < 2 * D; d++) {
+            const int ax = d >> 1, s = (d & 1) ? 1 : -1;
+            int q[3] = {i, j, k};
+            q[ax] += s;
+            if (q[ax] >= 0 && q[ax] < NB) continue;
+            const double cc = ri >= 0 ? (double)L0.rec[8 * (long long)ri + d] : inv;
+            if (cc == 0.0) continue;
+            const double bv = L0.bcv ? (double)L0.bcv[face_slot<D>(ax, s, i, j, k, NB, L0.nface)] : 0.0;
+            r -= 2.0 * cc * bv;
+        }
+        rhs[c] = S[c] * r;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int row = blockIdx.x * ROWS_PER_WG + wave; row < min(NCELL, (int)(blockIdx.x + 1) * ROWS_PER_WG);
+         row += blockDim.x / 64) {
+        double acc = 0.0;
+        for (int c = lane; c < NCELL; c += 64) acc += M[(long long)row * NCELL + c] * rhs[c];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+        if (lane == 0) {
+            const int i = row % NB, j = (row / NB) % NB, k = D == 3 ? row / (NB * NB) : 0;
+            phi[split_of<D, NB>(i, j, k)] = (T)acc;
+        }
+    }
+}
+
+// ------------------------------------------------------ residual norm
+template <typename T, int D, int N, bool ZERO>
+__global__ __launch_bounds__((Blk<D, N>::THREADS)) void k_residual_max(LV<T> L, LV<T> Lc, unsigned long long *out) {
+    if (inactive(L)) return;
+    using B = Blk<D, N>;
+    const int blk = blockIdx.x;
+    __shared__ int snb[2 * D];
+    __shared__ int smo;
+    __shared__ double wmax[B::THREADS / 64 + 1];
+    if (!L.leaf[blk]) return;
+    const int4 P = L.pos[blk];
+    load_neighbours<T, D>(L, P, snb, &smo, blk);
+    __syncthreads();
+    const T *phi = L.phi + (long long)blockIdx.y * L.fstride;
+    const T *g = L.g + (long long)blockIdx.y * L.fstride;
+    const T *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
+    const long long base = (long long)blk * B::CPB;
+    double m = 0.0;
+    for (int c = threadIdx.x; c < B::CPB; c += B::THREADS) {
+        const int i = c % N, j = (c / N) % N, k = D == 3 ? c / (N * N) : 0;
+        const long long me = base + split_of<D, N>(i, j, k);
+        const T own = ZERO ? T(0) : phi[me];
+        const T lphi = apply_op<T, D, N, ZERO>(L, Lc, phi, phic, base, snb, P, smo, i, j, k, own);
+        m = fmax(m, fabs((double)(g[me] - lphi)));
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+    if (threadIdx.x % 64 == 0) wmax[threadIdx.x / 64] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(B::THREADS + 63) / 64; w++) m = fmax(m, wmax[w]);
+        if (m != m) m = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +Inf
+        atomicMax(out + blockIdx.y, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// ------------------------------------------------------ data movement
+template <int D, int N>
+__global__ void k_scatter_leaf(LV<double> L, const int *lb, const double *src, long long sstride, long long base,
+                               int field) {
+    using B = Blk<D, N>;
+    const int blk = lb[blockIdx.x];
+    double *dst = (field == 0 ? L.phi : L.g) + (long long)blockIdx.y * L.fstride + (long long)blk * B::CPB;
+    const double *s = src + (long long)blockIdx.y * sstride + base + (long long)blockIdx.x * B::CPB;
+    for (int c = threadIdx.x; c < B::CPB; c += blockDim.x) {
+        const int i = c % N, j = (c / N) % N, k = D == 3 ? c / (N * N) : 0;
+        dst[split_of<D, N>(i, j, k)] = s[c];
+    }
+}
+
+template <int D, int N>
+__global__ void k_gather_leaf(LV<double> L, const int *lb, double *dst, long long dstride, long long base) {
+    using B = Blk<D, N>;
+    const int blk = lb[blockIdx.x];
+    const double *src = L.phi + (long long)blockIdx.y * L.fstride + (long long)blk * B::CPB;
+    double *d = dst + (long long)blockIdx.y * dstride + base + (long long)blockIdx.x * B::CPB;
+    for (int c = threadIdx.x; c < B::CPB; c += blockDim.x) {
+        const int i = c % N, j = (c / N) % N, k = D == 3 ? c / (N * N) : 0;
+        d[c] = src[split_of<D, N>(i, j, k)];
+    }
+}
+
+template <int D, int N>
+__global__ void k_level_copy(double *split, double *canon, int to_split) {
+    using B = Blk<D, N>;
+    const long long base = (long long)blockIdx.x * B::CPB;
+    for (int c = threadIdx.x; c < B::CPB; c += blockDim.x) {
+        const int i = c % N, j = (c / N) % N, k = D == 3 ? c / (N * N) : 0;
+        if (to_split) split[base + split_of<D, N>(i, j, k)] = canon[base + c];
+        else canon[base + c] = split[base + split_of<D, N>(i, j, k)];
+    }
+}
+
+// mixed precision: FP64 defect on leaf blocks -> FP32 rhs, FP32 phi = 0
+template <int D, int N>
+__global__ __launch_bounds__((Blk<D, N>::THREADS)) void k_defect(LV<double> L, LV<double> Lc, LV<float> L32,
+                                                                const int *lb, unsigned long long *out) {
+    if (inactive(L)) return;
+    using B = Blk<D, N>;
+    const int blk = lb[blockIdx.x];
+    __shared__ int snb[2 * D];
+    __shared__ int smo;
+    __shared__ double wmax[B::THREADS / 64 + 1];
+    const int4 P = L.pos[blk];
+    load_neighbours<double, D>(L, P, snb, &smo, blk);
+    __syncthreads();
+    const double *phi = L.phi + (long long)blockIdx.y * L.fstride;
+    const double *g = L.g + (long long)blockIdx.y * L.fstride;
+    const double *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
+    float *g32 = L32.g + (long long)blockIdx.y * L32.fstride;
+    float *p32 = L32.phi + (long long)blockIdx.y * L32.fstride;
+    const long long base = (long long)blk * B::CPB;
+    double m = 0.0;
+    for (int c = threadIdx.x; c < B::CPB; c += B::THREADS) {
+        const int i = c % N, j = (c / N) % N, k = D == 3 ? c / (N * N) : 0;
+        const long long me = base + split_of<D, N>(i, j, k);
+        const double own = phi[me];
+        const double r = g[me] - apply_op<double, D, N, false>(L, Lc, phi, phic, base, snb, P, smo, i, j, k, own);
+        m = fmax(m, fabs(r));
+        g32[me] = (float)r;
+        p32[me] = 0.0f;
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+    if (threadIdx.x % 64 == 0) wmax[threadIdx.x / 64] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(B::THREADS + 63) / 64; w++) m = fmax(m, wmax[w]);
+        if (m != m) m = __longlong_as_double(0x7ff0000000000000ll);
+        atomicMax(out + blockIdx.y, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+template <int D, int N>
+__global__ void k_update(LV<double> L, LV<float> L32, const int *lb) {
+    if (inactive(L)) return;
+    using B = Blk<D, N>;
+    const int blk = lb[blockIdx.x];
+    double *phi = L.phi + (long long)blockIdx.y * L.fstride + (long long)blk * B::CPB;
+    const float *e = L32.phi + (long long)blockIdx.y * L32.fstride + (long long)blk * B::CPB;
+    for (int c = threadIdx.x; c < B::CPB; c += blockDim.x) phi[c] += (double)e[c];
+}
+
+__global__ void k_boundary_terms(int D, const int *meta, const double *cfull, int nrec, const double *vals,
+                                 double *b64, float *b32) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrec) return;
+    const int cut = meta[4 * r + 2];
+    int p = meta[4 * r + 3];
+    double b = 0.0;
+    for (int k = 0; k < 2 * D; k++) {
+        if (!(cut >> k & 1)) continue;
+        b = b + cfull[6 * r + k] * (vals ? vals[p] : 0.0);
+        p++;
+    }
+    b64[r] = b;
+    if (b32) b32[r] = (float)b;
+}
+
+__global__ void k_fill(double *p, long long n, double v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fillf(float *p, long long n, float v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u64(unsigned long long *p, long long n, unsigned long long v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_copy_d2f(const double *s, float *d, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        d[i] = (float)s[i];
+}
+__global__ void k_check_finite(const double *p, long long n, int *flag) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        if (!isfinite(p[i])) atomicOr(flag, 1);
+}
+
+int grid_for(long long n) {
+    long long g = (n + 255) / 256;
+    return (int)(g < 4096 ? (g < 1 ? 1 : g) : 4096);
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- dispatch
+#define OCTMG_DN(D_, N_, CALL) \
+    if (D == D_ && N == N_) { CALL; return hipGetLastError(); }
+
+template <typename T>
+hipError_t launch_gs_half(int D, int N, const LV<T> &L, const LV<T> &Lc, int color, int nrhs, hipStream_t s) {
+    if (L.nblocks == 0) return hipSuccess;
+    dim3 grid(L.nblocks, nrhs);
+#define GS(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_gs_half<T, D_, N_>), grid, dim3(Blk<D_, N_>::THREADS), 0, s, L, Lc, color))
+    GS(3, 16) GS(3, 8) GS(2, 8) GS(2, 16)
+#undef GS
+    return hipErrorInvalidValue;
+}
+
+#define OCTMG_DNC(D_, N_, NC_, CALL) \
+    if (D == D_ && N == N_ && Nc == NC_) { CALL; return hipGetLastError(); }
+
+template <typename T>
+hipError_t launch_restrict_fas(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int into_old, int nrhs,
+                               hipStream_t s) {
+    if (L.nblocks == 0) return hipSuccess;
+    dim3 grid(L.nblocks, nrhs);
+#define RF(D_, N_, NC_) OCTMG_DNC(D_, N_, NC_, hipLaunchKernelGGL((k_restrict_fas<T, D_, N_, NC_>), grid, dim3(256), 0, s, L, Lc, into_old))
+    RF(3, 16, 16) RF(3, 16, 8) RF(3, 8, 8) RF(2, 8, 8) RF(2, 16, 16) RF(2, 16, 8)
+#undef RF
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_copy_parents(int D, int N, const LV<T> &L, int nrhs, hipStream_t s) {
+    if (L.nblocks == 0) return hipSuccess;
+    dim3 grid(L.nblocks, nrhs);
+#define CP(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_copy_parents<T, D_, N_>), grid, dim3(256), 0, s, L))
+    CP(3, 16) CP(3, 8) CP(2, 8) CP(2, 16)
+#undef CP
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_restrict_rhs(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int nrhs, hipStream_t s) {
+    if (L.nblocks == 0) return hipSuccess;
+    dim3 grid(L.nblocks, nrhs);
+#define RR(D_, N_, NC_) OCTMG_DNC(D_, N_, NC_, hipLaunchKernelGGL((k_restrict_rhs<T, D_, N_, NC_>), grid, dim3(256), 0, s, L, Lc))
+    RR(3, 16, 16) RR(3, 16, 8) RR(3, 8, 8) RR(2, 8, 8) RR(2, 16, 16) RR(2, 16, 8)
+#undef RR
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_restrict_phi(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int nrhs, hipStream_t s) {
+    if (L.nblocks == 0) return hipSuccess;
+    dim3 grid(L.nblocks, nrhs);
+#define RP(D_, N_, NC_) OCTMG_DNC(D_, N_, NC_, hipLaunchKernelGGL((k_restrict_phi<T, D_, N_, NC_>), grid, dim3(256), 0, s, L, Lc))
+    RP(3, 16, 16) RP(3, 16, 8) RP(3, 8, 8) RP(2, 8, 8) RP(2, 16, 16) RP(2, 16, 8)
+#undef RP
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_fas_rhs(int D, int N, const LV<T> &L, const LV<T> &Lc, int parents_only, int nrhs, hipStream_t s) {
+    if (L.nblocks == 0) return hipSuccess;
+    dim3 grid(L.nblocks, nrhs);
+#define FR(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_fas_rhs<T, D_, N_>), grid, dim3(Blk<D_, N_>::THREADS), 0, s, L, Lc, parents_only))
+    FR(3, 16) FR(3, 8) FR(2, 8) FR(2, 16)
+#undef FR
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_prolong(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int solution_mode, int nrhs,
+                          hipStream_t s) {
+    if (L.nblocks == 0) return hipSuccess;
+    dim3 grid(L.nblocks, nrhs);
+#define PR(D_, N_, NC_) OCTMG_DNC(D_, N_, NC_, hipLaunchKernelGGL((k_prolong<T, D_, N_, NC_>), grid, dim3(256), 0, s, L, Lc, solution_mode))
+    PR(3, 16, 16) PR(3, 16, 8) PR(3, 8, 8) PR(2, 8, 8) PR(2, 16, 16) PR(2, 16, 8)
+#undef PR
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_coarse_solve(int D, const LV<T> &L0, const double *M, const double *S, int nrhs, hipStream_t s) {
+    if (D == 3) {
+        hipLaunchKernelGGL((k_coarse_solve<T, 3>), dim3(512 / 32, nrhs), dim3(256), 0, s, L0, M, S);
+    } else {
+        hipLaunchKernelGGL((k_coarse_solve<T, 2>), dim3(64 / 16, nrhs), dim3(256), 0, s, L0, M, S);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_residual_max(int D, int N, const LV<T> &L, const LV<T> &Lc, int phi_zero, unsigned long long *out,
+                               int nrhs, hipStream_t s) {
+    if (L.nblocks == 0) return hipSuccess;
+    dim3 grid(L.nblocks, nrhs);
+#define RM(D_, N_)                                                                                                  \
+    if (D == D_ && N == N_) {                                                                                       \
+        if (phi_zero) hipLaunchKernelGGL((k_residual_max<T, D_, N_, true>), grid, dim3(Blk<D_, N_>::THREADS), 0, s, L, Lc, out); \
+        else hipLaunchKernelGGL((k_residual_max<T, D_, N_, false>), grid, dim3(Blk<D_, N_>::THREADS), 0, s, L, Lc, out); \
+        return hipGetLastError();                                                                                   \
+    }
+    RM(3, 16) RM(3, 8) RM(2, 8) RM(2, 16)
+#undef RM
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_scatter_leaf(int D, int N, const LV<double> &L, const int *lb, int nlb, const double *src,
+                               long long src_stride, long long base, int field, int nrhs, hipStream_t s) {
+    if (nlb == 0) return hipSuccess;
+    dim3 grid(nlb, nrhs);
+#define SC(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_scatter_leaf<D_, N_>), grid, dim3(256), 0, s, L, lb, src, src_stride, base, field))
+    SC(3, 16) SC(3, 8) SC(2, 8) SC(2, 16)
+#undef SC
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_gather_leaf(int D, int N, const LV<double> &L, const int *lb, int nlb, double *dst,
+                              long long dst_stride, long long base, int nrhs, hipStream_t s) {
+    if (nlb == 0) return hipSuccess;
+    dim3 grid(nlb, nrhs);
+#define GA(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_gather_leaf<D_, N_>), grid, dim3(256), 0, s, L, lb, dst, dst_stride, base))
+    GA(3, 16) GA(3, 8) GA(2, 8) GA(2, 16)
+#undef GA
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_level_copy(int D, int N, double *split, double *canon, int nblocks, int to_split, hipStream_t s) {
+    if (nblocks == 0) return hipSuccess;
+#define LC(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_level_copy<D_, N_>), dim3(nblocks), dim3(256), 0, s, split, canon, to_split))
+    LC(3, 16) LC(3, 8) LC(2, 8) LC(2, 16)
+#undef LC
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_defect(int D, int N, const LV<double> &L, const LV<double> &Lc, LV<float> L32, const int *lb,
+                         int nlb, unsigned long long *out, int nrhs, hipStream_t s) {
+    if (nlb == 0) return hipSuccess;
+    dim3 grid(nlb, nrhs);
+#define DF(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_defect<D_, N_>), grid, dim3(Blk<D_, N_>::THREADS), 0, s, L, Lc, L32, lb, out))
+    DF(3, 16) DF(3, 8) DF(2, 8) DF(2, 16)
+#undef DF
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_update(int D, int N, const LV<double> &L, LV<float> L32, const int *lb, int nlb, int nrhs,
+                         hipStream_t s) {
+    if (nlb == 0) return hipSuccess;
+    dim3 grid(nlb, nrhs);
+#define UP(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_update<D_, N_>), grid, dim3(256), 0, s, L, L32, lb))
+    UP(3, 16) UP(3, 8) UP(2, 8) UP(2, 16)
+#undef UP
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_boundary_terms(int D, const int *meta, const double *cfull, int nrec, const double *vals,
+                                 double *b64, float *b32, hipStream_t s) {
+    if (nrec == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_boundary_terms, dim3((nrec + 255) / 256), dim3(256), 0, s, D, meta, cfull, nrec, vals, b64, b32);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *p, long long n, double v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_fillf(float *p, long long n, float v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fillf, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long long v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_copy_d2f(const double *src, float *dst, long long n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_d2f, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+hipError_t launch_check_finite(const double *p, long long n, int *flag, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_finite, dim3(grid_for(n)), dim3(256), 0, s, p, n, flag);
+    return hipGetLastError();
+}
+
+#define OCTMG_INST(T)                                                                                              \
+    template hipError_t launch_gs_half<T>(int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t);           \
+    template hipError_t launch_restrict_fas<T>(int, int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t); \
+    template hipError_t launch_copy_parents<T>(int, int, const LV<T> &, int, hipStream_t);                         \
+    template hipError_t launch_restrict_rhs<T>(int, int, int, const LV<T> &, const LV<T> &, int, hipStream_t);      \
+    template hipError_t launch_restrict_phi<T>(int, int, int, const LV<T> &, const LV<T> &, int, hipStream_t);      \
+    template hipError_t launch_fas_rhs<T>(int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t);           \
+    template hipError_t launch_prolong<T>(int, int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t);      \
+    template hipError_t launch_coarse_solve<T>(int, const LV<T> &, const double *, const double *, int, hipStream_t); \
+    template hipError_t launch_residual_max<T>(int, int, const LV<T> &, const LV<T> &, int, unsigned long long *, int, hipStream_t);
+OCTMG_INST(double)
+OCTMG_INST(float)
+
+}  // namespace octmg

@@ -1,0 +1,149 @@
+// Internal declarations of the octree multigrid library (host + device).
+//
+// Device data layout (per level, per right-hand side):
+//   * blocks of N^D cells are stored one after another in the level's Morton
+//     block order (block-major, Sec. 2.1);
+//   * inside a block the cells are split by colour of the red-black
+//     Gauss-Seidel smoother: [colour][N^D/2], colour = (i+j+k) & 1 (red = 0),
+//     and within a colour x is compressed by two: q = (k*N + j)*(N/2) + i/2.
+//     A red half-sweep then reads only black values and writes only red
+//     values, so one smoothing step moves 24 B per cell in FP64 (read phi of
+//     the other colour, read g, write phi) instead of twice that.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "octmg.h"
+
+namespace octmg {
+
+constexpr int kMaxLevels = 24;
+
+// ------------------------------------------------------------ host tree
+struct TreeLevel {
+    int n = 0;    // cells per edge
+    int Nb = 0;   // block edge
+    int nb = 0;   // blocks per edge
+    std::vector<int> pos;       // [nblocks][3], Morton order
+    std::vector<uint8_t> leaf;  // [nblocks]
+    std::vector<int> lut;       // nb^D -> block index or -1
+    int nblocks() const { return (int)leaf.size(); }
+};
+
+struct Tree {
+    int D = 0, N = 0, nsub = 0;
+    bool adaptive = false;
+    std::vector<TreeLevel> lv;  // coarsest first
+};
+
+// Builds the block tree: uniform or near-interface refinement, then 2:1
+// balance over face, edge and corner neighbours (Sec. 2.1).  Returns false
+// with a message on invalid input.
+bool build_tree(const octmg_geom_desc &d, Tree *out, std::string *err);
+
+// Host evaluation of the built-in level sets (block-centre refinement test).
+double lsf_host(const octmg_geom_desc &d, const double *params, const double *x);
+
+// ------------------------------------------------------- device views
+// One level as seen by a kernel.  Field pointers are the rhs-0 base; the
+// kernel adds blockIdx.y * fstride for batched right-hand sides.
+template <typename T>
+struct LV {
+    int n, nb, nblocks, nface;
+    T dx2, inv_dx2;
+    const int *lut;      // nb^D
+    const int4 *pos;     // [nblocks] block coordinates
+    const int *leaf;     // [nblocks]
+    const int *map_off;  // [nblocks] offset of the block's record map, or -1
+    const int *map;      // record index per cell (split order) or -1
+    const T *rec;        // [nrec][8] = c(x-,x+,y-,y+,z-,z+) with cut links 0, diag, 1/diag
+    const T *b;          // [nrec] moved boundary term (nullptr: homogeneous)
+    const T *bcv;        // [2D][nface] domain face values (nullptr: homogeneous)
+    T *phi, *g, *old;
+    long long fstride;
+    const int *active;   // [nrhs] nonzero = right-hand side still iterating (nullptr: all)
+};
+
+// ---------------------------------------------------------- launches
+// All launches are asynchronous on `s`; `nrhs` is the grid's y extent.
+// D in {2,3}; N (block edge of the level) in {8,16}; Nc the coarse level's
+// block edge.  Return hipSuccess or the launch error.
+template <typename T>
+hipError_t launch_gs_half(int D, int N, const LV<T> &L, const LV<T> &Lc, int color, int nrhs, hipStream_t s);
+// phi_c is written to Lc.phi, or to Lc.old when `into_old` (adaptive trees:
+// refinement-boundary ghosts of the fine level still read Lc.phi); then
+// launch_copy_parents moves it to phi on parent blocks.
+template <typename T>
+hipError_t launch_restrict_fas(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int into_old, int nrhs,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_copy_parents(int D, int N, const LV<T> &L, int nrhs, hipStream_t s);
+template <typename T>
+hipError_t launch_restrict_rhs(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int nrhs, hipStream_t s);
+template <typename T>
+hipError_t launch_fas_rhs(int D, int N, const LV<T> &L, const LV<T> &Lc, int parents_only, int nrhs, hipStream_t s);
+template <typename T>
+hipError_t launch_restrict_phi(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int nrhs, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int solution_mode, int nrhs,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_coarse_solve(int D, const LV<T> &L0, const double *M, const double *S, int nrhs, hipStream_t s);
+// max |r| over the leaf blocks of a level into out[rhs] (bit pattern of a
+// non-negative double, combined with atomicMax); phi_zero: residual of 0.
+template <typename T>
+hipError_t launch_residual_max(int D, int N, const LV<T> &L, const LV<T> &Lc, int phi_zero,
+                               unsigned long long *out, int nrhs, hipStream_t s);
+// leaf data <-> level fields (canonical leaf order); lb = leaf block ids.
+hipError_t launch_scatter_leaf(int D, int N, const LV<double> &L, const int *lb, int nlb, const double *src,
+                               long long src_stride, long long base, int field, int nrhs, hipStream_t s);
+hipError_t launch_gather_leaf(int D, int N, const LV<double> &L, const int *lb, int nlb, double *dst,
+                              long long dst_stride, long long base, int nrhs, hipStream_t s);
+// whole-level canonical order <-> split layout (debug accessors)
+hipError_t launch_level_copy(int D, int N, double *split, double *canon, int nblocks, int to_split, hipStream_t s);
+// mixed precision: r64 = g - L phi on leaf blocks -> g32 = (float)r64,
+// phi32 = 0 there, max |r64| into out; and phi64 += phi32 on leaf blocks.
+hipError_t launch_defect(int D, int N, const LV<double> &L, const LV<double> &Lc, LV<float> L32, const int *lb,
+                         int nlb, unsigned long long *out, int nrhs, hipStream_t s);
+hipError_t launch_update(int D, int N, const LV<double> &L, LV<float> L32, const int *lb, int nlb, int nrhs,
+                         hipStream_t s);
+// b_i = sum over cut links of c_link * phi_b(point)
+hipError_t launch_boundary_terms(int D, const int *meta, const double *cfull, int nrec, const double *vals,
+                                 double *b64, float *b32, hipStream_t s);
+hipError_t launch_fill(double *p, long long n, double v, hipStream_t s);
+hipError_t launch_fillf(float *p, long long n, float v, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long long v, hipStream_t s);
+hipError_t launch_copy_d2f(const double *src, float *dst, long long n, hipStream_t s);
+hipError_t launch_check_finite(const double *p, long long n, int *flag, hipStream_t s);
+
+// ------------------------------------------------------------- setup
+// FP64 interface setup of one level (built without FMA contraction).
+struct SetupLevel {
+    int D, n, Nb, nblocks, nb;
+    double dx, lo[3];
+    const int4 *pos;
+    const int *lut;
+    const int *leaf;
+    int lsf_kind, lsf_n;
+    const double *lsf_params;  // device copy
+    double mask_L;             // mask_factor * sqrt(D) * dx
+    double w_min;
+    int nbisect, ngolden;
+};
+// pass 1: per block, the number of custom cells and of cut links
+hipError_t launch_setup_count(const SetupLevel &S, int *counts /*[nblocks][2]*/, hipStream_t s);
+// pass 2: records in canonical order at the given per-block offsets
+hipError_t launch_setup_emit(const SetupLevel &S, const int *rec_off, const int *pt_off, const int *map_off,
+                             int *map, int *meta /*[nrec][4]*/, double *d6, double *cfull /*[nrec][6]*/,
+                             double *rec8, float *rec8f, double *pts, hipStream_t s);
+// coarsest grid: dense operator with domain ghosts folded in, then a
+// row-equilibrated Gauss-Jordan inverse M and scales S (A^-1 = M diag(S)).
+hipError_t launch_coarse_assemble(int D, int Nb, double dx, const int *map, const double *rec8, double *A,
+                                  hipStream_t s);
+hipError_t launch_gauss_jordan(int n, double *A, double *M, double *S, int *fail, hipStream_t s);
+
+}  // namespace octmg

@@ -1,0 +1,436 @@
+// FP64 interface setup on the device.
+//
+// For every cell of a level: the boundary mask of eq. (boundary-mask), the
+// relative distances d of Sec. 3.2 (bisection when a link is bracketed,
+// golden-section bracket search otherwise), the unresolved-boundary search
+// of Sec. 3.6.3 on parent blocks of coarse levels, and the interface stencil
+// of eqs. (lpl-1d-lsf)/(lpl-2d-lsf) with cut links moved to the right-hand
+// side (Sec. 3.6.2).  The level-set decisions must not depend on rounding
+// shortcuts, so this file is compiled with -ffp-contract=off and uses only
+// + - * / sqrt and comparisons (all correctly rounded).
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+#include "octmg_internal.hpp"
+
+namespace octmg {
+namespace {
+
+__device__ double lsf_dev(const SetupLevel &S, const double *x) {
+    const double *p = S.lsf_params;
+    if (S.lsf_kind == OCTMG_LSF_SPHERES) {
+        double best = 0.0;
+        for (int m = 0; m < S.lsf_n; m++) {
+            double ex = x[0] - p[4 * m], ey = x[1] - p[4 * m + 1];
+            double r2 = ex * ex + ey * ey;
+            if (S.D == 3) {
+                double ez = x[2] - p[4 * m + 2];
+                r2 = r2 + ez * ez;
+            }
+            double v = __dsqrt_rn(r2) - p[4 * m + 3];
+            if (m == 0 || v < best) best = v;
+        }
+        return best;
+    }
+    if (S.lsf_kind == OCTMG_LSF_CYLINDER_Z) {
+        double ex = x[0] - p[0], ey = x[1] - p[1];
+        return __dsqrt_rn(ex * ex + ey * ey) - p[2];
+    }
+    return 1.0;
+}
+
+__device__ inline double centre(const SetupLevel &S, int a, int gi) {
+    return S.lo[a] + ((double)gi + 0.5) * S.dx;
+}
+
+__device__ inline void along(const double *a, const double *b, double t, double *x) {
+    for (int c = 0; c < 3; c++) x[c] = a[c] + t * (b[c] - a[c]);
+}
+
+// bisection on [0, thi] of a->b; sign test f(a) f(x) <= 0
+__device__ double bisect(const SetupLevel &S, const double *a, const double *b, double fa, double thi) {
+    double lo = 0.0, hi = thi, x[3];
+    for (int it = 0; it < S.nbisect; it++) {
+        double mid = 0.5 * (lo + hi);
+        along(a, b, mid, x);
+        if (fa * lsf_dev(S, x) <= 0.0) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// root of f on a->b (t in (0,1]); *hit = 0 when no bracket is found within
+// the golden-section evaluation budget
+__device__ double root_on_link(const SetupLevel &S, const double *a, const double *b, double fa, int *hit) {
+    double x[3];
+    *hit = 1;
+    if (fa * lsf_dev(S, b) <= 0.0) return bisect(S, a, b, fa, 1.0);
+    const double rho = 0.5 * (__dsqrt_rn(5.0) - 1.0);
+    double lo = 0.0, hi = 1.0;
+    double t1 = hi - rho * (hi - lo), t2 = lo + rho * (hi - lo);
+    along(a, b, t1, x);
+    double h1 = fa * lsf_dev(S, x);
+    if (h1 <= 0.0) return bisect(S, a, b, fa, t1);
+    along(a, b, t2, x);
+    double h2 = fa * lsf_dev(S, x);
+    if (h2 <= 0.0) return bisect(S, a, b, fa, t2);
+    for (int used = 2; used < S.ngolden; used++) {
+        if (h1 < h2) {
+            hi = t2;
+            t2 = t1;
+            h2 = h1;
+            t1 = hi - rho * (hi - lo);
+            along(a, b, t1, x);
+            h1 = fa * lsf_dev(S, x);
+            if (h1 <= 0.0) return bisect(S, a, b, fa, t1);
+        } else {
+            lo = t1;
+            t1 = t2;
+            h1 = h2;
+            t2 = lo + rho * (hi - lo);
+            along(a, b, t2, x);
+            h2 = fa * lsf_dev(S, x);
+            if (h2 <= 0.0) return bisect(S, a, b, fa, t2);
+        }
+    }
+    *hit = 0;
+    return 1.0;
+}
+
+// Sec. 3.6.3: descent with step w_min towards f = 0, then a line search a->x.
+__device__ int unresolved_search(const SetupLevel &S, const double *a, double fa, double *dout, int *dir,
+                                 double *x0) {
+    const double w = S.w_min;
+    double x[3] = {a[0], a[1], a[2]};
+    const double sgn = fa > 0.0 ? 1.0 : -1.0;
+    const int steps = (int)floor(S.dx / w);
+    int hit = 0;
+    for (int st = 0; st < steps; st++) {
+        double gr[3] = {0.0, 0.0, 0.0}, n2 = 0.0;
+        for (int c = 0; c < S.D; c++) {
+            double xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
+            xp[c] = x[c] + w;
+            xm[c] = x[c] - w;
+            gr[c] = (lsf_dev(S, xp) - lsf_dev(S, xm)) / (2.0 * w);
+            n2 = n2 + gr[c] * gr[c];
+        }
+        double nrm = __dsqrt_rn(n2);
+        if (!(nrm > 0.0)) break;
+        bool leaves = false;
+        for (int c = 0; c < S.D; c++) {
+            double step = -sgn * gr[c] / nrm;
+            x[c] = x[c] + w * step;
+            if (x[c] < S.lo[c] || x[c] > S.lo[c] + 1.0) leaves = true;
+        }
+        if (leaves) break;
+        if (fa * lsf_dev(S, x) <= 0.0) {
+            hit = 1;
+            break;
+        }
+    }
+    if (!hit) return 0;
+    double t = bisect(S, a, x, fa, 1.0), p[3], s2 = 0.0;
+    along(a, x, t, p);
+    for (int c = 0; c < S.D; c++) s2 = s2 + (p[c] - a[c]) * (p[c] - a[c]);
+    double d = __dsqrt_rn(s2) / S.dx;
+    if (!(d < 1.0)) return 0;
+    double best = -1.0;
+    int k = 0;
+    for (int c = 0; c < S.D; c++) {
+        double v = x[c] - a[c];
+        if (v > best) { best = v; k = 2 * c + 1; }
+        if (-v > best) { best = -v; k = 2 * c; }
+    }
+    *dout = d;
+    *dir = k;
+    for (int c = 0; c < 3; c++) x0[c] = p[c];
+    return 1;
+}
+
+struct CellSetup {
+    int cut;
+    double d[6];
+    double x0[6][3];
+};
+
+// returns 1 if the cell carries a custom stencil (at least one cut link)
+__device__ int analyse_cell(const SetupLevel &S, int blk, int li, CellSetup &R) {
+    const int4 p = S.pos[blk];
+    int l[3] = {li % S.Nb, (li / S.Nb) % S.Nb, S.D == 3 ? li / (S.Nb * S.Nb) : 0};
+    int g[3] = {p.x * S.Nb + l[0], p.y * S.Nb + l[1], S.D == 3 ? p.z * S.Nb + l[2] : 0};
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < S.D; c++) a[c] = centre(S, c, g[c]);
+    const double fa = lsf_dev(S, a);
+    double n2 = 0.0;
+    for (int c = 0; c < S.D; c++) {
+        double xp[3] = {a[0], a[1], a[2]}, xm[3] = {a[0], a[1], a[2]};
+        xp[c] = centre(S, c, g[c] + 1);
+        xm[c] = centre(S, c, g[c] - 1);
+        double gc = (lsf_dev(S, xp) - lsf_dev(S, xm)) / (2.0 * S.dx);
+        n2 = n2 + gc * gc;
+    }
+    R.cut = 0;
+    for (int k = 0; k < 6; k++) R.d[k] = 1.0;
+    if (!(fabs(fa) < S.mask_L * __dsqrt_rn(n2))) return 0;
+    for (int k = 0; k < 2 * S.D; k++) {
+        const int ax = k >> 1, s = (k & 1) ? 1 : -1;
+        if (g[ax] + s < 0 || g[ax] + s >= S.n) continue;  // links leaving the domain
+        double b[3] = {a[0], a[1], a[2]};
+        b[ax] = centre(S, ax, g[ax] + s);
+        int hit;
+        double t = root_on_link(S, a, b, fa, &hit);
+        if (hit) {
+            R.d[k] = t;
+            R.cut |= 1 << k;
+            along(a, b, t, R.x0[k]);
+        }
+    }
+    if (!R.cut && !S.leaf[blk] && S.w_min > 0.0 && S.dx > S.w_min) {
+        double d, x0[3];
+        int k;
+        if (unresolved_search(S, a, fa, &d, &k, x0)) {
+            R.d[k] = d;
+            R.cut = 1 << k;
+            for (int c = 0; c < 3; c++) R.x0[k][c] = x0[c];
+        }
+    }
+    return R.cut != 0;
+}
+
+__device__ inline int split_index(int D, int N, int li) {
+    const int i = li % N, j = (li / N) % N, k = D == 3 ? li / (N * N) : 0;
+    const int half = (D == 3 ? N * N * N : N * N) / 2;
+    return ((i + j + k) & 1) * half + (k * N + j) * (N / 2) + (i >> 1);
+}
+
+constexpr int kSetupThreads = 256;
+
+__global__ __launch_bounds__(kSetupThreads) void k_setup_count(SetupLevel S, int *counts) {
+    const int blk = blockIdx.x;
+    const int cpb = S.D == 3 ? S.Nb * S.Nb * S.Nb : S.Nb * S.Nb;
+    int nrec = 0, npt = 0;
+    CellSetup R;
+    for (int li = threadIdx.x; li < cpb; li += blockDim.x) {
+        if (analyse_cell(S, blk, li, R)) {
+            nrec++;
+            npt += __popc(R.cut);
+        }
+    }
+    __shared__ int sr[kSetupThreads], sp[kSetupThreads];
+    sr[threadIdx.x] = nrec;
+    sp[threadIdx.x] = npt;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sr[threadIdx.x] += sr[threadIdx.x + w];
+            sp[threadIdx.x] += sp[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        counts[2 * blk] = sr[0];
+        counts[2 * blk + 1] = sp[0];
+    }
+}
+
+// Records of a block in canonical (x-fastest) cell order: thread t owns the
+// contiguous cells [t*chunk, (t+1)*chunk); an exclusive scan over threads
+// gives every thread its first record and point slot.
+__global__ __launch_bounds__(kSetupThreads) void k_setup_emit(SetupLevel S, const int *rec_off,
+                                                               const int *pt_off, const int *map_off, int *map,
+                                                               int *meta, double *d6, double *cfull, double *rec8,
+                                                               float *rec8f, double *pts) {
+    const int blk = blockIdx.x;
+    const int cpb = S.D == 3 ? S.Nb * S.Nb * S.Nb : S.Nb * S.Nb;
+    const int chunk = (cpb + blockDim.x - 1) / blockDim.x;
+    const int c0 = threadIdx.x * chunk, c1 = min(cpb, c0 + chunk);
+    CellSetup R;
+    int nrec = 0, npt = 0;
+    for (int li = c0; li < c1; li++)
+        if (analyse_cell(S, blk, li, R)) {
+            nrec++;
+            npt += __popc(R.cut);
+        }
+    __shared__ int sr[kSetupThreads], sp[kSetupThreads];
+    sr[threadIdx.x] = nrec;
+    sp[threadIdx.x] = npt;
+    __syncthreads();
+    if (threadIdx.x == 0) {  // exclusive scan (setup only, 256 entries)
+        int a = 0, b = 0;
+        for (int t = 0; t < (int)blockDim.x; t++) {
+            int x = sr[t], y = sp[t];
+            sr[t] = a;
+            sp[t] = b;
+            a += x;
+            b += y;
+        }
+    }
+    __syncthreads();
+    int r = rec_off[blk] + sr[threadIdx.x];
+    int q = pt_off[blk] + sp[threadIdx.x];
+    const double dx2 = S.dx * S.dx;
+    for (int li = c0; li < c1; li++) {
+        if (!analyse_cell(S, blk, li, R)) continue;
+        double c[6] = {0, 0, 0, 0, 0, 0}, diag = 0.0;
+        for (int ax = 0; ax < S.D; ax++) {
+            double dm = R.d[2 * ax], dp = R.d[2 * ax + 1];
+            c[2 * ax] = 2.0 / ((dm + dp) * dm * dx2);
+            c[2 * ax + 1] = 2.0 / ((dm + dp) * dp * dx2);
+            diag = diag - c[2 * ax] - c[2 * ax + 1];
+        }
+        const int si = split_index(S.D, S.Nb, li);
+        meta[4 * r + 0] = blk;
+        meta[4 * r + 1] = si;
+        meta[4 * r + 2] = R.cut;
+        meta[4 * r + 3] = q;
+        for (int k = 0; k < 6; k++) {
+            d6[6 * r + k] = R.d[k];
+            cfull[6 * r + k] = c[k];
+            double hot = (R.cut >> k & 1) ? 0.0 : c[k];
+            rec8[8 * r + k] = hot;
+            rec8f[8 * r + k] = (float)hot;
+        }
+        rec8[8 * r + 6] = diag;
+        rec8[8 * r + 7] = 1.0 / diag;
+        rec8f[8 * r + 6] = (float)diag;
+        rec8f[8 * r + 7] = (float)(1.0 / diag);
+        map[map_off[blk] + si] = r;
+        for (int k = 0; k < 2 * S.D; k++) {
+            if (!(R.cut >> k & 1)) continue;
+            for (int cc = 0; cc < 3; cc++) pts[3 * q + cc] = R.x0[k][cc];
+            q++;
+        }
+        r++;
+    }
+}
+
+// Dense operator of the single-block coarsest grid (canonical cell order),
+// domain ghosts 2 phi_b - phi_in folded into the diagonal.
+__global__ void k_coarse_assemble(int D, int Nb, double dx, const int *map, const double *rec8, double *A) {
+    const int n = D == 3 ? Nb * Nb * Nb : Nb * Nb;
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= n) return;
+    const double inv = 1.0 / (dx * dx);
+    const int i = row % Nb, j = (row / Nb) % Nb, k = D == 3 ? row / (Nb * Nb) : 0;
+    const int ri = map ? map[split_index(D, Nb, row)] : -1;
+    for (int c = 0; c < n; c++) A[(long)row * n + c] = 0.0;
+    double diag = ri >= 0 ? rec8[8 * ri + 6] : -2.0 * D * inv;
+    for (int kk = 0; kk < 2 * D; kk++) {
+        const int ax = kk >> 1, s = (kk & 1) ? 1 : -1;
+        const double c = ri >= 0 ? rec8[8 * ri + kk] : inv;  // 0 for cut links
+        if (c == 0.0) continue;
+        int q[3] = {i, j, k};
+        q[ax] += s;
+        if (q[ax] < 0 || q[ax] >= Nb) {
+            diag -= c;
+            continue;
+        }
+        const int col = D == 3 ? (q[2] * Nb + q[1]) * Nb + q[0] : q[1] * Nb + q[0];
+        A[(long)row * n + col] += c;
+    }
+    A[(long)row * n + row] += diag;
+}
+
+// Row-equilibrated Gauss-Jordan inverse with partial pivoting, one
+// workgroup: S_i = 1 / max_j |A_ij|, M = (diag(S) A)^-1, A^-1 = M diag(S).
+__global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double *A, double *M, double *S, int *fail) {
+    __shared__ double sval[1024];
+    __shared__ int sidx[1024];
+    __shared__ double mult[512];
+    const int t = threadIdx.x, T = blockDim.x;
+    for (int r = t; r < n; r += T) {
+        double m = 0.0;
+        for (int c = 0; c < n; c++) m = fmax(m, fabs(A[(long)r * n + c]));
+        S[r] = m > 0.0 ? 1.0 / m : 1.0;
+    }
+    __syncthreads();
+    for (long e = t; e < (long)n * n; e += T) {
+        const int r = (int)(e / n), c = (int)(e % n);
+        A[e] *= S[r];
+        M[e] = r == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int k = 0; k < n; k++) {
+        double best = -1.0;
+        int bi = k;
+        for (int r = k + t; r < n; r += T) {
+            double v = fabs(A[(long)r * n + k]);
+            if (v > best) { best = v; bi = r; }
+        }
+        sval[t] = best;
+        sidx[t] = bi;
+        __syncthreads();
+        for (int w = T / 2; w > 0; w >>= 1) {
+            if (t < w && (sval[t + w] > sval[t] || (sval[t + w] == sval[t] && sidx[t + w] < sidx[t]))) {
+                sval[t] = sval[t + w];
+                sidx[t] = sidx[t + w];
+            }
+            __syncthreads();
+        }
+        const int p = sidx[0];
+        if (!(sval[0] > 0.0)) {
+            if (t == 0) *fail = 1;
+            return;
+        }
+        if (p != k)
+            for (int c = t; c < n; c += T) {
+                double x = A[(long)k * n + c], y = M[(long)k * n + c];
+                A[(long)k * n + c] = A[(long)p * n + c];
+                M[(long)k * n + c] = M[(long)p * n + c];
+                A[(long)p * n + c] = x;
+                M[(long)p * n + c] = y;
+            }
+        __syncthreads();
+        const double inv = 1.0 / A[(long)k * n + k];
+        __syncthreads();
+        for (int c = t; c < n; c += T) {
+            A[(long)k * n + c] *= inv;
+            M[(long)k * n + c] *= inv;
+        }
+        __syncthreads();
+        for (int r = t; r < n; r += T) mult[r] = r == k ? 0.0 : A[(long)r * n + k];
+        __syncthreads();
+        for (long e = t; e < (long)n * n; e += T) {
+            const int r = (int)(e / n), c = (int)(e % n);
+            const double m = mult[r];
+            if (m != 0.0) {
+                A[e] -= m * A[(long)k * n + c];
+                M[e] -= m * M[(long)k * n + c];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_setup_count(const SetupLevel &S, int *counts, hipStream_t s) {
+    if (S.nblocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_setup_count, dim3(S.nblocks), dim3(kSetupThreads), 0, s, S, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup_emit(const SetupLevel &S, const int *rec_off, const int *pt_off, const int *map_off,
+                             int *map, int *meta, double *d6, double *cfull, double *rec8, float *rec8f,
+                             double *pts, hipStream_t s) {
+    if (S.nblocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_setup_emit, dim3(S.nblocks), dim3(kSetupThreads), 0, s, S, rec_off, pt_off, map_off, map,
+                       meta, d6, cfull, rec8, rec8f, pts);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_assemble(int D, int Nb, double dx, const int *map, const double *rec8, double *A,
+                                  hipStream_t s) {
+    const int n = D == 3 ? Nb * Nb * Nb : Nb * Nb;
+    hipLaunchKernelGGL(k_coarse_assemble, dim3((n + 127) / 128), dim3(128), 0, s, D, Nb, dx, map, rec8, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauss_jordan(int n, double *A, double *M, double *S, int *fail, hipStream_t s) {
+    if (n > 512) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s, n, A, M, S, fail);
+    return hipGetLastError();
+}
+
+}  // namespace octmg

@@ -1,0 +1,199 @@
+// Host construction of the block quadtree/octree (Sec. 2.1 of the paper):
+// blocks of N^D cells, refinement halves the spacing and creates 2^D
+// children, adjacent blocks differ by at most one level (2:1 balance over
+// faces, edges and corners).  Below the root, single-block levels halve the
+// cell count down to the directly solved coarse grid.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "octmg_internal.hpp"
+
+namespace octmg {
+
+double lsf_host(const octmg_geom_desc &d, const double *p, const double *x) {
+    switch (d.lsf_kind) {
+        case OCTMG_LSF_SPHERES: {
+            double best = 0.0;
+            for (int m = 0; m < d.lsf_n; m++) {
+                const double *s = p + 4 * m;
+                double ex = x[0] - s[0], ey = x[1] - s[1];
+                double r2 = ex * ex + ey * ey;
+                if (d.dim == 3) {
+                    double ez = x[2] - s[2];
+                    r2 = r2 + ez * ez;
+                }
+                double v = std::sqrt(r2) - s[3];
+                if (m == 0 || v < best) best = v;
+            }
+            return best;
+        }
+        case OCTMG_LSF_CYLINDER_Z: {
+            double ex = x[0] - p[0], ey = x[1] - p[1];
+            return std::sqrt(ex * ex + ey * ey) - p[2];
+        }
+        default:
+            return 1.0;
+    }
+}
+
+namespace {
+
+// dense occupancy of one tree level
+struct Occ {
+    int D, nb;
+    std::vector<uint8_t> bits;
+    long idx(int x, int y, int z) const { return D == 3 ? ((long)z * nb + y) * nb + x : (long)y * nb + x; }
+    bool has(int x, int y, int z) const { return bits[idx(x, y, z)] != 0; }
+};
+
+uint64_t interleave(int D, int x, int y, int z) {
+    uint64_t key = 0;
+    for (int bit = 0; bit < 21; bit++) {
+        key |= (uint64_t)((x >> bit) & 1) << (D * bit);
+        key |= (uint64_t)((y >> bit) & 1) << (D * bit + 1);
+        if (D == 3) key |= (uint64_t)((z >> bit) & 1) << (D * bit + 2);
+    }
+    return key;
+}
+
+void add_children(std::vector<Occ> &occ, int l, int x, int y, int z) {
+    Occ &f = occ[l + 1];
+    int nz = f.D == 3 ? 2 : 1;
+    for (int c = 0; c < nz; c++)
+        for (int b = 0; b < 2; b++)
+            for (int a = 0; a < 2; a++) f.bits[f.idx(2 * x + a, 2 * y + b, f.D == 3 ? 2 * z + c : 0)] = 1;
+}
+
+}  // namespace
+
+bool build_tree(const octmg_geom_desc &d, Tree *out, std::string *err) {
+    const int D = d.dim, N = d.block_n, lmax = d.max_level;
+    if (D != 2 && D != 3) { *err = "dim must be 2 or 3"; return false; }
+    if (N != 8 && N != 16) { *err = "block_n must be 8 or 16"; return false; }
+    if (d.coarse_n != 8) { *err = "coarse_n must be 8"; return false; }
+    if (lmax < 1 || lmax > 14) { *err = "max_level out of range"; return false; }
+    if (d.lsf_kind == OCTMG_LSF_SPHERES && (d.lsf_n < 1 || !d.lsf_params)) { *err = "spheres need lsf_n >= 1 and params"; return false; }
+    if (d.lsf_kind == OCTMG_LSF_CYLINDER_Z && !d.lsf_params) { *err = "cylinder needs params"; return false; }
+    if (d.lsf_kind < 0 || d.lsf_kind > 2) { *err = "unknown lsf_kind"; return false; }
+    if (d.refine_kind != OCTMG_REFINE_UNIFORM && d.refine_kind != OCTMG_REFINE_NEAR_INTERFACE) { *err = "unknown refine_kind"; return false; }
+    if ((long)N << (lmax - 1) > (1L << 15)) { *err = "grid too large"; return false; }
+
+    // occupancy per tree level 1..lmax (index 0 unused)
+    std::vector<Occ> occ(lmax + 1);
+    for (int l = 1; l <= lmax; l++) {
+        occ[l].D = D;
+        occ[l].nb = 1 << (l - 1);
+        long cnt = 1;
+        for (int a = 0; a < D; a++) cnt *= occ[l].nb;
+        occ[l].bits.assign(cnt, 0);
+    }
+    occ[1].bits[0] = 1;
+    for (int l = 1; l < lmax; l++) {
+        const int nb = occ[l].nb, nz = D == 3 ? nb : 1;
+        const double w = 1.0 / (double)nb;
+        for (int z = 0; z < nz; z++)
+            for (int y = 0; y < nb; y++)
+                for (int x = 0; x < nb; x++) {
+                    if (!occ[l].has(x, y, z)) continue;
+                    bool refine = true;
+                    if (d.refine_kind == OCTMG_REFINE_NEAR_INTERFACE) {
+                        double c[3] = {d.lo[0] + ((double)x + 0.5) * w, d.lo[1] + ((double)y + 0.5) * w,
+                                       D == 3 ? d.lo[2] + ((double)z + 0.5) * w : 0.0};
+                        refine = std::fabs(lsf_host(d, d.lsf_params, c)) < d.refine_width * w;
+                    }
+                    if (refine) add_children(occ, l, x, y, z);
+                }
+    }
+    // 2:1 balance: a block at level l needs every neighbour region covered at
+    // level >= l-1, i.e. the level-(l-1) block containing each neighbour
+    // position must exist.  Missing ones are created by refining down from
+    // their deepest existing ancestor.  Processing fine to coarse handles the
+    // blocks this creates.
+    for (int l = lmax; l >= 3; l--) {
+        const int nb = occ[l].nb, nz = D == 3 ? nb : 1;
+        for (int z = 0; z < nz; z++)
+            for (int y = 0; y < nb; y++)
+                for (int x = 0; x < nb; x++) {
+                    if (!occ[l].has(x, y, z)) continue;
+                    for (int oz = (D == 3 ? -1 : 0); oz <= (D == 3 ? 1 : 0); oz++)
+                        for (int oy = -1; oy <= 1; oy++)
+                            for (int ox = -1; ox <= 1; ox++) {
+                                int qx = x + ox, qy = y + oy, qz = z + oz;
+                                if (qx < 0 || qy < 0 || qz < 0 || qx >= nb || qy >= nb || qz >= nb) continue;
+                                // required: block (l-1, q/2)
+                                int tx = qx >> 1, ty = qy >> 1, tz = qz >> 1, tl = l - 1;
+                                if (occ[tl].has(tx, ty, tz)) continue;
+                                // deepest existing ancestor
+                                int al = tl, ax = tx, ay = ty, az = tz;
+                                while (!occ[al].has(ax, ay, az)) {
+                                    al--;
+                                    ax >>= 1;
+                                    ay >>= 1;
+                                    az >>= 1;
+                                }
+                                // refine along the chain down to level tl
+                                while (al < tl) {
+                                    add_children(occ, al, ax, ay, az);
+                                    al++;
+                                    int sh = tl - al;
+                                    ax = tx >> sh;
+                                    ay = ty >> sh;
+                                    az = tz >> sh;
+                                }
+                            }
+                }
+    }
+
+    Tree t;
+    t.D = D;
+    t.N = N;
+    t.nsub = 0;
+    for (int n = N; n > d.coarse_n; n >>= 1) t.nsub++;
+    const int nlev = t.nsub + lmax;
+    if (nlev > kMaxLevels) { *err = "too many levels"; return false; }
+    t.lv.resize(nlev);
+    for (int il = 0; il < nlev; il++) {
+        TreeLevel &L = t.lv[il];
+        const int l = il - t.nsub + 1;
+        if (l <= 0) {
+            L.n = N >> (1 - l);
+            L.Nb = L.n;
+            L.nb = 1;
+        } else {
+            L.n = N << (l - 1);
+            L.Nb = N;
+            L.nb = 1 << (l - 1);
+        }
+        const int nb = L.nb, nz = D == 3 ? nb : 1;
+        std::vector<std::pair<uint64_t, std::array<int, 3>>> keyed;
+        for (int z = 0; z < nz; z++)
+            for (int y = 0; y < nb; y++)
+                for (int x = 0; x < nb; x++) {
+                    if (l >= 1 && !occ[l].has(x, y, z)) continue;
+                    keyed.push_back({interleave(D, x, y, z), {x, y, z}});
+                }
+        std::sort(keyed.begin(), keyed.end(),
+                  [](const auto &a, const auto &b) { return a.first < b.first; });
+        long cnt = 1;
+        for (int a = 0; a < D; a++) cnt *= nb;
+        L.lut.assign(cnt, -1);
+        L.pos.resize(keyed.size() * 3);
+        L.leaf.resize(keyed.size());
+        for (size_t i = 0; i < keyed.size(); i++) {
+            const auto &p = keyed[i].second;
+            for (int a = 0; a < 3; a++) L.pos[3 * i + a] = p[a];
+            L.lut[D == 3 ? ((long)p[2] * nb + p[1]) * nb + p[0] : (long)p[1] * nb + p[0]] = (int)i;
+            bool leaf;
+            if (l <= 0) leaf = false;
+            else if (l == lmax) leaf = true;
+            else leaf = !occ[l + 1].has(2 * p[0], 2 * p[1], D == 3 ? 2 * p[2] : 0);
+            L.leaf[i] = leaf;
+            if (leaf && l < lmax) t.adaptive = true;
+        }
+    }
+    *out = std::move(t);
+    return true;
+}
+
+}  // namespace octmg

@@ -1,0 +1,321 @@
+"""ctypes binding of liboctmg.so (C ABI in include/octmg.h).
+
+Argument marshalling only: every step of the solver runs in the library's
+HIP kernels.  The library must have been built (``python -m
+paper_2205_09411_amd.build``); there is no fallback, and importing a missing
+library raises.  PyTorch is optional here: device tensors and streams may be
+passed by pointer (``tensor.data_ptr()``, ``torch.cuda.current_stream()``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboctmg.so")
+
+OK = 0
+ERR_INVALID, ERR_OOM, ERR_HIP, ERR_NOT_CONVERGED, ERR_NONFINITE, ERR_GEOMETRY, ERR_BUDGET = -1, -2, -3, -4, -5, -6, -7
+LSF_NONE, LSF_SPHERES, LSF_CYLINDER_Z = 0, 1, 2
+REFINE_UNIFORM, REFINE_NEAR_INTERFACE = 0, 1
+FP64, MIXED = 0, 1
+CYCLE_V, CYCLE_FMG = 0, 1
+FIELD_PHI, FIELD_G, FIELD_OLD = 0, 1, 2
+STEP_HALF_SWEEP, STEP_SMOOTH, STEP_RESTRICT_FAS, STEP_PROLONG, STEP_COARSE_SOLVE, STEP_RESTRICT_RHS = range(6)
+
+
+class OctmgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"octmg status {status}: {msg}")
+        self.status = status
+
+
+class GeomDesc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("block_n", C.c_int), ("max_level", C.c_int), ("refine_kind", C.c_int),
+                ("lsf_kind", C.c_int), ("lsf_n", C.c_int), ("coarse_n", C.c_int), ("reserved", C.c_int),
+                ("refine_width", C.c_double), ("eps_tol", C.c_double), ("mask_factor", C.c_double),
+                ("w_min", C.c_double), ("lo", C.c_double * 3), ("lsf_params", C.POINTER(C.c_double))]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("cycle_kind", C.c_int), ("max_cycles", C.c_int), ("zero_start", C.c_int),
+                ("reserved", C.c_int), ("rtol", C.c_double)]
+
+
+class SolveReport(C.Structure):
+    _fields_ = [("cycles", C.c_int), ("status", C.c_int), ("r0", C.c_double), ("r_final", C.c_double),
+                ("history", C.c_double * 64)]
+
+
+_lib = None
+_vp, _dp, _ip, _i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int64)
+_SIGS = {
+    "octmg_last_error": (C.c_char_p, []),
+    "octmg_version": (C.c_int, []),
+    "octmg_plan_levels": (C.c_int, [C.POINTER(GeomDesc), _ip, _i64p]),
+    "octmg_plan_blocks": (C.c_int, [C.POINTER(GeomDesc), C.c_int, _ip, _ip]),
+    "octmg_geom_create": (C.c_int, [C.POINTER(GeomDesc), C.c_int, C.POINTER(_vp)]),
+    "octmg_geom_destroy": (None, [_vp]),
+    "octmg_geom_info": (C.c_int, [_vp, _i64p]),
+    "octmg_geom_level_info": (C.c_int, [_vp, C.c_int, _i64p]),
+    "octmg_geom_leaf_coords": (C.c_int, [_vp, _dp, _ip]),
+    "octmg_geom_iface_points": (C.c_int, [_vp, _dp]),
+    "octmg_geom_domain_points": (C.c_int, [_vp, _dp]),
+    "octmg_geom_records": (C.c_int, [_vp, C.c_int, _ip, _dp, _dp]),
+    "octmg_geom_block_positions": (C.c_int, [_vp, C.c_int, _ip, _ip]),
+    "octmg_state_create": (C.c_int, [_vp, C.c_int, C.c_int, C.POINTER(_vp)]),
+    "octmg_state_destroy": (None, [_vp]),
+    "octmg_state_set_smoothing": (C.c_int, [_vp, C.c_int, C.c_int]),
+    "octmg_set_boundary": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp]),
+    "octmg_set_rhs": (C.c_int, [_vp, _vp, C.c_int, _vp]),
+    "octmg_set_solution": (C.c_int, [_vp, _vp, C.c_int, _vp]),
+    "octmg_get_solution": (C.c_int, [_vp, _vp, C.c_int, _vp]),
+    "octmg_zero_solution": (C.c_int, [_vp, _vp]),
+    "octmg_cycle": (C.c_int, [_vp, C.c_int, C.c_int, _vp]),
+    "octmg_residual_norm": (C.c_int, [_vp, C.c_int, _dp, _vp]),
+    "octmg_solve": (C.c_int, [_vp, C.POINTER(SolveOpts), _vp, C.POINTER(SolveReport)]),
+    "octmg_debug_get_field": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _dp]),
+    "octmg_debug_set_field": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _dp]),
+    "octmg_debug_step": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _vp]),
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2205_09411_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_names():
+    return list(_SIGS)
+
+
+def _check(status: int):
+    if status != OK:
+        raise OctmgError(status, lib().octmg_last_error().decode())
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def make_desc(geom) -> GeomDesc:
+    """GeomDesc from a workloads.Geometry-like object (keeps params alive)."""
+    params = np.ascontiguousarray(np.asarray(geom.lsf_params, dtype=np.float64).reshape(-1))
+    if params.size == 0:
+        params = np.zeros(1)
+    d = GeomDesc()
+    d.dim, d.block_n, d.max_level = geom.dim, geom.block_n, geom.max_level
+    d.refine_kind, d.lsf_kind, d.lsf_n = geom.refine_kind, geom.lsf_kind, geom.lsf_n
+    d.coarse_n = geom.coarse_n
+    d.refine_width, d.eps_tol, d.mask_factor, d.w_min = geom.refine_width, geom.eps_tol, geom.mask_factor, geom.w_min
+    for i in range(3):
+        d.lo[i] = geom.lo[i]
+    d.lsf_params = _ptr(params, C.c_double)
+    d._keep = params
+    return d
+
+
+def plan_levels(geom):
+    """Host-only tree plan: list of dicts per level (no device needed)."""
+    d = make_desc(geom)
+    n = C.c_int()
+    info = np.zeros(4 * 24, dtype=np.int64)
+    _check(lib().octmg_plan_levels(C.byref(d), C.byref(n), _ptr(info, C.c_int64)))
+    keys = ["n", "Nb", "nblocks", "nleaf"]
+    return [dict(zip(keys, (int(v) for v in info[4 * i:4 * i + 4]))) for i in range(n.value)]
+
+
+def plan_blocks(geom, level: int):
+    d = make_desc(geom)
+    nb = plan_levels(geom)[level]["nblocks"]
+    pos = np.zeros((nb, 3), dtype=np.int32)
+    leaf = np.zeros(nb, dtype=np.int32)
+    _check(lib().octmg_plan_blocks(C.byref(d), level, _ptr(pos, C.c_int), _ptr(leaf, C.c_int)))
+    return pos, leaf
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream  # torch.cuda.Stream
+
+
+class Geometry:
+    """Tree, FP64 interface setup and coarse inverse on one HIP device."""
+
+    def __init__(self, geom, device: int = 0):
+        self.desc = make_desc(geom)
+        self.geom = geom
+        h = _vp()
+        _check(lib().octmg_geom_create(C.byref(self.desc), device, C.byref(h)))
+        self._h = h
+        self.device = device
+        info = np.zeros(8, dtype=np.int64)
+        _check(lib().octmg_geom_info(self._h, _ptr(info, C.c_int64)))
+        (self.n_levels, self.n_leaf, self.n_iface, self.n_domain, self.n_records, self.device_bytes,
+         self.n_blocks, self.n_iface_blocks) = (int(v) for v in info)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().octmg_geom_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def level_info(self, level: int) -> dict:
+        out = np.zeros(8, dtype=np.int64)
+        _check(lib().octmg_geom_level_info(self._h, level, _ptr(out, C.c_int64)))
+        keys = ["n", "Nb", "nblocks", "nleaf", "nrec", "npts", "nface", "n_iface_blocks"]
+        return dict(zip(keys, (int(v) for v in out)))
+
+    def leaf_coords(self):
+        xyz = np.zeros((self.n_leaf, 3))
+        lvl = np.zeros(self.n_leaf, dtype=np.int32)
+        _check(lib().octmg_geom_leaf_coords(self._h, _ptr(xyz, C.c_double), _ptr(lvl, C.c_int)))
+        return xyz, lvl
+
+    def iface_points(self):
+        xyz = np.zeros((self.n_iface, 3))
+        if self.n_iface:
+            _check(lib().octmg_geom_iface_points(self._h, _ptr(xyz, C.c_double)))
+        return xyz
+
+    def domain_points(self):
+        xyz = np.zeros((self.n_domain, 3))
+        _check(lib().octmg_geom_domain_points(self._h, _ptr(xyz, C.c_double)))
+        return xyz
+
+    def records(self, level: int):
+        n = self.level_info(level)["nrec"]
+        ids = np.zeros((n, 3), dtype=np.int32)
+        d = np.zeros((n, 6))
+        coef = np.zeros((n, 8))
+        if n:
+            _check(lib().octmg_geom_records(self._h, level, _ptr(ids, C.c_int), _ptr(d, C.c_double),
+                                            _ptr(coef, C.c_double)))
+        return ids, d, coef
+
+    def block_positions(self, level: int):
+        nb = self.level_info(level)["nblocks"]
+        pos = np.zeros((nb, 3), dtype=np.int32)
+        leaf = np.zeros(nb, dtype=np.int32)
+        _check(lib().octmg_geom_block_positions(self._h, level, _ptr(pos, C.c_int), _ptr(leaf, C.c_int)))
+        return pos, leaf
+
+
+class State:
+    """Fields of n_rhs right-hand sides on a Geometry (FP64 or MIXED)."""
+
+    def __init__(self, geometry: Geometry, n_rhs: int = 1, precision: int = FP64):
+        self.geometry = geometry
+        self.n_rhs = n_rhs
+        self.precision = precision
+        h = _vp()
+        _check(lib().octmg_state_create(geometry._h, n_rhs, precision, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().octmg_state_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_smoothing(self, n_down: int, n_up: int):
+        _check(lib().octmg_state_set_smoothing(self._h, n_down, n_up))
+
+    def _arr(self, a, n):
+        """(pointer, on_device, keepalive) for a numpy array or torch tensor."""
+        if hasattr(a, "data_ptr"):
+            assert a.dtype.__str__() == "torch.float64" and a.is_contiguous() and a.numel() == n
+            return a.data_ptr(), int(a.is_cuda), a
+        arr = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+        assert arr.size == n, (arr.size, n)
+        return arr.ctypes.data, 0, arr
+
+    def set_boundary(self, iface_vals=None, domain_vals=None, stream=None):
+        g = self.geometry
+        pi, od1, k1 = self._arr(iface_vals, g.n_iface) if iface_vals is not None and g.n_iface else (None, 0, None)
+        pd, od2, k2 = self._arr(domain_vals, g.n_domain) if domain_vals is not None else (None, 0, None)
+        on_dev = od1 or od2
+        _check(lib().octmg_set_boundary(self._h, pi, pd, on_dev, _stream_ptr(stream)))
+
+    def set_boundary_fn(self, iface_fn, domain_fn, stream=None):
+        g = self.geometry
+        p = g.iface_points()
+        q = g.domain_points()
+        self.set_boundary(iface_fn(p) if len(p) else None, domain_fn(q), stream)
+
+    def set_rhs(self, g, stream=None):
+        p, od, keep = self._arr(g, self.geometry.n_leaf * self.n_rhs)
+        _check(lib().octmg_set_rhs(self._h, p, od, _stream_ptr(stream)))
+
+    def set_solution(self, phi, stream=None):
+        p, od, keep = self._arr(phi, self.geometry.n_leaf * self.n_rhs)
+        _check(lib().octmg_set_solution(self._h, p, od, _stream_ptr(stream)))
+
+    def get_solution(self, out=None, stream=None) -> np.ndarray:
+        n = self.geometry.n_leaf * self.n_rhs
+        if out is not None and hasattr(out, "data_ptr"):
+            _check(lib().octmg_get_solution(self._h, out.data_ptr(), int(out.is_cuda), _stream_ptr(stream)))
+            return out
+        a = np.zeros(n)
+        _check(lib().octmg_get_solution(self._h, a.ctypes.data, 0, _stream_ptr(stream)))
+        return a.reshape(self.n_rhs, -1) if self.n_rhs > 1 else a
+
+    def zero_solution(self, stream=None):
+        _check(lib().octmg_zero_solution(self._h, _stream_ptr(stream)))
+
+    def cycle(self, kind: int = CYCLE_V, have_guess: bool = True, stream=None):
+        _check(lib().octmg_cycle(self._h, kind, int(have_guess), _stream_ptr(stream)))
+
+    def vcycle(self, stream=None):
+        self.cycle(CYCLE_V, True, stream)
+
+    def fmg(self, have_guess: bool = True, stream=None):
+        self.cycle(CYCLE_FMG, have_guess, stream)
+
+    def residual_norm(self, phi_zero: bool = False, stream=None) -> np.ndarray:
+        out = np.zeros(self.n_rhs)
+        _check(lib().octmg_residual_norm(self._h, int(phi_zero), _ptr(out, C.c_double), _stream_ptr(stream)))
+        return out
+
+    def solve(self, rtol: float = 1e-10, max_cycles: int = 40, kind: int = CYCLE_V, zero_start: bool = False,
+              stream=None, raise_on_fail: bool = True) -> SolveReport:
+        o = SolveOpts()
+        o.cycle_kind, o.max_cycles, o.zero_start, o.rtol = kind, max_cycles, int(zero_start), rtol
+        rep = SolveReport()
+        st = lib().octmg_solve(self._h, C.byref(o), _stream_ptr(stream), C.byref(rep))
+        if raise_on_fail:
+            _check(st)
+        return rep
+
+    # ---- kernel-level access (parity checks)
+    def get_field(self, level: int, field: int, rhs: int = 0) -> np.ndarray:
+        info = self.geometry.level_info(level)
+        a = np.zeros(info["nblocks"] * info["Nb"] ** self.geometry.geom.dim)
+        _check(lib().octmg_debug_get_field(self._h, level, field, rhs, _ptr(a, C.c_double)))
+        return a
+
+    def set_field(self, level: int, field: int, vals, rhs: int = 0):
+        a = np.ascontiguousarray(vals, dtype=np.float64)
+        _check(lib().octmg_debug_set_field(self._h, level, field, rhs, _ptr(a, C.c_double)))
+
+    def step(self, step: int, level: int, arg: int = 0, stream=None):
+        _check(lib().octmg_debug_step(self._h, step, level, arg, _stream_ptr(stream)))

@@ -1,0 +1,216 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU checker.
+
+* setup: leaf centres, interface points x0 and relative distances d are
+  bitwise equal; stencil coefficients agree to 1e-15 relative;
+* single steps (half sweep, FAS restriction, prolongation, coarse solve):
+  1e-13 relative max-norm on the same inputs;
+* cycles: 1e-10 relative max-norm of phi after every V-cycle and FMG;
+* solves reach the requested relative residual.
+Sizes span several blocks and levels, 2D and 3D, uniform and adaptive."""
+import numpy as np
+import pytest
+
+from paper_2205_09411_amd import octmg
+from paper_2205_09411_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CONFIGS = {
+    "mms2d_64": lambda: W.mms2d(max_level=4),
+    "mms2d_b16": lambda: W.mms2d(max_level=3, block_n=16),
+    "mms3d_b8_32": lambda: W.mms3d(max_level=3, block_n=8),
+    "mms3d_b16_64": lambda: W.mms3d(max_level=3, block_n=16),
+    "cylinder_64": lambda: W.cylinder(max_level=3),
+    "spheres_amr": lambda: W.spheres(n_spheres=5, max_level=5, block_n=8, seed=9),
+    "sphere_f1_3d": lambda: W.sphere_f1(dim=3, max_level=4),
+    "spheres_amr16": lambda: W.spheres(n_spheres=8, max_level=5, block_n=16, seed=12),
+}
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def make_pair(orc, w, n_rhs=1, precision=octmg.FP64):
+    o = orc.setup_workload(w)
+    G = octmg.Geometry(w.geom)
+    S = octmg.State(G, n_rhs, precision)
+    xo, _ = o.leaf_coords()
+    S.set_boundary(w.iface_value(o.iface_points()) if G.n_iface else None, w.domain_value(o.domain_points()))
+    g = w.rhs(xo)
+    S.set_rhs(np.tile(g, n_rhs) if n_rhs > 1 else g)
+    return o, G, S
+
+
+@pytest.mark.parametrize("name", sorted(CONFIGS))
+def test_setup_parity(orc, name):
+    w = CONFIGS[name]()
+    print("setup parity", name, flush=True)
+    o = orc.Oracle(w.geom)
+    G = octmg.Geometry(w.geom)
+    assert G.n_levels == o.n_levels
+    xg, lg = G.leaf_coords()
+    xo, lo = o.leaf_coords()
+    assert np.array_equal(xg, xo) and np.array_equal(lg, lo)
+    assert np.array_equal(G.domain_points(), o.domain_points())
+    assert np.array_equal(G.iface_points(), o.iface_points())
+    for il in range(o.n_levels):
+        ig, dg, cg = G.records(il)
+        io, do, co = o.records(il)
+        D = w.geom.dim
+        assert np.array_equal(ig, io), il
+        assert np.array_equal(dg[:, :2 * D], do[:, :2 * D]), il
+        cols = list(range(2 * D)) + [6]
+        assert np.abs(cg[:, cols] - co[:, cols]).max(initial=0) <= 1e-15 * np.abs(co[:, cols]).max(initial=1), il
+
+
+@pytest.mark.parametrize("name", ["mms2d_64", "mms3d_b16_64", "spheres_amr"])
+def test_single_steps(orc, name):
+    w = CONFIGS[name]()
+    print("single steps", name, flush=True)
+    o, G, S = make_pair(orc, w)
+    top = G.n_levels - 1
+    rng = np.random.default_rng(7)
+    for il in range(G.n_levels):
+        n = G.level_info(il)["nblocks"] * G.level_info(il)["Nb"] ** w.geom.dim
+        for f in (octmg.FIELD_PHI, octmg.FIELD_OLD):
+            v = rng.standard_normal(n)
+            S.set_field(il, f, v)
+            o.set_field(il, f, v)
+        if il < top:
+            v = rng.standard_normal(n)
+            S.set_field(il, octmg.FIELD_G, v)
+            o.set_field(il, octmg.FIELD_G, v)
+    # one half sweep of each colour on every level
+    for il in range(1, G.n_levels):
+        for color in (0, 1):
+            S.step(octmg.STEP_HALF_SWEEP, il, color)
+            o.half_sweep(il, color)
+            assert rel(S.get_field(il, 0), o.get_field(il, 0)) < 1e-13, (il, color)
+    # FAS restriction top -> top-1 (phi, g, old of the coarse level)
+    S.step(octmg.STEP_RESTRICT_FAS, top)
+    o.restrict_fas(top)
+    for f in (0, 1, 2):
+        assert rel(S.get_field(top - 1, f), o.get_field(top - 1, f)) < 1e-13, f
+    # coarse solve and prolongation (correction and solution mode)
+    S.step(octmg.STEP_COARSE_SOLVE, 0)
+    o.coarse_solve()
+    assert rel(S.get_field(0, 0), o.get_field(0, 0)) < 1e-12
+    for mode in (0, 1):
+        S.step(octmg.STEP_PROLONG, top, mode)
+        o.prolong(top, bool(mode))
+        assert rel(S.get_field(top, 0), o.get_field(top, 0)) < 1e-13, mode
+
+
+@pytest.mark.parametrize("name", sorted(CONFIGS))
+def test_vcycle_and_fmg_parity(orc, name):
+    w = CONFIGS[name]()
+    print("cycle parity", name, flush=True)
+    o, G, S = make_pair(orc, w)
+    # FMG without guess, then V-cycles, then FMG with guess
+    S.fmg(have_guess=False)
+    o.fmg(have_guess=False)
+    assert rel(S.get_solution(), o.get_solution()) < 1e-10
+    for k in range(4):
+        S.vcycle()
+        o.vcycle()
+        assert rel(S.get_solution(), o.get_solution()) < 1e-10, k
+    S.fmg(have_guess=True)
+    o.fmg(have_guess=True)
+    assert rel(S.get_solution(), o.get_solution()) < 1e-10
+    rg = S.residual_norm()[0]
+    ro = o.residual_max()
+    assert abs(rg - ro) <= 1e-6 * ro + 1e-9 * o.residual_max(phi_zero=True)
+
+
+def test_vcycle_parity_from_zero(orc):
+    w = CONFIGS["mms3d_b16_64"]()
+    o, G, S = make_pair(orc, w)
+    assert abs(S.residual_norm(phi_zero=True)[0] - o.residual_max(phi_zero=True)) <= 1e-12 * o.residual_max(phi_zero=True)
+    for k in range(6):
+        S.vcycle()
+        o.vcycle()
+        assert rel(S.get_solution(), o.get_solution()) < 1e-10, k
+
+
+def test_solve_fp64_and_mixed(orc):
+    """FP64 solve to 1e-10 matches the checker iterate for iterate (same number
+    of cycles); the mixed-precision solve reaches the same relative residual
+    and its error against the FP64 checker is reported."""
+    w = CONFIGS["mms3d_b16_64"]()
+    o, G, S = make_pair(orc, w)
+    rep = S.solve(rtol=1e-10, max_cycles=40)
+    assert rep.status == 0 and rep.r_final <= 1e-10 * rep.r0
+    r0, hist = o.solve(rtol=1e-10, max_cycles=40)
+    assert len(hist) - 1 == rep.cycles
+    assert rel(S.get_solution(), o.get_solution()) < 1e-10
+    ref = o.get_solution()
+    _, Gm, Sm = make_pair(orc, w, precision=octmg.MIXED)
+    repm = Sm.solve(rtol=1e-10, max_cycles=40)
+    assert repm.status == 0 and repm.r_final <= 1e-10 * repm.r0
+    o.solve(rtol=1e-13, max_cycles=40)
+    conv = o.get_solution()
+    err_m = rel(Sm.get_solution(), conv)
+    err_d = rel(S.get_solution(), conv)
+    print(f"FP64 cycles {rep.cycles} err {err_d:.2e}; mixed cycles {repm.cycles} err {err_m:.2e} (vs converged FP64 checker)")
+    assert err_m < 10 * err_d + 1e-9
+    xyz, _ = o.leaf_coords()
+    ex = w.exact(xyz)
+    assert abs(np.abs(Sm.get_solution() - ex).max() / np.abs(ref - ex).max() - 1.0) < 1e-2
+
+
+def test_batched_rhs_equal_single(orc):
+    w = W.cylinder(max_level=3)
+    G = octmg.Geometry(w.geom)
+    xyz, _ = G.leaf_coords()
+    g = np.stack([w.rhs(xyz, i) for i in range(4)])
+    Sb = octmg.State(G, 4)
+    Sb.set_boundary(None, np.zeros(G.n_domain))
+    Sb.set_rhs(g)
+    Sb.solve(rtol=1e-10)
+    batched = Sb.get_solution()
+    for i in range(4):
+        S1 = octmg.State(G, 1)
+        S1.set_boundary(None, np.zeros(G.n_domain))
+        S1.set_rhs(g[i])
+        S1.solve(rtol=1e-10)
+        assert rel(batched[i], S1.get_solution()) <= 1e-14
+
+
+def test_nonfinite_rhs_rejected():
+    w = CONFIGS["mms2d_64"]()
+    G = octmg.Geometry(w.geom)
+    S = octmg.State(G)
+    g = np.zeros(G.n_leaf)
+    g[5] = np.nan
+    with pytest.raises(octmg.OctmgError) as e:
+        S.set_rhs(g)
+    assert e.value.status == octmg.ERR_NONFINITE
+
+
+def test_invalid_arguments():
+    w = CONFIGS["mms2d_64"]()
+    G = octmg.Geometry(w.geom)
+    with pytest.raises(octmg.OctmgError):
+        octmg.State(G, 0)
+    S = octmg.State(G)
+    with pytest.raises(octmg.OctmgError):
+        S.step(octmg.STEP_HALF_SWEEP, 99, 0)
+    with pytest.raises(octmg.OctmgError):
+        S.solve(rtol=-1.0)
+
+
+def test_full_size_mms3d_256(orc):
+    """The 256^3 manufactured problem in 16^3 blocks (the benchmark
+    workload): setup parity on every level, then per-V-cycle parity."""
+    w = W.mms3d(max_level=5, block_n=16)
+    print("full size 256^3", flush=True)
+    o, G, S = make_pair(orc, w)
+    assert np.array_equal(G.iface_points(), o.iface_points())
+    for il in range(o.n_levels):
+        assert np.array_equal(G.records(il)[1][:, :6], o.records(il)[1][:, :6])
+    for k in range(2):
+        S.vcycle()
+        o.vcycle()
+        assert rel(S.get_solution(), o.get_solution()) < 1e-10, k
+    print("residual", S.residual_norm()[0], o.residual_max(), flush=True)
