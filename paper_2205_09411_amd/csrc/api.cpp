@@ -100,8 +100,33 @@ struct Fields32 {
 
 }  // namespace
 
+struct Profile {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    std::vector<hipEvent_t> spare;
+    double updates = 0.0;
+    hipEvent_t get() {
+        if (!spare.empty()) {
+            hipEvent_t e = spare.back();
+            spare.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    ~Profile() {
+        for (auto &p : pending) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
+        for (auto e : spare) (void)hipEventDestroy(e);
+    }
+};
+
 struct octmg_state_s {
     octmg_geom geom = nullptr;
+    Profile *prof = nullptr;
     int nrhs = 1, precision = OCTMG_FP64, n_down = 2, n_up = 2;
     std::vector<Fields64> f64;
     std::vector<Fields32> f32;
@@ -193,9 +218,26 @@ struct Engine {
     int Nb(int il) const { return s->geom->L[il].Nb; }
 
     octmg_status smooth(int il, int steps) {
+        Profile *P = s->prof;
+        const bool timed = P && P->on && il == (int)s->geom->L.size() - 1;
         for (int k = 0; k < steps; k++)
-            for (int color = 0; color < 2; color++)
+            for (int color = 0; color < 2; color++) {
+                hipEvent_t a = nullptr, b = nullptr;
+                if (timed) {
+                    a = P->get();
+                    b = P->get();
+                    HIPCK(hipEventRecord(a, st));
+                }
                 HIPCK(launch_gs_half<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1), color, s->nrhs, st));
+                if (timed) {
+                    HIPCK(hipEventRecord(b, st));
+                    P->pending.push_back({a, b});
+                }
+                if (P && P->on) {
+                    const GeomLevel &G = s->geom->L[il];
+                    P->updates += 0.5 * (double)G.nblocks * G.cpb * s->nrhs;
+                }
+            }
         return OCTMG_OK;
     }
     octmg_status half_sweep(int il, int color) {
@@ -729,8 +771,43 @@ void octmg_state_destroy(octmg_state s) {
     (void)hipSetDevice(s->geom->device);
     (void)hipDeviceSynchronize();
     octmg_geom g = s->geom;
+    delete s->prof;
     delete s;
     release_geom(g);
+}
+
+octmg_status octmg_profile_enable(octmg_state s, int enable) {
+    if (!s) return fail(OCTMG_ERR_INVALID, "null state");
+    if (!s->prof) s->prof = new Profile();
+    s->prof->on = enable != 0;
+    return OCTMG_OK;
+}
+
+octmg_status octmg_profile_read(octmg_state s, double *out) {
+    if (!s || !out) return fail(OCTMG_ERR_INVALID, "null argument");
+    HIPCK(hipSetDevice(s->geom->device));
+    Profile *P = s->prof;
+    double ms_total = 0.0, n = 0.0, upd = 0.0;
+    if (P) {
+        for (auto &pr : P->pending) {
+            HIPCK(hipEventSynchronize(pr.second));
+            float ms = 0.0f;
+            HIPCK(hipEventElapsedTime(&ms, pr.first, pr.second));
+            ms_total += ms;
+            n += 1.0;
+            P->spare.push_back(pr.first);
+            P->spare.push_back(pr.second);
+        }
+        P->pending.clear();
+        upd = P->updates;
+        P->updates = 0.0;
+    }
+    const GeomLevel &top = s->geom->L.back();
+    out[0] = n;
+    out[1] = ms_total;
+    out[2] = upd;
+    out[3] = (double)top.nblocks * top.cpb;
+    return OCTMG_OK;
 }
 
 octmg_status octmg_state_set_smoothing(octmg_state s, int n_down, int n_up) {

@@ -76,6 +76,8 @@ _SIGS = {
     "octmg_cycle": (C.c_int, [_vp, C.c_int, C.c_int, _vp]),
     "octmg_residual_norm": (C.c_int, [_vp, C.c_int, _dp, _vp]),
     "octmg_solve": (C.c_int, [_vp, C.POINTER(SolveOpts), _vp, C.POINTER(SolveReport)]),
+    "octmg_profile_enable": (C.c_int, [_vp, C.c_int]),
+    "octmg_profile_read": (C.c_int, [_vp, _dp]),
     "octmg_debug_get_field": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _dp]),
     "octmg_debug_set_field": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _dp]),
     "octmg_debug_step": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _vp]),
@@ -305,6 +307,15 @@ class State:
         if raise_on_fail:
             _check(st)
         return rep
+
+    def profile(self, enable: bool = True):
+        _check(lib().octmg_profile_enable(self._h, int(enable)))
+
+    def profile_read(self) -> dict:
+        out = np.zeros(4)
+        _check(lib().octmg_profile_read(self._h, _ptr(out, C.c_double)))
+        return {"finest_half_sweeps": int(out[0]), "finest_half_sweep_ms": float(out[1]),
+                "smoother_cell_updates": float(out[2]), "finest_cells": int(out[3])}
 
     # ---- kernel-level access (parity checks)
     def get_field(self, level: int, field: int, rhs: int = 0) -> np.ndarray:
