@@ -57,7 +57,7 @@ __device__ __forceinline__ T level_value(const LV<T> &L, const T *f, int qi, int
 
 // refinement-boundary ghost for fine cell G in direction (ax, s)
 template <typename T, int D, int N>
-__device__ __noinline__ T cf_ghost(const LV<T> &Lc, const T *phic, int gi, int gj, int gk, int ax, int s, T f1,
+__device__ __forceinline__ T cf_ghost(const LV<T> &Lc, const T *phic, int gi, int gj, int gk, int ax, int s, T f1,
                                    T f2) {
     int ng[3] = {gi, gj, gk};
     ng[ax] += s;
@@ -249,6 +249,7 @@ __global__ __launch_bounds__(256) void k_restrict_fas(LV<T> L, LV<T> Lc, int int
     const long long base = (long long)blk * Blk<D, N>::CPB;
     const int C0[3] = {P.x * H, P.y * H, D == 3 ? P.z * H : 0};
     const int pb = block_at<T, D>(Lc, C0[0] / NC, C0[1] / NC, D == 3 ? C0[2] / NC : 0);
+    if (pb < 0) return;
     const T inv = T(1) / T(1 << D);
     for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
         const int ci = c % H, cj = (c / H) % H, ck = D == 3 ? c / (H * H) : 0;
@@ -289,6 +290,7 @@ __global__ __launch_bounds__(256) void k_restrict_rhs(LV<T> L, LV<T> Lc) {
     const long long base = (long long)blk * Blk<D, N>::CPB;
     const int C0[3] = {P.x * H, P.y * H, D == 3 ? P.z * H : 0};
     const int pb = block_at<T, D>(Lc, C0[0] / NC, C0[1] / NC, D == 3 ? C0[2] / NC : 0);
+    if (pb < 0) return;
     const T inv = T(1) / T(1 << D);
     for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
         const int ci = c % H, cj = (c / H) % H, ck = D == 3 ? c / (H * H) : 0;
@@ -315,6 +317,7 @@ __global__ __launch_bounds__(256) void k_restrict_phi(LV<T> L, LV<T> Lc) {
     const long long base = (long long)blk * Blk<D, N>::CPB;
     const int C0[3] = {P.x * H, P.y * H, D == 3 ? P.z * H : 0};
     const int pb = block_at<T, D>(Lc, C0[0] / NC, C0[1] / NC, D == 3 ? C0[2] / NC : 0);
+    if (pb < 0) return;
     const T inv = T(1) / T(1 << D);
     for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
         const int ci = c % H, cj = (c / H) % H, ck = D == 3 ? c / (H * H) : 0;
@@ -694,6 +697,540 @@ __global__ void k_check_finite(const double *p, long long n, int *flag) {
         if (!isfinite(p[i])) atomicOr(flag, 1);
 }
 
+// ============================================================ 3D, LDS-staged
+// For 3D levels every per-level operation works colour by colour: the other
+// colour of the block, plus a one-cell halo from the face neighbours, is
+// staged in LDS (26 KB in FP64 for 16^3 blocks), while the cell's own
+// values, g and record-map entries are prefetched into registers, so that
+// every HBM load of a workgroup is in flight before the first LDS barrier.
+// Ghost values at domain faces and refinement boundaries are formed per
+// cell as in gather().  Workgroup w runs on XCD w mod 8; blocks are mapped
+// so that each XCD walks a contiguous Morton range of the level, which
+// keeps face halos in that XCD's L2.
+
+__device__ __forceinline__ int xcd_block() {
+    const int nb = gridDim.x, bid = blockIdx.x, xcd = bid & 7, slot = bid >> 3;
+    const int q = nb >> 3, r = nb & 7;
+    return xcd * q + min(xcd, r) + slot;
+}
+
+// one colour of a block with halo: (N+2) x (N+2) x (N/2+2), index (k, j, h)
+template <int N>
+struct ColTile {
+    static constexpr int NH = N / 2, HX = NH + 2, JY = N + 2, SIZE = (N + 2) * JY * HX;
+    __device__ static __forceinline__ int at(int k, int j, int h) { return ((k + 1) * JY + (j + 1)) * HX + (h + 1); }
+};
+
+template <int N>
+struct Per {
+    static constexpr int HALF = N * N * N / 2, PER = HALF / 256;  // cells of one colour per thread
+};
+
+template <typename T, int N>
+__device__ __forceinline__ void face_ids(const LV<T> &L, int4 P, int nbk[6]) {
+#pragma unroll
+    for (int d = 0; d < 6; d++) {
+        int q[3] = {P.x, P.y, P.z};
+        q[d >> 1] += (d & 1) ? 1 : -1;
+        nbk[d] = block_at<T, 3>(L, q[0], q[1], q[2]);
+    }
+}
+
+// Ghost values for the open faces of a block (no neighbour block: -2 domain
+// face, -1 coarser level).  Each cell of colour `col` on such a face reads
+// exactly one halo slot of the other-colour tile across that face; the slot
+// receives the ghost seen by that cell (Dirichlet 2 phi_b - own, or the
+// refinement-boundary interpolation).  Runs once per block after staging,
+// so the update loops read every neighbour from LDS without branches.
+template <typename T, int N, bool ZERO>
+__device__ void open_face_ghosts(T *tile, const LV<T> &L, const LV<T> &Lc, const T *__restrict__ own_col,
+                                 const T *phic, const int *nbk, int4 P, int col) {
+    using CT = ColTile<N>;
+    constexpr int NH = N / 2;
+    const int t = threadIdx.x;
+    if (t >= N * NH) return;
+#pragma unroll 1
+    for (int d = 0; d < 6; d++) {
+        if (nbk[d] >= 0) continue;
+        const int ax = d >> 1, s = (d & 1) ? 1 : -1;
+        int i, j, k, slot;
+        if (ax == 0) {
+            const int want = s < 0 ? 0 : 1;  // parity (col+j+k)&1 of rows whose cell touches the face
+            k = t / NH;
+            j = 2 * (t % NH) + ((col + k + want) & 1);
+            i = s < 0 ? 0 : N - 1;
+            slot = CT::at(k, j, s < 0 ? -1 : NH);
+        } else if (ax == 1) {
+            k = t / NH;
+            const int h = t % NH;
+            j = s < 0 ? 0 : N - 1;
+            i = 2 * h + ((col + j + k) & 1);
+            slot = CT::at(k, s < 0 ? -1 : N, h);
+        } else {
+            j = t / NH;
+            const int h = t % NH;
+            k = s < 0 ? 0 : N - 1;
+            i = 2 * h + ((col + j + k) & 1);
+            slot = CT::at(s < 0 ? -1 : N, j, h);
+        }
+        const T own = ZERO ? T(0) : own_col[(k * N + j) * NH + (i >> 1)];
+        const int gi = P.x * N + i, gj = P.y * N + j, gk = P.z * N + k;
+        T ghost;
+        if (nbk[d] == -2) {
+            const T bv = L.bcv ? L.bcv[face_slot<3>(ax, s, gi, gj, gk, L.n, L.nface)] : T(0);
+            ghost = T(2) * bv - own;
+        } else if (ZERO || !phic) {
+            ghost = T(0);
+        } else {
+            int c[3] = {i, j, k};
+            c[ax] -= s;  // inward neighbour, other colour, inside the block
+            const T f2 = tile[CT::at(c[2], c[1], c[0] >> 1)];
+            ghost = cf_ghost<T, 3, N>(Lc, phic, gi, gj, gk, ax, s, own, f2);
+        }
+        tile[slot] = ghost;
+    }
+}
+
+// Stage colour `col` of block `blk` and its face halos into a ColTile.
+// All global loads of the thread are issued before the LDS writes.
+template <typename T, int N, bool ZERO>
+__device__ __forceinline__ void stage_colour(T *tile, const T *__restrict__ phi, int blk, const int *nbk, int col) {
+    using B = Blk<3, N>;
+    using CT = ColTile<N>;
+    constexpr int NH = N / 2, PER = Per<N>::PER;
+    const int t = threadIdx.x, oc = col * B::HALF;
+    if (ZERO) {
+        for (int e = t; e < CT::SIZE; e += 256) tile[e] = T(0);
+        return;
+    }
+    const T *__restrict__ src = phi + (long long)blk * B::CPB + oc;
+    T r[PER];
+#pragma unroll
+    for (int m = 0; m < PER; m++) r[m] = src[t + 256 * m];
+    const int fh = t % NH, fr = t / NH;  // y/z face entry (N*NH <= 256)
+    const int xj = t % N, xk = t / N;    // x face entry (N*N <= 256)
+    const bool fz = t < N * NH, fx = t < N * N;
+    T y0 = T(0), y1 = T(0), z0 = T(0), z1 = T(0), x0 = T(0), x1 = T(0);
+    if (fz && nbk[2] >= 0) y0 = phi[(long long)nbk[2] * B::CPB + oc + (fr * N + N - 1) * NH + fh];
+    if (fz && nbk[3] >= 0) y1 = phi[(long long)nbk[3] * B::CPB + oc + (fr * N) * NH + fh];
+    if (fz && nbk[4] >= 0) z0 = phi[(long long)nbk[4] * B::CPB + oc + ((N - 1) * N + fr) * NH + fh];
+    if (fz && nbk[5] >= 0) z1 = phi[(long long)nbk[5] * B::CPB + oc + fr * NH + fh];
+    if (fx && nbk[0] >= 0) x0 = phi[(long long)nbk[0] * B::CPB + oc + (xk * N + xj) * NH + NH - 1];
+    if (fx && nbk[1] >= 0) x1 = phi[(long long)nbk[1] * B::CPB + oc + (xk * N + xj) * NH];
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        const int q = t + 256 * m;
+        tile[CT::at(q / (NH * N), (q / NH) % N, q % NH)] = r[m];
+    }
+    if (fz) {
+        tile[CT::at(fr, -1, fh)] = y0;
+        tile[CT::at(fr, N, fh)] = y1;
+        tile[CT::at(-1, fr, fh)] = z0;
+        tile[CT::at(N, fr, fh)] = z1;
+    }
+    if (fx) {
+        tile[CT::at(xk, xj, -1)] = x0;
+        tile[CT::at(xk, xj, NH)] = x1;
+    }
+}
+
+// the 6 neighbour values of cell q of colour `col` from the other-colour tile
+template <typename T, int N>
+__device__ __forceinline__ void tile_neighbours(const T *tile, int col, int q, int &i, int &j, int &k, T v[6]) {
+    using CT = ColTile<N>;
+    constexpr int NH = N / 2;
+    const int h = q % NH;
+    j = (q / NH) % N;
+    k = q / (NH * N);
+    const int par = (col + j + k) & 1;
+    i = 2 * h + par;
+    v[0] = tile[CT::at(k, j, h - 1 + par)];
+    v[1] = tile[CT::at(k, j, h + par)];
+    v[2] = tile[CT::at(k, j - 1, h)];
+    v[3] = tile[CT::at(k, j + 1, h)];
+    v[4] = tile[CT::at(k - 1, j, h)];
+    v[5] = tile[CT::at(k + 1, j, h)];
+}
+
+// red-black half sweep
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_gs_half3(LV<T> L, LV<T> Lc, int color) {
+    using B = Blk<3, N>;
+    constexpr int PER = Per<N>::PER;
+    if (inactive(L)) return;
+    __shared__ T tile[ColTile<N>::SIZE];
+    const int blk = xcd_block();
+    const int4 P = L.pos[blk];
+    int nbk[6];
+    face_ids<T, N>(L, P, nbk);
+    const int mo = L.map_off ? L.map_off[blk] : -1;
+    T *__restrict__ phi = L.phi + (long long)blockIdx.y * L.fstride;
+    const long long base = (long long)blk * B::CPB;
+    const T *__restrict__ gm = L.g + (long long)blockIdx.y * L.fstride + base + color * B::HALF;
+    T gv[PER];
+    int ri[PER];
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        gv[m] = gm[threadIdx.x + 256 * m];
+        ri[m] = mo >= 0 ? L.map[mo + color * B::HALF + threadIdx.x + 256 * m] : -1;
+    }
+    stage_colour<T, N, false>(tile, phi, blk, nbk, 1 - color);
+    __syncthreads();
+    const T *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
+    T *__restrict__ dst = phi + base + color * B::HALF;
+    if (nbk[0] < 0 || nbk[1] < 0 || nbk[2] < 0 || nbk[3] < 0 || nbk[4] < 0 || nbk[5] < 0) {
+        open_face_ghosts<T, N, false>(tile, L, Lc, dst, phic, nbk, P, color);
+        __syncthreads();
+    }
+    const T inv6 = T(1) / T(6);
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        const int q = threadIdx.x + 256 * m;
+        int i, j, k;
+        T v[6];
+        tile_neighbours<T, N>(tile, color, q, i, j, k, v);
+        T nv;
+        if (ri[m] < 0) {
+            nv = (((v[0] + v[1]) + (v[2] + v[3])) + (v[4] + v[5]) - L.dx2 * gv[m]) * inv6;
+        } else {
+            const T *r = L.rec + 8 * (long long)ri[m];
+            T s = T(0);
+#pragma unroll
+            for (int d = 0; d < 6; d++) s += r[d] * v[d];
+            const T bt = L.b ? L.b[ri[m]] : T(0);
+            nv = (gv[m] - bt - s) * r[7];
+        }
+        dst[q] = nv;
+    }
+}
+
+// L phi for the PER cells of colour `col` owned by this thread; `own` holds
+// their values (prefetched by the caller).  Leaves the tile in use: the
+// caller must __syncthreads() before restaging it.
+template <typename T, int N, bool ZERO>
+__device__ __forceinline__ void colour_op(const LV<T> &L, const LV<T> &Lc, const T *phi, const T *phic, T *tile,
+                                          int blk, const int *nbk, int4 P, const int *ri, int col, const T *own,
+                                          T *out) {
+    constexpr int PER = Per<N>::PER;
+    stage_colour<T, N, ZERO>(tile, phi, blk, nbk, 1 - col);
+    __syncthreads();
+    if (nbk[0] < 0 || nbk[1] < 0 || nbk[2] < 0 || nbk[3] < 0 || nbk[4] < 0 || nbk[5] < 0) {
+        open_face_ghosts<T, N, ZERO>(tile, L, Lc, phi + (long long)blk * Blk<3, N>::CPB + col * Blk<3, N>::HALF,
+                                     phic, nbk, P, col);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        const int q = threadIdx.x + 256 * m;
+        int i, j, k;
+        T v[6];
+        tile_neighbours<T, N>(tile, col, q, i, j, k, v);
+        if (ri[m] < 0) {
+            out[m] = L.inv_dx2 * ((((v[0] + v[1]) + (v[2] + v[3])) + (v[4] + v[5])) - T(6) * own[m]);
+        } else {
+            const T *r = L.rec + 8 * (long long)ri[m];
+            T s = T(0);
+#pragma unroll
+            for (int d = 0; d < 6; d++) s += r[d] * v[d];
+            out[m] = s + r[6] * own[m] + (L.b ? L.b[ri[m]] : T(0));
+        }
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void q_to_ijk(int col, int q, int &i, int &j, int &k) {
+    constexpr int NH = N / 2;
+    const int h = q % NH;
+    j = (q / NH) % N;
+    k = q / (NH * N);
+    i = 2 * h + ((col + j + k) & 1);
+}
+
+// FAS restriction, 3D: residual of every cell (colour by colour, from LDS),
+// then the 2x2x2 means of r and phi through a natural-order LDS array.
+// phi_c goes to Lc.phi, or to Lc.old when `into_old`.
+template <typename T, int N, int NC>
+__global__ __launch_bounds__(256) void k_restrict_fas3(LV<T> L, LV<T> Lc, int into_old) {
+    using B = Blk<3, N>;
+    constexpr int PER = Per<N>::PER, H = N / 2, NCELL = H * H * H, CPER = (NCELL + 255) / 256;
+    constexpr int SM = ColTile<N>::SIZE > B::CPB ? ColTile<N>::SIZE : B::CPB;
+    if (inactive(L)) return;
+    __shared__ T sm[SM];
+    const int blk = xcd_block();
+    const int4 P = L.pos[blk];
+    int nbk[6];
+    face_ids<T, N>(L, P, nbk);
+    const int mo = L.map_off ? L.map_off[blk] : -1;
+    const T *__restrict__ phi = L.phi + (long long)blockIdx.y * L.fstride;
+    const T *__restrict__ g = L.g + (long long)blockIdx.y * L.fstride;
+    const T *phic = Lc.phi + (long long)blockIdx.y * Lc.fstride;
+    const long long base = (long long)blk * B::CPB;
+    T r[2][PER];
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        T own[PER], gv[PER];
+        int ri[PER];
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            const int s = c * B::HALF + threadIdx.x + 256 * m;
+            own[m] = phi[base + s];
+            gv[m] = g[base + s];
+            ri[m] = mo >= 0 ? L.map[mo + s] : -1;
+        }
+        colour_op<T, N, false>(L, Lc, phi, phic, sm, blk, nbk, P, ri, c, own, r[c]);
+#pragma unroll
+        for (int m = 0; m < PER; m++) r[c][m] = gv[m] - r[c][m];
+        __syncthreads();
+    }
+    // residual means
+#pragma unroll
+    for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            int i, j, k;
+            q_to_ijk<N>(c, threadIdx.x + 256 * m, i, j, k);
+            sm[(k * N + j) * N + i] = r[c][m];
+        }
+    __syncthreads();
+    T rc[CPER], pc[CPER];
+#pragma unroll
+    for (int m = 0; m < CPER; m++) {
+        const int cc = threadIdx.x + 256 * m;
+        T s = T(0);
+        if (cc < NCELL) {
+            const int ci = cc % H, cj = (cc / H) % H, ck = cc / (H * H);
+#pragma unroll
+            for (int ch = 0; ch < 8; ch++)
+                s += sm[((2 * ck + ((ch >> 2) & 1)) * N + 2 * cj + ((ch >> 1) & 1)) * N + 2 * ci + (ch & 1)];
+        }
+        rc[m] = s;
+    }
+    __syncthreads();
+    // phi means (re-read from cache)
+#pragma unroll
+    for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            int i, j, k;
+            q_to_ijk<N>(c, threadIdx.x + 256 * m, i, j, k);
+            sm[(k * N + j) * N + i] = phi[base + c * B::HALF + threadIdx.x + 256 * m];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < CPER; m++) {
+        const int cc = threadIdx.x + 256 * m;
+        T s = T(0);
+        if (cc < NCELL) {
+            const int ci = cc % H, cj = (cc / H) % H, ck = cc / (H * H);
+#pragma unroll
+            for (int ch = 0; ch < 8; ch++)
+                s += sm[((2 * ck + ((ch >> 2) & 1)) * N + 2 * cj + ((ch >> 1) & 1)) * N + 2 * ci + (ch & 1)];
+        }
+        pc[m] = s;
+    }
+    T *phiw = (into_old ? Lc.old : Lc.phi) + (long long)blockIdx.y * Lc.fstride;
+    T *gw = Lc.g + (long long)blockIdx.y * Lc.fstride;
+    const int C0[3] = {P.x * H, P.y * H, P.z * H};
+    const int pb = block_at<T, 3>(Lc, C0[0] / NC, C0[1] / NC, C0[2] / NC);
+    if (pb < 0) return;  // excluded by construction: every block has a parent
+    const T inv = T(0.125);
+#pragma unroll
+    for (int m = 0; m < CPER; m++) {
+        const int cc = threadIdx.x + 256 * m;
+        if (cc >= NCELL) continue;
+        const int ci = cc % H, cj = (cc / H) % H, ck = cc / (H * H);
+        const int gi = C0[0] + ci, gj = C0[1] + cj, gk = C0[2] + ck;
+        const long long o = (long long)pb * Blk<3, NC>::CPB + split_of<3, NC>(gi % NC, gj % NC, gk % NC);
+        phiw[o] = pc[m] * inv;
+        gw[o] = rc[m] * inv;
+    }
+}
+
+// FAS rhs on parent blocks (g = L phi + g) and old = phi, 3D
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_fas_rhs3(LV<T> L, LV<T> Lc, int do_rhs) {
+    using B = Blk<3, N>;
+    constexpr int PER = Per<N>::PER;
+    if (inactive(L)) return;
+    __shared__ T tile[ColTile<N>::SIZE];
+    const int blk = xcd_block();
+    T *phi = L.phi + (long long)blockIdx.y * L.fstride;
+    T *g = L.g + (long long)blockIdx.y * L.fstride;
+    T *old = L.old + (long long)blockIdx.y * L.fstride;
+    const long long base = (long long)blk * B::CPB;
+    if (L.leaf[blk] || !do_rhs) {
+        for (int s = threadIdx.x; s < B::CPB; s += 256) old[base + s] = phi[base + s];
+        return;
+    }
+    const int4 P = L.pos[blk];
+    int nbk[6];
+    face_ids<T, N>(L, P, nbk);
+    const int mo = L.map_off ? L.map_off[blk] : -1;
+    const T *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
+    // the tile of the second colour overwrites nothing the first colour's
+    // results depend on: g and old are written only after both passes
+    T lp[2][PER];
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        T own[PER];
+        int ri[PER];
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            const int s = c * B::HALF + threadIdx.x + 256 * m;
+            own[m] = phi[base + s];
+            ri[m] = mo >= 0 ? L.map[mo + s] : -1;
+        }
+        colour_op<T, N, false>(L, Lc, phi, phic, tile, blk, nbk, P, ri, c, own, lp[c]);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            const int s = c * B::HALF + threadIdx.x + 256 * m;
+            g[base + s] = lp[c][m] + g[base + s];
+            old[base + s] = phi[base + s];
+        }
+}
+
+// max |g - L phi| over a leaf block (3D); ZERO: residual of phi = 0
+template <typename T, int N, bool ZERO>
+__global__ __launch_bounds__(256) void k_residual_max3(LV<T> L, LV<T> Lc, unsigned long long *out) {
+    using B = Blk<3, N>;
+    constexpr int PER = Per<N>::PER;
+    if (inactive(L)) return;
+    const int blk = xcd_block();
+    if (!L.leaf[blk]) return;
+    __shared__ T tile[ColTile<N>::SIZE];
+    __shared__ double wmax[4];
+    const int4 P = L.pos[blk];
+    int nbk[6];
+    face_ids<T, N>(L, P, nbk);
+    const int mo = L.map_off ? L.map_off[blk] : -1;
+    const T *__restrict__ phi = L.phi + (long long)blockIdx.y * L.fstride;
+    const T *__restrict__ g = L.g + (long long)blockIdx.y * L.fstride;
+    const T *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
+    const long long base = (long long)blk * B::CPB;
+    double mx = 0.0;
+#pragma unroll 1
+    for (int c = 0; c < 2; c++) {
+        T own[PER], gv[PER], lp[PER];
+        int ri[PER];
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            const int s = c * B::HALF + threadIdx.x + 256 * m;
+            own[m] = ZERO ? T(0) : phi[base + s];
+            gv[m] = g[base + s];
+            ri[m] = mo >= 0 ? L.map[mo + s] : -1;
+        }
+        colour_op<T, N, ZERO>(L, Lc, phi, phic, tile, blk, nbk, P, ri, c, own, lp);
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PER; m++) mx = fmax(mx, fabs((double)(gv[m] - lp[m])));
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
+    if (threadIdx.x % 64 == 0) wmax[threadIdx.x / 64] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; w++) mx = fmax(mx, wmax[w]);
+        if (mx != mx) mx = __longlong_as_double(0x7ff0000000000000ll);
+        atomicMax(out + blockIdx.y, (unsigned long long)__double_as_longlong(mx));
+    }
+}
+
+// prolongation, 3D: the coarse correction of the parent region (plus a
+// one-cell halo) is staged in LDS, then every fine cell is updated once.
+template <typename T, int N, int NC>
+__global__ __launch_bounds__(256) void k_prolong3(LV<T> L, LV<T> Lc, int solution) {
+    using B = Blk<3, N>;
+    constexpr int H = N / 2, E = H + 2, ESZ = E * E * E, PER = B::CPB / 256;
+    if (inactive(L)) return;
+    __shared__ T et[ESZ];
+    const int blk = xcd_block();
+    const int4 P = L.pos[blk];
+    const T *phic = Lc.phi + (long long)blockIdx.y * Lc.fstride;
+    const T *oldc = Lc.old + (long long)blockIdx.y * Lc.fstride;
+    T *__restrict__ phi = L.phi + (long long)blockIdx.y * L.fstride + (long long)blk * B::CPB;
+    T f[PER];
+#pragma unroll
+    for (int m = 0; m < PER; m++) f[m] = phi[threadIdx.x + 256 * m];
+    const int C0[3] = {P.x * H, P.y * H, P.z * H};
+    for (int e = threadIdx.x; e < ESZ; e += 256) {
+        const int x = e % E, y = (e / E) % E, z = e / (E * E);
+        et[e] = coarse_e<T, 3, NC>(Lc, phic, oldc, C0[0] + x - 1, C0[1] + y - 1, C0[2] + z - 1, solution);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        const int s = threadIdx.x + 256 * m;
+        int i, j, k;
+        q_to_ijk<N>(s / B::HALF, s % B::HALF, i, j, k);
+        const int ci = (i >> 1) + 1, cj = (j >> 1) + 1, ck = (k >> 1) + 1;
+        const int ox = (i & 1) ? 1 : -1, oy = (j & 1) ? 1 : -1, oz = (k & 1) ? 1 : -1;
+        T e = T(0);
+#pragma unroll
+        for (int dl = 0; dl < 8; dl++) {
+            const int ax = dl & 1, ay = (dl >> 1) & 1, az = (dl >> 2) & 1;
+            const T w = (ax ? T(0.25) : T(0.75)) * (ay ? T(0.25) : T(0.75)) * (az ? T(0.25) : T(0.75));
+            e = e + w * et[((ck + az * oz) * E + (cj + ay * oy)) * E + (ci + ax * ox)];
+        }
+        phi[s] = f[m] + e;
+    }
+}
+
+// mixed precision defect (FP64): g32 = g - L phi on a leaf block, phi32 = 0
+template <int N>
+__global__ __launch_bounds__(256) void k_defect3(LV<double> L, LV<double> Lc, LV<float> L32, const int *lb,
+                                                  unsigned long long *out) {
+    using B = Blk<3, N>;
+    constexpr int PER = Per<N>::PER;
+    if (inactive(L)) return;
+    __shared__ double tile[ColTile<N>::SIZE];
+    __shared__ double wmax[4];
+    const int blk = lb[blockIdx.x];
+    const int4 P = L.pos[blk];
+    int nbk[6];
+    face_ids<double, N>(L, P, nbk);
+    const int mo = L.map_off ? L.map_off[blk] : -1;
+    const double *__restrict__ phi = L.phi + (long long)blockIdx.y * L.fstride;
+    const double *__restrict__ g = L.g + (long long)blockIdx.y * L.fstride;
+    const double *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
+    const long long base = (long long)blk * B::CPB;
+    float *g32 = L32.g + (long long)blockIdx.y * L32.fstride + base;
+    float *p32 = L32.phi + (long long)blockIdx.y * L32.fstride + base;
+    double mx = 0.0;
+#pragma unroll 1
+    for (int c = 0; c < 2; c++) {
+        double own[PER], gv[PER], lp[PER];
+        int ri[PER];
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            const int s = c * B::HALF + threadIdx.x + 256 * m;
+            own[m] = phi[base + s];
+            gv[m] = g[base + s];
+            ri[m] = mo >= 0 ? L.map[mo + s] : -1;
+        }
+        colour_op<double, N, false>(L, Lc, phi, phic, tile, blk, nbk, P, ri, c, own, lp);
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            const int s = c * B::HALF + threadIdx.x + 256 * m;
+            const double r = gv[m] - lp[m];
+            mx = fmax(mx, fabs(r));
+            g32[s] = (float)r;
+            p32[s] = 0.0f;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
+    if (threadIdx.x % 64 == 0) wmax[threadIdx.x / 64] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; w++) mx = fmax(mx, wmax[w]);
+        if (mx != mx) mx = __longlong_as_double(0x7ff0000000000000ll);
+        atomicMax(out + blockIdx.y, (unsigned long long)__double_as_longlong(mx));
+    }
+}
+
 int grid_for(long long n) {
     long long g = (n + 255) / 256;
     return (int)(g < 4096 ? (g < 1 ? 1 : g) : 4096);
@@ -710,7 +1247,9 @@ hipError_t launch_gs_half(int D, int N, const LV<T> &L, const LV<T> &Lc, int col
     if (L.nblocks == 0) return hipSuccess;
     dim3 grid(L.nblocks, nrhs);
 #define GS(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_gs_half<T, D_, N_>), grid, dim3(Blk<D_, N_>::THREADS), 0, s, L, Lc, color))
-    GS(3, 16) GS(3, 8) GS(2, 8) GS(2, 16)
+#define GS3(N_) OCTMG_DN(3, N_, hipLaunchKernelGGL((k_gs_half3<T, N_>), grid, dim3(256), 0, s, L, Lc, color))
+    GS3(16) GS3(8) GS(2, 8) GS(2, 16)
+#undef GS3
 #undef GS
     return hipErrorInvalidValue;
 }
@@ -724,7 +1263,9 @@ hipError_t launch_restrict_fas(int D, int N, int Nc, const LV<T> &L, const LV<T>
     if (L.nblocks == 0) return hipSuccess;
     dim3 grid(L.nblocks, nrhs);
 #define RF(D_, N_, NC_) OCTMG_DNC(D_, N_, NC_, hipLaunchKernelGGL((k_restrict_fas<T, D_, N_, NC_>), grid, dim3(256), 0, s, L, Lc, into_old))
-    RF(3, 16, 16) RF(3, 16, 8) RF(3, 8, 8) RF(2, 8, 8) RF(2, 16, 16) RF(2, 16, 8)
+#define RF3(N_, NC_) OCTMG_DNC(3, N_, NC_, hipLaunchKernelGGL((k_restrict_fas3<T, N_, NC_>), grid, dim3(256), 0, s, L, Lc, into_old))
+    RF3(16, 16) RF3(16, 8) RF3(8, 8) RF(2, 8, 8) RF(2, 16, 16) RF(2, 16, 8)
+#undef RF3
 #undef RF
     return hipErrorInvalidValue;
 }
@@ -764,7 +1305,9 @@ hipError_t launch_fas_rhs(int D, int N, const LV<T> &L, const LV<T> &Lc, int par
     if (L.nblocks == 0) return hipSuccess;
     dim3 grid(L.nblocks, nrhs);
 #define FR(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_fas_rhs<T, D_, N_>), grid, dim3(Blk<D_, N_>::THREADS), 0, s, L, Lc, parents_only))
-    FR(3, 16) FR(3, 8) FR(2, 8) FR(2, 16)
+#define FR3(N_) OCTMG_DN(3, N_, hipLaunchKernelGGL((k_fas_rhs3<T, N_>), grid, dim3(256), 0, s, L, Lc, parents_only))
+    FR3(16) FR3(8) FR(2, 8) FR(2, 16)
+#undef FR3
 #undef FR
     return hipErrorInvalidValue;
 }
@@ -775,7 +1318,9 @@ hipError_t launch_prolong(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc,
     if (L.nblocks == 0) return hipSuccess;
     dim3 grid(L.nblocks, nrhs);
 #define PR(D_, N_, NC_) OCTMG_DNC(D_, N_, NC_, hipLaunchKernelGGL((k_prolong<T, D_, N_, NC_>), grid, dim3(256), 0, s, L, Lc, solution_mode))
-    PR(3, 16, 16) PR(3, 16, 8) PR(3, 8, 8) PR(2, 8, 8) PR(2, 16, 16) PR(2, 16, 8)
+#define PR3(N_, NC_) OCTMG_DNC(3, N_, NC_, hipLaunchKernelGGL((k_prolong3<T, N_, NC_>), grid, dim3(256), 0, s, L, Lc, solution_mode))
+    PR3(16, 16) PR3(16, 8) PR3(8, 8) PR(2, 8, 8) PR(2, 16, 16) PR(2, 16, 8)
+#undef PR3
 #undef PR
     return hipErrorInvalidValue;
 }
@@ -801,7 +1346,14 @@ hipError_t launch_residual_max(int D, int N, const LV<T> &L, const LV<T> &Lc, in
         else hipLaunchKernelGGL((k_residual_max<T, D_, N_, false>), grid, dim3(Blk<D_, N_>::THREADS), 0, s, L, Lc, out); \
         return hipGetLastError();                                                                                   \
     }
-    RM(3, 16) RM(3, 8) RM(2, 8) RM(2, 16)
+#define RM3(N_)                                                                                                     \
+    if (D == 3 && N == N_) {                                                                                        \
+        if (phi_zero) hipLaunchKernelGGL((k_residual_max3<T, N_, true>), grid, dim3(256), 0, s, L, Lc, out);            \
+        else hipLaunchKernelGGL((k_residual_max3<T, N_, false>), grid, dim3(256), 0, s, L, Lc, out);                    \
+        return hipGetLastError();                                                                                   \
+    }
+    RM3(16) RM3(8) RM(2, 8) RM(2, 16)
+#undef RM3
 #undef RM
     return hipErrorInvalidValue;
 }
@@ -839,7 +1391,9 @@ hipError_t launch_defect(int D, int N, const LV<double> &L, const LV<double> &Lc
     if (nlb == 0) return hipSuccess;
     dim3 grid(nlb, nrhs);
 #define DF(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_defect<D_, N_>), grid, dim3(Blk<D_, N_>::THREADS), 0, s, L, Lc, L32, lb, out))
-    DF(3, 16) DF(3, 8) DF(2, 8) DF(2, 16)
+#define DF3(N_) OCTMG_DN(3, N_, hipLaunchKernelGGL((k_defect3<N_>), grid, dim3(256), 0, s, L, Lc, L32, lb, out))
+    DF3(16) DF3(8) DF(2, 8) DF(2, 16)
+#undef DF3
 #undef DF
     return hipErrorInvalidValue;
 }
