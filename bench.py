@@ -31,6 +31,23 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+PMC_RECORD = os.path.join(ROOT, "profiles", "gs_half3_mms3d_256_pmc.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the finest-level sweep from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs, if they were taken on the current
+    kernel source (sha256 recorded with them); otherwise None."""
+    import hashlib
+    try:
+        rec = json.load(open(PMC_RECORD))
+        src = open(os.path.join(ROOT, "paper_2205_09411_amd", "csrc", "kernels.hip"), "rb").read()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec["hbm_bytes_per_launch"]
 
 
 def workload(name):
@@ -152,7 +169,7 @@ def main():
                    "cells_finest": ncell, "blocks": G.n_blocks, "levels": G.n_levels,
                    "interface_records": G.n_records, "rtol": args.rtol},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "k_gs_half<double,3,16> (finest level)",
                      "bytes_per_launch": bytes_per_launch, "mean_launch_ms": round(mean_ms, 5)},
         "solves_per_s": round(args.steps / dt, 3),

@@ -179,10 +179,11 @@ octmg_status octmg_residual_norm(octmg_state s, int phi_zero, double *out, void 
 /* Cycles until max|r| <= rtol * max|r(phi=0)| for every rhs. */
 octmg_status octmg_solve(octmg_state s, const octmg_solve_opts *opts, void *stream, octmg_solve_report *rep);
 
-/* Profiling.  When enabled, every red-black half sweep of the finest level
- * is bracketed by HIP events recorded on the stream it runs on, and the
+/* Profiling.  When enabled, each group of back-to-back red-black half
+ * sweeps of the finest level (one level visit) is bracketed by HIP events
+ * recorded on the stream it runs on, and the
  * smoother's cell updates are counted on all levels.  out[0] = finest-level
- * half sweeps timed, out[1] = their summed kernel time in ms (synchronises
+ * half sweeps timed, out[1] = their summed time in ms (synchronises
  * the recorded events), out[2] = smoother cell updates (all levels and
  * right-hand sides; a full red+black step counts each cell once), out[3] =
  * cells of the finest level.  Reading resets the counters. */

@@ -103,6 +103,7 @@ struct Fields32 {
 struct Profile {
     bool on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    std::vector<int> launches;  // half sweeps inside each pending pair
     std::vector<hipEvent_t> spare;
     double updates = 0.0;
     hipEvent_t get() {
@@ -134,6 +135,11 @@ struct octmg_state_s {
     unsigned long long *d_norm = nullptr;
     int *d_flag = nullptr;
     int *d_active = nullptr;  // [nrhs], 1 while a right-hand side iterates
+    std::vector<int> active_host;              // last values uploaded to d_active
+    unsigned long long *h_norm = nullptr;      // pinned, host-mapped copy of d_norm
+    unsigned long long *h_norm_dev = nullptr;  // device view of h_norm
+    std::vector<double> r0_cache;              // residual of phi = 0 (valid while !r0_dirty)
+    bool r0_dirty = true;
     DevPool pool;
 };
 
@@ -217,27 +223,31 @@ struct Engine {
     int D() const { return s->geom->tree.D; }
     int Nb(int il) const { return s->geom->L[il].Nb; }
 
+    // The half sweeps of one level visit run back to back; when profiling,
+    // one event pair brackets the whole group on the finest level and the
+    // group's time is shared evenly by its launches.
     octmg_status smooth(int il, int steps) {
         Profile *P = s->prof;
-        const bool timed = P && P->on && il == (int)s->geom->L.size() - 1;
+        const bool timed = P && P->on && il == (int)s->geom->L.size() - 1 && steps > 0;
+        hipEvent_t a = nullptr, b = nullptr;
+        if (timed) {
+            a = P->get();
+            b = P->get();
+            HIPCK(hipEventRecord(a, st));
+        }
         for (int k = 0; k < steps; k++)
             for (int color = 0; color < 2; color++) {
-                hipEvent_t a = nullptr, b = nullptr;
-                if (timed) {
-                    a = P->get();
-                    b = P->get();
-                    HIPCK(hipEventRecord(a, st));
-                }
                 HIPCK(launch_gs_half<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1), color, s->nrhs, st));
-                if (timed) {
-                    HIPCK(hipEventRecord(b, st));
-                    P->pending.push_back({a, b});
-                }
                 if (P && P->on) {
                     const GeomLevel &G = s->geom->L[il];
                     P->updates += 0.5 * (double)G.nblocks * G.cpb * s->nrhs;
                 }
             }
+        if (timed) {
+            HIPCK(hipEventRecord(b, st));
+            P->pending.push_back({a, b});
+            P->launches.push_back(2 * steps);
+        }
         return OCTMG_OK;
     }
     octmg_status half_sweep(int il, int color) {
@@ -327,11 +337,15 @@ octmg_status residual_norm_dev(octmg_state s, int phi_zero, hipStream_t st) {
     return OCTMG_OK;
 }
 
+// the norms reach the host through a pinned, host-mapped buffer written by a
+// one-workgroup kernel (cheaper than a copy for a few bytes)
 octmg_status read_norms(octmg_state s, double *out, hipStream_t st) {
-    std::vector<unsigned long long> h(s->nrhs);
-    HIPCK(hipMemcpyAsync(h.data(), s->d_norm, sizeof(unsigned long long) * s->nrhs, hipMemcpyDeviceToHost, st));
+    HIPCK(launch_copy_u64(s->d_norm, s->h_norm_dev, s->nrhs, st));
     HIPCK(hipStreamSynchronize(st));
-    for (int r = 0; r < s->nrhs; r++) std::memcpy(&out[r], &h[r], sizeof(double));
+    for (int r = 0; r < s->nrhs; r++) {
+        const unsigned long long v = ((volatile unsigned long long *)s->h_norm)[r];
+        std::memcpy(&out[r], &v, sizeof(double));
+    }
     return OCTMG_OK;
 }
 
@@ -756,10 +770,10 @@ octmg_status octmg_state_create(octmg_geom g, int n_rhs, int precision, octmg_st
     HIPCK(s->pool.alloc(&s->d_norm, n_rhs));
     HIPCK(s->pool.alloc(&s->d_flag, 1));
     HIPCK(s->pool.alloc(&s->d_active, n_rhs));
-    {
-        std::vector<int> ones(n_rhs, 1);
-        HIPCK(hipMemcpy(s->d_active, ones.data(), sizeof(int) * n_rhs, hipMemcpyHostToDevice));
-    }
+    s->active_host.assign(n_rhs, 1);
+    HIPCK(hipMemcpy(s->d_active, s->active_host.data(), sizeof(int) * n_rhs, hipMemcpyHostToDevice));
+    HIPCK(hipHostMalloc((void **)&s->h_norm, sizeof(unsigned long long) * n_rhs, hipHostMallocMapped));
+    HIPCK(hipHostGetDevicePointer((void **)&s->h_norm_dev, s->h_norm, 0));
     HIPCK(hipDeviceSynchronize());
     g->refs++;
     *out = s.release();
@@ -771,6 +785,7 @@ void octmg_state_destroy(octmg_state s) {
     (void)hipSetDevice(s->geom->device);
     (void)hipDeviceSynchronize();
     octmg_geom g = s->geom;
+    if (s->h_norm) (void)hipHostFree(s->h_norm);
     delete s->prof;
     delete s;
     release_geom(g);
@@ -789,16 +804,18 @@ octmg_status octmg_profile_read(octmg_state s, double *out) {
     Profile *P = s->prof;
     double ms_total = 0.0, n = 0.0, upd = 0.0;
     if (P) {
-        for (auto &pr : P->pending) {
+        for (size_t i = 0; i < P->pending.size(); i++) {
+            auto &pr = P->pending[i];
             HIPCK(hipEventSynchronize(pr.second));
             float ms = 0.0f;
             HIPCK(hipEventElapsedTime(&ms, pr.first, pr.second));
             ms_total += ms;
-            n += 1.0;
+            n += P->launches[i];
             P->spare.push_back(pr.first);
             P->spare.push_back(pr.second);
         }
         P->pending.clear();
+        P->launches.clear();
         upd = P->updates;
         P->updates = 0.0;
     }
@@ -841,6 +858,7 @@ static octmg_status check_finite(octmg_state s, const double *dptr, long long n,
 octmg_status octmg_set_boundary(octmg_state s, const double *iface_vals, const double *domain_vals, int on_device,
                                 void *stream) {
     if (!s) return fail(OCTMG_ERR_INVALID, "null state");
+    s->r0_dirty = true;
     hipStream_t st = (hipStream_t)stream;
     octmg_geom g = s->geom;
     HIPCK(hipSetDevice(g->device));
@@ -889,6 +907,7 @@ static octmg_status set_leaf_field(octmg_state s, const double *src, int on_devi
 
 octmg_status octmg_set_rhs(octmg_state s, const double *gv, int on_device, void *stream) {
     if (!s || !gv) return fail(OCTMG_ERR_INVALID, "null argument");
+    s->r0_dirty = true;
     return set_leaf_field(s, gv, on_device, (hipStream_t)stream, 1);
 }
 
@@ -920,10 +939,14 @@ octmg_status octmg_zero_solution(octmg_state s, void *stream) {
     if (!s) return fail(OCTMG_ERR_INVALID, "null state");
     hipStream_t st = (hipStream_t)stream;
     HIPCK(hipSetDevice(s->geom->device));
+    // on uniform trees only the leaf level is ever read before a cycle
+    // overwrites it (restriction sets phi and old of coarser levels)
+    const bool all = s->geom->tree.adaptive;
     for (size_t il = 0; il < s->f64.size(); il++) {
+        if (!all && s->geom->L[il].nleaf == 0) continue;
         const long long n = s->stride[il] * s->nrhs;
         HIPCK(launch_fill(s->f64[il].phi, n, 0.0, st));
-        HIPCK(launch_fill(s->f64[il].old, n, 0.0, st));
+        if (all) HIPCK(launch_fill(s->f64[il].old, n, 0.0, st));
     }
     return OCTMG_OK;
 }
@@ -950,7 +973,9 @@ octmg_status octmg_residual_norm(octmg_state s, int phi_zero, double *out, void 
 }
 
 static octmg_status set_active(octmg_state s, const std::vector<int> &act, hipStream_t st) {
-    HIPCK(hipMemcpyAsync(s->d_active, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice, st));
+    if (act == s->active_host) return OCTMG_OK;
+    s->active_host = act;
+    HIPCK(hipMemcpyAsync(s->d_active, s->active_host.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice, st));
     HIPCK(hipStreamSynchronize(st));
     return OCTMG_OK;
 }
@@ -963,17 +988,28 @@ static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStre
     std::vector<double> r0(R), rk(R), cur(R, 0.0), prev(R, 0.0);
     std::vector<int> act(R, 1);
     STCK(set_active(s, act, st));
-    STCK(residual_norm_dev(s, 1, st));
-    STCK(read_norms(s, r0.data(), st));
+    if (s->r0_dirty) {
+        STCK(residual_norm_dev(s, 1, st));
+        STCK(read_norms(s, r0.data(), st));
+        s->r0_cache = r0;
+        s->r0_dirty = false;
+    }
+    r0 = s->r0_cache;
     if (o->zero_start) STCK(octmg_zero_solution(s, st));
     std::memset(rp, 0, sizeof(*rp));
     for (double v : r0) rp->r0 = std::max(rp->r0, v);
     int stall = 0;
     bool have_guess = !o->zero_start;
     for (int k = 0; k <= o->max_cycles; k++) {
-        if (s->precision == OCTMG_MIXED) STCK(mixed_defect(s, st));
-        else STCK(residual_norm_dev(s, 0, st));
-        STCK(read_norms(s, rk.data(), st));
+        if (s->precision == OCTMG_MIXED) {
+            STCK(mixed_defect(s, st));
+            STCK(read_norms(s, rk.data(), st));
+        } else if (k == 0 && o->zero_start) {
+            rk = r0;  // the residual of phi = 0 is r0 itself
+        } else {
+            STCK(residual_norm_dev(s, 0, st));
+            STCK(read_norms(s, rk.data(), st));
+        }
         bool all_done = true, nonfinite = false, changed = false;
         double rmax = 0.0;
         for (int r = 0; r < R; r++) {

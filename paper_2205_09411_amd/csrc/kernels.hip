@@ -688,6 +688,9 @@ __global__ void k_fill_u64(unsigned long long *p, long long n, unsigned long lon
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         p[i] = v;
 }
+__global__ void k_copy_u64(const unsigned long long *s, unsigned long long *d, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
+}
 __global__ void k_copy_d2f(const double *s, float *d, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         d[i] = (float)s[i];
@@ -794,7 +797,8 @@ __device__ void open_face_ghosts(T *tile, const LV<T> &L, const LV<T> &Lc, const
 // Stage colour `col` of block `blk` and its face halos into a ColTile.
 // All global loads of the thread are issued before the LDS writes.
 template <typename T, int N, bool ZERO>
-__device__ __forceinline__ void stage_colour(T *tile, const T *__restrict__ phi, int blk, const int *nbk, int col) {
+__device__ __forceinline__ void stage_colour(T *tile, const T *__restrict__ phi, int blk, const int *nbk, int col,
+                                             const T *interior = nullptr) {
     using B = Blk<3, N>;
     using CT = ColTile<N>;
     constexpr int NH = N / 2, PER = Per<N>::PER;
@@ -806,7 +810,7 @@ __device__ __forceinline__ void stage_colour(T *tile, const T *__restrict__ phi,
     const T *__restrict__ src = phi + (long long)blk * B::CPB + oc;
     T r[PER];
 #pragma unroll
-    for (int m = 0; m < PER; m++) r[m] = src[t + 256 * m];
+    for (int m = 0; m < PER; m++) r[m] = interior ? interior[m] : src[t + 256 * m];
     const int fh = t % NH, fr = t / NH;  // y/z face entry (N*NH <= 256)
     const int xj = t % N, xk = t / N;    // x face entry (N*N <= 256)
     const bool fz = t < N * NH, fx = t < N * N;
@@ -871,7 +875,9 @@ __global__ __launch_bounds__(256) void k_gs_half3(LV<T> L, LV<T> Lc, int color) 
     int ri[PER];
 #pragma unroll
     for (int m = 0; m < PER; m++) {
-        gv[m] = gm[threadIdx.x + 256 * m];
+        // g is read once per sweep: keep it from evicting the phi lines
+        // that neighbouring blocks read as halos
+        gv[m] = __builtin_nontemporal_load(gm + threadIdx.x + 256 * m);
         ri[m] = mo >= 0 ? L.map[mo + color * B::HALF + threadIdx.x + 256 * m] : -1;
     }
     stage_colour<T, N, false>(tile, phi, blk, nbk, 1 - color);
@@ -904,21 +910,11 @@ __global__ __launch_bounds__(256) void k_gs_half3(LV<T> L, LV<T> Lc, int color) 
     }
 }
 
-// L phi for the PER cells of colour `col` owned by this thread; `own` holds
-// their values (prefetched by the caller).  Leaves the tile in use: the
-// caller must __syncthreads() before restaging it.
-template <typename T, int N, bool ZERO>
-__device__ __forceinline__ void colour_op(const LV<T> &L, const LV<T> &Lc, const T *phi, const T *phic, T *tile,
-                                          int blk, const int *nbk, int4 P, const int *ri, int col, const T *own,
-                                          T *out) {
+// L phi at the PER cells of colour `col` owned by this thread, from the
+// other-colour tile (already staged, ghosts filled); `own` their values.
+template <typename T, int N>
+__device__ __forceinline__ void tile_op(const LV<T> &L, const T *tile, const int *ri, int col, const T *own, T *out) {
     constexpr int PER = Per<N>::PER;
-    stage_colour<T, N, ZERO>(tile, phi, blk, nbk, 1 - col);
-    __syncthreads();
-    if (nbk[0] < 0 || nbk[1] < 0 || nbk[2] < 0 || nbk[3] < 0 || nbk[4] < 0 || nbk[5] < 0) {
-        open_face_ghosts<T, N, ZERO>(tile, L, Lc, phi + (long long)blk * Blk<3, N>::CPB + col * Blk<3, N>::HALF,
-                                     phic, nbk, P, col);
-        __syncthreads();
-    }
 #pragma unroll
     for (int m = 0; m < PER; m++) {
         const int q = threadIdx.x + 256 * m;
@@ -937,6 +933,34 @@ __device__ __forceinline__ void colour_op(const LV<T> &L, const LV<T> &Lc, const
     }
 }
 
+// Pass over colour `col` of block `blk`: stage the other colour (from HBM,
+// or from `interior` registers), fill open-face ghosts, apply L.  The tile
+// stays live until the caller's next __syncthreads().
+template <typename T, int N, bool ZERO>
+__device__ __forceinline__ void colour_pass(const LV<T> &L, const LV<T> &Lc, const T *phi, const T *phic, T *tile,
+                                            int blk, const int *nbk, int4 P, const int *ri, int col, const T *own,
+                                            const T *interior, T *out) {
+    stage_colour<T, N, ZERO>(tile, phi, blk, nbk, 1 - col, interior);
+    __syncthreads();
+    if (nbk[0] < 0 || nbk[1] < 0 || nbk[2] < 0 || nbk[3] < 0 || nbk[4] < 0 || nbk[5] < 0) {
+        open_face_ghosts<T, N, ZERO>(tile, L, Lc, phi + (long long)blk * Blk<3, N>::CPB + col * Blk<3, N>::HALF,
+                                     phic, nbk, P, col);
+        __syncthreads();
+    }
+    tile_op<T, N>(L, tile, ri, col, own, out);
+}
+
+// own values of colour 1 read back from the colour-1 tile of the first pass
+template <typename T, int N>
+__device__ __forceinline__ void own_from_tile(const T *tile, T *own) {
+    constexpr int NH = N / 2, PER = Per<N>::PER;
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        const int q = threadIdx.x + 256 * m;
+        own[m] = tile[ColTile<N>::at(q / (NH * N), (q / NH) % N, q % NH)];
+    }
+}
+
 template <int N>
 __device__ __forceinline__ void q_to_ijk(int col, int q, int &i, int &j, int &k) {
     constexpr int NH = N / 2;
@@ -946,9 +970,13 @@ __device__ __forceinline__ void q_to_ijk(int col, int q, int &i, int &j, int &k)
     i = 2 * h + ((col + j + k) & 1);
 }
 
-// FAS restriction, 3D: residual of every cell (colour by colour, from LDS),
-// then the 2x2x2 means of r and phi through a natural-order LDS array.
-// phi_c goes to Lc.phi, or to Lc.old when `into_old`.
+// The kernels below read each colour array of the block once from HBM:
+// pass 0 stages colour 1 (which pass 1 then takes its own values from) and
+// pass 1 stages colour 0 from the registers that held its own values.
+
+// FAS restriction, 3D: residual of every cell, then the 2x2x2 means of phi
+// and r through a natural-order LDS array.  phi_c goes to Lc.phi, or to
+// Lc.old when `into_old`.
 template <typename T, int N, int NC>
 __global__ __launch_bounds__(256) void k_restrict_fas3(LV<T> L, LV<T> Lc, int into_old) {
     using B = Blk<3, N>;
@@ -965,68 +993,59 @@ __global__ __launch_bounds__(256) void k_restrict_fas3(LV<T> L, LV<T> Lc, int in
     const T *__restrict__ g = L.g + (long long)blockIdx.y * L.fstride;
     const T *phic = Lc.phi + (long long)blockIdx.y * Lc.fstride;
     const long long base = (long long)blk * B::CPB;
-    T r[2][PER];
+    T own0[PER], own1[PER], r0[PER], r1[PER], gv[PER];
+    int ri[PER];
+    // colour 0
 #pragma unroll
-    for (int c = 0; c < 2; c++) {
-        T own[PER], gv[PER];
-        int ri[PER];
-#pragma unroll
-        for (int m = 0; m < PER; m++) {
-            const int s = c * B::HALF + threadIdx.x + 256 * m;
-            own[m] = phi[base + s];
-            gv[m] = g[base + s];
-            ri[m] = mo >= 0 ? L.map[mo + s] : -1;
-        }
-        colour_op<T, N, false>(L, Lc, phi, phic, sm, blk, nbk, P, ri, c, own, r[c]);
-#pragma unroll
-        for (int m = 0; m < PER; m++) r[c][m] = gv[m] - r[c][m];
-        __syncthreads();
+    for (int m = 0; m < PER; m++) {
+        const int s = threadIdx.x + 256 * m;
+        own0[m] = phi[base + s];
+        gv[m] = g[base + s];
+        ri[m] = mo >= 0 ? L.map[mo + s] : -1;
     }
-    // residual means
+    colour_pass<T, N, false>(L, Lc, phi, phic, sm, blk, nbk, P, ri, 0, own0, nullptr, r0);
+    own_from_tile<T, N>(sm, own1);
 #pragma unroll
-    for (int c = 0; c < 2; c++)
-#pragma unroll
-        for (int m = 0; m < PER; m++) {
-            int i, j, k;
-            q_to_ijk<N>(c, threadIdx.x + 256 * m, i, j, k);
-            sm[(k * N + j) * N + i] = r[c][m];
-        }
+    for (int m = 0; m < PER; m++) r0[m] = gv[m] - r0[m];
     __syncthreads();
+    // colour 1
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        const int s = B::HALF + threadIdx.x + 256 * m;
+        gv[m] = g[base + s];
+        ri[m] = mo >= 0 ? L.map[mo + s] : -1;
+    }
+    colour_pass<T, N, false>(L, Lc, phi, phic, sm, blk, nbk, P, ri, 1, own1, own0, r1);
+#pragma unroll
+    for (int m = 0; m < PER; m++) r1[m] = gv[m] - r1[m];
+    __syncthreads();
+    // 2x2x2 means of r, then of phi, through natural-order LDS
     T rc[CPER], pc[CPER];
 #pragma unroll
-    for (int m = 0; m < CPER; m++) {
-        const int cc = threadIdx.x + 256 * m;
-        T s = T(0);
-        if (cc < NCELL) {
-            const int ci = cc % H, cj = (cc / H) % H, ck = cc / (H * H);
-#pragma unroll
-            for (int ch = 0; ch < 8; ch++)
-                s += sm[((2 * ck + ((ch >> 2) & 1)) * N + 2 * cj + ((ch >> 1) & 1)) * N + 2 * ci + (ch & 1)];
-        }
-        rc[m] = s;
-    }
-    __syncthreads();
-    // phi means (re-read from cache)
-#pragma unroll
-    for (int c = 0; c < 2; c++)
+    for (int pass = 0; pass < 2; pass++) {
 #pragma unroll
         for (int m = 0; m < PER; m++) {
             int i, j, k;
-            q_to_ijk<N>(c, threadIdx.x + 256 * m, i, j, k);
-            sm[(k * N + j) * N + i] = phi[base + c * B::HALF + threadIdx.x + 256 * m];
+            q_to_ijk<N>(0, threadIdx.x + 256 * m, i, j, k);
+            sm[(k * N + j) * N + i] = pass == 0 ? r0[m] : own0[m];
+            q_to_ijk<N>(1, threadIdx.x + 256 * m, i, j, k);
+            sm[(k * N + j) * N + i] = pass == 0 ? r1[m] : own1[m];
         }
-    __syncthreads();
+        __syncthreads();
 #pragma unroll
-    for (int m = 0; m < CPER; m++) {
-        const int cc = threadIdx.x + 256 * m;
-        T s = T(0);
-        if (cc < NCELL) {
-            const int ci = cc % H, cj = (cc / H) % H, ck = cc / (H * H);
+        for (int m = 0; m < CPER; m++) {
+            const int cc = threadIdx.x + 256 * m;
+            T s = T(0);
+            if (cc < NCELL) {
+                const int ci = cc % H, cj = (cc / H) % H, ck = cc / (H * H);
 #pragma unroll
-            for (int ch = 0; ch < 8; ch++)
-                s += sm[((2 * ck + ((ch >> 2) & 1)) * N + 2 * cj + ((ch >> 1) & 1)) * N + 2 * ci + (ch & 1)];
+                for (int ch = 0; ch < 8; ch++)
+                    s += sm[((2 * ck + ((ch >> 2) & 1)) * N + 2 * cj + ((ch >> 1) & 1)) * N + 2 * ci + (ch & 1)];
+            }
+            if (pass == 0) rc[m] = s;
+            else pc[m] = s;
         }
-        pc[m] = s;
+        __syncthreads();
     }
     T *phiw = (into_old ? Lc.old : Lc.phi) + (long long)blockIdx.y * Lc.fstride;
     T *gw = Lc.g + (long long)blockIdx.y * Lc.fstride;
@@ -1067,30 +1086,28 @@ __global__ __launch_bounds__(256) void k_fas_rhs3(LV<T> L, LV<T> Lc, int do_rhs)
     face_ids<T, N>(L, P, nbk);
     const int mo = L.map_off ? L.map_off[blk] : -1;
     const T *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
-    // the tile of the second colour overwrites nothing the first colour's
-    // results depend on: g and old are written only after both passes
-    T lp[2][PER];
+    T own0[PER], own1[PER], lp[PER], gv[PER];
+    int ri[PER];
 #pragma unroll
     for (int c = 0; c < 2; c++) {
-        T own[PER];
-        int ri[PER];
 #pragma unroll
         for (int m = 0; m < PER; m++) {
             const int s = c * B::HALF + threadIdx.x + 256 * m;
-            own[m] = phi[base + s];
+            if (c == 0) own0[m] = phi[base + s];
+            gv[m] = g[base + s];
             ri[m] = mo >= 0 ? L.map[mo + s] : -1;
         }
-        colour_op<T, N, false>(L, Lc, phi, phic, tile, blk, nbk, P, ri, c, own, lp[c]);
-        __syncthreads();
-    }
-#pragma unroll
-    for (int c = 0; c < 2; c++)
+        colour_pass<T, N, false>(L, Lc, phi, phic, tile, blk, nbk, P, ri, c, c == 0 ? own0 : own1,
+                                 c == 0 ? nullptr : own0, lp);
+        if (c == 0) own_from_tile<T, N>(tile, own1);
 #pragma unroll
         for (int m = 0; m < PER; m++) {
             const int s = c * B::HALF + threadIdx.x + 256 * m;
-            g[base + s] = lp[c][m] + g[base + s];
-            old[base + s] = phi[base + s];
+            g[base + s] = lp[m] + gv[m];
+            old[base + s] = c == 0 ? own0[m] : own1[m];
         }
+        __syncthreads();
+    }
 }
 
 // max |g - L phi| over a leaf block (3D); ZERO: residual of phi = 0
@@ -1111,22 +1128,31 @@ __global__ __launch_bounds__(256) void k_residual_max3(LV<T> L, LV<T> Lc, unsign
     const T *__restrict__ g = L.g + (long long)blockIdx.y * L.fstride;
     const T *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
     const long long base = (long long)blk * B::CPB;
+    T own0[PER], own1[PER], lp[PER], gv[PER];
+    int ri[PER];
     double mx = 0.0;
-#pragma unroll 1
+#pragma unroll
     for (int c = 0; c < 2; c++) {
-        T own[PER], gv[PER], lp[PER];
-        int ri[PER];
 #pragma unroll
         for (int m = 0; m < PER; m++) {
             const int s = c * B::HALF + threadIdx.x + 256 * m;
-            own[m] = ZERO ? T(0) : phi[base + s];
+            if (c == 0) own0[m] = ZERO ? T(0) : phi[base + s];
             gv[m] = g[base + s];
             ri[m] = mo >= 0 ? L.map[mo + s] : -1;
         }
-        colour_op<T, N, ZERO>(L, Lc, phi, phic, tile, blk, nbk, P, ri, c, own, lp);
-        __syncthreads();
+        colour_pass<T, N, ZERO>(L, Lc, phi, phic, tile, blk, nbk, P, ri, c, c == 0 ? own0 : own1,
+                                c == 0 || ZERO ? nullptr : own0, lp);
+        if (c == 0) {
+            if (ZERO) {
+#pragma unroll
+                for (int m = 0; m < PER; m++) own1[m] = T(0);
+            } else {
+                own_from_tile<T, N>(tile, own1);
+            }
+        }
 #pragma unroll
         for (int m = 0; m < PER; m++) mx = fmax(mx, fabs((double)(gv[m] - lp[m])));
+        __syncthreads();
     }
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
     if (threadIdx.x % 64 == 0) wmax[threadIdx.x / 64] = mx;
@@ -1198,20 +1224,21 @@ __global__ __launch_bounds__(256) void k_defect3(LV<double> L, LV<double> Lc, LV
     const long long base = (long long)blk * B::CPB;
     float *g32 = L32.g + (long long)blockIdx.y * L32.fstride + base;
     float *p32 = L32.phi + (long long)blockIdx.y * L32.fstride + base;
+    double own0[PER], own1[PER], lp[PER], gv[PER];
+    int ri[PER];
     double mx = 0.0;
-#pragma unroll 1
+#pragma unroll
     for (int c = 0; c < 2; c++) {
-        double own[PER], gv[PER], lp[PER];
-        int ri[PER];
 #pragma unroll
         for (int m = 0; m < PER; m++) {
             const int s = c * B::HALF + threadIdx.x + 256 * m;
-            own[m] = phi[base + s];
+            if (c == 0) own0[m] = phi[base + s];
             gv[m] = g[base + s];
             ri[m] = mo >= 0 ? L.map[mo + s] : -1;
         }
-        colour_op<double, N, false>(L, Lc, phi, phic, tile, blk, nbk, P, ri, c, own, lp);
-        __syncthreads();
+        colour_pass<double, N, false>(L, Lc, phi, phic, tile, blk, nbk, P, ri, c, c == 0 ? own0 : own1,
+                                      c == 0 ? nullptr : own0, lp);
+        if (c == 0) own_from_tile<double, N>(tile, own1);
 #pragma unroll
         for (int m = 0; m < PER; m++) {
             const int s = c * B::HALF + threadIdx.x + 256 * m;
@@ -1220,6 +1247,7 @@ __global__ __launch_bounds__(256) void k_defect3(LV<double> L, LV<double> Lc, LV
             g32[s] = (float)r;
             p32[s] = 0.0f;
         }
+        __syncthreads();
     }
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
     if (threadIdx.x % 64 == 0) wmax[threadIdx.x / 64] = mx;
@@ -1428,6 +1456,10 @@ hipError_t launch_fillf(float *p, long long n, float v, hipStream_t s) {
 hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long long v, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_copy_u64(const unsigned long long *src, unsigned long long *dst, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(64), 0, s, src, dst, n);
     return hipGetLastError();
 }
 hipError_t launch_copy_d2f(const double *src, float *dst, long long n, hipStream_t s) {
