@@ -153,6 +153,12 @@ octmg_status octmg_state_create(octmg_geom g, int n_rhs, int precision, octmg_st
 void octmg_state_destroy(octmg_state s);
 /* Smoothing steps per level visit (default 2 and 2). */
 octmg_status octmg_state_set_smoothing(octmg_state s, int n_down, int n_up);
+/* Levels with at most max_blocks blocks (3D) run the bottom of every
+ * V-cycle -- the same smoothing, restriction, coarse solve and prolongation
+ * steps (Sec. 2.2) -- inside one cooperative kernel launch with grid-wide
+ * barriers between the steps; 0 (the default) launches every step
+ * separately.  Results are identical either way. */
+octmg_status octmg_state_set_fused_levels(octmg_state s, int max_blocks);
 /* Dirichlet data shared by all right-hand sides: phi_b at every interface
  * point (octmg_geom_iface_points order; NULL = all zero) and at every domain
  * face point (octmg_geom_domain_points order; NULL = all zero).  The

@@ -140,6 +140,11 @@ struct octmg_state_s {
     unsigned long long *h_norm_dev = nullptr;  // device view of h_norm
     std::vector<double> r0_cache;              // residual of phi = 0 (valid while !r0_dirty)
     bool r0_dirty = true;
+    int fused_max_blocks = 0;                  // levels with <= this many blocks run fused (0: off)
+    int fused_top = 0;                         // highest fused level (0: none)
+    int fused_grid64 = 0, fused_grid32 = 0;    // co-resident workgroups of the fused kernel
+    SmallLevels<double> *d_small64 = nullptr;  // device copies of the fused level tables
+    SmallLevels<float> *d_small32 = nullptr;
     DevPool pool;
 };
 
@@ -285,14 +290,18 @@ struct Engine {
             HIPCK(launch_restrict_phi<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), s->nrhs, st));
         return OCTMG_OK;
     }
-    // FAS V-cycle with top level `top` (Sec. 2.2)
+    octmg_status fused(int top);
+    // FAS V-cycle with top level `top` (Sec. 2.2).  Levels up to fused_top
+    // (few blocks each) run in one cooperative launch with the same steps.
     octmg_status vcycle(int top) {
-        for (int il = top; il > 0; il--) {
+        const int ft = std::min(top, s->fused_top);
+        for (int il = top; il > ft; il--) {
             STCK(smooth(il, s->n_down));
             STCK(restrict_fas(il));
         }
-        STCK(coarse_solve());
-        for (int il = 1; il <= top; il++) {
+        if (ft >= 1) STCK(fused(ft));
+        else STCK(coarse_solve());
+        for (int il = std::max(ft, 0) + 1; il <= top; il++) {
             STCK(prolong(il, 0));
             STCK(smooth(il, s->n_up));
         }
@@ -317,6 +326,22 @@ struct Engine {
     }
 };
 
+template <>
+octmg_status Engine<double>::fused(int top) {
+    int most = 16;
+    for (int il = 0; il <= top; il++) most = std::max(most, s->geom->L[il].nblocks);
+    const int grid = std::max(1, std::min(s->fused_grid64, most * s->nrhs));
+    HIPCK(launch_small_vcycle<double>(s->d_small64, top, grid, st));
+    return OCTMG_OK;
+}
+template <>
+octmg_status Engine<float>::fused(int top) {
+    int most = 16;
+    for (int il = 0; il <= top; il++) most = std::max(most, s->geom->L[il].nblocks);
+    const int grid = std::max(1, std::min(s->fused_grid32, most * s->nrhs));
+    HIPCK(launch_small_vcycle<float>(s->d_small32, top, grid, st));
+    return OCTMG_OK;
+}
 template <>
 hipError_t Engine<double>::fill(double *p, long long n) { return launch_fill(p, n, 0.0, st); }
 template <>
@@ -378,6 +403,43 @@ octmg_status mixed_correct(octmg_state s, int kind, hipStream_t st) {
         if (G.nleaf == 0) continue;
         HIPCK(launch_update(D, G.Nb, lv64(s, il), lv32(s, il), G.d_leaf_blocks, G.nleaf, s->nrhs, st));
     }
+    return OCTMG_OK;
+}
+
+// (re)build the device tables of the fused bottom of the V-cycle
+octmg_status setup_fused(octmg_state s) {
+    s->fused_top = 0;
+    if (s->fused_max_blocks <= 0 || s->geom->tree.D != 3) return OCTMG_OK;
+    int ft = 0;
+    for (int il = 0; il < (int)s->geom->L.size() && il < kMaxSmallLevels; il++) {
+        if (s->geom->L[il].nblocks > s->fused_max_blocks) break;
+        ft = il;
+    }
+    if (ft < 1) return OCTMG_OK;
+    SmallLevels<double> h64{};
+    SmallLevels<float> h32{};
+    for (int il = 0; il <= ft; il++) {
+        h64.L[il] = lv64(s, il);
+        h64.N[il] = s->geom->L[il].Nb;
+        if (s->precision == OCTMG_MIXED) h32.L[il] = lv32(s, il);
+        h32.N[il] = s->geom->L[il].Nb;
+    }
+    h64.n_down = h32.n_down = s->n_down;
+    h64.n_up = h32.n_up = s->n_up;
+    h64.nrhs = h32.nrhs = s->nrhs;
+    h64.into_old = h32.into_old = s->geom->tree.adaptive ? 1 : 0;
+    h64.M = h32.M = s->geom->d_M;
+    h64.S = h32.S = s->geom->d_S;
+    if (!s->d_small64) {
+        HIPCK(s->pool.alloc(&s->d_small64, 1));
+        HIPCK(s->pool.alloc(&s->d_small32, 1));
+        HIPCK(small_vcycle_max_grid<double>(&s->fused_grid64));
+        HIPCK(small_vcycle_max_grid<float>(&s->fused_grid32));
+    }
+    if (s->fused_grid64 < 1 || s->fused_grid32 < 1) return OCTMG_OK;
+    HIPCK(hipMemcpy(s->d_small64, &h64, sizeof(h64), hipMemcpyHostToDevice));
+    HIPCK(hipMemcpy(s->d_small32, &h32, sizeof(h32), hipMemcpyHostToDevice));
+    s->fused_top = ft;
     return OCTMG_OK;
 }
 
@@ -774,6 +836,7 @@ octmg_status octmg_state_create(octmg_geom g, int n_rhs, int precision, octmg_st
     HIPCK(hipMemcpy(s->d_active, s->active_host.data(), sizeof(int) * n_rhs, hipMemcpyHostToDevice));
     HIPCK(hipHostMalloc((void **)&s->h_norm, sizeof(unsigned long long) * n_rhs, hipHostMallocMapped));
     HIPCK(hipHostGetDevicePointer((void **)&s->h_norm_dev, s->h_norm, 0));
+    STCK(setup_fused(s.get()));
     HIPCK(hipDeviceSynchronize());
     g->refs++;
     *out = s.release();
@@ -831,7 +894,15 @@ octmg_status octmg_state_set_smoothing(octmg_state s, int n_down, int n_up) {
     if (!s || n_down < 0 || n_up < 0 || n_down > 16 || n_up > 16) return fail(OCTMG_ERR_INVALID, "bad argument");
     s->n_down = n_down;
     s->n_up = n_up;
-    return OCTMG_OK;
+    HIPCK(hipSetDevice(s->geom->device));
+    return setup_fused(s);
+}
+
+octmg_status octmg_state_set_fused_levels(octmg_state s, int max_blocks) {
+    if (!s || max_blocks < 0) return fail(OCTMG_ERR_INVALID, "bad argument");
+    s->fused_max_blocks = max_blocks;
+    HIPCK(hipSetDevice(s->geom->device));
+    return setup_fused(s);
 }
 
 static octmg_status stage_in(const double *src, size_t n, int on_device, hipStream_t st, double **dev,

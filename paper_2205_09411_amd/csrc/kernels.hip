@@ -12,6 +12,7 @@
 //                      makes the coarse flux equal the averaged fine flux.
 // Cells near the interface carry their own stencil (record index per cell,
 // Sec. 3.6.2); every other cell uses the constant 2D+1 point Laplacian.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include "octmg_internal.hpp"
@@ -858,19 +859,17 @@ __device__ __forceinline__ void tile_neighbours(const T *tile, int col, int q, i
 
 // red-black half sweep
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_gs_half3(LV<T> L, LV<T> Lc, int color) {
+__device__ __forceinline__ void gs_half3_body(const LV<T> &L, const LV<T> &Lc, int color, int blk, int rhs, T *tile) {
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER;
-    if (inactive(L)) return;
-    __shared__ T tile[ColTile<N>::SIZE];
-    const int blk = xcd_block();
+    if (L.active && !L.active[rhs]) return;
     const int4 P = L.pos[blk];
     int nbk[6];
     face_ids<T, N>(L, P, nbk);
     const int mo = L.map_off ? L.map_off[blk] : -1;
-    T *__restrict__ phi = L.phi + (long long)blockIdx.y * L.fstride;
+    T *__restrict__ phi = L.phi + (long long)rhs * L.fstride;
     const long long base = (long long)blk * B::CPB;
-    const T *__restrict__ gm = L.g + (long long)blockIdx.y * L.fstride + base + color * B::HALF;
+    const T *__restrict__ gm = L.g + (long long)rhs * L.fstride + base + color * B::HALF;
     T gv[PER];
     int ri[PER];
 #pragma unroll
@@ -882,7 +881,7 @@ __global__ __launch_bounds__(256) void k_gs_half3(LV<T> L, LV<T> Lc, int color) 
     }
     stage_colour<T, N, false>(tile, phi, blk, nbk, 1 - color);
     __syncthreads();
-    const T *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
+    const T *phic = Lc.phi ? Lc.phi + (long long)rhs * Lc.fstride : nullptr;
     T *__restrict__ dst = phi + base + color * B::HALF;
     if (nbk[0] < 0 || nbk[1] < 0 || nbk[2] < 0 || nbk[3] < 0 || nbk[4] < 0 || nbk[5] < 0) {
         open_face_ghosts<T, N, false>(tile, L, Lc, dst, phic, nbk, P, color);
@@ -908,6 +907,14 @@ __global__ __launch_bounds__(256) void k_gs_half3(LV<T> L, LV<T> Lc, int color) 
         }
         dst[q] = nv;
     }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_gs_half3(LV<T> L, LV<T> Lc, int color) {
+    using B = Blk<3, N>;
+    constexpr int PER = Per<N>::PER;
+    __shared__ T tile[ColTile<N>::SIZE];
+    gs_half3_body<T, N>(L, Lc, color, xcd_block(), blockIdx.y, tile);
 }
 
 // L phi at the PER cells of colour `col` owned by this thread, from the
@@ -978,20 +985,18 @@ __device__ __forceinline__ void q_to_ijk(int col, int q, int &i, int &j, int &k)
 // and r through a natural-order LDS array.  phi_c goes to Lc.phi, or to
 // Lc.old when `into_old`.
 template <typename T, int N, int NC>
-__global__ __launch_bounds__(256) void k_restrict_fas3(LV<T> L, LV<T> Lc, int into_old) {
+__device__ __forceinline__ void restrict_fas3_body(const LV<T> &L, const LV<T> &Lc, int into_old, int blk, int rhs, T *sm) {
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER, H = N / 2, NCELL = H * H * H, CPER = (NCELL + 255) / 256;
     constexpr int SM = ColTile<N>::SIZE > B::CPB ? ColTile<N>::SIZE : B::CPB;
-    if (inactive(L)) return;
-    __shared__ T sm[SM];
-    const int blk = xcd_block();
+    if (L.active && !L.active[rhs]) return;
     const int4 P = L.pos[blk];
     int nbk[6];
     face_ids<T, N>(L, P, nbk);
     const int mo = L.map_off ? L.map_off[blk] : -1;
-    const T *__restrict__ phi = L.phi + (long long)blockIdx.y * L.fstride;
-    const T *__restrict__ g = L.g + (long long)blockIdx.y * L.fstride;
-    const T *phic = Lc.phi + (long long)blockIdx.y * Lc.fstride;
+    const T *__restrict__ phi = L.phi + (long long)rhs * L.fstride;
+    const T *__restrict__ g = L.g + (long long)rhs * L.fstride;
+    const T *phic = Lc.phi + (long long)rhs * Lc.fstride;
     const long long base = (long long)blk * B::CPB;
     T own0[PER], own1[PER], r0[PER], r1[PER], gv[PER];
     int ri[PER];
@@ -1047,8 +1052,8 @@ __global__ __launch_bounds__(256) void k_restrict_fas3(LV<T> L, LV<T> Lc, int in
         }
         __syncthreads();
     }
-    T *phiw = (into_old ? Lc.old : Lc.phi) + (long long)blockIdx.y * Lc.fstride;
-    T *gw = Lc.g + (long long)blockIdx.y * Lc.fstride;
+    T *phiw = (into_old ? Lc.old : Lc.phi) + (long long)rhs * Lc.fstride;
+    T *gw = Lc.g + (long long)rhs * Lc.fstride;
     const int C0[3] = {P.x * H, P.y * H, P.z * H};
     const int pb = block_at<T, 3>(Lc, C0[0] / NC, C0[1] / NC, C0[2] / NC);
     if (pb < 0) return;  // excluded by construction: every block has a parent
@@ -1065,17 +1070,24 @@ __global__ __launch_bounds__(256) void k_restrict_fas3(LV<T> L, LV<T> Lc, int in
     }
 }
 
+template <typename T, int N, int NC>
+__global__ __launch_bounds__(256) void k_restrict_fas3(LV<T> L, LV<T> Lc, int into_old) {
+    using B = Blk<3, N>;
+    constexpr int PER = Per<N>::PER, H = N / 2, NCELL = H * H * H, CPER = (NCELL + 255) / 256;
+    constexpr int SM = ColTile<N>::SIZE > B::CPB ? ColTile<N>::SIZE : B::CPB;
+    __shared__ T sm[SM];
+    restrict_fas3_body<T, N, NC>(L, Lc, into_old, xcd_block(), blockIdx.y, sm);
+}
+
 // FAS rhs on parent blocks (g = L phi + g) and old = phi, 3D
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_fas_rhs3(LV<T> L, LV<T> Lc, int do_rhs) {
+__device__ __forceinline__ void fas_rhs3_body(const LV<T> &L, const LV<T> &Lc, int do_rhs, int blk, int rhs, T *tile) {
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER;
-    if (inactive(L)) return;
-    __shared__ T tile[ColTile<N>::SIZE];
-    const int blk = xcd_block();
-    T *phi = L.phi + (long long)blockIdx.y * L.fstride;
-    T *g = L.g + (long long)blockIdx.y * L.fstride;
-    T *old = L.old + (long long)blockIdx.y * L.fstride;
+    if (L.active && !L.active[rhs]) return;
+    T *phi = L.phi + (long long)rhs * L.fstride;
+    T *g = L.g + (long long)rhs * L.fstride;
+    T *old = L.old + (long long)rhs * L.fstride;
     const long long base = (long long)blk * B::CPB;
     if (L.leaf[blk] || !do_rhs) {
         for (int s = threadIdx.x; s < B::CPB; s += 256) old[base + s] = phi[base + s];
@@ -1085,7 +1097,7 @@ __global__ __launch_bounds__(256) void k_fas_rhs3(LV<T> L, LV<T> Lc, int do_rhs)
     int nbk[6];
     face_ids<T, N>(L, P, nbk);
     const int mo = L.map_off ? L.map_off[blk] : -1;
-    const T *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
+    const T *phic = Lc.phi ? Lc.phi + (long long)rhs * Lc.fstride : nullptr;
     T own0[PER], own1[PER], lp[PER], gv[PER];
     int ri[PER];
 #pragma unroll
@@ -1108,6 +1120,14 @@ __global__ __launch_bounds__(256) void k_fas_rhs3(LV<T> L, LV<T> Lc, int do_rhs)
         }
         __syncthreads();
     }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_fas_rhs3(LV<T> L, LV<T> Lc, int do_rhs) {
+    using B = Blk<3, N>;
+    constexpr int PER = Per<N>::PER;
+    __shared__ T tile[ColTile<N>::SIZE];
+    fas_rhs3_body<T, N>(L, Lc, do_rhs, xcd_block(), blockIdx.y, tile);
 }
 
 // max |g - L phi| over a leaf block (3D); ZERO: residual of phi = 0
@@ -1167,16 +1187,14 @@ __global__ __launch_bounds__(256) void k_residual_max3(LV<T> L, LV<T> Lc, unsign
 // prolongation, 3D: the coarse correction of the parent region (plus a
 // one-cell halo) is staged in LDS, then every fine cell is updated once.
 template <typename T, int N, int NC>
-__global__ __launch_bounds__(256) void k_prolong3(LV<T> L, LV<T> Lc, int solution) {
+__device__ __forceinline__ void prolong3_body(const LV<T> &L, const LV<T> &Lc, int solution, int blk, int rhs, T *et) {
     using B = Blk<3, N>;
     constexpr int H = N / 2, E = H + 2, ESZ = E * E * E, PER = B::CPB / 256;
-    if (inactive(L)) return;
-    __shared__ T et[ESZ];
-    const int blk = xcd_block();
+    if (L.active && !L.active[rhs]) return;
     const int4 P = L.pos[blk];
-    const T *phic = Lc.phi + (long long)blockIdx.y * Lc.fstride;
-    const T *oldc = Lc.old + (long long)blockIdx.y * Lc.fstride;
-    T *__restrict__ phi = L.phi + (long long)blockIdx.y * L.fstride + (long long)blk * B::CPB;
+    const T *phic = Lc.phi + (long long)rhs * Lc.fstride;
+    const T *oldc = Lc.old + (long long)rhs * Lc.fstride;
+    T *__restrict__ phi = L.phi + (long long)rhs * L.fstride + (long long)blk * B::CPB;
     T f[PER];
 #pragma unroll
     for (int m = 0; m < PER; m++) f[m] = phi[threadIdx.x + 256 * m];
@@ -1202,6 +1220,14 @@ __global__ __launch_bounds__(256) void k_prolong3(LV<T> L, LV<T> Lc, int solutio
         }
         phi[s] = f[m] + e;
     }
+}
+
+template <typename T, int N, int NC>
+__global__ __launch_bounds__(256) void k_prolong3(LV<T> L, LV<T> Lc, int solution) {
+    using B = Blk<3, N>;
+    constexpr int H = N / 2, E = H + 2, ESZ = E * E * E, PER = B::CPB / 256;
+    __shared__ T et[ESZ];
+    prolong3_body<T, N, NC>(L, Lc, solution, xcd_block(), blockIdx.y, et);
 }
 
 // mixed precision defect (FP64): g32 = g - L phi on a leaf block, phi32 = 0
@@ -1257,6 +1283,144 @@ __global__ __launch_bounds__(256) void k_defect3(LV<double> L, LV<double> Lc, LV
         if (mx != mx) mx = __longlong_as_double(0x7ff0000000000000ll);
         atomicMax(out + blockIdx.y, (unsigned long long)__double_as_longlong(mx));
     }
+}
+
+// ================================================ bottom of the V-cycle, fused
+// Levels with few blocks are launch- and latency-bound: one launch costs a
+// few microseconds even for a single workgroup.  k_small_vcycle runs the
+// V-cycle below and including level `top` (smoothing, FAS restriction,
+// coarse solve, prolongation) in one cooperative launch.  Each phase is a
+// loop of the workgroups over (block, rhs) items calling the same per-block
+// bodies as the standalone kernels, followed by a grid-wide barrier, so the
+// results are identical to the launch-per-phase path.
+
+__device__ __forceinline__ void copy_parents_body3(int N, const LV<double> &L, int blk, int rhs) {
+    if (L.active && !L.active[rhs]) return;
+    if (L.leaf[blk]) return;
+    const int cpb = N * N * N;
+    const long long o = (long long)rhs * L.fstride + (long long)blk * cpb;
+    for (int c = threadIdx.x; c < cpb; c += blockDim.x) L.phi[o + c] = L.old[o + c];
+}
+__device__ __forceinline__ void copy_parents_body3(int N, const LV<float> &L, int blk, int rhs) {
+    if (L.active && !L.active[rhs]) return;
+    if (L.leaf[blk]) return;
+    const int cpb = N * N * N;
+    const long long o = (long long)rhs * L.fstride + (long long)blk * cpb;
+    for (int c = threadIdx.x; c < cpb; c += blockDim.x) L.phi[o + c] = L.old[o + c];
+}
+
+// exact coarse solve, rows [tile*32, tile*32+32) of one rhs (3D, 8^3 grid)
+template <typename T>
+__device__ __forceinline__ void coarse_solve3_body(const LV<T> &L0, const double *M, const double *S, int tile, int rhs,
+                                                   double *rhsv) {
+    constexpr int NB = 8, NCELL = 512, ROWS = 32;
+    if (L0.active && !L0.active[rhs]) return;
+    const T *g = L0.g + (long long)rhs * L0.fstride;
+    T *phi = L0.phi + (long long)rhs * L0.fstride;
+    const int mo = L0.map_off ? L0.map_off[0] : -1;
+    const double inv = 1.0 / ((double)L0.dx2);
+    for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
+        const int i = c % NB, j = (c / NB) % NB, k = c / (NB * NB);
+        const int si = split_of<3, NB>(i, j, k);
+        const int ri = mo >= 0 ? L0.map[mo + si] : -1;
+        double r = (double)g[si];
+        if (ri >= 0 && L0.b) r -= (double)L0.b[ri];
+        for (int d = 0; d < 6; d++) {
+            const int ax = d >> 1, s = (d & 1) ? 1 : -1;
+            int q[3] = {i, j, k};
+            q[ax] += s;
+            if (q[ax] >= 0 && q[ax] < NB) continue;
+            const double cc = ri >= 0 ? (double)L0.rec[8 * (long long)ri + d] : inv;
+            if (cc == 0.0) continue;
+            const double bv = L0.bcv ? (double)L0.bcv[face_slot<3>(ax, s, i, j, k, NB, L0.nface)] : 0.0;
+            r -= 2.0 * cc * bv;
+        }
+        rhsv[c] = S[c] * r;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int row = tile * ROWS + wave; row < (tile + 1) * ROWS; row += blockDim.x / 64) {
+        double acc = 0.0;
+        for (int c = lane; c < NCELL; c += 64) acc += M[(long long)row * NCELL + c] * rhsv[c];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+        if (lane == 0) {
+            const int i = row % NB, j = (row / NB) % NB, k = row / (NB * NB);
+            phi[split_of<3, NB>(i, j, k)] = (T)acc;
+        }
+    }
+}
+
+// out-of-line entry points of the per-block bodies for the fused kernel: each
+// keeps its own register allocation instead of the fused kernel taking the
+// union of all of them
+template <typename T, int N>
+__device__ __noinline__ void gs_call(const LV<T> &L, const LV<T> &Lc, int color, int blk, int rhs, T *sm) {
+    gs_half3_body<T, N>(L, Lc, color, blk, rhs, sm);
+}
+template <typename T, int N, int NC>
+__device__ __noinline__ void restrict_call(const LV<T> &L, const LV<T> &Lc, int into_old, int blk, int rhs, T *sm) {
+    restrict_fas3_body<T, N, NC>(L, Lc, into_old, blk, rhs, sm);
+}
+template <typename T, int N>
+__device__ __noinline__ void fas_rhs_call(const LV<T> &L, const LV<T> &Lc, int blk, int rhs, T *sm) {
+    fas_rhs3_body<T, N>(L, Lc, 1, blk, rhs, sm);
+}
+template <typename T, int N, int NC>
+__device__ __noinline__ void prolong_call(const LV<T> &L, const LV<T> &Lc, int blk, int rhs, T *sm) {
+    prolong3_body<T, N, NC>(L, Lc, 0, blk, rhs, sm);
+}
+template <typename T>
+__device__ __noinline__ void coarse_call(const LV<T> &L0, const double *M, const double *S, int tile, int rhs,
+                                         double *sm) {
+    coarse_solve3_body<T>(L0, M, S, tile, rhs, sm);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_small_vcycle(const SmallLevels<T> *__restrict__ P, int top) {
+    __shared__ double smem[4096];  // largest body: restriction of a 16^3 block (32 KB)
+    T *sm = reinterpret_cast<T *>(smem);
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    const int G = gridDim.x, R = P->nrhs, into_old = P->into_old;
+#define OCTMG_PHASE(NBLK, ...)                                                  \
+    {                                                                           \
+        const int nb_ = (NBLK);                                                 \
+        for (int it_ = blockIdx.x; it_ < nb_ * R; it_ += G) {                   \
+            const int blk = it_ % nb_, rhs = it_ / nb_;                         \
+            __VA_ARGS__;                                                        \
+            __syncthreads();                                                    \
+        }                                                                       \
+        grid.sync();                                                            \
+    }
+    for (int il = top; il > 0; il--) {
+        const LV<T> &L = P->L[il], &Lc = P->L[il - 1];
+        const LV<T> &Lcc = P->L[il >= 2 ? il - 2 : il - 1];
+        const int N = P->N[il], NC = P->N[il - 1];
+        for (int st = 0; st < P->n_down; st++)
+            for (int color = 0; color < 2; color++)
+                OCTMG_PHASE(L.nblocks, if (N == 16) gs_call<T, 16>(L, Lc, color, blk, rhs, sm);
+                            else gs_call<T, 8>(L, Lc, color, blk, rhs, sm))
+        OCTMG_PHASE(L.nblocks, if (N == 16 && NC == 16) restrict_call<T, 16, 16>(L, Lc, into_old, blk, rhs, sm);
+                    else if (N == 16) restrict_call<T, 16, 8>(L, Lc, into_old, blk, rhs, sm);
+                    else restrict_call<T, 8, 8>(L, Lc, into_old, blk, rhs, sm))
+        if (into_old) OCTMG_PHASE(Lc.nblocks, copy_parents_body3(NC, Lc, blk, rhs))
+        // the coarse level's refinement ghosts come from level il-2; level 0
+        // has none (it is complete), so Lcc is only read when il >= 2
+        OCTMG_PHASE(Lc.nblocks, if (NC == 16) fas_rhs_call<T, 16>(Lc, Lcc, blk, rhs, sm);
+                    else fas_rhs_call<T, 8>(Lc, Lcc, blk, rhs, sm))
+    }
+    OCTMG_PHASE(16, coarse_call<T>(P->L[0], P->M, P->S, blk, rhs, smem))
+    for (int il = 1; il <= top; il++) {
+        const LV<T> &L = P->L[il], &Lc = P->L[il - 1];
+        const int N = P->N[il], NC = P->N[il - 1];
+        OCTMG_PHASE(L.nblocks, if (N == 16 && NC == 16) prolong_call<T, 16, 16>(L, Lc, blk, rhs, sm);
+                    else if (N == 16) prolong_call<T, 16, 8>(L, Lc, blk, rhs, sm);
+                    else prolong_call<T, 8, 8>(L, Lc, blk, rhs, sm))
+        for (int st = 0; st < P->n_up; st++)
+            for (int color = 0; color < 2; color++)
+                OCTMG_PHASE(L.nblocks, if (N == 16) gs_call<T, 16>(L, Lc, color, blk, rhs, sm);
+                            else gs_call<T, 8>(L, Lc, color, blk, rhs, sm))
+    }
+#undef OCTMG_PHASE
 }
 
 int grid_for(long long n) {
@@ -1385,6 +1549,33 @@ hipError_t launch_residual_max(int D, int N, const LV<T> &L, const LV<T> &Lc, in
 #undef RM
     return hipErrorInvalidValue;
 }
+
+template <typename T>
+hipError_t launch_small_vcycle(const SmallLevels<T> *P, int top, int grid, hipStream_t s) {
+    const SmallLevels<T> *arg = P;
+    int top_arg = top;
+    void *args[] = {&arg, &top_arg};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_small_vcycle<T>), dim3(grid), dim3(256), args,
+                                      0, s);
+}
+
+template <typename T>
+hipError_t small_vcycle_max_grid(int *grid) {
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_small_vcycle<T>), 256, 0);
+    if (e != hipSuccess) return e;
+    *grid = per_cu * prop.multiProcessorCount;
+    return hipSuccess;
+}
+template hipError_t launch_small_vcycle<double>(const SmallLevels<double> *, int, int, hipStream_t);
+template hipError_t launch_small_vcycle<float>(const SmallLevels<float> *, int, int, hipStream_t);
+template hipError_t small_vcycle_max_grid<double>(int *);
+template hipError_t small_vcycle_max_grid<float>(int *);
 
 hipError_t launch_scatter_leaf(int D, int N, const LV<double> &L, const int *lb, int nlb, const double *src,
                                long long src_stride, long long base, int field, int nrhs, hipStream_t s) {

@@ -93,6 +93,22 @@ hipError_t launch_prolong(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc,
                           hipStream_t s);
 template <typename T>
 hipError_t launch_coarse_solve(int D, const LV<T> &L0, const double *M, const double *S, int nrhs, hipStream_t s);
+// The bottom of a FAS V-cycle (levels 0..top, 3D) in one cooperative launch.
+constexpr int kMaxSmallLevels = 8;
+template <typename T>
+struct SmallLevels {
+    LV<T> L[kMaxSmallLevels];
+    int N[kMaxSmallLevels];
+    int n_down, n_up, nrhs, into_old;
+    const double *M, *S;
+};
+// P: device copy of the level table (read by the kernel while it runs);
+// top: highest level of the fused part (1 <= top < kMaxSmallLevels)
+template <typename T>
+hipError_t launch_small_vcycle(const SmallLevels<T> *P, int top, int grid, hipStream_t s);
+// co-resident workgroups of k_small_vcycle on the current device
+template <typename T>
+hipError_t small_vcycle_max_grid(int *grid);
 // max |r| over the leaf blocks of a level into out[rhs] (bit pattern of a
 // non-negative double, combined with atomicMax); phi_zero: residual of 0.
 template <typename T>

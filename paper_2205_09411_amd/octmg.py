@@ -68,6 +68,7 @@ _SIGS = {
     "octmg_state_create": (C.c_int, [_vp, C.c_int, C.c_int, C.POINTER(_vp)]),
     "octmg_state_destroy": (None, [_vp]),
     "octmg_state_set_smoothing": (C.c_int, [_vp, C.c_int, C.c_int]),
+    "octmg_state_set_fused_levels": (C.c_int, [_vp, C.c_int]),
     "octmg_set_boundary": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp]),
     "octmg_set_rhs": (C.c_int, [_vp, _vp, C.c_int, _vp]),
     "octmg_set_solution": (C.c_int, [_vp, _vp, C.c_int, _vp]),
@@ -241,6 +242,10 @@ class State:
 
     def set_smoothing(self, n_down: int, n_up: int):
         _check(lib().octmg_state_set_smoothing(self._h, n_down, n_up))
+
+    def set_fused_levels(self, max_blocks: int):
+        """Run levels with <= max_blocks blocks in one fused launch (0: off)."""
+        _check(lib().octmg_state_set_fused_levels(self._h, max_blocks))
 
     def _arr(self, a, n):
         """(pointer, on_device, keepalive) for a numpy array or torch tensor."""

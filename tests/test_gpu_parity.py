@@ -214,3 +214,26 @@ def test_full_size_mms3d_256(orc):
         o.vcycle()
         assert rel(S.get_solution(), o.get_solution()) < 1e-10, k
     print("residual", S.residual_norm()[0], o.residual_max(), flush=True)
+
+
+@pytest.mark.parametrize("name", ["mms3d_b16_64", "spheres_amr16", "cylinder_64", "sphere_f1_3d"])
+def test_fused_bottom_equals_separate_launches(name):
+    """The bottom of the V-cycle run in one cooperative launch gives the same
+    iterates, bit for bit, as one launch per step."""
+    w = CONFIGS[name]()
+    G = octmg.Geometry(w.geom)
+    xyz, _ = G.leaf_coords()
+    states = []
+    for fused in (64, 0):
+        S = octmg.State(G)
+        S.set_fused_levels(fused)
+        S.set_boundary(w.iface_value(G.iface_points()) if G.n_iface else None, w.domain_value(G.domain_points()))
+        S.set_rhs(w.rhs(xyz))
+        states.append(S)
+    for k in range(3):
+        for S in states:
+            S.vcycle()
+        assert np.array_equal(states[0].get_solution(), states[1].get_solution()), k
+    for S in states:
+        S.fmg(have_guess=True)
+    assert np.array_equal(states[0].get_solution(), states[1].get_solution())
