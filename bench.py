@@ -141,6 +141,20 @@ def main():
     dt = t1 - t0
     phi = S.get_solution()
     err = float(np.abs(phi - exact).max())
+    cycles = reps[-1].cycles
+    # the same solves with the cycles replayed from captured HIP graphs
+    graph = {}
+    for mode in (1, 2):
+        mc = 40 if mode == 1 else cycles
+        S.solve(rtol=args.rtol, max_cycles=mc, zero_start=True, stream=stream, graph_mode=mode)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.steps):
+            r = S.solve(rtol=args.rtol, max_cycles=mc, zero_start=True, stream=stream, graph_mode=mode)
+            assert r.cycles == cycles
+        torch.cuda.synchronize()
+        graph[mode] = args.steps / (time.perf_counter() - tg)
+        assert np.array_equal(S.get_solution(), phi)
 
     ncell = top["nblocks"] * top["Nb"] ** 3
     # algorithmic bytes of one FP64 half sweep: read the other colour's phi,
@@ -173,6 +187,8 @@ def main():
                      "kernel": "k_gs_half<double,3,16> (finest level)",
                      "bytes_per_launch": bytes_per_launch, "mean_launch_ms": round(mean_ms, 5)},
         "solves_per_s": round(args.steps / dt, 3),
+        "solves_per_s_graph_cycle": round(graph[1], 3),
+        "solves_per_s_graph_solve": round(graph[2], 3),
         "cycles_per_solve": int(np.mean([r.cycles for r in reps])),
         "final_rel_residual": max(r.r_final / r.r0 for r in reps),
         "max_err_vs_exact": err,

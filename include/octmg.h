@@ -94,9 +94,16 @@ typedef struct octmg_state_s *octmg_state;
 /* Solve options (Sec. 2.2: V-cycle or FMG, N_down = N_up = 2). rtol is
  * relative to the max-norm residual of phi = 0 over the leaf cells.  The
  * solve stops with OCTMG_ERR_NOT_CONVERGED after max_cycles, or when the
- * residual ratio of successive cycles stays above 0.95 for 3 cycles. */
+ * residual ratio of successive cycles stays above 0.95 for 3 cycles.
+ * graph_mode: 0 launches every kernel; 1 captures one cycle (with its
+ * residual norm) in a HIP graph and replays it each cycle; 2 captures the
+ * whole solve (max_cycles cycles, convergence tested on the device, no stall
+ * test) and launches it once.  Results are identical in all modes.  Graph
+ * modes capture on `stream` (or an internal stream if NULL) and need the
+ * fused levels off; graphs are cached per state and rebuilt when the
+ * smoothing counts or fused levels change. */
 typedef struct octmg_solve_opts {
-    int cycle_kind, max_cycles, zero_start, reserved;
+    int cycle_kind, max_cycles, zero_start, graph_mode;
     double rtol;
 } octmg_solve_opts;
 

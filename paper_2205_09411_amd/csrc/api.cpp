@@ -145,6 +145,11 @@ struct octmg_state_s {
     int fused_grid64 = 0, fused_grid32 = 0;    // co-resident workgroups of the fused kernel
     SmallLevels<double> *d_small64 = nullptr;  // device copies of the fused level tables
     SmallLevels<float> *d_small32 = nullptr;
+    // captured solves: key -> executable graph (see solve_impl)
+    std::vector<std::pair<long long, hipGraphExec_t>> graphs;
+    hipStream_t own_stream = nullptr;          // capture stream when the caller passes NULL
+    double *d_thresh = nullptr;                // [nrhs] rtol * r0 for device-side convergence
+    double *d_hist = nullptr;                  // [64][nrhs] residual history of a graph solve
     DevPool pool;
 };
 
@@ -406,8 +411,15 @@ octmg_status mixed_correct(octmg_state s, int kind, hipStream_t st) {
     return OCTMG_OK;
 }
 
-// (re)build the device tables of the fused bottom of the V-cycle
+void drop_graphs(octmg_state s) {
+    for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    s->graphs.clear();
+}
+
+// (re)build the device tables of the fused bottom of the V-cycle; captured
+// graphs bake in the cycle structure and are dropped
 octmg_status setup_fused(octmg_state s) {
+    drop_graphs(s);
     s->fused_top = 0;
     if (s->fused_max_blocks <= 0 || s->geom->tree.D != 3) return OCTMG_OK;
     int ft = 0;
@@ -836,6 +848,8 @@ octmg_status octmg_state_create(octmg_geom g, int n_rhs, int precision, octmg_st
     HIPCK(hipMemcpy(s->d_active, s->active_host.data(), sizeof(int) * n_rhs, hipMemcpyHostToDevice));
     HIPCK(hipHostMalloc((void **)&s->h_norm, sizeof(unsigned long long) * n_rhs, hipHostMallocMapped));
     HIPCK(hipHostGetDevicePointer((void **)&s->h_norm_dev, s->h_norm, 0));
+    HIPCK(s->pool.alloc(&s->d_thresh, n_rhs));
+    HIPCK(s->pool.alloc(&s->d_hist, (size_t)64 * n_rhs));
     STCK(setup_fused(s.get()));
     HIPCK(hipDeviceSynchronize());
     g->refs++;
@@ -849,6 +863,8 @@ void octmg_state_destroy(octmg_state s) {
     (void)hipDeviceSynchronize();
     octmg_geom g = s->geom;
     if (s->h_norm) (void)hipHostFree(s->h_norm);
+    for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
     delete s->prof;
     delete s;
     release_geom(g);
@@ -1051,9 +1067,68 @@ static octmg_status set_active(octmg_state s, const std::vector<int> &act, hipSt
     return OCTMG_OK;
 }
 
+// One step of a solve after the convergence check: a cycle (or, in MIXED
+// precision, the FP32 correction and the next FP64 defect), then the
+// residual norms of the new iterate into d_norm and the mapped host buffer.
+static octmg_status cycle_and_norm(octmg_state s, int kind, int have_guess, hipStream_t st) {
+    if (s->precision == OCTMG_MIXED) {
+        STCK(mixed_correct(s, kind, st));
+        STCK(mixed_defect(s, st));
+    } else {
+        Engine<double> e{s, st};
+        STCK(e.cycle(kind, have_guess));
+        STCK(residual_norm_dev(s, 0, st));
+    }
+    HIPCK(launch_copy_u64(s->d_norm, s->h_norm_dev, s->nrhs, st));
+    return OCTMG_OK;
+}
+
+extern "C++" {
+// Capture `body` on stream st into an executable graph (cached under key).
+template <typename F>
+static octmg_status graph_for(octmg_state s, long long key, hipStream_t st, F &&body, hipGraphExec_t *out) {
+    for (auto &kv : s->graphs)
+        if (kv.first == key) {
+            *out = kv.second;
+            return OCTMG_OK;
+        }
+    // profiling events and counters cover eager launches only
+    const bool prof_on = s->prof && s->prof->on;
+    if (prof_on) s->prof->on = false;
+    HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const octmg_status r = body();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    if (prof_on) s->prof->on = true;
+    if (r != OCTMG_OK) {
+        if (e == hipSuccess && g) (void)hipGraphDestroy(g);
+        return r;
+    }
+    HIPCK(e);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCK(ei);
+    s->graphs.push_back({key, exec});
+    *out = exec;
+    return OCTMG_OK;
+}
+
+}  // extern "C++"
+
+static void read_mapped(octmg_state s, std::vector<double> &out) {
+    for (int r = 0; r < s->nrhs; r++) {
+        const unsigned long long v = ((volatile unsigned long long *)s->h_norm)[r];
+        std::memcpy(&out[r], &v, sizeof(double));
+    }
+}
+
 // Cycles until every right-hand side satisfies max|r| <= rtol * max|r(0)|.
 // A right-hand side that has converged is frozen (its kernels exit early),
 // so each one receives exactly the cycles a solve of it alone would.
+// graph_mode 0: eager launches; 1: each cycle replays one captured graph;
+// 2: the whole solve is one captured graph of max_cycles cycles, with the
+// convergence test on the device (no stall test in that mode).
 static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStream_t st, octmg_solve_report *rp) {
     const int R = s->nrhs;
     std::vector<double> r0(R), rk(R), cur(R, 0.0), prev(R, 0.0);
@@ -1069,18 +1144,81 @@ static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStre
     if (o->zero_start) STCK(octmg_zero_solution(s, st));
     std::memset(rp, 0, sizeof(*rp));
     for (double v : r0) rp->r0 = std::max(rp->r0, v);
+    // residual of the starting iterate
+    if (s->precision == OCTMG_MIXED) {
+        STCK(mixed_defect(s, st));
+        STCK(read_norms(s, rk.data(), st));
+    } else if (o->zero_start) {
+        rk = r0;  // the residual of phi = 0 is r0 itself
+    } else {
+        STCK(residual_norm_dev(s, 0, st));
+        STCK(read_norms(s, rk.data(), st));
+    }
+    if (o->graph_mode == 2) {
+        // everything after the first check runs inside one graph
+        bool all_done = true;
+        std::vector<double> th(R);
+        for (int r = 0; r < R; r++) {
+            cur[r] = rk[r];
+            th[r] = o->rtol * r0[r];
+            if (!(rk[r] <= th[r])) all_done = false;
+            act[r] = rk[r] <= th[r] ? 0 : 1;
+            rp->r_final = std::max(rp->r_final, rk[r]);
+        }
+        if (all_done) {
+            rp->status = OCTMG_OK;
+            return OCTMG_OK;
+        }
+        STCK(set_active(s, act, st));
+        HIPCK(hipMemcpyAsync(s->d_thresh, th.data(), sizeof(double) * R, hipMemcpyHostToDevice, st));
+        const long long key = 2000000LL + 1000LL * o->max_cycles + 10 * o->cycle_kind + (o->zero_start ? 1 : 0);
+        hipGraphExec_t exec = nullptr;
+        STCK(graph_for(s, key, st, [&]() -> octmg_status {
+            for (int c = 0; c < o->max_cycles; c++) {
+                STCK(cycle_and_norm(s, o->cycle_kind, (c > 0 || !o->zero_start) ? 1 : 0, st));
+                HIPCK(launch_converge(s->d_norm, s->d_thresh, s->d_active, s->d_hist, c, R, st));
+            }
+            return OCTMG_OK;
+        }, &exec));
+        HIPCK(hipGraphLaunch(exec, st));
+        std::vector<double> hist((size_t)o->max_cycles * R);
+        std::vector<int> act_after(R);
+        HIPCK(hipMemcpyAsync(hist.data(), s->d_hist, sizeof(double) * hist.size(), hipMemcpyDeviceToHost, st));
+        HIPCK(hipMemcpyAsync(act_after.data(), s->d_active, sizeof(int) * R, hipMemcpyDeviceToHost, st));
+        HIPCK(hipStreamSynchronize(st));
+        s->active_host = act_after;
+        int cycles = 0;
+        bool nonfinite = false;
+        for (int c = 0; c < o->max_cycles; c++) {
+            double rmax = 0.0;
+            bool any = false;
+            for (int r = 0; r < R; r++) {
+                if (!act[r]) continue;  // converged before this cycle
+                cur[r] = hist[(size_t)c * R + r];
+                if (!std::isfinite(cur[r])) nonfinite = true;
+                if (cur[r] <= th[r]) act[r] = 0;
+                any = true;
+            }
+            if (!any) break;
+            for (int r = 0; r < R; r++) rmax = std::max(rmax, cur[r]);
+            rp->history[c] = rmax;
+            cycles = c + 1;
+            rp->r_final = rmax;
+        }
+        rp->cycles = cycles;
+        bool done = true;
+        for (int r = 0; r < R; r++)
+            if (act[r]) done = false;
+        if (nonfinite) {
+            rp->status = OCTMG_ERR_NONFINITE;
+            return fail(OCTMG_ERR_NONFINITE, "residual became non-finite");
+        }
+        rp->status = done ? OCTMG_OK : OCTMG_ERR_NOT_CONVERGED;
+        return done ? OCTMG_OK : fail(OCTMG_ERR_NOT_CONVERGED, "rtol not reached");
+    }
     int stall = 0;
     bool have_guess = !o->zero_start;
     for (int k = 0; k <= o->max_cycles; k++) {
-        if (s->precision == OCTMG_MIXED) {
-            STCK(mixed_defect(s, st));
-            STCK(read_norms(s, rk.data(), st));
-        } else if (k == 0 && o->zero_start) {
-            rk = r0;  // the residual of phi = 0 is r0 itself
-        } else {
-            STCK(residual_norm_dev(s, 0, st));
-            STCK(read_norms(s, rk.data(), st));
-        }
         bool all_done = true, nonfinite = false, changed = false;
         double rmax = 0.0;
         for (int r = 0; r < R; r++) {
@@ -1114,12 +1252,16 @@ static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStre
         }
         prev = cur;
         if (changed) STCK(set_active(s, act, st));
-        if (s->precision == OCTMG_MIXED) {
-            STCK(mixed_correct(s, o->cycle_kind, st));
+        if (o->graph_mode == 1 && have_guess) {
+            const long long key = 1000000LL + 10 * o->cycle_kind;
+            hipGraphExec_t exec = nullptr;
+            STCK(graph_for(s, key, st, [&]() { return cycle_and_norm(s, o->cycle_kind, 1, st); }, &exec));
+            HIPCK(hipGraphLaunch(exec, st));
         } else {
-            Engine<double> e{s, st};
-            STCK(e.cycle(o->cycle_kind, have_guess ? 1 : 0));
+            STCK(cycle_and_norm(s, o->cycle_kind, have_guess ? 1 : 0, st));
         }
+        HIPCK(hipStreamSynchronize(st));
+        read_mapped(s, rk);
         have_guess = true;
     }
     rp->status = OCTMG_ERR_NOT_CONVERGED;
@@ -1130,8 +1272,16 @@ octmg_status octmg_solve(octmg_state s, const octmg_solve_opts *o, void *stream,
     if (!s || !o) return fail(OCTMG_ERR_INVALID, "null argument");
     if (!(o->rtol > 0.0) || o->max_cycles < 1 || o->max_cycles > 64) return fail(OCTMG_ERR_INVALID, "bad options");
     if (o->cycle_kind != OCTMG_CYCLE_V && o->cycle_kind != OCTMG_CYCLE_FMG) return fail(OCTMG_ERR_INVALID, "bad cycle kind");
+    if (o->graph_mode < 0 || o->graph_mode > 2) return fail(OCTMG_ERR_INVALID, "bad graph_mode");
     hipStream_t st = (hipStream_t)stream;
     HIPCK(hipSetDevice(s->geom->device));
+    if (o->graph_mode && s->fused_top >= 1) return fail(OCTMG_ERR_INVALID, "graph capture needs fused levels off");
+    if (o->graph_mode && !st) {
+        // the legacy default stream cannot be captured: use a blocking stream
+        // of the state, which orders itself with the default stream
+        if (!s->own_stream) HIPCK(hipStreamCreate(&s->own_stream));
+        st = s->own_stream;
+    }
     octmg_solve_report local{};
     octmg_status res = solve_impl(s, o, st, rep ? rep : &local);
     std::string msg = g_last_error;

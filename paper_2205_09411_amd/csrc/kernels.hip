@@ -692,6 +692,15 @@ __global__ void k_fill_u64(unsigned long long *p, long long n, unsigned long lon
 __global__ void k_copy_u64(const unsigned long long *s, unsigned long long *d, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
 }
+__global__ void k_converge(const unsigned long long *norm, const double *thresh, int *active, double *hist, int c,
+                           int nrhs) {
+    for (int r = threadIdx.x; r < nrhs; r += blockDim.x) {
+        if (!active[r]) continue;
+        const double v = __longlong_as_double((long long)norm[r]);
+        hist[(long long)c * nrhs + r] = v;
+        if (v <= thresh[r] || !(v == v)) active[r] = 0;
+    }
+}
 __global__ void k_copy_d2f(const double *s, float *d, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         d[i] = (float)s[i];
@@ -1651,6 +1660,11 @@ hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long lon
 }
 hipError_t launch_copy_u64(const unsigned long long *src, unsigned long long *dst, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(64), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+hipError_t launch_converge(const unsigned long long *norm, const double *thresh, int *active, double *hist, int c,
+                           int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_converge, dim3(1), dim3(256), 0, s, norm, thresh, active, hist, c, nrhs);
     return hipGetLastError();
 }
 hipError_t launch_copy_d2f(const double *src, float *dst, long long n, hipStream_t s) {

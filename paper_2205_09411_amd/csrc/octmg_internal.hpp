@@ -134,6 +134,10 @@ hipError_t launch_fill(double *p, long long n, double v, hipStream_t s);
 hipError_t launch_fillf(float *p, long long n, float v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long long v, hipStream_t s);
 hipError_t launch_copy_u64(const unsigned long long *src, unsigned long long *dst, int n, hipStream_t s);
+// device-side convergence test of cycle c: for every active rhs record its
+// norm in hist[c][rhs] and freeze it once the norm is <= thresh[rhs]
+hipError_t launch_converge(const unsigned long long *norm, const double *thresh, int *active, double *hist, int c,
+                           int nrhs, hipStream_t s);
 hipError_t launch_copy_d2f(const double *src, float *dst, long long n, hipStream_t s);
 hipError_t launch_check_finite(const double *p, long long n, int *flag, hipStream_t s);
 

@@ -41,7 +41,7 @@ class GeomDesc(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("cycle_kind", C.c_int), ("max_cycles", C.c_int), ("zero_start", C.c_int),
-                ("reserved", C.c_int), ("rtol", C.c_double)]
+                ("graph_mode", C.c_int), ("rtol", C.c_double)]
 
 
 class SolveReport(C.Structure):
@@ -304,9 +304,10 @@ class State:
         return out
 
     def solve(self, rtol: float = 1e-10, max_cycles: int = 40, kind: int = CYCLE_V, zero_start: bool = False,
-              stream=None, raise_on_fail: bool = True) -> SolveReport:
+              stream=None, raise_on_fail: bool = True, graph_mode: int = 0) -> SolveReport:
         o = SolveOpts()
         o.cycle_kind, o.max_cycles, o.zero_start, o.rtol = kind, max_cycles, int(zero_start), rtol
+        o.graph_mode = graph_mode
         rep = SolveReport()
         st = lib().octmg_solve(self._h, C.byref(o), _stream_ptr(stream), C.byref(rep))
         if raise_on_fail:
