@@ -66,6 +66,103 @@ def smoother_updates_per_vcycle(levels, n_smooth=4):
     return sum(l["nblocks"] * l["Nb"] ** 3 for l in levels[1:]) * n_smooth
 
 
+def timed_solves(S, n, stream, **kw):
+    import torch
+    S.solve(stream=stream, zero_start=True, **kw)  # warm (graphs captured here)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps = [S.solve(stream=stream, zero_start=True, **kw) for _ in range(n)]
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / n, reps[-1]
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def leg_mixed(G, w, phi64, t64, stream, steps, rtol):
+    """Same problem, FP32 inner cycles inside FP64 defect correction."""
+    from paper_2205_09411_amd import octmg
+    S = octmg.State(G, 1, octmg.MIXED)
+    S.set_boundary_fn(w.iface_value, w.domain_value)
+    xyz, _ = G.leaf_coords()
+    S.set_rhs(w.rhs(xyz))
+    dt, rep = timed_solves(S, steps, stream, rtol=rtol, max_cycles=40, graph_mode=1)
+    phi = S.get_solution()
+    return {"solves_per_s": round(1 / dt, 3), "ms_per_solve": round(dt * 1e3, 3), "speedup_vs_fp64": round(t64 / dt, 3),
+            "outer_iterations": rep.cycles, "final_rel_residual": rep.r_final / rep.r0,
+            "rel_diff_vs_fp64_solution": rel(phi, phi64), "max_err_vs_exact": float(np.abs(phi - w.exact(xyz)).max())}
+
+
+def leg_batched(stream, rtol, reps=3, n_single=4):
+    """Cylinder r=0.2, 128^3 in 16^3 blocks, 64 Gaussian-source rhs solved
+    together (FP32 inner / FP64 outer, captured cycle graph) against FP64
+    and one-rhs-at-a-time solves on the same GPU."""
+    from paper_2205_09411_amd import octmg
+    from paper_2205_09411_amd import workloads as W
+    w = W.cylinder(max_level=4, n_rhs=64)
+    G = octmg.Geometry(w.geom)
+    xyz, _ = G.leaf_coords()
+    g = np.stack([w.rhs(xyz, i) for i in range(64)])
+    out = {"workload": f"{w.geom.name}: 128^3 in 16^3 blocks ({G.n_blocks} blocks), 64 rhs, phi=0 on cylinder and cube",
+           "cells_all_levels_per_rhs": int(sum(G.level_info(i)["nblocks"] * G.level_info(i)["Nb"] ** 3
+                                              for i in range(G.n_levels)))}
+    sols = {}
+    for name, prec in (("mixed", octmg.MIXED), ("fp64", octmg.FP64)):
+        S = octmg.State(G, 64, prec)
+        S.set_boundary(None, np.zeros(G.n_domain))
+        S.set_rhs(g)
+        dt, rep = timed_solves(S, reps, stream, rtol=rtol, max_cycles=40, graph_mode=1)
+        sols[name] = S.get_solution()
+        out[name] = {"batch_ms": round(dt * 1e3, 3), "rhs_solves_per_s": round(64 / dt, 2), "cycles": rep.cycles,
+                     "final_rel_residual": rep.r_final / rep.r0}
+        del S
+    S1 = octmg.State(G, 1, octmg.FP64)
+    S1.set_boundary(None, np.zeros(G.n_domain))
+    t1 = 0.0
+    d1 = 0.0
+    for i in range(n_single):
+        S1.set_rhs(g[i])
+        dt, _ = timed_solves(S1, 1, stream, rtol=rtol, max_cycles=40, graph_mode=1)
+        t1 += dt
+        d1 = max(d1, rel(sols["fp64"][i], S1.get_solution()))
+    out["single_rhs_fp64"] = {"ms_per_rhs": round(t1 / n_single * 1e3, 3), "rhs_solves_per_s": round(n_single / t1, 2),
+                              "sample": f"first {n_single} rhs, one at a time"}
+    out["batched_fp64_vs_single_max_rel_diff"] = d1
+    out["mixed_vs_fp64_max_rel_diff"] = rel(sols["mixed"], sols["fp64"])
+    out["speedup_mixed_batch_vs_single_fp64"] = round(out["mixed"]["rhs_solves_per_s"] /
+                                                      out["single_rhs_fp64"]["rhs_solves_per_s"], 2)
+    return out
+
+
+def leg_adaptive(stream, rtol, reps=3):
+    """20 seeded spheres, adaptive 16^3-block octree to level 6 (dx = 1/512),
+    phi=1 on the spheres, 0 on the cube, g ~ N(0,1): FP64 against mixed."""
+    from paper_2205_09411_amd import octmg
+    from paper_2205_09411_amd import workloads as W
+    w = W.spheres()
+    t = time.perf_counter()
+    G = octmg.Geometry(w.geom)
+    setup = time.perf_counter() - t
+    xyz, _ = G.leaf_coords()
+    g = w.rhs(xyz)
+    out = {"workload": f"{w.geom.name}: adaptive octree, {G.n_levels} levels, {G.n_blocks} blocks",
+           "leaf_cells": int(G.n_leaf), "interface_records": int(G.n_records), "setup_s": round(setup, 3)}
+    sols = {}
+    for name, prec in (("fp64", octmg.FP64), ("mixed", octmg.MIXED)):
+        S = octmg.State(G, 1, prec)
+        S.set_boundary_fn(w.iface_value, w.domain_value)
+        S.set_rhs(g)
+        dt, rep = timed_solves(S, reps, stream, rtol=rtol, max_cycles=40, graph_mode=1)
+        sols[name] = S.get_solution()
+        out[name] = {"ms_per_solve": round(dt * 1e3, 3), "solves_per_s": round(1 / dt, 3), "cycles": rep.cycles,
+                     "final_rel_residual": rep.r_final / rep.r0,
+                     "leaf_cell_solves_per_s_G": round(G.n_leaf / dt / 1e9, 3)}
+        del S
+    out["mixed_vs_fp64_max_rel_diff"] = rel(sols["mixed"], sols["fp64"])
+    return out
+
+
 def cpu_baseline(w, n_cycles):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -91,6 +188,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--cpu-cycles", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="mixed,batched,adaptive",
+                    help="extra measurements after the headline: mixed,batched,adaptive or none")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -195,6 +294,25 @@ def main():
         "sweep_kernel_mcups": round(ncell / 2 / (mean_ms * 1e-3) / 1e6, 1),
         "setup_s": round(setup_s, 3),
     }
+    legs = {}
+    for leg in [x for x in args.legs.split(",") if x and x != "none"]:
+        t = time.perf_counter()
+        try:
+            if leg == "mixed":
+                legs[leg] = leg_mixed(G, w, phi, dt / args.steps, stream, args.steps, args.rtol)
+            elif leg == "batched":
+                legs[leg] = leg_batched(stream, args.rtol)
+            elif leg == "adaptive":
+                legs[leg] = leg_adaptive(stream, args.rtol)
+            else:
+                raise ValueError(f"unknown leg {leg}")
+        except Exception as e:  # a failed leg is reported, the headline stands
+            legs[leg] = {"error": f"{type(e).__name__}: {e}"}
+        legs[leg]["leg_wall_s"] = round(time.perf_counter() - t, 1)
+        print(f"leg {leg} done in {legs[leg]['leg_wall_s']} s", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    if legs:
+        out["legs"] = legs
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_cycles)
     print(json.dumps(out))
