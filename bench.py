@@ -163,6 +163,125 @@ def leg_adaptive(stream, rtol, reps=3):
     return out
 
 
+def leg_serving(stream, n_requests=1000, pool=4, rtol=1e-8, budget_gb=64, max_lanes=16):
+    """Poisson arrivals over 4 sphere-union geometries x {64^3, 128^3, 256^3}
+    (16^3 blocks), Gaussian-source rhs resident in HBM, rtol 1e-8: the
+    batching server (mixed precision) against a plain FP64 one-at-a-time
+    loop on the same GPU, at 0.8x the plain loop's throughput and above."""
+    import torch
+    from paper_2205_09411_amd import octmg
+    from paper_2205_09411_amd import workloads as W
+    params = W.serving_geometries()
+    pairs = {}
+    t = time.perf_counter()
+    for lv in (3, 4, 5):
+        for gid, p in enumerate(params):
+            geom = W.Geometry(dim=3, block_n=16, max_level=lv, lsf_kind=W.LSF_SPHERES, lsf_params=p,
+                              w_min=8e-3, name=f"serve_g{gid}_{16 << (lv - 1)}")
+            G = octmg.Geometry(geom)
+            xyz, _ = G.leaf_coords()
+            x = torch.tensor(xyz, device="cuda")
+            rhs = []
+            for j in range(pool):
+                amp, wid, cen = W.gaussian_params(10000 + j)
+                g = torch.zeros(G.n_leaf, dtype=torch.float64, device="cuda")
+                for a, w_, c in zip(amp, wid, cen):
+                    d2 = ((x - torch.tensor(c, device="cuda")) ** 2).sum(dim=1)
+                    g += a * torch.exp(-d2 / (2.0 * w_ * w_))
+                rhs.append(g)
+            pairs[(lv, gid)] = {"G": G, "rhs": rhs, "iface": np.ones(G.n_iface),
+                                "dom": np.zeros(G.n_domain), "free": []}
+            del x
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+
+    def out_buf(pr):
+        return pr["free"].pop() if pr["free"] else torch.empty(pr["G"].n_leaf, dtype=torch.float64, device="cuda")
+
+    # plain loop: one FP64 state per pair, one request at a time
+    plain = {}
+    for key, pr in pairs.items():
+        S = octmg.State(pr["G"], 1, octmg.FP64)
+        S.set_boundary(pr["iface"], pr["dom"])
+        pr["plain"] = S
+        S.set_rhs(pr["rhs"][0], stream=stream)
+        S.solve(rtol=rtol, zero_start=True, stream=stream)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for j in range(2):
+            S.solve(rtol=rtol, zero_start=True, stream=stream)
+        torch.cuda.synchronize()
+        plain[key] = (time.perf_counter() - t) / 2
+    mu_plain = 1.0 / float(np.mean(list(plain.values())))
+
+    def run_plain(reqs):
+        lat = []
+        t0 = time.perf_counter()
+        for (ta, lv, gid, seed) in reqs:
+            now = time.perf_counter() - t0
+            if now < ta:
+                time.sleep(ta - now)
+            pr = pairs[(lv, gid)]
+            S = pr["plain"]
+            S.set_rhs(pr["rhs"][seed % pool], stream=stream)
+            S.solve(rtol=rtol, zero_start=True, stream=stream)
+            lat.append(time.perf_counter() - t0 - ta)
+        return np.array(lat), time.perf_counter() - t0
+
+    def run_server(reqs):
+        srv = octmg.Server(hbm_budget_bytes=budget_gb << 30, max_lanes=max_lanes, precision=octmg.MIXED)
+        slot = {key: srv.add_geometry(pr["G"], pr["iface"], pr["dom"]) for key, pr in pairs.items()}
+        meta = {}
+        done = {}
+        t0 = time.perf_counter()
+        i = 0
+        while len(done) < len(reqs):
+            now = time.perf_counter() - t0
+            while i < len(reqs) and reqs[i][0] <= now:
+                ta, lv, gid, seed = reqs[i]
+                pr = pairs[(lv, gid)]
+                o = out_buf(pr)
+                rid = srv.submit(slot[(lv, gid)], pr["rhs"][seed % pool], o, rtol)
+                meta[rid] = (ta, pr, o)
+                i += 1
+            for r in srv.poll():
+                ta, pr, o = meta.pop(r["id"])
+                pr["free"].append(o)
+                done[r["id"]] = r
+            time.sleep(0.0002)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        bad = sum(1 for r in done.values() if r["status"] != 0)
+        lat = np.array([r["t_done"] - r["t_submit"] for r in done.values()])
+        return lat, wall, st, bad
+
+    def summary(lat, wall, n):
+        return {"solves_per_s": round(n / wall, 1), "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3), "wall_s": round(wall, 2)}
+
+    out = {"workload": "4 geometries (unions of 1/5/10/20 spheres, phi=1 on spheres, 0 on cube) x {64^3,128^3,256^3} "
+                       "in 16^3 blocks, Gaussian-source rhs resident in HBM, Poisson arrivals, rtol 1e-8",
+           "requests": n_requests, "setup_s": round(setup_s, 2),
+           "plain_fp64_service_ms": {f"{16 << (k[0] - 1)}^3/g{k[1]}": round(v * 1e3, 3) for k, v in plain.items()},
+           "plain_fp64_capacity_solves_per_s": round(mu_plain, 1)}
+    lam = 0.8 * mu_plain
+    reqs = W.serving_stream(n_requests, lam)
+    lat, wall = run_plain(reqs)
+    out["plain_fp64_at_0.8x"] = dict(summary(lat, wall, n_requests), rate_hz=round(lam, 1))
+    for f in (0.8, 2.0, 4.0):
+        reqs = W.serving_stream(n_requests, f * mu_plain)
+        lat, wall, st, bad = run_server(reqs)
+        out[f"server_mixed_at_{f}x"] = dict(summary(lat, wall, n_requests), rate_hz=round(f * mu_plain, 1),
+                                            failed=bad, states_created=st["states_created"],
+                                            lanes_per_cycle=round(st["lane_cycles"] / max(1, st["cycles_launched"]), 2),
+                                            peak_gb=round(st["peak_bytes"] / 2 ** 30, 2))
+        print(f"serving at {f}x done", file=sys.stderr, flush=True)
+    for pr in pairs.values():
+        del pr["plain"]
+    return out
+
+
 def cpu_baseline(w, n_cycles):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -188,8 +307,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--cpu-cycles", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="mixed,batched,adaptive",
-                    help="extra measurements after the headline: mixed,batched,adaptive or none")
+    ap.add_argument("--legs", default="mixed,batched,adaptive,serving",
+                    help="extra measurements after the headline: mixed,batched,adaptive,serving or none")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -304,6 +423,8 @@ def main():
                 legs[leg] = leg_batched(stream, args.rtol)
             elif leg == "adaptive":
                 legs[leg] = leg_adaptive(stream, args.rtol)
+            elif leg == "serving":
+                legs[leg] = leg_serving(stream)
             else:
                 raise ValueError(f"unknown leg {leg}")
         except Exception as e:  # a failed leg is reported, the headline stands

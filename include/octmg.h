@@ -210,6 +210,67 @@ octmg_status octmg_debug_get_field(octmg_state s, int level, int field, int rhs,
 octmg_status octmg_debug_set_field(octmg_state s, int level, int field, int rhs, const double *in);
 octmg_status octmg_debug_step(octmg_state s, int step, int level, int arg, void *stream);
 
+/* ------------------------------------------------------------ serving
+ * Independent solve requests, one right-hand side each, on geometries added
+ * to the server (the method is built for solving many right-hand sides on
+ * one set of boundaries, Sec. 1).  A worker thread batches the requests of
+ * one geometry into the lanes of one multi-rhs state and admits waiting
+ * requests between two V-cycles of the running ones (continuous batching);
+ * each geometry's batch runs on its own stream, so batches of different
+ * geometries overlap.  Every request is solved from phi = 0 with FAS
+ * V(2,2) cycles and the tests of octmg_solve (rtol relative to the residual
+ * of phi = 0, max_cycles, stall), and its result is identical to that of a
+ * one-rhs octmg_solve of the same problem in the same precision.
+ *
+ * Device memory: lane fields (3 FP64 fields, plus 3 FP32 fields in MIXED
+ * precision, per cell of every level) are held within hbm_budget_bytes; a
+ * geometry's state gets as many lanes as the budget, its waiting demand
+ * (at least 4) and max_lanes allow; idle states of other geometries are
+ * released when a waiting geometry needs room.  A request whose single lane
+ * exceeds the budget completes with OCTMG_ERR_BUDGET.  Geometries are owned
+ * by the caller and must outlive the server.
+ *
+ * Buffers are borrowed: rhs (n_leaf values in canonical leaf order) and
+ * solution (n_leaf values) must stay valid until the request's result has
+ * been polled; on_device selects device or host memory.  The solution is
+ * written before the result is published (also for NOT_CONVERGED; not for
+ * NONFINITE or BUDGET).  Submit and poll are thread-safe and never block on
+ * the GPU. */
+typedef struct octmg_server_s *octmg_server;
+typedef struct octmg_server_opts {
+    size_t hbm_budget_bytes;
+    int max_lanes;  /* right-hand sides per batch, 1..4096 */
+    int precision;  /* OCTMG_FP64 or OCTMG_MIXED */
+    int max_cycles; /* per request, 1..64 */
+    int reserved;
+} octmg_server_opts;
+typedef struct octmg_result {
+    uint64_t id;
+    int status; /* OCTMG_OK, OCTMG_ERR_NOT_CONVERGED, _NONFINITE, _BUDGET, _HIP */
+    int cycles;
+    double r0, r_final;             /* max-norm residuals of phi = 0 and of the result */
+    double t_submit, t_admit, t_done; /* seconds on the server's monotonic clock */
+} octmg_result;
+typedef struct octmg_server_stats {
+    uint64_t submitted, admitted, completed, failed;
+    uint64_t states_created, states_released, cycles_launched, lane_cycles;
+    uint64_t peak_bytes, bytes_in_use;
+    double now; /* the server clock */
+} octmg_server_stats;
+
+octmg_status octmg_server_create(int device, const octmg_server_opts *opts, octmg_server *out);
+/* Register a geometry with its Dirichlet data (host arrays as for
+ * octmg_set_boundary; copied).  *slot names it in submissions. */
+octmg_status octmg_server_add_geometry(octmg_server s, octmg_geom g, const double *iface_vals,
+                                       const double *domain_vals, int *slot);
+octmg_status octmg_server_submit(octmg_server s, int slot, const double *rhs, int rhs_on_device, double *solution,
+                                 int solution_on_device, double rtol, uint64_t *id);
+/* Up to cap finished results, in completion order (non-blocking). */
+octmg_status octmg_server_poll(octmg_server s, octmg_result *done, int cap, int *n_done);
+octmg_status octmg_server_get_stats(octmg_server s, octmg_server_stats *out);
+/* Waits for queued and running requests to finish, then frees the server. */
+void octmg_server_destroy(octmg_server s);
+
 #ifdef __cplusplus
 }
 #endif

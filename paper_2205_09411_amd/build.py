@@ -26,6 +26,7 @@ PER_FILE = {
     "tree.cpp": ["-ffp-contract=off", "-x", "hip"],
     "api.cpp": ["-ffp-contract=off", "-x", "hip"],
     "kernels.hip": [],
+    "server.cpp": ["-x", "hip", "-pthread"],
 }
 
 
@@ -40,11 +41,11 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [os.path.join(CSRC, f) for f in ("kernels.hip", "setup.hip", "tree.cpp", "api.cpp")]
+    srcs = [os.path.join(CSRC, f) for f in ("kernels.hip", "setup.hip", "tree.cpp", "api.cpp", "server.cpp")]
     with ThreadPoolExecutor(max_workers=4) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = ["hipcc", "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

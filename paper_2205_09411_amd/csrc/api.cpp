@@ -1363,3 +1363,103 @@ octmg_status octmg_debug_step(octmg_state s, int step, int level, int arg, void 
 }
 
 }  // extern "C"
+
+// ------------------------------------------------- lanes (serving engine)
+// A lane is one right-hand side of a multi-rhs state.  These calls touch only
+// the lanes they are given; the serving engine batches independent requests
+// on one geometry by giving each its own lane.
+namespace octmg {
+
+octmg_status api_fail(octmg_status st, const std::string &msg) { return fail(st, msg); }
+
+int geom_device(octmg_geom g) { return g->device; }
+
+size_t lane_bytes(octmg_geom g, int precision) {
+    size_t cells = 0;
+    for (const GeomLevel &L : g->L) cells += (size_t)L.nblocks * L.cpb;
+    return cells * (3 * sizeof(double) + (precision == OCTMG_MIXED ? 3 * sizeof(float) : 0));
+}
+
+static LV<double> lv64_lane(const octmg_state_s *s, int il, int lane) {
+    LV<double> v = lv64(s, il);
+    const long long o = (long long)lane * s->stride[il];
+    v.phi += o;
+    v.g += o;
+    v.old += o;
+    v.active += lane;
+    return v;
+}
+
+octmg_status lane_load(octmg_state s, int lane, const double *src, int on_device, hipStream_t st) {
+    if (lane < 0 || lane >= s->nrhs) return fail(OCTMG_ERR_INVALID, "lane out of range");
+    octmg_geom g = s->geom;
+    DevPool tmp;
+    double *dv = nullptr;
+    STCK(stage_in(src, (size_t)g->n_leaf, on_device, st, &dv, &tmp));
+    STCK(check_finite(s, dv, g->n_leaf, st));
+    for (size_t il = 0; il < g->L.size(); il++) {
+        const GeomLevel &L = g->L[il];
+        const long long o = (long long)lane * s->stride[il];
+        HIPCK(launch_fill(s->f64[il].phi + o, s->stride[il], 0.0, st));
+        HIPCK(launch_fill(s->f64[il].old + o, s->stride[il], 0.0, st));
+        LV<double> v = lv64_lane(s, (int)il, lane);
+        v.active = nullptr;
+        HIPCK(launch_scatter_leaf(g->tree.D, L.Nb, v, L.d_leaf_blocks, L.nleaf, dv, g->n_leaf, L.leaf_base, 1, 1,
+                                  st));
+    }
+    HIPCK(hipStreamSynchronize(st));  // the staging buffer dies here
+    return OCTMG_OK;
+}
+
+octmg_status lane_store(octmg_state s, int lane, double *dst, int on_device, hipStream_t st) {
+    if (lane < 0 || lane >= s->nrhs) return fail(OCTMG_ERR_INVALID, "lane out of range");
+    octmg_geom g = s->geom;
+    DevPool tmp;
+    double *dv = dst;
+    if (!on_device) HIPCK(tmp.alloc(&dv, (size_t)g->n_leaf));
+    for (size_t il = 0; il < g->L.size(); il++) {
+        const GeomLevel &L = g->L[il];
+        LV<double> v = lv64_lane(s, (int)il, lane);
+        v.active = nullptr;
+        HIPCK(launch_gather_leaf(g->tree.D, L.Nb, v, L.d_leaf_blocks, L.nleaf, dv, g->n_leaf, L.leaf_base, 1, st));
+    }
+    if (!on_device) HIPCK(hipMemcpyAsync(dst, dv, sizeof(double) * g->n_leaf, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    return OCTMG_OK;
+}
+
+// r0 (residual of phi = 0) and the first convergence norm of the lanes set
+// in `fresh`; lanes not in `fresh` keep their fields.
+octmg_status lanes_begin(octmg_state s, const std::vector<int> &fresh, hipStream_t st, std::vector<double> &r0,
+                         std::vector<double> &rk) {
+    r0.assign(s->nrhs, 0.0);
+    STCK(set_active(s, fresh, st));
+    STCK(residual_norm_dev(s, 1, st));
+    STCK(read_norms(s, r0.data(), st));
+    if (s->precision == OCTMG_MIXED) {
+        STCK(mixed_defect(s, st));
+        rk.assign(s->nrhs, 0.0);
+        STCK(read_norms(s, rk.data(), st));
+    } else {
+        rk = r0;
+    }
+    return OCTMG_OK;
+}
+
+// Launch one cycle of the lanes set in `running` and the norms of the new
+// iterates into the host-mapped buffer; returns without waiting.
+octmg_status lanes_cycle(octmg_state s, const std::vector<int> &running, int kind, hipStream_t st) {
+    STCK(set_active(s, running, st));
+    const long long key = 1000000LL + 10 * kind;
+    hipGraphExec_t exec = nullptr;
+    STCK(graph_for(s, key, st, [&]() { return cycle_and_norm(s, kind, 1, st); }, &exec));
+    HIPCK(hipGraphLaunch(exec, st));
+    return OCTMG_OK;
+}
+
+void lanes_norms(octmg_state s, std::vector<double> &out) {
+    out.resize(s->nrhs);
+    read_mapped(s, out);
+}
+
+}  // namespace octmg

@@ -167,4 +167,20 @@ hipError_t launch_coarse_assemble(int D, int Nb, double dx, const int *map, cons
                                   hipStream_t s);
 hipError_t launch_gauss_jordan(int n, double *A, double *M, double *S, int *fail, hipStream_t s);
 
+// ---- lanes of a multi-rhs state (api.cpp), used by the serving engine
+octmg_status api_fail(octmg_status st, const std::string &msg);
+int geom_device(octmg_geom g);
+size_t lane_bytes(octmg_geom g, int precision);  // device bytes of one lane's fields
+// rhs of one lane from leaf-ordered values (host or device); zeroes its phi
+octmg_status lane_load(octmg_state s, int lane, const double *src, int on_device, hipStream_t st);
+// leaf-ordered phi of one lane into dst (host or device); waits for the copy
+octmg_status lane_store(octmg_state s, int lane, double *dst, int on_device, hipStream_t st);
+// r0 and first convergence norm of the lanes flagged in `fresh` (waits)
+octmg_status lanes_begin(octmg_state s, const std::vector<int> &fresh, hipStream_t st, std::vector<double> &r0,
+                         std::vector<double> &rk);
+// one V-cycle of the flagged lanes plus their norms, asynchronously
+octmg_status lanes_cycle(octmg_state s, const std::vector<int> &running, int kind, hipStream_t st);
+// norms written by the last lanes_cycle (after its stream has passed it)
+void lanes_norms(octmg_state s, std::vector<double> &out);
+
 }  // namespace octmg

@@ -49,6 +49,22 @@ class SolveReport(C.Structure):
                 ("history", C.c_double * 64)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_lanes", C.c_int), ("precision", C.c_int),
+                ("max_cycles", C.c_int), ("reserved", C.c_int)]
+
+
+class Result(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("status", C.c_int), ("cycles", C.c_int), ("r0", C.c_double),
+                ("r_final", C.c_double), ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(k, C.c_uint64) for k in ("submitted", "admitted", "completed", "failed", "states_created",
+                                          "states_released", "cycles_launched", "lane_cycles", "peak_bytes",
+                                          "bytes_in_use")] + [("now", C.c_double)]
+
+
 _lib = None
 _vp, _dp, _ip, _i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int64)
 _SIGS = {
@@ -82,6 +98,13 @@ _SIGS = {
     "octmg_debug_get_field": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _dp]),
     "octmg_debug_set_field": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _dp]),
     "octmg_debug_step": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _vp]),
+    "octmg_server_create": (C.c_int, [C.c_int, C.POINTER(ServerOpts), C.POINTER(_vp)]),
+    "octmg_server_add_geometry": (C.c_int, [_vp, _vp, _vp, _vp, _ip]),
+    "octmg_server_submit": (C.c_int, [_vp, C.c_int, _vp, C.c_int, _vp, C.c_int, C.c_double,
+                                      C.POINTER(C.c_uint64)]),
+    "octmg_server_poll": (C.c_int, [_vp, C.POINTER(Result), C.c_int, _ip]),
+    "octmg_server_get_stats": (C.c_int, [_vp, C.POINTER(ServerStats)]),
+    "octmg_server_destroy": (None, [_vp]),
 }
 
 
@@ -336,3 +359,78 @@ class State:
 
     def step(self, step: int, level: int, arg: int = 0, stream=None):
         _check(lib().octmg_debug_step(self._h, step, level, arg, _stream_ptr(stream)))
+
+
+def _buf(a):
+    """(pointer, on_device) of a float64 numpy array or device tensor."""
+    if isinstance(a, np.ndarray):
+        if a.dtype != np.float64 or not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("host buffers must be contiguous float64")
+        return a.ctypes.data, 0
+    if not a.is_contiguous() or str(a.dtype) != "torch.float64":
+        raise ValueError("tensors must be contiguous float64")
+    return a.data_ptr(), 1 if a.is_cuda else 0
+
+
+class Server:
+    """Serving engine (octmg_server_*): continuous batching of one-rhs
+    solve requests over resident geometries within a device-memory budget.
+
+    Buffers passed to submit() are kept referenced here until their result
+    has been polled."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 8 << 30, max_lanes: int = 16,
+                 precision: int = MIXED, max_cycles: int = 40):
+        o = ServerOpts()
+        o.hbm_budget_bytes, o.max_lanes, o.precision, o.max_cycles = hbm_budget_bytes, max_lanes, precision, max_cycles
+        h = C.c_void_p()
+        _check(lib().octmg_server_create(device, C.byref(o), C.byref(h)))
+        self._h = h
+        self._geoms = []
+        self._held = {}
+
+    def add_geometry(self, geometry: "Geometry", iface_vals=None, domain_vals=None) -> int:
+        iv = None if iface_vals is None else np.ascontiguousarray(iface_vals, dtype=np.float64)
+        dv = None if domain_vals is None else np.ascontiguousarray(domain_vals, dtype=np.float64)
+        slot = C.c_int()
+        _check(lib().octmg_server_add_geometry(self._h, geometry._h, None if iv is None else iv.ctypes.data,
+                                               None if dv is None else dv.ctypes.data, C.byref(slot)))
+        self._geoms.append(geometry)
+        return slot.value
+
+    def submit(self, slot: int, rhs, out, rtol: float = 1e-8) -> int:
+        rp, rd = _buf(rhs)
+        op, od = _buf(out)
+        rid = C.c_uint64()
+        _check(lib().octmg_server_submit(self._h, slot, rp, rd, op, od, rtol, C.byref(rid)))
+        self._held[rid.value] = (rhs, out)
+        return rid.value
+
+    def poll(self, cap: int = 256):
+        buf = (Result * cap)()
+        n = C.c_int()
+        _check(lib().octmg_server_poll(self._h, buf, cap, C.byref(n)))
+        out = []
+        for i in range(n.value):
+            r = buf[i]
+            self._held.pop(r.id, None)
+            out.append({"id": r.id, "status": r.status, "cycles": r.cycles, "r0": r.r0, "r_final": r.r_final,
+                        "t_submit": r.t_submit, "t_admit": r.t_admit, "t_done": r.t_done})
+        return out
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().octmg_server_get_stats(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().octmg_server_destroy(self._h)
+            self._h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

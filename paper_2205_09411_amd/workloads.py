@@ -136,13 +136,20 @@ def spheres(n_spheres: int = 20, max_level: int = 6, block_n: int = 16, seed: in
     return Workload(geom, rhs, lambda x: np.ones(x.shape[0]), lambda x: np.zeros(x.shape[0]))
 
 
-def gaussian_sources(x: np.ndarray, seed: int, n_src: int = 8) -> np.ndarray:
-    """Sum of n_src Gaussians: amplitude U[-1,1], width U[0.02,0.05],
-    centres U[0.1,0.9]^3, g = sum A exp(-|x-c|^2 / (2 w^2))."""
+def gaussian_params(seed: int, n_src: int = 8):
+    """Amplitudes U[-1,1], widths U[0.02,0.05] and centres U[0.1,0.9]^3 of
+    n_src Gaussian sources (seeded)."""
     rng = np.random.default_rng(seed)
     amp = rng.uniform(-1.0, 1.0, n_src)
     wid = rng.uniform(0.02, 0.05, n_src)
     cen = rng.uniform(0.1, 0.9, size=(n_src, 3))
+    return amp, wid, cen
+
+
+def gaussian_sources(x: np.ndarray, seed: int, n_src: int = 8) -> np.ndarray:
+    """Sum of n_src Gaussians: g = sum A exp(-|x-c|^2 / (2 w^2)) with the
+    parameters of gaussian_params(seed)."""
+    amp, wid, cen = gaussian_params(seed, n_src)
     out = np.zeros(x.shape[0])
     for a, w, c in zip(amp, wid, cen):
         d2 = ((x[:, :3] - c) ** 2).sum(axis=1)
