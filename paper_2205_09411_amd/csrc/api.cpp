@@ -68,7 +68,7 @@ struct GeomLevel {
     long long leaf_base = 0;   // canonical offset of the level's first leaf cell
     int nrec = 0, n_iface_blocks = 0;
     long long npts = 0, pt_base = 0;
-    int4 *d_pos = nullptr;
+    int4 *d_pos = nullptr, *d_nbr = nullptr;
     int *d_lut = nullptr, *d_leaf = nullptr, *d_map_off = nullptr, *d_map = nullptr;
     int *d_leaf_blocks = nullptr, *d_meta = nullptr;
     double *d_rec8 = nullptr, *d_d6 = nullptr, *d_cfull = nullptr, *d_pts = nullptr;
@@ -178,6 +178,7 @@ LV<double> lv64(const octmg_state_s *s, int il) {
     v.inv_dx2 = 1.0 / (G.dx * G.dx);
     v.lut = G.d_lut;
     v.pos = G.d_pos;
+    v.nbr = G.d_nbr;
     v.leaf = G.d_leaf;
     v.map_off = G.nrec ? G.d_map_off : nullptr;
     v.map = G.d_map;
@@ -204,6 +205,7 @@ LV<float> lv32(const octmg_state_s *s, int il) {
     v.inv_dx2 = (float)(1.0 / (G.dx * G.dx));
     v.lut = G.d_lut;
     v.pos = G.d_pos;
+    v.nbr = G.d_nbr;
     v.leaf = G.d_leaf;
     v.map_off = G.nrec ? G.d_map_off : nullptr;
     v.map = G.d_map;
@@ -574,6 +576,24 @@ octmg_status octmg_geom_create(const octmg_geom_desc *d, int hip_device, octmg_g
         HIPCK(G->pool.alloc(&L.d_map_off, L.nblocks));
         HIPCK(G->pool.alloc(&L.d_leaf_blocks, std::max(1, L.nleaf)));
         HIPCK(hipMemcpy(L.d_pos, pos4.data(), L.nblocks * sizeof(int4), hipMemcpyHostToDevice));
+        {
+            // face neighbour table: one lookup per block instead of a
+            // position load followed by six table lookups in every kernel
+            std::vector<int> nbr((size_t)8 * L.nblocks, -2);
+            for (int b = 0; b < L.nblocks; b++)
+                for (int f = 0; f < 2 * D; f++) {
+                    int q[3] = {pos4[b].x, pos4[b].y, pos4[b].z};
+                    q[f >> 1] += (f & 1) ? 1 : -1;
+                    bool in = true;
+                    for (int a = 0; a < D; a++) in = in && q[a] >= 0 && q[a] < L.nb;
+                    if (!in) continue;
+                    const long long li = D == 3 ? ((long long)q[2] * L.nb + q[1]) * L.nb + q[0]
+                                                : (long long)q[1] * L.nb + q[0];
+                    nbr[(size_t)8 * b + f] = T.lut[li];
+                }
+            HIPCK(G->pool.alloc(&L.d_nbr, (size_t)2 * L.nblocks));
+            HIPCK(hipMemcpy(L.d_nbr, nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice));
+        }
         HIPCK(hipMemcpy(L.d_lut, T.lut.data(), T.lut.size() * sizeof(int), hipMemcpyHostToDevice));
         HIPCK(hipMemcpy(L.d_leaf, leaf.data(), L.nblocks * sizeof(int), hipMemcpyHostToDevice));
         if (L.nleaf)

@@ -740,31 +740,36 @@ struct Per {
 };
 
 template <typename T, int N>
-__device__ __forceinline__ void face_ids(const LV<T> &L, int4 P, int nbk[6]) {
-#pragma unroll
-    for (int d = 0; d < 6; d++) {
-        int q[3] = {P.x, P.y, P.z};
-        q[d >> 1] += (d & 1) ? 1 : -1;
-        nbk[d] = block_at<T, 3>(L, q[0], q[1], q[2]);
-    }
+__device__ __forceinline__ void face_ids(const LV<T> &L, int blk, int nbk[6]) {
+    const int4 a = L.nbr[2 * blk], b = L.nbr[2 * blk + 1];
+    nbk[0] = a.x;
+    nbk[1] = a.y;
+    nbk[2] = a.z;
+    nbk[3] = a.w;
+    nbk[4] = b.x;
+    nbk[5] = b.y;
 }
 
-// Ghost values for the open faces of a block (no neighbour block: -2 domain
-// face, -1 coarser level).  Each cell of colour `col` on such a face reads
-// exactly one halo slot of the other-colour tile across that face; the slot
-// receives the ghost seen by that cell (Dirichlet 2 phi_b - own, or the
-// refinement-boundary interpolation).  Runs once per block after staging,
-// so the update loops read every neighbour from LDS without branches.
-template <typename T, int N, bool ZERO>
-__device__ void open_face_ghosts(T *tile, const LV<T> &L, const LV<T> &Lc, const T *__restrict__ own_col,
-                                 const T *phic, const int *nbk, int4 P, int col) {
+__device__ __forceinline__ bool any_coarser(const int *nbk) {
+    return nbk[0] == -1 || nbk[1] == -1 || nbk[2] == -1 || nbk[3] == -1 || nbk[4] == -1 || nbk[5] == -1;
+}
+
+// Ghost values at the faces of a block that border a coarser level (-1).
+// Each cell of colour `col` on such a face reads exactly one halo slot of
+// the other-colour tile across that face; the slot receives the refinement
+// boundary interpolation seen by that cell.  Runs after staging (it reads
+// the inward neighbour from the tile); domain faces are filled while
+// staging.
+template <typename T, int N>
+__device__ void coarser_face_ghosts(T *tile, const LV<T> &Lc, const T *__restrict__ own_col, const T *phic,
+                                    const int *nbk, int4 P, int col) {
     using CT = ColTile<N>;
     constexpr int NH = N / 2;
     const int t = threadIdx.x;
     if (t >= N * NH) return;
 #pragma unroll 1
     for (int d = 0; d < 6; d++) {
-        if (nbk[d] >= 0) continue;
+        if (nbk[d] != -1) continue;
         const int ax = d >> 1, s = (d & 1) ? 1 : -1;
         int i, j, k, slot;
         if (ax == 0) {
@@ -786,55 +791,89 @@ __device__ void open_face_ghosts(T *tile, const LV<T> &L, const LV<T> &Lc, const
             i = 2 * h + ((col + j + k) & 1);
             slot = CT::at(s < 0 ? -1 : N, j, h);
         }
-        const T own = ZERO ? T(0) : own_col[(k * N + j) * NH + (i >> 1)];
-        const int gi = P.x * N + i, gj = P.y * N + j, gk = P.z * N + k;
-        T ghost;
-        if (nbk[d] == -2) {
-            const T bv = L.bcv ? L.bcv[face_slot<3>(ax, s, gi, gj, gk, L.n, L.nface)] : T(0);
-            ghost = T(2) * bv - own;
-        } else if (ZERO || !phic) {
-            ghost = T(0);
-        } else {
+        T ghost = T(0);
+        if (phic) {
+            const T own = own_col[(k * N + j) * NH + (i >> 1)];
             int c[3] = {i, j, k};
             c[ax] -= s;  // inward neighbour, other colour, inside the block
             const T f2 = tile[CT::at(c[2], c[1], c[0] >> 1)];
-            ghost = cf_ghost<T, 3, N>(Lc, phic, gi, gj, gk, ax, s, own, f2);
+            ghost = cf_ghost<T, 3, N>(Lc, phic, P.x * N + i, P.y * N + j, P.z * N + k, ax, s, own, f2);
         }
         tile[slot] = ghost;
     }
 }
 
-// Stage colour `col` of block `blk` and its face halos into a ColTile.
-// All global loads of the thread are issued before the LDS writes.
+// Halo value across face d of the block for the reading cell (i, j, k) of
+// the other colour: the neighbour block's cell, or at a domain face the
+// Dirichlet ghost 2 phi_b - own (own: the reading cell's value; 0 for
+// ZERO); 0 at a coarser-level face (filled later by coarser_face_ghosts).
 template <typename T, int N, bool ZERO>
-__device__ __forceinline__ void stage_colour(T *tile, const T *__restrict__ phi, int blk, const int *nbk, int col,
-                                             const T *interior = nullptr) {
+__device__ __forceinline__ T halo_value(const LV<T> &L, const T *__restrict__ phi, const T *__restrict__ own_col,
+                                        int nb, long long nidx, int d, int4 P, int i, int j, int k, int oidx) {
+    if (nb >= 0) return ZERO ? T(0) : phi[(long long)nb * Blk<3, N>::CPB + nidx];
+    if (nb == -1) return T(0);
+    const T bv = L.bcv ? L.bcv[face_slot<3>(d >> 1, (d & 1) ? 1 : -1, P.x * N + i, P.y * N + j, P.z * N + k, L.n,
+                                            L.nface)]
+                       : T(0);
+    const T own = ZERO ? T(0) : own_col[oidx];
+    return T(2) * bv - own;
+}
+
+// Stage colour `col` of block `blk` and its face halos into a ColTile, the
+// halos at domain faces as the Dirichlet ghosts seen by the cells of the
+// other colour.  All global loads of the thread are issued before the LDS
+// writes.
+template <typename T, int N, bool ZERO>
+__device__ __forceinline__ void stage_colour(T *tile, const LV<T> &L, const T *__restrict__ phi, int blk,
+                                             const int *nbk, int4 P, int col, const T *interior = nullptr) {
     using B = Blk<3, N>;
     using CT = ColTile<N>;
     constexpr int NH = N / 2, PER = Per<N>::PER;
-    const int t = threadIdx.x, oc = col * B::HALF;
+    const int t = threadIdx.x, oc = col * B::HALF, uc = (1 - col) * B::HALF;
+    const T *__restrict__ own_col = phi + (long long)blk * B::CPB + uc;
+    T r[PER];
     if (ZERO) {
         for (int e = t; e < CT::SIZE; e += 256) tile[e] = T(0);
-        return;
-    }
-    const T *__restrict__ src = phi + (long long)blk * B::CPB + oc;
-    T r[PER];
+    } else {
 #pragma unroll
-    for (int m = 0; m < PER; m++) r[m] = interior ? interior[m] : src[t + 256 * m];
+        for (int m = 0; m < PER; m++) r[m] = interior ? interior[m] : phi[(long long)blk * B::CPB + oc + t + 256 * m];
+    }
+    const int ucol = 1 - col;
     const int fh = t % NH, fr = t / NH;  // y/z face entry (N*NH <= 256)
     const int xj = t % N, xk = t / N;    // x face entry (N*N <= 256)
     const bool fz = t < N * NH, fx = t < N * N;
     T y0 = T(0), y1 = T(0), z0 = T(0), z1 = T(0), x0 = T(0), x1 = T(0);
-    if (fz && nbk[2] >= 0) y0 = phi[(long long)nbk[2] * B::CPB + oc + (fr * N + N - 1) * NH + fh];
-    if (fz && nbk[3] >= 0) y1 = phi[(long long)nbk[3] * B::CPB + oc + (fr * N) * NH + fh];
-    if (fz && nbk[4] >= 0) z0 = phi[(long long)nbk[4] * B::CPB + oc + ((N - 1) * N + fr) * NH + fh];
-    if (fz && nbk[5] >= 0) z1 = phi[(long long)nbk[5] * B::CPB + oc + fr * NH + fh];
-    if (fx && nbk[0] >= 0) x0 = phi[(long long)nbk[0] * B::CPB + oc + (xk * N + xj) * NH + NH - 1];
-    if (fx && nbk[1] >= 0) x1 = phi[(long long)nbk[1] * B::CPB + oc + (xk * N + xj) * NH];
+    if (fz) {
+        // y faces: entry (k = fr, h = fh); z faces: entry (j = fr, h = fh)
+        const int ky = fr, jz = fr;
+        y0 = halo_value<T, N, ZERO>(L, phi, own_col, nbk[2], oc + (ky * N + N - 1) * NH + fh, 2, P,
+                                    2 * fh + ((ucol + ky) & 1), 0, ky, (ky * N) * NH + fh);
+        y1 = halo_value<T, N, ZERO>(L, phi, own_col, nbk[3], oc + (ky * N) * NH + fh, 3, P,
+                                    2 * fh + ((ucol + N - 1 + ky) & 1), N - 1, ky, (ky * N + N - 1) * NH + fh);
+        z0 = halo_value<T, N, ZERO>(L, phi, own_col, nbk[4], oc + ((N - 1) * N + jz) * NH + fh, 4, P,
+                                    2 * fh + ((ucol + jz) & 1), jz, 0, jz * NH + fh);
+        z1 = halo_value<T, N, ZERO>(L, phi, own_col, nbk[5], oc + jz * NH + fh, 5, P,
+                                    2 * fh + ((ucol + jz + N - 1) & 1), jz, N - 1, ((N - 1) * N + jz) * NH + fh);
+    }
+    if (fx) {
+        // x faces: entry (j = xj, k = xk); the halo slot is read only by rows
+        // whose reading cell sits on the face (i = 0, resp. i = N-1)
+        const int p = (ucol + xj + xk) & 1;
+        if (p == 0 || nbk[0] >= 0)
+            x0 = halo_value<T, N, ZERO>(L, phi, own_col, nbk[0], oc + (xk * N + xj) * NH + NH - 1, 0, P, 0, xj, xk,
+                                        (xk * N + xj) * NH);
+        if (p == 1 || nbk[1] >= 0)
+            x1 = halo_value<T, N, ZERO>(L, phi, own_col, nbk[1], oc + (xk * N + xj) * NH, 1, P, N - 1, xj, xk,
+                                        (xk * N + xj) * NH + NH - 1);
+    }
+    if (!ZERO) {
 #pragma unroll
-    for (int m = 0; m < PER; m++) {
-        const int q = t + 256 * m;
-        tile[CT::at(q / (NH * N), (q / NH) % N, q % NH)] = r[m];
+        for (int m = 0; m < PER; m++) {
+            const int q = t + 256 * m;
+            tile[CT::at(q / (NH * N), (q / NH) % N, q % NH)] = r[m];
+        }
+    } else {
+        __syncthreads();  // the zero fill before the halo writes
     }
     if (fz) {
         tile[CT::at(fr, -1, fh)] = y0;
@@ -871,11 +910,13 @@ template <typename T, int N>
 __device__ __forceinline__ void gs_half3_body(const LV<T> &L, const LV<T> &Lc, int color, int blk, int rhs, T *tile) {
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER;
-    if (L.active && !L.active[rhs]) return;
+    // the block's tables and the rhs flag are loaded together
+    const int act = L.active ? L.active[rhs] : 1;
     const int4 P = L.pos[blk];
     int nbk[6];
-    face_ids<T, N>(L, P, nbk);
+    face_ids<T, N>(L, blk, nbk);
     const int mo = L.map_off ? L.map_off[blk] : -1;
+    if (!act) return;
     T *__restrict__ phi = L.phi + (long long)rhs * L.fstride;
     const long long base = (long long)blk * B::CPB;
     const T *__restrict__ gm = L.g + (long long)rhs * L.fstride + base + color * B::HALF;
@@ -888,12 +929,12 @@ __device__ __forceinline__ void gs_half3_body(const LV<T> &L, const LV<T> &Lc, i
         gv[m] = __builtin_nontemporal_load(gm + threadIdx.x + 256 * m);
         ri[m] = mo >= 0 ? L.map[mo + color * B::HALF + threadIdx.x + 256 * m] : -1;
     }
-    stage_colour<T, N, false>(tile, phi, blk, nbk, 1 - color);
+    stage_colour<T, N, false>(tile, L, phi, blk, nbk, P, 1 - color);
     __syncthreads();
-    const T *phic = Lc.phi ? Lc.phi + (long long)rhs * Lc.fstride : nullptr;
     T *__restrict__ dst = phi + base + color * B::HALF;
-    if (nbk[0] < 0 || nbk[1] < 0 || nbk[2] < 0 || nbk[3] < 0 || nbk[4] < 0 || nbk[5] < 0) {
-        open_face_ghosts<T, N, false>(tile, L, Lc, dst, phic, nbk, P, color);
+    if (any_coarser(nbk)) {
+        const T *phic = Lc.phi ? Lc.phi + (long long)rhs * Lc.fstride : nullptr;
+        coarser_face_ghosts<T, N>(tile, Lc, dst, phic, nbk, P, color);
         __syncthreads();
     }
     const T inv6 = T(1) / T(6);
@@ -956,11 +997,11 @@ template <typename T, int N, bool ZERO>
 __device__ __forceinline__ void colour_pass(const LV<T> &L, const LV<T> &Lc, const T *phi, const T *phic, T *tile,
                                             int blk, const int *nbk, int4 P, const int *ri, int col, const T *own,
                                             const T *interior, T *out) {
-    stage_colour<T, N, ZERO>(tile, phi, blk, nbk, 1 - col, interior);
+    stage_colour<T, N, ZERO>(tile, L, phi, blk, nbk, P, 1 - col, interior);
     __syncthreads();
-    if (nbk[0] < 0 || nbk[1] < 0 || nbk[2] < 0 || nbk[3] < 0 || nbk[4] < 0 || nbk[5] < 0) {
-        open_face_ghosts<T, N, ZERO>(tile, L, Lc, phi + (long long)blk * Blk<3, N>::CPB + col * Blk<3, N>::HALF,
-                                     phic, nbk, P, col);
+    if (!ZERO && any_coarser(nbk)) {
+        coarser_face_ghosts<T, N>(tile, Lc, phi + (long long)blk * Blk<3, N>::CPB + col * Blk<3, N>::HALF, phic, nbk,
+                                  P, col);
         __syncthreads();
     }
     tile_op<T, N>(L, tile, ri, col, own, out);
@@ -998,11 +1039,12 @@ __device__ __forceinline__ void restrict_fas3_body(const LV<T> &L, const LV<T> &
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER, H = N / 2, NCELL = H * H * H, CPER = (NCELL + 255) / 256;
     constexpr int SM = ColTile<N>::SIZE > B::CPB ? ColTile<N>::SIZE : B::CPB;
-    if (L.active && !L.active[rhs]) return;
+    const int act = L.active ? L.active[rhs] : 1;
     const int4 P = L.pos[blk];
     int nbk[6];
-    face_ids<T, N>(L, P, nbk);
+    face_ids<T, N>(L, blk, nbk);
     const int mo = L.map_off ? L.map_off[blk] : -1;
+    if (!act) return;
     const T *__restrict__ phi = L.phi + (long long)rhs * L.fstride;
     const T *__restrict__ g = L.g + (long long)rhs * L.fstride;
     const T *phic = Lc.phi + (long long)rhs * Lc.fstride;
@@ -1093,19 +1135,21 @@ template <typename T, int N>
 __device__ __forceinline__ void fas_rhs3_body(const LV<T> &L, const LV<T> &Lc, int do_rhs, int blk, int rhs, T *tile) {
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER;
-    if (L.active && !L.active[rhs]) return;
+    const int act = L.active ? L.active[rhs] : 1;
+    const int leaf = L.leaf[blk];
+    const int4 P = L.pos[blk];
+    int nbk[6];
+    face_ids<T, N>(L, blk, nbk);
+    const int mo = L.map_off ? L.map_off[blk] : -1;
+    if (!act) return;
     T *phi = L.phi + (long long)rhs * L.fstride;
     T *g = L.g + (long long)rhs * L.fstride;
     T *old = L.old + (long long)rhs * L.fstride;
     const long long base = (long long)blk * B::CPB;
-    if (L.leaf[blk] || !do_rhs) {
+    if (leaf || !do_rhs) {
         for (int s = threadIdx.x; s < B::CPB; s += 256) old[base + s] = phi[base + s];
         return;
     }
-    const int4 P = L.pos[blk];
-    int nbk[6];
-    face_ids<T, N>(L, P, nbk);
-    const int mo = L.map_off ? L.map_off[blk] : -1;
     const T *phic = Lc.phi ? Lc.phi + (long long)rhs * Lc.fstride : nullptr;
     T own0[PER], own1[PER], lp[PER], gv[PER];
     int ri[PER];
@@ -1144,15 +1188,16 @@ template <typename T, int N, bool ZERO>
 __global__ __launch_bounds__(256) void k_residual_max3(LV<T> L, LV<T> Lc, unsigned long long *out) {
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER;
-    if (inactive(L)) return;
     const int blk = xcd_block();
-    if (!L.leaf[blk]) return;
-    __shared__ T tile[ColTile<N>::SIZE];
-    __shared__ double wmax[4];
+    const int act = L.active ? L.active[blockIdx.y] : 1;
+    const int leaf = L.leaf[blk];
     const int4 P = L.pos[blk];
     int nbk[6];
-    face_ids<T, N>(L, P, nbk);
+    face_ids<T, N>(L, blk, nbk);
     const int mo = L.map_off ? L.map_off[blk] : -1;
+    if (!act || !leaf) return;
+    __shared__ T tile[ColTile<N>::SIZE];
+    __shared__ double wmax[4];
     const T *__restrict__ phi = L.phi + (long long)blockIdx.y * L.fstride;
     const T *__restrict__ g = L.g + (long long)blockIdx.y * L.fstride;
     const T *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
@@ -1245,14 +1290,15 @@ __global__ __launch_bounds__(256) void k_defect3(LV<double> L, LV<double> Lc, LV
                                                   unsigned long long *out) {
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER;
-    if (inactive(L)) return;
     __shared__ double tile[ColTile<N>::SIZE];
     __shared__ double wmax[4];
+    const int act = L.active ? L.active[blockIdx.y] : 1;
     const int blk = lb[blockIdx.x];
     const int4 P = L.pos[blk];
     int nbk[6];
-    face_ids<double, N>(L, P, nbk);
+    face_ids<double, N>(L, blk, nbk);
     const int mo = L.map_off ? L.map_off[blk] : -1;
+    if (!act) return;
     const double *__restrict__ phi = L.phi + (long long)blockIdx.y * L.fstride;
     const double *__restrict__ g = L.g + (long long)blockIdx.y * L.fstride;
     const double *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;

@@ -57,6 +57,8 @@ struct LV {
     T dx2, inv_dx2;
     const int *lut;      // nb^D
     const int4 *pos;     // [nblocks] block coordinates
+    const int4 *nbr;     // [2 nblocks] face neighbours x-,x+,y-,y+,z-,z+,pad,pad: block,
+                         // -1 none on this level (coarser), -2 outside the domain
     const int *leaf;     // [nblocks]
     const int *map_off;  // [nblocks] offset of the block's record map, or -1
     const int *map;      // record index per cell (split order) or -1

@@ -237,3 +237,34 @@ def test_fused_bottom_equals_separate_launches(name):
     for S in states:
         S.fmg(have_guess=True)
     assert np.array_equal(states[0].get_solution(), states[1].get_solution())
+
+
+@pytest.mark.timeout(900)
+def test_full_size_adaptive_spheres(orc):
+    """The adaptive 20-sphere octree to level 6 (dx = 1/512, 71M leaf cells in
+    16^3 blocks, the size the adaptive benchmark leg runs): setup parity on
+    every level, then the first V-cycle against the checker (which needs
+    about a minute for setup and cycle on the host)."""
+    w = W.spheres()
+    print("full size adaptive spheres: checker setup", flush=True)
+    o = orc.setup_workload(w)
+    print("device setup", flush=True)
+    G = octmg.Geometry(w.geom)
+    assert G.n_leaf > 50_000_000
+    assert np.array_equal(G.iface_points(), o.iface_points())
+    assert np.array_equal(G.domain_points(), o.domain_points())
+    for il in range(o.n_levels):
+        ig, dg, cg = G.records(il)
+        io, do, co = o.records(il)
+        assert np.array_equal(ig, io) and np.array_equal(dg[:, :6], do[:, :6]), il
+    S = octmg.State(G)
+    S.set_boundary(w.iface_value(o.iface_points()), w.domain_value(o.domain_points()))
+    xyz, _ = o.leaf_coords()
+    S.set_rhs(w.rhs(xyz))
+    del xyz
+    print("one V-cycle each", flush=True)
+    S.vcycle()
+    o.vcycle()
+    d = rel(S.get_solution(), o.get_solution())
+    print("rel diff after one V-cycle", d, flush=True)
+    assert d < 1e-10
