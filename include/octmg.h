@@ -91,6 +91,22 @@ typedef struct octmg_geom_desc {
 typedef struct octmg_geom_s *octmg_geom;
 typedef struct octmg_state_s *octmg_state;
 
+/* Launch configuration of a state's cycles.  Every choice gives the same
+ * iterates, bit for bit; only the speed differs.
+ *   block_order: which workgroup handles which block in the 3D level
+ *     kernels -- 0: each of the 8 XCDs walks a contiguous Morton range of
+ *     the level (face halos stay in that XCD's L2); 1: hardware order.
+ *   bottom_kind: 0 one launch per step and level; 1 the levels with at most
+ *     bottom_max_blocks blocks run inside one cooperative launch (as
+ *     octmg_state_set_fused_levels).
+ *   graph_mode: the octmg_solve_opts.graph_mode recommended with it (a
+ *     cooperative bottom cannot be captured: graph_mode 0 with bottom_kind 1). */
+typedef struct octmg_launch_config {
+    int block_order, bottom_kind, bottom_max_blocks, graph_mode;
+} octmg_launch_config;
+octmg_status octmg_state_set_launch(octmg_state s, const octmg_launch_config *c);
+octmg_status octmg_state_get_launch(octmg_state s, octmg_launch_config *c);
+
 /* Solve options (Sec. 2.2: V-cycle or FMG, N_down = N_up = 2). rtol is
  * relative to the max-norm residual of phi = 0 over the leaf cells.  The
  * solve stops with OCTMG_ERR_NOT_CONVERGED after max_cycles, or when the
@@ -192,6 +208,17 @@ octmg_status octmg_residual_norm(octmg_state s, int phi_zero, double *out, void 
 /* Cycles until max|r| <= rtol * max|r(phi=0)| for every rhs. */
 octmg_status octmg_solve(octmg_state s, const octmg_solve_opts *opts, void *stream, octmg_solve_report *rep);
 
+/* Autotuner: solves the state's current problem from phi = 0 (opts, with
+ * zero_start and graph_mode taken from each candidate) once to warm up and
+ * `reps` times timed, under every candidate launch configuration (both block
+ * orders x {separate, separate in a per-cycle graph, cooperative bottom up
+ * to 8 and to 64 blocks (3D)}), then keeps the fastest in the state and
+ * returns it.  ms[i] (if not NULL, room for 8) receives the mean wall time
+ * per solve of candidate i, *n_candidates their number.  Afterwards phi
+ * holds the solution (the same under every candidate). */
+octmg_status octmg_autotune(octmg_state s, const octmg_solve_opts *opts, int reps, void *stream,
+                            octmg_launch_config *best, double *ms, int *n_candidates);
+
 /* Profiling.  When enabled, each group of back-to-back red-black half
  * sweeps of the finest level (one level visit) is bracketed by HIP events
  * recorded on the stream it runs on, and the
@@ -224,9 +251,9 @@ octmg_status octmg_debug_step(octmg_state s, int step, int level, int arg, void 
  *
  * Device memory: lane fields (3 FP64 fields, plus 3 FP32 fields in MIXED
  * precision, per cell of every level) are held within hbm_budget_bytes; a
- * geometry's state gets as many lanes as the budget, its waiting demand
- * (at least 4) and max_lanes allow; idle states of other geometries are
- * released when a waiting geometry needs room.  A request whose single lane
+ * geometry's state gets as many lanes as the budget and max_lanes allow;
+ * idle states of other geometries are released when a waiting geometry
+ * needs room, and while one waits the others admit no new requests.  A request whose single lane
  * exceeds the budget completes with OCTMG_ERR_BUDGET.  Geometries are owned
  * by the caller and must outlive the server.
  *

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -140,6 +141,8 @@ struct octmg_state_s {
     unsigned long long *h_norm_dev = nullptr;  // device view of h_norm
     std::vector<double> r0_cache;              // residual of phi = 0 (valid while !r0_dirty)
     bool r0_dirty = true;
+    int block_order = 0;                       // LV::order of every level
+    int tuned_graph = 0;                       // graph mode recommended by octmg_autotune
     int fused_max_blocks = 0;                  // levels with <= this many blocks run fused (0: off)
     int fused_top = 0;                         // highest fused level (0: none)
     int fused_grid64 = 0, fused_grid32 = 0;    // co-resident workgroups of the fused kernel
@@ -190,6 +193,7 @@ LV<double> lv64(const octmg_state_s *s, int il) {
     v.old = s->f64[il].old;
     v.fstride = s->stride[il];
     v.active = s->d_active;
+    v.order = s->block_order;
     return v;
 }
 
@@ -217,6 +221,7 @@ LV<float> lv32(const octmg_state_s *s, int il) {
     v.old = s->f32[il].old;
     v.fstride = s->stride[il];
     v.active = s->d_active;
+    v.order = s->block_order;
     return v;
 }
 
@@ -871,7 +876,9 @@ octmg_status octmg_state_create(octmg_geom g, int n_rhs, int precision, octmg_st
     HIPCK(s->pool.alloc(&s->d_thresh, n_rhs));
     HIPCK(s->pool.alloc(&s->d_hist, (size_t)64 * n_rhs));
     STCK(setup_fused(s.get()));
-    HIPCK(hipDeviceSynchronize());
+    // the fills ran on the legacy default stream; other streams' work (a
+    // server's running batches) need not be waited for
+    HIPCK(hipStreamSynchronize(nullptr));
     g->refs++;
     *out = s.release();
     return OCTMG_OK;
@@ -939,6 +946,29 @@ octmg_status octmg_state_set_fused_levels(octmg_state s, int max_blocks) {
     s->fused_max_blocks = max_blocks;
     HIPCK(hipSetDevice(s->geom->device));
     return setup_fused(s);
+}
+
+octmg_status octmg_state_set_launch(octmg_state s, const octmg_launch_config *c) {
+    if (!s || !c) return fail(OCTMG_ERR_INVALID, "null argument");
+    if ((c->block_order != 0 && c->block_order != 1) || c->bottom_max_blocks < 0 || c->graph_mode < 0 ||
+        c->graph_mode > 2 || (c->bottom_kind != 0 && c->bottom_kind != 1))
+        return fail(OCTMG_ERR_INVALID, "bad launch configuration");
+    if (c->bottom_kind == 1 && c->graph_mode != 0)
+        return fail(OCTMG_ERR_INVALID, "the cooperative bottom launch cannot be captured");
+    s->block_order = c->block_order;
+    s->tuned_graph = c->graph_mode;
+    s->fused_max_blocks = c->bottom_kind ? c->bottom_max_blocks : 0;
+    HIPCK(hipSetDevice(s->geom->device));
+    return setup_fused(s);  // rebuilds the level tables and drops captured graphs
+}
+
+octmg_status octmg_state_get_launch(octmg_state s, octmg_launch_config *c) {
+    if (!s || !c) return fail(OCTMG_ERR_INVALID, "null argument");
+    c->block_order = s->block_order;
+    c->bottom_kind = s->fused_max_blocks > 0 ? 1 : 0;
+    c->bottom_max_blocks = s->fused_max_blocks;
+    c->graph_mode = s->tuned_graph;
+    return OCTMG_OK;
 }
 
 static octmg_status stage_in(const double *src, size_t n, int on_device, hipStream_t st, double **dev,
@@ -1309,6 +1339,38 @@ octmg_status octmg_solve(octmg_state s, const octmg_solve_opts *o, void *stream,
     STCK(set_active(s, all, st));
     if (res != OCTMG_OK) return fail(res, msg);
     return OCTMG_OK;
+}
+
+octmg_status octmg_autotune(octmg_state s, const octmg_solve_opts *o, int reps, void *stream,
+                            octmg_launch_config *best, double *ms, int *n_candidates) {
+    if (!s || !o || !best || reps < 1) return fail(OCTMG_ERR_INVALID, "bad argument");
+    std::vector<octmg_launch_config> cand;
+    for (int order = 0; order < 2; order++) {
+        cand.push_back({order, 0, 0, 0});
+        cand.push_back({order, 0, 0, 1});
+        if (s->geom->tree.D == 3) {
+            cand.push_back({order, 1, 8, 0});
+            cand.push_back({order, 1, 64, 0});
+        }
+    }
+    if (n_candidates) *n_candidates = (int)cand.size();
+    double best_ms = 0.0;
+    int best_i = -1;
+    for (size_t i = 0; i < cand.size(); i++) {
+        STCK(octmg_state_set_launch(s, &cand[i]));
+        octmg_solve_opts so = *o;
+        so.zero_start = 1;
+        so.graph_mode = cand[i].graph_mode;
+        octmg_solve_report rep{};
+        STCK(octmg_solve(s, &so, stream, &rep));  // warm: captures graphs, fills caches
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int r = 0; r < reps; r++) STCK(octmg_solve(s, &so, stream, &rep));
+        const double t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / reps;
+        if (ms) ms[i] = t;
+        if (best_i < 0 || t < best_ms) best_ms = t, best_i = (int)i;
+    }
+    *best = cand[best_i];
+    return octmg_state_set_launch(s, best);
 }
 
 octmg_status octmg_debug_get_field(octmg_state s, int level, int field, int rhs, double *out) {

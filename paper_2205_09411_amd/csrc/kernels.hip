@@ -727,6 +727,11 @@ __device__ __forceinline__ int xcd_block() {
     return xcd * q + min(xcd, r) + slot;
 }
 
+// block of this workgroup: order 0 maps XCD-contiguous Morton ranges as
+// above, order 1 keeps the hardware order (consecutive blocks on
+// consecutive XCDs); the result of every block is the same either way
+__device__ __forceinline__ int block_of(int order) { return order ? (int)blockIdx.x : xcd_block(); }
+
 // one colour of a block with halo: (N+2) x (N+2) x (N/2+2), index (k, j, h)
 template <int N>
 struct ColTile {
@@ -964,7 +969,7 @@ __global__ __launch_bounds__(256) void k_gs_half3(LV<T> L, LV<T> Lc, int color) 
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER;
     __shared__ T tile[ColTile<N>::SIZE];
-    gs_half3_body<T, N>(L, Lc, color, xcd_block(), blockIdx.y, tile);
+    gs_half3_body<T, N>(L, Lc, color, block_of(L.order), blockIdx.y, tile);
 }
 
 // L phi at the PER cells of colour `col` owned by this thread, from the
@@ -1127,7 +1132,7 @@ __global__ __launch_bounds__(256) void k_restrict_fas3(LV<T> L, LV<T> Lc, int in
     constexpr int PER = Per<N>::PER, H = N / 2, NCELL = H * H * H, CPER = (NCELL + 255) / 256;
     constexpr int SM = ColTile<N>::SIZE > B::CPB ? ColTile<N>::SIZE : B::CPB;
     __shared__ T sm[SM];
-    restrict_fas3_body<T, N, NC>(L, Lc, into_old, xcd_block(), blockIdx.y, sm);
+    restrict_fas3_body<T, N, NC>(L, Lc, into_old, block_of(L.order), blockIdx.y, sm);
 }
 
 // FAS rhs on parent blocks (g = L phi + g) and old = phi, 3D
@@ -1180,7 +1185,7 @@ __global__ __launch_bounds__(256) void k_fas_rhs3(LV<T> L, LV<T> Lc, int do_rhs)
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER;
     __shared__ T tile[ColTile<N>::SIZE];
-    fas_rhs3_body<T, N>(L, Lc, do_rhs, xcd_block(), blockIdx.y, tile);
+    fas_rhs3_body<T, N>(L, Lc, do_rhs, block_of(L.order), blockIdx.y, tile);
 }
 
 // max |g - L phi| over a leaf block (3D); ZERO: residual of phi = 0
@@ -1188,7 +1193,7 @@ template <typename T, int N, bool ZERO>
 __global__ __launch_bounds__(256) void k_residual_max3(LV<T> L, LV<T> Lc, unsigned long long *out) {
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER;
-    const int blk = xcd_block();
+    const int blk = block_of(L.order);
     const int act = L.active ? L.active[blockIdx.y] : 1;
     const int leaf = L.leaf[blk];
     const int4 P = L.pos[blk];
@@ -1281,7 +1286,7 @@ __global__ __launch_bounds__(256) void k_prolong3(LV<T> L, LV<T> Lc, int solutio
     using B = Blk<3, N>;
     constexpr int H = N / 2, E = H + 2, ESZ = E * E * E, PER = B::CPB / 256;
     __shared__ T et[ESZ];
-    prolong3_body<T, N, NC>(L, Lc, solution, xcd_block(), blockIdx.y, et);
+    prolong3_body<T, N, NC>(L, Lc, solution, block_of(L.order), blockIdx.y, et);
 }
 
 // mixed precision defect (FP64): g32 = g - L phi on a leaf block, phi32 = 0

@@ -131,9 +131,9 @@ struct octmg_server_s {
         return OCTMG_OK;
     }
 
-    // A state for S with as many lanes as the budget allows (up to the
-    // waiting demand and max_lanes), releasing idle states of other
-    // geometries first if that is what it takes to fit one lane.
+    // A state for S with as many lanes as the budget allows (up to
+    // max_lanes), releasing idle states of other geometries first if that is
+    // what it takes to fit one lane.
     octmg_status acquire(Slot &S, int idx, bool *rejected) {
         *rejected = false;
         const size_t per = lane_bytes(S.geom, opts.precision);
@@ -164,8 +164,7 @@ struct octmg_server_s {
             }
         }
         const size_t fit = (opts.hbm_budget_bytes - used) / per;
-        const size_t want = std::max<size_t>(4, S.pending.size());
-        const int n = (int)std::min<size_t>({fit, want, (size_t)opts.max_lanes});
+        const int n = (int)std::min<size_t>(fit, (size_t)opts.max_lanes);
         octmg_state st = nullptr;
         SSTCK(octmg_state_create(S.geom, n, opts.precision, &st));
         octmg_status r = octmg_set_boundary(st, S.iface.empty() ? nullptr : S.iface.data(), S.dom.data(), 0,

@@ -44,6 +44,14 @@ class SolveOpts(C.Structure):
                 ("graph_mode", C.c_int), ("rtol", C.c_double)]
 
 
+class LaunchConfig(C.Structure):
+    _fields_ = [("block_order", C.c_int), ("bottom_kind", C.c_int), ("bottom_max_blocks", C.c_int),
+                ("graph_mode", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class SolveReport(C.Structure):
     _fields_ = [("cycles", C.c_int), ("status", C.c_int), ("r0", C.c_double), ("r_final", C.c_double),
                 ("history", C.c_double * 64)]
@@ -93,6 +101,9 @@ _SIGS = {
     "octmg_cycle": (C.c_int, [_vp, C.c_int, C.c_int, _vp]),
     "octmg_residual_norm": (C.c_int, [_vp, C.c_int, _dp, _vp]),
     "octmg_solve": (C.c_int, [_vp, C.POINTER(SolveOpts), _vp, C.POINTER(SolveReport)]),
+    "octmg_state_set_launch": (C.c_int, [_vp, C.POINTER(LaunchConfig)]),
+    "octmg_state_get_launch": (C.c_int, [_vp, C.POINTER(LaunchConfig)]),
+    "octmg_autotune": (C.c_int, [_vp, C.POINTER(SolveOpts), C.c_int, _vp, C.POINTER(LaunchConfig), _dp, _ip]),
     "octmg_profile_enable": (C.c_int, [_vp, C.c_int]),
     "octmg_profile_read": (C.c_int, [_vp, _dp]),
     "octmg_debug_get_field": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _dp]),
@@ -265,6 +276,27 @@ class State:
 
     def set_smoothing(self, n_down: int, n_up: int):
         _check(lib().octmg_state_set_smoothing(self._h, n_down, n_up))
+
+    def set_launch(self, block_order=0, bottom_kind=0, bottom_max_blocks=0, graph_mode=0):
+        c = LaunchConfig(block_order, bottom_kind, bottom_max_blocks, graph_mode)
+        _check(lib().octmg_state_set_launch(self._h, C.byref(c)))
+
+    def get_launch(self) -> dict:
+        c = LaunchConfig()
+        _check(lib().octmg_state_get_launch(self._h, C.byref(c)))
+        return c.as_dict()
+
+    def autotune(self, rtol: float = 1e-10, max_cycles: int = 40, kind: int = CYCLE_V, reps: int = 2, stream=None):
+        """Time every candidate launch configuration; keep and return the
+        fastest, with the per-candidate mean ms per solve."""
+        o = SolveOpts()
+        o.cycle_kind, o.max_cycles, o.zero_start, o.rtol = kind, max_cycles, 1, rtol
+        best = LaunchConfig()
+        ms = np.zeros(8)
+        n = C.c_int()
+        _check(lib().octmg_autotune(self._h, C.byref(o), reps, _stream_ptr(stream), C.byref(best),
+                                    _ptr(ms, C.c_double), C.byref(n)))
+        return best.as_dict(), ms[:n.value].tolist()
 
     def set_fused_levels(self, max_blocks: int):
         """Run levels with <= max_blocks blocks in one fused launch (0: off)."""

@@ -100,3 +100,32 @@ def test_graph_rejects_fused_levels():
         S.solve(rtol=1e-10, graph_mode=1)
     S.set_fused_levels(0)
     S.solve(rtol=1e-10, graph_mode=1, zero_start=True)
+
+
+def test_launch_configurations_and_autotune_identical():
+    """Every launch configuration the autotuner picks from gives the same
+    iterates bit for bit; the autotuner keeps one of them."""
+    print("launch configurations and autotune", flush=True)
+    w = W.cylinder(max_level=3)
+    G = octmg.Geometry(w.geom)
+    S = octmg.State(G, 3, octmg.MIXED)
+    S.set_boundary(None, np.zeros(G.n_domain))
+    xyz, _ = G.leaf_coords()
+    S.set_rhs(np.stack([w.rhs(xyz, i) for i in range(3)]))
+    ref_rep = S.solve(rtol=1e-10, zero_start=True)
+    ref = S.get_solution()
+    configs = [dict(block_order=o, bottom_kind=b, bottom_max_blocks=m, graph_mode=g)
+               for o in (0, 1) for (b, m, g) in ((0, 0, 0), (0, 0, 1), (0, 0, 2), (1, 8, 0), (1, 64, 0))]
+    for c in configs:
+        S.set_launch(**c)
+        assert S.get_launch() == c
+        r = S.solve(rtol=1e-10, zero_start=True, graph_mode=c["graph_mode"], max_cycles=ref_rep.cycles + 1)
+        assert r.cycles == ref_rep.cycles, c
+        assert np.array_equal(S.get_solution(), ref), c
+    best, ms = S.autotune(rtol=1e-10, reps=1)
+    print("autotune", best, ms, flush=True)
+    assert len(ms) == 8 and all(m > 0 for m in ms)
+    assert S.get_launch() == best
+    assert np.array_equal(S.get_solution(), ref)
+    with pytest.raises(octmg.OctmgError):
+        S.set_launch(bottom_kind=1, bottom_max_blocks=8, graph_mode=1)
