@@ -135,8 +135,13 @@ struct octmg_state_s {
     std::vector<long long> stride;  // per level: cells per rhs
     unsigned long long *d_norm = nullptr;
     int *d_flag = nullptr;
-    int *d_active = nullptr;  // [nrhs], 1 while a right-hand side iterates
-    std::vector<int> active_host;              // last values uploaded to d_active
+    // launch set: d_active[0, nrhs) = 1 while a right-hand side iterates;
+    // d_active[nrhs, nrhs + n_launch) = the iterating right-hand sides, which
+    // the kernels' grid rows walk (all of them: no list, grid y = rhs)
+    int *d_active = nullptr;
+    std::vector<int> active_host;              // flags last uploaded
+    std::vector<int> lanes_host;               // list last uploaded
+    int n_launch = 1;                          // grid rows of every per-rhs launch
     unsigned long long *h_norm = nullptr;      // pinned, host-mapped copy of d_norm
     unsigned long long *h_norm_dev = nullptr;  // device view of h_norm
     std::vector<double> r0_cache;              // residual of phi = 0 (valid while !r0_dirty)
@@ -193,6 +198,7 @@ LV<double> lv64(const octmg_state_s *s, int il) {
     v.old = s->f64[il].old;
     v.fstride = s->stride[il];
     v.active = s->d_active;
+    v.lanes = s->n_launch < s->nrhs ? s->d_active + s->nrhs : nullptr;
     v.order = s->block_order;
     return v;
 }
@@ -221,6 +227,7 @@ LV<float> lv32(const octmg_state_s *s, int il) {
     v.old = s->f32[il].old;
     v.fstride = s->stride[il];
     v.active = s->d_active;
+    v.lanes = s->n_launch < s->nrhs ? s->d_active + s->nrhs : nullptr;
     v.order = s->block_order;
     return v;
 }
@@ -254,10 +261,10 @@ struct Engine {
         }
         for (int k = 0; k < steps; k++)
             for (int color = 0; color < 2; color++) {
-                HIPCK(launch_gs_half<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1), color, s->nrhs, st));
+                HIPCK(launch_gs_half<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1), color, s->n_launch, st));
                 if (P && P->on) {
                     const GeomLevel &G = s->geom->L[il];
-                    P->updates += 0.5 * (double)G.nblocks * G.cpb * s->nrhs;
+                    P->updates += 0.5 * (double)G.nblocks * G.cpb * s->n_launch;
                 }
             }
         if (timed) {
@@ -268,15 +275,15 @@ struct Engine {
         return OCTMG_OK;
     }
     octmg_status half_sweep(int il, int color) {
-        HIPCK(launch_gs_half<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1), color, s->nrhs, st));
+        HIPCK(launch_gs_half<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1), color, s->n_launch, st));
         return OCTMG_OK;
     }
     // FAS restriction il -> il-1, then g_c = L_c phi_c + r_c, old_c = phi_c
     octmg_status restrict_fas(int il) {
         const int adaptive = s->geom->tree.adaptive ? 1 : 0;
-        HIPCK(launch_restrict_fas<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), adaptive, s->nrhs, st));
-        if (adaptive) HIPCK(launch_copy_parents<T>(D(), Nb(il - 1), lvT<T>(s, il - 1), s->nrhs, st));
-        HIPCK(launch_fas_rhs<T>(D(), Nb(il - 1), lvT<T>(s, il - 1), lvT<T>(s, il - 2), 1, s->nrhs, st));
+        HIPCK(launch_restrict_fas<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), adaptive, s->n_launch, st));
+        if (adaptive) HIPCK(launch_copy_parents<T>(D(), Nb(il - 1), lvT<T>(s, il - 1), s->n_launch, st));
+        HIPCK(launch_fas_rhs<T>(D(), Nb(il - 1), lvT<T>(s, il - 1), lvT<T>(s, il - 2), 1, s->n_launch, st));
         return OCTMG_OK;
     }
     octmg_status restrict_rhs(int il) {
@@ -284,22 +291,22 @@ struct Engine {
         const long long n = s->stride[il - 1] * s->nrhs;
         HIPCK(fill(c.phi, n));
         HIPCK(fill(c.old, n));
-        HIPCK(launch_restrict_rhs<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), c, s->nrhs, st));
+        HIPCK(launch_restrict_rhs<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), c, s->n_launch, st));
         return OCTMG_OK;
     }
     octmg_status prolong(int il, int solution_mode) {
-        HIPCK(launch_prolong<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), solution_mode, s->nrhs, st));
+        HIPCK(launch_prolong<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), solution_mode, s->n_launch, st));
         return OCTMG_OK;
     }
     octmg_status coarse_solve() {
-        HIPCK(launch_coarse_solve<T>(D(), lvT<T>(s, 0), s->geom->d_M, s->geom->d_S, s->nrhs, st));
+        HIPCK(launch_coarse_solve<T>(D(), lvT<T>(s, 0), s->geom->d_M, s->geom->d_S, s->n_launch, st));
         return OCTMG_OK;
     }
     hipError_t fill(T *p, long long n);
     octmg_status sync_down() {
         if (!s->geom->tree.adaptive) return OCTMG_OK;
         for (int il = (int)s->geom->L.size() - 1; il > 0; il--)
-            HIPCK(launch_restrict_phi<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), s->nrhs, st));
+            HIPCK(launch_restrict_phi<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), s->n_launch, st));
         return OCTMG_OK;
     }
     octmg_status fused(int top);
@@ -369,7 +376,7 @@ octmg_status residual_norm_dev(octmg_state s, int phi_zero, hipStream_t st) {
     for (int il = 0; il < (int)s->geom->L.size(); il++) {
         const GeomLevel &G = s->geom->L[il];
         if (G.nleaf == 0) continue;
-        HIPCK(launch_residual_max<double>(D, G.Nb, lv64(s, il), lv64(s, il - 1), phi_zero, s->d_norm, s->nrhs, st));
+        HIPCK(launch_residual_max<double>(D, G.Nb, lv64(s, il), lv64(s, il - 1), phi_zero, s->d_norm, s->n_launch, st));
     }
     return OCTMG_OK;
 }
@@ -401,7 +408,7 @@ octmg_status mixed_defect(octmg_state s, hipStream_t st) {
         const GeomLevel &G = s->geom->L[il];
         if (G.nleaf == 0) continue;
         HIPCK(launch_defect(D, G.Nb, lv64(s, il), lv64(s, il - 1), lv32(s, il), G.d_leaf_blocks, G.nleaf, s->d_norm,
-                            s->nrhs, st));
+                            s->n_launch, st));
     }
     return OCTMG_OK;
 }
@@ -413,7 +420,7 @@ octmg_status mixed_correct(octmg_state s, int kind, hipStream_t st) {
     for (int il = 0; il < (int)s->geom->L.size(); il++) {
         const GeomLevel &G = s->geom->L[il];
         if (G.nleaf == 0) continue;
-        HIPCK(launch_update(D, G.Nb, lv64(s, il), lv32(s, il), G.d_leaf_blocks, G.nleaf, s->nrhs, st));
+        HIPCK(launch_update(D, G.Nb, lv64(s, il), lv32(s, il), G.d_leaf_blocks, G.nleaf, s->n_launch, st));
     }
     return OCTMG_OK;
 }
@@ -438,9 +445,12 @@ octmg_status setup_fused(octmg_state s) {
     SmallLevels<double> h64{};
     SmallLevels<float> h32{};
     for (int il = 0; il <= ft; il++) {
+        // the fused kernel walks every rhs itself (flags skip finished ones)
         h64.L[il] = lv64(s, il);
+        h64.L[il].lanes = nullptr;
         h64.N[il] = s->geom->L[il].Nb;
         if (s->precision == OCTMG_MIXED) h32.L[il] = lv32(s, il);
+        h32.L[il].lanes = nullptr;
         h32.N[il] = s->geom->L[il].Nb;
     }
     h64.n_down = h32.n_down = s->n_down;
@@ -868,9 +878,15 @@ octmg_status octmg_state_create(octmg_geom g, int n_rhs, int precision, octmg_st
     }
     HIPCK(s->pool.alloc(&s->d_norm, n_rhs));
     HIPCK(s->pool.alloc(&s->d_flag, 1));
-    HIPCK(s->pool.alloc(&s->d_active, n_rhs));
+    HIPCK(s->pool.alloc(&s->d_active, 2 * (size_t)n_rhs));
     s->active_host.assign(n_rhs, 1);
-    HIPCK(hipMemcpy(s->d_active, s->active_host.data(), sizeof(int) * n_rhs, hipMemcpyHostToDevice));
+    s->n_launch = n_rhs;
+    for (int r = 0; r < n_rhs; r++) s->lanes_host.push_back(r);
+    {
+        std::vector<int> ctrl(s->active_host);
+        ctrl.insert(ctrl.end(), s->lanes_host.begin(), s->lanes_host.end());
+        HIPCK(hipMemcpy(s->d_active, ctrl.data(), sizeof(int) * ctrl.size(), hipMemcpyHostToDevice));
+    }
     HIPCK(hipHostMalloc((void **)&s->h_norm, sizeof(unsigned long long) * n_rhs, hipHostMallocMapped));
     HIPCK(hipHostGetDevicePointer((void **)&s->h_norm_dev, s->h_norm, 0));
     HIPCK(s->pool.alloc(&s->d_thresh, n_rhs));
@@ -1109,10 +1125,23 @@ octmg_status octmg_residual_norm(octmg_state s, int phi_zero, double *out, void 
     return read_norms(s, out, st);
 }
 
+// Flags and launch list in one upload: later launches cover only the
+// iterating right-hand sides (grid y = their number), so finished or idle
+// ones cost no workgroups.  With none iterating the list keeps every rhs
+// (their kernels then exit at the flag) so that no launch is empty.
 static octmg_status set_active(octmg_state s, const std::vector<int> &act, hipStream_t st) {
-    if (act == s->active_host) return OCTMG_OK;
+    std::vector<int> list;
+    for (int r = 0; r < (int)act.size(); r++)
+        if (act[r]) list.push_back(r);
+    if (list.empty())
+        for (int r = 0; r < (int)act.size(); r++) list.push_back(r);
+    if (act == s->active_host && list == s->lanes_host) return OCTMG_OK;
     s->active_host = act;
-    HIPCK(hipMemcpyAsync(s->d_active, s->active_host.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice, st));
+    s->lanes_host = list;
+    s->n_launch = (int)list.size();
+    std::vector<int> ctrl(act);
+    ctrl.insert(ctrl.end(), list.begin(), list.end());
+    HIPCK(hipMemcpyAsync(s->d_active, ctrl.data(), sizeof(int) * ctrl.size(), hipMemcpyHostToDevice, st));
     HIPCK(hipStreamSynchronize(st));
     return OCTMG_OK;
 }
@@ -1165,6 +1194,12 @@ static octmg_status graph_for(octmg_state s, long long key, hipStream_t st, F &&
 }
 
 }  // extern "C++"
+
+// cache key of a captured graph: what it was captured for, including the
+// number of grid rows of its launches
+static long long graph_key(int mode, int kind, int max_cycles, int zero_start, int n_launch) {
+    return ((((long long)mode * 8 + kind) * 128 + max_cycles) * 2 + zero_start) * 8192 + n_launch;
+}
 
 static void read_mapped(octmg_state s, std::vector<double> &out) {
     for (int r = 0; r < s->nrhs; r++) {
@@ -1221,7 +1256,7 @@ static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStre
         }
         STCK(set_active(s, act, st));
         HIPCK(hipMemcpyAsync(s->d_thresh, th.data(), sizeof(double) * R, hipMemcpyHostToDevice, st));
-        const long long key = 2000000LL + 1000LL * o->max_cycles + 10 * o->cycle_kind + (o->zero_start ? 1 : 0);
+        const long long key = graph_key(2, o->cycle_kind, o->max_cycles, o->zero_start ? 1 : 0, s->n_launch);
         hipGraphExec_t exec = nullptr;
         STCK(graph_for(s, key, st, [&]() -> octmg_status {
             for (int c = 0; c < o->max_cycles; c++) {
@@ -1303,7 +1338,7 @@ static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStre
         prev = cur;
         if (changed) STCK(set_active(s, act, st));
         if (o->graph_mode == 1 && have_guess) {
-            const long long key = 1000000LL + 10 * o->cycle_kind;
+            const long long key = graph_key(1, o->cycle_kind, 0, 0, s->n_launch);
             hipGraphExec_t exec = nullptr;
             STCK(graph_for(s, key, st, [&]() { return cycle_and_norm(s, o->cycle_kind, 1, st); }, &exec));
             HIPCK(hipGraphLaunch(exec, st));
@@ -1469,6 +1504,7 @@ static LV<double> lv64_lane(const octmg_state_s *s, int il, int lane) {
     v.g += o;
     v.old += o;
     v.active += lane;
+    v.lanes = nullptr;
     return v;
 }
 
@@ -1532,7 +1568,7 @@ octmg_status lanes_begin(octmg_state s, const std::vector<int> &fresh, hipStream
 // iterates into the host-mapped buffer; returns without waiting.
 octmg_status lanes_cycle(octmg_state s, const std::vector<int> &running, int kind, hipStream_t st) {
     STCK(set_active(s, running, st));
-    const long long key = 1000000LL + 10 * kind;
+    const long long key = graph_key(1, kind, 0, 0, s->n_launch);
     hipGraphExec_t exec = nullptr;
     STCK(graph_for(s, key, st, [&]() { return cycle_and_norm(s, kind, 1, st); }, &exec));
     HIPCK(hipGraphLaunch(exec, st));

@@ -145,9 +145,16 @@ __device__ __forceinline__ bool on_block_face(int i, int j, int k) {
     return i == 0 || i == N - 1 || j == 0 || j == N - 1 || (D == 3 && (k == 0 || k == N - 1));
 }
 
+// right-hand side of this workgroup: grid y walks the launch's lane list
+// (the running right-hand sides), or all of them when there is none
+template <typename T>
+__device__ __forceinline__ int rhs_of(const LV<T> &L) {
+    return L.lanes ? L.lanes[blockIdx.y] : (int)blockIdx.y;
+}
+
 template <typename T>
 __device__ __forceinline__ bool inactive(const LV<T> &L) {
-    return L.active && !L.active[blockIdx.y];
+    return L.active && !L.active[rhs_of(L)];
 }
 
 template <typename T, int D>
@@ -174,9 +181,9 @@ __global__ __launch_bounds__((Blk<D, N>::THREADS)) void k_gs_half(LV<T> L, LV<T>
     const int4 P = L.pos[blk];
     load_neighbours<T, D>(L, P, snb, &smo, blk);
     __syncthreads();
-    T *phi = L.phi + (long long)blockIdx.y * L.fstride;
-    const T *g = L.g + (long long)blockIdx.y * L.fstride;
-    const T *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
+    T *phi = L.phi + (long long)rhs_of(L) * L.fstride;
+    const T *g = L.g + (long long)rhs_of(L) * L.fstride;
+    const T *phic = Lc.phi ? Lc.phi + (long long)rhs_of(L) * Lc.fstride : nullptr;
     const long long base = (long long)blk * B::CPB;
     const int mo = smo;
     const T inv2d = T(1) / T(2 * D);
@@ -242,11 +249,11 @@ __global__ __launch_bounds__(256) void k_restrict_fas(LV<T> L, LV<T> Lc, int int
     const int4 P = L.pos[blk];
     load_neighbours<T, D>(L, P, snb, &smo, blk);
     __syncthreads();
-    const T *phi = L.phi + (long long)blockIdx.y * L.fstride;
-    const T *g = L.g + (long long)blockIdx.y * L.fstride;
-    const T *phic = Lc.phi + (long long)blockIdx.y * Lc.fstride;
-    T *phiw = (into_old ? Lc.old : Lc.phi) + (long long)blockIdx.y * Lc.fstride;
-    T *gw = Lc.g + (long long)blockIdx.y * Lc.fstride;
+    const T *phi = L.phi + (long long)rhs_of(L) * L.fstride;
+    const T *g = L.g + (long long)rhs_of(L) * L.fstride;
+    const T *phic = Lc.phi + (long long)rhs_of(L) * Lc.fstride;
+    T *phiw = (into_old ? Lc.old : Lc.phi) + (long long)rhs_of(L) * Lc.fstride;
+    T *gw = Lc.g + (long long)rhs_of(L) * Lc.fstride;
     const long long base = (long long)blk * Blk<D, N>::CPB;
     const int C0[3] = {P.x * H, P.y * H, D == 3 ? P.z * H : 0};
     const int pb = block_at<T, D>(Lc, C0[0] / NC, C0[1] / NC, D == 3 ? C0[2] / NC : 0);
@@ -275,7 +282,7 @@ __global__ __launch_bounds__(256) void k_copy_parents(LV<T> L) {
     if (inactive(L)) return;
     const int blk = blockIdx.x;
     if (L.leaf[blk]) return;
-    const long long o = (long long)blockIdx.y * L.fstride + (long long)blk * Blk<D, N>::CPB;
+    const long long o = (long long)rhs_of(L) * L.fstride + (long long)blk * Blk<D, N>::CPB;
     for (int c = threadIdx.x; c < Blk<D, N>::CPB; c += blockDim.x) L.phi[o + c] = L.old[o + c];
 }
 
@@ -286,8 +293,8 @@ __global__ __launch_bounds__(256) void k_restrict_rhs(LV<T> L, LV<T> Lc) {
     constexpr int H = N / 2, NCELL = D == 3 ? H * H * H : H * H;
     const int blk = blockIdx.x;
     const int4 P = L.pos[blk];
-    const T *g = L.g + (long long)blockIdx.y * L.fstride;
-    T *gw = Lc.g + (long long)blockIdx.y * Lc.fstride;
+    const T *g = L.g + (long long)rhs_of(L) * L.fstride;
+    T *gw = Lc.g + (long long)rhs_of(L) * Lc.fstride;
     const long long base = (long long)blk * Blk<D, N>::CPB;
     const int C0[3] = {P.x * H, P.y * H, D == 3 ? P.z * H : 0};
     const int pb = block_at<T, D>(Lc, C0[0] / NC, C0[1] / NC, D == 3 ? C0[2] / NC : 0);
@@ -313,8 +320,8 @@ __global__ __launch_bounds__(256) void k_restrict_phi(LV<T> L, LV<T> Lc) {
     constexpr int H = N / 2, NCELL = D == 3 ? H * H * H : H * H;
     const int blk = blockIdx.x;
     const int4 P = L.pos[blk];
-    const T *phi = L.phi + (long long)blockIdx.y * L.fstride;
-    T *pw = Lc.phi + (long long)blockIdx.y * Lc.fstride;
+    const T *phi = L.phi + (long long)rhs_of(L) * L.fstride;
+    T *pw = Lc.phi + (long long)rhs_of(L) * Lc.fstride;
     const long long base = (long long)blk * Blk<D, N>::CPB;
     const int C0[3] = {P.x * H, P.y * H, D == 3 ? P.z * H : 0};
     const int pb = block_at<T, D>(Lc, C0[0] / NC, C0[1] / NC, D == 3 ? C0[2] / NC : 0);
@@ -346,10 +353,10 @@ __global__ __launch_bounds__((Blk<D, N>::THREADS)) void k_fas_rhs(LV<T> L, LV<T>
     const int4 P = L.pos[blk];
     load_neighbours<T, D>(L, P, snb, &smo, blk);
     __syncthreads();
-    T *phi = L.phi + (long long)blockIdx.y * L.fstride;
-    T *g = L.g + (long long)blockIdx.y * L.fstride;
-    T *old = L.old + (long long)blockIdx.y * L.fstride;
-    const T *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
+    T *phi = L.phi + (long long)rhs_of(L) * L.fstride;
+    T *g = L.g + (long long)rhs_of(L) * L.fstride;
+    T *old = L.old + (long long)rhs_of(L) * L.fstride;
+    const T *phic = Lc.phi ? Lc.phi + (long long)rhs_of(L) * Lc.fstride : nullptr;
     const long long base = (long long)blk * B::CPB;
     const bool parent = !L.leaf[blk];
     for (int c = threadIdx.x; c < B::CPB; c += B::THREADS) {
@@ -454,9 +461,9 @@ __global__ __launch_bounds__(256) void k_prolong(LV<T> L, LV<T> Lc, int solution
     constexpr int H = N / 2, NCELL = D == 3 ? H * H * H : H * H;
     const int blk = blockIdx.x;
     const int4 P = L.pos[blk];
-    T *phi = L.phi + (long long)blockIdx.y * L.fstride;
-    const T *phic = Lc.phi + (long long)blockIdx.y * Lc.fstride;
-    const T *oldc = Lc.old + (long long)blockIdx.y * Lc.fstride;
+    T *phi = L.phi + (long long)rhs_of(L) * L.fstride;
+    const T *phic = Lc.phi + (long long)rhs_of(L) * Lc.fstride;
+    const T *oldc = Lc.old + (long long)rhs_of(L) * Lc.fstride;
     const long long base = (long long)blk * Blk<D, N>::CPB;
     const int C0[3] = {P.x * H, P.y * H, D == 3 ? P.z * H : 0};
     for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
@@ -504,8 +511,8 @@ __global__ __launch_bounds__(256) void k_coarse_solve(LV<T> L0, const double *M,
     constexpr int NB = 8, NCELL = D == 3 ? 512 : 64;
     constexpr int ROWS_PER_WG = D == 3 ? 32 : 16;
     __shared__ double rhs[NCELL];
-    const T *g = L0.g + (long long)blockIdx.y * L0.fstride;
-    T *phi = L0.phi + (long long)blockIdx.y * L0.fstride;
+    const T *g = L0.g + (long long)rhs_of(L0) * L0.fstride;
+    T *phi = L0.phi + (long long)rhs_of(L0) * L0.fstride;
     const int mo = L0.map_off ? L0.map_off[0] : -1;
     const double inv = 1.0 / ((double)L0.dx2);
     for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
@@ -553,9 +560,9 @@ __global__ __launch_bounds__((Blk<D, N>::THREADS)) void k_residual_max(LV<T> L, 
     const int4 P = L.pos[blk];
     load_neighbours<T, D>(L, P, snb, &smo, blk);
     __syncthreads();
-    const T *phi = L.phi + (long long)blockIdx.y * L.fstride;
-    const T *g = L.g + (long long)blockIdx.y * L.fstride;
-    const T *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
+    const T *phi = L.phi + (long long)rhs_of(L) * L.fstride;
+    const T *g = L.g + (long long)rhs_of(L) * L.fstride;
+    const T *phic = Lc.phi ? Lc.phi + (long long)rhs_of(L) * Lc.fstride : nullptr;
     const long long base = (long long)blk * B::CPB;
     double m = 0.0;
     for (int c = threadIdx.x; c < B::CPB; c += B::THREADS) {
@@ -571,7 +578,7 @@ __global__ __launch_bounds__((Blk<D, N>::THREADS)) void k_residual_max(LV<T> L, 
     if (threadIdx.x == 0) {
         for (int w = 1; w < (int)(B::THREADS + 63) / 64; w++) m = fmax(m, wmax[w]);
         if (m != m) m = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +Inf
-        atomicMax(out + blockIdx.y, (unsigned long long)__double_as_longlong(m));
+        atomicMax(out + rhs_of(L), (unsigned long long)__double_as_longlong(m));
     }
 }
 
@@ -625,11 +632,11 @@ __global__ __launch_bounds__((Blk<D, N>::THREADS)) void k_defect(LV<double> L, L
     const int4 P = L.pos[blk];
     load_neighbours<double, D>(L, P, snb, &smo, blk);
     __syncthreads();
-    const double *phi = L.phi + (long long)blockIdx.y * L.fstride;
-    const double *g = L.g + (long long)blockIdx.y * L.fstride;
-    const double *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
-    float *g32 = L32.g + (long long)blockIdx.y * L32.fstride;
-    float *p32 = L32.phi + (long long)blockIdx.y * L32.fstride;
+    const double *phi = L.phi + (long long)rhs_of(L) * L.fstride;
+    const double *g = L.g + (long long)rhs_of(L) * L.fstride;
+    const double *phic = Lc.phi ? Lc.phi + (long long)rhs_of(L) * Lc.fstride : nullptr;
+    float *g32 = L32.g + (long long)rhs_of(L) * L32.fstride;
+    float *p32 = L32.phi + (long long)rhs_of(L) * L32.fstride;
     const long long base = (long long)blk * B::CPB;
     double m = 0.0;
     for (int c = threadIdx.x; c < B::CPB; c += B::THREADS) {
@@ -647,7 +654,7 @@ __global__ __launch_bounds__((Blk<D, N>::THREADS)) void k_defect(LV<double> L, L
     if (threadIdx.x == 0) {
         for (int w = 1; w < (int)(B::THREADS + 63) / 64; w++) m = fmax(m, wmax[w]);
         if (m != m) m = __longlong_as_double(0x7ff0000000000000ll);
-        atomicMax(out + blockIdx.y, (unsigned long long)__double_as_longlong(m));
+        atomicMax(out + rhs_of(L), (unsigned long long)__double_as_longlong(m));
     }
 }
 
@@ -656,8 +663,8 @@ __global__ void k_update(LV<double> L, LV<float> L32, const int *lb) {
     if (inactive(L)) return;
     using B = Blk<D, N>;
     const int blk = lb[blockIdx.x];
-    double *phi = L.phi + (long long)blockIdx.y * L.fstride + (long long)blk * B::CPB;
-    const float *e = L32.phi + (long long)blockIdx.y * L32.fstride + (long long)blk * B::CPB;
+    double *phi = L.phi + (long long)rhs_of(L) * L.fstride + (long long)blk * B::CPB;
+    const float *e = L32.phi + (long long)rhs_of(L) * L32.fstride + (long long)blk * B::CPB;
     for (int c = threadIdx.x; c < B::CPB; c += blockDim.x) phi[c] += (double)e[c];
 }
 
@@ -969,7 +976,7 @@ __global__ __launch_bounds__(256) void k_gs_half3(LV<T> L, LV<T> Lc, int color) 
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER;
     __shared__ T tile[ColTile<N>::SIZE];
-    gs_half3_body<T, N>(L, Lc, color, block_of(L.order), blockIdx.y, tile);
+    gs_half3_body<T, N>(L, Lc, color, block_of(L.order), rhs_of(L), tile);
 }
 
 // L phi at the PER cells of colour `col` owned by this thread, from the
@@ -1132,7 +1139,7 @@ __global__ __launch_bounds__(256) void k_restrict_fas3(LV<T> L, LV<T> Lc, int in
     constexpr int PER = Per<N>::PER, H = N / 2, NCELL = H * H * H, CPER = (NCELL + 255) / 256;
     constexpr int SM = ColTile<N>::SIZE > B::CPB ? ColTile<N>::SIZE : B::CPB;
     __shared__ T sm[SM];
-    restrict_fas3_body<T, N, NC>(L, Lc, into_old, block_of(L.order), blockIdx.y, sm);
+    restrict_fas3_body<T, N, NC>(L, Lc, into_old, block_of(L.order), rhs_of(L), sm);
 }
 
 // FAS rhs on parent blocks (g = L phi + g) and old = phi, 3D
@@ -1185,7 +1192,7 @@ __global__ __launch_bounds__(256) void k_fas_rhs3(LV<T> L, LV<T> Lc, int do_rhs)
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER;
     __shared__ T tile[ColTile<N>::SIZE];
-    fas_rhs3_body<T, N>(L, Lc, do_rhs, block_of(L.order), blockIdx.y, tile);
+    fas_rhs3_body<T, N>(L, Lc, do_rhs, block_of(L.order), rhs_of(L), tile);
 }
 
 // max |g - L phi| over a leaf block (3D); ZERO: residual of phi = 0
@@ -1194,7 +1201,8 @@ __global__ __launch_bounds__(256) void k_residual_max3(LV<T> L, LV<T> Lc, unsign
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER;
     const int blk = block_of(L.order);
-    const int act = L.active ? L.active[blockIdx.y] : 1;
+    const int rhs = rhs_of(L);
+    const int act = L.active ? L.active[rhs] : 1;
     const int leaf = L.leaf[blk];
     const int4 P = L.pos[blk];
     int nbk[6];
@@ -1203,9 +1211,9 @@ __global__ __launch_bounds__(256) void k_residual_max3(LV<T> L, LV<T> Lc, unsign
     if (!act || !leaf) return;
     __shared__ T tile[ColTile<N>::SIZE];
     __shared__ double wmax[4];
-    const T *__restrict__ phi = L.phi + (long long)blockIdx.y * L.fstride;
-    const T *__restrict__ g = L.g + (long long)blockIdx.y * L.fstride;
-    const T *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
+    const T *__restrict__ phi = L.phi + (long long)rhs * L.fstride;
+    const T *__restrict__ g = L.g + (long long)rhs * L.fstride;
+    const T *phic = Lc.phi ? Lc.phi + (long long)rhs * Lc.fstride : nullptr;
     const long long base = (long long)blk * B::CPB;
     T own0[PER], own1[PER], lp[PER], gv[PER];
     int ri[PER];
@@ -1239,7 +1247,7 @@ __global__ __launch_bounds__(256) void k_residual_max3(LV<T> L, LV<T> Lc, unsign
     if (threadIdx.x == 0) {
         for (int w = 1; w < 4; w++) mx = fmax(mx, wmax[w]);
         if (mx != mx) mx = __longlong_as_double(0x7ff0000000000000ll);
-        atomicMax(out + blockIdx.y, (unsigned long long)__double_as_longlong(mx));
+        atomicMax(out + rhs, (unsigned long long)__double_as_longlong(mx));
     }
 }
 
@@ -1286,7 +1294,7 @@ __global__ __launch_bounds__(256) void k_prolong3(LV<T> L, LV<T> Lc, int solutio
     using B = Blk<3, N>;
     constexpr int H = N / 2, E = H + 2, ESZ = E * E * E, PER = B::CPB / 256;
     __shared__ T et[ESZ];
-    prolong3_body<T, N, NC>(L, Lc, solution, block_of(L.order), blockIdx.y, et);
+    prolong3_body<T, N, NC>(L, Lc, solution, block_of(L.order), rhs_of(L), et);
 }
 
 // mixed precision defect (FP64): g32 = g - L phi on a leaf block, phi32 = 0
@@ -1297,19 +1305,20 @@ __global__ __launch_bounds__(256) void k_defect3(LV<double> L, LV<double> Lc, LV
     constexpr int PER = Per<N>::PER;
     __shared__ double tile[ColTile<N>::SIZE];
     __shared__ double wmax[4];
-    const int act = L.active ? L.active[blockIdx.y] : 1;
+    const int rhs = rhs_of(L);
+    const int act = L.active ? L.active[rhs] : 1;
     const int blk = lb[blockIdx.x];
     const int4 P = L.pos[blk];
     int nbk[6];
     face_ids<double, N>(L, blk, nbk);
     const int mo = L.map_off ? L.map_off[blk] : -1;
     if (!act) return;
-    const double *__restrict__ phi = L.phi + (long long)blockIdx.y * L.fstride;
-    const double *__restrict__ g = L.g + (long long)blockIdx.y * L.fstride;
-    const double *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
+    const double *__restrict__ phi = L.phi + (long long)rhs * L.fstride;
+    const double *__restrict__ g = L.g + (long long)rhs * L.fstride;
+    const double *phic = Lc.phi ? Lc.phi + (long long)rhs * Lc.fstride : nullptr;
     const long long base = (long long)blk * B::CPB;
-    float *g32 = L32.g + (long long)blockIdx.y * L32.fstride + base;
-    float *p32 = L32.phi + (long long)blockIdx.y * L32.fstride + base;
+    float *g32 = L32.g + (long long)rhs * L32.fstride + base;
+    float *p32 = L32.phi + (long long)rhs * L32.fstride + base;
     double own0[PER], own1[PER], lp[PER], gv[PER];
     int ri[PER];
     double mx = 0.0;
@@ -1341,7 +1350,7 @@ __global__ __launch_bounds__(256) void k_defect3(LV<double> L, LV<double> Lc, LV
     if (threadIdx.x == 0) {
         for (int w = 1; w < 4; w++) mx = fmax(mx, wmax[w]);
         if (mx != mx) mx = __longlong_as_double(0x7ff0000000000000ll);
-        atomicMax(out + blockIdx.y, (unsigned long long)__double_as_longlong(mx));
+        atomicMax(out + rhs, (unsigned long long)__double_as_longlong(mx));
     }
 }
 

@@ -68,6 +68,7 @@ struct LV {
     T *phi, *g, *old;
     long long fstride;
     const int *active;   // [nrhs] nonzero = right-hand side still iterating (nullptr: all)
+    const int *lanes;    // [grid y] right-hand side of each grid row (nullptr: row = rhs)
     int order;           // workgroup -> block order of the 3D kernels (0 XCD ranges, 1 hardware)
 };
 
