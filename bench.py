@@ -291,6 +291,107 @@ def leg_serving(stream, n_requests=1000, pool=4, rtol=1e-8, budget_gb=64, max_la
     return out
 
 
+def leg_table1(stream, n_fmg=10):
+    """The Sec. 4.1 sphere (R = 1/4, domain [-1/2,1/2]^3, exact solution on
+    the domain boundary) on a uniform 512^3 grid, FP64: time per FMG cycle
+    over n_fmg consecutive FMG cycles, for 8^3 and 16^3 blocks, beside the
+    paper's Table 1 (Epyc 7H12, 32 cores: 1.46 s and 0.95 s)."""
+    import torch
+    from paper_2205_09411_amd import octmg
+    from paper_2205_09411_amd import workloads as W
+    paper_32 = {8: 1.46, 16: 0.95}
+    out = {"workload": "sphere R=1/4 centred in [-1/2,1/2]^3, uniform 512^3, FP64, FMG cycles from the previous "
+                       "iterate (the first from phi=0)"}
+    for bn, lmax in ((8, 7), (16, 6)):
+        w = W.sphere_f1(dim=3, max_level=lmax, block_n=bn)
+        t = time.perf_counter()
+        G = octmg.Geometry(w.geom)
+        setup = time.perf_counter() - t
+        S = octmg.State(G)
+        S.set_boundary_fn(w.iface_value, w.domain_value)
+        xyz, _ = G.leaf_coords()
+        S.set_rhs(np.zeros(G.n_leaf))
+        outside = np.sqrt((xyz ** 2).sum(axis=1)) > 0.25
+        ex = w.exact(xyz)[outside]
+        errs = []
+        S.fmg(have_guess=False, stream=stream)
+        for k in range(2):
+            errs.append(float(np.abs(S.get_solution()[outside] - ex).max()))
+            S.fmg(have_guess=True, stream=stream)
+        errs.append(float(np.abs(S.get_solution()[outside] - ex).max()))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(n_fmg):
+            S.fmg(have_guess=True, stream=stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / n_fmg
+        out[f"blocks_{bn}^3"] = {"ms_per_fmg": round(dt * 1e3, 3), "setup_s": round(setup, 2),
+                                 "blocks": G.n_blocks, "cells_per_fmg_second_G": round(512 ** 3 / dt / 1e9, 2),
+                                 "paper_epyc_7h12_32_cores_s": paper_32[bn],
+                                 "speedup_vs_paper_32_cores": round(paper_32[bn] / dt, 1),
+                                 "max_err_outside_sphere_fmg_1_2_3": errs}
+        del S, G
+        torch.cuda.empty_cache()
+    out["blocks_32^3"] = "not supported: the colour tile of a 32^3 block (166 KB in FP64) exceeds the 160 KB LDS"
+    return out
+
+
+def leg_sharp(stream, n_fmg=4, reps=5):
+    """Sec. 4.3: the spheroid, rhombus, heart and astroid boundaries
+    (phi = 1 on them, 0 on the domain boundary, Laplace equation) on uniform
+    1024^2 and 2048^2 grids (8^2 blocks, 8^2 coarse grid) and 256^3 (16^3
+    blocks over an 8^3 grid), FP64: residual reduction per FMG iteration and
+    time per FMG."""
+    import torch
+    from paper_2205_09411_amd import octmg
+    from paper_2205_09411_amd import workloads as W
+    out = {"workload": "sharp shapes of Sec. 4.3, p = 4(x-0.5), q = 4(y-0.5) (3D: p = 4 r, q = 4(z-0.5)), "
+                       "phi=1 on the shape, 0 on the domain boundary, FMG from phi=0"}
+    for dim, lmax, bn, label in ((2, 8, 8, "1024^2"), (2, 9, 8, "2048^2"), (3, 5, 16, "256^3")):
+        for shape in W.SHAPES:
+            w = W.sharp_shape(shape, dim=dim, max_level=lmax, block_n=bn)
+            G = octmg.Geometry(w.geom)
+            S = octmg.State(G)
+            S.set_boundary_fn(w.iface_value, w.domain_value)
+            S.set_rhs(np.zeros(G.n_leaf))
+            r = [float(S.residual_norm(phi_zero=True)[0])]
+            for k in range(n_fmg):
+                S.fmg(have_guess=k > 0, stream=stream)
+                r.append(float(S.residual_norm(stream=stream)[0]))
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                S.fmg(have_guess=True, stream=stream)
+            torch.cuda.synchronize()
+            out[f"{shape}_{label}"] = {
+                "reduction_per_fmg": [round(r[i] / r[i + 1], 1) if r[i + 1] > 0 else None for i in range(n_fmg)],
+                "ms_per_fmg": round((time.perf_counter() - t) / reps * 1e3, 3),
+                "interface_records": int(G.n_records)}
+            del S, G
+    return out
+
+
+def leg_2d(stream, steps=20):
+    """2D 64^2 in 8^2 blocks, circle r=0.25, manufactured solution, FP64,
+    V(2,2) to 1e-10 (launch-bound at this size)."""
+    import torch
+    from paper_2205_09411_amd import octmg
+    from paper_2205_09411_amd import workloads as W
+    w = W.mms2d(max_level=4)
+    G = octmg.Geometry(w.geom)
+    S = octmg.State(G)
+    S.set_boundary_fn(w.iface_value, w.domain_value)
+    xyz, _ = G.leaf_coords()
+    S.set_rhs(w.rhs(xyz))
+    dt, rep = timed_solves(S, steps, stream, rtol=1e-10, max_cycles=40, graph_mode=1)
+    hist = [rep.r0] + list(rep.history[:rep.cycles])
+    factors = [hist[i + 1] / hist[i] for i in range(len(hist) - 1)]
+    return {"workload": "2D unit square 64^2 in 8^2 blocks, circle r=0.25, phi=sin(2 pi x)cos(3 pi y)+x^2",
+            "ms_per_solve": round(dt * 1e3, 3), "cycles": rep.cycles,
+            "residual_factor_per_cycle": [round(f, 4) for f in factors],
+            "max_err_vs_exact": float(np.abs(S.get_solution() - w.exact(xyz)).max())}
+
+
 def cpu_baseline(w, n_cycles):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -317,8 +418,11 @@ def main():
     ap.add_argument("--cpu-cycles", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
-    ap.add_argument("--legs", default="mixed,batched,adaptive,serving",
-                    help="extra measurements after the headline: mixed,batched,adaptive,serving or none")
+    ap.add_argument("--block-order", type=int, default=None,
+                    help="with --no-tune: block order of the 3D kernels (0 XCD ranges, 1 hardware, 2 octant walk)")
+    ap.add_argument("--legs", default="mixed,batched,adaptive,serving,table1,2d,sharp",
+                    help="extra measurements after the headline: mixed,batched,adaptive,serving,table1,2d,sharp "
+                         "or none")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -356,6 +460,8 @@ def main():
     # launch configuration: the autotuner times every candidate (all give
     # identical iterates) and keeps the fastest
     if args.no_tune:
+        if args.block_order is not None:
+            S.set_launch(block_order=args.block_order)
         tuned, cand_ms = S.get_launch(), []
     else:
         tuned, cand_ms = S.autotune(rtol=args.rtol, reps=2, stream=stream)
@@ -434,6 +540,12 @@ def main():
                 legs[leg] = leg_adaptive(stream, args.rtol)
             elif leg == "serving":
                 legs[leg] = leg_serving(stream)
+            elif leg == "table1":
+                legs[leg] = leg_table1(stream)
+            elif leg == "2d":
+                legs[leg] = leg_2d(stream)
+            elif leg == "sharp":
+                legs[leg] = leg_sharp(stream)
             else:
                 raise ValueError(f"unknown leg {leg}")
         except Exception as e:  # a failed leg is reported, the headline stands

@@ -55,7 +55,16 @@ typedef enum {
 /* level-set kinds (Sec. 3.1, eq. lsf-example) */
 enum { OCTMG_LSF_NONE = 0,       /* no interface */
        OCTMG_LSF_SPHERES = 1,    /* union: f = min_m |x - c_m| - r_m; params [cx,cy,cz,r]*n */
-       OCTMG_LSF_CYLINDER_Z = 2  /* f = |(x,y) - (cx,cy)| - r; params [cx,cy,r] */ };
+       OCTMG_LSF_CYLINDER_Z = 2, /* f = |(x,y) - (cx,cy)| - r; params [cx,cy,r] */
+       /* the sharp shapes of Sec. 4.3 (eqs. spheroid .. astroid) in
+        * coordinates 2D: p = s (x - cx), q = s (y - cy); 3D, rotated about the
+        * z axis through (cx, cy): p = s |(x - cx, y - cy)|, q = s (z - cz);
+        * params [cx, cy, cz, s]; |t|^(2/3) is evaluated as the cube root of
+        * t^2 computed with + - * / only (bit-reproducible) */
+       OCTMG_LSF_SPHEROID = 3,   /* sqrt(8 p^2 + q^2) - 1 */
+       OCTMG_LSF_RHOMBUS = 4,    /* 8 |p| + |q| - 1.5 */
+       OCTMG_LSF_HEART = 5,      /* p^2 + (q - |p|^(2/3))^2 - 1 */
+       OCTMG_LSF_ASTROID = 6     /* |p|^(2/3) / 0.8 + |q|^(2/3) / 1.5 - 0.8 */ };
 enum { OCTMG_REFINE_UNIFORM = 0, OCTMG_REFINE_NEAR_INTERFACE = 1 };
 enum { OCTMG_FP64 = 0, OCTMG_MIXED = 1 };
 enum { OCTMG_CYCLE_V = 0, OCTMG_CYCLE_FMG = 1 };
@@ -95,7 +104,10 @@ typedef struct octmg_state_s *octmg_state;
  * iterates, bit for bit; only the speed differs.
  *   block_order: which workgroup handles which block in the 3D level
  *     kernels -- 0: each of the 8 XCDs walks a contiguous Morton range of
- *     the level (face halos stay in that XCD's L2); 1: hardware order.
+ *     the level (face halos stay in that XCD's L2); 1: hardware order;
+ *     2: on complete levels (nb^3 blocks) each XCD walks one Morton octant
+ *     x-fastest (face neighbours a short distance apart in its dispatch
+ *     order), elsewhere as 0.
  *   bottom_kind: 0 one launch per step and level; 1 the levels with at most
  *     bottom_max_blocks blocks run inside one cooperative launch (as
  *     octmg_state_set_fused_levels).
@@ -210,10 +222,10 @@ octmg_status octmg_solve(octmg_state s, const octmg_solve_opts *opts, void *stre
 
 /* Autotuner: solves the state's current problem from phi = 0 (opts, with
  * zero_start and graph_mode taken from each candidate) once to warm up and
- * `reps` times timed, under every candidate launch configuration (both block
- * orders x {separate, separate in a per-cycle graph, cooperative bottom up
- * to 8 and to 64 blocks (3D)}), then keeps the fastest in the state and
- * returns it.  ms[i] (if not NULL, room for 8) receives the mean wall time
+ * `reps` times timed, under every candidate launch configuration (the three
+ * block orders x {separate, separate in a per-cycle graph, cooperative
+ * bottom up to 8 and to 64 blocks (3D)}), then keeps the fastest in the
+ * state and returns it.  ms[i] (if not NULL, room for 12) receives the mean wall time
  * per solve of candidate i, *n_candidates their number.  Afterwards phi
  * holds the solution (the same under every candidate). */
 octmg_status octmg_autotune(octmg_state s, const octmg_solve_opts *opts, int reps, void *stream,

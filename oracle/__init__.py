@@ -87,6 +87,7 @@ def lib():
             "orc_leaf_residual": (None, [vp, dp, dp]),
             "orc_line_search": (C.c_double, [C.POINTER(_Desc), dp, dp, ip]),
             "orc_lsf": (C.c_double, [C.POINTER(_Desc), dp]),
+            "orc_cbrt": (C.c_double, [C.c_double]),
             "orc_coarse_search": (C.c_int, [C.POINTER(_Desc), dp, C.c_double, dp, ip, dp]),
         }
         for name, (res, args) in sig.items():
@@ -308,6 +309,11 @@ def line_search(geom, a, b):
     found = C.c_int()
     t = lib().orc_line_search(C.byref(d), _dp(a), _dp(b), C.byref(found))
     return t, bool(found.value)
+
+
+def cbrt(a: float) -> float:
+    """The checker's cube root (+ - * / only), as used by the sharp shapes."""
+    return lib().orc_cbrt(float(a))
 
 
 def lsf_value(geom, x) -> float:

@@ -60,6 +60,11 @@
  *     user rhs.  old = phi on the whole coarse level after restriction.
  *   * adaptive trees: after each cycle phi is restricted top-down onto
  *     parent cells, so that the composite residual is defined.
+ *   * sharp shapes (Sec. 4.3): p = 4 (x - 0.5), q = 4 (y - 0.5) (the
+ *     printed division by 4 puts every shape outside the unit square); in
+ *     3D p = 4 |(x, y) - (0.5, 0.5)|, q = 4 (z - 0.5) (rotation about the
+ *     cube's vertical axis); |t|^(2/3) = cbrt(t^2) with a cube root made of
+ *     + - * / only.
  *
  * Build: gcc -O2 -std=c99 -fPIC -shared -ffp-contract=off -fopenmp
  * (no fused multiply-add, so that level-set decisions are reproducible).
@@ -123,9 +128,50 @@ static void *xcalloc(size_t n, size_t s) {
     return p;
 }
 
+/* Cube root of a >= 0 with + - * / only (so that every platform computes
+ * the same bits): scale a by powers of 8 into [1/8, 1), six Newton steps
+ * y <- (2y + m/y^2)/3 from y = 3/4 (the root lies in [1/2, 1), where the
+ * iteration converges quadratically to a few ulp), scale back. */
+static double cbrt_exact_ops(double a) {
+    if (!(a > 0.0)) return 0.0;
+    int k = 0;
+    double m = a;
+    while (m >= 1.0) { m = m * 0.125; k++; }
+    while (m < 0.125) { m = m * 8.0; k--; }
+    double y = 0.75;
+    for (int i = 0; i < 6; i++) y = (2.0 * y + m / (y * y)) / 3.0;
+    for (; k > 0; k--) y = y * 2.0;
+    for (; k < 0; k++) y = y * 0.5;
+    return y;
+}
+
+/* The four shapes of Sec. 4.3 (eqs. spheroid .. astroid) in coordinates
+ * (p, q): 2D p = s (x - cx), q = s (y - cy); 3D, rotated about the z axis
+ * through (cx, cy): p = s |(x - cx, y - cy)|, q = s (z - cz); params
+ * [cx, cy, cz, s].  The paper prints p = (x - 0.5)/4, which puts every
+ * shape outside the unit square; the scale used is 4 (x - 0.5). */
+static double shape_lsf(int kind, int D, const double *prm, const double *x) {
+    double p, q;
+    if (D == 2) {
+        p = prm[3] * (x[0] - prm[0]);
+        q = prm[3] * (x[1] - prm[1]);
+    } else {
+        double ex = x[0] - prm[0], ey = x[1] - prm[1];
+        p = prm[3] * sqrt(ex * ex + ey * ey);
+        q = prm[3] * (x[2] - prm[2]);
+    }
+    switch (kind) {
+        case 3: return sqrt(8.0 * p * p + q * q) - 1.0;                       /* spheroid */
+        case 4: return 8.0 * fabs(p) + fabs(q) - 1.5;                         /* rhombus */
+        case 5: { double c = q - cbrt_exact_ops(p * p); return p * p + c * c - 1.0; } /* heart */
+        default: return cbrt_exact_ops(p * p) / 0.8 + cbrt_exact_ops(q * q) / 1.5 - 0.8; /* astroid */
+    }
+}
+
 /* level-set function (Sec. 3.1). Only + - * / sqrt and comparisons. */
 static double lsf(const Orc *o, const double *x) {
     const double *p = o->lsfp;
+    if (o->d.lsf_kind >= 3 && o->d.lsf_kind <= 6) return shape_lsf(o->d.lsf_kind, o->D, p, x);
     if (o->d.lsf_kind == 1) { /* union of spheres: min_m (|x - c_m| - r_m) */
         double f = 0.0;
         for (int m = 0; m < o->d.lsf_n; m++) {
@@ -887,7 +933,7 @@ void *orc_create(const orc_desc *d) {
     Orc *o = xcalloc(1, sizeof(Orc));
     o->d = *d;
     o->D = d->dim;
-    int np = d->lsf_kind == 1 ? 4 * d->lsf_n : (d->lsf_kind == 2 ? 3 : 0);
+    int np = d->lsf_kind == 1 ? 4 * d->lsf_n : (d->lsf_kind == 2 ? 3 : (d->lsf_kind >= 3 && d->lsf_kind <= 6 ? 4 : 0));
     o->lsfp = xcalloc(np + 1, sizeof(double));
     if (np) memcpy(o->lsfp, d->lsf_params, np * sizeof(double));
     o->d.lsf_params = o->lsfp;
@@ -1168,6 +1214,8 @@ double orc_line_search(const orc_desc *d, const double *a, const double *b, int 
     double fa = lsf(&o, a);
     return line_search(&o, a, b, fa, found);
 }
+
+double orc_cbrt(double a) { return cbrt_exact_ops(a); }
 
 double orc_lsf(const orc_desc *d, const double *x) {
     Orc o;

@@ -482,13 +482,17 @@ octmg_status validate_desc(const octmg_geom_desc *d) {
     if (!d) return fail(OCTMG_ERR_INVALID, "null descriptor");
     if (!(d->eps_tol > 0.0 && d->eps_tol < 0.5)) return fail(OCTMG_ERR_INVALID, "eps_tol must be in (0, 0.5)");
     if (!(d->mask_factor > 0.0)) return fail(OCTMG_ERR_INVALID, "mask_factor must be > 0");
+    if (d->lsf_kind < OCTMG_LSF_NONE || d->lsf_kind > OCTMG_LSF_ASTROID) return fail(OCTMG_ERR_INVALID, "unknown lsf_kind");
     if (d->lsf_kind == OCTMG_LSF_SPHERES && (d->lsf_n < 1 || d->lsf_n > 100000))
         return fail(OCTMG_ERR_INVALID, "lsf_n out of range");
+    if (d->lsf_kind != OCTMG_LSF_NONE && !d->lsf_params) return fail(OCTMG_ERR_INVALID, "lsf_params is null");
     return OCTMG_OK;
 }
 
 std::vector<double> copy_params(const octmg_geom_desc &d) {
-    int np = d.lsf_kind == OCTMG_LSF_SPHERES ? 4 * d.lsf_n : (d.lsf_kind == OCTMG_LSF_CYLINDER_Z ? 3 : 0);
+    const bool shape = d.lsf_kind >= OCTMG_LSF_SPHEROID && d.lsf_kind <= OCTMG_LSF_ASTROID;
+    int np = d.lsf_kind == OCTMG_LSF_SPHERES ? 4 * d.lsf_n
+                                             : (d.lsf_kind == OCTMG_LSF_CYLINDER_Z ? 3 : (shape ? 4 : 0));
     std::vector<double> p(np + 1, 0.0);
     if (np && d.lsf_params) std::memcpy(p.data(), d.lsf_params, np * sizeof(double));
     return p;
@@ -966,7 +970,7 @@ octmg_status octmg_state_set_fused_levels(octmg_state s, int max_blocks) {
 
 octmg_status octmg_state_set_launch(octmg_state s, const octmg_launch_config *c) {
     if (!s || !c) return fail(OCTMG_ERR_INVALID, "null argument");
-    if ((c->block_order != 0 && c->block_order != 1) || c->bottom_max_blocks < 0 || c->graph_mode < 0 ||
+    if (c->block_order < 0 || c->block_order > 2 || c->bottom_max_blocks < 0 || c->graph_mode < 0 ||
         c->graph_mode > 2 || (c->bottom_kind != 0 && c->bottom_kind != 1))
         return fail(OCTMG_ERR_INVALID, "bad launch configuration");
     if (c->bottom_kind == 1 && c->graph_mode != 0)
@@ -1380,7 +1384,7 @@ octmg_status octmg_autotune(octmg_state s, const octmg_solve_opts *o, int reps, 
                             octmg_launch_config *best, double *ms, int *n_candidates) {
     if (!s || !o || !best || reps < 1) return fail(OCTMG_ERR_INVALID, "bad argument");
     std::vector<octmg_launch_config> cand;
-    for (int order = 0; order < 2; order++) {
+    for (int order = 0; order < 3; order++) {
         cand.push_back({order, 0, 0, 0});
         cand.push_back({order, 0, 0, 1});
         if (s->geom->tree.D == 3) {

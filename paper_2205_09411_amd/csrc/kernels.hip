@@ -734,10 +734,35 @@ __device__ __forceinline__ int xcd_block() {
     return xcd * q + min(xcd, r) + slot;
 }
 
+// Order 2, for a complete level of nb^3 blocks (nb a power of two >= 2):
+// XCD x takes Morton octant x (an (nb/2)^3 cube, a contiguous index range)
+// and walks it x-fastest, so the face neighbours inside the octant are at
+// most (nb/2)^2 workgroups apart in its dispatch order and their halos are
+// read while still in that XCD's L2.  Block index = Morton code with x in
+// bit 0, y in bit 1, z in bit 2 of each triple (the tree's order).
+__device__ __forceinline__ int spread3(int v) {
+    int r = 0;
+#pragma unroll
+    for (int b = 0; b < 10; b++) r |= ((v >> b) & 1) << (3 * b);
+    return r;
+}
+__device__ __forceinline__ int octant_block(int nb) {
+    const int bid = blockIdx.x, xcd = bid & 7, slot = bid >> 3, h = nb >> 1;
+    const int i = slot % h, j = (slot / h) % h, k = slot / (h * h);
+    return xcd * h * h * h + (spread3(i) | (spread3(j) << 1) | (spread3(k) << 2));
+}
+
 // block of this workgroup: order 0 maps XCD-contiguous Morton ranges as
 // above, order 1 keeps the hardware order (consecutive blocks on
-// consecutive XCDs); the result of every block is the same either way
-__device__ __forceinline__ int block_of(int order) { return order ? (int)blockIdx.x : xcd_block(); }
+// consecutive XCDs), order 2 the octant walk (complete levels; otherwise
+// order 0); the result of every block is the same either way
+template <typename T>
+__device__ __forceinline__ int block_of(const LV<T> &L) {
+    if (L.order == 1) return (int)blockIdx.x;
+    if (L.order == 2 && L.nb >= 2 && (L.nb & (L.nb - 1)) == 0 && L.nblocks == L.nb * L.nb * L.nb)
+        return octant_block(L.nb);
+    return xcd_block();
+}
 
 // one colour of a block with halo: (N+2) x (N+2) x (N/2+2), index (k, j, h)
 template <int N>
@@ -976,7 +1001,7 @@ __global__ __launch_bounds__(256) void k_gs_half3(LV<T> L, LV<T> Lc, int color) 
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER;
     __shared__ T tile[ColTile<N>::SIZE];
-    gs_half3_body<T, N>(L, Lc, color, block_of(L.order), rhs_of(L), tile);
+    gs_half3_body<T, N>(L, Lc, color, block_of(L), rhs_of(L), tile);
 }
 
 // L phi at the PER cells of colour `col` owned by this thread, from the
@@ -1139,7 +1164,7 @@ __global__ __launch_bounds__(256) void k_restrict_fas3(LV<T> L, LV<T> Lc, int in
     constexpr int PER = Per<N>::PER, H = N / 2, NCELL = H * H * H, CPER = (NCELL + 255) / 256;
     constexpr int SM = ColTile<N>::SIZE > B::CPB ? ColTile<N>::SIZE : B::CPB;
     __shared__ T sm[SM];
-    restrict_fas3_body<T, N, NC>(L, Lc, into_old, block_of(L.order), rhs_of(L), sm);
+    restrict_fas3_body<T, N, NC>(L, Lc, into_old, block_of(L), rhs_of(L), sm);
 }
 
 // FAS rhs on parent blocks (g = L phi + g) and old = phi, 3D
@@ -1192,7 +1217,7 @@ __global__ __launch_bounds__(256) void k_fas_rhs3(LV<T> L, LV<T> Lc, int do_rhs)
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER;
     __shared__ T tile[ColTile<N>::SIZE];
-    fas_rhs3_body<T, N>(L, Lc, do_rhs, block_of(L.order), rhs_of(L), tile);
+    fas_rhs3_body<T, N>(L, Lc, do_rhs, block_of(L), rhs_of(L), tile);
 }
 
 // max |g - L phi| over a leaf block (3D); ZERO: residual of phi = 0
@@ -1200,7 +1225,7 @@ template <typename T, int N, bool ZERO>
 __global__ __launch_bounds__(256) void k_residual_max3(LV<T> L, LV<T> Lc, unsigned long long *out) {
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER;
-    const int blk = block_of(L.order);
+    const int blk = block_of(L);
     const int rhs = rhs_of(L);
     const int act = L.active ? L.active[rhs] : 1;
     const int leaf = L.leaf[blk];
@@ -1294,7 +1319,7 @@ __global__ __launch_bounds__(256) void k_prolong3(LV<T> L, LV<T> Lc, int solutio
     using B = Blk<3, N>;
     constexpr int H = N / 2, E = H + 2, ESZ = E * E * E, PER = B::CPB / 256;
     __shared__ T et[ESZ];
-    prolong3_body<T, N, NC>(L, Lc, solution, block_of(L.order), rhs_of(L), et);
+    prolong3_body<T, N, NC>(L, Lc, solution, block_of(L), rhs_of(L), et);
 }
 
 // mixed precision defect (FP64): g32 = g - L phi on a leaf block, phi32 = 0

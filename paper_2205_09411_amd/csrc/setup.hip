@@ -17,8 +17,51 @@
 namespace octmg {
 namespace {
 
+// cube root of a >= 0 from + - * / alone: powers of 8 bring a into
+// [1/8, 1), six Newton steps from 3/4 on t^3 = m, powers of 2 scale back
+__device__ double cbrt_ops(double a) {
+    if (!(a > 0.0)) return 0.0;
+    int k = 0;
+    double m = a;
+    while (m >= 1.0) {
+        m = m * 0.125;
+        ++k;
+    }
+    while (m < 0.125) {
+        m = m * 8.0;
+        --k;
+    }
+    double t = 0.75;
+    for (int it = 0; it < 6; ++it) t = (2.0 * t + m / (t * t)) / 3.0;
+    for (; k > 0; --k) t = t * 2.0;
+    for (; k < 0; ++k) t = t * 0.5;
+    return t;
+}
+
+// sharp shapes of Sec. 4.3 on the (p, q) plane; params [cx, cy, cz, s]
+__device__ double shape_dev(const SetupLevel &S, const double *x) {
+    const double *c = S.lsf_params;
+    double p, q;
+    if (S.D == 2) {
+        p = c[3] * (x[0] - c[0]);
+        q = c[3] * (x[1] - c[1]);
+    } else {
+        const double ex = x[0] - c[0], ey = x[1] - c[1];
+        p = c[3] * __dsqrt_rn(ex * ex + ey * ey);
+        q = c[3] * (x[2] - c[2]);
+    }
+    if (S.lsf_kind == OCTMG_LSF_SPHEROID) return __dsqrt_rn(8.0 * p * p + q * q) - 1.0;
+    if (S.lsf_kind == OCTMG_LSF_RHOMBUS) return 8.0 * fabs(p) + fabs(q) - 1.5;
+    if (S.lsf_kind == OCTMG_LSF_HEART) {
+        const double h = q - cbrt_ops(p * p);
+        return p * p + h * h - 1.0;
+    }
+    return cbrt_ops(p * p) / 0.8 + cbrt_ops(q * q) / 1.5 - 0.8;
+}
+
 __device__ double lsf_dev(const SetupLevel &S, const double *x) {
     const double *p = S.lsf_params;
+    if (S.lsf_kind >= OCTMG_LSF_SPHEROID && S.lsf_kind <= OCTMG_LSF_ASTROID) return shape_dev(S, x);
     if (S.lsf_kind == OCTMG_LSF_SPHERES) {
         double best = 0.0;
         for (int m = 0; m < S.lsf_n; m++) {

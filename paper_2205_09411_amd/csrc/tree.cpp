@@ -11,7 +11,48 @@
 
 namespace octmg {
 
+// cube root of a >= 0 with + - * / only (the device setup uses the same
+// steps, so refinement and interface decisions agree bit for bit)
+static double cbrt_ops_host(double a) {
+    if (!(a > 0.0)) return 0.0;
+    int k = 0;
+    double m = a;
+    while (m >= 1.0) {
+        m = m * 0.125;
+        ++k;
+    }
+    while (m < 0.125) {
+        m = m * 8.0;
+        --k;
+    }
+    double t = 0.75;
+    for (int it = 0; it < 6; ++it) t = (2.0 * t + m / (t * t)) / 3.0;
+    for (; k > 0; --k) t = t * 2.0;
+    for (; k < 0; ++k) t = t * 0.5;
+    return t;
+}
+
 double lsf_host(const octmg_geom_desc &d, const double *p, const double *x) {
+    if (d.lsf_kind >= OCTMG_LSF_SPHEROID && d.lsf_kind <= OCTMG_LSF_ASTROID) {
+        double a, b;
+        if (d.dim == 2) {
+            a = p[3] * (x[0] - p[0]);
+            b = p[3] * (x[1] - p[1]);
+        } else {
+            const double ex = x[0] - p[0], ey = x[1] - p[1];
+            a = p[3] * std::sqrt(ex * ex + ey * ey);
+            b = p[3] * (x[2] - p[2]);
+        }
+        switch (d.lsf_kind) {
+            case OCTMG_LSF_SPHEROID: return std::sqrt(8.0 * a * a + b * b) - 1.0;
+            case OCTMG_LSF_RHOMBUS: return 8.0 * std::fabs(a) + std::fabs(b) - 1.5;
+            case OCTMG_LSF_HEART: {
+                const double h = b - cbrt_ops_host(a * a);
+                return a * a + h * h - 1.0;
+            }
+            default: return cbrt_ops_host(a * a) / 0.8 + cbrt_ops_host(b * b) / 1.5 - 0.8;
+        }
+    }
     switch (d.lsf_kind) {
         case OCTMG_LSF_SPHERES: {
             double best = 0.0;
@@ -75,7 +116,7 @@ bool build_tree(const octmg_geom_desc &d, Tree *out, std::string *err) {
     if (lmax < 1 || lmax > 14) { *err = "max_level out of range"; return false; }
     if (d.lsf_kind == OCTMG_LSF_SPHERES && (d.lsf_n < 1 || !d.lsf_params)) { *err = "spheres need lsf_n >= 1 and params"; return false; }
     if (d.lsf_kind == OCTMG_LSF_CYLINDER_Z && !d.lsf_params) { *err = "cylinder needs params"; return false; }
-    if (d.lsf_kind < 0 || d.lsf_kind > 2) { *err = "unknown lsf_kind"; return false; }
+    if (d.lsf_kind < OCTMG_LSF_NONE || d.lsf_kind > OCTMG_LSF_ASTROID) { *err = "unknown lsf_kind"; return false; }
     if (d.refine_kind != OCTMG_REFINE_UNIFORM && d.refine_kind != OCTMG_REFINE_NEAR_INTERFACE) { *err = "unknown refine_kind"; return false; }
     if ((long)N << (lmax - 1) > (1L << 15)) { *err = "grid too large"; return false; }
 

@@ -292,7 +292,7 @@ class State:
         o = SolveOpts()
         o.cycle_kind, o.max_cycles, o.zero_start, o.rtol = kind, max_cycles, 1, rtol
         best = LaunchConfig()
-        ms = np.zeros(8)
+        ms = np.zeros(12)
         n = C.c_int()
         _check(lib().octmg_autotune(self._h, C.byref(o), reps, _stream_ptr(stream), C.byref(best),
                                     _ptr(ms, C.c_double), C.byref(n)))

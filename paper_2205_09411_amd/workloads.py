@@ -32,6 +32,10 @@ import numpy as np
 LSF_NONE = 0
 LSF_SPHERES = 1      # union of spheres/circles: params [cx, cy, cz, r] * n
 LSF_CYLINDER_Z = 2   # infinite cylinder along z: params [cx, cy, r]
+# the sharp shapes of Sec. 4.3, params [cx, cy, cz, s]: 2D p = s(x-cx),
+# q = s(y-cy); 3D p = s|(x-cx, y-cy)|, q = s(z-cz)
+LSF_SPHEROID, LSF_RHOMBUS, LSF_HEART, LSF_ASTROID = 3, 4, 5, 6
+SHAPES = {"spheroid": LSF_SPHEROID, "rhombus": LSF_RHOMBUS, "heart": LSF_HEART, "astroid": LSF_ASTROID}
 
 REFINE_UNIFORM = 0
 REFINE_NEAR_INTERFACE = 1
@@ -58,7 +62,7 @@ class Geometry:
     def lsf_n(self) -> int:
         if self.lsf_kind == LSF_SPHERES:
             return len(self.lsf_params) // 4
-        if self.lsf_kind == LSF_CYLINDER_Z:
+        if self.lsf_kind in (LSF_CYLINDER_Z, LSF_SPHEROID, LSF_RHOMBUS, LSF_HEART, LSF_ASTROID):
             return 1
         return 0
 
@@ -190,6 +194,17 @@ def sphere_f1(dim: int = 3, max_level: int = 4, R: float = 0.25, block_n: int = 
 
     return Workload(geom, lambda x: np.zeros(x.shape[0]), lambda x: np.full(x.shape[0], phi_b),
                     exact, exact=exact)
+
+
+def sharp_shape(shape: str, dim: int = 2, max_level: int = 4, block_n: int = 8) -> Workload:
+    """Sec. 4.3: Laplace equation on the unit square/cube, phi = 1 on the
+    shape's boundary, 0 on the domain boundary, uniform grid, w_min = 4e-3
+    (2D) or 8e-3 (3D); shapes centred at 0.5 with scale 4."""
+    geom = Geometry(dim=dim, block_n=block_n, max_level=max_level, lsf_kind=SHAPES[shape],
+                    lsf_params=np.array([0.5, 0.5, 0.5, 4.0]), w_min=4e-3 if dim == 2 else 8e-3,
+                    name=f"{shape}_{dim}d_{block_n * (1 << (max_level - 1))}")
+    return Workload(geom, lambda x: np.zeros(x.shape[0]), lambda x: np.ones(x.shape[0]),
+                    lambda x: np.zeros(x.shape[0]))
 
 
 def serving_geometries(seed0: int = 500, counts=(1, 5, 10, 20)):

@@ -37,6 +37,15 @@ GEOMS = {
     "spheres_amr": lambda: W.spheres(n_spheres=6, max_level=5, block_n=8, seed=9).geom,
     "spheres_amr16": lambda: W.spheres(n_spheres=20, max_level=5, block_n=16).geom,
     "cylinder": lambda: W.cylinder(max_level=3).geom,
+    # sharp shapes refined near the interface: the host refinement predicate
+    # evaluates the shape (with its + - * / cube root) like the checker
+    "heart_amr2d": lambda: W.Geometry(dim=2, block_n=8, max_level=5, lsf_kind=W.LSF_HEART,
+                                      lsf_params=np.array([0.5, 0.5, 0.5, 4.0]), refine_kind=W.REFINE_NEAR_INTERFACE,
+                                      refine_width=2.0 + np.sqrt(3) / 2, w_min=4e-3),
+    "astroid_amr3d": lambda: W.Geometry(dim=3, block_n=8, max_level=4, lsf_kind=W.LSF_ASTROID,
+                                        lsf_params=np.array([0.5, 0.5, 0.5, 4.0]),
+                                        refine_kind=W.REFINE_NEAR_INTERFACE, refine_width=2.0 + np.sqrt(3) / 2,
+                                        w_min=8e-3),
 }
 
 

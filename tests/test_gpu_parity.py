@@ -24,6 +24,11 @@ CONFIGS = {
     "spheres_amr": lambda: W.spheres(n_spheres=5, max_level=5, block_n=8, seed=9),
     "sphere_f1_3d": lambda: W.sphere_f1(dim=3, max_level=4),
     "spheres_amr16": lambda: W.spheres(n_spheres=8, max_level=5, block_n=16, seed=12),
+    # the sharp shapes of Sec. 4.3
+    "heart_2d": lambda: W.sharp_shape("heart", dim=2, max_level=4),
+    "astroid_2d": lambda: W.sharp_shape("astroid", dim=2, max_level=5),
+    "spheroid_3d": lambda: W.sharp_shape("spheroid", dim=3, max_level=3, block_n=16),
+    "rhombus_3d": lambda: W.sharp_shape("rhombus", dim=3, max_level=3, block_n=8),
 }
 
 

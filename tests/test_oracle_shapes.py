@@ -1,0 +1,158 @@
+"""Pins of the checker's sharp-shape level sets (Sec. 4.3, eqs. spheroid ..
+astroid): the cube root against numpy, interface roots against the shapes'
+closed forms, a dense sign scan, the 3D shapes as rotations of the 2D ones,
+and exactness of the discretisation for linear phi around the sharp
+boundaries."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2205_09411_amd import workloads as W
+
+S = 4.0  # coordinate scale of the shapes: p = 4 (x - 0.5), q = 4 (y - 0.5)
+
+
+def shape_geom(shape, dim=2, max_level=1, **kw):
+    return W.Geometry(dim=dim, block_n=8, max_level=max_level, lsf_kind=W.SHAPES[shape],
+                      lsf_params=np.array([0.5, 0.5, 0.5, S]), w_min=4e-3 if dim == 2 else 8e-3, **kw)
+
+
+def test_cube_root_to_an_ulp(orc):
+    rng = np.random.default_rng(1)
+    xs = np.concatenate([rng.random(2000) * 8.0, 10.0 ** rng.uniform(-12, 6, 2000), [1.0, 8.0, 0.125, 27.0]])
+    for a in xs:
+        ref = np.cbrt(a)
+        assert abs(orc.cbrt(a) - ref) <= 2.0 * np.spacing(ref), (a, orc.cbrt(a), ref)
+    assert orc.cbrt(0.0) == 0.0
+
+
+# closed-form interface points of each shape on a horizontal line q = q0
+# (p >= 0 branch), or for the heart on a vertical line p = p0 (upper branch)
+def p_root(shape, q0):
+    if shape == "spheroid":
+        return math.sqrt((1.0 - q0 * q0) / 8.0)
+    if shape == "rhombus":
+        return (1.5 - abs(q0)) / 8.0
+    if shape == "astroid":
+        return (0.8 * (0.8 - abs(q0) ** (2.0 / 3.0) / 1.5)) ** 1.5
+    raise ValueError(shape)
+
+
+@pytest.mark.parametrize("shape", ["spheroid", "rhombus", "astroid"])
+def test_horizontal_links_hit_closed_form_root(orc, shape):
+    """A bracketed horizontal link's d puts x0 on the shape (the closed-form
+    root of f(p, q0) = 0) within the bisection tolerance."""
+    g = shape_geom(shape)
+    rng = np.random.default_rng(2)
+    h = 1.0 / 64
+    checked = 0
+    for _ in range(200):
+        q0 = rng.uniform(-0.9, 0.9)
+        pr = p_root(shape, q0)
+        xr = 0.5 + pr / S
+        a = np.array([xr - rng.uniform(0.0, h), 0.5 + q0 / S, 0.0])
+        b = a + np.array([h, 0.0, 0.0])
+        t, found = orc.line_search(g, a, b)
+        assert found
+        assert abs(a[0] + t * h - xr) <= h * 2.0 ** -26, (shape, q0, a[0] + t * h, xr)
+        checked += 1
+    assert checked == 200
+
+
+def test_heart_vertical_links_hit_closed_form_root(orc):
+    g = shape_geom("heart")
+    rng = np.random.default_rng(3)
+    h = 1.0 / 64
+    for _ in range(200):
+        p0 = rng.uniform(-0.95, 0.95)
+        qr = np.cbrt(p0 * p0) + math.sqrt(1.0 - p0 * p0)  # upper branch of (q - |p|^(2/3))^2 = 1 - p^2
+        yr = 0.5 + qr / S
+        a = np.array([0.5 + p0 / S, yr - rng.uniform(0.0, h), 0.0])
+        b = a + np.array([0.0, h, 0.0])
+        t, found = orc.line_search(g, a, b)
+        assert found
+        assert abs(a[1] + t * h - yr) <= h * 2.0 ** -26
+
+
+def np_shape(shape, p, q):
+    if shape == "spheroid":
+        return np.sqrt(8 * p * p + q * q) - 1.0
+    if shape == "rhombus":
+        return 8 * np.abs(p) + np.abs(q) - 1.5
+    if shape == "heart":
+        return p * p + (q - np.cbrt(p * p)) ** 2 - 1.0
+    return np.cbrt(p * p) / 0.8 + np.cbrt(q * q) / 1.5 - 0.8
+
+
+@pytest.mark.parametrize("shape", sorted(W.SHAPES))
+def test_sign_scan_2d(orc, shape):
+    """Every link of a 32^2 grid with a sign change of the shape's f (dense
+    sampling with numpy's cube root) is cut, links where f keeps its sign are
+    not, and d is the first sign change."""
+    g = shape_geom(shape, max_level=3)  # 32^2 in 8^2 blocks
+    o = orc.Oracle(g)
+    il = o.n_levels - 1
+    ids, d, _ = o.records(il)
+    pos, _ = o.block_positions(il)
+    n, h, N = 32, 1.0 / 32, 8
+    rec = {}
+    for i3, dd in zip(ids, d):
+        blk, cell = int(i3[0]), int(i3[1])
+        bi, bj = pos[blk][0], pos[blk][1]
+        gi, gj = bi * N + cell % N, bj * N + cell // N
+        rec[(gi, gj)] = (int(i3[2]), dd)
+    ts = np.linspace(0.0, 1.0, 4001)
+    f = lambda pts: np_shape(shape, S * (pts[..., 0] - 0.5), S * (pts[..., 1] - 0.5))
+    cut_links = 0
+    for j in range(n):
+        for i in range(n):
+            a = np.array([(i + 0.5) * h, (j + 0.5) * h])
+            for k in range(4):
+                ax, s = k // 2, (1 if k & 1 else -1)
+                if not 0 <= (i, j)[ax] + s < n:
+                    continue
+                b = a.copy()
+                b[ax] += s * h
+                vals = f(a[None, :] + ts[:, None] * (b - a)[None, :])
+                sc = np.nonzero(vals[0] * vals[1:] <= 0)[0]
+                crosses = np.any(vals[0] * vals[1:] < 0)
+                r = rec.get((i, j))
+                if len(sc) == 0:
+                    assert r is None or not (r[0] >> k & 1), (shape, i, j, k)
+                elif not crosses:
+                    continue  # f only touches zero (a vertex on the link): either answer is valid
+                else:
+                    assert r is not None and (r[0] >> k & 1), (shape, i, j, k)
+                    assert abs(r[1][k] - ts[sc[0] + 1]) < 1e-3
+                    cut_links += 1
+    assert cut_links > 20
+
+
+@pytest.mark.parametrize("shape", sorted(W.SHAPES))
+def test_3d_shape_is_rotation_of_2d(orc, shape):
+    """3D: f(x, y, z) = f_2D(0.5 + r, z) with r the distance to the cube's
+    vertical axis (Sec. 4.3's cylindrical generalisation)."""
+    g2, g3 = shape_geom(shape, dim=2), shape_geom(shape, dim=3)
+    rng = np.random.default_rng(4)
+    for _ in range(300):
+        x = rng.random(3)
+        r = math.hypot(x[0] - 0.5, x[1] - 0.5)
+        v3 = orc.lsf_value(g3, x)
+        v2 = orc.lsf_value(g2, np.array([0.5 + r, x[2], 0.0]))
+        assert abs(v3 - v2) <= 1e-12 * max(1.0, abs(v2))
+        assert abs(v3 - np_shape(shape, S * r, S * (x[2] - 0.5))) <= 1e-12 * max(1.0, abs(v3))
+
+
+@pytest.mark.parametrize("shape", sorted(W.SHAPES))
+def test_linear_exact_around_sharp_boundary(orc, shape):
+    """Linear phi is reproduced to rounding with the shape's interface: every
+    cut-link stencil is exact for linear data, however sharp the boundary."""
+    lin = lambda x: 0.3 - 1.5 * x[:, 0] + 2.5 * x[:, 1]
+    o = orc.Oracle(shape_geom(shape, max_level=4))  # 64^2
+    o.set_boundary_fn(lin, lin)
+    xyz, _ = o.leaf_coords()
+    o.set_rhs(np.zeros(len(xyz)))
+    for _ in range(40):
+        o.vcycle()
+    assert np.abs(o.get_solution() - lin(xyz)).max() < 1e-11
