@@ -509,8 +509,17 @@ template <typename T, int D>
 __global__ __launch_bounds__(256) void k_coarse_solve(LV<T> L0, const double *M, const double *S) {
     if (inactive(L0)) return;
     constexpr int NB = 8, NCELL = D == 3 ? 512 : 64;
-    constexpr int ROWS_PER_WG = D == 3 ? 32 : 16;
+    constexpr int ROWS_PER_WG = D == 3 ? 8 : 16, RPW = ROWS_PER_WG / 4, CPL = NCELL / 64;
     __shared__ double rhs[NCELL];
+    // the wave's rows of the inverse do not depend on the rhs: their loads
+    // are issued first and complete while the rhs vector is formed
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    double mrow[RPW][CPL];
+#pragma unroll
+    for (int r = 0; r < RPW; r++)
+#pragma unroll
+        for (int c = 0; c < CPL; c++)
+            mrow[r][c] = M[(long long)(blockIdx.x * ROWS_PER_WG + wave + 4 * r) * NCELL + lane + 64 * c];
     const T *g = L0.g + (long long)rhs_of(L0) * L0.fstride;
     T *phi = L0.phi + (long long)rhs_of(L0) * L0.fstride;
     const int mo = L0.map_off ? L0.map_off[0] : -1;
@@ -534,11 +543,12 @@ __global__ __launch_bounds__(256) void k_coarse_solve(LV<T> L0, const double *M,
         rhs[c] = S[c] * r;
     }
     __syncthreads();
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    for (int row = blockIdx.x * ROWS_PER_WG + wave; row < min(NCELL, (int)(blockIdx.x + 1) * ROWS_PER_WG);
-         row += blockDim.x / 64) {
+#pragma unroll
+    for (int r = 0; r < RPW; r++) {
+        const int row = blockIdx.x * ROWS_PER_WG + wave + 4 * r;
         double acc = 0.0;
-        for (int c = lane; c < NCELL; c += 64) acc += M[(long long)row * NCELL + c] * rhs[c];
+#pragma unroll
+        for (int c = 0; c < CPL; c++) acc += mrow[r][c] * rhs[lane + 64 * c];
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
         if (lane == 0) {
             const int i = row % NB, j = (row / NB) % NB, k = D == 3 ? row / (NB * NB) : 0;
@@ -1614,7 +1624,7 @@ hipError_t launch_prolong(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc,
 template <typename T>
 hipError_t launch_coarse_solve(int D, const LV<T> &L0, const double *M, const double *S, int nrhs, hipStream_t s) {
     if (D == 3) {
-        hipLaunchKernelGGL((k_coarse_solve<T, 3>), dim3(512 / 32, nrhs), dim3(256), 0, s, L0, M, S);
+        hipLaunchKernelGGL((k_coarse_solve<T, 3>), dim3(512 / 8, nrhs), dim3(256), 0, s, L0, M, S);
     } else {
         hipLaunchKernelGGL((k_coarse_solve<T, 2>), dim3(64 / 16, nrhs), dim3(256), 0, s, L0, M, S);
     }
