@@ -371,6 +371,50 @@ def leg_sharp(stream, n_fmg=4, reps=5):
     return out
 
 
+def leg_electrodes(stream, n_fmg=4, reps=3):
+    """Sec. 4.4: rod (phi = 1) and half sphere (phi = 0) electrodes, phi = 1
+    on top, 0 at the bottom, zero flux on the sides; dx = 1/128 everywhere
+    and 1/512 near the electrodes (8^3 blocks): residual reduction per FMG
+    iteration (the paper: about 30-40), time per FMG and per solve to 1e-10
+    (FP64 and mixed), and the field |grad phi| by face differences."""
+    import torch
+    from paper_2205_09411_amd import octmg
+    from paper_2205_09411_amd import workloads as W
+    w = W.two_electrodes()
+    t = time.perf_counter()
+    G = octmg.Geometry(w.geom)
+    out = {"workload": "two electrodes, uniform 128^3 + refinement to 1/512 near the electrodes, 8^3 blocks, "
+                       "zero-flux sides", "setup_s": round(time.perf_counter() - t, 3), "leaf_cells": int(G.n_leaf),
+           "blocks": int(G.n_blocks), "levels": int(G.n_levels), "interface_records": int(G.n_records)}
+    S = octmg.State(G)
+    S.set_boundary_fn(w.iface_value, w.domain_value)
+    S.set_rhs(np.zeros(G.n_leaf))
+    r = [float(S.residual_norm(phi_zero=True)[0])]
+    for k in range(n_fmg):
+        S.fmg(have_guess=k > 0, stream=stream)
+        r.append(float(S.residual_norm(stream=stream)[0]))
+    out["reduction_per_fmg"] = [round(r[i] / r[i + 1], 1) for i in range(n_fmg)]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        S.fmg(have_guess=True, stream=stream)
+    torch.cuda.synchronize()
+    out["ms_per_fmg"] = round((time.perf_counter() - t) / reps * 1e3, 3)
+    t = time.perf_counter()
+    E = S.gradient(inside_zero=True, stream=stream)
+    out["gradient_s_incl_copy"] = round(time.perf_counter() - t, 3)
+    mag = np.linalg.norm(E, axis=1)
+    out["max_abs_grad_phi"] = round(float(mag.max()), 3)
+    for name, prec in (("fp64", octmg.FP64), ("mixed", octmg.MIXED)):
+        Sp = octmg.State(G, 1, prec)
+        Sp.set_boundary_fn(w.iface_value, w.domain_value)
+        Sp.set_rhs(np.zeros(G.n_leaf))
+        dt, rep = timed_solves(Sp, reps, stream, rtol=1e-10, max_cycles=40, graph_mode=1)
+        out[name] = {"ms_per_solve": round(dt * 1e3, 3), "cycles": rep.cycles, "final_rel_residual": rep.r_final / rep.r0}
+        del Sp
+    return out
+
+
 def leg_2d(stream, steps=20):
     """2D 64^2 in 8^2 blocks, circle r=0.25, manufactured solution, FP64,
     V(2,2) to 1e-10 (launch-bound at this size)."""
@@ -420,9 +464,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--block-order", type=int, default=None,
                     help="with --no-tune: block order of the 3D kernels (0 XCD ranges, 1 hardware, 2 octant walk)")
-    ap.add_argument("--legs", default="mixed,batched,adaptive,serving,table1,2d,sharp",
-                    help="extra measurements after the headline: mixed,batched,adaptive,serving,table1,2d,sharp "
-                         "or none")
+    ap.add_argument("--legs", default="mixed,batched,adaptive,serving,table1,2d,sharp,electrodes",
+                    help="extra measurements after the headline: mixed,batched,adaptive,serving,table1,2d,sharp,"
+                         "electrodes or none")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -546,6 +590,8 @@ def main():
                 legs[leg] = leg_2d(stream)
             elif leg == "sharp":
                 legs[leg] = leg_sharp(stream)
+            elif leg == "electrodes":
+                legs[leg] = leg_electrodes(stream)
             else:
                 raise ValueError(f"unknown leg {leg}")
         except Exception as e:  # a failed leg is reported, the headline stands

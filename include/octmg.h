@@ -64,7 +64,10 @@ enum { OCTMG_LSF_NONE = 0,       /* no interface */
        OCTMG_LSF_SPHEROID = 3,   /* sqrt(8 p^2 + q^2) - 1 */
        OCTMG_LSF_RHOMBUS = 4,    /* 8 |p| + |q| - 1.5 */
        OCTMG_LSF_HEART = 5,      /* p^2 + (q - |p|^(2/3))^2 - 1 */
-       OCTMG_LSF_ASTROID = 6     /* |p|^(2/3) / 0.8 + |q|^(2/3) / 1.5 - 0.8 */ };
+       OCTMG_LSF_ASTROID = 6,    /* |p|^(2/3) / 0.8 + |q|^(2/3) / 1.5 - 0.8 */
+       /* two electrodes (Sec. 4.4): min(dist(x, segment a-b) - r_rod,
+        * |x - c| - r_sph); params [ax,ay,az, bx,by,bz, r_rod, cx,cy,cz, r_sph] */
+       OCTMG_LSF_ELECTRODES = 7 };
 enum { OCTMG_REFINE_UNIFORM = 0, OCTMG_REFINE_NEAR_INTERFACE = 1 };
 enum { OCTMG_FP64 = 0, OCTMG_MIXED = 1 };
 enum { OCTMG_CYCLE_V = 0, OCTMG_CYCLE_FMG = 1 };
@@ -88,13 +91,20 @@ enum { OCTMG_STEP_HALF_SWEEP = 0,   /* arg = colour (0 red, 1 black) */
  * boundary-mask (1.5 in the paper); w_min the smallest width resolved on
  * coarse grids (Sec. 3.6.3; <= 0 disables); coarse_n the cells per edge of the
  * directly solved coarsest grid (8).  lsf_params is a host array read during
- * octmg_geom_create only. */
+ * octmg_geom_create only.
+ * neumann_faces: bit f set makes domain face f (x-, x+, y-, y+, z-, z+ =
+ * bits 0..5) a zero-flux face (ghost = the inside value), as on the sides of
+ * the two-electrode problem of Sec. 4.4; the others are Dirichlet (values
+ * from octmg_set_boundary).  At least one face or the interface must carry
+ * Dirichlet data.  uniform_level: levels up to this one are complete
+ * whatever refine_kind says (0: no such base). */
 typedef struct octmg_geom_desc {
     int dim, block_n, max_level, refine_kind;
-    int lsf_kind, lsf_n, coarse_n, reserved;
+    int lsf_kind, lsf_n, coarse_n, neumann_faces;
     double refine_width, eps_tol, mask_factor, w_min;
     double lo[3];
     const double *lsf_params;
+    int uniform_level, reserved;
 } octmg_geom_desc;
 
 typedef struct octmg_geom_s *octmg_geom;
@@ -213,6 +223,15 @@ octmg_status octmg_zero_solution(octmg_state s, void *stream);
  * precision one call is one outer defect-correction step around an FP32
  * cycle of that kind. */
 octmg_status octmg_cycle(octmg_state s, int kind, int have_guess, void *stream);
+/* Gradient of phi at every leaf cell centre (the field E = -grad phi of the
+ * application in Sec. 4.4): on each cell face the difference to the
+ * neighbour value or ghost over dx, or (phi_b - phi_i)/(d dx) across a cut
+ * link (d the stored relative distance, phi_b the interface value); each
+ * component is the mean of the cell's two faces.  inside_zero != 0: cells
+ * with a cut link whose centre lies inside the interface (f < 0) report 0.
+ * out[n_rhs][n_leaf][3] in canonical leaf order (host or device memory);
+ * synchronises the stream. */
+octmg_status octmg_gradient(octmg_state s, int inside_zero, double *out, int on_device, void *stream);
 /* Max-norm of r = g - L phi (eq. residual) over the leaf cells, per rhs,
  * into the host array out[n_rhs] (synchronises the stream). phi_zero != 0:
  * residual of phi = 0. */

@@ -35,10 +35,11 @@ def build(force: bool = True) -> str:
 class _Desc(C.Structure):
     _fields_ = [("dim", C.c_int), ("block_n", C.c_int), ("max_level", C.c_int),
                 ("refine_kind", C.c_int), ("lsf_kind", C.c_int), ("lsf_n", C.c_int),
-                ("coarse_n", C.c_int), ("n_down", C.c_int), ("n_up", C.c_int), ("pad_", C.c_int),
+                ("coarse_n", C.c_int), ("n_down", C.c_int), ("n_up", C.c_int), ("neumann", C.c_int),
                 ("refine_width", C.c_double), ("eps_tol", C.c_double),
                 ("mask_factor", C.c_double), ("w_min", C.c_double),
-                ("lo", C.c_double * 3), ("lsf_params", C.POINTER(C.c_double))]
+                ("lo", C.c_double * 3), ("lsf_params", C.POINTER(C.c_double)),
+                ("uniform_level", C.c_int), ("pad_", C.c_int)]
 
 
 _lib = None
@@ -88,6 +89,7 @@ def lib():
             "orc_line_search": (C.c_double, [C.POINTER(_Desc), dp, dp, ip]),
             "orc_lsf": (C.c_double, [C.POINTER(_Desc), dp]),
             "orc_cbrt": (C.c_double, [C.c_double]),
+            "orc_gradient": (None, [vp, dp, C.c_int]),
             "orc_coarse_search": (C.c_int, [C.POINTER(_Desc), dp, C.c_double, dp, ip, dp]),
         }
         for name, (res, args) in sig.items():
@@ -115,6 +117,8 @@ def make_desc(geom, n_down: int = 2, n_up: int = 2):
     d.coarse_n, d.n_down, d.n_up = geom.coarse_n, n_down, n_up
     d.refine_width, d.eps_tol = geom.refine_width, geom.eps_tol
     d.mask_factor, d.w_min = geom.mask_factor, geom.w_min
+    d.neumann = getattr(geom, "neumann_faces", 0)
+    d.uniform_level = getattr(geom, "uniform_level", 0)
     for i in range(3):
         d.lo[i] = geom.lo[i]
     d.lsf_params = _dp(params)
@@ -271,6 +275,13 @@ class Oracle:
 
     def residual_max(self, phi_zero: bool = False) -> float:
         return lib().orc_residual_max(self._h, int(phi_zero))
+
+    def gradient(self, inside_zero: bool = False) -> np.ndarray:
+        """grad phi at the leaf cell centres, [n_leaf][3] (face differences
+        using the interface distances, Sec. 4.4)."""
+        out = np.zeros((self.n_leaf, 3))
+        lib().orc_gradient(self._h, _dp(out), int(inside_zero))
+        return out
 
     def leaf_residual(self, phi) -> np.ndarray:
         a = np.ascontiguousarray(phi, dtype=np.float64)

@@ -60,6 +60,9 @@
  *     user rhs.  old = phi on the whole coarse level after restriction.
  *   * adaptive trees: after each cycle phi is restricted top-down onto
  *     parent cells, so that the composite residual is defined.
+ *   * zero-flux (Neumann) domain faces (Sec. 4.4): ghost = phi_inside;
+ *     prolonged corrections are mirrored without the sign flip; the coarse
+ *     operator folds the ghost into the diagonal.
  *   * sharp shapes (Sec. 4.3): p = 4 (x - 0.5), q = 4 (y - 0.5) (the
  *     printed division by 4 puts every shape outside the unit square); in
  *     3D p = 4 |(x, y) - (0.5, 0.5)|, q = 4 (z - 0.5) (rotation about the
@@ -80,11 +83,15 @@
 typedef struct {
     int dim, block_n, max_level, refine_kind;
     int lsf_kind, lsf_n, coarse_n, n_down;
-    int n_up, pad_;
+    int n_up, neumann;        /* neumann: bit f set = zero-flux domain face f (x-,x+,y-,y+,z-,z+) */
     double refine_width, eps_tol, mask_factor, w_min;
     double lo[3];
     const double *lsf_params;
+    int uniform_level, pad_;  /* levels <= uniform_level are complete (refinement) */
 } orc_desc;
+
+/* zero-flux (Neumann) domain face?  face = 2 axis + (side > 0) */
+static int is_neumann(const orc_desc *d, int ax, int s) { return (d->neumann >> (2 * ax + (s > 0))) & 1; }
 
 typedef struct {
     int blk, cell;  /* block index within the level, local cell index */
@@ -94,6 +101,8 @@ typedef struct {
     double b;       /* sum over cut links of c * phi_b (moved to the rhs) */
     int cut;        /* bitmask of cut links */
     long pt0;       /* first interface point of this record (level-local) */
+    int inside;     /* f(cell centre) < 0 */
+    double pb[6];   /* phi_b at the interface point of each cut link */
 } Rec;
 
 typedef struct {
@@ -168,9 +177,25 @@ static double shape_lsf(int kind, int D, const double *prm, const double *x) {
     }
 }
 
+/* Two electrodes (Sec. 4.4): a rod, the points within r_rod of the segment
+ * a-b, and a sphere; f = min(dist(x, [a, b]) - r_rod, |x - c| - r_sph).
+ * params [ax, ay, az, bx, by, bz, r_rod, cx, cy, cz, r_sph]. */
+static double electrodes_lsf(const double *q, const double *x) {
+    double ab[3], ax[3], t = 0.0, ll = 0.0, d2 = 0.0, s2 = 0.0;
+    for (int c = 0; c < 3; c++) { ab[c] = q[3 + c] - q[c]; ax[c] = x[c] - q[c]; t += ax[c] * ab[c]; ll += ab[c] * ab[c]; }
+    t = t / ll;
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    for (int c = 0; c < 3; c++) { double e = x[c] - (q[c] + t * ab[c]); d2 += e * e; }
+    for (int c = 0; c < 3; c++) { double e = x[c] - q[7 + c]; s2 += e * e; }
+    double rod = sqrt(d2) - q[6], sph = sqrt(s2) - q[10];
+    return rod < sph ? rod : sph;
+}
+
 /* level-set function (Sec. 3.1). Only + - * / sqrt and comparisons. */
 static double lsf(const Orc *o, const double *x) {
     const double *p = o->lsfp;
+    if (o->d.lsf_kind == 7) return electrodes_lsf(p, x);
     if (o->d.lsf_kind >= 3 && o->d.lsf_kind <= 6) return shape_lsf(o->d.lsf_kind, o->D, p, x);
     if (o->d.lsf_kind == 1) { /* union of spheres: min_m (|x - c_m| - r_m) */
         double f = 0.0;
@@ -398,7 +423,7 @@ static void build_levels(Orc *o) {
             if (!F.ex[l][i]) continue;
             int p[3] = {(int)(i % F.nb[l]), (int)((i / F.nb[l]) % F.nb[l]), D == 3 ? (int)(i / ((long)F.nb[l] * F.nb[l])) : 0};
             int refine = 1;
-            if (o->d.refine_kind == 1) {
+            if (o->d.refine_kind == 1 && l >= o->d.uniform_level) {
                 double w = 1.0 / (double)F.nb[l], x[3] = {0, 0, 0};
                 for (int a = 0; a < D; a++) x[a] = o->d.lo[a] + ((double)p[a] + 0.5) * w;
                 refine = fabs(lsf(o, x)) < o->d.refine_width * w;
@@ -548,6 +573,7 @@ static void setup_level(Orc *o, int il) {
             if (!R.cut) continue;
             R.blk = b;
             R.cell = (int)li;
+            R.inside = fa < 0.0;
             double dx2 = dx * dx;
             R.diag = 0.0;
             for (int ax = 0; ax < D; ax++) {
@@ -579,7 +605,8 @@ static double cf_ghost(const Orc *o, int il, const double *ff, const double *fc,
 
 /* value of the uncut neighbour of cell g in direction (ax, s) on level il for
    field f (coarse field fc for refinement boundaries), ghosts included.
-   Domain ghost: 2 phi_b(face centre) - phi_inside. */
+   Domain ghost: 2 phi_b(face centre) - phi_inside (Dirichlet), phi_inside
+   (zero flux). */
 static double nb_value(const Orc *o, int il, const double *f, const double *fc,
                        const int *g, long self, int ax, int s) {
     const Level *L = &o->L[il];
@@ -587,7 +614,7 @@ static double nb_value(const Orc *o, int il, const double *f, const double *fc,
     ng[ax] += s;
     long fl = flat_of(o, L, ng);
     if (fl >= 0) return f[fl];
-    if (fl == -2) return 2.0 * L->bcv[face_index(o, L, ax, s, g)] - f[self];
+    if (fl == -2) return is_neumann(&o->d, ax, s) ? f[self] : 2.0 * L->bcv[face_index(o, L, ax, s, g)] - f[self];
     return cf_ghost(o, il, f, fc, g, ax, s);
 }
 
@@ -598,7 +625,9 @@ static double coarse_val(const Orc *o, int ilc, const double *fc,
     const Level *Lc = &o->L[ilc];
     long fl = flat_of(o, Lc, q);
     if (fl >= 0) return fc[fl];
-    if (fl == -2) return 2.0 * Lc->bcv[face_index(o, Lc, t, s, qin)] - fc[flat_of(o, Lc, qin)];
+    if (fl == -2)
+        return is_neumann(&o->d, t, s) ? fc[flat_of(o, Lc, qin)]
+                                       : 2.0 * Lc->bcv[face_index(o, Lc, t, s, qin)] - fc[flat_of(o, Lc, qin)];
     fprintf(stderr, "oracle: coarse cell missing (2:1 balance violated)\n");
     abort();
 }
@@ -745,14 +774,15 @@ static void restrict_fas(Orc *o, int il) {
 }
 
 /* coarse correction e = phi_c - old_c at coarse cell q; outside the domain
-   the correction is reflected with a sign flip per outside axis */
+   the correction is reflected, with a sign flip per outside axis across a
+   Dirichlet face (homogeneous ghost -e) and none across a zero-flux face */
 static double corr_at(const Orc *o, int ilc, const int *q) {
     const Level *Lc = &o->L[ilc];
     int qq[3] = {q[0], q[1], q[2]};
     double sign = 1.0;
     for (int a = 0; a < o->D; a++) {
-        if (qq[a] < 0) { qq[a] = 0; sign = -sign; }
-        else if (qq[a] >= Lc->n) { qq[a] = Lc->n - 1; sign = -sign; }
+        if (qq[a] < 0) { qq[a] = 0; if (!is_neumann(&o->d, a, -1)) sign = -sign; }
+        else if (qq[a] >= Lc->n) { qq[a] = Lc->n - 1; if (!is_neumann(&o->d, a, 1)) sign = -sign; }
     }
     long fl = flat_of(o, Lc, qq);
     if (fl < 0) { fprintf(stderr, "oracle: prolongation source missing\n"); abort(); }
@@ -761,7 +791,8 @@ static double corr_at(const Orc *o, int ilc, const int *q) {
 
 /* coarse solution phi_c at coarse cell q with Dirichlet ghosts: across one
    face 2 phi_b - phi_in; at edges and corners linear extrapolation along the
-   first outside axis from two face-ghost values */
+   first outside axis from two face-ghost values.  Across a zero-flux face
+   (first outside axis) the value of the mirror cell. */
 static double sol_at(const Orc *o, int ilc, const int *q) {
     const Level *Lc = &o->L[ilc];
     int out = -1;
@@ -771,6 +802,11 @@ static double sol_at(const Orc *o, int ilc, const int *q) {
     int nout = 0;
     for (int a = 0; a < o->D; a++) nout += (q[a] < 0 || q[a] >= Lc->n);
     int s = q[out] < 0 ? -1 : 1;
+    if (is_neumann(&o->d, out, s)) {  /* zero flux: the mirror image inside */
+        int qi[3] = {q[0], q[1], q[2]};
+        qi[out] -= s;
+        return sol_at(o, ilc, qi);
+    }
     if (nout == 1) {
         int qi[3] = {q[0], q[1], q[2]};
         qi[out] -= s;
@@ -837,6 +873,7 @@ static void coarse_solve(Orc *o) {
                 ng[ax] += s;
                 long j = flat_of(o, L, ng);
                 if (j >= 0) A[i * n + j] += c;
+                else if (is_neumann(&o->d, ax, s)) A[i * n + i] += c;  /* ghost = phi_i */
                 else {
                     A[i * n + i] -= c;
                     rhs[i] -= 2.0 * c * L->bcv[face_index(o, L, ax, s, g)];
@@ -933,7 +970,8 @@ void *orc_create(const orc_desc *d) {
     Orc *o = xcalloc(1, sizeof(Orc));
     o->d = *d;
     o->D = d->dim;
-    int np = d->lsf_kind == 1 ? 4 * d->lsf_n : (d->lsf_kind == 2 ? 3 : (d->lsf_kind >= 3 && d->lsf_kind <= 6 ? 4 : 0));
+    int np = d->lsf_kind == 1 ? 4 * d->lsf_n
+             : (d->lsf_kind == 2 ? 3 : (d->lsf_kind >= 3 && d->lsf_kind <= 6 ? 4 : (d->lsf_kind == 7 ? 11 : 0)));
     o->lsfp = xcalloc(np + 1, sizeof(double));
     if (np) memcpy(o->lsfp, d->lsf_params, np * sizeof(double));
     o->d.lsf_params = o->lsfp;
@@ -1080,7 +1118,9 @@ void orc_set_boundary(void *h, const double *iface, const double *dom) {
             double b = 0.0;
             long p = pi + R->pt0;
             for (int k = 0; k < 2 * o->D; k++) {
+                R->pb[k] = 0.0;
                 if (!(R->cut >> k & 1)) continue;
+                R->pb[k] = iface[p];
                 b = b + R->c[k] * iface[p++];
             }
             R->b = b;
@@ -1194,6 +1234,45 @@ double orc_residual_max(void *h, int phi_zero) {
 }
 
 /* composite residual for a given leaf vector (dense-assembly probing) */
+/* Gradient of phi at every leaf cell centre (Sec. 4.4): the derivative on
+ * each cell face is (phi_nb - phi_i)/dx with the neighbour's value or ghost,
+ * or (phi_b - phi_i)/(d dx) towards a boundary between the cells (taken on
+ * the side of the cut link); each component is the mean of its two faces.
+ * inside_zero: cells with a cut link whose centre is inside (f < 0) get 0.
+ * out[n_leaf][3] in canonical leaf order. */
+void orc_gradient(void *h, double *out, int inside_zero) {
+    Orc *o = h;
+    sync_down(o);
+    long n = 0;
+    for (int il = 0; il < o->nlev; il++) {
+        Level *L = &o->L[il];
+        const double *fc = coarse_phi(o, il);
+        for (int b = 0; b < L->nblocks; b++) {
+            if (!L->leaf[b]) continue;
+            for (long li = 0; li < L->cpb; li++, n++) {
+                long fl = (long)b * L->cpb + li;
+                int g[3];
+                cell_g(o, L, b, li, g);
+                const Rec *R = L->rec_of[fl] >= 0 ? &L->rec[L->rec_of[fl]] : NULL;
+                double phi = L->phi[fl];
+                for (int c = 0; c < 3; c++) out[3 * n + c] = 0.0;
+                if (inside_zero && R && R->inside) continue;
+                for (int ax = 0; ax < o->D; ax++) {
+                    double face[2];
+                    for (int side = 0; side < 2; side++) {
+                        int k = 2 * ax + side, s = side ? 1 : -1;
+                        double dv;
+                        if (R && (R->cut >> k & 1)) dv = (R->pb[k] - phi) / (R->d[k] * L->dx);
+                        else dv = (nb_value(o, il, L->phi, fc, g, fl, ax, s) - phi) / L->dx;
+                        face[side] = s * dv;  /* derivative along +axis on that face */
+                    }
+                    out[3 * n + ax] = 0.5 * (face[0] + face[1]);
+                }
+            }
+        }
+    }
+}
+
 void orc_leaf_residual(void *h, const double *phi_leaf, double *r_leaf) {
     Orc *o = h;
     orc_set_solution(o, phi_leaf);

@@ -71,7 +71,7 @@ struct GeomLevel {
     long long npts = 0, pt_base = 0;
     int4 *d_pos = nullptr, *d_nbr = nullptr;
     int *d_lut = nullptr, *d_leaf = nullptr, *d_map_off = nullptr, *d_map = nullptr;
-    int *d_leaf_blocks = nullptr, *d_meta = nullptr;
+    int *d_leaf_blocks = nullptr, *d_meta = nullptr, *d_inside = nullptr;
     double *d_rec8 = nullptr, *d_d6 = nullptr, *d_cfull = nullptr, *d_pts = nullptr;
     float *d_rec8f = nullptr;
 };
@@ -94,6 +94,7 @@ namespace {
 
 struct Fields64 {
     double *phi = nullptr, *g = nullptr, *old = nullptr, *b = nullptr, *bcv = nullptr;
+    double *pb = nullptr;  // phi_b at the level's interface points (for the gradient)
 };
 struct Fields32 {
     float *phi = nullptr, *g = nullptr, *old = nullptr;
@@ -200,6 +201,7 @@ LV<double> lv64(const octmg_state_s *s, int il) {
     v.active = s->d_active;
     v.lanes = s->n_launch < s->nrhs ? s->d_active + s->nrhs : nullptr;
     v.order = s->block_order;
+    v.neumann = s->geom->desc.neumann_faces;
     return v;
 }
 
@@ -229,6 +231,7 @@ LV<float> lv32(const octmg_state_s *s, int il) {
     v.active = s->d_active;
     v.lanes = s->n_launch < s->nrhs ? s->d_active + s->nrhs : nullptr;
     v.order = s->block_order;
+    v.neumann = s->geom->desc.neumann_faces;
     return v;
 }
 
@@ -482,17 +485,25 @@ octmg_status validate_desc(const octmg_geom_desc *d) {
     if (!d) return fail(OCTMG_ERR_INVALID, "null descriptor");
     if (!(d->eps_tol > 0.0 && d->eps_tol < 0.5)) return fail(OCTMG_ERR_INVALID, "eps_tol must be in (0, 0.5)");
     if (!(d->mask_factor > 0.0)) return fail(OCTMG_ERR_INVALID, "mask_factor must be > 0");
-    if (d->lsf_kind < OCTMG_LSF_NONE || d->lsf_kind > OCTMG_LSF_ASTROID) return fail(OCTMG_ERR_INVALID, "unknown lsf_kind");
+    if (d->lsf_kind < OCTMG_LSF_NONE || d->lsf_kind > OCTMG_LSF_ELECTRODES) return fail(OCTMG_ERR_INVALID, "unknown lsf_kind");
     if (d->lsf_kind == OCTMG_LSF_SPHERES && (d->lsf_n < 1 || d->lsf_n > 100000))
         return fail(OCTMG_ERR_INVALID, "lsf_n out of range");
     if (d->lsf_kind != OCTMG_LSF_NONE && !d->lsf_params) return fail(OCTMG_ERR_INVALID, "lsf_params is null");
+    if (d->neumann_faces < 0 || d->neumann_faces >= (1 << (2 * d->dim)))
+        return fail(OCTMG_ERR_INVALID, "neumann_faces has bits beyond the 2D faces");
+    if (d->neumann_faces == (1 << (2 * d->dim)) - 1 && d->lsf_kind == OCTMG_LSF_NONE)
+        return fail(OCTMG_ERR_INVALID, "all faces zero-flux without an interface: the operator is singular");
+    if (d->uniform_level < 0 || d->uniform_level > d->max_level) return fail(OCTMG_ERR_INVALID, "bad uniform_level");
     return OCTMG_OK;
 }
 
 std::vector<double> copy_params(const octmg_geom_desc &d) {
     const bool shape = d.lsf_kind >= OCTMG_LSF_SPHEROID && d.lsf_kind <= OCTMG_LSF_ASTROID;
-    int np = d.lsf_kind == OCTMG_LSF_SPHERES ? 4 * d.lsf_n
-                                             : (d.lsf_kind == OCTMG_LSF_CYLINDER_Z ? 3 : (shape ? 4 : 0));
+    int np = d.lsf_kind == OCTMG_LSF_SPHERES      ? 4 * d.lsf_n
+             : d.lsf_kind == OCTMG_LSF_CYLINDER_Z   ? 3
+             : d.lsf_kind == OCTMG_LSF_ELECTRODES   ? 11
+             : shape                                ? 4
+                                                    : 0;
     std::vector<double> p(np + 1, 0.0);
     if (np && d.lsf_params) std::memcpy(p.data(), d.lsf_params, np * sizeof(double));
     return p;
@@ -675,8 +686,9 @@ octmg_status octmg_geom_create(const octmg_geom_desc *d, int hip_device, octmg_g
             HIPCK(G->pool.alloc(&L.d_rec8, (size_t)8 * nrec));
             HIPCK(G->pool.alloc(&L.d_rec8f, (size_t)8 * nrec));
             HIPCK(G->pool.alloc(&L.d_pts, (size_t)3 * std::max<long long>(1, npt)));
+            HIPCK(G->pool.alloc(&L.d_inside, (size_t)nrec));
             HIPCK(launch_setup_emit(S, d_roff, d_poff, L.d_map_off, L.d_map, L.d_meta, L.d_d6, L.d_cfull, L.d_rec8,
-                                    L.d_rec8f, L.d_pts, nullptr));
+                                    L.d_rec8f, L.d_pts, L.d_inside, nullptr));
             HIPCK(hipDeviceSynchronize());
         }
         G->n_rec += nrec;
@@ -702,7 +714,8 @@ octmg_status octmg_geom_create(const octmg_geom_desc *d, int hip_device, octmg_g
         HIPCK(G->pool.alloc(&G->d_S, (size_t)n0));
         int mo = -1;
         HIPCK(hipMemcpy(&mo, L0.d_map_off, sizeof(int), hipMemcpyDeviceToHost));
-        HIPCK(launch_coarse_assemble(D, L0.Nb, L0.dx, mo >= 0 ? L0.d_map + mo : nullptr, L0.d_rec8, d_A, nullptr));
+        HIPCK(launch_coarse_assemble(D, L0.Nb, L0.dx, mo >= 0 ? L0.d_map + mo : nullptr, L0.d_rec8,
+                                     G->desc.neumann_faces, d_A, nullptr));
         HIPCK(launch_gauss_jordan(n0, d_A, G->d_M, G->d_S, d_fail, nullptr));
         int hf = 0;
         HIPCK(hipMemcpy(&hf, d_fail, sizeof(int), hipMemcpyDeviceToHost));
@@ -865,6 +878,8 @@ octmg_status octmg_state_create(octmg_geom g, int n_rhs, int precision, octmg_st
         HIPCK(s->pool.alloc(&F.old, n));
         HIPCK(s->pool.alloc(&F.b, std::max(1, L.nrec)));
         HIPCK(s->pool.alloc(&F.bcv, (size_t)2 * D * L.nface));
+        HIPCK(s->pool.alloc(&F.pb, (size_t)std::max<long long>(1, L.npts)));
+        HIPCK(launch_fill(F.pb, std::max<long long>(1, L.npts), 0.0, nullptr));
         HIPCK(launch_fill(F.phi, n, 0.0, nullptr));
         HIPCK(launch_fill(F.g, n, 0.0, nullptr));
         HIPCK(launch_fill(F.old, n, 0.0, nullptr));
@@ -1036,6 +1051,10 @@ octmg_status octmg_set_boundary(octmg_state s, const double *iface_vals, const d
         Fields64 &F = s->f64[il];
         HIPCK(launch_boundary_terms(D, L.d_meta, L.d_cfull, L.nrec, dv_iface ? dv_iface + L.pt_base : nullptr, F.b,
                                     nullptr, st));
+        if (L.npts) {
+            if (dv_iface) HIPCK(hipMemcpyAsync(F.pb, dv_iface + L.pt_base, L.npts * sizeof(double), hipMemcpyDeviceToDevice, st));
+            else HIPCK(launch_fill(F.pb, L.npts, 0.0, st));
+        }
         const long long nf = 2LL * D * L.nface;
         if (dv_dom) HIPCK(hipMemcpyAsync(F.bcv, dv_dom + dom_off, nf * sizeof(double), hipMemcpyDeviceToDevice, st));
         else HIPCK(launch_fill(F.bcv, nf, 0.0, st));
@@ -1088,6 +1107,29 @@ octmg_status octmg_get_solution(octmg_state s, double *phi, int on_device, void 
                                  L.leaf_base, s->nrhs, st));
     }
     if (!on_device) HIPCK(hipMemcpyAsync(phi, dv, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    return OCTMG_OK;
+}
+
+octmg_status octmg_gradient(octmg_state s, int inside_zero, double *out, int on_device, void *stream) {
+    if (!s || !out) return fail(OCTMG_ERR_INVALID, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    octmg_geom g = s->geom;
+    HIPCK(hipSetDevice(g->device));
+    Engine<double> e{s, st};
+    STCK(e.sync_down());  // coarse copies of leaf values for refinement-boundary ghosts
+    const size_t n = (size_t)3 * g->n_leaf * s->nrhs;
+    DevPool tmp;
+    double *dv = out;
+    if (!on_device) HIPCK(tmp.alloc(&dv, n));
+    for (size_t il = 0; il < g->L.size(); il++) {
+        const GeomLevel &L = g->L[il];
+        LV<double> v = lv64(s, (int)il), vc = lv64(s, (int)il - 1);
+        v.lanes = vc.lanes = nullptr;  // every rhs, grid y = rhs
+        HIPCK(launch_gradient(g->tree.D, L.Nb, v, vc, L.d_leaf_blocks, L.nleaf, L.d_meta, L.d_d6, L.d_inside,
+                              s->f64[il].pb, inside_zero, dv, 3LL * g->n_leaf, L.leaf_base, s->nrhs, st));
+    }
+    if (!on_device) HIPCK(hipMemcpyAsync(out, dv, n * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
     return OCTMG_OK;
 }

@@ -40,6 +40,10 @@ __device__ __forceinline__ int block_at(const LV<T> &L, int bx, int by, int bz) 
     return L.lut[D == 3 ? (bz * L.nb + by) * L.nb + bx : by * L.nb + bx];
 }
 
+// zero-flux (Neumann) domain face of axis ax, side s: the ghost is the
+// inside value (mirror); otherwise Dirichlet, ghost 2 phi_b - inside
+__device__ __forceinline__ bool zero_flux(int mask, int ax, int s) { return (mask >> (2 * ax + (s > 0))) & 1; }
+
 template <int D>
 __device__ __forceinline__ int face_slot(int ax, int s, int gi, int gj, int gk, int n, int nface) {
     int t;
@@ -74,13 +78,13 @@ __device__ __forceinline__ T cf_ghost(const LV<T> &Lc, const T *phic, int gi, in
         T cp, cm;
         if (P[t] >= Lc.n) {
             T bv = Lc.bcv ? Lc.bcv[face_slot<D>(t, 1, C[0], C[1], C[2], Lc.n, Lc.nface)] : T(0);
-            cp = T(2) * bv - Cv;
+            cp = zero_flux(Lc.neumann, t, 1) ? Cv : T(2) * bv - Cv;
         } else {
             cp = level_value<T, D, N>(Lc, phic, P[0], P[1], P[2]);
         }
         if (M[t] < 0) {
             T bv = Lc.bcv ? Lc.bcv[face_slot<D>(t, -1, C[0], C[1], C[2], Lc.n, Lc.nface)] : T(0);
-            cm = T(2) * bv - Cv;
+            cm = zero_flux(Lc.neumann, t, -1) ? Cv : T(2) * bv - Cv;
         } else {
             cm = level_value<T, D, N>(Lc, phic, M[0], M[1], M[2]);
         }
@@ -105,7 +109,7 @@ __device__ __forceinline__ void gather(const LV<T> &L, const LV<T> &Lc, const T 
             v[d] = T(0);
             if (c[ax] < 0 || c[ax] >= N) {
                 const int nbk = snb[d];
-                if (nbk == -2) {
+                if (nbk == -2 && !zero_flux(L.neumann, ax, s)) {
                     const int gi = P.x * N + i, gj = P.y * N + j, gk = D == 3 ? P.z * N + k : 0;
                     v[d] = L.bcv ? T(2) * L.bcv[face_slot<D>(ax, s, gi, gj, gk, L.n, L.nface)] : T(0);
                 }
@@ -122,7 +126,7 @@ __device__ __forceinline__ void gather(const LV<T> &L, const LV<T> &Lc, const T 
             } else if (nbk == -2) {
                 const int gi = P.x * N + i, gj = P.y * N + j, gk = D == 3 ? P.z * N + k : 0;
                 const T bv = L.bcv ? L.bcv[face_slot<D>(ax, s, gi, gj, gk, L.n, L.nface)] : T(0);
-                v[d] = T(2) * bv - own;
+                v[d] = zero_flux(L.neumann, ax, s) ? own : T(2) * bv - own;
             } else {
                 pending |= 1 << d;
                 v[d] = T(0);
@@ -376,83 +380,58 @@ __global__ __launch_bounds__((Blk<D, N>::THREADS)) void k_fas_rhs(LV<T> L, LV<T>
 // e_c = phi_c - old_c (Sec. 2.2, 3.4); outside the domain e_c is reflected
 // with a sign flip per axis.  Solution mode (first FMG without guess): e_c =
 // phi_c with Dirichlet ghosts, linear extrapolation at edges/corners.
-template <typename T, int D, int NC>
-__device__ T coarse_e(const LV<T> &Lc, const T *phic, const T *oldc, int x0, int x1, int x2, int solution) {
-    int q[3] = {x0, x1, x2};
+// Coarse solution value at coarse cell q for the first interpolation of a
+// nested iteration, with ghosts outside the domain: across the first
+// outside axis the mirror cell (zero-flux face), else 2 phi_b - inside when
+// only that axis is outside, else linear extrapolation 2 v(q - s e) -
+// v(q - 2 s e).  Each step brings one axis inside, so DEPTH = D + 1 levels
+// of expansion always suffice.
+template <typename T, int D, int NC, int DEPTH>
+__device__ __forceinline__ T coarse_sol(const LV<T> &Lc, const T *phic, int q0, int q1, int q2) {
+    const int q[3] = {q0, q1, q2};
     int out = -1, nout = 0;
     for (int a = 0; a < D; a++)
         if (q[a] < 0 || q[a] >= Lc.n) {
             nout++;
             if (out < 0) out = a;
         }
-    if (!solution) {
-        T sign = T(1);
-        for (int a = 0; a < D; a++) {
-            if (q[a] < 0) { q[a] = 0; sign = -sign; }
-            else if (q[a] >= Lc.n) { q[a] = Lc.n - 1; sign = -sign; }
-        }
-        const int b = block_at<T, D>(Lc, q[0] / NC, q[1] / NC, D == 3 ? q[2] / NC : 0);
-        if (b < 0) return T(0);
-        const long long o = (long long)b * Blk<D, NC>::CPB + split_of<D, NC>(q[0] % NC, q[1] % NC, D == 3 ? q[2] % NC : 0);
-        return sign * (phic[o] - oldc[o]);
-    }
-    if (nout == 0) return level_value<T, D, NC>(Lc, phic, q[0], q[1], q[2]);
-    // solution mode: extrapolate along the first outside axis until one face
-    // ghost remains: value(q) = 2 value(q - s e) - value(q - 2 s e)
+    if (nout == 0 || DEPTH == 0) return level_value<T, D, NC>(Lc, phic, q[0], q[1], q[2]);
     const int s = q[out] < 0 ? -1 : 1;
+    int a1[3] = {q[0], q[1], q[2]};
+    a1[out] -= s;
+    if (zero_flux(Lc.neumann, out, s)) return coarse_sol<T, D, NC, (DEPTH > 0 ? DEPTH - 1 : 0)>(Lc, phic, a1[0], a1[1], a1[2]);
     if (nout == 1) {
-        int qi[3] = {q[0], q[1], q[2]};
-        qi[out] -= s;
-        const T bv = Lc.bcv ? Lc.bcv[face_slot<D>(out, s, qi[0], qi[1], qi[2], Lc.n, Lc.nface)] : T(0);
-        return T(2) * bv - level_value<T, D, NC>(Lc, phic, qi[0], qi[1], qi[2]);
+        const T bv = Lc.bcv ? Lc.bcv[face_slot<D>(out, s, a1[0], a1[1], a1[2], Lc.n, Lc.nface)] : T(0);
+        return T(2) * bv - level_value<T, D, NC>(Lc, phic, a1[0], a1[1], a1[2]);
     }
-    // nout >= 2: both shifted points remain outside in the other axes
-    T acc = T(0);
-    // expand 2 v(q1) - v(q2) with v evaluated recursively (depth <= 2 more)
-    int q1[3] = {q[0], q[1], q[2]}, q2[3] = {q[0], q[1], q[2]};
-    q1[out] -= s;
-    q2[out] -= 2 * s;
-    T v1, v2;
-    {
-        // second outside axis
-        int o2 = -1, n2 = 0;
-        for (int a = 0; a < D; a++)
-            if (q1[a] < 0 || q1[a] >= Lc.n) {
-                n2++;
-                if (o2 < 0) o2 = a;
-            }
-        auto face1 = [&](const int *p, int ax) -> T {
-            const int ss = p[ax] < 0 ? -1 : 1;
-            int pi[3] = {p[0], p[1], p[2]};
-            pi[ax] -= ss;
-            const T bv = Lc.bcv ? Lc.bcv[face_slot<D>(ax, ss, pi[0], pi[1], pi[2], Lc.n, Lc.nface)] : T(0);
-            return T(2) * bv - level_value<T, D, NC>(Lc, phic, pi[0], pi[1], pi[2]);
-        };
-        auto eval = [&](const int *p) -> T {
-            int oo = -1, nn = 0;
-            for (int a = 0; a < D; a++)
-                if (p[a] < 0 || p[a] >= Lc.n) {
-                    nn++;
-                    if (oo < 0) oo = a;
-                }
-            if (nn == 1) return face1(p, oo);
-            // nn == 2 (3D corner after one shift)
-            const int ss = p[oo] < 0 ? -1 : 1;
-            int p1[3] = {p[0], p[1], p[2]}, p2[3] = {p[0], p[1], p[2]};
-            p1[oo] -= ss;
-            p2[oo] -= 2 * ss;
-            int o3 = -1;
-            for (int a = 0; a < D; a++)
-                if (p1[a] < 0 || p1[a] >= Lc.n) { o3 = a; break; }
-            return T(2) * face1(p1, o3) - face1(p2, o3);
-        };
-        (void)n2;
-        (void)o2;
-        v1 = eval(q1);
-        v2 = eval(q2);
+    int a2[3] = {q[0], q[1], q[2]};
+    a2[out] -= 2 * s;
+    return T(2) * coarse_sol<T, D, NC, (DEPTH > 0 ? DEPTH - 1 : 0)>(Lc, phic, a1[0], a1[1], a1[2]) -
+           coarse_sol<T, D, NC, (DEPTH > 0 ? DEPTH - 1 : 0)>(Lc, phic, a2[0], a2[1], a2[2]);
+}
+
+// Coarse correction e = phi_c - old_c at coarse cell q for the
+// prolongation; outside the domain it is mirrored, with a sign flip per
+// Dirichlet axis (homogeneous ghost -e) and none per zero-flux axis.  In
+// solution mode the coarse solution with its ghosts (coarse_sol).
+template <typename T, int D, int NC, bool SOL>
+__device__ __forceinline__ T coarse_e(const LV<T> &Lc, const T *phic, const T *oldc, int x0, int x1, int x2) {
+    if (SOL) return coarse_sol<T, D, NC, D + 1>(Lc, phic, x0, x1, x2);
+    int q[3] = {x0, x1, x2};
+    T sign = T(1);
+    for (int a = 0; a < D; a++) {
+        if (q[a] < 0) {
+            q[a] = 0;
+            if (!zero_flux(Lc.neumann, a, -1)) sign = -sign;
+        } else if (q[a] >= Lc.n) {
+            q[a] = Lc.n - 1;
+            if (!zero_flux(Lc.neumann, a, 1)) sign = -sign;
+        }
     }
-    acc = T(2) * v1 - v2;
-    return acc;
+    const int b = block_at<T, D>(Lc, q[0] / NC, q[1] / NC, D == 3 ? q[2] / NC : 0);
+    if (b < 0) return T(0);
+    const long long o = (long long)b * Blk<D, NC>::CPB + split_of<D, NC>(q[0] % NC, q[1] % NC, D == 3 ? q[2] % NC : 0);
+    return sign * (phic[o] - oldc[o]);
 }
 
 template <typename T, int D, int N, int NC>
@@ -477,7 +456,8 @@ __global__ __launch_bounds__(256) void k_prolong(LV<T> L, LV<T> Lc, int solution
 #pragma unroll
                 for (int x = 0; x < 3; x++)
                     E[(z * 3 + y) * 3 + x] =
-                        coarse_e<T, D, NC>(Lc, phic, oldc, G[0] + x - 1, G[1] + y - 1, D == 3 ? G[2] + z - 1 : 0, solution);
+                        solution ? coarse_e<T, D, NC, true>(Lc, phic, oldc, G[0] + x - 1, G[1] + y - 1, D == 3 ? G[2] + z - 1 : 0)
+                                 : coarse_e<T, D, NC, false>(Lc, phic, oldc, G[0] + x - 1, G[1] + y - 1, D == 3 ? G[2] + z - 1 : 0);
 #pragma unroll
         for (int ch = 0; ch < (1 << D); ch++) {
             const int a = ch & 1, bb = (ch >> 1) & 1, cc = (ch >> 2) & 1;
@@ -536,7 +516,7 @@ __global__ __launch_bounds__(256) void k_coarse_solve(LV<T> L0, const double *M,
             q[ax] += s;
             if (q[ax] >= 0 && q[ax] < NB) continue;
             const double cc = ri >= 0 ? (double)L0.rec[8 * (long long)ri + d] : inv;
-            if (cc == 0.0) continue;
+            if (cc == 0.0 || zero_flux(L0.neumann, ax, s)) continue;  // zero flux: folded into the operator
             const double bv = L0.bcv ? (double)L0.bcv[face_slot<D>(ax, s, i, j, k, NB, L0.nface)] : 0.0;
             r -= 2.0 * cc * bv;
         }
@@ -615,6 +595,55 @@ __global__ void k_gather_leaf(LV<double> L, const int *lb, double *dst, long lon
     for (int c = threadIdx.x; c < B::CPB; c += blockDim.x) {
         const int i = c % N, j = (c / N) % N, k = D == 3 ? c / (N * N) : 0;
         d[c] = src[split_of<D, N>(i, j, k)];
+    }
+}
+
+// grad phi of the leaf cells of one level (Sec. 4.4, the application's
+// field): on every face the difference to the neighbour value or ghost over
+// dx, or (phi_b - phi_i)/(d dx) towards a boundary on that link; each
+// component is the mean of its two faces.  Post-processing, run once per
+// solution: one thread per cell, no LDS staging.
+template <int D, int N>
+__global__ void k_gradient(LV<double> L, LV<double> Lc, const int *lb, const int *meta, const double *d6,
+                           const int *inside, const double *pb, int inside_zero, double *out, long long ostride,
+                           long long base) {
+    using B = Blk<D, N>;
+    const int blk = lb[blockIdx.x];
+    __shared__ int snb[2 * D];
+    __shared__ int smo;
+    const int4 P = L.pos[blk];
+    load_neighbours<double, D>(L, P, snb, &smo, blk);
+    __syncthreads();
+    const double *phi = L.phi + (long long)blockIdx.y * L.fstride;
+    const double *phic = Lc.phi ? Lc.phi + (long long)blockIdx.y * Lc.fstride : nullptr;
+    const double *pbr = pb;
+    const long long bb = (long long)blk * B::CPB;
+    double *o = out + (long long)blockIdx.y * ostride + 3 * (base + (long long)blockIdx.x * B::CPB);
+    const double inv = 1.0 / sqrt(L.dx2);
+    for (int c = threadIdx.x; c < B::CPB; c += blockDim.x) {
+        const int i = c % N, j = (c / N) % N, k = D == 3 ? c / (N * N) : 0;
+        const int si = split_of<D, N>(i, j, k);
+        const double own = phi[bb + si];
+        const int ri = smo >= 0 ? L.map[smo + si] : -1;
+        const int cut = ri >= 0 ? meta[4 * ri + 2] : 0;
+        double gr[3] = {0.0, 0.0, 0.0};
+        if (!(inside_zero && ri >= 0 && inside[ri])) {
+            double v[2 * D];
+            gather<double, D, N, false>(L, Lc, phi, phic, bb, snb, P, i, j, k, own, v);
+            int pt = ri >= 0 ? meta[4 * ri + 3] : 0;  // points of the cut links, in link order
+            for (int ax = 0; ax < D; ax++) {
+                double face[2];
+                for (int side = 0; side < 2; side++) {
+                    const int kk = 2 * ax + side;
+                    double dv;
+                    if (cut >> kk & 1) dv = (pbr[pt++] - own) / (d6[6 * ri + kk] * sqrt(L.dx2));
+                    else dv = (v[kk] - own) * inv;
+                    face[side] = side ? dv : -dv;
+                }
+                gr[ax] = 0.5 * (face[0] + face[1]);
+            }
+        }
+        for (int a = 0; a < 3; a++) o[3 * c + a] = gr[a];
     }
 }
 
@@ -859,6 +888,7 @@ __device__ __forceinline__ T halo_value(const LV<T> &L, const T *__restrict__ ph
                                         int nb, long long nidx, int d, int4 P, int i, int j, int k, int oidx) {
     if (nb >= 0) return ZERO ? T(0) : phi[(long long)nb * Blk<3, N>::CPB + nidx];
     if (nb == -1) return T(0);
+    if (zero_flux(L.neumann, d >> 1, (d & 1) ? 1 : -1)) return ZERO ? T(0) : own_col[oidx];
     const T bv = L.bcv ? L.bcv[face_slot<3>(d >> 1, (d & 1) ? 1 : -1, P.x * N + i, P.y * N + j, P.z * N + k, L.n,
                                             L.nface)]
                        : T(0);
@@ -1288,8 +1318,8 @@ __global__ __launch_bounds__(256) void k_residual_max3(LV<T> L, LV<T> Lc, unsign
 
 // prolongation, 3D: the coarse correction of the parent region (plus a
 // one-cell halo) is staged in LDS, then every fine cell is updated once.
-template <typename T, int N, int NC>
-__device__ __forceinline__ void prolong3_body(const LV<T> &L, const LV<T> &Lc, int solution, int blk, int rhs, T *et) {
+template <typename T, int N, int NC, bool SOL>
+__device__ __forceinline__ void prolong3_body(const LV<T> &L, const LV<T> &Lc, int blk, int rhs, T *et) {
     using B = Blk<3, N>;
     constexpr int H = N / 2, E = H + 2, ESZ = E * E * E, PER = B::CPB / 256;
     if (L.active && !L.active[rhs]) return;
@@ -1303,7 +1333,7 @@ __device__ __forceinline__ void prolong3_body(const LV<T> &L, const LV<T> &Lc, i
     const int C0[3] = {P.x * H, P.y * H, P.z * H};
     for (int e = threadIdx.x; e < ESZ; e += 256) {
         const int x = e % E, y = (e / E) % E, z = e / (E * E);
-        et[e] = coarse_e<T, 3, NC>(Lc, phic, oldc, C0[0] + x - 1, C0[1] + y - 1, C0[2] + z - 1, solution);
+        et[e] = coarse_e<T, 3, NC, SOL>(Lc, phic, oldc, C0[0] + x - 1, C0[1] + y - 1, C0[2] + z - 1);
     }
     __syncthreads();
 #pragma unroll
@@ -1324,12 +1354,12 @@ __device__ __forceinline__ void prolong3_body(const LV<T> &L, const LV<T> &Lc, i
     }
 }
 
-template <typename T, int N, int NC>
-__global__ __launch_bounds__(256) void k_prolong3(LV<T> L, LV<T> Lc, int solution) {
+template <typename T, int N, int NC, bool SOL>
+__global__ __launch_bounds__(256) void k_prolong3(LV<T> L, LV<T> Lc) {
     using B = Blk<3, N>;
     constexpr int H = N / 2, E = H + 2, ESZ = E * E * E, PER = B::CPB / 256;
     __shared__ T et[ESZ];
-    prolong3_body<T, N, NC>(L, Lc, solution, block_of(L), rhs_of(L), et);
+    prolong3_body<T, N, NC, SOL>(L, Lc, block_of(L), rhs_of(L), et);
 }
 
 // mixed precision defect (FP64): g32 = g - L phi on a leaf block, phi32 = 0
@@ -1435,7 +1465,7 @@ __device__ __forceinline__ void coarse_solve3_body(const LV<T> &L0, const double
             q[ax] += s;
             if (q[ax] >= 0 && q[ax] < NB) continue;
             const double cc = ri >= 0 ? (double)L0.rec[8 * (long long)ri + d] : inv;
-            if (cc == 0.0) continue;
+            if (cc == 0.0 || zero_flux(L0.neumann, ax, s)) continue;  // zero flux: folded into the operator
             const double bv = L0.bcv ? (double)L0.bcv[face_slot<3>(ax, s, i, j, k, NB, L0.nface)] : 0.0;
             r -= 2.0 * cc * bv;
         }
@@ -1471,7 +1501,7 @@ __device__ __noinline__ void fas_rhs_call(const LV<T> &L, const LV<T> &Lc, int b
 }
 template <typename T, int N, int NC>
 __device__ __noinline__ void prolong_call(const LV<T> &L, const LV<T> &Lc, int blk, int rhs, T *sm) {
-    prolong3_body<T, N, NC>(L, Lc, 0, blk, rhs, sm);
+    prolong3_body<T, N, NC, false>(L, Lc, blk, rhs, sm);
 }
 template <typename T>
 __device__ __noinline__ void coarse_call(const LV<T> &L0, const double *M, const double *S, int tile, int rhs,
@@ -1614,7 +1644,7 @@ hipError_t launch_prolong(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc,
     if (L.nblocks == 0) return hipSuccess;
     dim3 grid(L.nblocks, nrhs);
 #define PR(D_, N_, NC_) OCTMG_DNC(D_, N_, NC_, hipLaunchKernelGGL((k_prolong<T, D_, N_, NC_>), grid, dim3(256), 0, s, L, Lc, solution_mode))
-#define PR3(N_, NC_) OCTMG_DNC(3, N_, NC_, hipLaunchKernelGGL((k_prolong3<T, N_, NC_>), grid, dim3(256), 0, s, L, Lc, solution_mode))
+#define PR3(N_, NC_) OCTMG_DNC(3, N_, NC_, if (solution_mode) hipLaunchKernelGGL((k_prolong3<T, N_, NC_, true>), grid, dim3(256), 0, s, L, Lc); else hipLaunchKernelGGL((k_prolong3<T, N_, NC_, false>), grid, dim3(256), 0, s, L, Lc))
     PR3(16, 16) PR3(16, 8) PR3(8, 8) PR(2, 8, 8) PR(2, 16, 16) PR(2, 16, 8)
 #undef PR3
 #undef PR
@@ -1698,6 +1728,17 @@ hipError_t launch_gather_leaf(int D, int N, const LV<double> &L, const int *lb, 
 #define GA(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_gather_leaf<D_, N_>), grid, dim3(256), 0, s, L, lb, dst, dst_stride, base))
     GA(3, 16) GA(3, 8) GA(2, 8) GA(2, 16)
 #undef GA
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_gradient(int D, int N, const LV<double> &L, const LV<double> &Lc, const int *lb, int nlb,
+                           const int *meta, const double *d6, const int *inside, const double *pb, int inside_zero,
+                           double *out, long long out_stride, long long base, int nrhs, hipStream_t s) {
+    if (nlb == 0) return hipSuccess;
+    dim3 grid(nlb, nrhs);
+#define GR(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_gradient<D_, N_>), grid, dim3(256), 0, s, L, Lc, lb, meta, d6, inside, pb, inside_zero, out, out_stride, base))
+    GR(3, 16) GR(3, 8) GR(2, 8) GR(2, 16)
+#undef GR
     return hipErrorInvalidValue;
 }
 

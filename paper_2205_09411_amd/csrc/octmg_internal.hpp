@@ -70,6 +70,7 @@ struct LV {
     const int *active;   // [nrhs] nonzero = right-hand side still iterating (nullptr: all)
     const int *lanes;    // [grid y] right-hand side of each grid row (nullptr: row = rhs)
     int order;           // workgroup -> block order of the 3D kernels (0 XCD ranges, 1 hardware)
+    int neumann;         // bit 2 axis + (side > 0): zero-flux domain face (ghost = inside value)
 };
 
 // ---------------------------------------------------------- launches
@@ -144,6 +145,12 @@ hipError_t launch_converge(const unsigned long long *norm, const double *thresh,
                            int nrhs, hipStream_t s);
 hipError_t launch_copy_d2f(const double *src, float *dst, long long n, hipStream_t s);
 hipError_t launch_check_finite(const double *p, long long n, int *flag, hipStream_t s);
+// grad phi at the leaf cells of one level (Sec. 4.4: face differences, with
+// (phi_b - phi_i)/(d dx) across cut links), out[rhs][n_leaf][3] at leaf
+// offset base; inside_zero: cut cells with f(centre) < 0 get 0
+hipError_t launch_gradient(int D, int N, const LV<double> &L, const LV<double> &Lc, const int *lb, int nlb,
+                           const int *meta, const double *d6, const int *inside, const double *pb, int inside_zero,
+                           double *out, long long out_stride, long long base, int nrhs, hipStream_t s);
 
 // ------------------------------------------------------------- setup
 // FP64 interface setup of one level (built without FMA contraction).
@@ -164,11 +171,11 @@ hipError_t launch_setup_count(const SetupLevel &S, int *counts /*[nblocks][2]*/,
 // pass 2: records in canonical order at the given per-block offsets
 hipError_t launch_setup_emit(const SetupLevel &S, const int *rec_off, const int *pt_off, const int *map_off,
                              int *map, int *meta /*[nrec][4]*/, double *d6, double *cfull /*[nrec][6]*/,
-                             double *rec8, float *rec8f, double *pts, hipStream_t s);
+                             double *rec8, float *rec8f, double *pts, int *inside /*[nrec]*/, hipStream_t s);
 // coarsest grid: dense operator with domain ghosts folded in, then a
 // row-equilibrated Gauss-Jordan inverse M and scales S (A^-1 = M diag(S)).
-hipError_t launch_coarse_assemble(int D, int Nb, double dx, const int *map, const double *rec8, double *A,
-                                  hipStream_t s);
+hipError_t launch_coarse_assemble(int D, int Nb, double dx, const int *map, const double *rec8, int neumann,
+                                  double *A, hipStream_t s);
 hipError_t launch_gauss_jordan(int n, double *A, double *M, double *S, int *fail, hipStream_t s);
 
 // ---- lanes of a multi-rhs state (api.cpp), used by the serving engine

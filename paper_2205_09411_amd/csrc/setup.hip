@@ -59,8 +59,29 @@ __device__ double shape_dev(const SetupLevel &S, const double *x) {
     return cbrt_ops(p * p) / 0.8 + cbrt_ops(q * q) / 1.5 - 0.8;
 }
 
+// rod (points within r_rod of segment a-b) and sphere, the nearer surface
+__device__ double electrodes_dev(const double *q, const double *x) {
+    double ab[3], t = 0.0, ll = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        ab[c] = q[3 + c] - q[c];
+        t += (x[c] - q[c]) * ab[c];
+        ll += ab[c] * ab[c];
+    }
+    t = t / ll;
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    double d2 = 0.0, s2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        const double e = x[c] - (q[c] + t * ab[c]), f = x[c] - q[7 + c];
+        d2 += e * e;
+        s2 += f * f;
+    }
+    const double rod = __dsqrt_rn(d2) - q[6], sph = __dsqrt_rn(s2) - q[10];
+    return rod < sph ? rod : sph;
+}
+
 __device__ double lsf_dev(const SetupLevel &S, const double *x) {
     const double *p = S.lsf_params;
+    if (S.lsf_kind == OCTMG_LSF_ELECTRODES) return electrodes_dev(p, x);
     if (S.lsf_kind >= OCTMG_LSF_SPHEROID && S.lsf_kind <= OCTMG_LSF_ASTROID) return shape_dev(S, x);
     if (S.lsf_kind == OCTMG_LSF_SPHERES) {
         double best = 0.0;
@@ -192,7 +213,7 @@ __device__ int unresolved_search(const SetupLevel &S, const double *a, double fa
 }
 
 struct CellSetup {
-    int cut;
+    int cut, inside;
     double d[6];
     double x0[6][3];
 };
@@ -214,6 +235,7 @@ __device__ int analyse_cell(const SetupLevel &S, int blk, int li, CellSetup &R) 
         n2 = n2 + gc * gc;
     }
     R.cut = 0;
+    R.inside = fa < 0.0;
     for (int k = 0; k < 6; k++) R.d[k] = 1.0;
     if (!(fabs(fa) < S.mask_L * __dsqrt_rn(n2))) return 0;
     for (int k = 0; k < 2 * S.D; k++) {
@@ -283,7 +305,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup_count(SetupLevel S, int
 __global__ __launch_bounds__(kSetupThreads) void k_setup_emit(SetupLevel S, const int *rec_off,
                                                                const int *pt_off, const int *map_off, int *map,
                                                                int *meta, double *d6, double *cfull, double *rec8,
-                                                               float *rec8f, double *pts) {
+                                                               float *rec8f, double *pts, int *inside) {
     const int blk = blockIdx.x;
     const int cpb = S.D == 3 ? S.Nb * S.Nb * S.Nb : S.Nb * S.Nb;
     const int chunk = (cpb + blockDim.x - 1) / blockDim.x;
@@ -327,6 +349,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup_emit(SetupLevel S, cons
         meta[4 * r + 1] = si;
         meta[4 * r + 2] = R.cut;
         meta[4 * r + 3] = q;
+        inside[r] = R.inside;
         for (int k = 0; k < 6; k++) {
             d6[6 * r + k] = R.d[k];
             cfull[6 * r + k] = c[k];
@@ -350,7 +373,8 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup_emit(SetupLevel S, cons
 
 // Dense operator of the single-block coarsest grid (canonical cell order),
 // domain ghosts 2 phi_b - phi_in folded into the diagonal.
-__global__ void k_coarse_assemble(int D, int Nb, double dx, const int *map, const double *rec8, double *A) {
+__global__ void k_coarse_assemble(int D, int Nb, double dx, const int *map, const double *rec8, int neumann,
+                                  double *A) {
     const int n = D == 3 ? Nb * Nb * Nb : Nb * Nb;
     const int row = blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= n) return;
@@ -366,7 +390,9 @@ __global__ void k_coarse_assemble(int D, int Nb, double dx, const int *map, cons
         int q[3] = {i, j, k};
         q[ax] += s;
         if (q[ax] < 0 || q[ax] >= Nb) {
-            diag -= c;
+            // ghost folded in: 2 phi_b - phi_i (Dirichlet), phi_i (zero flux)
+            if ((neumann >> (2 * ax + (s > 0))) & 1) diag += c;
+            else diag -= c;
             continue;
         }
         const int col = D == 3 ? (q[2] * Nb + q[1]) * Nb + q[0] : q[1] * Nb + q[0];
@@ -456,17 +482,17 @@ hipError_t launch_setup_count(const SetupLevel &S, int *counts, hipStream_t s) {
 
 hipError_t launch_setup_emit(const SetupLevel &S, const int *rec_off, const int *pt_off, const int *map_off,
                              int *map, int *meta, double *d6, double *cfull, double *rec8, float *rec8f,
-                             double *pts, hipStream_t s) {
+                             double *pts, int *inside, hipStream_t s) {
     if (S.nblocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_setup_emit, dim3(S.nblocks), dim3(kSetupThreads), 0, s, S, rec_off, pt_off, map_off, map,
-                       meta, d6, cfull, rec8, rec8f, pts);
+                       meta, d6, cfull, rec8, rec8f, pts, inside);
     return hipGetLastError();
 }
 
-hipError_t launch_coarse_assemble(int D, int Nb, double dx, const int *map, const double *rec8, double *A,
-                                  hipStream_t s) {
+hipError_t launch_coarse_assemble(int D, int Nb, double dx, const int *map, const double *rec8, int neumann,
+                                  double *A, hipStream_t s) {
     const int n = D == 3 ? Nb * Nb * Nb : Nb * Nb;
-    hipLaunchKernelGGL(k_coarse_assemble, dim3((n + 127) / 128), dim3(128), 0, s, D, Nb, dx, map, rec8, A);
+    hipLaunchKernelGGL(k_coarse_assemble, dim3((n + 127) / 128), dim3(128), 0, s, D, Nb, dx, map, rec8, neumann, A);
     return hipGetLastError();
 }
 

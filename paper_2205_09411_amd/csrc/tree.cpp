@@ -33,6 +33,24 @@ static double cbrt_ops_host(double a) {
 }
 
 double lsf_host(const octmg_geom_desc &d, const double *p, const double *x) {
+    if (d.lsf_kind == OCTMG_LSF_ELECTRODES) {
+        double ab[3], t = 0.0, ll = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            ab[c] = p[3 + c] - p[c];
+            t += (x[c] - p[c]) * ab[c];
+            ll += ab[c] * ab[c];
+        }
+        t = t / ll;
+        t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+        double d2 = 0.0, s2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const double e = x[c] - (p[c] + t * ab[c]), f = x[c] - p[7 + c];
+            d2 += e * e;
+            s2 += f * f;
+        }
+        const double rod = std::sqrt(d2) - p[6], sph = std::sqrt(s2) - p[10];
+        return rod < sph ? rod : sph;
+    }
     if (d.lsf_kind >= OCTMG_LSF_SPHEROID && d.lsf_kind <= OCTMG_LSF_ASTROID) {
         double a, b;
         if (d.dim == 2) {
@@ -116,9 +134,12 @@ bool build_tree(const octmg_geom_desc &d, Tree *out, std::string *err) {
     if (lmax < 1 || lmax > 14) { *err = "max_level out of range"; return false; }
     if (d.lsf_kind == OCTMG_LSF_SPHERES && (d.lsf_n < 1 || !d.lsf_params)) { *err = "spheres need lsf_n >= 1 and params"; return false; }
     if (d.lsf_kind == OCTMG_LSF_CYLINDER_Z && !d.lsf_params) { *err = "cylinder needs params"; return false; }
-    if (d.lsf_kind < OCTMG_LSF_NONE || d.lsf_kind > OCTMG_LSF_ASTROID) { *err = "unknown lsf_kind"; return false; }
+    if (d.lsf_kind < OCTMG_LSF_NONE || d.lsf_kind > OCTMG_LSF_ELECTRODES) { *err = "unknown lsf_kind"; return false; }
+    if (d.lsf_kind == OCTMG_LSF_ELECTRODES && d.dim != 3) { *err = "the electrode level set is 3D"; return false; }
     if (d.refine_kind != OCTMG_REFINE_UNIFORM && d.refine_kind != OCTMG_REFINE_NEAR_INTERFACE) { *err = "unknown refine_kind"; return false; }
     if ((long)N << (lmax - 1) > (1L << 15)) { *err = "grid too large"; return false; }
+    if (d.neumann_faces < 0 || d.neumann_faces >= (1 << (2 * D))) { *err = "neumann_faces has bits beyond the 2D faces"; return false; }
+    if (d.uniform_level < 0 || d.uniform_level > lmax) { *err = "bad uniform_level"; return false; }
 
     // occupancy per tree level 1..lmax (index 0 unused)
     std::vector<Occ> occ(lmax + 1);
@@ -138,7 +159,7 @@ bool build_tree(const octmg_geom_desc &d, Tree *out, std::string *err) {
                 for (int x = 0; x < nb; x++) {
                     if (!occ[l].has(x, y, z)) continue;
                     bool refine = true;
-                    if (d.refine_kind == OCTMG_REFINE_NEAR_INTERFACE) {
+                    if (d.refine_kind == OCTMG_REFINE_NEAR_INTERFACE && l >= d.uniform_level) {
                         double c[3] = {d.lo[0] + ((double)x + 0.5) * w, d.lo[1] + ((double)y + 0.5) * w,
                                        D == 3 ? d.lo[2] + ((double)z + 0.5) * w : 0.0};
                         refine = std::fabs(lsf_host(d, d.lsf_params, c)) < d.refine_width * w;

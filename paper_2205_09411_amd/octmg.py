@@ -34,9 +34,10 @@ class OctmgError(RuntimeError):
 
 class GeomDesc(C.Structure):
     _fields_ = [("dim", C.c_int), ("block_n", C.c_int), ("max_level", C.c_int), ("refine_kind", C.c_int),
-                ("lsf_kind", C.c_int), ("lsf_n", C.c_int), ("coarse_n", C.c_int), ("reserved", C.c_int),
+                ("lsf_kind", C.c_int), ("lsf_n", C.c_int), ("coarse_n", C.c_int), ("neumann_faces", C.c_int),
                 ("refine_width", C.c_double), ("eps_tol", C.c_double), ("mask_factor", C.c_double),
-                ("w_min", C.c_double), ("lo", C.c_double * 3), ("lsf_params", C.POINTER(C.c_double))]
+                ("w_min", C.c_double), ("lo", C.c_double * 3), ("lsf_params", C.POINTER(C.c_double)),
+                ("uniform_level", C.c_int), ("reserved", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -100,6 +101,7 @@ _SIGS = {
     "octmg_zero_solution": (C.c_int, [_vp, _vp]),
     "octmg_cycle": (C.c_int, [_vp, C.c_int, C.c_int, _vp]),
     "octmg_residual_norm": (C.c_int, [_vp, C.c_int, _dp, _vp]),
+    "octmg_gradient": (C.c_int, [_vp, C.c_int, _vp, C.c_int, _vp]),
     "octmg_solve": (C.c_int, [_vp, C.POINTER(SolveOpts), _vp, C.POINTER(SolveReport)]),
     "octmg_state_set_launch": (C.c_int, [_vp, C.POINTER(LaunchConfig)]),
     "octmg_state_get_launch": (C.c_int, [_vp, C.POINTER(LaunchConfig)]),
@@ -156,6 +158,8 @@ def make_desc(geom) -> GeomDesc:
     d.dim, d.block_n, d.max_level = geom.dim, geom.block_n, geom.max_level
     d.refine_kind, d.lsf_kind, d.lsf_n = geom.refine_kind, geom.lsf_kind, geom.lsf_n
     d.coarse_n = geom.coarse_n
+    d.neumann_faces = getattr(geom, "neumann_faces", 0)
+    d.uniform_level = getattr(geom, "uniform_level", 0)
     d.refine_width, d.eps_tol, d.mask_factor, d.w_min = geom.refine_width, geom.eps_tol, geom.mask_factor, geom.w_min
     for i in range(3):
         d.lo[i] = geom.lo[i]
@@ -352,6 +356,13 @@ class State:
 
     def fmg(self, have_guess: bool = True, stream=None):
         self.cycle(CYCLE_FMG, have_guess, stream)
+
+    def gradient(self, inside_zero: bool = False, stream=None) -> np.ndarray:
+        """grad phi at the leaf cell centres, [n_leaf][3] (or [n_rhs][n_leaf][3])."""
+        g = self.geometry
+        out = np.zeros((self.n_rhs, g.n_leaf, 3))
+        _check(lib().octmg_gradient(self._h, int(inside_zero), out.ctypes.data, 0, _stream_ptr(stream)))
+        return out[0] if self.n_rhs == 1 else out
 
     def residual_norm(self, phi_zero: bool = False, stream=None) -> np.ndarray:
         out = np.zeros(self.n_rhs)

@@ -36,6 +36,9 @@ LSF_CYLINDER_Z = 2   # infinite cylinder along z: params [cx, cy, r]
 # q = s(y-cy); 3D p = s|(x-cx, y-cy)|, q = s(z-cz)
 LSF_SPHEROID, LSF_RHOMBUS, LSF_HEART, LSF_ASTROID = 3, 4, 5, 6
 SHAPES = {"spheroid": LSF_SPHEROID, "rhombus": LSF_RHOMBUS, "heart": LSF_HEART, "astroid": LSF_ASTROID}
+# two electrodes: rod around segment a-b plus a sphere, params
+# [ax, ay, az, bx, by, bz, r_rod, cx, cy, cz, r_sphere]
+LSF_ELECTRODES = 7
 
 REFINE_UNIFORM = 0
 REFINE_NEAR_INTERFACE = 1
@@ -57,12 +60,14 @@ class Geometry:
     w_min: float = 0.0
     coarse_n: int = 8
     name: str = ""
+    neumann_faces: int = 0   # bit f: zero-flux domain face f (x-, x+, y-, y+, z-, z+)
+    uniform_level: int = 0   # levels <= this are complete; finer ones follow refine_kind
 
     @property
     def lsf_n(self) -> int:
         if self.lsf_kind == LSF_SPHERES:
             return len(self.lsf_params) // 4
-        if self.lsf_kind in (LSF_CYLINDER_Z, LSF_SPHEROID, LSF_RHOMBUS, LSF_HEART, LSF_ASTROID):
+        if self.lsf_kind in (LSF_CYLINDER_Z, LSF_SPHEROID, LSF_RHOMBUS, LSF_HEART, LSF_ASTROID, LSF_ELECTRODES):
             return 1
         return 0
 
@@ -205,6 +210,42 @@ def sharp_shape(shape: str, dim: int = 2, max_level: int = 4, block_n: int = 8) 
                     name=f"{shape}_{dim}d_{block_n * (1 << (max_level - 1))}")
     return Workload(geom, lambda x: np.zeros(x.shape[0]), lambda x: np.ones(x.shape[0]),
                     lambda x: np.zeros(x.shape[0]))
+
+
+def two_electrodes(max_level: int = 7, uniform_level: int = 5, block_n: int = 8, refine_width: float = 1.0,
+                   tip_z: float = 0.6) -> Workload:
+    """Sec. 4.4: unit cube, phi = 1 on the top face and 0 on the bottom face,
+    zero flux on the four sides; a rod electrode of radius 0.05 hanging from
+    the top (segment (0.5, 0.5, tip_z)-(0.5, 0.5, 1.1)) at phi = 1 and a
+    half sphere of radius 0.25 centred on the bottom face at phi = 0.
+    Uniform to `uniform_level`, then refined near the electrodes to
+    max_level (8^3 blocks: dx = 1/128 and 1/512 for 5 and 7); g = 0."""
+    p = np.array([0.5, 0.5, tip_z, 0.5, 0.5, 1.1, 0.05, 0.5, 0.5, 0.0, 0.25])
+    geom = Geometry(dim=3, block_n=block_n, max_level=max_level, lsf_kind=LSF_ELECTRODES, lsf_params=p,
+                    refine_kind=REFINE_NEAR_INTERFACE, refine_width=refine_width, w_min=8e-3,
+                    neumann_faces=0b001111, uniform_level=uniform_level,
+                    name=f"two_electrodes_L{max_level}")
+
+    def on_rod(x):
+        ab = p[3:6] - p[0:3]
+        t = np.clip(((x[:, :3] - p[0:3]) @ ab) / (ab @ ab), 0.0, 1.0)
+        rod = np.linalg.norm(x[:, :3] - (p[0:3] + t[:, None] * ab), axis=1) - p[6]
+        sph = np.linalg.norm(x[:, :3] - p[7:10], axis=1) - p[10]
+        return np.abs(rod) < np.abs(sph)
+
+    return Workload(geom, lambda x: np.zeros(x.shape[0]), lambda x: on_rod(x).astype(float),
+                    lambda x: (x[:, 2] > 0.5).astype(float))
+
+
+def neumann2d(max_level: int = 5) -> Workload:
+    """2D, zero flux on the x faces: phi = cos(pi x) exp(pi y) (harmonic,
+    d phi/dx = 0 at x = 0 and 1) on a circle and on the y faces, g = 0;
+    8^2 blocks refined near the circle."""
+    geom = Geometry(dim=2, block_n=8, max_level=max_level, lsf_kind=LSF_SPHERES,
+                    lsf_params=np.array([0.55, 0.45, 0.0, 0.2]), refine_kind=REFINE_NEAR_INTERFACE,
+                    refine_width=1.0, w_min=4e-3, neumann_faces=0b0011, name=f"neumann2d_L{max_level}")
+    phi = lambda x: np.cos(np.pi * x[:, 0]) * np.exp(np.pi * x[:, 1])
+    return Workload(geom, lambda x: np.zeros(x.shape[0]), phi, phi, exact=phi)
 
 
 def serving_geometries(seed0: int = 500, counts=(1, 5, 10, 20)):

@@ -70,7 +70,8 @@ def test_adaptive_plan_is_adaptive():
 
 
 @pytest.mark.parametrize("field,value", [("dim", 4), ("block_n", 12), ("max_level", 0), ("coarse_n", 4),
-                                         ("eps_tol", 0.0), ("lsf_kind", 7)])
+                                         ("eps_tol", 0.0), ("lsf_kind", 8), ("neumann_faces", 64),
+                                         ("uniform_level", 9)])
 def test_invalid_descriptor_rejected(field, value):
     geom = W.mms3d(max_level=2).geom
     setattr(geom, field, value)

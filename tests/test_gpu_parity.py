@@ -29,6 +29,9 @@ CONFIGS = {
     "astroid_2d": lambda: W.sharp_shape("astroid", dim=2, max_level=5),
     "spheroid_3d": lambda: W.sharp_shape("spheroid", dim=3, max_level=3, block_n=16),
     "rhombus_3d": lambda: W.sharp_shape("rhombus", dim=3, max_level=3, block_n=8),
+    # zero-flux side faces (Sec. 4.4)
+    "electrodes_small": lambda: W.two_electrodes(max_level=5, uniform_level=3),
+    "neumann_2d": lambda: W.neumann2d(max_level=5),
 }
 
 
@@ -272,4 +275,49 @@ def test_full_size_adaptive_spheres(orc):
     o.vcycle()
     d = rel(S.get_solution(), o.get_solution())
     print("rel diff after one V-cycle", d, flush=True)
+    assert d < 1e-10
+
+
+@pytest.mark.parametrize("name", ["electrodes_small", "neumann_2d", "spheres_amr", "heart_2d"])
+def test_gradient_parity(orc, name):
+    """The field post-processing (Sec. 4.4) on the same phi: face
+    differences, interface distances, ghosts at domain faces (Dirichlet and
+    zero flux) and refinement boundaries."""
+    w = CONFIGS[name]()
+    print("gradient parity", name, flush=True)
+    o, G, S = make_pair(orc, w)
+    for _ in range(3):
+        o.vcycle()
+    S.set_solution(o.get_solution())
+    for inside_zero in (False, True):
+        a = S.gradient(inside_zero=inside_zero)
+        b = o.gradient(inside_zero=inside_zero)
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max(), (inside_zero, np.abs(a - b).max())
+        if inside_zero:
+            assert np.array_equal(np.all(a == 0, axis=1), np.all(b == 0, axis=1))
+
+
+@pytest.mark.timeout(900)
+def test_full_size_two_electrodes(orc):
+    """The two-electrode problem on the paper's resolutions (dx = 1/128
+    everywhere, 1/512 near the electrodes, 8^3 blocks; 7.9M leaf cells):
+    setup parity on every level and the first FMG against the checker."""
+    w = W.two_electrodes()
+    print("full size two electrodes: checker setup", flush=True)
+    o = orc.setup_workload(w)
+    G = octmg.Geometry(w.geom)
+    assert G.n_leaf > 5_000_000
+    assert np.array_equal(G.iface_points(), o.iface_points())
+    for il in range(o.n_levels):
+        ig, dg, _ = G.records(il)
+        io, do, _ = o.records(il)
+        assert np.array_equal(ig, io) and np.array_equal(dg[:, :6], do[:, :6]), il
+    S = octmg.State(G)
+    S.set_boundary(w.iface_value(o.iface_points()), w.domain_value(o.domain_points()))
+    S.set_rhs(np.zeros(G.n_leaf))
+    print("one FMG each", flush=True)
+    S.fmg(have_guess=False)
+    o.fmg(have_guess=False)
+    d = rel(S.get_solution(), o.get_solution())
+    print("rel diff after the first FMG", d, flush=True)
     assert d < 1e-10
