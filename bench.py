@@ -415,6 +415,48 @@ def leg_electrodes(stream, n_fmg=4, reps=3):
     return out
 
 
+def leg_adapt(stream):
+    """Mesh adaptation on the 20-sphere adaptive problem (16^3 blocks, to
+    level 6): the leaves that a wider refinement band refines are flagged;
+    time of the adapted geometry (unchanged blocks keep their records)
+    against a setup from scratch of the same tree, and of carrying phi over."""
+    import torch
+    from paper_2205_09411_amd import octmg
+    from paper_2205_09411_amd import workloads as W
+    narrow = W.spheres(refine_width=1.5)
+    wide = W.spheres()
+    G0 = octmg.Geometry(narrow.geom)
+    target = {}
+    for il in range(len(octmg.plan_levels(wide.geom))):
+        pos, leaf = octmg.plan_blocks(wide.geom, il)
+        for p_, lf in zip(pos, leaf):
+            target[(il, *map(int, p_))] = int(lf)
+    flags = np.array([1 if target.get(tuple(int(v) for v in lb), 1) == 0 else 0 for lb in G0.leaf_blocks()],
+                     dtype=np.int8)
+    S0 = octmg.State(G0)
+    S0.set_boundary_fn(narrow.iface_value, narrow.domain_value)
+    x0, _ = G0.leaf_coords()
+    S0.set_rhs(narrow.rhs(x0))
+    S0.solve(rtol=1e-10)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    G1, stats = G0.adapt(flags, reuse=True)
+    t_adapt = time.perf_counter() - t
+    t = time.perf_counter()
+    G2, _ = G0.adapt(flags, reuse=False)
+    t_scratch = time.perf_counter() - t
+    S1 = octmg.State(G1)
+    t = time.perf_counter()
+    S1.remap_from(S0)
+    t_remap = time.perf_counter() - t
+    return {"workload": "20 spheres, 16^3 blocks to level 6: refinement band 1.5 -> 2.87 block widths in one step",
+            "leaf_cells_before": int(G0.n_leaf), "leaf_cells_after": int(G1.n_leaf),
+            "flagged_blocks": int(flags.sum()), "blocks_kept": int(stats[0]), "blocks_set_up": int(stats[1]),
+            "records_kept": int(stats[2]), "records_computed": int(stats[3]),
+            "adapt_s_reusing_records": round(t_adapt, 3), "adapt_s_from_scratch": round(t_scratch, 3),
+            "remap_phi_s": round(t_remap, 4)}
+
+
 def leg_2d(stream, steps=20):
     """2D 64^2 in 8^2 blocks, circle r=0.25, manufactured solution, FP64,
     V(2,2) to 1e-10 (launch-bound at this size)."""
@@ -464,9 +506,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--block-order", type=int, default=None,
                     help="with --no-tune: block order of the 3D kernels (0 XCD ranges, 1 hardware, 2 octant walk)")
-    ap.add_argument("--legs", default="mixed,batched,adaptive,serving,table1,2d,sharp,electrodes",
+    ap.add_argument("--legs", default="mixed,batched,adaptive,serving,table1,2d,sharp,electrodes,adapt",
                     help="extra measurements after the headline: mixed,batched,adaptive,serving,table1,2d,sharp,"
-                         "electrodes or none")
+                         "electrodes,adapt or none")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -592,6 +634,8 @@ def main():
                 legs[leg] = leg_sharp(stream)
             elif leg == "electrodes":
                 legs[leg] = leg_electrodes(stream)
+            elif leg == "adapt":
+                legs[leg] = leg_adapt(stream)
             else:
                 raise ValueError(f"unknown leg {leg}")
         except Exception as e:  # a failed leg is reported, the headline stands

@@ -190,6 +190,29 @@ octmg_status octmg_geom_domain_points(octmg_geom g, double *xyz);
 octmg_status octmg_geom_records(octmg_geom g, int level, int *ids, double *d, double *coef);
 octmg_status octmg_geom_block_positions(octmg_geom g, int level, int *pos, int *leaf);
 
+/* Mesh adaptation (the paper's setting: the mesh changes often, the
+ * boundary does not; Sec. 1 and Sec. 4.5).  flags[i] for the i-th leaf block
+ * of g (canonical order: level, then Morton order within the level; the
+ * blocks of octmg_geom_leaf_coords' cells, N^D cells each): +1 refine (below
+ * max_level), -1 coarsen (a family of 2^D leaves goes when all are flagged
+ * and their level is above uniform_level), 0 keep; then the tree is
+ * balanced 2:1 again.  The result is a new geometry with g's level set and
+ * descriptor.  reuse != 0: blocks with the same level, position and leaf
+ * status keep g's stencil records, interface points and (if the coarsest
+ * level is unchanged) the coarse inverse; only the other blocks run the
+ * boundary detection and line search (Sec. 4.5: new refinement needs the
+ * setup, removing refinement needs none).  The records equal those of a
+ * setup from scratch, bit for bit.  stats (may be NULL): [blocks kept,
+ * blocks set up, records kept, records computed].  g stays valid. */
+octmg_status octmg_geom_adapt(octmg_geom g, const int8_t *flags, int reuse, octmg_geom *out, int64_t *stats);
+/* phi of `from` carried to `to` (a state of a geometry adapted from
+ * from's geometry, same n_rhs): unchanged cells are copied, cells of newly
+ * refined blocks interpolated with the cell-centred (3/4, 1/4) weights from
+ * the parent level, cells of coarsened blocks get the mean of their old
+ * children.  A warm start for solves on the new mesh; rhs and boundary
+ * values are set on `to` as usual.  Synchronises the stream. */
+octmg_status octmg_state_remap(octmg_state from, octmg_state to, void *stream);
+
 /* Fields for n_rhs right-hand sides on geometry g (kept alive by the state).
  * precision OCTMG_FP64, or OCTMG_MIXED: FP32 smoothing, transfers and ghost
  * fill inside an FP64 defect correction (FP64 residual, update, setup and

@@ -74,6 +74,8 @@ struct GeomLevel {
     int *d_leaf_blocks = nullptr, *d_meta = nullptr, *d_inside = nullptr;
     double *d_rec8 = nullptr, *d_d6 = nullptr, *d_cfull = nullptr, *d_pts = nullptr;
     float *d_rec8f = nullptr;
+    // per block: records and interface points, their offsets, record-map offset
+    std::vector<int> h_nrec, h_npt, h_rec_off, h_pt_off, h_map_off;
 };
 
 }  // namespace
@@ -554,21 +556,11 @@ octmg_status octmg_plan_blocks(const octmg_geom_desc *d, int level, int *pos, in
     return OCTMG_OK;
 }
 
-octmg_status octmg_geom_create(const octmg_geom_desc *d, int hip_device, octmg_geom *out) {
-    STCK(validate_desc(d));
-    if (!out) return fail(OCTMG_ERR_INVALID, "null output");
-    *out = nullptr;
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(OCTMG_ERR_HIP, "no HIP device");
-    if (hip_device < 0 || hip_device >= ndev) return fail(OCTMG_ERR_INVALID, "bad device index");
-    HIPCK(hipSetDevice(hip_device));
-    std::unique_ptr<octmg_geom_s> G(new octmg_geom_s());
-    G->desc = *d;
-    G->params = copy_params(*d);
-    G->desc.lsf_params = G->params.data();
-    G->device = hip_device;
-    std::string err;
-    if (!build_tree(G->desc, &G->tree, &err)) return fail(OCTMG_ERR_INVALID, err);
+// Device tables, FP64 interface setup and coarse inverse of G->tree.  With
+// `reuse` (the geometry G was adapted from), the records of unchanged
+// blocks are copied instead of recomputed; stats[0..3] += blocks kept,
+// blocks set up, records kept, records computed.
+static octmg_status setup_geometry(octmg_geom_s *G, const octmg_geom_s *reuse, int64_t *stats) {
     const int D = G->tree.D;
     const int nlev = (int)G->tree.lv.size();
     G->L.resize(nlev);
@@ -576,10 +568,11 @@ octmg_status octmg_geom_create(const octmg_geom_desc *d, int hip_device, octmg_g
     double *d_params = nullptr;
     HIPCK(G->pool.alloc(&d_params, G->params.size()));
     HIPCK(hipMemcpy(d_params, G->params.data(), G->params.size() * sizeof(double), hipMemcpyHostToDevice));
-    const int nbisect = (int)std::ceil(-std::log(d->eps_tol) / std::log(2.0));
-    const int ngolden = (int)std::ceil(std::log(d->eps_tol) / std::log(0.5 * (std::sqrt(5.0) - 1.0)));
+    const int nbisect = (int)std::ceil(-std::log(G->desc.eps_tol) / std::log(2.0));
+    const int ngolden = (int)std::ceil(std::log(G->desc.eps_tol) / std::log(0.5 * (std::sqrt(5.0) - 1.0)));
 
     long long leaf_base = 0, pt_base = 0;
+    bool coarse_kept = false;  // level 0 unchanged: the coarse inverse carries over
     for (int il = 0; il < nlev; il++) {
         const TreeLevel &T = G->tree.lv[il];
         GeomLevel &L = G->L[il];
@@ -637,23 +630,54 @@ octmg_status octmg_geom_create(const octmg_geom_desc *d, int hip_device, octmg_g
         S.nblocks = L.nblocks;
         S.nb = L.nb;
         S.dx = L.dx;
-        for (int a = 0; a < 3; a++) S.lo[a] = d->lo[a];
+        for (int a = 0; a < 3; a++) S.lo[a] = G->desc.lo[a];
         S.pos = L.d_pos;
         S.lut = L.d_lut;
         S.leaf = L.d_leaf;
-        S.lsf_kind = d->lsf_kind;
-        S.lsf_n = d->lsf_n;
+        S.lsf_kind = G->desc.lsf_kind;
+        S.lsf_n = G->desc.lsf_n;
         S.lsf_params = d_params;
-        S.mask_L = d->mask_factor * std::sqrt((double)D) * L.dx;
-        S.w_min = d->w_min;
+        S.mask_L = G->desc.mask_factor * std::sqrt((double)D) * L.dx;
+        S.w_min = G->desc.w_min;
         S.nbisect = nbisect;
         S.ngolden = ngolden;
-        int *d_counts = nullptr;
+        // blocks of the previous geometry with the same level, position and
+        // leaf status keep their records; only the others are set up
+        const GeomLevel *Lo = reuse && il < (int)reuse->L.size() ? &reuse->L[il] : nullptr;
+        const TreeLevel *To = reuse && il < (int)reuse->tree.lv.size() ? &reuse->tree.lv[il] : nullptr;
+        std::vector<int> old_of(L.nblocks, -1), fresh;
+        for (int b = 0; b < L.nblocks; b++) {
+            if (To && To->nb == T.nb) {
+                const long long li = D == 3 ? ((long long)pos4[b].z * T.nb + pos4[b].y) * T.nb + pos4[b].x
+                                            : (long long)pos4[b].y * T.nb + pos4[b].x;
+                const int ob = To->lut[li];
+                if (ob >= 0 && To->leaf[ob] == T.leaf[b]) old_of[b] = ob;
+            }
+            if (old_of[b] < 0) fresh.push_back(b);
+        }
+        if (stats) {
+            stats[0] += L.nblocks - (long long)fresh.size();
+            stats[1] += (long long)fresh.size();
+        }
+        if (il == 0) coarse_kept = reuse && fresh.empty();
+        int *d_counts = nullptr, *d_fresh = nullptr;
         HIPCK(hipMalloc(&d_counts, sizeof(int) * 2 * L.nblocks));
         std::unique_ptr<int, void (*)(int *)> counts_guard(d_counts, [](int *p) { (void)hipFree(p); });
-        HIPCK(launch_setup_count(S, d_counts, nullptr));
-        std::vector<int> counts(2 * L.nblocks);
-        HIPCK(hipMemcpy(counts.data(), d_counts, sizeof(int) * 2 * L.nblocks, hipMemcpyDeviceToHost));
+        HIPCK(hipMalloc(&d_fresh, sizeof(int) * std::max<size_t>(1, fresh.size())));
+        std::unique_ptr<int, void (*)(int *)> fresh_guard(d_fresh, [](int *p) { (void)hipFree(p); });
+        std::vector<int> counts(2 * L.nblocks, 0);
+        if (!fresh.empty()) {
+            HIPCK(hipMemcpy(d_fresh, fresh.data(), sizeof(int) * fresh.size(), hipMemcpyHostToDevice));
+            S.blocks = (int)fresh.size() == L.nblocks ? nullptr : d_fresh;
+            S.nlist = (int)fresh.size();
+            HIPCK(launch_setup_count(S, d_counts, nullptr));
+            HIPCK(hipMemcpy(counts.data(), d_counts, sizeof(int) * 2 * L.nblocks, hipMemcpyDeviceToHost));
+        }
+        for (int b = 0; b < L.nblocks; b++)
+            if (old_of[b] >= 0) {
+                counts[2 * b] = Lo->h_nrec[old_of[b]];
+                counts[2 * b + 1] = Lo->h_npt[old_of[b]];
+            }
         std::vector<int> rec_off(L.nblocks), pt_off(L.nblocks), map_off(L.nblocks, -1);
         int nrec = 0, nib = 0;
         long long npt = 0;
@@ -664,6 +688,15 @@ octmg_status octmg_geom_create(const octmg_geom_desc *d, int hip_device, octmg_g
             nrec += counts[2 * b];
             npt += counts[2 * b + 1];
         }
+        L.h_nrec.resize(L.nblocks);
+        L.h_npt.resize(L.nblocks);
+        for (int b = 0; b < L.nblocks; b++) {
+            L.h_nrec[b] = counts[2 * b];
+            L.h_npt[b] = counts[2 * b + 1];
+        }
+        L.h_rec_off = rec_off;
+        L.h_pt_off = pt_off;
+        L.h_map_off = map_off;
         L.nrec = nrec;
         L.npts = npt;
         L.n_iface_blocks = nib;
@@ -687,8 +720,28 @@ octmg_status octmg_geom_create(const octmg_geom_desc *d, int hip_device, octmg_g
             HIPCK(G->pool.alloc(&L.d_rec8f, (size_t)8 * nrec));
             HIPCK(G->pool.alloc(&L.d_pts, (size_t)3 * std::max<long long>(1, npt)));
             HIPCK(G->pool.alloc(&L.d_inside, (size_t)nrec));
-            HIPCK(launch_setup_emit(S, d_roff, d_poff, L.d_map_off, L.d_map, L.d_meta, L.d_d6, L.d_cfull, L.d_rec8,
-                                    L.d_rec8f, L.d_pts, L.d_inside, nullptr));
+            if (!fresh.empty())
+                HIPCK(launch_setup_emit(S, d_roff, d_poff, L.d_map_off, L.d_map, L.d_meta, L.d_d6, L.d_cfull, L.d_rec8,
+                                        L.d_rec8f, L.d_pts, L.d_inside, nullptr));
+            std::vector<ReuseBlock> keep;
+            for (int b = 0; b < L.nblocks; b++) {
+                const int ob = old_of[b];
+                if (ob < 0 || (counts[2 * b] == 0 && map_off[b] < 0)) continue;
+                keep.push_back({ob, b, Lo->h_rec_off[ob], rec_off[b], counts[2 * b], Lo->h_pt_off[ob], pt_off[b],
+                                counts[2 * b + 1], Lo->h_map_off[ob], map_off[b]});
+            }
+            if (stats)
+                for (const ReuseBlock &k : keep) stats[2] += k.nrec;
+            if (!keep.empty()) {
+                ReuseBlock *d_keep = nullptr;
+                HIPCK(hipMalloc(&d_keep, sizeof(ReuseBlock) * keep.size()));
+                std::unique_ptr<ReuseBlock, void (*)(ReuseBlock *)> g3(d_keep, [](ReuseBlock *p) { (void)hipFree(p); });
+                HIPCK(hipMemcpy(d_keep, keep.data(), sizeof(ReuseBlock) * keep.size(), hipMemcpyHostToDevice));
+                const ReuseArrays ra{Lo->d_map, Lo->d_meta, Lo->d_inside, Lo->d_d6, Lo->d_cfull, Lo->d_rec8,
+                                     Lo->d_pts, Lo->d_rec8f};
+                const ReuseArrays rb{L.d_map, L.d_meta, L.d_inside, L.d_d6, L.d_cfull, L.d_rec8, L.d_pts, L.d_rec8f};
+                HIPCK(launch_reuse_records(d_keep, (int)keep.size(), L.cpb, ra, rb, nullptr));
+            }
             HIPCK(hipDeviceSynchronize());
         }
         G->n_rec += nrec;
@@ -712,16 +765,59 @@ octmg_status octmg_geom_create(const octmg_geom_desc *d, int hip_device, octmg_g
         HIPCK(hipMemset(d_fail, 0, sizeof(int)));
         HIPCK(G->pool.alloc(&G->d_M, (size_t)n0 * n0));
         HIPCK(G->pool.alloc(&G->d_S, (size_t)n0));
-        int mo = -1;
-        HIPCK(hipMemcpy(&mo, L0.d_map_off, sizeof(int), hipMemcpyDeviceToHost));
-        HIPCK(launch_coarse_assemble(D, L0.Nb, L0.dx, mo >= 0 ? L0.d_map + mo : nullptr, L0.d_rec8,
-                                     G->desc.neumann_faces, d_A, nullptr));
-        HIPCK(launch_gauss_jordan(n0, d_A, G->d_M, G->d_S, d_fail, nullptr));
-        int hf = 0;
-        HIPCK(hipMemcpy(&hf, d_fail, sizeof(int), hipMemcpyDeviceToHost));
-        if (hf) return fail(OCTMG_ERR_GEOMETRY, "coarse-grid operator is singular");
+        if (coarse_kept) {
+            HIPCK(hipMemcpy(G->d_M, reuse->d_M, sizeof(double) * n0 * n0, hipMemcpyDeviceToDevice));
+            HIPCK(hipMemcpy(G->d_S, reuse->d_S, sizeof(double) * n0, hipMemcpyDeviceToDevice));
+        } else {
+            int mo = -1;
+            HIPCK(hipMemcpy(&mo, L0.d_map_off, sizeof(int), hipMemcpyDeviceToHost));
+            HIPCK(launch_coarse_assemble(D, L0.Nb, L0.dx, mo >= 0 ? L0.d_map + mo : nullptr, L0.d_rec8,
+                                         G->desc.neumann_faces, d_A, nullptr));
+            HIPCK(launch_gauss_jordan(n0, d_A, G->d_M, G->d_S, d_fail, nullptr));
+            int hf = 0;
+            HIPCK(hipMemcpy(&hf, d_fail, sizeof(int), hipMemcpyDeviceToHost));
+            if (hf) return fail(OCTMG_ERR_GEOMETRY, "coarse-grid operator is singular");
+        }
     }
+    if (stats) stats[3] += G->n_rec;
     HIPCK(hipDeviceSynchronize());
+    return OCTMG_OK;
+}
+
+octmg_status octmg_geom_create(const octmg_geom_desc *d, int hip_device, octmg_geom *out) {
+    STCK(validate_desc(d));
+    if (!out) return fail(OCTMG_ERR_INVALID, "null output");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(OCTMG_ERR_HIP, "no HIP device");
+    if (hip_device < 0 || hip_device >= ndev) return fail(OCTMG_ERR_INVALID, "bad device index");
+    HIPCK(hipSetDevice(hip_device));
+    std::unique_ptr<octmg_geom_s> G(new octmg_geom_s());
+    G->desc = *d;
+    G->params = copy_params(*d);
+    G->desc.lsf_params = G->params.data();
+    G->device = hip_device;
+    std::string err;
+    if (!build_tree(G->desc, &G->tree, &err)) return fail(OCTMG_ERR_INVALID, err);
+    STCK(setup_geometry(G.get(), nullptr, nullptr));
+    *out = G.release();
+    return OCTMG_OK;
+}
+
+octmg_status octmg_geom_adapt(octmg_geom g, const int8_t *flags, int reuse, octmg_geom *out, int64_t *stats) {
+    if (!g || !flags || !out) return fail(OCTMG_ERR_INVALID, "null argument");
+    *out = nullptr;
+    HIPCK(hipSetDevice(g->device));
+    std::unique_ptr<octmg_geom_s> G(new octmg_geom_s());
+    G->desc = g->desc;
+    G->params = g->params;
+    G->desc.lsf_params = G->params.data();
+    G->device = g->device;
+    std::string err;
+    if (!adapt_tree(G->desc, g->tree, flags, &G->tree, &err)) return fail(OCTMG_ERR_INVALID, err);
+    if (stats) std::memset(stats, 0, 4 * sizeof(int64_t));
+    STCK(setup_geometry(G.get(), reuse ? g : nullptr, stats));
+    if (stats) stats[3] -= stats[2];
     *out = G.release();
     return OCTMG_OK;
 }
@@ -1130,6 +1226,47 @@ octmg_status octmg_gradient(octmg_state s, int inside_zero, double *out, int on_
                               s->f64[il].pb, inside_zero, dv, 3LL * g->n_leaf, L.leaf_base, s->nrhs, st));
     }
     if (!on_device) HIPCK(hipMemcpyAsync(out, dv, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    return OCTMG_OK;
+}
+
+octmg_status octmg_state_remap(octmg_state from, octmg_state to, void *stream) {
+    if (!from || !to) return fail(OCTMG_ERR_INVALID, "null argument");
+    const octmg_geom go = from->geom, gn = to->geom;
+    if (go->tree.D != gn->tree.D || go->tree.N != gn->tree.N || go->tree.nsub != gn->tree.nsub ||
+        go->L.size() != gn->L.size() || from->nrhs != to->nrhs || go->device != gn->device)
+        return fail(OCTMG_ERR_INVALID, "states of incompatible geometries");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCK(hipSetDevice(gn->device));
+    const int D = gn->tree.D, nlev = (int)gn->L.size();
+    // every old cell, parent cells included, holds the mean of its leaves
+    for (int il = nlev - 1; il > 0; il--) {
+        LV<double> a = lv64(from, il), b = lv64(from, il - 1);
+        a.lanes = b.lanes = nullptr;
+        a.active = b.active = nullptr;
+        HIPCK(launch_restrict_phi<double>(D, go->L[il].Nb, go->L[il - 1].Nb, a, b, from->nrhs, st));
+    }
+    std::vector<LV<double>> old(nlev);
+    std::vector<int> nbo(nlev);
+    for (int il = 0; il < nlev; il++) {
+        old[il] = lv64(from, il);
+        old[il].lanes = nullptr;
+        old[il].active = nullptr;
+        nbo[il] = go->L[il].Nb;
+    }
+    DevPool tmp;
+    LV<double> *d_old = nullptr;
+    int *d_nb = nullptr;
+    HIPCK(tmp.alloc(&d_old, (size_t)nlev));
+    HIPCK(tmp.alloc(&d_nb, (size_t)nlev));
+    HIPCK(hipMemcpyAsync(d_old, old.data(), sizeof(LV<double>) * nlev, hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(d_nb, nbo.data(), sizeof(int) * nlev, hipMemcpyHostToDevice, st));
+    for (int il = 0; il < nlev; il++) {
+        const GeomLevel &L = gn->L[il];
+        HIPCK(launch_remap(D, L.Nb, lv64(to, il), il, d_old, d_nb, L.d_leaf_blocks, L.nleaf, to->nrhs, st));
+    }
+    Engine<double> e{to, st};
+    STCK(e.sync_down());
     HIPCK(hipStreamSynchronize(st));
     return OCTMG_OK;
 }

@@ -647,6 +647,77 @@ __global__ void k_gradient(LV<double> L, LV<double> Lc, const int *lb, const int
     }
 }
 
+// colour-split index for a block edge known only at run time
+__device__ __forceinline__ int split_rt(int D, int Nb, int i, int j, int k) {
+    const int cpb = D == 3 ? Nb * Nb * Nb : Nb * Nb;
+    return ((i + j + k) & 1) * (cpb / 2) + (k * Nb + j) * (Nb / 2) + (i >> 1);
+}
+
+// value of the old tree at level lv, global cell (x, y, z) (block must exist)
+__device__ __forceinline__ double old_value(int D, const LV<double> &L, int Nb, int b, int rhs, int x, int y, int z) {
+    const int cpb = D == 3 ? Nb * Nb * Nb : Nb * Nb;
+    return L.phi[(long long)rhs * L.fstride + (long long)b * cpb + split_rt(D, Nb, x % Nb, y % Nb, D == 3 ? z % Nb : 0)];
+}
+
+// phi of one level of an adapted tree from the previous tree (whose parent
+// cells hold the means of their children): the same cell where the old tree
+// has it; one level finer than the old tree: the cell-centred (3/4, 1/4)
+// interpolation of the old cells (a neighbour the old level lacks, or one
+// outside the domain, is replaced by the centre cell); deeper: the value of
+// the old cell containing the centre.
+template <int D, int N>
+__global__ void k_remap(LV<double> Ln, int il, const LV<double> *Lold, const int *nb_old, const int *lb) {
+    using B = Blk<D, N>;
+    const int blk = lb[blockIdx.x], rhs = blockIdx.y;
+    const int4 P = Ln.pos[blk];
+    double *dst = Ln.phi + (long long)rhs * Ln.fstride + (long long)blk * B::CPB;
+    for (int c = threadIdx.x; c < B::CPB; c += blockDim.x) {
+        const int i = c % N, j = (c / N) % N, k = D == 3 ? c / (N * N) : 0;
+        const int g[3] = {P.x * N + i, P.y * N + j, D == 3 ? P.z * N + k : 0};
+        const LV<double> &Ls = Lold[il];
+        int b = block_at<double, D>(Ls, g[0] / N, g[1] / N, D == 3 ? g[2] / N : 0);
+        double val;
+        if (b >= 0) {
+            val = old_value(D, Ls, N, b, rhs, g[0], g[1], g[2]);
+        } else {
+            int lv = il - 1, ga[3] = {g[0] >> 1, g[1] >> 1, g[2] >> 1};
+            for (; lv > 0; lv--) {
+                const int nb = nb_old[lv];
+                b = block_at<double, D>(Lold[lv], ga[0] / nb, ga[1] / nb, D == 3 ? ga[2] / nb : 0);
+                if (b >= 0) break;
+                for (int a = 0; a < 3; a++) ga[a] >>= 1;
+            }
+            const LV<double> &La = Lold[lv];
+            const int nb = nb_old[lv];
+            if (lv == 0) b = 0;
+            const double ctr = old_value(D, La, nb, b, rhs, ga[0], ga[1], ga[2]);
+            if (lv != il - 1) {
+                val = ctr;
+            } else {
+                val = 0.0;
+                for (int m = 0; m < (1 << D); m++) {
+                    int q[3] = {ga[0], ga[1], ga[2]};
+                    double w = 1.0;
+                    for (int a = 0; a < D; a++) {
+                        const bool far = (m >> a) & 1;
+                        w *= far ? 0.25 : 0.75;
+                        if (far) q[a] += (g[a] & 1) ? 1 : -1;
+                    }
+                    double v = ctr;
+                    bool inside = true;
+                    for (int a = 0; a < D; a++) inside = inside && q[a] >= 0 && q[a] < La.n;
+                    if (inside) {
+                        const int bq = block_at<double, D>(La, q[0] / nb, q[1] / nb, D == 3 ? q[2] / nb : 0);
+                        if (bq >= 0) v = old_value(D, La, nb, bq, rhs, q[0], q[1], q[2]);
+                    }
+                    val += w * v;
+                }
+            }
+        }
+        dst[split_of<D, N>(i, j, k)] = val;
+    }
+}
+
 template <int D, int N>
 __global__ void k_level_copy(double *split, double *canon, int to_split) {
     using B = Blk<D, N>;
@@ -1739,6 +1810,16 @@ hipError_t launch_gradient(int D, int N, const LV<double> &L, const LV<double> &
 #define GR(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_gradient<D_, N_>), grid, dim3(256), 0, s, L, Lc, lb, meta, d6, inside, pb, inside_zero, out, out_stride, base))
     GR(3, 16) GR(3, 8) GR(2, 8) GR(2, 16)
 #undef GR
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_remap(int D, int N, const LV<double> &Ln, int il, const LV<double> *Lold, const int *nb_old,
+                        const int *lb, int nlb, int nrhs, hipStream_t s) {
+    if (nlb == 0) return hipSuccess;
+    dim3 grid(nlb, nrhs);
+#define RM(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_remap<D_, N_>), grid, dim3(256), 0, s, Ln, il, Lold, nb_old, lb))
+    RM(3, 16) RM(3, 8) RM(2, 8) RM(2, 16)
+#undef RM
     return hipErrorInvalidValue;
 }
 

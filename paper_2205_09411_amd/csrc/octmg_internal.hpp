@@ -44,6 +44,11 @@ struct Tree {
 // balance over face, edge and corner neighbours (Sec. 2.1).  Returns false
 // with a message on invalid input.
 bool build_tree(const octmg_geom_desc &d, Tree *out, std::string *err);
+// The tree of `old` after its leaves (canonical leaf order: level, then Morton)
+// are flagged +1 refine (below max_level) or -1 coarsen (a family goes when
+// all its children are flagged leaves above uniform_level), then balanced
+// again.  The paper's setting: the mesh changes, the boundary does not.
+bool adapt_tree(const octmg_geom_desc &d, const Tree &old, const int8_t *flags, Tree *out, std::string *err);
 
 // Host evaluation of the built-in level sets (block-centre refinement test).
 double lsf_host(const octmg_geom_desc &d, const double *params, const double *x);
@@ -145,6 +150,10 @@ hipError_t launch_converge(const unsigned long long *norm, const double *thresh,
                            int nrhs, hipStream_t s);
 hipError_t launch_copy_d2f(const double *src, float *dst, long long n, hipStream_t s);
 hipError_t launch_check_finite(const double *p, long long n, int *flag, hipStream_t s);
+// phi of one level's leaf blocks of an adapted tree from the levels of the
+// previous tree (Lold[nlev] and their block edges in device memory)
+hipError_t launch_remap(int D, int N, const LV<double> &Ln, int il, const LV<double> *Lold, const int *nb_old,
+                        const int *lb, int nlb, int nrhs, hipStream_t s);
 // grad phi at the leaf cells of one level (Sec. 4.4: face differences, with
 // (phi_b - phi_i)/(d dx) across cut links), out[rhs][n_leaf][3] at leaf
 // offset base; inside_zero: cut cells with f(centre) < 0 get 0
@@ -165,7 +174,20 @@ struct SetupLevel {
     double mask_L;             // mask_factor * sqrt(D) * dx
     double w_min;
     int nbisect, ngolden;
+    const int *blocks = nullptr;  // if set: only these blocks (nlist of them)
+    int nlist = 0;
 };
+// a block whose records an adapted geometry copies from its predecessor
+struct ReuseBlock {
+    int old_blk, new_blk, old_roff, new_roff, nrec, old_poff, new_poff, npt, old_moff, new_moff;
+};
+struct ReuseArrays {
+    int *map, *meta, *inside;
+    double *d6, *cfull, *rec8, *pts;
+    float *rec8f;
+};
+hipError_t launch_reuse_records(const ReuseBlock *list, int nlist, int cpb, const ReuseArrays &o,
+                                const ReuseArrays &n, hipStream_t s);
 // pass 1: per block, the number of custom cells and of cut links
 hipError_t launch_setup_count(const SetupLevel &S, int *counts /*[nblocks][2]*/, hipStream_t s);
 // pass 2: records in canonical order at the given per-block offsets

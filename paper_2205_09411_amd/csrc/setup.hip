@@ -272,7 +272,7 @@ __device__ inline int split_index(int D, int N, int li) {
 constexpr int kSetupThreads = 256;
 
 __global__ __launch_bounds__(kSetupThreads) void k_setup_count(SetupLevel S, int *counts) {
-    const int blk = blockIdx.x;
+    const int blk = S.blocks ? S.blocks[blockIdx.x] : (int)blockIdx.x;
     const int cpb = S.D == 3 ? S.Nb * S.Nb * S.Nb : S.Nb * S.Nb;
     int nrec = 0, npt = 0;
     CellSetup R;
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup_emit(SetupLevel S, cons
                                                                const int *pt_off, const int *map_off, int *map,
                                                                int *meta, double *d6, double *cfull, double *rec8,
                                                                float *rec8f, double *pts, int *inside) {
-    const int blk = blockIdx.x;
+    const int blk = S.blocks ? S.blocks[blockIdx.x] : (int)blockIdx.x;
     const int cpb = S.D == 3 ? S.Nb * S.Nb * S.Nb : S.Nb * S.Nb;
     const int chunk = (cpb + blockDim.x - 1) / blockDim.x;
     const int c0 = threadIdx.x * chunk, c1 = min(cpb, c0 + chunk);
@@ -369,6 +369,36 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup_emit(SetupLevel S, cons
         }
         r++;
     }
+}
+
+// Records of a block that an adapted tree keeps unchanged (same level,
+// position and leaf status): copied from the previous geometry with their
+// block, record and point indices moved to the new offsets.
+__global__ void k_reuse_records(const ReuseBlock *list, int cpb, ReuseArrays o, ReuseArrays n) {
+    const ReuseBlock R = list[blockIdx.x];
+    for (int t = threadIdx.x; t < R.nrec; t += blockDim.x) {
+        const long ro = R.old_roff + t, rn = R.new_roff + t;
+        n.meta[4 * rn + 0] = R.new_blk;
+        n.meta[4 * rn + 1] = o.meta[4 * ro + 1];
+        n.meta[4 * rn + 2] = o.meta[4 * ro + 2];
+        n.meta[4 * rn + 3] = o.meta[4 * ro + 3] - R.old_poff + R.new_poff;
+        for (int k = 0; k < 6; k++) {
+            n.d6[6 * rn + k] = o.d6[6 * ro + k];
+            n.cfull[6 * rn + k] = o.cfull[6 * ro + k];
+        }
+        for (int k = 0; k < 8; k++) {
+            n.rec8[8 * rn + k] = o.rec8[8 * ro + k];
+            n.rec8f[8 * rn + k] = o.rec8f[8 * ro + k];
+        }
+        n.inside[rn] = o.inside[ro];
+    }
+    for (int t = threadIdx.x; t < 3 * R.npt; t += blockDim.x)
+        n.pts[3L * R.new_poff + t] = o.pts[3L * R.old_poff + t];
+    if (R.new_moff >= 0)
+        for (int c = threadIdx.x; c < cpb; c += blockDim.x) {
+            const int v = o.map[(long)R.old_moff + c];
+            n.map[(long)R.new_moff + c] = v >= 0 ? v - R.old_roff + R.new_roff : -1;
+        }
 }
 
 // Dense operator of the single-block coarsest grid (canonical cell order),
@@ -476,7 +506,9 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double *A, double 
 
 hipError_t launch_setup_count(const SetupLevel &S, int *counts, hipStream_t s) {
     if (S.nblocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_setup_count, dim3(S.nblocks), dim3(kSetupThreads), 0, s, S, counts);
+    const int grid = S.blocks ? S.nlist : S.nblocks;
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_setup_count, dim3(grid), dim3(kSetupThreads), 0, s, S, counts);
     return hipGetLastError();
 }
 
@@ -484,8 +516,17 @@ hipError_t launch_setup_emit(const SetupLevel &S, const int *rec_off, const int 
                              int *map, int *meta, double *d6, double *cfull, double *rec8, float *rec8f,
                              double *pts, int *inside, hipStream_t s) {
     if (S.nblocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_setup_emit, dim3(S.nblocks), dim3(kSetupThreads), 0, s, S, rec_off, pt_off, map_off, map,
+    const int grid = S.blocks ? S.nlist : S.nblocks;
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_setup_emit, dim3(grid), dim3(kSetupThreads), 0, s, S, rec_off, pt_off, map_off, map,
                        meta, d6, cfull, rec8, rec8f, pts, inside);
+    return hipGetLastError();
+}
+
+hipError_t launch_reuse_records(const ReuseBlock *list, int nlist, int cpb, const ReuseArrays &o,
+                                const ReuseArrays &n, hipStream_t s) {
+    if (nlist == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reuse_records, dim3(nlist), dim3(256), 0, s, list, cpb, o, n);
     return hipGetLastError();
 }
 

@@ -126,7 +126,9 @@ void add_children(std::vector<Occ> &occ, int l, int x, int y, int z) {
 
 }  // namespace
 
-bool build_tree(const octmg_geom_desc &d, Tree *out, std::string *err) {
+namespace {
+
+bool check_desc(const octmg_geom_desc &d, std::string *err) {
     const int D = d.dim, N = d.block_n, lmax = d.max_level;
     if (D != 2 && D != 3) { *err = "dim must be 2 or 3"; return false; }
     if (N != 8 && N != 16) { *err = "block_n must be 8 or 16"; return false; }
@@ -141,7 +143,10 @@ bool build_tree(const octmg_geom_desc &d, Tree *out, std::string *err) {
     if (d.neumann_faces < 0 || d.neumann_faces >= (1 << (2 * D))) { *err = "neumann_faces has bits beyond the 2D faces"; return false; }
     if (d.uniform_level < 0 || d.uniform_level > lmax) { *err = "bad uniform_level"; return false; }
 
-    // occupancy per tree level 1..lmax (index 0 unused)
+    return true;
+}
+
+std::vector<Occ> empty_occ(int D, int lmax) {
     std::vector<Occ> occ(lmax + 1);
     for (int l = 1; l <= lmax; l++) {
         occ[l].D = D;
@@ -150,28 +155,15 @@ bool build_tree(const octmg_geom_desc &d, Tree *out, std::string *err) {
         for (int a = 0; a < D; a++) cnt *= occ[l].nb;
         occ[l].bits.assign(cnt, 0);
     }
-    occ[1].bits[0] = 1;
-    for (int l = 1; l < lmax; l++) {
-        const int nb = occ[l].nb, nz = D == 3 ? nb : 1;
-        const double w = 1.0 / (double)nb;
-        for (int z = 0; z < nz; z++)
-            for (int y = 0; y < nb; y++)
-                for (int x = 0; x < nb; x++) {
-                    if (!occ[l].has(x, y, z)) continue;
-                    bool refine = true;
-                    if (d.refine_kind == OCTMG_REFINE_NEAR_INTERFACE && l >= d.uniform_level) {
-                        double c[3] = {d.lo[0] + ((double)x + 0.5) * w, d.lo[1] + ((double)y + 0.5) * w,
-                                       D == 3 ? d.lo[2] + ((double)z + 0.5) * w : 0.0};
-                        refine = std::fabs(lsf_host(d, d.lsf_params, c)) < d.refine_width * w;
-                    }
-                    if (refine) add_children(occ, l, x, y, z);
-                }
-    }
-    // 2:1 balance: a block at level l needs every neighbour region covered at
-    // level >= l-1, i.e. the level-(l-1) block containing each neighbour
-    // position must exist.  Missing ones are created by refining down from
-    // their deepest existing ancestor.  Processing fine to coarse handles the
-    // blocks this creates.
+    return occ;
+}
+
+// 2:1 balance: a block at level l needs every neighbour region covered at
+// level >= l-1, i.e. the level-(l-1) block containing each neighbour
+// position must exist.  Missing ones are created by refining down from
+// their deepest existing ancestor.  Processing fine to coarse handles the
+// blocks this creates.
+void balance(std::vector<Occ> &occ, int D, int lmax) {
     for (int l = lmax; l >= 3; l--) {
         const int nb = occ[l].nb, nz = D == 3 ? nb : 1;
         for (int z = 0; z < nz; z++)
@@ -207,6 +199,11 @@ bool build_tree(const octmg_geom_desc &d, Tree *out, std::string *err) {
                 }
     }
 
+}
+
+// levels (sub-root coarse levels first), Morton order, lookup tables, leaves
+bool finalize(const octmg_geom_desc &d, const std::vector<Occ> &occ, Tree *out, std::string *err) {
+    const int D = d.dim, N = d.block_n, lmax = d.max_level;
     Tree t;
     t.D = D;
     t.N = N;
@@ -256,6 +253,79 @@ bool build_tree(const octmg_geom_desc &d, Tree *out, std::string *err) {
     }
     *out = std::move(t);
     return true;
+}
+
+}  // namespace
+
+bool build_tree(const octmg_geom_desc &d, Tree *out, std::string *err) {
+    if (!check_desc(d, err)) return false;
+    const int D = d.dim, lmax = d.max_level;
+    std::vector<Occ> occ = empty_occ(D, lmax);
+    occ[1].bits[0] = 1;
+    for (int l = 1; l < lmax; l++) {
+        const int nb = occ[l].nb, nz = D == 3 ? nb : 1;
+        const double w = 1.0 / (double)nb;
+        for (int z = 0; z < nz; z++)
+            for (int y = 0; y < nb; y++)
+                for (int x = 0; x < nb; x++) {
+                    if (!occ[l].has(x, y, z)) continue;
+                    bool refine = true;
+                    if (d.refine_kind == OCTMG_REFINE_NEAR_INTERFACE && l >= d.uniform_level) {
+                        double c[3] = {d.lo[0] + ((double)x + 0.5) * w, d.lo[1] + ((double)y + 0.5) * w,
+                                       D == 3 ? d.lo[2] + ((double)z + 0.5) * w : 0.0};
+                        refine = std::fabs(lsf_host(d, d.lsf_params, c)) < d.refine_width * w;
+                    }
+                    if (refine) add_children(occ, l, x, y, z);
+                }
+    }
+    balance(occ, D, lmax);
+    return finalize(d, occ, out, err);
+}
+
+bool adapt_tree(const octmg_geom_desc &d, const Tree &old, const int8_t *flags, Tree *out, std::string *err) {
+    if (!check_desc(d, err)) return false;
+    const int D = d.dim, lmax = d.max_level;
+    std::vector<Occ> occ = empty_occ(D, lmax);
+    // the old blocks, and the flags of its leaves in canonical leaf order
+    std::vector<std::array<int, 5>> coarsen;  // level, x, y, z, -
+    long fi = 0;
+    for (size_t il = 0; il < old.lv.size(); il++) {
+        const int l = (int)il - old.nsub + 1;
+        const TreeLevel &T = old.lv[il];
+        for (int b = 0; b < T.nblocks(); b++) {
+            const int x = T.pos[3 * b], y = T.pos[3 * b + 1], z = T.pos[3 * b + 2];
+            if (l >= 1) occ[l].bits[occ[l].idx(x, y, z)] = 1;
+            if (!T.leaf[b]) continue;
+            const int f = flags[fi++];
+            if (l < 1) continue;
+            if (f > 0 && l < lmax) add_children(occ, l, x, y, z);
+            if (f < 0 && l > 1 && l > d.uniform_level) coarsen.push_back({l, x, y, z, 0});
+        }
+    }
+    // a parent loses its children only when all of them were leaves flagged
+    // for coarsening (and none was refined above)
+    std::vector<std::vector<uint8_t>> votes(lmax + 1);
+    for (int l = 1; l <= lmax; l++) votes[l].assign(occ[l].bits.size(), 0);
+    for (const auto &c : coarsen) votes[c[0] - 1][occ[c[0] - 1].idx(c[1] >> 1, c[2] >> 1, c[3] >> 1)]++;
+    const int nch = D == 3 ? 8 : 4;
+    for (int l = 2; l <= lmax; l++) {
+        const int nb = occ[l - 1].nb, nz = D == 3 ? nb : 1;
+        for (int z = 0; z < nz; z++)
+            for (int y = 0; y < nb; y++)
+                for (int x = 0; x < nb; x++) {
+                    if (votes[l - 1][occ[l - 1].idx(x, y, z)] != nch) continue;
+                    bool grand = false;  // a refined child keeps the family
+                    if (l < lmax)
+                        for (int c = 0; c < nch; c++)
+                            grand = grand || occ[l + 1].has(2 * (2 * x + (c & 1)), 2 * (2 * y + (c >> 1 & 1)),
+                                                            D == 3 ? 2 * (2 * z + (c >> 2)) : 0);
+                    if (grand) continue;
+                    for (int c = 0; c < nch; c++)
+                        occ[l].bits[occ[l].idx(2 * x + (c & 1), 2 * y + (c >> 1 & 1), D == 3 ? 2 * z + (c >> 2) : 0)] = 0;
+                }
+    }
+    balance(occ, D, lmax);
+    return finalize(d, occ, out, err);
 }
 
 }  // namespace octmg

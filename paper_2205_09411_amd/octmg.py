@@ -103,6 +103,8 @@ _SIGS = {
     "octmg_residual_norm": (C.c_int, [_vp, C.c_int, _dp, _vp]),
     "octmg_gradient": (C.c_int, [_vp, C.c_int, _vp, C.c_int, _vp]),
     "octmg_solve": (C.c_int, [_vp, C.POINTER(SolveOpts), _vp, C.POINTER(SolveReport)]),
+    "octmg_geom_adapt": (C.c_int, [_vp, _vp, C.c_int, C.POINTER(_vp), _i64p]),
+    "octmg_state_remap": (C.c_int, [_vp, _vp, _vp]),
     "octmg_state_set_launch": (C.c_int, [_vp, C.POINTER(LaunchConfig)]),
     "octmg_state_get_launch": (C.c_int, [_vp, C.POINTER(LaunchConfig)]),
     "octmg_autotune": (C.c_int, [_vp, C.POINTER(SolveOpts), C.c_int, _vp, C.POINTER(LaunchConfig), _dp, _ip]),
@@ -198,17 +200,43 @@ def _stream_ptr(stream):
 class Geometry:
     """Tree, FP64 interface setup and coarse inverse on one HIP device."""
 
-    def __init__(self, geom, device: int = 0):
+    def __init__(self, geom, device: int = 0, _handle=None):
         self.desc = make_desc(geom)
         self.geom = geom
-        h = _vp()
-        _check(lib().octmg_geom_create(C.byref(self.desc), device, C.byref(h)))
+        if _handle is None:
+            h = _vp()
+            _check(lib().octmg_geom_create(C.byref(self.desc), device, C.byref(h)))
+        else:
+            h = _handle
         self._h = h
         self.device = device
+        self._refresh()
+
+    def adapt(self, flags, reuse: bool = True):
+        """New geometry after refining (+1) / coarsening (-1) leaf blocks
+        (one flag per leaf block, canonical order); returns (geometry,
+        stats [blocks kept, blocks set up, records kept, records computed])."""
+        f = np.ascontiguousarray(flags, dtype=np.int8)
+        assert f.size == self.n_leaf_blocks, (f.size, self.n_leaf_blocks)
+        h = _vp()
+        stats = np.zeros(4, dtype=np.int64)
+        _check(lib().octmg_geom_adapt(self._h, f.ctypes.data, int(reuse), C.byref(h), _ptr(stats, C.c_int64)))
+        return Geometry(self.geom, self.device, _handle=h), stats
+
+    def leaf_blocks(self):
+        """(level, x, y, z) of every leaf block in canonical order."""
+        out = []
+        for il in range(self.n_levels):
+            pos, leaf = self.block_positions(il)
+            out.extend((il, *p) for p, lf in zip(pos, leaf) if lf)
+        return np.array(out, dtype=np.int64).reshape(-1, 4)
+
+    def _refresh(self):
         info = np.zeros(8, dtype=np.int64)
         _check(lib().octmg_geom_info(self._h, _ptr(info, C.c_int64)))
         (self.n_levels, self.n_leaf, self.n_iface, self.n_domain, self.n_records, self.device_bytes,
          self.n_blocks, self.n_iface_blocks) = (int(v) for v in info)
+        self.n_leaf_blocks = sum(self.level_info(il)["nleaf"] for il in range(self.n_levels))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -331,6 +359,10 @@ class State:
     def set_rhs(self, g, stream=None):
         p, od, keep = self._arr(g, self.geometry.n_leaf * self.n_rhs)
         _check(lib().octmg_set_rhs(self._h, p, od, _stream_ptr(stream)))
+
+    def remap_from(self, other: "State", stream=None):
+        """phi carried over from a state of the geometry this one was adapted from."""
+        _check(lib().octmg_state_remap(other._h, self._h, _stream_ptr(stream)))
 
     def set_solution(self, phi, stream=None):
         p, od, keep = self._arr(phi, self.geometry.n_leaf * self.n_rhs)

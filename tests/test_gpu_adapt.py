@@ -1,0 +1,155 @@
+"""Mesh adaptation: refining and coarsening a geometry's leaf blocks gives a
+tree and stencil records identical, bit for bit, to a setup from scratch of
+the same tree, while unchanged blocks keep their records; the adapted
+geometry solves in parity with the checker; phi carries over."""
+import numpy as np
+import pytest
+
+from paper_2205_09411_amd import octmg
+from paper_2205_09411_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def sphere_geom(dim, width, max_level=5):
+    params = np.array([0.45, 0.52, 0.5, 0.17, 0.7, 0.3, 0.6, 0.08]) if dim == 3 else \
+        np.array([0.45, 0.52, 0.0, 0.17, 0.7, 0.3, 0.0, 0.08])
+    return W.Geometry(dim=dim, block_n=8, max_level=max_level, lsf_kind=W.LSF_SPHERES, lsf_params=params,
+                      refine_kind=W.REFINE_NEAR_INTERFACE, refine_width=width, w_min=4e-3 if dim == 2 else 8e-3)
+
+
+def tree_of(geom):
+    """{(level, x, y, z): leaf} of a descriptor's tree (host plan)."""
+    out = {}
+    for il in range(len(octmg.plan_levels(geom))):
+        pos, leaf = octmg.plan_blocks(geom, il)
+        for p, lf in zip(pos, leaf):
+            out[(il, *map(int, p))] = int(lf)
+    return out
+
+
+def tree_of_geometry(G):
+    out = {}
+    for il in range(G.n_levels):
+        pos, leaf = G.block_positions(il)
+        for p, lf in zip(pos, leaf):
+            out[(il, *map(int, p))] = int(lf)
+    return out
+
+
+def adapt_towards(G, target, limit=6):
+    """Flag the leaves of G that `target` refines further (+1) or that
+    `target` does not have (-1) until G's tree equals it."""
+    stats = []
+    for _ in range(limit):
+        cur = tree_of_geometry(G)
+        if cur == target:
+            return G, stats
+        flags = []
+        for lb in G.leaf_blocks():
+            key = tuple(int(v) for v in lb)
+            if key in target and target[key] == 0:
+                flags.append(1)
+            elif key not in target:
+                flags.append(-1)
+            else:
+                flags.append(0)
+        G, st = G.adapt(np.array(flags), reuse=True)
+        stats.append(st)
+    assert tree_of_geometry(G) == target
+    return G, stats
+
+
+def same_geometry(Ga, Gb):
+    assert Ga.n_levels == Gb.n_levels and Ga.n_leaf == Gb.n_leaf and Ga.n_records == Gb.n_records
+    xa, la = Ga.leaf_coords()
+    xb, lb = Gb.leaf_coords()
+    assert np.array_equal(xa, xb) and np.array_equal(la, lb)
+    assert np.array_equal(Ga.iface_points(), Gb.iface_points())
+    assert np.array_equal(Ga.domain_points(), Gb.domain_points())
+    for il in range(Ga.n_levels):
+        for a, b in zip(Ga.records(il), Gb.records(il)):
+            assert np.array_equal(a, b), il
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_refine_then_coarsen_equals_setup_from_scratch(orc, dim):
+    print("adapt refine/coarsen", dim, flush=True)
+    narrow, wide = sphere_geom(dim, 0.5), sphere_geom(dim, 2.0)
+    G0 = octmg.Geometry(narrow)
+    Gr, st_r = adapt_towards(G0, tree_of(wide))
+    assert len(st_r) >= 1
+    kept = sum(int(s[2]) for s in st_r)
+    computed = sum(int(s[3]) for s in st_r)
+    print("refine steps", len(st_r), "records kept", kept, "computed", computed, flush=True)
+    assert kept > 0 and all(s[0] > 0 and s[1] > 0 for s in st_r)
+    Gw = octmg.Geometry(wide)
+    same_geometry(Gr, Gw)
+    # and back
+    Gc, st_c = adapt_towards(Gr, tree_of(narrow))
+    assert len(st_c) >= 1
+    same_geometry(Gc, octmg.Geometry(narrow))
+    # the adapted geometry solves in parity with the checker's own setup of it
+    w = W.Workload(wide, lambda x: np.sin(5 * x[:, 0]) * x[:, 1], lambda x: 1.0 + x[:, 0],
+                   lambda x: x[:, 1] * x[:, 1])
+    o = orc.setup_workload(w)
+    S = octmg.State(Gr)
+    S.set_boundary(w.iface_value(o.iface_points()), w.domain_value(o.domain_points()))
+    xyz, _ = o.leaf_coords()
+    S.set_rhs(w.rhs(xyz))
+    for k in range(3):
+        S.vcycle()
+        o.vcycle()
+        a, b = S.get_solution(), o.get_solution()
+        assert np.abs(a - b).max() <= 1e-10 * np.abs(b).max(), k
+
+
+def test_adapt_without_reuse_matches_and_flags_respected():
+    G0 = octmg.Geometry(sphere_geom(3, 0.5, max_level=4))
+    lbs = G0.leaf_blocks()
+    flags = np.zeros(len(lbs), dtype=np.int8)
+    flags[::7] = 1
+    Ga, sa = G0.adapt(flags, reuse=True)
+    Gb, sb = G0.adapt(flags, reuse=False)
+    same_geometry(Ga, Gb)
+    assert sb[0] == 0 and sb[2] == 0 and sa[2] > 0
+    tree = tree_of_geometry(Ga)
+    for (il, x, y, z), f in zip(lbs, flags):
+        if f and il < Ga.n_levels - 1:
+            assert tree[(int(il), int(x), int(y), int(z))] == 0  # refined: no longer a leaf
+    with pytest.raises(Exception):
+        G0.adapt(np.zeros(len(lbs) + 1, dtype=np.int8))
+
+
+def test_remap_carries_phi():
+    """phi carried from a solved coarser mesh: cells kept by the adaptation
+    are copied exactly, and a solve on the new mesh from the carried phi
+    needs fewer cycles than from zero."""
+    w_narrow = sphere_geom(3, 0.5)
+    G0 = octmg.Geometry(w_narrow)
+    rhs = lambda x: np.cos(4 * x[:, 0]) * x[:, 2]
+    bval = lambda x: 1.0 + x[:, 0] * x[:, 1]
+    S0 = octmg.State(G0)
+    S0.set_boundary_fn(bval, bval)
+    x0, l0 = G0.leaf_coords()
+    S0.set_rhs(rhs(x0))
+    S0.solve(rtol=1e-10)
+    flags = np.zeros(G0.n_leaf_blocks, dtype=np.int8)
+    flags[1::3] = 1
+    G1, _ = G0.adapt(flags)
+    S1 = octmg.State(G1)
+    S1.set_boundary_fn(bval, bval)
+    x1, l1 = G1.leaf_coords()
+    S1.set_rhs(rhs(x1))
+    S1.remap_from(S0)
+    carried = S1.get_solution()
+    # cells present in both meshes (same level and centre) are copied
+    key0 = {(int(l), *np.round(p * 4096).astype(int)): v for p, l, v in zip(x0, l0, S0.get_solution())}
+    common = [(i, key0[(int(l), *np.round(p * 4096).astype(int))]) for i, (p, l) in enumerate(zip(x1, l1))
+              if (int(l), *np.round(p * 4096).astype(int)) in key0]
+    assert len(common) > 0.1 * len(x1)
+    idx, vals = zip(*common)
+    assert np.array_equal(carried[list(idx)], np.array(vals))
+    warm = S1.solve(rtol=1e-10, zero_start=False).cycles
+    cold = S1.solve(rtol=1e-10, zero_start=True).cycles
+    assert warm < cold, (warm, cold)
