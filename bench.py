@@ -506,6 +506,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--block-order", type=int, default=None,
                     help="with --no-tune: block order of the 3D kernels (0 XCD ranges, 1 hardware, 2 octant walk)")
+    ap.add_argument("--pair-max-blocks", type=int, default=None,
+                    help="with --no-tune: largest launch (workgroups) of the 3D transfer and residual kernels "
+                         "that takes the 512-thread colour-pair variants")
     ap.add_argument("--legs", default="mixed,batched,adaptive,serving,table1,2d,sharp,electrodes,adapt",
                     help="extra measurements after the headline: mixed,batched,adaptive,serving,table1,2d,sharp,"
                          "electrodes,adapt or none")
@@ -546,8 +549,9 @@ def main():
     # launch configuration: the autotuner times every candidate (all give
     # identical iterates) and keeps the fastest
     if args.no_tune:
-        if args.block_order is not None:
-            S.set_launch(block_order=args.block_order)
+        if args.block_order is not None or args.pair_max_blocks is not None:
+            S.set_launch(block_order=args.block_order or 0,
+                         pair_max_blocks=(1 << 30) if args.pair_max_blocks is None else args.pair_max_blocks)
         tuned, cand_ms = S.get_launch(), []
     else:
         tuned, cand_ms = S.autotune(rtol=args.rtol, reps=2, stream=stream)

@@ -122,9 +122,15 @@ typedef struct octmg_state_s *octmg_state;
  *     bottom_max_blocks blocks run inside one cooperative launch (as
  *     octmg_state_set_fused_levels).
  *   graph_mode: the octmg_solve_opts.graph_mode recommended with it (a
- *     cooperative bottom cannot be captured: graph_mode 0 with bottom_kind 1). */
+ *     cooperative bottom cannot be captured: graph_mode 0 with bottom_kind 1).
+ *   pair_max_blocks: 3D launches of at most this many workgroups (blocks x
+ *     running right-hand sides) use 512 threads per block: restriction,
+ *     FAS right-hand side and residual stage the two colours at the same
+ *     time, prolongation and (16^3 blocks) the smoother give each thread
+ *     half the cells.  Larger launches use 256 threads.  0: never.
+ *     Default 1 << 30 (every launch). */
 typedef struct octmg_launch_config {
-    int block_order, bottom_kind, bottom_max_blocks, graph_mode;
+    int block_order, bottom_kind, bottom_max_blocks, graph_mode, pair_max_blocks;
 } octmg_launch_config;
 octmg_status octmg_state_set_launch(octmg_state s, const octmg_launch_config *c);
 octmg_status octmg_state_get_launch(octmg_state s, octmg_launch_config *c);
@@ -266,8 +272,10 @@ octmg_status octmg_solve(octmg_state s, const octmg_solve_opts *opts, void *stre
  * zero_start and graph_mode taken from each candidate) once to warm up and
  * `reps` times timed, under every candidate launch configuration (the three
  * block orders x {separate, separate in a per-cycle graph, cooperative
- * bottom up to 8 and to 64 blocks (3D)}), then keeps the fastest in the
- * state and returns it.  ms[i] (if not NULL, room for 12) receives the mean wall time
+ * bottom up to 8 and to 64 blocks (3D)}, with the 512-thread variants on
+ * every level, plus block order 0 {separate, per-cycle graph} with them on
+ * none), then keeps the fastest in the
+ * state and returns it.  ms[i] (if not NULL, room for 14) receives the mean wall time
  * per solve of candidate i, *n_candidates their number.  Afterwards phi
  * holds the solution (the same under every candidate). */
 octmg_status octmg_autotune(octmg_state s, const octmg_solve_opts *opts, int reps, void *stream,

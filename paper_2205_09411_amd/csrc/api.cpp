@@ -152,6 +152,7 @@ struct octmg_state_s {
     int block_order = 0;                       // LV::order of every level
     int tuned_graph = 0;                       // graph mode recommended by octmg_autotune
     int fused_max_blocks = 0;                  // levels with <= this many blocks run fused (0: off)
+    int pair_max_blocks = 1 << 30;             // LV::pair_max of every level
     int fused_top = 0;                         // highest fused level (0: none)
     int fused_grid64 = 0, fused_grid32 = 0;    // co-resident workgroups of the fused kernel
     SmallLevels<double> *d_small64 = nullptr;  // device copies of the fused level tables
@@ -204,6 +205,7 @@ LV<double> lv64(const octmg_state_s *s, int il) {
     v.lanes = s->n_launch < s->nrhs ? s->d_active + s->nrhs : nullptr;
     v.order = s->block_order;
     v.neumann = s->geom->desc.neumann_faces;
+    v.pair_max = s->pair_max_blocks;
     return v;
 }
 
@@ -234,6 +236,7 @@ LV<float> lv32(const octmg_state_s *s, int il) {
     v.lanes = s->n_launch < s->nrhs ? s->d_active + s->nrhs : nullptr;
     v.order = s->block_order;
     v.neumann = s->geom->desc.neumann_faces;
+    v.pair_max = s->pair_max_blocks;
     return v;
 }
 
@@ -437,20 +440,12 @@ void drop_graphs(octmg_state s) {
 
 // (re)build the device tables of the fused bottom of the V-cycle; captured
 // graphs bake in the cycle structure and are dropped
-octmg_status setup_fused(octmg_state s) {
-    drop_graphs(s);
-    s->fused_top = 0;
-    if (s->fused_max_blocks <= 0 || s->geom->tree.D != 3) return OCTMG_OK;
-    int ft = 0;
-    for (int il = 0; il < (int)s->geom->L.size() && il < kMaxSmallLevels; il++) {
-        if (s->geom->L[il].nblocks > s->fused_max_blocks) break;
-        ft = il;
-    }
-    if (ft < 1) return OCTMG_OK;
-    SmallLevels<double> h64{};
-    SmallLevels<float> h32{};
-    for (int il = 0; il <= ft; il++) {
-        // the fused kernel walks every rhs itself (flags skip finished ones)
+// level tables (device copies) of levels 0..top for the bottom kernels
+void bottom_tables(octmg_state s, int top, SmallLevels<double> &h64, SmallLevels<float> &h32) {
+    h64 = SmallLevels<double>{};
+    h32 = SmallLevels<float>{};
+    for (int il = 0; il <= top; il++) {
+        // these kernels walk every rhs themselves (flags skip finished ones)
         h64.L[il] = lv64(s, il);
         h64.L[il].lanes = nullptr;
         h64.N[il] = s->geom->L[il].Nb;
@@ -464,6 +459,21 @@ octmg_status setup_fused(octmg_state s) {
     h64.into_old = h32.into_old = s->geom->tree.adaptive ? 1 : 0;
     h64.M = h32.M = s->geom->d_M;
     h64.S = h32.S = s->geom->d_S;
+}
+
+octmg_status setup_fused(octmg_state s) {
+    drop_graphs(s);
+    s->fused_top = 0;
+    if (s->fused_max_blocks <= 0 || s->geom->tree.D != 3) return OCTMG_OK;
+    int ft = 0;
+    for (int il = 0; il < (int)s->geom->L.size() && il < kMaxSmallLevels; il++) {
+        if (s->geom->L[il].nblocks > s->fused_max_blocks) break;
+        ft = il;
+    }
+    if (ft < 1) return OCTMG_OK;
+    SmallLevels<double> h64;
+    SmallLevels<float> h32;
+    bottom_tables(s, ft, h64, h32);
     if (!s->d_small64) {
         HIPCK(s->pool.alloc(&s->d_small64, 1));
         HIPCK(s->pool.alloc(&s->d_small32, 1));
@@ -1082,11 +1092,12 @@ octmg_status octmg_state_set_fused_levels(octmg_state s, int max_blocks) {
 octmg_status octmg_state_set_launch(octmg_state s, const octmg_launch_config *c) {
     if (!s || !c) return fail(OCTMG_ERR_INVALID, "null argument");
     if (c->block_order < 0 || c->block_order > 2 || c->bottom_max_blocks < 0 || c->graph_mode < 0 ||
-        c->graph_mode > 2 || (c->bottom_kind != 0 && c->bottom_kind != 1))
+        c->graph_mode > 2 || (c->bottom_kind != 0 && c->bottom_kind != 1) || c->pair_max_blocks < 0)
         return fail(OCTMG_ERR_INVALID, "bad launch configuration");
     if (c->bottom_kind == 1 && c->graph_mode != 0)
         return fail(OCTMG_ERR_INVALID, "the cooperative bottom launch cannot be captured");
     s->block_order = c->block_order;
+    s->pair_max_blocks = c->pair_max_blocks;
     s->tuned_graph = c->graph_mode;
     s->fused_max_blocks = c->bottom_kind ? c->bottom_max_blocks : 0;
     HIPCK(hipSetDevice(s->geom->device));
@@ -1099,6 +1110,7 @@ octmg_status octmg_state_get_launch(octmg_state s, octmg_launch_config *c) {
     c->bottom_kind = s->fused_max_blocks > 0 ? 1 : 0;
     c->bottom_max_blocks = s->fused_max_blocks;
     c->graph_mode = s->tuned_graph;
+    c->pair_max_blocks = s->pair_max_blocks;
     return OCTMG_OK;
 }
 
@@ -1563,13 +1575,18 @@ octmg_status octmg_autotune(octmg_state s, const octmg_solve_opts *o, int reps, 
                             octmg_launch_config *best, double *ms, int *n_candidates) {
     if (!s || !o || !best || reps < 1) return fail(OCTMG_ERR_INVALID, "bad argument");
     std::vector<octmg_launch_config> cand;
+    constexpr int all = 1 << 30;
     for (int order = 0; order < 3; order++) {
-        cand.push_back({order, 0, 0, 0});
-        cand.push_back({order, 0, 0, 1});
+        cand.push_back({order, 0, 0, 0, all});
+        cand.push_back({order, 0, 0, 1, all});
         if (s->geom->tree.D == 3) {
-            cand.push_back({order, 1, 8, 0});
-            cand.push_back({order, 1, 64, 0});
+            cand.push_back({order, 1, 8, 0, all});
+            cand.push_back({order, 1, 64, 0, all});
         }
+    }
+    if (s->geom->tree.D == 3) {
+        cand.push_back({0, 0, 0, 0, 0});
+        cand.push_back({0, 0, 0, 1, 0});
     }
     if (n_candidates) *n_candidates = (int)cand.size();
     double best_ms = 0.0;

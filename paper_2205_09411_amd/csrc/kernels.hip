@@ -897,6 +897,16 @@ __device__ __forceinline__ void face_ids(const LV<T> &L, int blk, int nbk[6]) {
     nbk[5] = b.y;
 }
 
+// The per-block table loads (rhs flag, leaf flag, position, face
+// neighbours, record offset) are issued together and waited for once: the
+// empty asm takes them all as operands before the early exits, which keeps
+// the compiler from sinking the later ones below the exit tests (one
+// dependent memory round trip instead of two or three per launch).
+__device__ __forceinline__ void tables_loaded(int act, int leaf, int4 P, const int *nbk, int mo) {
+    asm volatile("" ::"s"(act), "s"(leaf), "s"(P.x), "s"(P.y), "s"(P.z), "s"(nbk[0]), "s"(nbk[1]), "s"(nbk[2]),
+                 "s"(nbk[3]), "s"(nbk[4]), "s"(nbk[5]), "s"(mo));
+}
+
 __device__ __forceinline__ bool any_coarser(const int *nbk) {
     return nbk[0] == -1 || nbk[1] == -1 || nbk[2] == -1 || nbk[3] == -1 || nbk[4] == -1 || nbk[5] == -1;
 }
@@ -909,10 +919,9 @@ __device__ __forceinline__ bool any_coarser(const int *nbk) {
 // staging.
 template <typename T, int N>
 __device__ void coarser_face_ghosts(T *tile, const LV<T> &Lc, const T *__restrict__ own_col, const T *phic,
-                                    const int *nbk, int4 P, int col) {
+                                    const int *nbk, int4 P, int col, int t) {
     using CT = ColTile<N>;
     constexpr int NH = N / 2;
-    const int t = threadIdx.x;
     if (t >= N * NH) return;
 #pragma unroll 1
     for (int d = 0; d < 6; d++) {
@@ -953,71 +962,95 @@ __device__ void coarser_face_ghosts(T *tile, const LV<T> &Lc, const T *__restric
 // Halo value across face d of the block for the reading cell (i, j, k) of
 // the other colour: the neighbour block's cell, or at a domain face the
 // Dirichlet ghost 2 phi_b - own (own: the reading cell's value; 0 for
-// ZERO); 0 at a coarser-level face (filled later by coarser_face_ghosts).
+// ZERO) or the zero-flux ghost own; 0 at a coarser-level face (filled later
+// by coarser_face_ghosts).  Split in two so that a thread's face loads all
+// leave before any is waited for: halo_load issues both loads from valid
+// addresses whatever the face type (a: neighbour cell or own value; b: face
+// value, else a repeat of a's address), halo_pick selects the result.
+template <typename T>
+struct HaloLoads {
+    T a, b;
+};
+
 template <typename T, int N, bool ZERO>
-__device__ __forceinline__ T halo_value(const LV<T> &L, const T *__restrict__ phi, const T *__restrict__ own_col,
-                                        int nb, long long nidx, int d, int4 P, int i, int j, int k, int oidx) {
-    if (nb >= 0) return ZERO ? T(0) : phi[(long long)nb * Blk<3, N>::CPB + nidx];
-    if (nb == -1) return T(0);
-    if (zero_flux(L.neumann, d >> 1, (d & 1) ? 1 : -1)) return ZERO ? T(0) : own_col[oidx];
-    const T bv = L.bcv ? L.bcv[face_slot<3>(d >> 1, (d & 1) ? 1 : -1, P.x * N + i, P.y * N + j, P.z * N + k, L.n,
-                                            L.nface)]
-                       : T(0);
-    const T own = ZERO ? T(0) : own_col[oidx];
-    return T(2) * bv - own;
+__device__ __forceinline__ HaloLoads<T> halo_load(const LV<T> &L, const T *__restrict__ phi,
+                                                  const T *__restrict__ own_col, int nb, long long nidx, int d,
+                                                  int4 P, int i, int j, int k, int oidx) {
+    const bool zf = zero_flux(L.neumann, d >> 1, (d & 1) ? 1 : -1);
+    const T *src = nb >= 0 ? phi + (long long)nb * Blk<3, N>::CPB + nidx : own_col + oidx;
+    const T *bsrc = nb == -2 && !zf && L.bcv ? L.bcv + face_slot<3>(d >> 1, (d & 1) ? 1 : -1, P.x * N + i,
+                                                                     P.y * N + j, P.z * N + k, L.n, L.nface)
+                                             : src;
+    return {ZERO ? T(0) : *src, *bsrc};
+}
+
+template <typename T, bool ZERO>
+__device__ __forceinline__ T halo_pick(const LV<T> &L, HaloLoads<T> h, int nb, int d) {
+    const bool zf = zero_flux(L.neumann, d >> 1, (d & 1) ? 1 : -1);
+    const T bv = nb == -2 && !zf && L.bcv ? h.b : T(0);
+    if (ZERO) return nb == -2 && !zf ? T(2) * bv : T(0);
+    return nb >= 0 ? h.a : (nb == -1 ? T(0) : (zf ? h.a : T(2) * bv - h.a));
 }
 
 // Stage colour `col` of block `blk` and its face halos into a ColTile, the
 // halos at domain faces as the Dirichlet ghosts seen by the cells of the
 // other colour.  All global loads of the thread are issued before the LDS
 // writes.
-template <typename T, int N, bool ZERO>
+// NT threads stage the colour (t < NT); the faces take the first N*N.
+template <typename T, int N, bool ZERO, int NT = 256>
 __device__ __forceinline__ void stage_colour(T *tile, const LV<T> &L, const T *__restrict__ phi, int blk,
-                                             const int *nbk, int4 P, int col, const T *interior = nullptr) {
+                                             const int *nbk, int4 P, int col, int t,
+                                             const T *interior = nullptr) {
     using B = Blk<3, N>;
     using CT = ColTile<N>;
-    constexpr int NH = N / 2, PER = Per<N>::PER;
-    const int t = threadIdx.x, oc = col * B::HALF, uc = (1 - col) * B::HALF;
+    constexpr int NH = N / 2, PER = B::HALF / NT;
+    const int oc = col * B::HALF, uc = (1 - col) * B::HALF;
     const T *__restrict__ own_col = phi + (long long)blk * B::CPB + uc;
     T r[PER];
     if (ZERO) {
-        for (int e = t; e < CT::SIZE; e += 256) tile[e] = T(0);
+        for (int e = t; e < CT::SIZE; e += NT) tile[e] = T(0);
     } else {
 #pragma unroll
-        for (int m = 0; m < PER; m++) r[m] = interior ? interior[m] : phi[(long long)blk * B::CPB + oc + t + 256 * m];
+        for (int m = 0; m < PER; m++) r[m] = interior ? interior[m] : phi[(long long)blk * B::CPB + oc + t + NT * m];
     }
     const int ucol = 1 - col;
     const int fh = t % NH, fr = t / NH;  // y/z face entry (N*NH <= 256)
     const int xj = t % N, xk = t / N;    // x face entry (N*N <= 256)
     const bool fz = t < N * NH, fx = t < N * N;
-    T y0 = T(0), y1 = T(0), z0 = T(0), z1 = T(0), x0 = T(0), x1 = T(0);
+    HaloLoads<T> hy0{}, hy1{}, hz0{}, hz1{}, hx0{}, hx1{};
     if (fz) {
         // y faces: entry (k = fr, h = fh); z faces: entry (j = fr, h = fh)
         const int ky = fr, jz = fr;
-        y0 = halo_value<T, N, ZERO>(L, phi, own_col, nbk[2], oc + (ky * N + N - 1) * NH + fh, 2, P,
+        hy0 = halo_load<T, N, ZERO>(L, phi, own_col, nbk[2], oc + (ky * N + N - 1) * NH + fh, 2, P,
                                     2 * fh + ((ucol + ky) & 1), 0, ky, (ky * N) * NH + fh);
-        y1 = halo_value<T, N, ZERO>(L, phi, own_col, nbk[3], oc + (ky * N) * NH + fh, 3, P,
+        hy1 = halo_load<T, N, ZERO>(L, phi, own_col, nbk[3], oc + (ky * N) * NH + fh, 3, P,
                                     2 * fh + ((ucol + N - 1 + ky) & 1), N - 1, ky, (ky * N + N - 1) * NH + fh);
-        z0 = halo_value<T, N, ZERO>(L, phi, own_col, nbk[4], oc + ((N - 1) * N + jz) * NH + fh, 4, P,
+        hz0 = halo_load<T, N, ZERO>(L, phi, own_col, nbk[4], oc + ((N - 1) * N + jz) * NH + fh, 4, P,
                                     2 * fh + ((ucol + jz) & 1), jz, 0, jz * NH + fh);
-        z1 = halo_value<T, N, ZERO>(L, phi, own_col, nbk[5], oc + jz * NH + fh, 5, P,
+        hz1 = halo_load<T, N, ZERO>(L, phi, own_col, nbk[5], oc + jz * NH + fh, 5, P,
                                     2 * fh + ((ucol + jz + N - 1) & 1), jz, N - 1, ((N - 1) * N + jz) * NH + fh);
     }
     if (fx) {
         // x faces: entry (j = xj, k = xk); the halo slot is read only by rows
-        // whose reading cell sits on the face (i = 0, resp. i = N-1)
-        const int p = (ucol + xj + xk) & 1;
-        if (p == 0 || nbk[0] >= 0)
-            x0 = halo_value<T, N, ZERO>(L, phi, own_col, nbk[0], oc + (xk * N + xj) * NH + NH - 1, 0, P, 0, xj, xk,
-                                        (xk * N + xj) * NH);
-        if (p == 1 || nbk[1] >= 0)
-            x1 = halo_value<T, N, ZERO>(L, phi, own_col, nbk[1], oc + (xk * N + xj) * NH, 1, P, N - 1, xj, xk,
-                                        (xk * N + xj) * NH + NH - 1);
+        // whose reading cell sits on the face (i = 0, resp. i = N-1); on the
+        // other rows the value is unused
+        hx0 = halo_load<T, N, ZERO>(L, phi, own_col, nbk[0], oc + (xk * N + xj) * NH + NH - 1, 0, P, 0, xj, xk,
+                                    (xk * N + xj) * NH);
+        hx1 = halo_load<T, N, ZERO>(L, phi, own_col, nbk[1], oc + (xk * N + xj) * NH, 1, P, N - 1, xj, xk,
+                                    (xk * N + xj) * NH + NH - 1);
     }
+    // one wait for all face loads (the empty asm consumes them; without it
+    // the compiler moves each face's second load into a branch and waits
+    // for it there, one round trip per face)
+    asm volatile("" ::"v"(hy0.a), "v"(hy0.b), "v"(hy1.a), "v"(hy1.b), "v"(hz0.a), "v"(hz0.b), "v"(hz1.a),
+                 "v"(hz1.b), "v"(hx0.a), "v"(hx0.b), "v"(hx1.a), "v"(hx1.b));
+    const T y0 = halo_pick<T, ZERO>(L, hy0, nbk[2], 2), y1 = halo_pick<T, ZERO>(L, hy1, nbk[3], 3);
+    const T z0 = halo_pick<T, ZERO>(L, hz0, nbk[4], 4), z1 = halo_pick<T, ZERO>(L, hz1, nbk[5], 5);
+    const T x0 = halo_pick<T, ZERO>(L, hx0, nbk[0], 0), x1 = halo_pick<T, ZERO>(L, hx1, nbk[1], 1);
     if (!ZERO) {
 #pragma unroll
         for (int m = 0; m < PER; m++) {
-            const int q = t + 256 * m;
+            const int q = t + NT * m;
             tile[CT::at(q / (NH * N), (q / NH) % N, q % NH)] = r[m];
         }
     } else {
@@ -1053,17 +1086,17 @@ __device__ __forceinline__ void tile_neighbours(const T *tile, int col, int q, i
     v[5] = tile[CT::at(k + 1, j, h)];
 }
 
-// red-black half sweep
-template <typename T, int N>
+// red-black half sweep, NT threads per block
+template <typename T, int N, int NT = 256>
 __device__ __forceinline__ void gs_half3_body(const LV<T> &L, const LV<T> &Lc, int color, int blk, int rhs, T *tile) {
     using B = Blk<3, N>;
-    constexpr int PER = Per<N>::PER;
-    // the block's tables and the rhs flag are loaded together
-    const int act = L.active ? L.active[rhs] : 1;
+    constexpr int PER = B::HALF / NT;
     const int4 P = L.pos[blk];
     int nbk[6];
     face_ids<T, N>(L, blk, nbk);
     const int mo = L.map_off ? L.map_off[blk] : -1;
+    const int act = L.active ? L.active[rhs] : 1;
+    tables_loaded(act, 1, P, nbk, mo);
     if (!act) return;
     T *__restrict__ phi = L.phi + (long long)rhs * L.fstride;
     const long long base = (long long)blk * B::CPB;
@@ -1074,21 +1107,21 @@ __device__ __forceinline__ void gs_half3_body(const LV<T> &L, const LV<T> &Lc, i
     for (int m = 0; m < PER; m++) {
         // g is read once per sweep: keep it from evicting the phi lines
         // that neighbouring blocks read as halos
-        gv[m] = __builtin_nontemporal_load(gm + threadIdx.x + 256 * m);
-        ri[m] = mo >= 0 ? L.map[mo + color * B::HALF + threadIdx.x + 256 * m] : -1;
+        gv[m] = __builtin_nontemporal_load(gm + threadIdx.x + NT * m);
+        ri[m] = mo >= 0 ? L.map[mo + color * B::HALF + threadIdx.x + NT * m] : -1;
     }
-    stage_colour<T, N, false>(tile, L, phi, blk, nbk, P, 1 - color);
+    stage_colour<T, N, false, NT>(tile, L, phi, blk, nbk, P, 1 - color, threadIdx.x);
     __syncthreads();
     T *__restrict__ dst = phi + base + color * B::HALF;
     if (any_coarser(nbk)) {
         const T *phic = Lc.phi ? Lc.phi + (long long)rhs * Lc.fstride : nullptr;
-        coarser_face_ghosts<T, N>(tile, Lc, dst, phic, nbk, P, color);
+        coarser_face_ghosts<T, N>(tile, Lc, dst, phic, nbk, P, color, threadIdx.x);
         __syncthreads();
     }
     const T inv6 = T(1) / T(6);
 #pragma unroll
     for (int m = 0; m < PER; m++) {
-        const int q = threadIdx.x + 256 * m;
+        const int q = threadIdx.x + NT * m;
         int i, j, k;
         T v[6];
         tile_neighbours<T, N>(tile, color, q, i, j, k, v);
@@ -1107,22 +1140,21 @@ __device__ __forceinline__ void gs_half3_body(const LV<T> &L, const LV<T> &Lc, i
     }
 }
 
-template <typename T, int N>
-__global__ __launch_bounds__(256) void k_gs_half3(LV<T> L, LV<T> Lc, int color) {
-    using B = Blk<3, N>;
-    constexpr int PER = Per<N>::PER;
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(NT) void k_gs_half3(LV<T> L, LV<T> Lc, int color) {
     __shared__ T tile[ColTile<N>::SIZE];
-    gs_half3_body<T, N>(L, Lc, color, block_of(L), rhs_of(L), tile);
+    gs_half3_body<T, N, NT>(L, Lc, color, block_of(L), rhs_of(L), tile);
 }
 
 // L phi at the PER cells of colour `col` owned by this thread, from the
 // other-colour tile (already staged, ghosts filled); `own` their values.
 template <typename T, int N>
-__device__ __forceinline__ void tile_op(const LV<T> &L, const T *tile, const int *ri, int col, const T *own, T *out) {
+__device__ __forceinline__ void tile_op(const LV<T> &L, const T *tile, const int *ri, int col, const T *own, T *out,
+                                        int t) {
     constexpr int PER = Per<N>::PER;
 #pragma unroll
     for (int m = 0; m < PER; m++) {
-        const int q = threadIdx.x + 256 * m;
+        const int q = t + 256 * m;
         int i, j, k;
         T v[6];
         tile_neighbours<T, N>(tile, col, q, i, j, k, v);
@@ -1145,14 +1177,14 @@ template <typename T, int N, bool ZERO>
 __device__ __forceinline__ void colour_pass(const LV<T> &L, const LV<T> &Lc, const T *phi, const T *phic, T *tile,
                                             int blk, const int *nbk, int4 P, const int *ri, int col, const T *own,
                                             const T *interior, T *out) {
-    stage_colour<T, N, ZERO>(tile, L, phi, blk, nbk, P, 1 - col, interior);
+    stage_colour<T, N, ZERO>(tile, L, phi, blk, nbk, P, 1 - col, threadIdx.x, interior);
     __syncthreads();
     if (!ZERO && any_coarser(nbk)) {
         coarser_face_ghosts<T, N>(tile, Lc, phi + (long long)blk * Blk<3, N>::CPB + col * Blk<3, N>::HALF, phic, nbk,
-                                  P, col);
+                                  P, col, threadIdx.x);
         __syncthreads();
     }
-    tile_op<T, N>(L, tile, ri, col, own, out);
+    tile_op<T, N>(L, tile, ri, col, own, out, threadIdx.x);
 }
 
 // own values of colour 1 read back from the colour-1 tile of the first pass
@@ -1187,11 +1219,12 @@ __device__ __forceinline__ void restrict_fas3_body(const LV<T> &L, const LV<T> &
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER, H = N / 2, NCELL = H * H * H, CPER = (NCELL + 255) / 256;
     constexpr int SM = ColTile<N>::SIZE > B::CPB ? ColTile<N>::SIZE : B::CPB;
-    const int act = L.active ? L.active[rhs] : 1;
     const int4 P = L.pos[blk];
     int nbk[6];
     face_ids<T, N>(L, blk, nbk);
     const int mo = L.map_off ? L.map_off[blk] : -1;
+    const int act = L.active ? L.active[rhs] : 1;
+    tables_loaded(act, 1, P, nbk, mo);
     if (!act) return;
     const T *__restrict__ phi = L.phi + (long long)rhs * L.fstride;
     const T *__restrict__ g = L.g + (long long)rhs * L.fstride;
@@ -1283,12 +1316,13 @@ template <typename T, int N>
 __device__ __forceinline__ void fas_rhs3_body(const LV<T> &L, const LV<T> &Lc, int do_rhs, int blk, int rhs, T *tile) {
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER;
-    const int act = L.active ? L.active[rhs] : 1;
     const int leaf = L.leaf[blk];
     const int4 P = L.pos[blk];
     int nbk[6];
     face_ids<T, N>(L, blk, nbk);
     const int mo = L.map_off ? L.map_off[blk] : -1;
+    const int act = L.active ? L.active[rhs] : 1;
+    tables_loaded(act, leaf, P, nbk, mo);
     if (!act) return;
     T *phi = L.phi + (long long)rhs * L.fstride;
     T *g = L.g + (long long)rhs * L.fstride;
@@ -1331,6 +1365,186 @@ __global__ __launch_bounds__(256) void k_fas_rhs3(LV<T> L, LV<T> Lc, int do_rhs)
     fas_rhs3_body<T, N>(L, Lc, do_rhs, block_of(L), rhs_of(L), tile);
 }
 
+// ------------------------------------------- colour-pair variants (3D)
+// Workgroups of 512 threads in which wave group c = threadIdx.x / 256 owns
+// the cells of colour c.  Each group stages its own colour, with the halos
+// seen by the other colour, into its own tile, so both tiles fill in one
+// round of loads; after the refinement-boundary ghosts each group applies L
+// to its colour from the other group's tile.  The arithmetic is that of the
+// two-pass kernels above, term by term, so the results are the same bits;
+// only the latency differs (one dependent load round instead of two), which
+// is what bounds the levels with few blocks.
+template <typename T, int N>
+struct PairTiles {
+    static constexpr int SIZE = 2 * ColTile<N>::SIZE;
+};
+
+// L phi at this thread's PER cells of colour c; `own` holds their values
+// (registers), `tiles` two ColTiles.  Every thread of the workgroup calls it.
+template <typename T, int N>
+__device__ __forceinline__ void pair_op(const LV<T> &L, const LV<T> &Lc, const T *phi, const T *phic, T *tiles,
+                                        int blk, const int *nbk, int4 P, const int *ri, const T *own, T *out) {
+    const int c = threadIdx.x >> 8, t = threadIdx.x & 255;
+    T *mine = tiles + c * ColTile<N>::SIZE, *other = tiles + (1 - c) * ColTile<N>::SIZE;
+    stage_colour<T, N, false>(mine, L, phi, blk, nbk, P, c, t, own);
+    __syncthreads();
+    if (any_coarser(nbk)) {
+        coarser_face_ghosts<T, N>(other, Lc, phi + (long long)blk * Blk<3, N>::CPB + c * Blk<3, N>::HALF, phic, nbk,
+                                  P, c, t);
+        __syncthreads();
+    }
+    tile_op<T, N>(L, other, ri, c, own, out, t);
+}
+
+template <typename T, int N, int NC>
+__global__ __launch_bounds__(512) void k_restrict_fas3_pair(LV<T> L, LV<T> Lc, int into_old) {
+    using B = Blk<3, N>;
+    constexpr int PER = Per<N>::PER, H = N / 2, NCELL = H * H * H;
+    constexpr int SM = PairTiles<T, N>::SIZE > 2 * B::CPB ? PairTiles<T, N>::SIZE : 2 * B::CPB;
+    __shared__ T sm[SM];
+    const int blk = block_of(L), rhs = rhs_of(L);
+    const int c = threadIdx.x >> 8, t = threadIdx.x & 255;
+    const int4 P = L.pos[blk];
+    int nbk[6];
+    face_ids<T, N>(L, blk, nbk);
+    const int mo = L.map_off ? L.map_off[blk] : -1;
+    const int act = L.active ? L.active[rhs] : 1;
+    tables_loaded(act, 1, P, nbk, mo);
+    if (!act) return;
+    const T *__restrict__ phi = L.phi + (long long)rhs * L.fstride;
+    const T *__restrict__ g = L.g + (long long)rhs * L.fstride;
+    const T *phic = Lc.phi + (long long)rhs * Lc.fstride;
+    const long long base = (long long)blk * B::CPB + c * B::HALF;
+    T own[PER], r[PER], gv[PER];
+    int ri[PER];
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        const int s = t + 256 * m;
+        own[m] = phi[base + s];
+        gv[m] = g[base + s];
+        ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + s] : -1;
+    }
+    pair_op<T, N>(L, Lc, phi, phic, sm, blk, nbk, P, ri, own, r);
+#pragma unroll
+    for (int m = 0; m < PER; m++) r[m] = gv[m] - r[m];
+    __syncthreads();  // the tiles become the natural-order arrays of r and phi
+    T *sr = sm, *sp = sm + B::CPB;
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        int i, j, k;
+        q_to_ijk<N>(c, t + 256 * m, i, j, k);
+        sr[(k * N + j) * N + i] = r[m];
+        sp[(k * N + j) * N + i] = own[m];
+    }
+    __syncthreads();
+    T *phiw = (into_old ? Lc.old : Lc.phi) + (long long)rhs * Lc.fstride;
+    T *gw = Lc.g + (long long)rhs * Lc.fstride;
+    const int C0[3] = {P.x * H, P.y * H, P.z * H};
+    const int pb = block_at<T, 3>(Lc, C0[0] / NC, C0[1] / NC, C0[2] / NC);
+    if (pb < 0) return;  // excluded by construction: every block has a parent
+    const T inv = T(0.125);
+    for (int cc = threadIdx.x; cc < NCELL; cc += 512) {
+        const int ci = cc % H, cj = (cc / H) % H, ck = cc / (H * H);
+        T rs = T(0), ps = T(0);
+#pragma unroll
+        for (int ch = 0; ch < 8; ch++) {
+            const int e = ((2 * ck + ((ch >> 2) & 1)) * N + 2 * cj + ((ch >> 1) & 1)) * N + 2 * ci + (ch & 1);
+            rs += sr[e];
+            ps += sp[e];
+        }
+        const int gi = C0[0] + ci, gj = C0[1] + cj, gk = C0[2] + ck;
+        const long long o = (long long)pb * Blk<3, NC>::CPB + split_of<3, NC>(gi % NC, gj % NC, gk % NC);
+        phiw[o] = ps * inv;
+        gw[o] = rs * inv;
+    }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(512) void k_fas_rhs3_pair(LV<T> L, LV<T> Lc, int do_rhs) {
+    using B = Blk<3, N>;
+    constexpr int PER = Per<N>::PER;
+    __shared__ T tiles[PairTiles<T, N>::SIZE];
+    const int blk = block_of(L), rhs = rhs_of(L);
+    const int c = threadIdx.x >> 8, t = threadIdx.x & 255;
+    const int leaf = L.leaf[blk];
+    const int4 P = L.pos[blk];
+    int nbk[6];
+    face_ids<T, N>(L, blk, nbk);
+    const int mo = L.map_off ? L.map_off[blk] : -1;
+    const int act = L.active ? L.active[rhs] : 1;
+    tables_loaded(act, leaf, P, nbk, mo);
+    if (!act) return;
+    const T *phi = L.phi + (long long)rhs * L.fstride;
+    T *g = L.g + (long long)rhs * L.fstride;
+    T *old = L.old + (long long)rhs * L.fstride;
+    if (leaf || !do_rhs) {
+        const long long b0 = (long long)blk * B::CPB;
+        for (int s = threadIdx.x; s < B::CPB; s += 512) old[b0 + s] = phi[b0 + s];
+        return;
+    }
+    const T *phic = Lc.phi ? Lc.phi + (long long)rhs * Lc.fstride : nullptr;
+    const long long base = (long long)blk * B::CPB + c * B::HALF;
+    T own[PER], lp[PER], gv[PER];
+    int ri[PER];
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        const int s = t + 256 * m;
+        own[m] = phi[base + s];
+        gv[m] = g[base + s];
+        ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + s] : -1;
+    }
+    pair_op<T, N>(L, Lc, phi, phic, tiles, blk, nbk, P, ri, own, lp);
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        const int s = t + 256 * m;
+        g[base + s] = lp[m] + gv[m];
+        old[base + s] = own[m];
+    }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(512) void k_residual_max3_pair(LV<T> L, LV<T> Lc, unsigned long long *out) {
+    using B = Blk<3, N>;
+    constexpr int PER = Per<N>::PER;
+    __shared__ T tiles[PairTiles<T, N>::SIZE];
+    __shared__ double wmax[8];
+    const int blk = block_of(L), rhs = rhs_of(L);
+    const int c = threadIdx.x >> 8, t = threadIdx.x & 255;
+    const int leaf = L.leaf[blk];
+    const int4 P = L.pos[blk];
+    int nbk[6];
+    face_ids<T, N>(L, blk, nbk);
+    const int mo = L.map_off ? L.map_off[blk] : -1;
+    const int act = L.active ? L.active[rhs] : 1;
+    tables_loaded(act, leaf, P, nbk, mo);
+    if (!act || !leaf) return;
+    const T *__restrict__ phi = L.phi + (long long)rhs * L.fstride;
+    const T *__restrict__ g = L.g + (long long)rhs * L.fstride;
+    const T *phic = Lc.phi ? Lc.phi + (long long)rhs * Lc.fstride : nullptr;
+    const long long base = (long long)blk * B::CPB + c * B::HALF;
+    T own[PER], lp[PER], gv[PER];
+    int ri[PER];
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        const int s = t + 256 * m;
+        own[m] = phi[base + s];
+        gv[m] = g[base + s];
+        ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + s] : -1;
+    }
+    pair_op<T, N>(L, Lc, phi, phic, tiles, blk, nbk, P, ri, own, lp);
+    double mx = 0.0;
+#pragma unroll
+    for (int m = 0; m < PER; m++) mx = fmax(mx, fabs((double)(gv[m] - lp[m])));
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
+    if (threadIdx.x % 64 == 0) wmax[threadIdx.x / 64] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 8; w++) mx = fmax(mx, wmax[w]);
+        if (mx != mx) mx = __longlong_as_double(0x7ff0000000000000ll);
+        atomicMax(out + rhs, (unsigned long long)__double_as_longlong(mx));
+    }
+}
+
 // max |g - L phi| over a leaf block (3D); ZERO: residual of phi = 0
 template <typename T, int N, bool ZERO>
 __global__ __launch_bounds__(256) void k_residual_max3(LV<T> L, LV<T> Lc, unsigned long long *out) {
@@ -1338,12 +1552,13 @@ __global__ __launch_bounds__(256) void k_residual_max3(LV<T> L, LV<T> Lc, unsign
     constexpr int PER = Per<N>::PER;
     const int blk = block_of(L);
     const int rhs = rhs_of(L);
-    const int act = L.active ? L.active[rhs] : 1;
     const int leaf = L.leaf[blk];
     const int4 P = L.pos[blk];
     int nbk[6];
     face_ids<T, N>(L, blk, nbk);
     const int mo = L.map_off ? L.map_off[blk] : -1;
+    const int act = L.active ? L.active[rhs] : 1;
+    tables_loaded(act, leaf, P, nbk, mo);
     if (!act || !leaf) return;
     __shared__ T tile[ColTile<N>::SIZE];
     __shared__ double wmax[4];
@@ -1389,27 +1604,41 @@ __global__ __launch_bounds__(256) void k_residual_max3(LV<T> L, LV<T> Lc, unsign
 
 // prolongation, 3D: the coarse correction of the parent region (plus a
 // one-cell halo) is staged in LDS, then every fine cell is updated once.
-template <typename T, int N, int NC, bool SOL>
+// NT threads per workgroup; all coarse loads of a thread are issued before
+// its LDS writes.
+template <typename T, int N, int NC, bool SOL, int NT>
 __device__ __forceinline__ void prolong3_body(const LV<T> &L, const LV<T> &Lc, int blk, int rhs, T *et) {
     using B = Blk<3, N>;
-    constexpr int H = N / 2, E = H + 2, ESZ = E * E * E, PER = B::CPB / 256;
-    if (L.active && !L.active[rhs]) return;
+    constexpr int H = N / 2, E = H + 2, ESZ = E * E * E, PER = B::CPB / NT, EPER = (ESZ + NT - 1) / NT;
     const int4 P = L.pos[blk];
+    const int act = L.active ? L.active[rhs] : 1;
+    asm volatile("" ::"s"(act), "s"(P.x), "s"(P.y), "s"(P.z));  // both loads in one round trip
+    if (!act) return;
     const T *phic = Lc.phi + (long long)rhs * Lc.fstride;
     const T *oldc = Lc.old + (long long)rhs * Lc.fstride;
     T *__restrict__ phi = L.phi + (long long)rhs * L.fstride + (long long)blk * B::CPB;
     T f[PER];
 #pragma unroll
-    for (int m = 0; m < PER; m++) f[m] = phi[threadIdx.x + 256 * m];
+    for (int m = 0; m < PER; m++) f[m] = phi[threadIdx.x + NT * m];
     const int C0[3] = {P.x * H, P.y * H, P.z * H};
-    for (int e = threadIdx.x; e < ESZ; e += 256) {
-        const int x = e % E, y = (e / E) % E, z = e / (E * E);
-        et[e] = coarse_e<T, 3, NC, SOL>(Lc, phic, oldc, C0[0] + x - 1, C0[1] + y - 1, C0[2] + z - 1);
+    T ev[EPER];
+#pragma unroll
+    for (int m = 0; m < EPER; m++) {
+        const int e = threadIdx.x + NT * m;
+        if (e < ESZ) {
+            const int x = e % E, y = (e / E) % E, z = e / (E * E);
+            ev[m] = coarse_e<T, 3, NC, SOL>(Lc, phic, oldc, C0[0] + x - 1, C0[1] + y - 1, C0[2] + z - 1);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < EPER; m++) {
+        const int e = threadIdx.x + NT * m;
+        if (e < ESZ) et[e] = ev[m];
     }
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < PER; m++) {
-        const int s = threadIdx.x + 256 * m;
+        const int s = threadIdx.x + NT * m;
         int i, j, k;
         q_to_ijk<N>(s / B::HALF, s % B::HALF, i, j, k);
         const int ci = (i >> 1) + 1, cj = (j >> 1) + 1, ck = (k >> 1) + 1;
@@ -1425,12 +1654,11 @@ __device__ __forceinline__ void prolong3_body(const LV<T> &L, const LV<T> &Lc, i
     }
 }
 
-template <typename T, int N, int NC, bool SOL>
-__global__ __launch_bounds__(256) void k_prolong3(LV<T> L, LV<T> Lc) {
-    using B = Blk<3, N>;
-    constexpr int H = N / 2, E = H + 2, ESZ = E * E * E, PER = B::CPB / 256;
+template <typename T, int N, int NC, bool SOL, int NT>
+__global__ __launch_bounds__(NT) void k_prolong3(LV<T> L, LV<T> Lc) {
+    constexpr int H = N / 2, E = H + 2, ESZ = E * E * E;
     __shared__ T et[ESZ];
-    prolong3_body<T, N, NC, SOL>(L, Lc, block_of(L), rhs_of(L), et);
+    prolong3_body<T, N, NC, SOL, NT>(L, Lc, block_of(L), rhs_of(L), et);
 }
 
 // mixed precision defect (FP64): g32 = g - L phi on a leaf block, phi32 = 0
@@ -1442,12 +1670,13 @@ __global__ __launch_bounds__(256) void k_defect3(LV<double> L, LV<double> Lc, LV
     __shared__ double tile[ColTile<N>::SIZE];
     __shared__ double wmax[4];
     const int rhs = rhs_of(L);
-    const int act = L.active ? L.active[rhs] : 1;
     const int blk = lb[blockIdx.x];
     const int4 P = L.pos[blk];
     int nbk[6];
     face_ids<double, N>(L, blk, nbk);
     const int mo = L.map_off ? L.map_off[blk] : -1;
+    const int act = L.active ? L.active[rhs] : 1;
+    tables_loaded(act, 1, P, nbk, mo);
     if (!act) return;
     const double *__restrict__ phi = L.phi + (long long)rhs * L.fstride;
     const double *__restrict__ g = L.g + (long long)rhs * L.fstride;
@@ -1572,7 +1801,7 @@ __device__ __noinline__ void fas_rhs_call(const LV<T> &L, const LV<T> &Lc, int b
 }
 template <typename T, int N, int NC>
 __device__ __noinline__ void prolong_call(const LV<T> &L, const LV<T> &Lc, int blk, int rhs, T *sm) {
-    prolong3_body<T, N, NC, false>(L, Lc, blk, rhs, sm);
+    prolong3_body<T, N, NC, false, 256>(L, Lc, blk, rhs, sm);
 }
 template <typename T>
 __device__ __noinline__ void coarse_call(const LV<T> &L0, const double *M, const double *S, int tile, int rhs,
@@ -1644,7 +1873,13 @@ hipError_t launch_gs_half(int D, int N, const LV<T> &L, const LV<T> &Lc, int col
     if (L.nblocks == 0) return hipSuccess;
     dim3 grid(L.nblocks, nrhs);
 #define GS(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_gs_half<T, D_, N_>), grid, dim3(Blk<D_, N_>::THREADS), 0, s, L, Lc, color))
-#define GS3(N_) OCTMG_DN(3, N_, hipLaunchKernelGGL((k_gs_half3<T, N_>), grid, dim3(256), 0, s, L, Lc, color))
+    // 16^3 blocks: launches of at most pair_max workgroups split a colour
+    // over 512 threads (4 cells each instead of 8)
+    if (D == 3 && N == 16 && (long long)L.nblocks * nrhs <= L.pair_max) {
+        hipLaunchKernelGGL((k_gs_half3<T, 16, 512>), grid, dim3(512), 0, s, L, Lc, color);
+        return hipGetLastError();
+    }
+#define GS3(N_) OCTMG_DN(3, N_, hipLaunchKernelGGL((k_gs_half3<T, N_, 256>), grid, dim3(256), 0, s, L, Lc, color))
     GS3(16) GS3(8) GS(2, 8) GS(2, 16)
 #undef GS3
 #undef GS
@@ -1660,7 +1895,11 @@ hipError_t launch_restrict_fas(int D, int N, int Nc, const LV<T> &L, const LV<T>
     if (L.nblocks == 0) return hipSuccess;
     dim3 grid(L.nblocks, nrhs);
 #define RF(D_, N_, NC_) OCTMG_DNC(D_, N_, NC_, hipLaunchKernelGGL((k_restrict_fas<T, D_, N_, NC_>), grid, dim3(256), 0, s, L, Lc, into_old))
-#define RF3(N_, NC_) OCTMG_DNC(3, N_, NC_, hipLaunchKernelGGL((k_restrict_fas3<T, N_, NC_>), grid, dim3(256), 0, s, L, Lc, into_old))
+    const bool pair = (long long)L.nblocks * nrhs <= L.pair_max;
+#define RF3(N_, NC_)                                                                                              \
+    OCTMG_DNC(3, N_, NC_,                                                                                         \
+              if (pair) hipLaunchKernelGGL((k_restrict_fas3_pair<T, N_, NC_>), grid, dim3(512), 0, s, L, Lc, into_old); \
+              else hipLaunchKernelGGL((k_restrict_fas3<T, N_, NC_>), grid, dim3(256), 0, s, L, Lc, into_old))
     RF3(16, 16) RF3(16, 8) RF3(8, 8) RF(2, 8, 8) RF(2, 16, 16) RF(2, 16, 8)
 #undef RF3
 #undef RF
@@ -1702,7 +1941,10 @@ hipError_t launch_fas_rhs(int D, int N, const LV<T> &L, const LV<T> &Lc, int par
     if (L.nblocks == 0) return hipSuccess;
     dim3 grid(L.nblocks, nrhs);
 #define FR(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_fas_rhs<T, D_, N_>), grid, dim3(Blk<D_, N_>::THREADS), 0, s, L, Lc, parents_only))
-#define FR3(N_) OCTMG_DN(3, N_, hipLaunchKernelGGL((k_fas_rhs3<T, N_>), grid, dim3(256), 0, s, L, Lc, parents_only))
+    const bool pair = (long long)L.nblocks * nrhs <= L.pair_max;
+#define FR3(N_)                                                                                                 \
+    OCTMG_DN(3, N_, if (pair) hipLaunchKernelGGL((k_fas_rhs3_pair<T, N_>), grid, dim3(512), 0, s, L, Lc, parents_only); \
+             else hipLaunchKernelGGL((k_fas_rhs3<T, N_>), grid, dim3(256), 0, s, L, Lc, parents_only))
     FR3(16) FR3(8) FR(2, 8) FR(2, 16)
 #undef FR3
 #undef FR
@@ -1715,7 +1957,16 @@ hipError_t launch_prolong(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc,
     if (L.nblocks == 0) return hipSuccess;
     dim3 grid(L.nblocks, nrhs);
 #define PR(D_, N_, NC_) OCTMG_DNC(D_, N_, NC_, hipLaunchKernelGGL((k_prolong<T, D_, N_, NC_>), grid, dim3(256), 0, s, L, Lc, solution_mode))
-#define PR3(N_, NC_) OCTMG_DNC(3, N_, NC_, if (solution_mode) hipLaunchKernelGGL((k_prolong3<T, N_, NC_, true>), grid, dim3(256), 0, s, L, Lc); else hipLaunchKernelGGL((k_prolong3<T, N_, NC_, false>), grid, dim3(256), 0, s, L, Lc))
+    const bool wide = (long long)L.nblocks * nrhs <= L.pair_max;
+#define PR3(N_, NC_)                                                                                            \
+    OCTMG_DNC(3, N_, NC_,                                                                                       \
+              if (solution_mode) {                                                                              \
+                  if (wide) hipLaunchKernelGGL((k_prolong3<T, N_, NC_, true, 512>), grid, dim3(512), 0, s, L, Lc); \
+                  else hipLaunchKernelGGL((k_prolong3<T, N_, NC_, true, 256>), grid, dim3(256), 0, s, L, Lc);    \
+              } else {                                                                                          \
+                  if (wide) hipLaunchKernelGGL((k_prolong3<T, N_, NC_, false, 512>), grid, dim3(512), 0, s, L, Lc); \
+                  else hipLaunchKernelGGL((k_prolong3<T, N_, NC_, false, 256>), grid, dim3(256), 0, s, L, Lc);   \
+              })
     PR3(16, 16) PR3(16, 8) PR3(8, 8) PR(2, 8, 8) PR(2, 16, 16) PR(2, 16, 8)
 #undef PR3
 #undef PR
@@ -1737,6 +1988,7 @@ hipError_t launch_residual_max(int D, int N, const LV<T> &L, const LV<T> &Lc, in
                                int nrhs, hipStream_t s) {
     if (L.nblocks == 0) return hipSuccess;
     dim3 grid(L.nblocks, nrhs);
+    const bool pair = (long long)L.nblocks * nrhs <= L.pair_max;
 #define RM(D_, N_)                                                                                                  \
     if (D == D_ && N == N_) {                                                                                       \
         if (phi_zero) hipLaunchKernelGGL((k_residual_max<T, D_, N_, true>), grid, dim3(Blk<D_, N_>::THREADS), 0, s, L, Lc, out); \
@@ -1746,6 +1998,7 @@ hipError_t launch_residual_max(int D, int N, const LV<T> &L, const LV<T> &Lc, in
 #define RM3(N_)                                                                                                     \
     if (D == 3 && N == N_) {                                                                                        \
         if (phi_zero) hipLaunchKernelGGL((k_residual_max3<T, N_, true>), grid, dim3(256), 0, s, L, Lc, out);            \
+        else if (pair) hipLaunchKernelGGL((k_residual_max3_pair<T, N_>), grid, dim3(512), 0, s, L, Lc, out);            \
         else hipLaunchKernelGGL((k_residual_max3<T, N_, false>), grid, dim3(256), 0, s, L, Lc, out);                    \
         return hipGetLastError();                                                                                   \
     }

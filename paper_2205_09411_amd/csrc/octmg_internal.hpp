@@ -76,6 +76,8 @@ struct LV {
     const int *lanes;    // [grid y] right-hand side of each grid row (nullptr: row = rhs)
     int order;           // workgroup -> block order of the 3D kernels (0 XCD ranges, 1 hardware)
     int neumann;         // bit 2 axis + (side > 0): zero-flux domain face (ghost = inside value)
+    int pair_max;        // 3D launches of at most this many workgroups (blocks x grid rows) take the
+                         // 512-thread variants (both colours staged at once); same results
 };
 
 // ---------------------------------------------------------- launches

@@ -47,7 +47,7 @@ class SolveOpts(C.Structure):
 
 class LaunchConfig(C.Structure):
     _fields_ = [("block_order", C.c_int), ("bottom_kind", C.c_int), ("bottom_max_blocks", C.c_int),
-                ("graph_mode", C.c_int)]
+                ("graph_mode", C.c_int), ("pair_max_blocks", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -309,8 +309,8 @@ class State:
     def set_smoothing(self, n_down: int, n_up: int):
         _check(lib().octmg_state_set_smoothing(self._h, n_down, n_up))
 
-    def set_launch(self, block_order=0, bottom_kind=0, bottom_max_blocks=0, graph_mode=0):
-        c = LaunchConfig(block_order, bottom_kind, bottom_max_blocks, graph_mode)
+    def set_launch(self, block_order=0, bottom_kind=0, bottom_max_blocks=0, graph_mode=0, pair_max_blocks=1 << 30):
+        c = LaunchConfig(block_order, bottom_kind, bottom_max_blocks, graph_mode, pair_max_blocks)
         _check(lib().octmg_state_set_launch(self._h, C.byref(c)))
 
     def get_launch(self) -> dict:
@@ -324,7 +324,7 @@ class State:
         o = SolveOpts()
         o.cycle_kind, o.max_cycles, o.zero_start, o.rtol = kind, max_cycles, 1, rtol
         best = LaunchConfig()
-        ms = np.zeros(12)
+        ms = np.zeros(14)
         n = C.c_int()
         _check(lib().octmg_autotune(self._h, C.byref(o), reps, _stream_ptr(stream), C.byref(best),
                                     _ptr(ms, C.c_double), C.byref(n)))
