@@ -408,9 +408,16 @@ octmg_status mixed_defect(octmg_state s, hipStream_t st) {
     STCK(e64.sync_down());
     HIPCK(launch_fill_u64(s->d_norm, s->nrhs, 0ull, st));
     const int D = s->geom->tree.D;
-    for (int il = 0; il < (int)s->geom->L.size(); il++) {
-        const long long n = s->stride[il] * s->nrhs;
-        HIPCK(launch_fillf(s->f32[il].phi, n, 0.0f, st));
+    // The correction starts from zero.  The defect below zeroes it on every
+    // leaf block, and restriction overwrites every parent block before the
+    // cycle reads it, except where a refinement-boundary ghost reads a
+    // coarse parent block first (adaptive trees): only there, and never on
+    // the finest level (all leaves), is it cleared here.
+    if (s->geom->tree.adaptive) {
+        for (int il = 0; il + 1 < (int)s->geom->L.size(); il++) {
+            const long long n = s->stride[il] * s->nrhs;
+            HIPCK(launch_fillf(s->f32[il].phi, n, 0.0f, st));
+        }
     }
     for (int il = 0; il < (int)s->geom->L.size(); il++) {
         const GeomLevel &G = s->geom->L[il];
