@@ -1148,13 +1148,13 @@ __global__ __launch_bounds__(NT) void k_gs_half3(LV<T> L, LV<T> Lc, int color) {
 
 // L phi at the PER cells of colour `col` owned by this thread, from the
 // other-colour tile (already staged, ghosts filled); `own` their values.
-template <typename T, int N>
+template <typename T, int N, int NT = 256>
 __device__ __forceinline__ void tile_op(const LV<T> &L, const T *tile, const int *ri, int col, const T *own, T *out,
                                         int t) {
-    constexpr int PER = Per<N>::PER;
+    constexpr int PER = Blk<3, N>::HALF / NT;
 #pragma unroll
     for (int m = 0; m < PER; m++) {
-        const int q = t + 256 * m;
+        const int q = t + NT * m;
         int i, j, k;
         T v[6];
         tile_neighbours<T, N>(tile, col, q, i, j, k, v);
@@ -1366,8 +1366,8 @@ __global__ __launch_bounds__(256) void k_fas_rhs3(LV<T> L, LV<T> Lc, int do_rhs)
 }
 
 // ------------------------------------------- colour-pair variants (3D)
-// Workgroups of 512 threads in which wave group c = threadIdx.x / 256 owns
-// the cells of colour c.  Each group stages its own colour, with the halos
+// Workgroups of 2 NTC threads in which wave group c = threadIdx.x / NTC owns
+// the cells of colour c (NTC = 256, or 512 for 16^3 blocks).  Each group stages its own colour, with the halos
 // seen by the other colour, into its own tile, so both tiles fill in one
 // round of loads; after the refinement-boundary ghosts each group applies L
 // to its colour from the other group's tile.  The arithmetic is that of the
@@ -1379,31 +1379,32 @@ struct PairTiles {
     static constexpr int SIZE = 2 * ColTile<N>::SIZE;
 };
 
-// L phi at this thread's PER cells of colour c; `own` holds their values
-// (registers), `tiles` two ColTiles.  Every thread of the workgroup calls it.
-template <typename T, int N>
+// L phi at this thread's HALF/NTC cells of colour c; `own` holds their
+// values (registers), `tiles` two ColTiles.  Every thread of the workgroup
+// calls it.
+template <typename T, int N, int NTC>
 __device__ __forceinline__ void pair_op(const LV<T> &L, const LV<T> &Lc, const T *phi, const T *phic, T *tiles,
                                         int blk, const int *nbk, int4 P, const int *ri, const T *own, T *out) {
-    const int c = threadIdx.x >> 8, t = threadIdx.x & 255;
+    const int c = threadIdx.x / NTC, t = threadIdx.x % NTC;
     T *mine = tiles + c * ColTile<N>::SIZE, *other = tiles + (1 - c) * ColTile<N>::SIZE;
-    stage_colour<T, N, false>(mine, L, phi, blk, nbk, P, c, t, own);
+    stage_colour<T, N, false, NTC>(mine, L, phi, blk, nbk, P, c, t, own);
     __syncthreads();
     if (any_coarser(nbk)) {
         coarser_face_ghosts<T, N>(other, Lc, phi + (long long)blk * Blk<3, N>::CPB + c * Blk<3, N>::HALF, phic, nbk,
                                   P, c, t);
         __syncthreads();
     }
-    tile_op<T, N>(L, other, ri, c, own, out, t);
+    tile_op<T, N, NTC>(L, other, ri, c, own, out, t);
 }
 
-template <typename T, int N, int NC>
-__global__ __launch_bounds__(512) void k_restrict_fas3_pair(LV<T> L, LV<T> Lc, int into_old) {
+template <typename T, int N, int NC, int NTC>
+__global__ __launch_bounds__(2 * NTC) void k_restrict_fas3_pair(LV<T> L, LV<T> Lc, int into_old) {
     using B = Blk<3, N>;
-    constexpr int PER = Per<N>::PER, H = N / 2, NCELL = H * H * H;
+    constexpr int PER = B::HALF / NTC, H = N / 2, NCELL = H * H * H;
     constexpr int SM = PairTiles<T, N>::SIZE > 2 * B::CPB ? PairTiles<T, N>::SIZE : 2 * B::CPB;
     __shared__ T sm[SM];
     const int blk = block_of(L), rhs = rhs_of(L);
-    const int c = threadIdx.x >> 8, t = threadIdx.x & 255;
+    const int c = threadIdx.x / NTC, t = threadIdx.x % NTC;
     const int4 P = L.pos[blk];
     int nbk[6];
     face_ids<T, N>(L, blk, nbk);
@@ -1419,12 +1420,12 @@ __global__ __launch_bounds__(512) void k_restrict_fas3_pair(LV<T> L, LV<T> Lc, i
     int ri[PER];
 #pragma unroll
     for (int m = 0; m < PER; m++) {
-        const int s = t + 256 * m;
+        const int s = t + NTC * m;
         own[m] = phi[base + s];
         gv[m] = g[base + s];
         ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + s] : -1;
     }
-    pair_op<T, N>(L, Lc, phi, phic, sm, blk, nbk, P, ri, own, r);
+    pair_op<T, N, NTC>(L, Lc, phi, phic, sm, blk, nbk, P, ri, own, r);
 #pragma unroll
     for (int m = 0; m < PER; m++) r[m] = gv[m] - r[m];
     __syncthreads();  // the tiles become the natural-order arrays of r and phi
@@ -1432,7 +1433,7 @@ __global__ __launch_bounds__(512) void k_restrict_fas3_pair(LV<T> L, LV<T> Lc, i
 #pragma unroll
     for (int m = 0; m < PER; m++) {
         int i, j, k;
-        q_to_ijk<N>(c, t + 256 * m, i, j, k);
+        q_to_ijk<N>(c, t + NTC * m, i, j, k);
         sr[(k * N + j) * N + i] = r[m];
         sp[(k * N + j) * N + i] = own[m];
     }
@@ -1443,7 +1444,7 @@ __global__ __launch_bounds__(512) void k_restrict_fas3_pair(LV<T> L, LV<T> Lc, i
     const int pb = block_at<T, 3>(Lc, C0[0] / NC, C0[1] / NC, C0[2] / NC);
     if (pb < 0) return;  // excluded by construction: every block has a parent
     const T inv = T(0.125);
-    for (int cc = threadIdx.x; cc < NCELL; cc += 512) {
+    for (int cc = threadIdx.x; cc < NCELL; cc += 2 * NTC) {
         const int ci = cc % H, cj = (cc / H) % H, ck = cc / (H * H);
         T rs = T(0), ps = T(0);
 #pragma unroll
@@ -1459,13 +1460,13 @@ __global__ __launch_bounds__(512) void k_restrict_fas3_pair(LV<T> L, LV<T> Lc, i
     }
 }
 
-template <typename T, int N>
-__global__ __launch_bounds__(512) void k_fas_rhs3_pair(LV<T> L, LV<T> Lc, int do_rhs) {
+template <typename T, int N, int NTC>
+__global__ __launch_bounds__(2 * NTC) void k_fas_rhs3_pair(LV<T> L, LV<T> Lc, int do_rhs) {
     using B = Blk<3, N>;
-    constexpr int PER = Per<N>::PER;
+    constexpr int PER = B::HALF / NTC;
     __shared__ T tiles[PairTiles<T, N>::SIZE];
     const int blk = block_of(L), rhs = rhs_of(L);
-    const int c = threadIdx.x >> 8, t = threadIdx.x & 255;
+    const int c = threadIdx.x / NTC, t = threadIdx.x % NTC;
     const int leaf = L.leaf[blk];
     const int4 P = L.pos[blk];
     int nbk[6];
@@ -1479,7 +1480,7 @@ __global__ __launch_bounds__(512) void k_fas_rhs3_pair(LV<T> L, LV<T> Lc, int do
     T *old = L.old + (long long)rhs * L.fstride;
     if (leaf || !do_rhs) {
         const long long b0 = (long long)blk * B::CPB;
-        for (int s = threadIdx.x; s < B::CPB; s += 512) old[b0 + s] = phi[b0 + s];
+        for (int s = threadIdx.x; s < B::CPB; s += 2 * NTC) old[b0 + s] = phi[b0 + s];
         return;
     }
     const T *phic = Lc.phi ? Lc.phi + (long long)rhs * Lc.fstride : nullptr;
@@ -1488,28 +1489,28 @@ __global__ __launch_bounds__(512) void k_fas_rhs3_pair(LV<T> L, LV<T> Lc, int do
     int ri[PER];
 #pragma unroll
     for (int m = 0; m < PER; m++) {
-        const int s = t + 256 * m;
+        const int s = t + NTC * m;
         own[m] = phi[base + s];
         gv[m] = g[base + s];
         ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + s] : -1;
     }
-    pair_op<T, N>(L, Lc, phi, phic, tiles, blk, nbk, P, ri, own, lp);
+    pair_op<T, N, NTC>(L, Lc, phi, phic, tiles, blk, nbk, P, ri, own, lp);
 #pragma unroll
     for (int m = 0; m < PER; m++) {
-        const int s = t + 256 * m;
+        const int s = t + NTC * m;
         g[base + s] = lp[m] + gv[m];
         old[base + s] = own[m];
     }
 }
 
-template <typename T, int N>
-__global__ __launch_bounds__(512) void k_residual_max3_pair(LV<T> L, LV<T> Lc, unsigned long long *out) {
+template <typename T, int N, int NTC>
+__global__ __launch_bounds__(2 * NTC) void k_residual_max3_pair(LV<T> L, LV<T> Lc, unsigned long long *out) {
     using B = Blk<3, N>;
-    constexpr int PER = Per<N>::PER;
+    constexpr int PER = B::HALF / NTC;
     __shared__ T tiles[PairTiles<T, N>::SIZE];
-    __shared__ double wmax[8];
+    __shared__ double wmax[2 * NTC / 64];
     const int blk = block_of(L), rhs = rhs_of(L);
-    const int c = threadIdx.x >> 8, t = threadIdx.x & 255;
+    const int c = threadIdx.x / NTC, t = threadIdx.x % NTC;
     const int leaf = L.leaf[blk];
     const int4 P = L.pos[blk];
     int nbk[6];
@@ -1526,12 +1527,12 @@ __global__ __launch_bounds__(512) void k_residual_max3_pair(LV<T> L, LV<T> Lc, u
     int ri[PER];
 #pragma unroll
     for (int m = 0; m < PER; m++) {
-        const int s = t + 256 * m;
+        const int s = t + NTC * m;
         own[m] = phi[base + s];
         gv[m] = g[base + s];
         ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + s] : -1;
     }
-    pair_op<T, N>(L, Lc, phi, phic, tiles, blk, nbk, P, ri, own, lp);
+    pair_op<T, N, NTC>(L, Lc, phi, phic, tiles, blk, nbk, P, ri, own, lp);
     double mx = 0.0;
 #pragma unroll
     for (int m = 0; m < PER; m++) mx = fmax(mx, fabs((double)(gv[m] - lp[m])));
@@ -1539,7 +1540,7 @@ __global__ __launch_bounds__(512) void k_residual_max3_pair(LV<T> L, LV<T> Lc, u
     if (threadIdx.x % 64 == 0) wmax[threadIdx.x / 64] = mx;
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < 8; w++) mx = fmax(mx, wmax[w]);
+        for (int w = 1; w < 2 * NTC / 64; w++) mx = fmax(mx, wmax[w]);
         if (mx != mx) mx = __longlong_as_double(0x7ff0000000000000ll);
         atomicMax(out + rhs, (unsigned long long)__double_as_longlong(mx));
     }
@@ -1857,6 +1858,14 @@ __global__ __launch_bounds__(256) void k_small_vcycle(const SmallLevels<T> *__re
 #undef OCTMG_PHASE
 }
 
+// threads per colour of the colour-pair FAS right-hand side: 512 on 16^3
+// blocks (measured 1.3-2.5 us faster per launch on every level at 256^3;
+// restriction and residual measured slower that way at the finest level)
+template <int N>
+constexpr int fas_ntc() {
+    return N == 16 ? 512 : 256;
+}
+
 int grid_for(long long n) {
     long long g = (n + 255) / 256;
     return (int)(g < 4096 ? (g < 1 ? 1 : g) : 4096);
@@ -1898,7 +1907,7 @@ hipError_t launch_restrict_fas(int D, int N, int Nc, const LV<T> &L, const LV<T>
     const bool pair = (long long)L.nblocks * nrhs <= L.pair_max;
 #define RF3(N_, NC_)                                                                                              \
     OCTMG_DNC(3, N_, NC_,                                                                                         \
-              if (pair) hipLaunchKernelGGL((k_restrict_fas3_pair<T, N_, NC_>), grid, dim3(512), 0, s, L, Lc, into_old); \
+              if (pair) hipLaunchKernelGGL((k_restrict_fas3_pair<T, N_, NC_, 256>), grid, dim3(512), 0, s, L, Lc, into_old); \
               else hipLaunchKernelGGL((k_restrict_fas3<T, N_, NC_>), grid, dim3(256), 0, s, L, Lc, into_old))
     RF3(16, 16) RF3(16, 8) RF3(8, 8) RF(2, 8, 8) RF(2, 16, 16) RF(2, 16, 8)
 #undef RF3
@@ -1943,7 +1952,7 @@ hipError_t launch_fas_rhs(int D, int N, const LV<T> &L, const LV<T> &Lc, int par
 #define FR(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_fas_rhs<T, D_, N_>), grid, dim3(Blk<D_, N_>::THREADS), 0, s, L, Lc, parents_only))
     const bool pair = (long long)L.nblocks * nrhs <= L.pair_max;
 #define FR3(N_)                                                                                                 \
-    OCTMG_DN(3, N_, if (pair) hipLaunchKernelGGL((k_fas_rhs3_pair<T, N_>), grid, dim3(512), 0, s, L, Lc, parents_only); \
+    OCTMG_DN(3, N_, if (pair) hipLaunchKernelGGL((k_fas_rhs3_pair<T, N_, fas_ntc<N_>()>), grid, dim3(2 * fas_ntc<N_>()), 0, s, L, Lc, parents_only); \
              else hipLaunchKernelGGL((k_fas_rhs3<T, N_>), grid, dim3(256), 0, s, L, Lc, parents_only))
     FR3(16) FR3(8) FR(2, 8) FR(2, 16)
 #undef FR3
@@ -1998,7 +2007,7 @@ hipError_t launch_residual_max(int D, int N, const LV<T> &L, const LV<T> &Lc, in
 #define RM3(N_)                                                                                                     \
     if (D == 3 && N == N_) {                                                                                        \
         if (phi_zero) hipLaunchKernelGGL((k_residual_max3<T, N_, true>), grid, dim3(256), 0, s, L, Lc, out);            \
-        else if (pair) hipLaunchKernelGGL((k_residual_max3_pair<T, N_>), grid, dim3(512), 0, s, L, Lc, out);            \
+        else if (pair) hipLaunchKernelGGL((k_residual_max3_pair<T, N_, 256>), grid, dim3(512), 0, s, L, Lc, out);       \
         else hipLaunchKernelGGL((k_residual_max3<T, N_, false>), grid, dim3(256), 0, s, L, Lc, out);                    \
         return hipGetLastError();                                                                                   \
     }

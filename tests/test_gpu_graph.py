@@ -132,3 +132,24 @@ def test_launch_configurations_and_autotune_identical():
     assert np.array_equal(S.get_solution(), ref)
     with pytest.raises(octmg.OctmgError):
         S.set_launch(bottom_kind=1, bottom_max_blocks=8, graph_mode=1)
+
+
+@pytest.mark.parametrize("precision", [octmg.FP64, octmg.MIXED])
+def test_thread_variants_identical_adaptive(precision):
+    """The 512-lane kernels (every launch), the 256-lane kernels (none) and a
+    mix (levels of at most 64 blocks) give the same iterates, bit for bit, on
+    an adaptive octree with refinement-boundary ghosts, 16^3 and 8^3 blocks."""
+    print("thread variants, adaptive", precision, flush=True)
+    for bn in (16, 8):
+        w = W.spheres(n_spheres=6, max_level=5, block_n=bn, refine_width=1.0)
+        G, S = state(w, 2 if precision == octmg.MIXED else 1, precision)
+        assert any(G.level_info(i)["nleaf"] not in (0, G.level_info(i)["nblocks"]) for i in range(G.n_levels))
+        ref = None
+        for p in (1 << 30, 0, 64):
+            S.set_launch(pair_max_blocks=p)
+            r = S.solve(rtol=1e-10, zero_start=True)
+            sol = S.get_solution()
+            if ref is None:
+                ref, ref_cycles = sol, r.cycles
+            assert r.cycles == ref_cycles, p
+            assert np.array_equal(sol, ref), p
