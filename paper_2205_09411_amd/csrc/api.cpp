@@ -258,7 +258,9 @@ struct Engine {
     // The half sweeps of one level visit run back to back; when profiling,
     // one event pair brackets the whole group on the finest level and the
     // group's time is shared evenly by its launches.
-    octmg_status smooth(int il, int steps) {
+    // fas_first: the first red half sweep also forms the level's FAS
+    // right-hand side (see restrict_only)
+    octmg_status smooth(int il, int steps, bool fas_first = false) {
         Profile *P = s->prof;
         const bool timed = P && P->on && il == (int)s->geom->L.size() - 1 && steps > 0;
         hipEvent_t a = nullptr, b = nullptr;
@@ -269,7 +271,10 @@ struct Engine {
         }
         for (int k = 0; k < steps; k++)
             for (int color = 0; color < 2; color++) {
-                HIPCK(launch_gs_half<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1), color, s->n_launch, st));
+                if (fas_first && k == 0 && color == 0)
+                    HIPCK(launch_fas_gs<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1), s->n_launch, st));
+                else
+                    HIPCK(launch_gs_half<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1), color, s->n_launch, st));
                 if (P && P->on) {
                     const GeomLevel &G = s->geom->L[il];
                     P->updates += 0.5 * (double)G.nblocks * G.cpb * s->n_launch;
@@ -293,6 +298,22 @@ struct Engine {
         if (adaptive) HIPCK(launch_copy_parents<T>(D(), Nb(il - 1), lvT<T>(s, il - 1), s->n_launch, st));
         HIPCK(launch_fas_rhs<T>(D(), Nb(il - 1), lvT<T>(s, il - 1), lvT<T>(s, il - 2), 1, s->n_launch, st));
         return OCTMG_OK;
+    }
+    // FAS restriction il -> il-1 without the right-hand side, which the first
+    // half sweep of il-1 then forms (smooth with fas_first); leaves phi = old
+    // on every block of il-1
+    octmg_status restrict_only(int il) {
+        const int adaptive = s->geom->tree.adaptive ? 1 : 0;
+        HIPCK(launch_restrict_fas<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), adaptive, s->n_launch, st));
+        if (adaptive) HIPCK(launch_copy_parents<T>(D(), Nb(il - 1), lvT<T>(s, il - 1), s->n_launch, st));
+        return OCTMG_OK;
+    }
+    // whether coarse level lc of a V-cycle whose levels up to ft run fused
+    // gets its FAS right-hand side from its first half sweep (3D, lc smoothed
+    // by separate launches of the 512-lane kernels)
+    bool fas_in_sweep(int lc, int ft) const {
+        return D() == 3 && s->n_down >= 1 && lc > ft && lc >= 1 &&
+               (long long)s->geom->L[lc].nblocks * s->n_launch <= s->pair_max_blocks;
     }
     octmg_status restrict_rhs(int il) {
         LV<T> c = lvT<T>(s, il - 1);
@@ -322,9 +343,11 @@ struct Engine {
     // (few blocks each) run in one cooperative launch with the same steps.
     octmg_status vcycle(int top) {
         const int ft = std::min(top, s->fused_top);
+        bool fas_pending = false;
         for (int il = top; il > ft; il--) {
-            STCK(smooth(il, s->n_down));
-            STCK(restrict_fas(il));
+            STCK(smooth(il, s->n_down, fas_pending));
+            fas_pending = fas_in_sweep(il - 1, ft);
+            STCK(fas_pending ? restrict_only(il) : restrict_fas(il));
         }
         if (ft >= 1) STCK(fused(ft));
         else STCK(coarse_solve());

@@ -285,8 +285,11 @@ template <typename T, int D, int N>
 __global__ __launch_bounds__(256) void k_copy_parents(LV<T> L) {
     if (inactive(L)) return;
     const int blk = blockIdx.x;
-    if (L.leaf[blk]) return;
     const long long o = (long long)rhs_of(L) * L.fstride + (long long)blk * Blk<D, N>::CPB;
+    if (L.leaf[blk]) {
+        for (int c = threadIdx.x; c < Blk<D, N>::CPB; c += blockDim.x) L.old[o + c] = L.phi[o + c];
+        return;
+    }
     for (int c = threadIdx.x; c < Blk<D, N>::CPB; c += blockDim.x) L.phi[o + c] = L.old[o + c];
 }
 
@@ -1212,8 +1215,8 @@ __device__ __forceinline__ void q_to_ijk(int col, int q, int &i, int &j, int &k)
 // pass 1 stages colour 0 from the registers that held its own values.
 
 // FAS restriction, 3D: residual of every cell, then the 2x2x2 means of phi
-// and r through a natural-order LDS array.  phi_c goes to Lc.phi, or to
-// Lc.old when `into_old`.
+// and r through a natural-order LDS array.  phi_c goes to Lc.old, and to
+// Lc.phi as well unless `into_old`.
 template <typename T, int N, int NC>
 __device__ __forceinline__ void restrict_fas3_body(const LV<T> &L, const LV<T> &Lc, int into_old, int blk, int rhs, T *sm) {
     using B = Blk<3, N>;
@@ -1284,7 +1287,7 @@ __device__ __forceinline__ void restrict_fas3_body(const LV<T> &L, const LV<T> &
         }
         __syncthreads();
     }
-    T *phiw = (into_old ? Lc.old : Lc.phi) + (long long)rhs * Lc.fstride;
+    T *oldw = Lc.old + (long long)rhs * Lc.fstride, *phiw = Lc.phi + (long long)rhs * Lc.fstride;
     T *gw = Lc.g + (long long)rhs * Lc.fstride;
     const int C0[3] = {P.x * H, P.y * H, P.z * H};
     const int pb = block_at<T, 3>(Lc, C0[0] / NC, C0[1] / NC, C0[2] / NC);
@@ -1297,7 +1300,9 @@ __device__ __forceinline__ void restrict_fas3_body(const LV<T> &L, const LV<T> &
         const int ci = cc % H, cj = (cc / H) % H, ck = cc / (H * H);
         const int gi = C0[0] + ci, gj = C0[1] + cj, gk = C0[2] + ck;
         const long long o = (long long)pb * Blk<3, NC>::CPB + split_of<3, NC>(gi % NC, gj % NC, gk % NC);
-        phiw[o] = pc[m] * inv;
+        const T pv = pc[m] * inv;
+        oldw[o] = pv;
+        if (!into_old) phiw[o] = pv;
         gw[o] = rc[m] * inv;
     }
 }
@@ -1438,7 +1443,7 @@ __global__ __launch_bounds__(2 * NTC) void k_restrict_fas3_pair(LV<T> L, LV<T> L
         sp[(k * N + j) * N + i] = own[m];
     }
     __syncthreads();
-    T *phiw = (into_old ? Lc.old : Lc.phi) + (long long)rhs * Lc.fstride;
+    T *oldw = Lc.old + (long long)rhs * Lc.fstride, *phiw = Lc.phi + (long long)rhs * Lc.fstride;
     T *gw = Lc.g + (long long)rhs * Lc.fstride;
     const int C0[3] = {P.x * H, P.y * H, P.z * H};
     const int pb = block_at<T, 3>(Lc, C0[0] / NC, C0[1] / NC, C0[2] / NC);
@@ -1455,7 +1460,9 @@ __global__ __launch_bounds__(2 * NTC) void k_restrict_fas3_pair(LV<T> L, LV<T> L
         }
         const int gi = C0[0] + ci, gj = C0[1] + cj, gk = C0[2] + ck;
         const long long o = (long long)pb * Blk<3, NC>::CPB + split_of<3, NC>(gi % NC, gj % NC, gk % NC);
-        phiw[o] = ps * inv;
+        const T pv = ps * inv;
+        oldw[o] = pv;
+        if (!into_old) phiw[o] = pv;
         gw[o] = rs * inv;
     }
 }
@@ -1500,6 +1507,77 @@ __global__ __launch_bounds__(2 * NTC) void k_fas_rhs3_pair(LV<T> L, LV<T> Lc, in
         const int s = t + NTC * m;
         g[base + s] = lp[m] + gv[m];
         old[base + s] = own[m];
+    }
+}
+
+// FAS right-hand side fused with the first red half sweep of a coarse
+// level (3D).  Entry state: phi = old on every block of the level (the
+// restriction wrote both; on leaf blocks of adaptive trees old was copied
+// from phi).  Both colour tiles are staged from old, which no workgroup
+// writes here, so the red half sweep may overwrite phi meanwhile.  Each
+// wave group applies L to its colour; on parent blocks g <- L phi + g (the
+// FAS right-hand side, Sec. 2.2); then group 0 updates the red cells from
+// the black tile with that g.  Term by term the arithmetic of k_fas_rhs3
+// followed by k_gs_half3 on colour 0: the same bits.
+template <typename T, int N, int NTC>
+__global__ __launch_bounds__(2 * NTC) void k_fas_gs3_pair(LV<T> L, LV<T> Lc) {
+    using B = Blk<3, N>;
+    constexpr int PER = B::HALF / NTC;
+    __shared__ T tiles[PairTiles<T, N>::SIZE];
+    const int blk = block_of(L), rhs = rhs_of(L);
+    const int c = threadIdx.x / NTC, t = threadIdx.x % NTC;
+    const int leaf = L.leaf[blk];
+    const int4 P = L.pos[blk];
+    int nbk[6];
+    face_ids<T, N>(L, blk, nbk);
+    const int mo = L.map_off ? L.map_off[blk] : -1;
+    const int act = L.active ? L.active[rhs] : 1;
+    tables_loaded(act, leaf, P, nbk, mo);
+    if (!act) return;
+    const T *old = L.old + (long long)rhs * L.fstride;
+    T *phi = L.phi + (long long)rhs * L.fstride;
+    T *g = L.g + (long long)rhs * L.fstride;
+    const T *phic = Lc.phi ? Lc.phi + (long long)rhs * Lc.fstride : nullptr;
+    const long long base = (long long)blk * B::CPB + c * B::HALF;
+    T own[PER], lp[PER], gv[PER];
+    int ri[PER];
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        const int s = t + NTC * m;
+        own[m] = old[base + s];
+        gv[m] = g[base + s];
+        ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + s] : -1;
+    }
+    pair_op<T, N, NTC>(L, Lc, old, phic, tiles, blk, nbk, P, ri, own, lp);
+    if (!leaf) {
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            gv[m] = lp[m] + gv[m];
+            g[base + t + NTC * m] = gv[m];
+        }
+    }
+    if (c != 0) return;
+    // red half sweep from the black tile (its ghosts were filled for the red cells)
+    const T *tile = tiles + ColTile<N>::SIZE;
+    const T inv6 = T(1) / T(6);
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        const int q = t + NTC * m;
+        int i, j, k;
+        T v[6];
+        tile_neighbours<T, N>(tile, 0, q, i, j, k, v);
+        T nv;
+        if (ri[m] < 0) {
+            nv = (((v[0] + v[1]) + (v[2] + v[3])) + (v[4] + v[5]) - L.dx2 * gv[m]) * inv6;
+        } else {
+            const T *r = L.rec + 8 * (long long)ri[m];
+            T sm = T(0);
+#pragma unroll
+            for (int d = 0; d < 6; d++) sm += r[d] * v[d];
+            const T bt = L.b ? L.b[ri[m]] : T(0);
+            nv = (gv[m] - bt - sm) * r[7];
+        }
+        phi[base + q] = nv;
     }
 }
 
@@ -1731,16 +1809,22 @@ __global__ __launch_bounds__(256) void k_defect3(LV<double> L, LV<double> Lc, LV
 
 __device__ __forceinline__ void copy_parents_body3(int N, const LV<double> &L, int blk, int rhs) {
     if (L.active && !L.active[rhs]) return;
-    if (L.leaf[blk]) return;
     const int cpb = N * N * N;
     const long long o = (long long)rhs * L.fstride + (long long)blk * cpb;
+    if (L.leaf[blk]) {
+        for (int c = threadIdx.x; c < cpb; c += blockDim.x) L.old[o + c] = L.phi[o + c];
+        return;
+    }
     for (int c = threadIdx.x; c < cpb; c += blockDim.x) L.phi[o + c] = L.old[o + c];
 }
 __device__ __forceinline__ void copy_parents_body3(int N, const LV<float> &L, int blk, int rhs) {
     if (L.active && !L.active[rhs]) return;
-    if (L.leaf[blk]) return;
     const int cpb = N * N * N;
     const long long o = (long long)rhs * L.fstride + (long long)blk * cpb;
+    if (L.leaf[blk]) {
+        for (int c = threadIdx.x; c < cpb; c += blockDim.x) L.old[o + c] = L.phi[o + c];
+        return;
+    }
     for (int c = threadIdx.x; c < cpb; c += blockDim.x) L.phi[o + c] = L.old[o + c];
 }
 
@@ -1961,6 +2045,16 @@ hipError_t launch_fas_rhs(int D, int N, const LV<T> &L, const LV<T> &Lc, int par
 }
 
 template <typename T>
+hipError_t launch_fas_gs(int D, int N, const LV<T> &L, const LV<T> &Lc, int nrhs, hipStream_t s) {
+    if (L.nblocks == 0) return hipSuccess;
+    dim3 grid(L.nblocks, nrhs);
+#define FG3(N_) OCTMG_DN(3, N_, hipLaunchKernelGGL((k_fas_gs3_pair<T, N_, fas_ntc<N_>()>), grid, dim3(2 * fas_ntc<N_>()), 0, s, L, Lc))
+    FG3(16) FG3(8)
+#undef FG3
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
 hipError_t launch_prolong(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int solution_mode, int nrhs,
                           hipStream_t s) {
     if (L.nblocks == 0) return hipSuccess;
@@ -2164,6 +2258,7 @@ hipError_t launch_check_finite(const double *p, long long n, int *flag, hipStrea
     template hipError_t launch_restrict_rhs<T>(int, int, int, const LV<T> &, const LV<T> &, int, hipStream_t);      \
     template hipError_t launch_restrict_phi<T>(int, int, int, const LV<T> &, const LV<T> &, int, hipStream_t);      \
     template hipError_t launch_fas_rhs<T>(int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t);           \
+    template hipError_t launch_fas_gs<T>(int, int, const LV<T> &, const LV<T> &, int, hipStream_t);                  \
     template hipError_t launch_prolong<T>(int, int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t);      \
     template hipError_t launch_coarse_solve<T>(int, const LV<T> &, const double *, const double *, int, hipStream_t); \
     template hipError_t launch_residual_max<T>(int, int, const LV<T> &, const LV<T> &, int, unsigned long long *, int, hipStream_t);

@@ -88,7 +88,8 @@ template <typename T>
 hipError_t launch_gs_half(int D, int N, const LV<T> &L, const LV<T> &Lc, int color, int nrhs, hipStream_t s);
 // phi_c is written to Lc.phi, or to Lc.old when `into_old` (adaptive trees:
 // refinement-boundary ghosts of the fine level still read Lc.phi); then
-// launch_copy_parents moves it to phi on parent blocks.
+// launch_copy_parents moves it to phi on parent blocks (and copies phi to
+// old on leaf blocks).  In 3D phi_c is written to Lc.old in either case.
 template <typename T>
 hipError_t launch_restrict_fas(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int into_old, int nrhs,
                                hipStream_t s);
@@ -98,6 +99,12 @@ template <typename T>
 hipError_t launch_restrict_rhs(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int nrhs, hipStream_t s);
 template <typename T>
 hipError_t launch_fas_rhs(int D, int N, const LV<T> &L, const LV<T> &Lc, int parents_only, int nrhs, hipStream_t s);
+// 3D: the FAS right-hand side of level L (g <- L phi + g on parent blocks)
+// fused with its first red half sweep; needs phi = old on every block (as
+// the 3D restriction, plus launch_copy_parents on adaptive trees, leaves
+// them).  Same results as launch_fas_rhs then launch_gs_half(colour 0).
+template <typename T>
+hipError_t launch_fas_gs(int D, int N, const LV<T> &L, const LV<T> &Lc, int nrhs, hipStream_t s);
 template <typename T>
 hipError_t launch_restrict_phi(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int nrhs, hipStream_t s);
 template <typename T>
