@@ -327,8 +327,8 @@ struct Engine {
         HIPCK(launch_prolong<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), solution_mode, s->n_launch, st));
         return OCTMG_OK;
     }
-    octmg_status coarse_solve() {
-        HIPCK(launch_coarse_solve<T>(D(), lvT<T>(s, 0), s->geom->d_M, s->geom->d_S, s->n_launch, st));
+    octmg_status coarse_solve(int fas = 0) {
+        HIPCK(launch_coarse_solve<T>(D(), lvT<T>(s, 0), s->geom->d_M, s->geom->d_S, fas, s->n_launch, st));
         return OCTMG_OK;
     }
     hipError_t fill(T *p, long long n);
@@ -344,13 +344,15 @@ struct Engine {
     octmg_status vcycle(int top) {
         const int ft = std::min(top, s->fused_top);
         bool fas_pending = false;
+        // the coarsest level's FAS right-hand side is formed inside the solve (3D)
+        const bool fas_coarse = ft == 0 && D() == 3;
         for (int il = top; il > ft; il--) {
             STCK(smooth(il, s->n_down, fas_pending));
             fas_pending = fas_in_sweep(il - 1, ft);
-            STCK(fas_pending ? restrict_only(il) : restrict_fas(il));
+            STCK(fas_pending || (il == 1 && fas_coarse) ? restrict_only(il) : restrict_fas(il));
         }
         if (ft >= 1) STCK(fused(ft));
-        else STCK(coarse_solve());
+        else STCK(coarse_solve(fas_coarse && top >= 1 ? 1 : 0));
         for (int il = std::max(ft, 0) + 1; il <= top; il++) {
             STCK(prolong(il, 0));
             STCK(smooth(il, s->n_up));

@@ -488,7 +488,7 @@ __global__ __launch_bounds__(256) void k_prolong(LV<T> L, LV<T> Lc, int solution
 // Exact solve on the single-block coarsest grid (8^D cells): rhs_i = S_i (g_i
 // - b_i - sum over uncut domain links 2 c phi_b), phi = M rhs, where M is the
 // inverse of the row-equilibrated operator.  Grid: x = row tiles, y = rhs.
-template <typename T, int D>
+template <typename T, int D, bool FAS>
 __global__ __launch_bounds__(256) void k_coarse_solve(LV<T> L0, const double *M, const double *S) {
     if (inactive(L0)) return;
     constexpr int NB = 8, NCELL = D == 3 ? 512 : 64;
@@ -511,7 +511,39 @@ __global__ __launch_bounds__(256) void k_coarse_solve(LV<T> L0, const double *M,
         const int i = c % NB, j = (c / NB) % NB, k = D == 3 ? c / (NB * NB) : 0;
         const int si = split_of<D, NB>(i, j, k);
         const int ri = mo >= 0 ? L0.map[mo + si] : -1;
-        double r = (double)g[si];
+        double r;
+        if (FAS) {
+            // FAS right-hand side of the coarsest level, g + L phi with phi
+            // the restricted values in old (the arithmetic of k_fas_rhs3)
+            const T *old = L0.old + (long long)rhs_of(L0) * L0.fstride;
+            const T own = old[si];
+            T v[6];
+#pragma unroll
+            for (int d = 0; d < 6; d++) {
+                const int ax = d >> 1, sg = (d & 1) ? 1 : -1;
+                int q[3] = {i, j, k};
+                q[ax] += sg;
+                if (q[ax] >= 0 && q[ax] < NB) {
+                    v[d] = old[split_of<D, NB>(q[0], q[1], q[2])];
+                } else {
+                    const T bv = L0.bcv ? L0.bcv[face_slot<D>(ax, sg, i, j, k, NB, L0.nface)] : T(0);
+                    v[d] = zero_flux(L0.neumann, ax, sg) ? own : T(2) * bv - own;
+                }
+            }
+            T lp;
+            if (ri < 0) {
+                lp = L0.inv_dx2 * ((((v[0] + v[1]) + (v[2] + v[3])) + (v[4] + v[5])) - T(6) * own);
+            } else {
+                const T *rr = L0.rec + 8 * (long long)ri;
+                T sm = T(0);
+#pragma unroll
+                for (int d = 0; d < 6; d++) sm += rr[d] * v[d];
+                lp = sm + rr[6] * own + (L0.b ? L0.b[ri] : T(0));
+            }
+            r = (double)(lp + g[si]);
+        } else {
+            r = (double)g[si];
+        }
         if (ri >= 0 && L0.b) r -= (double)L0.b[ri];
         for (int d = 0; d < 2 * D; d++) {
             const int ax = d >> 1, s = (d & 1) ? 1 : -1;
@@ -2077,11 +2109,14 @@ hipError_t launch_prolong(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc,
 }
 
 template <typename T>
-hipError_t launch_coarse_solve(int D, const LV<T> &L0, const double *M, const double *S, int nrhs, hipStream_t s) {
+hipError_t launch_coarse_solve(int D, const LV<T> &L0, const double *M, const double *S, int fas, int nrhs,
+                               hipStream_t s) {
     if (D == 3) {
-        hipLaunchKernelGGL((k_coarse_solve<T, 3>), dim3(512 / 8, nrhs), dim3(256), 0, s, L0, M, S);
+        if (fas) hipLaunchKernelGGL((k_coarse_solve<T, 3, true>), dim3(512 / 8, nrhs), dim3(256), 0, s, L0, M, S);
+        else hipLaunchKernelGGL((k_coarse_solve<T, 3, false>), dim3(512 / 8, nrhs), dim3(256), 0, s, L0, M, S);
     } else {
-        hipLaunchKernelGGL((k_coarse_solve<T, 2>), dim3(64 / 16, nrhs), dim3(256), 0, s, L0, M, S);
+        if (fas) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_coarse_solve<T, 2, false>), dim3(64 / 16, nrhs), dim3(256), 0, s, L0, M, S);
     }
     return hipGetLastError();
 }
@@ -2260,7 +2295,7 @@ hipError_t launch_check_finite(const double *p, long long n, int *flag, hipStrea
     template hipError_t launch_fas_rhs<T>(int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t);           \
     template hipError_t launch_fas_gs<T>(int, int, const LV<T> &, const LV<T> &, int, hipStream_t);                  \
     template hipError_t launch_prolong<T>(int, int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t);      \
-    template hipError_t launch_coarse_solve<T>(int, const LV<T> &, const double *, const double *, int, hipStream_t); \
+    template hipError_t launch_coarse_solve<T>(int, const LV<T> &, const double *, const double *, int, int, hipStream_t); \
     template hipError_t launch_residual_max<T>(int, int, const LV<T> &, const LV<T> &, int, unsigned long long *, int, hipStream_t);
 OCTMG_INST(double)
 OCTMG_INST(float)

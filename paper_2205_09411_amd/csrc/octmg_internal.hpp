@@ -111,7 +111,10 @@ template <typename T>
 hipError_t launch_prolong(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int solution_mode, int nrhs,
                           hipStream_t s);
 template <typename T>
-hipError_t launch_coarse_solve(int D, const LV<T> &L0, const double *M, const double *S, int nrhs, hipStream_t s);
+// fas (3D): form the level's FAS right-hand side g + L phi from phi = old
+// inside the solve (after launch_restrict_fas without launch_fas_rhs)
+hipError_t launch_coarse_solve(int D, const LV<T> &L0, const double *M, const double *S, int fas, int nrhs,
+                               hipStream_t s);
 // The bottom of a FAS V-cycle (levels 0..top, 3D) in one cooperative launch.
 constexpr int kMaxSmallLevels = 8;
 template <typename T>
