@@ -1027,12 +1027,64 @@ __device__ __forceinline__ T halo_pick(const LV<T> &L, HaloLoads<T> h, int nb, i
     return nb >= 0 ? h.a : (nb == -1 ? T(0) : (zf ? h.a : T(2) * bv - h.a));
 }
 
+// colour slot m of thread t: the thread's cells are t + NT m, or with V2
+// adjacent pairs 2 (t + NT (m / 2)) + m % 2
+template <int NT, bool V2>
+__device__ __forceinline__ int cell_of(int t, int m) {
+    return V2 ? 2 * (t + NT * (m >> 1)) + (m & 1) : t + NT * m;
+}
+
+// the PER cells of thread t (slots of cell_of) from p, and back; with V2 one
+// 2-element vector access per pair (p even-aligned); NTL: non-temporal loads
+template <typename T, int PER, int NT, bool V2, bool NTL = false>
+__device__ __forceinline__ void load_cells(const T *p, int t, T *out) {
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    if (V2) {
+#pragma unroll
+        for (int m = 0; m < PER; m += 2) {
+            const T2 *a = reinterpret_cast<const T2 *>(p + cell_of<NT, true>(t, m));
+            const T2 w = NTL ? __builtin_nontemporal_load(a) : *a;
+            out[m] = w.x;
+            out[m + 1] = w.y;
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < PER; m++) out[m] = NTL ? __builtin_nontemporal_load(p + t + NT * m) : p[t + NT * m];
+    }
+}
+
+template <typename T, int PER, int NT, bool V2>
+__device__ __forceinline__ void store_cells(T *p, int t, const T *v) {
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    if (V2) {
+#pragma unroll
+        for (int m = 0; m < PER; m += 2) {
+            T2 w;
+            w.x = v[m];
+            w.y = v[m + 1];
+            *reinterpret_cast<T2 *>(p + cell_of<NT, true>(t, m)) = w;
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < PER; m++) p[t + NT * m] = v[m];
+    }
+}
+
+// paired cells are used on 16^3 blocks (an even number of cells per thread)
+constexpr bool kCellPairs = true;
+template <int N>
+constexpr bool cell_pairs() {
+    return kCellPairs && N == 16;
+}
+
 // Stage colour `col` of block `blk` and its face halos into a ColTile, the
 // halos at domain faces as the Dirichlet ghosts seen by the cells of the
 // other colour.  All global loads of the thread are issued before the LDS
 // writes.
 // NT threads stage the colour (t < NT); the faces take the first N*N.
-template <typename T, int N, bool ZERO, int NT = 256>
+// With V2 a thread's cells come in adjacent pairs (slots of cell_of), the
+// staged interior loaded with one 2-element vector access per pair.
+template <typename T, int N, bool ZERO, int NT = 256, bool V2 = false>
 __device__ __forceinline__ void stage_colour(T *tile, const LV<T> &L, const T *__restrict__ phi, int blk,
                                              const int *nbk, int4 P, int col, int t,
                                              const T *interior = nullptr) {
@@ -1044,9 +1096,11 @@ __device__ __forceinline__ void stage_colour(T *tile, const LV<T> &L, const T *_
     T r[PER];
     if (ZERO) {
         for (int e = t; e < CT::SIZE; e += NT) tile[e] = T(0);
-    } else {
+    } else if (interior) {
 #pragma unroll
-        for (int m = 0; m < PER; m++) r[m] = interior ? interior[m] : phi[(long long)blk * B::CPB + oc + t + NT * m];
+        for (int m = 0; m < PER; m++) r[m] = interior[m];
+    } else {
+        load_cells<T, PER, NT, V2>(phi + (long long)blk * B::CPB + oc, t, r);
     }
     const int ucol = 1 - col;
     const int fh = t % NH, fr = t / NH;  // y/z face entry (N*NH <= 256)
@@ -1085,7 +1139,7 @@ __device__ __forceinline__ void stage_colour(T *tile, const LV<T> &L, const T *_
     if (!ZERO) {
 #pragma unroll
         for (int m = 0; m < PER; m++) {
-            const int q = t + NT * m;
+            const int q = cell_of<NT, V2>(t, m);
             tile[CT::at(q / (NH * N), (q / NH) % N, q % NH)] = r[m];
         }
     } else {
@@ -1121,8 +1175,8 @@ __device__ __forceinline__ void tile_neighbours(const T *tile, int col, int q, i
     v[5] = tile[CT::at(k + 1, j, h)];
 }
 
-// red-black half sweep, NT threads per block
-template <typename T, int N, int NT = 256>
+// red-black half sweep, NT threads per block (V2: cells in adjacent pairs)
+template <typename T, int N, int NT = 256, bool V2 = false>
 __device__ __forceinline__ void gs_half3_body(const LV<T> &L, const LV<T> &Lc, int color, int blk, int rhs, T *tile) {
     using B = Blk<3, N>;
     constexpr int PER = B::HALF / NT;
@@ -1138,14 +1192,12 @@ __device__ __forceinline__ void gs_half3_body(const LV<T> &L, const LV<T> &Lc, i
     const T *__restrict__ gm = L.g + (long long)rhs * L.fstride + base + color * B::HALF;
     T gv[PER];
     int ri[PER];
+    // g is read once per sweep: non-temporal loads keep it from evicting the
+    // phi lines that neighbouring blocks read as halos
+    load_cells<T, PER, NT, V2, true>(gm, threadIdx.x, gv);
 #pragma unroll
-    for (int m = 0; m < PER; m++) {
-        // g is read once per sweep: keep it from evicting the phi lines
-        // that neighbouring blocks read as halos
-        gv[m] = __builtin_nontemporal_load(gm + threadIdx.x + NT * m);
-        ri[m] = mo >= 0 ? L.map[mo + color * B::HALF + threadIdx.x + NT * m] : -1;
-    }
-    stage_colour<T, N, false, NT>(tile, L, phi, blk, nbk, P, 1 - color, threadIdx.x);
+    for (int m = 0; m < PER; m++) ri[m] = mo >= 0 ? L.map[mo + color * B::HALF + cell_of<NT, V2>(threadIdx.x, m)] : -1;
+    stage_colour<T, N, false, NT, V2>(tile, L, phi, blk, nbk, P, 1 - color, threadIdx.x);
     __syncthreads();
     T *__restrict__ dst = phi + base + color * B::HALF;
     if (any_coarser(nbk)) {
@@ -1154,42 +1206,42 @@ __device__ __forceinline__ void gs_half3_body(const LV<T> &L, const LV<T> &Lc, i
         __syncthreads();
     }
     const T inv6 = T(1) / T(6);
+    T nv[PER];
 #pragma unroll
     for (int m = 0; m < PER; m++) {
-        const int q = threadIdx.x + NT * m;
+        const int q = cell_of<NT, V2>(threadIdx.x, m);
         int i, j, k;
         T v[6];
         tile_neighbours<T, N>(tile, color, q, i, j, k, v);
-        T nv;
         if (ri[m] < 0) {
-            nv = (((v[0] + v[1]) + (v[2] + v[3])) + (v[4] + v[5]) - L.dx2 * gv[m]) * inv6;
+            nv[m] = (((v[0] + v[1]) + (v[2] + v[3])) + (v[4] + v[5]) - L.dx2 * gv[m]) * inv6;
         } else {
             const T *r = L.rec + 8 * (long long)ri[m];
             T s = T(0);
 #pragma unroll
             for (int d = 0; d < 6; d++) s += r[d] * v[d];
             const T bt = L.b ? L.b[ri[m]] : T(0);
-            nv = (gv[m] - bt - s) * r[7];
+            nv[m] = (gv[m] - bt - s) * r[7];
         }
-        dst[q] = nv;
     }
+    store_cells<T, PER, NT, V2>(dst, threadIdx.x, nv);
 }
 
-template <typename T, int N, int NT>
+template <typename T, int N, int NT, bool V2>
 __global__ __launch_bounds__(NT) void k_gs_half3(LV<T> L, LV<T> Lc, int color) {
     __shared__ T tile[ColTile<N>::SIZE];
-    gs_half3_body<T, N, NT>(L, Lc, color, block_of(L), rhs_of(L), tile);
+    gs_half3_body<T, N, NT, V2>(L, Lc, color, block_of(L), rhs_of(L), tile);
 }
 
 // L phi at the PER cells of colour `col` owned by this thread, from the
 // other-colour tile (already staged, ghosts filled); `own` their values.
-template <typename T, int N, int NT = 256>
+template <typename T, int N, int NT = 256, bool V2 = false>
 __device__ __forceinline__ void tile_op(const LV<T> &L, const T *tile, const int *ri, int col, const T *own, T *out,
                                         int t) {
     constexpr int PER = Blk<3, N>::HALF / NT;
 #pragma unroll
     for (int m = 0; m < PER; m++) {
-        const int q = t + NT * m;
+        const int q = cell_of<NT, V2>(t, m);
         int i, j, k;
         T v[6];
         tile_neighbours<T, N>(tile, col, q, i, j, k, v);
@@ -1422,22 +1474,24 @@ struct PairTiles {
 template <typename T, int N, int NTC>
 __device__ __forceinline__ void pair_op(const LV<T> &L, const LV<T> &Lc, const T *phi, const T *phic, T *tiles,
                                         int blk, const int *nbk, int4 P, const int *ri, const T *own, T *out) {
+    constexpr bool V2 = cell_pairs<N>();
     const int c = threadIdx.x / NTC, t = threadIdx.x % NTC;
     T *mine = tiles + c * ColTile<N>::SIZE, *other = tiles + (1 - c) * ColTile<N>::SIZE;
-    stage_colour<T, N, false, NTC>(mine, L, phi, blk, nbk, P, c, t, own);
+    stage_colour<T, N, false, NTC, V2>(mine, L, phi, blk, nbk, P, c, t, own);
     __syncthreads();
     if (any_coarser(nbk)) {
         coarser_face_ghosts<T, N>(other, Lc, phi + (long long)blk * Blk<3, N>::CPB + c * Blk<3, N>::HALF, phic, nbk,
                                   P, c, t);
         __syncthreads();
     }
-    tile_op<T, N, NTC>(L, other, ri, c, own, out, t);
+    tile_op<T, N, NTC, V2>(L, other, ri, c, own, out, t);
 }
 
 template <typename T, int N, int NC, int NTC>
 __global__ __launch_bounds__(2 * NTC) void k_restrict_fas3_pair(LV<T> L, LV<T> Lc, int into_old) {
     using B = Blk<3, N>;
     constexpr int PER = B::HALF / NTC, H = N / 2, NCELL = H * H * H;
+    constexpr bool V2 = cell_pairs<N>();
     constexpr int SM = PairTiles<T, N>::SIZE > 2 * B::CPB ? PairTiles<T, N>::SIZE : 2 * B::CPB;
     __shared__ T sm[SM];
     const int blk = block_of(L), rhs = rhs_of(L);
@@ -1455,13 +1509,10 @@ __global__ __launch_bounds__(2 * NTC) void k_restrict_fas3_pair(LV<T> L, LV<T> L
     const long long base = (long long)blk * B::CPB + c * B::HALF;
     T own[PER], r[PER], gv[PER];
     int ri[PER];
+    load_cells<T, PER, NTC, V2>(phi + base, t, own);
+    load_cells<T, PER, NTC, V2>(g + base, t, gv);
 #pragma unroll
-    for (int m = 0; m < PER; m++) {
-        const int s = t + NTC * m;
-        own[m] = phi[base + s];
-        gv[m] = g[base + s];
-        ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + s] : -1;
-    }
+    for (int m = 0; m < PER; m++) ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + cell_of<NTC, V2>(t, m)] : -1;
     pair_op<T, N, NTC>(L, Lc, phi, phic, sm, blk, nbk, P, ri, own, r);
 #pragma unroll
     for (int m = 0; m < PER; m++) r[m] = gv[m] - r[m];
@@ -1470,7 +1521,7 @@ __global__ __launch_bounds__(2 * NTC) void k_restrict_fas3_pair(LV<T> L, LV<T> L
 #pragma unroll
     for (int m = 0; m < PER; m++) {
         int i, j, k;
-        q_to_ijk<N>(c, t + NTC * m, i, j, k);
+        q_to_ijk<N>(c, cell_of<NTC, V2>(t, m), i, j, k);
         sr[(k * N + j) * N + i] = r[m];
         sp[(k * N + j) * N + i] = own[m];
     }
@@ -1503,6 +1554,7 @@ template <typename T, int N, int NTC>
 __global__ __launch_bounds__(2 * NTC) void k_fas_rhs3_pair(LV<T> L, LV<T> Lc, int do_rhs) {
     using B = Blk<3, N>;
     constexpr int PER = B::HALF / NTC;
+    constexpr bool V2 = cell_pairs<N>();
     __shared__ T tiles[PairTiles<T, N>::SIZE];
     const int blk = block_of(L), rhs = rhs_of(L);
     const int c = threadIdx.x / NTC, t = threadIdx.x % NTC;
@@ -1526,20 +1578,15 @@ __global__ __launch_bounds__(2 * NTC) void k_fas_rhs3_pair(LV<T> L, LV<T> Lc, in
     const long long base = (long long)blk * B::CPB + c * B::HALF;
     T own[PER], lp[PER], gv[PER];
     int ri[PER];
+    load_cells<T, PER, NTC, V2>(phi + base, t, own);
+    load_cells<T, PER, NTC, V2>(g + base, t, gv);
 #pragma unroll
-    for (int m = 0; m < PER; m++) {
-        const int s = t + NTC * m;
-        own[m] = phi[base + s];
-        gv[m] = g[base + s];
-        ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + s] : -1;
-    }
+    for (int m = 0; m < PER; m++) ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + cell_of<NTC, V2>(t, m)] : -1;
     pair_op<T, N, NTC>(L, Lc, phi, phic, tiles, blk, nbk, P, ri, own, lp);
 #pragma unroll
-    for (int m = 0; m < PER; m++) {
-        const int s = t + NTC * m;
-        g[base + s] = lp[m] + gv[m];
-        old[base + s] = own[m];
-    }
+    for (int m = 0; m < PER; m++) lp[m] = lp[m] + gv[m];
+    store_cells<T, PER, NTC, V2>(g + base, t, lp);
+    store_cells<T, PER, NTC, V2>(old + base, t, own);
 }
 
 // FAS right-hand side fused with the first red half sweep of a coarse
@@ -1555,6 +1602,7 @@ template <typename T, int N, int NTC>
 __global__ __launch_bounds__(2 * NTC) void k_fas_gs3_pair(LV<T> L, LV<T> Lc) {
     using B = Blk<3, N>;
     constexpr int PER = B::HALF / NTC;
+    constexpr bool V2 = cell_pairs<N>();
     __shared__ T tiles[PairTiles<T, N>::SIZE];
     const int blk = block_of(L), rhs = rhs_of(L);
     const int c = threadIdx.x / NTC, t = threadIdx.x % NTC;
@@ -1573,50 +1621,46 @@ __global__ __launch_bounds__(2 * NTC) void k_fas_gs3_pair(LV<T> L, LV<T> Lc) {
     const long long base = (long long)blk * B::CPB + c * B::HALF;
     T own[PER], lp[PER], gv[PER];
     int ri[PER];
+    load_cells<T, PER, NTC, V2>(old + base, t, own);
+    load_cells<T, PER, NTC, V2>(g + base, t, gv);
 #pragma unroll
-    for (int m = 0; m < PER; m++) {
-        const int s = t + NTC * m;
-        own[m] = old[base + s];
-        gv[m] = g[base + s];
-        ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + s] : -1;
-    }
+    for (int m = 0; m < PER; m++) ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + cell_of<NTC, V2>(t, m)] : -1;
     pair_op<T, N, NTC>(L, Lc, old, phic, tiles, blk, nbk, P, ri, own, lp);
     if (!leaf) {
 #pragma unroll
-        for (int m = 0; m < PER; m++) {
-            gv[m] = lp[m] + gv[m];
-            g[base + t + NTC * m] = gv[m];
-        }
+        for (int m = 0; m < PER; m++) gv[m] = lp[m] + gv[m];
+        store_cells<T, PER, NTC, V2>(g + base, t, gv);
     }
     if (c != 0) return;
     // red half sweep from the black tile (its ghosts were filled for the red cells)
     const T *tile = tiles + ColTile<N>::SIZE;
     const T inv6 = T(1) / T(6);
+    T nv[PER];
 #pragma unroll
     for (int m = 0; m < PER; m++) {
-        const int q = t + NTC * m;
+        const int q = cell_of<NTC, V2>(t, m);
         int i, j, k;
         T v[6];
         tile_neighbours<T, N>(tile, 0, q, i, j, k, v);
-        T nv;
         if (ri[m] < 0) {
-            nv = (((v[0] + v[1]) + (v[2] + v[3])) + (v[4] + v[5]) - L.dx2 * gv[m]) * inv6;
+            nv[m] = (((v[0] + v[1]) + (v[2] + v[3])) + (v[4] + v[5]) - L.dx2 * gv[m]) * inv6;
         } else {
             const T *r = L.rec + 8 * (long long)ri[m];
             T sm = T(0);
 #pragma unroll
             for (int d = 0; d < 6; d++) sm += r[d] * v[d];
             const T bt = L.b ? L.b[ri[m]] : T(0);
-            nv = (gv[m] - bt - sm) * r[7];
+            nv[m] = (gv[m] - bt - sm) * r[7];
         }
-        phi[base + q] = nv;
     }
+    store_cells<T, PER, NTC, V2>(phi + base, t, nv);
 }
 
 template <typename T, int N, int NTC>
 __global__ __launch_bounds__(2 * NTC) void k_residual_max3_pair(LV<T> L, LV<T> Lc, unsigned long long *out) {
     using B = Blk<3, N>;
     constexpr int PER = B::HALF / NTC;
+    constexpr bool V2 = cell_pairs<N>();
     __shared__ T tiles[PairTiles<T, N>::SIZE];
     __shared__ double wmax[2 * NTC / 64];
     const int blk = block_of(L), rhs = rhs_of(L);
@@ -1635,13 +1679,10 @@ __global__ __launch_bounds__(2 * NTC) void k_residual_max3_pair(LV<T> L, LV<T> L
     const long long base = (long long)blk * B::CPB + c * B::HALF;
     T own[PER], lp[PER], gv[PER];
     int ri[PER];
+    load_cells<T, PER, NTC, V2>(phi + base, t, own);
+    load_cells<T, PER, NTC, V2>(g + base, t, gv);
 #pragma unroll
-    for (int m = 0; m < PER; m++) {
-        const int s = t + NTC * m;
-        own[m] = phi[base + s];
-        gv[m] = g[base + s];
-        ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + s] : -1;
-    }
+    for (int m = 0; m < PER; m++) ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + cell_of<NTC, V2>(t, m)] : -1;
     pair_op<T, N, NTC>(L, Lc, phi, phic, tiles, blk, nbk, P, ri, own, lp);
     double mx = 0.0;
 #pragma unroll
@@ -1721,6 +1762,7 @@ template <typename T, int N, int NC, bool SOL, int NT>
 __device__ __forceinline__ void prolong3_body(const LV<T> &L, const LV<T> &Lc, int blk, int rhs, T *et) {
     using B = Blk<3, N>;
     constexpr int H = N / 2, E = H + 2, ESZ = E * E * E, PER = B::CPB / NT, EPER = (ESZ + NT - 1) / NT;
+    constexpr bool V2 = cell_pairs<N>();
     const int4 P = L.pos[blk];
     const int act = L.active ? L.active[rhs] : 1;
     asm volatile("" ::"s"(act), "s"(P.x), "s"(P.y), "s"(P.z));  // both loads in one round trip
@@ -1729,8 +1771,7 @@ __device__ __forceinline__ void prolong3_body(const LV<T> &L, const LV<T> &Lc, i
     const T *oldc = Lc.old + (long long)rhs * Lc.fstride;
     T *__restrict__ phi = L.phi + (long long)rhs * L.fstride + (long long)blk * B::CPB;
     T f[PER];
-#pragma unroll
-    for (int m = 0; m < PER; m++) f[m] = phi[threadIdx.x + NT * m];
+    load_cells<T, PER, NT, V2>(phi, threadIdx.x, f);
     const int C0[3] = {P.x * H, P.y * H, P.z * H};
     T ev[EPER];
 #pragma unroll
@@ -1749,7 +1790,7 @@ __device__ __forceinline__ void prolong3_body(const LV<T> &L, const LV<T> &Lc, i
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < PER; m++) {
-        const int s = threadIdx.x + NT * m;
+        const int s = cell_of<NT, V2>(threadIdx.x, m);
         int i, j, k;
         q_to_ijk<N>(s / B::HALF, s % B::HALF, i, j, k);
         const int ci = (i >> 1) + 1, cj = (j >> 1) + 1, ck = (k >> 1) + 1;
@@ -1761,8 +1802,9 @@ __device__ __forceinline__ void prolong3_body(const LV<T> &L, const LV<T> &Lc, i
             const T w = (ax ? T(0.25) : T(0.75)) * (ay ? T(0.25) : T(0.75)) * (az ? T(0.25) : T(0.75));
             e = e + w * et[((ck + az * oz) * E + (cj + ay * oy)) * E + (ci + ax * ox)];
         }
-        phi[s] = f[m] + e;
+        f[m] = f[m] + e;
     }
+    store_cells<T, PER, NT, V2>(phi, threadIdx.x, f);
 }
 
 template <typename T, int N, int NC, bool SOL, int NT>
@@ -2001,10 +2043,10 @@ hipError_t launch_gs_half(int D, int N, const LV<T> &L, const LV<T> &Lc, int col
     // 16^3 blocks: launches of at most pair_max workgroups split a colour
     // over 512 threads (4 cells each instead of 8)
     if (D == 3 && N == 16 && (long long)L.nblocks * nrhs <= L.pair_max) {
-        hipLaunchKernelGGL((k_gs_half3<T, 16, 512>), grid, dim3(512), 0, s, L, Lc, color);
+        hipLaunchKernelGGL((k_gs_half3<T, 16, 512, cell_pairs<16>()>), grid, dim3(512), 0, s, L, Lc, color);
         return hipGetLastError();
     }
-#define GS3(N_) OCTMG_DN(3, N_, hipLaunchKernelGGL((k_gs_half3<T, N_, 256>), grid, dim3(256), 0, s, L, Lc, color))
+#define GS3(N_) OCTMG_DN(3, N_, hipLaunchKernelGGL((k_gs_half3<T, N_, 256, false>), grid, dim3(256), 0, s, L, Lc, color))
     GS3(16) GS3(8) GS(2, 8) GS(2, 16)
 #undef GS3
 #undef GS
