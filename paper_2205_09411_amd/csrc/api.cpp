@@ -272,7 +272,8 @@ struct Engine {
         for (int k = 0; k < steps; k++)
             for (int color = 0; color < 2; color++) {
                 if (fas_first && k == 0 && color == 0)
-                    HIPCK(launch_fas_gs<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1), s->n_launch, st));
+                    HIPCK(launch_fas_gs<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1),
+                                           s->geom->tree.adaptive ? 1 : 0, s->n_launch, st));
                 else
                     HIPCK(launch_gs_half<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1), color, s->n_launch, st));
                 if (P && P->on) {
@@ -300,12 +301,14 @@ struct Engine {
         return OCTMG_OK;
     }
     // FAS restriction il -> il-1 without the right-hand side, which the first
-    // half sweep of il-1 then forms (smooth with fas_first); leaves phi = old
-    // on every block of il-1
+    // half sweep of il-1 (smooth with fas_first), or the coarse solve, then
+    // forms from old.  On adaptive trees the restriction writes old only and
+    // leaf blocks copy phi to old here; the parents' phi is set by that
+    // half sweep (the coarse solve overwrites it).
     octmg_status restrict_only(int il) {
         const int adaptive = s->geom->tree.adaptive ? 1 : 0;
         HIPCK(launch_restrict_fas<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), adaptive, s->n_launch, st));
-        if (adaptive) HIPCK(launch_copy_parents<T>(D(), Nb(il - 1), lvT<T>(s, il - 1), s->n_launch, st));
+        if (adaptive) HIPCK(launch_copy_parents<T>(D(), Nb(il - 1), lvT<T>(s, il - 1), s->n_launch, st, 1));
         return OCTMG_OK;
     }
     // whether coarse level lc of a V-cycle whose levels up to ft run fused
@@ -371,10 +374,12 @@ struct Engine {
         }
         return OCTMG_OK;
     }
-    octmg_status cycle(int kind, int have_guess) {
+    // sync: leave the coarse copies of leaf values current (not needed when
+    // the iterate is a correction that only the leaves pass on)
+    octmg_status cycle(int kind, int have_guess, bool sync = true) {
         const int top = (int)s->geom->L.size() - 1;
         STCK(kind == OCTMG_CYCLE_FMG ? fmg(have_guess) : vcycle(top));
-        return sync_down();
+        return sync ? sync_down() : OCTMG_OK;
     }
 };
 
@@ -399,9 +404,10 @@ hipError_t Engine<double>::fill(double *p, long long n) { return launch_fill(p, 
 template <>
 hipError_t Engine<float>::fill(float *p, long long n) { return launch_fillf(p, n, 0.0f, st); }
 
-octmg_status residual_norm_dev(octmg_state s, int phi_zero, hipStream_t st) {
+// synced: phi's coarse copies are already current (right after a cycle)
+octmg_status residual_norm_dev(octmg_state s, int phi_zero, hipStream_t st, bool synced = false) {
     HIPCK(launch_fill_u64(s->d_norm, s->nrhs, 0ull, st));
-    if (!phi_zero) {
+    if (!phi_zero && !synced) {
         Engine<double> e{s, st};
         STCK(e.sync_down());
     }
@@ -455,7 +461,7 @@ octmg_status mixed_defect(octmg_state s, hipStream_t st) {
 
 octmg_status mixed_correct(octmg_state s, int kind, hipStream_t st) {
     Engine<float> e32{s, st};
-    STCK(e32.cycle(kind, kind == OCTMG_CYCLE_FMG ? 0 : 1));
+    STCK(e32.cycle(kind, kind == OCTMG_CYCLE_FMG ? 0 : 1, false));  // only leaf values are passed on
     const int D = s->geom->tree.D;
     for (int il = 0; il < (int)s->geom->L.size(); il++) {
         const GeomLevel &G = s->geom->L[il];
@@ -1383,7 +1389,7 @@ static octmg_status cycle_and_norm(octmg_state s, int kind, int have_guess, hipS
     } else {
         Engine<double> e{s, st};
         STCK(e.cycle(kind, have_guess));
-        STCK(residual_norm_dev(s, 0, st));
+        STCK(residual_norm_dev(s, 0, st, true));
     }
     HIPCK(launch_copy_u64(s->d_norm, s->h_norm_dev, s->nrhs, st));
     return OCTMG_OK;

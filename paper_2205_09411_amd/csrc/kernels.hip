@@ -282,7 +282,7 @@ __global__ __launch_bounds__(256) void k_restrict_fas(LV<T> L, LV<T> Lc, int int
 }
 
 template <typename T, int D, int N>
-__global__ __launch_bounds__(256) void k_copy_parents(LV<T> L) {
+__global__ __launch_bounds__(256) void k_copy_parents(LV<T> L, int leaves_only) {
     if (inactive(L)) return;
     const int blk = blockIdx.x;
     const long long o = (long long)rhs_of(L) * L.fstride + (long long)blk * Blk<D, N>::CPB;
@@ -290,6 +290,7 @@ __global__ __launch_bounds__(256) void k_copy_parents(LV<T> L) {
         for (int c = threadIdx.x; c < Blk<D, N>::CPB; c += blockDim.x) L.old[o + c] = L.phi[o + c];
         return;
     }
+    if (leaves_only) return;
     for (int c = threadIdx.x; c < Blk<D, N>::CPB; c += blockDim.x) L.phi[o + c] = L.old[o + c];
 }
 
@@ -1599,7 +1600,7 @@ __global__ __launch_bounds__(2 * NTC) void k_fas_rhs3_pair(LV<T> L, LV<T> Lc, in
 // the black tile with that g.  Term by term the arithmetic of k_fas_rhs3
 // followed by k_gs_half3 on colour 0: the same bits.
 template <typename T, int N, int NTC>
-__global__ __launch_bounds__(2 * NTC) void k_fas_gs3_pair(LV<T> L, LV<T> Lc) {
+__global__ __launch_bounds__(2 * NTC) void k_fas_gs3_pair(LV<T> L, LV<T> Lc, int own_to_phi) {
     using B = Blk<3, N>;
     constexpr int PER = B::HALF / NTC;
     constexpr bool V2 = cell_pairs<N>();
@@ -1631,7 +1632,12 @@ __global__ __launch_bounds__(2 * NTC) void k_fas_gs3_pair(LV<T> L, LV<T> Lc) {
         for (int m = 0; m < PER; m++) gv[m] = lp[m] + gv[m];
         store_cells<T, PER, NTC, V2>(g + base, t, gv);
     }
-    if (c != 0) return;
+    if (c != 0) {
+        // black cells of a parent block: phi <- old, when the restriction
+        // wrote old only (no workgroup reads phi of this level here)
+        if (own_to_phi && !leaf) store_cells<T, PER, NTC, V2>(phi + base, t, own);
+        return;
+    }
     // red half sweep from the black tile (its ghosts were filled for the red cells)
     const T *tile = tiles + ColTile<N>::SIZE;
     const T inv6 = T(1) / T(6);
@@ -2074,10 +2080,10 @@ hipError_t launch_restrict_fas(int D, int N, int Nc, const LV<T> &L, const LV<T>
 }
 
 template <typename T>
-hipError_t launch_copy_parents(int D, int N, const LV<T> &L, int nrhs, hipStream_t s) {
+hipError_t launch_copy_parents(int D, int N, const LV<T> &L, int nrhs, hipStream_t s, int leaves_only) {
     if (L.nblocks == 0) return hipSuccess;
     dim3 grid(L.nblocks, nrhs);
-#define CP(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_copy_parents<T, D_, N_>), grid, dim3(256), 0, s, L))
+#define CP(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_copy_parents<T, D_, N_>), grid, dim3(256), 0, s, L, leaves_only))
     CP(3, 16) CP(3, 8) CP(2, 8) CP(2, 16)
 #undef CP
     return hipErrorInvalidValue;
@@ -2119,10 +2125,10 @@ hipError_t launch_fas_rhs(int D, int N, const LV<T> &L, const LV<T> &Lc, int par
 }
 
 template <typename T>
-hipError_t launch_fas_gs(int D, int N, const LV<T> &L, const LV<T> &Lc, int nrhs, hipStream_t s) {
+hipError_t launch_fas_gs(int D, int N, const LV<T> &L, const LV<T> &Lc, int own_to_phi, int nrhs, hipStream_t s) {
     if (L.nblocks == 0) return hipSuccess;
     dim3 grid(L.nblocks, nrhs);
-#define FG3(N_) OCTMG_DN(3, N_, hipLaunchKernelGGL((k_fas_gs3_pair<T, N_, fas_ntc<N_>()>), grid, dim3(2 * fas_ntc<N_>()), 0, s, L, Lc))
+#define FG3(N_) OCTMG_DN(3, N_, hipLaunchKernelGGL((k_fas_gs3_pair<T, N_, fas_ntc<N_>()>), grid, dim3(2 * fas_ntc<N_>()), 0, s, L, Lc, own_to_phi))
     FG3(16) FG3(8)
 #undef FG3
     return hipErrorInvalidValue;
@@ -2331,11 +2337,11 @@ hipError_t launch_check_finite(const double *p, long long n, int *flag, hipStrea
 #define OCTMG_INST(T)                                                                                              \
     template hipError_t launch_gs_half<T>(int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t);           \
     template hipError_t launch_restrict_fas<T>(int, int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t); \
-    template hipError_t launch_copy_parents<T>(int, int, const LV<T> &, int, hipStream_t);                         \
+    template hipError_t launch_copy_parents<T>(int, int, const LV<T> &, int, hipStream_t, int);                    \
     template hipError_t launch_restrict_rhs<T>(int, int, int, const LV<T> &, const LV<T> &, int, hipStream_t);      \
     template hipError_t launch_restrict_phi<T>(int, int, int, const LV<T> &, const LV<T> &, int, hipStream_t);      \
     template hipError_t launch_fas_rhs<T>(int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t);           \
-    template hipError_t launch_fas_gs<T>(int, int, const LV<T> &, const LV<T> &, int, hipStream_t);                  \
+    template hipError_t launch_fas_gs<T>(int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t);             \
     template hipError_t launch_prolong<T>(int, int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t);      \
     template hipError_t launch_coarse_solve<T>(int, const LV<T> &, const double *, const double *, int, int, hipStream_t); \
     template hipError_t launch_residual_max<T>(int, int, const LV<T> &, const LV<T> &, int, unsigned long long *, int, hipStream_t);

@@ -94,17 +94,21 @@ template <typename T>
 hipError_t launch_restrict_fas(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int into_old, int nrhs,
                                hipStream_t s);
 template <typename T>
-hipError_t launch_copy_parents(int D, int N, const LV<T> &L, int nrhs, hipStream_t s);
+// leaves_only: only the leaf blocks' old <- phi (the parents' phi <- old is
+// then left to launch_fas_gs with own_to_phi)
+hipError_t launch_copy_parents(int D, int N, const LV<T> &L, int nrhs, hipStream_t s, int leaves_only = 0);
 template <typename T>
 hipError_t launch_restrict_rhs(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int nrhs, hipStream_t s);
 template <typename T>
 hipError_t launch_fas_rhs(int D, int N, const LV<T> &L, const LV<T> &Lc, int parents_only, int nrhs, hipStream_t s);
 // 3D: the FAS right-hand side of level L (g <- L phi + g on parent blocks)
-// fused with its first red half sweep; needs phi = old on every block (as
-// the 3D restriction, plus launch_copy_parents on adaptive trees, leaves
-// them).  Same results as launch_fas_rhs then launch_gs_half(colour 0).
+// fused with its first red half sweep; needs old = the restricted values on
+// parent blocks and old = phi on leaf blocks (as the 3D restriction, plus
+// launch_copy_parents on adaptive trees, leaves them).  own_to_phi: also
+// set the black phi of parent blocks from old (when the restriction wrote
+// old only).  Same results as launch_fas_rhs then launch_gs_half(colour 0).
 template <typename T>
-hipError_t launch_fas_gs(int D, int N, const LV<T> &L, const LV<T> &Lc, int nrhs, hipStream_t s);
+hipError_t launch_fas_gs(int D, int N, const LV<T> &L, const LV<T> &Lc, int own_to_phi, int nrhs, hipStream_t s);
 template <typename T>
 hipError_t launch_restrict_phi(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int nrhs, hipStream_t s);
 template <typename T>
