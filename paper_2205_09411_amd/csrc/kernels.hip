@@ -1107,7 +1107,7 @@ __device__ __forceinline__ void stage_colour(T *tile, const LV<T> &L, const T *_
     const int fh = t % NH, fr = t / NH;  // y/z face entry (N*NH <= 256)
     const int xj = t % N, xk = t / N;    // x face entry (N*N <= 256)
     const bool fz = t < N * NH, fx = t < N * N;
-    HaloLoads<T> hy0{}, hy1{}, hz0{}, hz1{}, hx0{}, hx1{};
+    HaloLoads<T> hy0{}, hy1{}, hz0{}, hz1{}, hx{};
     if (fz) {
         // y faces: entry (k = fr, h = fh); z faces: entry (j = fr, h = fh)
         const int ky = fr, jz = fr;
@@ -1120,23 +1120,22 @@ __device__ __forceinline__ void stage_colour(T *tile, const LV<T> &L, const T *_
         hz1 = halo_load<T, N, ZERO>(L, phi, own_col, nbk[5], oc + jz * NH + fh, 5, P,
                                     2 * fh + ((ucol + jz + N - 1) & 1), jz, N - 1, ((N - 1) * N + jz) * NH + fh);
     }
+    // x faces: entry (j = xj, k = xk).  A row's reading cells sit at
+    // i = 0 or at i = N-1, by its parity: it reads exactly one of its two x
+    // halos (x- when xp = 0, else x+), the only one loaded
+    const int xp = (ucol + xj + xk) & 1, nbx = xp ? nbk[1] : nbk[0];
     if (fx) {
-        // x faces: entry (j = xj, k = xk); the halo slot is read only by rows
-        // whose reading cell sits on the face (i = 0, resp. i = N-1); on the
-        // other rows the value is unused
-        hx0 = halo_load<T, N, ZERO>(L, phi, own_col, nbk[0], oc + (xk * N + xj) * NH + NH - 1, 0, P, 0, xj, xk,
-                                    (xk * N + xj) * NH);
-        hx1 = halo_load<T, N, ZERO>(L, phi, own_col, nbk[1], oc + (xk * N + xj) * NH, 1, P, N - 1, xj, xk,
-                                    (xk * N + xj) * NH + NH - 1);
+        hx = halo_load<T, N, ZERO>(L, phi, own_col, nbx, oc + (xk * N + xj) * NH + (xp ? 0 : NH - 1), xp, P,
+                                   xp ? N - 1 : 0, xj, xk, (xk * N + xj) * NH + (xp ? NH - 1 : 0));
     }
     // one wait for all face loads (the empty asm consumes them; without it
     // the compiler moves each face's second load into a branch and waits
     // for it there, one round trip per face)
     asm volatile("" ::"v"(hy0.a), "v"(hy0.b), "v"(hy1.a), "v"(hy1.b), "v"(hz0.a), "v"(hz0.b), "v"(hz1.a),
-                 "v"(hz1.b), "v"(hx0.a), "v"(hx0.b), "v"(hx1.a), "v"(hx1.b));
+                 "v"(hz1.b), "v"(hx.a), "v"(hx.b));
     const T y0 = halo_pick<T, ZERO>(L, hy0, nbk[2], 2), y1 = halo_pick<T, ZERO>(L, hy1, nbk[3], 3);
     const T z0 = halo_pick<T, ZERO>(L, hz0, nbk[4], 4), z1 = halo_pick<T, ZERO>(L, hz1, nbk[5], 5);
-    const T x0 = halo_pick<T, ZERO>(L, hx0, nbk[0], 0), x1 = halo_pick<T, ZERO>(L, hx1, nbk[1], 1);
+    const T xv = halo_pick<T, ZERO>(L, hx, nbx, xp);
     if (!ZERO) {
 #pragma unroll
         for (int m = 0; m < PER; m++) {
@@ -1152,10 +1151,7 @@ __device__ __forceinline__ void stage_colour(T *tile, const LV<T> &L, const T *_
         tile[CT::at(-1, fr, fh)] = z0;
         tile[CT::at(N, fr, fh)] = z1;
     }
-    if (fx) {
-        tile[CT::at(xk, xj, -1)] = x0;
-        tile[CT::at(xk, xj, NH)] = x1;
-    }
+    if (fx) tile[CT::at(xk, xj, xp ? NH : -1)] = xv;
 }
 
 // the 6 neighbour values of cell q of colour `col` from the other-colour tile
