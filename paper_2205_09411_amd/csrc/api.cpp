@@ -137,6 +137,11 @@ struct octmg_state_s {
     std::vector<Fields32> f32;
     std::vector<long long> stride;  // per level: cells per rhs
     unsigned long long *d_norm = nullptr;
+    unsigned long long *d_norm_slots = nullptr;  // per-rhs slots the norm kernels combine into
+    // the slots are zero (left so by the last reduction); false from the
+    // first norm kernel until the reduction, so that a norm cut short by an
+    // error is followed by a clearing fill
+    bool norm_slots_clean = false;
     int *d_flag = nullptr;
     // launch set: d_active[0, nrhs) = 1 while a right-hand side iterates;
     // d_active[nrhs, nrhs + n_launch) = the iterating right-hand sides, which
@@ -405,8 +410,10 @@ template <>
 hipError_t Engine<float>::fill(float *p, long long n) { return launch_fillf(p, n, 0.0f, st); }
 
 // synced: phi's coarse copies are already current (right after a cycle)
+// The norms land in d_norm and in the mapped host buffer.
 octmg_status residual_norm_dev(octmg_state s, int phi_zero, hipStream_t st, bool synced = false) {
-    HIPCK(launch_fill_u64(s->d_norm, s->nrhs, 0ull, st));
+    if (!s->norm_slots_clean) HIPCK(launch_fill_u64(s->d_norm_slots, norm_slot_words(s->nrhs), 0ull, st));
+    s->norm_slots_clean = false;
     if (!phi_zero && !synced) {
         Engine<double> e{s, st};
         STCK(e.sync_down());
@@ -415,15 +422,26 @@ octmg_status residual_norm_dev(octmg_state s, int phi_zero, hipStream_t st, bool
     for (int il = 0; il < (int)s->geom->L.size(); il++) {
         const GeomLevel &G = s->geom->L[il];
         if (G.nleaf == 0) continue;
-        HIPCK(launch_residual_max<double>(D, G.Nb, lv64(s, il), lv64(s, il - 1), phi_zero, s->d_norm, s->n_launch, st));
+        HIPCK(launch_residual_max<double>(D, G.Nb, lv64(s, il), lv64(s, il - 1), phi_zero, s->d_norm_slots,
+                                          s->n_launch, st));
     }
+    HIPCK(launch_norm_reduce(s->d_norm_slots, s->d_norm, s->h_norm_dev, s->nrhs, st));
+    s->norm_slots_clean = true;
     return OCTMG_OK;
 }
 
-// the norms reach the host through a pinned, host-mapped buffer written by a
-// one-workgroup kernel (cheaper than a copy for a few bytes)
+// Before replaying a captured graph: its norm kernels assume zero slots,
+// which an eager norm cut short by an error may have left otherwise.
+octmg_status clean_norm_slots(octmg_state s, hipStream_t st) {
+    if (!s->norm_slots_clean) HIPCK(launch_fill_u64(s->d_norm_slots, norm_slot_words(s->nrhs), 0ull, st));
+    s->norm_slots_clean = true;
+    return OCTMG_OK;
+}
+
+// the norms reach the host through a pinned, host-mapped buffer, written by
+// the one-workgroup kernel that reduces the norm slots (cheaper than a copy
+// for a few bytes); called after residual_norm_dev or mixed_defect
 octmg_status read_norms(octmg_state s, double *out, hipStream_t st) {
-    HIPCK(launch_copy_u64(s->d_norm, s->h_norm_dev, s->nrhs, st));
     HIPCK(hipStreamSynchronize(st));
     for (int r = 0; r < s->nrhs; r++) {
         const unsigned long long v = ((volatile unsigned long long *)s->h_norm)[r];
@@ -437,7 +455,8 @@ octmg_status read_norms(octmg_state s, double *out, hipStream_t st) {
 octmg_status mixed_defect(octmg_state s, hipStream_t st) {
     Engine<double> e64{s, st};
     STCK(e64.sync_down());
-    HIPCK(launch_fill_u64(s->d_norm, s->nrhs, 0ull, st));
+    if (!s->norm_slots_clean) HIPCK(launch_fill_u64(s->d_norm_slots, norm_slot_words(s->nrhs), 0ull, st));
+    s->norm_slots_clean = false;
     const int D = s->geom->tree.D;
     // The correction starts from zero.  The defect below zeroes it on every
     // leaf block, and restriction overwrites every parent block before the
@@ -453,9 +472,11 @@ octmg_status mixed_defect(octmg_state s, hipStream_t st) {
     for (int il = 0; il < (int)s->geom->L.size(); il++) {
         const GeomLevel &G = s->geom->L[il];
         if (G.nleaf == 0) continue;
-        HIPCK(launch_defect(D, G.Nb, lv64(s, il), lv64(s, il - 1), lv32(s, il), G.d_leaf_blocks, G.nleaf, s->d_norm,
-                            s->n_launch, st));
+        HIPCK(launch_defect(D, G.Nb, lv64(s, il), lv64(s, il - 1), lv32(s, il), G.d_leaf_blocks, G.nleaf,
+                            s->d_norm_slots, s->n_launch, st));
     }
+    HIPCK(launch_norm_reduce(s->d_norm_slots, s->d_norm, s->h_norm_dev, s->nrhs, st));
+    s->norm_slots_clean = true;
     return OCTMG_OK;
 }
 
@@ -1040,6 +1061,7 @@ octmg_status octmg_state_create(octmg_geom g, int n_rhs, int precision, octmg_st
         }
     }
     HIPCK(s->pool.alloc(&s->d_norm, n_rhs));
+    HIPCK(s->pool.alloc(&s->d_norm_slots, (size_t)norm_slot_words(n_rhs)));
     HIPCK(s->pool.alloc(&s->d_flag, 1));
     HIPCK(s->pool.alloc(&s->d_active, 2 * (size_t)n_rhs));
     s->active_host.assign(n_rhs, 1);
@@ -1391,7 +1413,6 @@ static octmg_status cycle_and_norm(octmg_state s, int kind, int have_guess, hipS
         STCK(e.cycle(kind, have_guess));
         STCK(residual_norm_dev(s, 0, st, true));
     }
-    HIPCK(launch_copy_u64(s->d_norm, s->h_norm_dev, s->nrhs, st));
     return OCTMG_OK;
 }
 
@@ -1407,11 +1428,14 @@ static octmg_status graph_for(octmg_state s, long long key, hipStream_t st, F &&
     // profiling events and counters cover eager launches only
     const bool prof_on = s->prof && s->prof->on;
     if (prof_on) s->prof->on = false;
+    // capturing runs no kernel: the state of the norm slots is unchanged
+    const bool slots_clean = s->norm_slots_clean;
     HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     const octmg_status r = body();
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(st, &g);
     if (prof_on) s->prof->on = true;
+    s->norm_slots_clean = slots_clean;
     if (r != OCTMG_OK) {
         if (e == hipSuccess && g) (void)hipGraphDestroy(g);
         return r;
@@ -1498,6 +1522,7 @@ static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStre
             }
             return OCTMG_OK;
         }, &exec));
+        STCK(clean_norm_slots(s, st));
         HIPCK(hipGraphLaunch(exec, st));
         std::vector<double> hist((size_t)o->max_cycles * R);
         std::vector<int> act_after(R);
@@ -1574,6 +1599,7 @@ static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStre
             const long long key = graph_key(1, o->cycle_kind, 0, 0, s->n_launch);
             hipGraphExec_t exec = nullptr;
             STCK(graph_for(s, key, st, [&]() { return cycle_and_norm(s, o->cycle_kind, 1, st); }, &exec));
+            STCK(clean_norm_slots(s, st));
             HIPCK(hipGraphLaunch(exec, st));
         } else {
             STCK(cycle_and_norm(s, o->cycle_kind, have_guess ? 1 : 0, st));
@@ -1809,6 +1835,7 @@ octmg_status lanes_cycle(octmg_state s, const std::vector<int> &running, int kin
     const long long key = graph_key(1, kind, 0, 0, s->n_launch);
     hipGraphExec_t exec = nullptr;
     STCK(graph_for(s, key, st, [&]() { return cycle_and_norm(s, kind, 1, st); }, &exec));
+    STCK(clean_norm_slots(s, st));
     HIPCK(hipGraphLaunch(exec, st));
     return OCTMG_OK;
 }

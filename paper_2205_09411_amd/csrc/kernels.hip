@@ -156,6 +156,11 @@ __device__ __forceinline__ int rhs_of(const LV<T> &L) {
     return L.lanes ? L.lanes[blockIdx.y] : (int)blockIdx.y;
 }
 
+// the norm slot of this workgroup for right-hand side rhs
+__device__ __forceinline__ unsigned long long *norm_slot(unsigned long long *out, int rhs) {
+    return out + ((long long)rhs * kNormSlots + blockIdx.x % kNormSlots) * kNormStride;
+}
+
 template <typename T>
 __device__ __forceinline__ bool inactive(const LV<T> &L) {
     return L.active && !L.active[rhs_of(L)];
@@ -604,7 +609,7 @@ __global__ __launch_bounds__((Blk<D, N>::THREADS)) void k_residual_max(LV<T> L, 
     if (threadIdx.x == 0) {
         for (int w = 1; w < (int)(B::THREADS + 63) / 64; w++) m = fmax(m, wmax[w]);
         if (m != m) m = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +Inf
-        atomicMax(out + rhs_of(L), (unsigned long long)__double_as_longlong(m));
+        atomicMax(norm_slot(out, rhs_of(L)), (unsigned long long)__double_as_longlong(m));
     }
 }
 
@@ -800,7 +805,7 @@ __global__ __launch_bounds__((Blk<D, N>::THREADS)) void k_defect(LV<double> L, L
     if (threadIdx.x == 0) {
         for (int w = 1; w < (int)(B::THREADS + 63) / 64; w++) m = fmax(m, wmax[w]);
         if (m != m) m = __longlong_as_double(0x7ff0000000000000ll);
-        atomicMax(out + rhs_of(L), (unsigned long long)__double_as_longlong(m));
+        atomicMax(norm_slot(out, rhs_of(L)), (unsigned long long)__double_as_longlong(m));
     }
 }
 
@@ -842,8 +847,19 @@ __global__ void k_fill_u64(unsigned long long *p, long long n, unsigned long lon
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         p[i] = v;
 }
-__global__ void k_copy_u64(const unsigned long long *s, unsigned long long *d, int n) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
+__global__ void k_norm_reduce(unsigned long long *slots, unsigned long long *norm, unsigned long long *mapped,
+                              int nrhs) {
+    for (int r = threadIdx.x; r < nrhs; r += blockDim.x) {
+        unsigned long long m = 0;
+        for (int k = 0; k < kNormSlots; k++) {
+            unsigned long long *p = slots + ((long long)r * kNormSlots + k) * kNormStride;
+            const unsigned long long v = *p;
+            m = v > m ? v : m;
+            *p = 0;
+        }
+        norm[r] = m;
+        mapped[r] = m;
+    }
 }
 __global__ void k_converge(const unsigned long long *norm, const double *thresh, int *active, double *hist, int c,
                            int nrhs) {
@@ -1453,13 +1469,14 @@ __global__ __launch_bounds__(256) void k_fas_rhs3(LV<T> L, LV<T> Lc, int do_rhs)
 
 // ------------------------------------------- colour-pair variants (3D)
 // Workgroups of 2 NTC threads in which wave group c = threadIdx.x / NTC owns
-// the cells of colour c (NTC = 256, or 512 for 16^3 blocks).  Each group stages its own colour, with the halos
-// seen by the other colour, into its own tile, so both tiles fill in one
-// round of loads; after the refinement-boundary ghosts each group applies L
-// to its colour from the other group's tile.  The arithmetic is that of the
-// two-pass kernels above, term by term, so the results are the same bits;
-// only the latency differs (one dependent load round instead of two), which
-// is what bounds the levels with few blocks.
+// the cells of colour c (NTC = 256; 512 in the FAS right-hand side of small
+// launches on 16^3 blocks).  Each group stages its own colour, with the
+// halos seen by the other colour, into its own tile, so both tiles fill in
+// one round of loads; after the refinement-boundary ghosts each group
+// applies L to its colour from the other group's tile.  The arithmetic is
+// that of the two-pass kernels above, term by term, so the results are the
+// same bits; only the latency differs (one dependent load round instead of
+// two).
 template <typename T, int N>
 struct PairTiles {
     static constexpr int SIZE = 2 * ColTile<N>::SIZE;
@@ -1467,11 +1484,14 @@ struct PairTiles {
 
 // L phi at this thread's HALF/NTC cells of colour c; `own` holds their
 // values (registers), `tiles` two ColTiles.  Every thread of the workgroup
-// calls it.
-template <typename T, int N, int NTC>
+// calls it.  RELOAD: own is read back from the thread's staged tile after
+// the barrier (the same values), so its registers are free while the halos
+// are in flight.
+template <typename T, int N, int NTC, bool RELOAD = false>
 __device__ __forceinline__ void pair_op(const LV<T> &L, const LV<T> &Lc, const T *phi, const T *phic, T *tiles,
-                                        int blk, const int *nbk, int4 P, const int *ri, const T *own, T *out) {
+                                        int blk, const int *nbk, int4 P, const int *ri, T *own, T *out) {
     constexpr bool V2 = cell_pairs<N>();
+    constexpr int PER = Blk<3, N>::HALF / NTC, NH = N / 2;
     const int c = threadIdx.x / NTC, t = threadIdx.x % NTC;
     T *mine = tiles + c * ColTile<N>::SIZE, *other = tiles + (1 - c) * ColTile<N>::SIZE;
     stage_colour<T, N, false, NTC, V2>(mine, L, phi, blk, nbk, P, c, t, own);
@@ -1481,15 +1501,29 @@ __device__ __forceinline__ void pair_op(const LV<T> &L, const LV<T> &Lc, const T
                                   P, c, t);
         __syncthreads();
     }
+    if (RELOAD) {
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            const int q = cell_of<NTC, V2>(t, m);
+            own[m] = mine[ColTile<N>::at(q / (NH * N), (q / NH) % N, q % NH)];
+        }
+    }
     tile_op<T, N, NTC, V2>(L, other, ri, c, own, out, t);
 }
 
-template <typename T, int N, int NC, int NTC>
-__global__ __launch_bounds__(2 * NTC) void k_restrict_fas3_pair(LV<T> L, LV<T> Lc, int into_old) {
+// LATE: g is loaded after the stencil, so its registers are not live across
+// the staging and three workgroups fit a CU (LDS and registers); pays where
+// a launch has many workgroups per CU, costs one dependent load where it
+// has few
+template <typename T, int N, int NC, int NTC, bool LATE>
+__global__ __launch_bounds__(2 * NTC) __attribute__((amdgpu_waves_per_eu(LATE ? 6 : 1))) void k_restrict_fas3_pair(
+    LV<T> L, LV<T> Lc, int into_old) {
     using B = Blk<3, N>;
     constexpr int PER = B::HALF / NTC, H = N / 2, NCELL = H * H * H;
+    static_assert(NCELL <= 2 * NTC, "one coarse cell per thread");
     constexpr bool V2 = cell_pairs<N>();
-    constexpr int SM = PairTiles<T, N>::SIZE > 2 * B::CPB ? PairTiles<T, N>::SIZE : 2 * B::CPB;
+    constexpr int NF = LATE ? 1 : 2;  // natural-order arrays held at once
+    constexpr int SM = PairTiles<T, N>::SIZE > NF * B::CPB ? PairTiles<T, N>::SIZE : NF * B::CPB;
     __shared__ T sm[SM];
     const int blk = block_of(L), rhs = rhs_of(L);
     const int c = threadIdx.x / NTC, t = threadIdx.x % NTC;
@@ -1507,44 +1541,54 @@ __global__ __launch_bounds__(2 * NTC) void k_restrict_fas3_pair(LV<T> L, LV<T> L
     T own[PER], r[PER], gv[PER];
     int ri[PER];
     load_cells<T, PER, NTC, V2>(phi + base, t, own);
-    load_cells<T, PER, NTC, V2>(g + base, t, gv);
+    if (!LATE) load_cells<T, PER, NTC, V2>(g + base, t, gv);
 #pragma unroll
     for (int m = 0; m < PER; m++) ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + cell_of<NTC, V2>(t, m)] : -1;
-    pair_op<T, N, NTC>(L, Lc, phi, phic, sm, blk, nbk, P, ri, own, r);
+    pair_op<T, N, NTC, LATE>(L, Lc, phi, phic, sm, blk, nbk, P, ri, own, r);
+    if (LATE) load_cells<T, PER, NTC, V2>(g + base, t, gv);
 #pragma unroll
     for (int m = 0; m < PER; m++) r[m] = gv[m] - r[m];
-    __syncthreads();  // the tiles become the natural-order arrays of r and phi
-    T *sr = sm, *sp = sm + B::CPB;
+    // the tiles become natural-order arrays of r and phi: both at once, or
+    // with LATE one after the other (one 32 KB array: three workgroups per
+    // CU fit the LDS)
+    const int cc = threadIdx.x, ci = cc % H, cj = (cc / H) % H, ck = cc / (H * H);
+    T sums[2];
 #pragma unroll
-    for (int m = 0; m < PER; m++) {
-        int i, j, k;
-        q_to_ijk<N>(c, cell_of<NTC, V2>(t, m), i, j, k);
-        sr[(k * N + j) * N + i] = r[m];
-        sp[(k * N + j) * N + i] = own[m];
+    for (int f0 = 0; f0 < 2; f0 += NF) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            int i, j, k;
+            q_to_ijk<N>(c, cell_of<NTC, V2>(t, m), i, j, k);
+#pragma unroll
+            for (int f = f0; f < f0 + NF; f++) sm[(f - f0) * B::CPB + (k * N + j) * N + i] = f == 0 ? r[m] : own[m];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int f = f0; f < f0 + NF; f++) {
+            T s = T(0);
+            if (cc < NCELL) {
+#pragma unroll
+                for (int ch = 0; ch < 8; ch++)
+                    s += sm[(f - f0) * B::CPB +
+                            ((2 * ck + ((ch >> 2) & 1)) * N + 2 * cj + ((ch >> 1) & 1)) * N + 2 * ci + (ch & 1)];
+            }
+            sums[f] = s;
+        }
     }
-    __syncthreads();
+    if (cc >= NCELL) return;
     T *oldw = Lc.old + (long long)rhs * Lc.fstride, *phiw = Lc.phi + (long long)rhs * Lc.fstride;
     T *gw = Lc.g + (long long)rhs * Lc.fstride;
     const int C0[3] = {P.x * H, P.y * H, P.z * H};
     const int pb = block_at<T, 3>(Lc, C0[0] / NC, C0[1] / NC, C0[2] / NC);
     if (pb < 0) return;  // excluded by construction: every block has a parent
     const T inv = T(0.125);
-    for (int cc = threadIdx.x; cc < NCELL; cc += 2 * NTC) {
-        const int ci = cc % H, cj = (cc / H) % H, ck = cc / (H * H);
-        T rs = T(0), ps = T(0);
-#pragma unroll
-        for (int ch = 0; ch < 8; ch++) {
-            const int e = ((2 * ck + ((ch >> 2) & 1)) * N + 2 * cj + ((ch >> 1) & 1)) * N + 2 * ci + (ch & 1);
-            rs += sr[e];
-            ps += sp[e];
-        }
-        const int gi = C0[0] + ci, gj = C0[1] + cj, gk = C0[2] + ck;
-        const long long o = (long long)pb * Blk<3, NC>::CPB + split_of<3, NC>(gi % NC, gj % NC, gk % NC);
-        const T pv = ps * inv;
-        oldw[o] = pv;
-        if (!into_old) phiw[o] = pv;
-        gw[o] = rs * inv;
-    }
+    const int gi = C0[0] + ci, gj = C0[1] + cj, gk = C0[2] + ck;
+    const long long o = (long long)pb * Blk<3, NC>::CPB + split_of<3, NC>(gi % NC, gj % NC, gk % NC);
+    const T pv = sums[1] * inv;
+    oldw[o] = pv;
+    if (!into_old) phiw[o] = pv;
+    gw[o] = sums[0] * inv;
 }
 
 template <typename T, int N, int NTC>
@@ -1658,8 +1702,10 @@ __global__ __launch_bounds__(2 * NTC) void k_fas_gs3_pair(LV<T> L, LV<T> Lc, int
     store_cells<T, PER, NTC, V2>(phi + base, t, nv);
 }
 
-template <typename T, int N, int NTC>
-__global__ __launch_bounds__(2 * NTC) void k_residual_max3_pair(LV<T> L, LV<T> Lc, unsigned long long *out) {
+// LATE as in the restriction
+template <typename T, int N, int NTC, bool LATE>
+__global__ __launch_bounds__(2 * NTC) __attribute__((amdgpu_waves_per_eu(LATE ? 6 : 1))) void k_residual_max3_pair(
+    LV<T> L, LV<T> Lc, unsigned long long *out) {
     using B = Blk<3, N>;
     constexpr int PER = B::HALF / NTC;
     constexpr bool V2 = cell_pairs<N>();
@@ -1682,10 +1728,11 @@ __global__ __launch_bounds__(2 * NTC) void k_residual_max3_pair(LV<T> L, LV<T> L
     T own[PER], lp[PER], gv[PER];
     int ri[PER];
     load_cells<T, PER, NTC, V2>(phi + base, t, own);
-    load_cells<T, PER, NTC, V2>(g + base, t, gv);
+    if (!LATE) load_cells<T, PER, NTC, V2>(g + base, t, gv);
 #pragma unroll
     for (int m = 0; m < PER; m++) ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + cell_of<NTC, V2>(t, m)] : -1;
-    pair_op<T, N, NTC>(L, Lc, phi, phic, tiles, blk, nbk, P, ri, own, lp);
+    pair_op<T, N, NTC, LATE>(L, Lc, phi, phic, tiles, blk, nbk, P, ri, own, lp);
+    if (LATE) load_cells<T, PER, NTC, V2>(g + base, t, gv);
     double mx = 0.0;
 #pragma unroll
     for (int m = 0; m < PER; m++) mx = fmax(mx, fabs((double)(gv[m] - lp[m])));
@@ -1695,7 +1742,7 @@ __global__ __launch_bounds__(2 * NTC) void k_residual_max3_pair(LV<T> L, LV<T> L
     if (threadIdx.x == 0) {
         for (int w = 1; w < 2 * NTC / 64; w++) mx = fmax(mx, wmax[w]);
         if (mx != mx) mx = __longlong_as_double(0x7ff0000000000000ll);
-        atomicMax(out + rhs, (unsigned long long)__double_as_longlong(mx));
+        atomicMax(norm_slot(out, rhs), (unsigned long long)__double_as_longlong(mx));
     }
 }
 
@@ -1752,7 +1799,7 @@ __global__ __launch_bounds__(256) void k_residual_max3(LV<T> L, LV<T> Lc, unsign
     if (threadIdx.x == 0) {
         for (int w = 1; w < 4; w++) mx = fmax(mx, wmax[w]);
         if (mx != mx) mx = __longlong_as_double(0x7ff0000000000000ll);
-        atomicMax(out + rhs, (unsigned long long)__double_as_longlong(mx));
+        atomicMax(norm_slot(out, rhs), (unsigned long long)__double_as_longlong(mx));
     }
 }
 
@@ -1870,7 +1917,7 @@ __global__ __launch_bounds__(256) void k_defect3(LV<double> L, LV<double> Lc, LV
     if (threadIdx.x == 0) {
         for (int w = 1; w < 4; w++) mx = fmax(mx, wmax[w]);
         if (mx != mx) mx = __longlong_as_double(0x7ff0000000000000ll);
-        atomicMax(out + rhs, (unsigned long long)__double_as_longlong(mx));
+        atomicMax(norm_slot(out, rhs), (unsigned long long)__double_as_longlong(mx));
     }
 }
 
@@ -2019,12 +2066,11 @@ __global__ __launch_bounds__(256) void k_small_vcycle(const SmallLevels<T> *__re
 }
 
 // threads per colour of the colour-pair FAS right-hand side: 512 on 16^3
-// blocks (measured 1.3-2.5 us faster per launch on every level at 256^3;
-// restriction and residual measured slower that way at the finest level)
-template <int N>
-constexpr int fas_ntc() {
-    return N == 16 ? 512 : 256;
-}
+// blocks when the launch has at most one workgroup per CU (measured 0.1-0.3
+// us faster per launch on the levels of 1-64 blocks at 256^3), else 256
+// (two workgroups then share a CU: 20.9 us against 22.9 us on 512 blocks;
+// restriction and residual measured slower with 512 at the finest level)
+constexpr long long kWideFasMax = 256;
 
 int grid_for(long long n) {
     long long g = (n + 255) / 256;
@@ -2034,6 +2080,10 @@ int grid_for(long long n) {
 }  // namespace
 
 // --------------------------------------------------------------- dispatch
+// launches with more workgroups than this load g after the stencil in the
+// residual and the restriction (two workgroups per CU on 256 CUs)
+constexpr long long kLateMin = 512;
+
 #define OCTMG_DN(D_, N_, CALL) \
     if (D == D_ && N == N_) { CALL; return hipGetLastError(); }
 
@@ -2065,9 +2115,11 @@ hipError_t launch_restrict_fas(int D, int N, int Nc, const LV<T> &L, const LV<T>
     dim3 grid(L.nblocks, nrhs);
 #define RF(D_, N_, NC_) OCTMG_DNC(D_, N_, NC_, hipLaunchKernelGGL((k_restrict_fas<T, D_, N_, NC_>), grid, dim3(256), 0, s, L, Lc, into_old))
     const bool pair = (long long)L.nblocks * nrhs <= L.pair_max;
+    const bool late = (long long)L.nblocks * nrhs > kLateMin;
 #define RF3(N_, NC_)                                                                                              \
     OCTMG_DNC(3, N_, NC_,                                                                                         \
-              if (pair) hipLaunchKernelGGL((k_restrict_fas3_pair<T, N_, NC_, 256>), grid, dim3(512), 0, s, L, Lc, into_old); \
+              if (pair && late) hipLaunchKernelGGL((k_restrict_fas3_pair<T, N_, NC_, 256, true>), grid, dim3(512), 0, s, L, Lc, into_old); \
+              else if (pair) hipLaunchKernelGGL((k_restrict_fas3_pair<T, N_, NC_, 256, false>), grid, dim3(512), 0, s, L, Lc, into_old); \
               else hipLaunchKernelGGL((k_restrict_fas3<T, N_, NC_>), grid, dim3(256), 0, s, L, Lc, into_old))
     RF3(16, 16) RF3(16, 8) RF3(8, 8) RF(2, 8, 8) RF(2, 16, 16) RF(2, 16, 8)
 #undef RF3
@@ -2111,8 +2163,13 @@ hipError_t launch_fas_rhs(int D, int N, const LV<T> &L, const LV<T> &Lc, int par
     dim3 grid(L.nblocks, nrhs);
 #define FR(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_fas_rhs<T, D_, N_>), grid, dim3(Blk<D_, N_>::THREADS), 0, s, L, Lc, parents_only))
     const bool pair = (long long)L.nblocks * nrhs <= L.pair_max;
+    const bool wide = (long long)L.nblocks * nrhs <= kWideFasMax;
+    if (D == 3 && N == 16 && pair && wide) {
+        hipLaunchKernelGGL((k_fas_rhs3_pair<T, 16, 512>), grid, dim3(1024), 0, s, L, Lc, parents_only);
+        return hipGetLastError();
+    }
 #define FR3(N_)                                                                                                 \
-    OCTMG_DN(3, N_, if (pair) hipLaunchKernelGGL((k_fas_rhs3_pair<T, N_, fas_ntc<N_>()>), grid, dim3(2 * fas_ntc<N_>()), 0, s, L, Lc, parents_only); \
+    OCTMG_DN(3, N_, if (pair) hipLaunchKernelGGL((k_fas_rhs3_pair<T, N_, 256>), grid, dim3(512), 0, s, L, Lc, parents_only); \
              else hipLaunchKernelGGL((k_fas_rhs3<T, N_>), grid, dim3(256), 0, s, L, Lc, parents_only))
     FR3(16) FR3(8) FR(2, 8) FR(2, 16)
 #undef FR3
@@ -2124,7 +2181,11 @@ template <typename T>
 hipError_t launch_fas_gs(int D, int N, const LV<T> &L, const LV<T> &Lc, int own_to_phi, int nrhs, hipStream_t s) {
     if (L.nblocks == 0) return hipSuccess;
     dim3 grid(L.nblocks, nrhs);
-#define FG3(N_) OCTMG_DN(3, N_, hipLaunchKernelGGL((k_fas_gs3_pair<T, N_, fas_ntc<N_>()>), grid, dim3(2 * fas_ntc<N_>()), 0, s, L, Lc, own_to_phi))
+    if (D == 3 && N == 16 && (long long)L.nblocks * nrhs <= kWideFasMax) {
+        hipLaunchKernelGGL((k_fas_gs3_pair<T, 16, 512>), grid, dim3(1024), 0, s, L, Lc, own_to_phi);
+        return hipGetLastError();
+    }
+#define FG3(N_) OCTMG_DN(3, N_, hipLaunchKernelGGL((k_fas_gs3_pair<T, N_, 256>), grid, dim3(512), 0, s, L, Lc, own_to_phi))
     FG3(16) FG3(8)
 #undef FG3
     return hipErrorInvalidValue;
@@ -2171,6 +2232,7 @@ hipError_t launch_residual_max(int D, int N, const LV<T> &L, const LV<T> &Lc, in
     if (L.nblocks == 0) return hipSuccess;
     dim3 grid(L.nblocks, nrhs);
     const bool pair = (long long)L.nblocks * nrhs <= L.pair_max;
+    const bool late = (long long)L.nblocks * nrhs > kLateMin;
 #define RM(D_, N_)                                                                                                  \
     if (D == D_ && N == N_) {                                                                                       \
         if (phi_zero) hipLaunchKernelGGL((k_residual_max<T, D_, N_, true>), grid, dim3(Blk<D_, N_>::THREADS), 0, s, L, Lc, out); \
@@ -2180,7 +2242,8 @@ hipError_t launch_residual_max(int D, int N, const LV<T> &L, const LV<T> &Lc, in
 #define RM3(N_)                                                                                                     \
     if (D == 3 && N == N_) {                                                                                        \
         if (phi_zero) hipLaunchKernelGGL((k_residual_max3<T, N_, true>), grid, dim3(256), 0, s, L, Lc, out);            \
-        else if (pair) hipLaunchKernelGGL((k_residual_max3_pair<T, N_, 256>), grid, dim3(512), 0, s, L, Lc, out);       \
+        else if (pair && late) hipLaunchKernelGGL((k_residual_max3_pair<T, N_, 256, true>), grid, dim3(512), 0, s, L, Lc, out); \
+        else if (pair) hipLaunchKernelGGL((k_residual_max3_pair<T, N_, 256, false>), grid, dim3(512), 0, s, L, Lc, out); \
         else hipLaunchKernelGGL((k_residual_max3<T, N_, false>), grid, dim3(256), 0, s, L, Lc, out);                    \
         return hipGetLastError();                                                                                   \
     }
@@ -2310,8 +2373,9 @@ hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long lon
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
-hipError_t launch_copy_u64(const unsigned long long *src, unsigned long long *dst, int n, hipStream_t s) {
-    hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(64), 0, s, src, dst, n);
+hipError_t launch_norm_reduce(unsigned long long *slots, unsigned long long *norm, unsigned long long *mapped,
+                              int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_norm_reduce, dim3(1), dim3(64), 0, s, slots, norm, mapped, nrhs);
     return hipGetLastError();
 }
 hipError_t launch_converge(const unsigned long long *norm, const double *thresh, int *active, double *hist, int c,

@@ -135,8 +135,19 @@ hipError_t launch_small_vcycle(const SmallLevels<T> *P, int top, int grid, hipSt
 // co-resident workgroups of k_small_vcycle on the current device
 template <typename T>
 hipError_t small_vcycle_max_grid(int *grid);
-// max |r| over the leaf blocks of a level into out[rhs] (bit pattern of a
-// non-negative double, combined with atomicMax); phi_zero: residual of 0.
+// Residual norms: every workgroup combines its max |r| (bit pattern of a
+// non-negative double; NaN as +Inf) with atomicMax into one of kNormSlots
+// slots of its rhs, kNormStride words apart (slot = workgroup index mod
+// kNormSlots), so that thousands of workgroups do not queue on one address;
+// launch_norm_reduce then takes the max over the slots.
+constexpr int kNormSlots = 16, kNormStride = 16;
+constexpr long long norm_slot_words(int nrhs) { return (long long)nrhs * kNormSlots * kNormStride; }
+// norm[r] = mapped[r] = max over the slots of rhs r, and the slots back to
+// zero for the next norm (one workgroup)
+hipError_t launch_norm_reduce(unsigned long long *slots, unsigned long long *norm, unsigned long long *mapped,
+                              int nrhs, hipStream_t s);
+// max |r| over the leaf blocks of a level into the norm slots `out`;
+// phi_zero: residual of 0.
 template <typename T>
 hipError_t launch_residual_max(int D, int N, const LV<T> &L, const LV<T> &Lc, int phi_zero,
                                unsigned long long *out, int nrhs, hipStream_t s);
@@ -148,7 +159,8 @@ hipError_t launch_gather_leaf(int D, int N, const LV<double> &L, const int *lb, 
 // whole-level canonical order <-> split layout (debug accessors)
 hipError_t launch_level_copy(int D, int N, double *split, double *canon, int nblocks, int to_split, hipStream_t s);
 // mixed precision: r64 = g - L phi on leaf blocks -> g32 = (float)r64,
-// phi32 = 0 there, max |r64| into out; and phi64 += phi32 on leaf blocks.
+// phi32 = 0 there, max |r64| into the norm slots `out`; and phi64 += phi32
+// on leaf blocks.
 hipError_t launch_defect(int D, int N, const LV<double> &L, const LV<double> &Lc, LV<float> L32, const int *lb,
                          int nlb, unsigned long long *out, int nrhs, hipStream_t s);
 hipError_t launch_update(int D, int N, const LV<double> &L, LV<float> L32, const int *lb, int nlb, int nrhs,
@@ -159,7 +171,6 @@ hipError_t launch_boundary_terms(int D, const int *meta, const double *cfull, in
 hipError_t launch_fill(double *p, long long n, double v, hipStream_t s);
 hipError_t launch_fillf(float *p, long long n, float v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long long v, hipStream_t s);
-hipError_t launch_copy_u64(const unsigned long long *src, unsigned long long *dst, int n, hipStream_t s);
 // device-side convergence test of cycle c: for every active rhs record its
 // norm in hist[c][rhs] and freeze it once the norm is <= thresh[rhs]
 hipError_t launch_converge(const unsigned long long *norm, const double *thresh, int *active, double *hist, int c,
