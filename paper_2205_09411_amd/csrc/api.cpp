@@ -298,9 +298,12 @@ struct Engine {
         return OCTMG_OK;
     }
     // FAS restriction il -> il-1, then g_c = L_c phi_c + r_c, old_c = phi_c
-    octmg_status restrict_fas(int il) {
+    // (done: the restriction itself has run, inside single_block_down)
+    octmg_status restrict_fas(int il, bool done = false) {
         const int adaptive = s->geom->tree.adaptive ? 1 : 0;
-        HIPCK(launch_restrict_fas<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), adaptive, s->n_launch, st));
+        if (!done)
+            HIPCK(launch_restrict_fas<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), adaptive, s->n_launch,
+                                         st));
         if (adaptive) HIPCK(launch_copy_parents<T>(D(), Nb(il - 1), lvT<T>(s, il - 1), s->n_launch, st));
         HIPCK(launch_fas_rhs<T>(D(), Nb(il - 1), lvT<T>(s, il - 1), lvT<T>(s, il - 2), 1, s->n_launch, st));
         return OCTMG_OK;
@@ -310,9 +313,11 @@ struct Engine {
     // forms from old.  On adaptive trees the restriction writes old only and
     // leaf blocks copy phi to old here; the parents' phi is set by that
     // half sweep (the coarse solve overwrites it).
-    octmg_status restrict_only(int il) {
+    octmg_status restrict_only(int il, bool done = false) {
         const int adaptive = s->geom->tree.adaptive ? 1 : 0;
-        HIPCK(launch_restrict_fas<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), adaptive, s->n_launch, st));
+        if (!done)
+            HIPCK(launch_restrict_fas<T>(D(), Nb(il), Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), adaptive, s->n_launch,
+                                         st));
         if (adaptive) HIPCK(launch_copy_parents<T>(D(), Nb(il - 1), lvT<T>(s, il - 1), s->n_launch, st, 1));
         return OCTMG_OK;
     }
@@ -322,6 +327,33 @@ struct Engine {
     bool fas_in_sweep(int lc, int ft) const {
         return D() == 3 && s->n_down >= 1 && lc > ft && lc >= 1 &&
                (long long)s->geom->L[lc].nblocks * s->n_launch <= s->pair_max_blocks;
+    }
+    // whether level il is one 16^3 block covering the domain, below the
+    // finest level (whose sweeps bench.py's profiling events time), with the
+    // colour-pair kernels enabled for its launches: then its steps of a
+    // V-cycle run in one workgroup per rhs (launch_single_block)
+    bool single_block(int il) const {
+        const GeomLevel &G = s->geom->L[il];
+        return D() == 3 && il >= 1 && il < (int)s->geom->L.size() - 1 && G.Nb == 16 && G.nb == 1 && G.nblocks == 1 &&
+               s->n_launch <= s->pair_max_blocks;
+    }
+    void count_updates(int il, int steps) {
+        Profile *P = s->prof;
+        if (P && P->on) P->updates += (double)steps * s->geom->L[il].nblocks * s->geom->L[il].cpb * s->n_launch;
+    }
+    // the down leg on such a level: [FAS rhs,] n_down sweeps and the
+    // restriction into il-1 (what smooth + launch_restrict_fas do)
+    octmg_status single_block_down(int il, bool fas) {
+        const int adaptive = s->geom->tree.adaptive ? 1 : 0;
+        HIPCK(launch_single_block<T>(Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), fas ? 1 : 0, 1, s->n_down, adaptive,
+                                     s->n_launch, st));
+        count_updates(il, s->n_down);
+        return OCTMG_OK;
+    }
+    octmg_status single_block_up(int il) {
+        HIPCK(launch_single_block<T>(Nb(il - 1), lvT<T>(s, il), lvT<T>(s, il - 1), 0, 0, s->n_up, 0, s->n_launch, st));
+        count_updates(il, s->n_up);
+        return OCTMG_OK;
     }
     octmg_status restrict_rhs(int il) {
         LV<T> c = lvT<T>(s, il - 1);
@@ -355,15 +387,16 @@ struct Engine {
         // the coarsest level's FAS right-hand side is formed inside the solve (3D)
         const bool fas_coarse = ft == 0 && D() == 3;
         for (int il = top; il > ft; il--) {
-            STCK(smooth(il, s->n_down, fas_pending));
+            const bool sb = single_block(il);
+            STCK(sb ? single_block_down(il, fas_pending) : smooth(il, s->n_down, fas_pending));
             fas_pending = fas_in_sweep(il - 1, ft);
-            STCK(fas_pending || (il == 1 && fas_coarse) ? restrict_only(il) : restrict_fas(il));
+            STCK(fas_pending || (il == 1 && fas_coarse) ? restrict_only(il, sb) : restrict_fas(il, sb));
         }
         if (ft >= 1) STCK(fused(ft));
         else STCK(coarse_solve(fas_coarse && top >= 1 ? 1 : 0));
         for (int il = std::max(ft, 0) + 1; il <= top; il++) {
             STCK(prolong(il, 0));
-            STCK(smooth(il, s->n_up));
+            STCK(single_block(il) ? single_block_up(il) : smooth(il, s->n_up));
         }
         return OCTMG_OK;
     }

@@ -1702,6 +1702,244 @@ __global__ __launch_bounds__(2 * NTC) void k_fas_gs3_pair(LV<T> L, LV<T> Lc, int
     store_cells<T, PER, NTC, V2>(phi + base, t, nv);
 }
 
+// ------------------------------------------- single-block level (3D)
+// A level made of one 16^3 block (the level above an 8^3 coarsest grid)
+// covers the domain: all six faces are domain faces, so its half sweeps need
+// no other workgroup's values.  One workgroup of 1024 threads keeps both
+// colours in LDS (a ColTile each, whose halos hold the ghosts seen by the
+// other colour) and runs the level's steps of a V-cycle behind workgroup
+// barriers instead of one launch each: on the way down the FAS right-hand
+// side from `old`, `steps` red-black sweeps, then the residual and the
+// restriction to the coarse grid; on the way up the sweeps alone.  Thread t
+// owns the cell pair 2t, 2t+1 of each colour; its g values, record rows and
+// boundary terms stay in registers.  The arithmetic is that of
+// k_fas_gs3_pair, k_gs_half3 and k_restrict_fas3_pair term by term (the same
+// bits).
+
+// ghosts in `dst` (a colour's tile) for the cells of colour u at the domain
+// faces, from their current values in `src` (colour u's tile): a zero-flux
+// face copies the cell, a Dirichlet face reflects it about the face value
+// (2 bv - value; bv = 0 without face data).  bv: [5][256] face values of the
+// reading colour (y-, y+, z-, z+, x entries)
+template <typename T>
+__device__ __forceinline__ void sb_ghosts(T *dst, const T *src, const T *bv, int u, int nm, int t) {
+    constexpr int N = 16, NH = 8;
+    using CT = ColTile<N>;
+    if (t < N * NH) {
+        const int fh = t % NH, fr = t / NH;
+        T a = src[CT::at(fr, 0, fh)];
+        dst[CT::at(fr, -1, fh)] = zero_flux(nm, 1, -1) ? a : T(2) * bv[t] - a;
+        a = src[CT::at(fr, N - 1, fh)];
+        dst[CT::at(fr, N, fh)] = zero_flux(nm, 1, 1) ? a : T(2) * bv[256 + t] - a;
+        a = src[CT::at(0, fr, fh)];
+        dst[CT::at(-1, fr, fh)] = zero_flux(nm, 2, -1) ? a : T(2) * bv[512 + t] - a;
+        a = src[CT::at(N - 1, fr, fh)];
+        dst[CT::at(N, fr, fh)] = zero_flux(nm, 2, 1) ? a : T(2) * bv[768 + t] - a;
+    }
+    if (t < N * N) {
+        const int xj = t % N, xk = t / N, xp = (u + xj + xk) & 1;
+        const T a = src[CT::at(xk, xj, xp ? NH - 1 : 0)];
+        dst[CT::at(xk, xj, xp ? NH : -1)] = zero_flux(nm, 0, xp ? 1 : -1) ? a : T(2) * bv[1024 + t] - a;
+    }
+}
+
+template <typename T, bool FAS, bool RESTRICT, int NC>
+__global__ __launch_bounds__(1024) void k_single_block3(LV<T> L, LV<T> Lc, int steps, int into_old) {
+    constexpr int N = 16, NH = 8, NT = 1024, H = N / 2;
+    using B = Blk<3, N>;
+    using CT = ColTile<N>;
+    constexpr int PER = B::HALF / NT;
+    constexpr int TS = 2 * CT::SIZE, NAT = RESTRICT ? 2 * B::CPB : 0;
+    __shared__ T sm[TS > NAT ? TS : NAT];
+    __shared__ T sbv[2 * 5 * 256];
+    T *tile[2] = {sm, sm + CT::SIZE};
+    const int rhs = rhs_of(L), t = threadIdx.x;
+    const int leaf = L.leaf[0];
+    const int4 P = L.pos[0];
+    const int mo = L.map_off ? L.map_off[0] : -1;
+    const int act = L.active ? L.active[rhs] : 1;
+    int nbk[6] = {-2, -2, -2, -2, -2, -2};
+    tables_loaded(act, leaf, P, nbk, mo);
+    if (!act) return;
+    const bool fas = FAS && !leaf;
+    T *phi = L.phi + (long long)rhs * L.fstride;
+    T *g = L.g + (long long)rhs * L.fstride;
+    const T *src = FAS ? L.old + (long long)rhs * L.fstride : phi;
+    T val[2][PER], gv[2][PER], rc[2][PER][8], bt[2][PER];
+    int ri[2][PER];
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        load_cells<T, PER, NT, true>(src + c * B::HALF, t, val[c]);
+        load_cells<T, PER, NT, true>(g + c * B::HALF, t, gv[c]);
+#pragma unroll
+        for (int m = 0; m < PER; m++) ri[c][m] = mo >= 0 ? L.map[mo + c * B::HALF + cell_of<NT, true>(t, m)] : -1;
+    }
+    // face values of the Dirichlet ghosts, per reading colour u (the cell
+    // indices of stage_colour's face entries)
+    if (t < N * N) {
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            T *bvu = sbv + u * 5 * 256;
+            auto face = [&](int d, int i, int j, int k) -> T {
+                const int ax = d >> 1, sd = (d & 1) ? 1 : -1;
+                return !zero_flux(L.neumann, ax, sd) && L.bcv
+                           ? L.bcv[face_slot<3>(ax, sd, P.x * N + i, P.y * N + j, P.z * N + k, L.n, L.nface)]
+                           : T(0);
+            };
+            if (t < N * NH) {
+                const int fh = t % NH, fr = t / NH;
+                bvu[t] = face(2, 2 * fh + ((u + fr) & 1), 0, fr);
+                bvu[256 + t] = face(3, 2 * fh + ((u + N - 1 + fr) & 1), N - 1, fr);
+                bvu[512 + t] = face(4, 2 * fh + ((u + fr) & 1), fr, 0);
+                bvu[768 + t] = face(5, 2 * fh + ((u + fr + N - 1) & 1), fr, N - 1);
+            }
+            const int xj = t % N, xk = t / N, xp = (u + xj + xk) & 1;
+            bvu[1024 + t] = face(xp, xp ? N - 1 : 0, xj, xk);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+#pragma unroll
+            for (int d = 0; d < 8; d++) rc[c][m][d] = T(0);
+            bt[c][m] = T(0);
+            if (ri[c][m] >= 0) {
+                const T *r = L.rec + 8 * (long long)ri[c][m];
+#pragma unroll
+                for (int d = 0; d < 8; d++) rc[c][m][d] = r[d];
+                if (L.b) bt[c][m] = L.b[ri[c][m]];
+            }
+        }
+#pragma unroll
+    for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            const int q = cell_of<NT, true>(t, m);
+            tile[c][CT::at(q / (NH * N), (q / NH) % N, q % NH)] = val[c][m];
+        }
+    __syncthreads();
+    sb_ghosts<T>(tile[1], tile[0], sbv, 0, L.neumann, t);
+    sb_ghosts<T>(tile[0], tile[1], sbv + 5 * 256, 1, L.neumann, t);
+    __syncthreads();
+    // L phi at the thread's cells of colour c (tile_op's arithmetic)
+    auto apply_op = [&](int c, T *out) {
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            const int q = cell_of<NT, true>(t, m);
+            int i, j, k;
+            T v[6];
+            tile_neighbours<T, N>(tile[1 - c], c, q, i, j, k, v);
+            const T own = tile[c][CT::at(k, j, q % NH)];
+            if (ri[c][m] < 0) {
+                out[m] = L.inv_dx2 * ((((v[0] + v[1]) + (v[2] + v[3])) + (v[4] + v[5])) - T(6) * own);
+            } else {
+                T s = T(0);
+#pragma unroll
+                for (int d = 0; d < 6; d++) s += rc[c][m][d] * v[d];
+                out[m] = s + rc[c][m][6] * own + bt[c][m];
+            }
+        }
+    };
+    if (fas) {
+        // FAS right-hand side g = L old + g (the restricted residual)
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            T lp[PER];
+            apply_op(c, lp);
+#pragma unroll
+            for (int m = 0; m < PER; m++) gv[c][m] = lp[m] + gv[c][m];
+            store_cells<T, PER, NT, true>(g + c * B::HALF, t, gv[c]);
+        }
+        __syncthreads();  // the first half sweep writes the tile read here
+    }
+    const T inv6 = T(1) / T(6);
+    for (int st = 0; st < steps; st++) {
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            // half sweep of colour u (gs_half3_body's arithmetic), and the
+            // ghosts the other colour will read, from colour 1-u, which this
+            // half sweep does not change
+#pragma unroll
+            for (int m = 0; m < PER; m++) {
+                const int q = cell_of<NT, true>(t, m);
+                int i, j, k;
+                T v[6];
+                tile_neighbours<T, N>(tile[1 - u], u, q, i, j, k, v);
+                T nv;
+                if (ri[u][m] < 0) {
+                    nv = (((v[0] + v[1]) + (v[2] + v[3])) + (v[4] + v[5]) - L.dx2 * gv[u][m]) * inv6;
+                } else {
+                    T s = T(0);
+#pragma unroll
+                    for (int d = 0; d < 6; d++) s += rc[u][m][d] * v[d];
+                    nv = (gv[u][m] - bt[u][m] - s) * rc[u][m][7];
+                }
+                tile[u][CT::at(k, j, q % NH)] = nv;
+            }
+            sb_ghosts<T>(tile[u], tile[1 - u], sbv + (1 - u) * 5 * 256, 1 - u, L.neumann, t);
+            __syncthreads();
+        }
+    }
+    T own[2][PER];
+#pragma unroll
+    for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            const int q = cell_of<NT, true>(t, m);
+            own[c][m] = tile[c][CT::at(q / (NH * N), (q / NH) % N, q % NH)];
+        }
+    if (FAS || steps > 0)
+#pragma unroll
+        for (int c = 0; c < 2; c++) store_cells<T, PER, NT, true>(phi + c * B::HALF, t, own[c]);
+    if (!RESTRICT) return;
+    // residual g - L phi from the final iterate: the ghosts of colour 0's
+    // tile still hold colour 1's values from before its last half sweep
+    if (steps > 0) {
+        sb_ghosts<T>(tile[0], tile[1], sbv + 5 * 256, 1, L.neumann, t);
+        __syncthreads();
+    }
+    T r[2][PER];
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        apply_op(c, r[c]);
+#pragma unroll
+        for (int m = 0; m < PER; m++) r[c][m] = gv[c][m] - r[c][m];
+    }
+    __syncthreads();  // the tiles become the natural-order arrays of r and phi
+    T *sr = sm, *sp = sm + B::CPB;
+#pragma unroll
+    for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            int i, j, k;
+            q_to_ijk<N>(c, cell_of<NT, true>(t, m), i, j, k);
+            sr[(k * N + j) * N + i] = r[c][m];
+            sp[(k * N + j) * N + i] = own[c][m];
+        }
+    __syncthreads();
+    if (t >= H * H * H) return;
+    const int ci = t % H, cj = (t / H) % H, ck = t / (H * H);
+    T rs = T(0), ps = T(0);
+#pragma unroll
+    for (int ch = 0; ch < 8; ch++) {
+        const int e = ((2 * ck + ((ch >> 2) & 1)) * N + 2 * cj + ((ch >> 1) & 1)) * N + 2 * ci + (ch & 1);
+        rs += sr[e];
+        ps += sp[e];
+    }
+    const int C0[3] = {P.x * H, P.y * H, P.z * H};
+    const int pb = block_at<T, 3>(Lc, C0[0] / NC, C0[1] / NC, C0[2] / NC);
+    if (pb < 0) return;  // excluded by construction: every block has a parent
+    const T inv = T(0.125);
+    const int gi = C0[0] + ci, gj = C0[1] + cj, gk = C0[2] + ck;
+    const long long o = (long long)rhs * Lc.fstride + (long long)pb * Blk<3, NC>::CPB +
+                        split_of<3, NC>(gi % NC, gj % NC, gk % NC);
+    const T pv = ps * inv;
+    Lc.old[o] = pv;
+    if (!into_old) Lc.phi[o] = pv;
+    Lc.g[o] = rs * inv;
+}
+
 // LATE as in the restriction
 template <typename T, int N, int NTC, bool LATE>
 __global__ __launch_bounds__(2 * NTC) __attribute__((amdgpu_waves_per_eu(LATE ? 6 : 1))) void k_residual_max3_pair(
@@ -2128,6 +2366,26 @@ hipError_t launch_restrict_fas(int D, int N, int Nc, const LV<T> &L, const LV<T>
 }
 
 template <typename T>
+hipError_t launch_single_block(int Nc, const LV<T> &L, const LV<T> &Lc, int fas, int restrict_to, int steps, int into_old,
+                               int nrhs, hipStream_t s) {
+    if (L.nblocks != 1 || L.nb != 1 || L.n != 16 || steps < 0) return hipErrorInvalidValue;
+    dim3 grid(1, nrhs);
+    if (!restrict_to) {
+        if (fas) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_single_block3<T, false, false, 8>), grid, dim3(1024), 0, s, L, Lc, steps, into_old);
+        return hipGetLastError();
+    }
+#define SB(F_, NC_)                                                                                              \
+    if (!!fas == F_ && Nc == NC_) {                                                                              \
+        hipLaunchKernelGGL((k_single_block3<T, F_, true, NC_>), grid, dim3(1024), 0, s, L, Lc, steps, into_old); \
+        return hipGetLastError();                                                                                \
+    }
+    SB(true, 8) SB(false, 8) SB(true, 16) SB(false, 16)
+#undef SB
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
 hipError_t launch_copy_parents(int D, int N, const LV<T> &L, int nrhs, hipStream_t s, int leaves_only) {
     if (L.nblocks == 0) return hipSuccess;
     dim3 grid(L.nblocks, nrhs);
@@ -2402,6 +2660,7 @@ hipError_t launch_check_finite(const double *p, long long n, int *flag, hipStrea
     template hipError_t launch_restrict_phi<T>(int, int, int, const LV<T> &, const LV<T> &, int, hipStream_t);      \
     template hipError_t launch_fas_rhs<T>(int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t);           \
     template hipError_t launch_fas_gs<T>(int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t);             \
+    template hipError_t launch_single_block<T>(int, const LV<T> &, const LV<T> &, int, int, int, int, int, hipStream_t); \
     template hipError_t launch_prolong<T>(int, int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t);      \
     template hipError_t launch_coarse_solve<T>(int, const LV<T> &, const double *, const double *, int, int, hipStream_t); \
     template hipError_t launch_residual_max<T>(int, int, const LV<T> &, const LV<T> &, int, unsigned long long *, int, hipStream_t);

@@ -93,6 +93,14 @@ hipError_t launch_gs_half(int D, int N, const LV<T> &L, const LV<T> &Lc, int col
 template <typename T>
 hipError_t launch_restrict_fas(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int into_old, int nrhs,
                                hipStream_t s);
+// A level of one 16^3 block covering the domain, in one workgroup per rhs:
+// with restrict_to, [fas: the FAS right-hand side from old, which is also
+// the starting iterate,] `steps` red-black sweeps, then the residual
+// restricted into Lc (block edge Nc; into_old as in launch_restrict_fas);
+// without, `steps` sweeps.  Same results as the separate launches.
+template <typename T>
+hipError_t launch_single_block(int Nc, const LV<T> &L, const LV<T> &Lc, int fas, int restrict_to, int steps, int into_old,
+                               int nrhs, hipStream_t s);
 template <typename T>
 // leaves_only: only the leaf blocks' old <- phi (the parents' phi <- old is
 // then left to launch_fas_gs with own_to_phi)
