@@ -127,8 +127,11 @@ typedef struct octmg_state_s *octmg_state;
  *     running right-hand sides) use 512 threads per block: restriction,
  *     FAS right-hand side and residual stage the two colours at the same
  *     time, prolongation and (16^3 blocks) the smoother give each thread
- *     half the cells.  Larger launches use 256 threads.  0: never.
- *     Default 1 << 30 (every launch). */
+ *     half the cells.  Larger launches use 256 threads.  When the running
+ *     right-hand sides number at most pair_max_blocks, a level made of one
+ *     16^3 block below the finest level also runs its steps of a V-cycle in
+ *     one 1024-thread workgroup per rhs (one launch per leg).  0: never.
+ *     Every value gives the same iterates.  Default 1 << 30 (every launch). */
 typedef struct octmg_launch_config {
     int block_order, bottom_kind, bottom_max_blocks, graph_mode, pair_max_blocks;
 } octmg_launch_config;
