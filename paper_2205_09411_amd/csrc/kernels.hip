@@ -6,7 +6,8 @@
 // (read), this colour's g (read) and this colour's phi (written).  Ghost
 // values are never stored; they are formed where a neighbour is read:
 //   same level      -> the neighbour block's cell (level lookup table)
-//   domain face     -> 2 phi_b(face centre) - phi_inside (Dirichlet)
+//   domain face     -> 2 phi_b(face centre) - phi_inside (Dirichlet), or
+//                      phi_inside (zero flux)
 //   refinement edge -> 1/2 C_k + 3/4 f1 - 1/4 f2, C_k = C + sum_t s_t
 //                      (C_t+ - C_t-)/8 from the next coarser level, which
 //                      makes the coarse flux equal the averaged fine flux.
@@ -968,33 +969,43 @@ __device__ __forceinline__ bool any_coarser(const int *nbk) {
 // the other-colour tile across that face; the slot receives the refinement
 // boundary interpolation seen by that cell.  Runs after staging (it reads
 // the inward neighbour from the tile); domain faces are filled while
-// staging.
-template <typename T, int N>
+// staging.  The NT calling threads take N*N/2 entries of a face each, so
+// that the coarser faces of a block (up to NT/(N*N/2) at a time) are filled
+// side by side, each a chain of two dependent loads (level table, value).
+template <typename T, int N, int NT = 256>
 __device__ void coarser_face_ghosts(T *tile, const LV<T> &Lc, const T *__restrict__ own_col, const T *phic,
                                     const int *nbk, int4 P, int col, int t) {
     using CT = ColTile<N>;
-    constexpr int NH = N / 2;
-    if (t >= N * NH) return;
+    constexpr int NH = N / 2, FE = N * NH, FPP = NT / FE > 0 ? NT / FE : 1;
+    int mask = 0;
+#pragma unroll
+    for (int d = 0; d < 6; d++) mask |= (nbk[d] == -1 ? 1 : 0) << d;
+    const int ncf = __popc(mask), slotf = t / FE, e = t % FE;
+    if (slotf >= FPP) return;
 #pragma unroll 1
-    for (int d = 0; d < 6; d++) {
-        if (nbk[d] != -1) continue;
+    for (int f0 = 0; f0 < ncf; f0 += FPP) {
+        const int fi = f0 + slotf;
+        if (fi >= ncf) break;
+        int m = mask;  // face d: the fi-th coarser face
+        for (int r = 0; r < fi; r++) m &= m - 1;
+        const int d = __ffs(m) - 1;
         const int ax = d >> 1, s = (d & 1) ? 1 : -1;
         int i, j, k, slot;
         if (ax == 0) {
             const int want = s < 0 ? 0 : 1;  // parity (col+j+k)&1 of rows whose cell touches the face
-            k = t / NH;
-            j = 2 * (t % NH) + ((col + k + want) & 1);
+            k = e / NH;
+            j = 2 * (e % NH) + ((col + k + want) & 1);
             i = s < 0 ? 0 : N - 1;
             slot = CT::at(k, j, s < 0 ? -1 : NH);
         } else if (ax == 1) {
-            k = t / NH;
-            const int h = t % NH;
+            k = e / NH;
+            const int h = e % NH;
             j = s < 0 ? 0 : N - 1;
             i = 2 * h + ((col + j + k) & 1);
             slot = CT::at(k, s < 0 ? -1 : N, h);
         } else {
-            j = t / NH;
-            const int h = t % NH;
+            j = e / NH;
+            const int h = e % NH;
             k = s < 0 ? 0 : N - 1;
             i = 2 * h + ((col + j + k) & 1);
             slot = CT::at(s < 0 ? -1 : N, j, h);
@@ -1215,7 +1226,7 @@ __device__ __forceinline__ void gs_half3_body(const LV<T> &L, const LV<T> &Lc, i
     T *__restrict__ dst = phi + base + color * B::HALF;
     if (any_coarser(nbk)) {
         const T *phic = Lc.phi ? Lc.phi + (long long)rhs * Lc.fstride : nullptr;
-        coarser_face_ghosts<T, N>(tile, Lc, dst, phic, nbk, P, color, threadIdx.x);
+        coarser_face_ghosts<T, N, NT>(tile, Lc, dst, phic, nbk, P, color, threadIdx.x);
         __syncthreads();
     }
     const T inv6 = T(1) / T(6);
@@ -1497,8 +1508,8 @@ __device__ __forceinline__ void pair_op(const LV<T> &L, const LV<T> &Lc, const T
     stage_colour<T, N, false, NTC, V2>(mine, L, phi, blk, nbk, P, c, t, own);
     __syncthreads();
     if (any_coarser(nbk)) {
-        coarser_face_ghosts<T, N>(other, Lc, phi + (long long)blk * Blk<3, N>::CPB + c * Blk<3, N>::HALF, phic, nbk,
-                                  P, c, t);
+        coarser_face_ghosts<T, N, NTC>(other, Lc, phi + (long long)blk * Blk<3, N>::CPB + c * Blk<3, N>::HALF, phic,
+                                       nbk, P, c, t);
         __syncthreads();
     }
     if (RELOAD) {
