@@ -35,6 +35,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 PMC_RECORD = os.path.join(ROOT, "profiles", "gs_half3_mms3d_256_pmc.json")
 
 
+def achievable_copy_gbs(torch, stream, mib=256, reps=5):
+    """Best rate of a plain 256 MiB device-to-device copy on this GPU (bytes
+    read + written per second, GB/s): the bandwidth an HBM-bound kernel can
+    reach in practice, beside the 8 TB/s peak."""
+    x = torch.ones(mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    best = float("inf")
+    with torch.cuda.stream(stream):
+        for _ in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            y.copy_(x)
+            b.record(stream)
+            b.synchronize()
+            best = min(best, a.elapsed_time(b))
+    return 2 * x.numel() * 8 / (best * 1e-3) / 1e9
+
+
 def measured_traffic():
     """HBM bytes per launch of the finest-level sweep from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE runs, if they were taken on the current
@@ -568,13 +586,19 @@ def main():
     S.profile(False)
     # timed region: whole solves in the tuned configuration
     torch.cuda.synchronize()
+    # per-solve HIP events on the solve's stream (they add no synchronisation)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
     reps = []
-    for _ in range(args.steps):
+    ev[0].record(stream)
+    for k in range(args.steps):
         reps.append(S.solve(rtol=args.rtol, max_cycles=40, zero_start=True, stream=stream, graph_mode=gm))
+        ev[k + 1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dt = t1 - t0
+    solve_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
+    copy_gbs = achievable_copy_gbs(torch, stream)
     phi = S.get_solution()
     err = float(np.abs(phi - exact).max())
     cycles = reps[-1].cycles
@@ -609,8 +633,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "k_gs_half3<double,16> (finest level)",
-                     "bytes_per_launch": bytes_per_launch, "mean_launch_ms": round(mean_ms, 5)},
+                     "bytes_per_launch": bytes_per_launch, "mean_launch_ms": round(mean_ms, 5),
+                     "achievable_copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "solves_per_s": round(args.steps / dt, 3),
+        "solve_ms_p10_p50_p90": [round(float(np.percentile(solve_ms, q)), 3) for q in (10, 50, 90)],
         "launch": {"chosen": tuned, "autotune_ms_per_solve": [round(v, 3) for v in cand_ms]},
         "cycles_per_solve": int(np.mean([r.cycles for r in reps])),
         "final_rel_residual": max(r.r_final / r.r0 for r in reps),
