@@ -1329,7 +1329,6 @@ template <typename T, int N, int NC>
 __device__ __forceinline__ void restrict_fas3_body(const LV<T> &L, const LV<T> &Lc, int into_old, int blk, int rhs, T *sm) {
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER, H = N / 2, NCELL = H * H * H, CPER = (NCELL + 255) / 256;
-    constexpr int SM = ColTile<N>::SIZE > B::CPB ? ColTile<N>::SIZE : B::CPB;
     const int4 P = L.pos[blk];
     int nbk[6];
     face_ids<T, N>(L, blk, nbk);
@@ -1418,7 +1417,6 @@ __device__ __forceinline__ void restrict_fas3_body(const LV<T> &L, const LV<T> &
 template <typename T, int N, int NC>
 __global__ __launch_bounds__(256) void k_restrict_fas3(LV<T> L, LV<T> Lc, int into_old) {
     using B = Blk<3, N>;
-    constexpr int PER = Per<N>::PER, H = N / 2, NCELL = H * H * H, CPER = (NCELL + 255) / 256;
     constexpr int SM = ColTile<N>::SIZE > B::CPB ? ColTile<N>::SIZE : B::CPB;
     __shared__ T sm[SM];
     restrict_fas3_body<T, N, NC>(L, Lc, into_old, block_of(L), rhs_of(L), sm);
@@ -1472,8 +1470,6 @@ __device__ __forceinline__ void fas_rhs3_body(const LV<T> &L, const LV<T> &Lc, i
 
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_fas_rhs3(LV<T> L, LV<T> Lc, int do_rhs) {
-    using B = Blk<3, N>;
-    constexpr int PER = Per<N>::PER;
     __shared__ T tile[ColTile<N>::SIZE];
     fas_rhs3_body<T, N>(L, Lc, do_rhs, block_of(L), rhs_of(L), tile);
 }
