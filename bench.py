@@ -17,7 +17,7 @@ HBM.  Printed as one JSON line:
   roofline   the dominant kernel (finest-level red-black half sweep):
              algorithmic bytes per launch / its mean duration from HIP
              events recorded on the solve's stream, against 8 TB/s
-  cpu_baseline  the FP64 CPU checker timed on the host cores over a bounded
+  cpu_baseline  the FP64 CPU oracle timed on the host cores over a bounded
              sample (a few V-cycles of the same problem)
 """
 from __future__ import annotations

@@ -1,4 +1,4 @@
-"""FP64 CPU checker for the octree multigrid solver -- TEST INFRASTRUCTURE.
+"""FP64 CPU oracle for the octree multigrid solver -- TEST INFRASTRUCTURE.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The library never does, and this
@@ -23,7 +23,7 @@ _LIB = os.path.join(_HERE, "liboctmg_oracle.so")
 
 
 def build(force: bool = True) -> str:
-    """Compile the checker with gcc (no FMA contraction, OpenMP for timing)."""
+    """Compile the oracle with gcc (no FMA contraction, OpenMP for timing)."""
     if force or not os.path.exists(_LIB):
         cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
                "-o", _LIB + ".tmp", _SRC, "-lm"]
@@ -127,7 +127,7 @@ def make_desc(geom, n_down: int = 2, n_up: int = 2):
 
 
 class Oracle:
-    """One octree problem (tree, stencils, fields) held by the C checker."""
+    """One octree problem (tree, stencils, fields) held by the C oracle."""
 
     FIELD_PHI, FIELD_G, FIELD_OLD, FIELD_R = 0, 1, 2, 3
 
@@ -323,7 +323,7 @@ def line_search(geom, a, b):
 
 
 def cbrt(a: float) -> float:
-    """The checker's cube root (+ - * / only), as used by the sharp shapes."""
+    """The oracle's cube root (+ - * / only), as used by the sharp shapes."""
     return lib().orc_cbrt(float(a))
 
 

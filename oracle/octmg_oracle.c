@@ -1,5 +1,5 @@
 /*
- * octmg_oracle.c -- FP64 CPU checker for the octree multigrid solver.
+ * octmg_oracle.c -- FP64 CPU oracle for the octree multigrid solver.
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
  * reference against which the HIP library is checked.  Only the tests, the

@@ -1,5 +1,5 @@
 """Seeded synthetic workloads: geometry descriptions, right-hand sides and
-boundary data for the multigrid solver and for its FP64 CPU checker.
+boundary data for the multigrid solver and for its FP64 CPU oracle.
 
 This module holds inputs only.  It contains none of the solver's arithmetic
 (no stencils, no line search, no transfers): it turns seeds and closed-form
@@ -28,7 +28,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-# level-set kinds understood by both the library and the checker
+# level-set kinds understood by both the library and the oracle
 LSF_NONE = 0
 LSF_SPHERES = 1      # union of spheres/circles: params [cx, cy, cz, r] * n
 LSF_CYLINDER_Z = 2   # infinite cylinder along z: params [cx, cy, r]

@@ -1,6 +1,6 @@
 """Host-side checks of the C ABI (no GPU): the shared library loads and
 exports every entry point declared in include/octmg.h, the host tree
-planner builds the same tree as the checker (uniform and adaptive, 2:1
+planner builds the same tree as the oracle (uniform and adaptive, 2:1
 balance), and invalid descriptors are rejected with OCTMG_ERR_INVALID."""
 import ctypes
 import os
@@ -38,7 +38,7 @@ GEOMS = {
     "spheres_amr16": lambda: W.spheres(n_spheres=20, max_level=5, block_n=16).geom,
     "cylinder": lambda: W.cylinder(max_level=3).geom,
     # sharp shapes refined near the interface: the host refinement predicate
-    # evaluates the shape (with its + - * / cube root) like the checker
+    # evaluates the shape (with its + - * / cube root) like the oracle
     "heart_amr2d": lambda: W.Geometry(dim=2, block_n=8, max_level=5, lsf_kind=W.LSF_HEART,
                                       lsf_params=np.array([0.5, 0.5, 0.5, 4.0]), refine_kind=W.REFINE_NEAR_INTERFACE,
                                       refine_width=2.0 + np.sqrt(3) / 2, w_min=4e-3),
@@ -50,7 +50,7 @@ GEOMS = {
 
 
 @pytest.mark.parametrize("name", sorted(GEOMS))
-def test_host_tree_matches_checker(orc, name):
+def test_host_tree_matches_oracle(orc, name):
     geom = GEOMS[name]()
     plan = octmg.plan_levels(geom)
     o = orc.Oracle(geom)

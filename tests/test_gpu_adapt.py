@@ -1,7 +1,7 @@
 """Mesh adaptation: refining and coarsening a geometry's leaf blocks gives a
 tree and stencil records identical, bit for bit, to a setup from scratch of
 the same tree, while unchanged blocks keep their records; the adapted
-geometry solves in parity with the checker; phi carries over."""
+geometry solves in parity with the oracle; phi carries over."""
 import numpy as np
 import pytest
 
@@ -89,7 +89,7 @@ def test_refine_then_coarsen_equals_setup_from_scratch(orc, dim):
     Gc, st_c = adapt_towards(Gr, tree_of(narrow))
     assert len(st_c) >= 1
     same_geometry(Gc, octmg.Geometry(narrow))
-    # the adapted geometry solves in parity with the checker's own setup of it
+    # the adapted geometry solves in parity with the oracle's own setup of it
     w = W.Workload(wide, lambda x: np.sin(5 * x[:, 0]) * x[:, 1], lambda x: 1.0 + x[:, 0],
                    lambda x: x[:, 1] * x[:, 1])
     o = orc.setup_workload(w)

@@ -1,4 +1,4 @@
-"""Parity of the HIP path (through the C ABI) with the FP64 CPU checker.
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
 * setup: leaf centres, interface points x0 and relative distances d are
   bitwise equal; stencil coefficients agree to 1e-15 relative;
@@ -142,9 +142,9 @@ def test_vcycle_parity_from_zero(orc):
 
 
 def test_solve_fp64_and_mixed(orc):
-    """FP64 solve to 1e-10 matches the checker iterate for iterate (same number
+    """FP64 solve to 1e-10 matches the oracle iterate for iterate (same number
     of cycles); the mixed-precision solve reaches the same relative residual
-    and its error against the FP64 checker is reported."""
+    and its error against the FP64 oracle is reported."""
     w = CONFIGS["mms3d_b16_64"]()
     o, G, S = make_pair(orc, w)
     rep = S.solve(rtol=1e-10, max_cycles=40)
@@ -160,7 +160,7 @@ def test_solve_fp64_and_mixed(orc):
     conv = o.get_solution()
     err_m = rel(Sm.get_solution(), conv)
     err_d = rel(S.get_solution(), conv)
-    print(f"FP64 cycles {rep.cycles} err {err_d:.2e}; mixed cycles {repm.cycles} err {err_m:.2e} (vs converged FP64 checker)")
+    print(f"FP64 cycles {rep.cycles} err {err_d:.2e}; mixed cycles {repm.cycles} err {err_m:.2e} (vs converged FP64 oracle)")
     assert err_m < 10 * err_d + 1e-9
     xyz, _ = o.leaf_coords()
     ex = w.exact(xyz)
@@ -256,10 +256,10 @@ def test_fused_bottom_equals_separate_launches(name):
 def test_full_size_adaptive_spheres(orc):
     """The adaptive 20-sphere octree to level 6 (dx = 1/512, 71M leaf cells in
     16^3 blocks, the size the adaptive benchmark leg runs): setup parity on
-    every level, then the first V-cycle against the checker (which needs
+    every level, then the first V-cycle against the oracle (which needs
     about a minute for setup and cycle on the host)."""
     w = W.spheres()
-    print("full size adaptive spheres: checker setup", flush=True)
+    print("full size adaptive spheres: oracle setup", flush=True)
     o = orc.setup_workload(w)
     print("device setup", flush=True)
     G = octmg.Geometry(w.geom)
@@ -306,9 +306,9 @@ def test_gradient_parity(orc, name):
 def test_full_size_two_electrodes(orc):
     """The two-electrode problem on the paper's resolutions (dx = 1/128
     everywhere, 1/512 near the electrodes, 8^3 blocks; 7.9M leaf cells):
-    setup parity on every level and the first FMG against the checker."""
+    setup parity on every level and the first FMG against the oracle."""
     w = W.two_electrodes()
-    print("full size two electrodes: checker setup", flush=True)
+    print("full size two electrodes: oracle setup", flush=True)
     o = orc.setup_workload(w)
     G = octmg.Geometry(w.geom)
     assert G.n_leaf > 5_000_000

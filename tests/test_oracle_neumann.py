@@ -1,4 +1,4 @@
-"""Pins of the checker's zero-flux (Neumann) domain faces, as used by the
+"""Pins of the oracle's zero-flux (Neumann) domain faces, as used by the
 two-electrode application of Sec. 4.4: the textbook cell-centred Laplacian
 with mirror ghosts assembled with scipy, exactness for a solution that is
 linear along the Dirichlet axis, a harmonic closed form with zero normal
@@ -177,7 +177,7 @@ def test_gradient_zero_flux_and_inside_cells(orc):
 def test_two_electrode_fmg_reduction(orc):
     """Sec. 4.4: the residual drops by about 30-40 per FMG iteration on the
     paper's mesh; on a coarser mesh of the same problem (uniform 32^3,
-    refined to 128^3 near the electrodes) the checker's reduction is at least
+    refined to 128^3 near the electrodes) the oracle's reduction is at least
     20 per iteration after the first."""
     w = W.two_electrodes(max_level=5, uniform_level=3)
     o = orc.setup_workload(w)

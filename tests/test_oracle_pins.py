@@ -1,9 +1,9 @@
-"""Pins of the FP64 CPU checker against what the paper and the mathematics
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics
 fix: closed-form roots, exactness on polynomials, a textbook discretisation
 assembled with scipy, a dense direct solve, second-order convergence, the
 paper's printed FMG reduction factors and error behaviour, symmetry,
 decoupling across the interface, and tree invariants.  None of these
-re-types the checker's own formulas; each would fail on a dropped term, a
+re-types the oracle's own formulas; each would fail on a dropped term, a
 swapped distance, a wrong sign or a transposed index."""
 import math
 import os

@@ -1,4 +1,4 @@
-"""Pins of the checker's sharp-shape level sets (Sec. 4.3, eqs. spheroid ..
+"""Pins of the oracle's sharp-shape level sets (Sec. 4.3, eqs. spheroid ..
 astroid): the cube root against numpy, interface roots against the shapes'
 closed forms, a dense sign scan, the 3D shapes as rotations of the 2D ones,
 and exactness of the discretisation for linear phi around the sharp
