@@ -3,7 +3,8 @@ steps of a cycle in one workgroup per right-hand side, both colours resident
 in LDS.  Its iterates must equal, bit for bit, those of the separate
 launches (pair_max_blocks = 0 selects them): Dirichlet faces with face data
 (FP64) and without (the FP32 correction equation), zero-flux faces,
-smoothing counts other than (2, 2), V-cycles and FMG, several rhs."""
+smoothing counts other than (2, 2), V-cycles and FMG, several rhs; and,
+with such counts, parity with the oracle."""
 import numpy as np
 import pytest
 
@@ -58,3 +59,31 @@ def test_single_block_equals_separate_launches(name, precision):
         if precision == octmg.FP64:
             na, nb = (S.residual_norm() for S in states)
             assert np.array_equal(na, nb)
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("counts", [(1, 3), (3, 1)])
+def test_single_block_oracle_parity(orc, name, counts):
+    """With smoothing counts other than (2, 2), the path with the one-block
+    kernel matches the oracle after every V-cycle and FMG (1e-10)."""
+    n_down, n_up = counts
+    print("single block oracle parity", name, counts, flush=True)
+    w = CASES[name]()
+    o = orc.setup_workload(w, n_down, n_up)
+    G = octmg.Geometry(w.geom)
+    S = octmg.State(G)
+    S.set_smoothing(n_down, n_up)
+    xo, _ = o.leaf_coords()
+    S.set_boundary(w.iface_value(o.iface_points()) if G.n_iface else None, w.domain_value(o.domain_points()))
+    S.set_rhs(w.rhs(xo))
+    S.fmg(have_guess=False)
+    o.fmg(have_guess=False)
+    assert rel(S.get_solution(), o.get_solution()) < 1e-10
+    for k in range(3):
+        S.vcycle()
+        o.vcycle()
+        assert rel(S.get_solution(), o.get_solution()) < 1e-10, k
