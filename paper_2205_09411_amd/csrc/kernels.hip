@@ -2166,6 +2166,62 @@ __global__ __launch_bounds__(256) void k_defect3(LV<double> L, LV<double> Lc, LV
     }
 }
 
+// the same defect with both colours staged at once by two wave groups (the
+// residual arithmetic of k_residual_max3_pair, the same bits as k_defect3);
+// LATE as in the restriction
+template <int N, int NTC, bool LATE>
+__global__ __launch_bounds__(2 * NTC) __attribute__((amdgpu_waves_per_eu(LATE ? 6 : 1))) void k_defect3_pair(
+    LV<double> L, LV<double> Lc, LV<float> L32, const int *lb, unsigned long long *out) {
+    using B = Blk<3, N>;
+    constexpr int PER = B::HALF / NTC;
+    constexpr bool V2 = cell_pairs<N>();
+    __shared__ double tiles[PairTiles<double, N>::SIZE];
+    __shared__ double wmax[2 * NTC / 64];
+    const int rhs = rhs_of(L);
+    const int blk = lb[blockIdx.x];
+    const int c = threadIdx.x / NTC, t = threadIdx.x % NTC;
+    const int4 P = L.pos[blk];
+    int nbk[6];
+    face_ids<double, N>(L, blk, nbk);
+    const int mo = L.map_off ? L.map_off[blk] : -1;
+    const int act = L.active ? L.active[rhs] : 1;
+    tables_loaded(act, 1, P, nbk, mo);
+    if (!act) return;
+    const double *__restrict__ phi = L.phi + (long long)rhs * L.fstride;
+    const double *__restrict__ g = L.g + (long long)rhs * L.fstride;
+    const double *phic = Lc.phi ? Lc.phi + (long long)rhs * Lc.fstride : nullptr;
+    const long long base = (long long)blk * B::CPB + c * B::HALF;
+    float *g32 = L32.g + (long long)rhs * L32.fstride + base;
+    float *p32 = L32.phi + (long long)rhs * L32.fstride + base;
+    double own[PER], lp[PER], gv[PER];
+    int ri[PER];
+    load_cells<double, PER, NTC, V2>(phi + base, t, own);
+    if (!LATE) load_cells<double, PER, NTC, V2>(g + base, t, gv);
+#pragma unroll
+    for (int m = 0; m < PER; m++) ri[m] = mo >= 0 ? L.map[mo + c * B::HALF + cell_of<NTC, V2>(t, m)] : -1;
+    pair_op<double, N, NTC, LATE>(L, Lc, phi, phic, tiles, blk, nbk, P, ri, own, lp);
+    if (LATE) load_cells<double, PER, NTC, V2>(g + base, t, gv);
+    float r32[PER], z32[PER];
+    double mx = 0.0;
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        const double r = gv[m] - lp[m];
+        mx = fmax(mx, fabs(r));
+        r32[m] = (float)r;
+        z32[m] = 0.0f;
+    }
+    store_cells<float, PER, NTC, V2>(g32, t, r32);
+    store_cells<float, PER, NTC, V2>(p32, t, z32);
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
+    if (threadIdx.x % 64 == 0) wmax[threadIdx.x / 64] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 2 * NTC / 64; w++) mx = fmax(mx, wmax[w]);
+        if (mx != mx) mx = __longlong_as_double(0x7ff0000000000000ll);
+        atomicMax(norm_slot(out, rhs), (unsigned long long)__double_as_longlong(mx));
+    }
+}
+
 // ================================================ bottom of the V-cycle, fused
 // Levels with few blocks are launch- and latency-bound: one launch costs a
 // few microseconds even for a single workgroup.  k_small_vcycle runs the
@@ -2599,7 +2655,12 @@ hipError_t launch_defect(int D, int N, const LV<double> &L, const LV<double> &Lc
     if (nlb == 0) return hipSuccess;
     dim3 grid(nlb, nrhs);
 #define DF(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_defect<D_, N_>), grid, dim3(Blk<D_, N_>::THREADS), 0, s, L, Lc, L32, lb, out))
-#define DF3(N_) OCTMG_DN(3, N_, hipLaunchKernelGGL((k_defect3<N_>), grid, dim3(256), 0, s, L, Lc, L32, lb, out))
+    const bool pair = (long long)nlb * nrhs <= L.pair_max, late = (long long)nlb * nrhs > kLateMin;
+#define DF3(N_)                                                                                                    \
+    OCTMG_DN(3, N_,                                                                                                \
+             if (pair && late) hipLaunchKernelGGL((k_defect3_pair<N_, 256, true>), grid, dim3(512), 0, s, L, Lc, L32, lb, out); \
+             else if (pair) hipLaunchKernelGGL((k_defect3_pair<N_, 256, false>), grid, dim3(512), 0, s, L, Lc, L32, lb, out); \
+             else hipLaunchKernelGGL((k_defect3<N_>), grid, dim3(256), 0, s, L, Lc, L32, lb, out))
     DF3(16) DF3(8) DF(2, 8) DF(2, 16)
 #undef DF3
 #undef DF
