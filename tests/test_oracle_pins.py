@@ -325,17 +325,31 @@ def test_paper_fmg_reduction_2d(orc):
 def test_paper_fmg_3d_lmax6(orc):
     """Sec. 4.1, 3D, l_max = 6 (256^3): reduction per FMG about 30-40, and the
     error hardly changes after two FMG iterations (printed: 0.32e-3, 0.11e-3,
-    0.11e-3). Checked: reduction >= 30; error(2) within 5 % of error(3);
-    error(1) a small multiple of the converged one; converged error within
-    the paper's printed error."""
+    0.11e-3).  Checked: reduction >= 30; error(2) within 5 % of error(3);
+    error(1) clearly above the converged error and below the printed one;
+    converged error below the printed one, and second order between 64^3,
+    128^3 and 256^3 (ratio 4 within 10 %).
+
+    The printed absolute error is not reproduced at 256^3: the oracle's
+    converged error there is 12x smaller.  Neither reading of the domain
+    ghost that keeps second order (2 phi_b - phi_in, or the exact value at
+    the ghost centre) moves it by more than 13 %, a first-order ghost
+    (ghost = face value) makes it 17x larger, and the maximum sits next to
+    the sphere, not at the domain faces.  The printed triple does match
+    this oracle's 64^3 run within about 30 % (5.8e-4, 1.42e-4, 1.43e-4),
+    so the paper's numbers may belong to a coarser grid than the stated
+    l_max gives; the absolute value stays unpinned."""
     gold = golden("paper_sphere_fmg.txt")
     res, errs = _fmg_run(orc, 3, 6, 3)
     fac = res[1:-1] / res[2:]
     assert (fac >= gold["fmg_reduction_3d_min"]).all(), fac
     assert abs(errs[1] - errs[2]) <= 0.05 * errs[2]
-    assert errs[0] <= 40 * errs[2]
+    assert 2.0 * errs[2] <= errs[0] <= 40 * errs[2]
     assert errs[2] <= gold["maxerr_3d_lmax6_fmg3"]
     assert errs[0] <= gold["maxerr_3d_lmax6_fmg1"]
+    conv = [_fmg_run(orc, 3, lm, 3)[1][-1] for lm in (4, 5)] + [errs[2]]
+    for a, b in zip(conv[:-1], conv[1:]):
+        assert 3.6 <= a / b <= 4.4, conv
 
 
 # ------------------------------------------------------------- invariants
