@@ -355,7 +355,7 @@ def leg_table1(stream, n_fmg=10):
 
 
 def leg_sharp(stream, n_fmg=4, reps=5):
-    """Sec. 4.3: the spheroid, rhombus, heart and astroid boundaries
+    """Sec. 4.2: the spheroid, rhombus, heart and astroid boundaries
     (phi = 1 on them, 0 on the domain boundary, Laplace equation) on uniform
     1024^2 and 2048^2 grids (8^2 blocks, 8^2 coarse grid) and 256^3 (16^3
     blocks over an 8^3 grid), FP64: residual reduction per FMG iteration and
@@ -363,7 +363,7 @@ def leg_sharp(stream, n_fmg=4, reps=5):
     import torch
     from paper_2205_09411_amd import octmg
     from paper_2205_09411_amd import workloads as W
-    out = {"workload": "sharp shapes of Sec. 4.3, p = 4(x-0.5), q = 4(y-0.5) (3D: p = 4 r, q = 4(z-0.5)), "
+    out = {"workload": "sharp shapes of Sec. 4.2, p = 4(x-0.5), q = 4(y-0.5) (3D: p = 4 r, q = 4(z-0.5)), "
                        "phi=1 on the shape, 0 on the domain boundary, FMG from phi=0"}
     for dim, lmax, bn, label in ((2, 8, 8, "1024^2"), (2, 9, 8, "2048^2"), (3, 5, 16, "256^3")):
         for shape in W.SHAPES:
@@ -390,7 +390,7 @@ def leg_sharp(stream, n_fmg=4, reps=5):
 
 
 def leg_electrodes(stream, n_fmg=4, reps=3):
-    """Sec. 4.4: rod (phi = 1) and half sphere (phi = 0) electrodes, phi = 1
+    """Sec. 4.3: rod (phi = 1) and half sphere (phi = 0) electrodes, phi = 1
     on top, 0 at the bottom, zero flux on the sides; dx = 1/128 everywhere
     and 1/512 near the electrodes (8^3 blocks): residual reduction per FMG
     iteration (the paper: about 30-40), time per FMG and per solve to 1e-10

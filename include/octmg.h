@@ -56,7 +56,7 @@ typedef enum {
 enum { OCTMG_LSF_NONE = 0,       /* no interface */
        OCTMG_LSF_SPHERES = 1,    /* union: f = min_m |x - c_m| - r_m; params [cx,cy,cz,r]*n */
        OCTMG_LSF_CYLINDER_Z = 2, /* f = |(x,y) - (cx,cy)| - r; params [cx,cy,r] */
-       /* the sharp shapes of Sec. 4.3 (eqs. spheroid .. astroid) in
+       /* the sharp shapes of Sec. 4.2 (eqs. spheroid .. astroid) in
         * coordinates 2D: p = s (x - cx), q = s (y - cy); 3D, rotated about the
         * z axis through (cx, cy): p = s |(x - cx, y - cy)|, q = s (z - cz);
         * params [cx, cy, cz, s]; |t|^(2/3) is evaluated as the cube root of
@@ -65,7 +65,7 @@ enum { OCTMG_LSF_NONE = 0,       /* no interface */
        OCTMG_LSF_RHOMBUS = 4,    /* 8 |p| + |q| - 1.5 */
        OCTMG_LSF_HEART = 5,      /* p^2 + (q - |p|^(2/3))^2 - 1 */
        OCTMG_LSF_ASTROID = 6,    /* |p|^(2/3) / 0.8 + |q|^(2/3) / 1.5 - 0.8 */
-       /* two electrodes (Sec. 4.4): min(dist(x, segment a-b) - r_rod,
+       /* two electrodes (Sec. 4.3): min(dist(x, segment a-b) - r_rod,
         * |x - c| - r_sph); params [ax,ay,az, bx,by,bz, r_rod, cx,cy,cz, r_sph] */
        OCTMG_LSF_ELECTRODES = 7 };
 enum { OCTMG_REFINE_UNIFORM = 0, OCTMG_REFINE_NEAR_INTERFACE = 1 };
@@ -94,7 +94,7 @@ enum { OCTMG_STEP_HALF_SWEEP = 0,   /* arg = colour (0 red, 1 black) */
  * octmg_geom_create only.
  * neumann_faces: bit f set makes domain face f (x-, x+, y-, y+, z-, z+ =
  * bits 0..5) a zero-flux face (ghost = the inside value), as on the sides of
- * the two-electrode problem of Sec. 4.4; the others are Dirichlet (values
+ * the two-electrode problem of Sec. 4.3; the others are Dirichlet (values
  * from octmg_set_boundary).  At least one face or the interface must carry
  * Dirichlet data.  uniform_level: levels up to this one are complete
  * whatever refine_kind says (0: no such base). */
@@ -200,7 +200,7 @@ octmg_status octmg_geom_records(octmg_geom g, int level, int *ids, double *d, do
 octmg_status octmg_geom_block_positions(octmg_geom g, int level, int *pos, int *leaf);
 
 /* Mesh adaptation (the paper's setting: the mesh changes often, the
- * boundary does not; Sec. 1 and Sec. 4.5).  flags[i] for the i-th leaf block
+ * boundary does not; Sec. 1 and Sec. 4.4).  flags[i] for the i-th leaf block
  * of g (canonical order: level, then Morton order within the level; the
  * blocks of octmg_geom_leaf_coords' cells, N^D cells each): +1 refine (below
  * max_level), -1 coarsen (a family of 2^D leaves goes when all are flagged
@@ -209,7 +209,7 @@ octmg_status octmg_geom_block_positions(octmg_geom g, int level, int *pos, int *
  * descriptor.  reuse != 0: blocks with the same level, position and leaf
  * status keep g's stencil records, interface points and (if the coarsest
  * level is unchanged) the coarse inverse; only the other blocks run the
- * boundary detection and line search (Sec. 4.5: new refinement needs the
+ * boundary detection and line search (Sec. 4.4: new refinement needs the
  * setup, removing refinement needs none).  The records equal those of a
  * setup from scratch, bit for bit.  stats (may be NULL): [blocks kept,
  * blocks set up, records kept, records computed].  g stays valid. */
@@ -256,7 +256,7 @@ octmg_status octmg_zero_solution(octmg_state s, void *stream);
  * cycle of that kind. */
 octmg_status octmg_cycle(octmg_state s, int kind, int have_guess, void *stream);
 /* Gradient of phi at every leaf cell centre (the field E = -grad phi of the
- * application in Sec. 4.4): on each cell face the difference to the
+ * application in Sec. 4.3): on each cell face the difference to the
  * neighbour value or ghost over dx, or (phi_b - phi_i)/(d dx) across a cut
  * link (d the stored relative distance, phi_b the interface value); each
  * component is the mean of the cell's two faces.  inside_zero != 0: cells

@@ -278,7 +278,7 @@ class Oracle:
 
     def gradient(self, inside_zero: bool = False) -> np.ndarray:
         """grad phi at the leaf cell centres, [n_leaf][3] (face differences
-        using the interface distances, Sec. 4.4)."""
+        using the interface distances, Sec. 4.3)."""
         out = np.zeros((self.n_leaf, 3))
         lib().orc_gradient(self._h, _dp(out), int(inside_zero))
         return out

@@ -60,10 +60,10 @@
  *     user rhs.  old = phi on the whole coarse level after restriction.
  *   * adaptive trees: after each cycle phi is restricted top-down onto
  *     parent cells, so that the composite residual is defined.
- *   * zero-flux (Neumann) domain faces (Sec. 4.4): ghost = phi_inside;
+ *   * zero-flux (Neumann) domain faces (Sec. 4.3): ghost = phi_inside;
  *     prolonged corrections are mirrored without the sign flip; the coarse
  *     operator folds the ghost into the diagonal.
- *   * sharp shapes (Sec. 4.3): p = 4 (x - 0.5), q = 4 (y - 0.5) (the
+ *   * sharp shapes (Sec. 4.2): p = 4 (x - 0.5), q = 4 (y - 0.5) (the
  *     printed division by 4 puts every shape outside the unit square); in
  *     3D p = 4 |(x, y) - (0.5, 0.5)|, q = 4 (z - 0.5) (rotation about the
  *     cube's vertical axis); |t|^(2/3) = cbrt(t^2) with a cube root made of
@@ -154,7 +154,7 @@ static double cbrt_exact_ops(double a) {
     return y;
 }
 
-/* The four shapes of Sec. 4.3 (eqs. spheroid .. astroid) in coordinates
+/* The four shapes of Sec. 4.2 (eqs. spheroid .. astroid) in coordinates
  * (p, q): 2D p = s (x - cx), q = s (y - cy); 3D, rotated about the z axis
  * through (cx, cy): p = s |(x - cx, y - cy)|, q = s (z - cz); params
  * [cx, cy, cz, s].  The paper prints p = (x - 0.5)/4, which puts every
@@ -177,7 +177,7 @@ static double shape_lsf(int kind, int D, const double *prm, const double *x) {
     }
 }
 
-/* Two electrodes (Sec. 4.4): a rod, the points within r_rod of the segment
+/* Two electrodes (Sec. 4.3): a rod, the points within r_rod of the segment
  * a-b, and a sphere; f = min(dist(x, [a, b]) - r_rod, |x - c| - r_sph).
  * params [ax, ay, az, bx, by, bz, r_rod, cx, cy, cz, r_sph]. */
 static double electrodes_lsf(const double *q, const double *x) {
@@ -1234,7 +1234,7 @@ double orc_residual_max(void *h, int phi_zero) {
 }
 
 /* composite residual for a given leaf vector (dense-assembly probing) */
-/* Gradient of phi at every leaf cell centre (Sec. 4.4): the derivative on
+/* Gradient of phi at every leaf cell centre (Sec. 4.3): the derivative on
  * each cell face is (phi_nb - phi_i)/dx with the neighbour's value or ghost,
  * or (phi_b - phi_i)/(d dx) towards a boundary between the cells (taken on
  * the side of the cut link); each component is the mean of its two faces.

@@ -640,7 +640,7 @@ __global__ void k_gather_leaf(LV<double> L, const int *lb, double *dst, long lon
     }
 }
 
-// grad phi of the leaf cells of one level (Sec. 4.4, the application's
+// grad phi of the leaf cells of one level (Sec. 4.3, the application's
 // field): on every face the difference to the neighbour value or ghost over
 // dx, or (phi_b - phi_i)/(d dx) towards a boundary on that link; each
 // component is the mean of its two faces.  Post-processing, run once per

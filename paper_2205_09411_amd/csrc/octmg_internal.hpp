@@ -189,7 +189,7 @@ hipError_t launch_check_finite(const double *p, long long n, int *flag, hipStrea
 // previous tree (Lold[nlev] and their block edges in device memory)
 hipError_t launch_remap(int D, int N, const LV<double> &Ln, int il, const LV<double> *Lold, const int *nb_old,
                         const int *lb, int nlb, int nrhs, hipStream_t s);
-// grad phi at the leaf cells of one level (Sec. 4.4: face differences, with
+// grad phi at the leaf cells of one level (Sec. 4.3: face differences, with
 // (phi_b - phi_i)/(d dx) across cut links), out[rhs][n_leaf][3] at leaf
 // offset base; inside_zero: cut cells with f(centre) < 0 get 0
 hipError_t launch_gradient(int D, int N, const LV<double> &L, const LV<double> &Lc, const int *lb, int nlb,

@@ -38,7 +38,7 @@ __device__ double cbrt_ops(double a) {
     return t;
 }
 
-// sharp shapes of Sec. 4.3 on the (p, q) plane; params [cx, cy, cz, s]
+// sharp shapes of Sec. 4.2 on the (p, q) plane; params [cx, cy, cz, s]
 __device__ double shape_dev(const SetupLevel &S, const double *x) {
     const double *c = S.lsf_params;
     double p, q;

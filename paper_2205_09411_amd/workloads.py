@@ -32,7 +32,7 @@ import numpy as np
 LSF_NONE = 0
 LSF_SPHERES = 1      # union of spheres/circles: params [cx, cy, cz, r] * n
 LSF_CYLINDER_Z = 2   # infinite cylinder along z: params [cx, cy, r]
-# the sharp shapes of Sec. 4.3, params [cx, cy, cz, s]: 2D p = s(x-cx),
+# the sharp shapes of Sec. 4.2, params [cx, cy, cz, s]: 2D p = s(x-cx),
 # q = s(y-cy); 3D p = s|(x-cx, y-cy)|, q = s(z-cz)
 LSF_SPHEROID, LSF_RHOMBUS, LSF_HEART, LSF_ASTROID = 3, 4, 5, 6
 SHAPES = {"spheroid": LSF_SPHEROID, "rhombus": LSF_RHOMBUS, "heart": LSF_HEART, "astroid": LSF_ASTROID}
@@ -202,7 +202,7 @@ def sphere_f1(dim: int = 3, max_level: int = 4, R: float = 0.25, block_n: int = 
 
 
 def sharp_shape(shape: str, dim: int = 2, max_level: int = 4, block_n: int = 8) -> Workload:
-    """Sec. 4.3: Laplace equation on the unit square/cube, phi = 1 on the
+    """Sec. 4.2: Laplace equation on the unit square/cube, phi = 1 on the
     shape's boundary, 0 on the domain boundary, uniform grid, w_min = 4e-3
     (2D) or 8e-3 (3D); shapes centred at 0.5 with scale 4."""
     geom = Geometry(dim=dim, block_n=block_n, max_level=max_level, lsf_kind=SHAPES[shape],
@@ -214,7 +214,7 @@ def sharp_shape(shape: str, dim: int = 2, max_level: int = 4, block_n: int = 8) 
 
 def two_electrodes(max_level: int = 7, uniform_level: int = 5, block_n: int = 8, refine_width: float = 1.0,
                    tip_z: float = 0.6) -> Workload:
-    """Sec. 4.4: unit cube, phi = 1 on the top face and 0 on the bottom face,
+    """Sec. 4.3: unit cube, phi = 1 on the top face and 0 on the bottom face,
     zero flux on the four sides; a rod electrode of radius 0.05 hanging from
     the top (segment (0.5, 0.5, tip_z)-(0.5, 0.5, 1.1)) at phi = 1 and a
     half sphere of radius 0.25 centred on the bottom face at phi = 0.

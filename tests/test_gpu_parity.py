@@ -24,12 +24,12 @@ CONFIGS = {
     "spheres_amr": lambda: W.spheres(n_spheres=5, max_level=5, block_n=8, seed=9),
     "sphere_f1_3d": lambda: W.sphere_f1(dim=3, max_level=4),
     "spheres_amr16": lambda: W.spheres(n_spheres=8, max_level=5, block_n=16, seed=12),
-    # the sharp shapes of Sec. 4.3
+    # the sharp shapes of Sec. 4.2
     "heart_2d": lambda: W.sharp_shape("heart", dim=2, max_level=4),
     "astroid_2d": lambda: W.sharp_shape("astroid", dim=2, max_level=5),
     "spheroid_3d": lambda: W.sharp_shape("spheroid", dim=3, max_level=3, block_n=16),
     "rhombus_3d": lambda: W.sharp_shape("rhombus", dim=3, max_level=3, block_n=8),
-    # zero-flux side faces (Sec. 4.4)
+    # zero-flux side faces (Sec. 4.3)
     "electrodes_small": lambda: W.two_electrodes(max_level=5, uniform_level=3),
     "neumann_2d": lambda: W.neumann2d(max_level=5),
 }
@@ -285,7 +285,7 @@ def test_full_size_adaptive_spheres(orc):
 
 @pytest.mark.parametrize("name", ["electrodes_small", "neumann_2d", "spheres_amr", "heart_2d"])
 def test_gradient_parity(orc, name):
-    """The field post-processing (Sec. 4.4) on the same phi: face
+    """The field post-processing (Sec. 4.3) on the same phi: face
     differences, interface distances, ghosts at domain faces (Dirichlet and
     zero flux) and refinement boundaries."""
     w = CONFIGS[name]()

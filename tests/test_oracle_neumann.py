@@ -1,5 +1,5 @@
 """Pins of the oracle's zero-flux (Neumann) domain faces, as used by the
-two-electrode application of Sec. 4.4: the textbook cell-centred Laplacian
+two-electrode application of Sec. 4.3: the textbook cell-centred Laplacian
 with mirror ghosts assembled with scipy, exactness for a solution that is
 linear along the Dirichlet axis, a harmonic closed form with zero normal
 derivative (second-order convergence), and the dense direct solve of the
@@ -130,7 +130,7 @@ def test_dense_direct_solve_neumann(orc):
     assert np.abs(o.get_solution() - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
-# ------------------------------------------------ two electrodes (Sec. 4.4)
+# ------------------------------------------------ two electrodes (Sec. 4.3)
 def test_gradient_exact_for_linear_phi(orc):
     """For linear phi every face difference is exact: neighbour values and
     domain/refinement ghosts, and at cut links (phi_b - phi_i)/(d dx)
@@ -175,7 +175,7 @@ def test_gradient_zero_flux_and_inside_cells(orc):
 
 
 def test_two_electrode_fmg_reduction(orc):
-    """Sec. 4.4: the residual drops by about 30-40 per FMG iteration on the
+    """Sec. 4.3: the residual drops by about 30-40 per FMG iteration on the
     paper's mesh; on a coarser mesh of the same problem (uniform 32^3,
     refined to 128^3 near the electrodes) the oracle's reduction is at least
     20 per iteration after the first."""

@@ -1,4 +1,4 @@
-"""Pins of the oracle's sharp-shape level sets (Sec. 4.3, eqs. spheroid ..
+"""Pins of the oracle's sharp-shape level sets (Sec. 4.2, eqs. spheroid ..
 astroid): the cube root against numpy, interface roots against the shapes'
 closed forms, a dense sign scan, the 3D shapes as rotations of the 2D ones,
 and exactness of the discretisation for linear phi around the sharp
@@ -132,7 +132,7 @@ def test_sign_scan_2d(orc, shape):
 @pytest.mark.parametrize("shape", sorted(W.SHAPES))
 def test_3d_shape_is_rotation_of_2d(orc, shape):
     """3D: f(x, y, z) = f_2D(0.5 + r, z) with r the distance to the cube's
-    vertical axis (Sec. 4.3's cylindrical generalisation)."""
+    vertical axis (Sec. 4.2's cylindrical generalisation)."""
     g2, g3 = shape_geom(shape, dim=2), shape_geom(shape, dim=3)
     rng = np.random.default_rng(4)
     for _ in range(300):
