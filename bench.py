@@ -677,7 +677,8 @@ def main():
         out["legs"] = legs
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_cycles)
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
+    octmg.close_all()  # release every device object before the interpreter exits
 
 
 if __name__ == "__main__":

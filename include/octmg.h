@@ -67,7 +67,22 @@ enum { OCTMG_LSF_NONE = 0,       /* no interface */
        OCTMG_LSF_ASTROID = 6,    /* |p|^(2/3) / 0.8 + |q|^(2/3) / 1.5 - 0.8 */
        /* two electrodes (Sec. 4.3): min(dist(x, segment a-b) - r_rod,
         * |x - c| - r_sph); params [ax,ay,az, bx,by,bz, r_rod, cx,cy,cz, r_sph] */
-       OCTMG_LSF_ELECTRODES = 7 };
+       OCTMG_LSF_ELECTRODES = 7,
+       /* any level set given as a host function (octmg_geom_desc.lsf_fn):
+        * the setup (boundary mask, line search, unresolved-boundary search,
+        * stencils) then runs on the host in FP64 with the same arithmetic as
+        * the device setup of the built-in kinds; see octmg_lsf_fn */
+       OCTMG_LSF_CALLBACK = 8 };
+
+/* A user level set f(x) (Sec. 3.1: the interface is f = 0; cells with
+ * f < 0 are inside).  x points to 3 coordinates (z = 0 in 2D).  Called on
+ * the thread that runs octmg_plan_*, octmg_geom_create or octmg_geom_adapt,
+ * one call at a time, about (1 + 2D) times per cell of every level plus a
+ * few tens of times per cell near the interface (Sec. 3.2, Sec. 3.6.1).  It
+ * must be deterministic.  As Sec. 3.6.1 notes, f need not be a distance
+ * function, but the boundary mask assumes |grad f| describes f near its
+ * zero contour. */
+typedef double (*octmg_lsf_fn)(const double *x, void *user);
 enum { OCTMG_REFINE_UNIFORM = 0, OCTMG_REFINE_NEAR_INTERFACE = 1 };
 enum { OCTMG_FP64 = 0, OCTMG_MIXED = 1 };
 enum { OCTMG_CYCLE_V = 0, OCTMG_CYCLE_FMG = 1 };
@@ -91,7 +106,9 @@ enum { OCTMG_STEP_HALF_SWEEP = 0,   /* arg = colour (0 red, 1 black) */
  * boundary-mask (1.5 in the paper); w_min the smallest width resolved on
  * coarse grids (Sec. 3.6.3; <= 0 disables); coarse_n the cells per edge of the
  * directly solved coarsest grid (8).  lsf_params is a host array read during
- * octmg_geom_create only.
+ * octmg_geom_create only.  lsf_fn and lsf_user (lsf_kind OCTMG_LSF_CALLBACK
+ * only; lsf_params may then be NULL) must stay valid for the life of the
+ * geometry and of the geometries adapted from it.
  * neumann_faces: bit f set makes domain face f (x-, x+, y-, y+, z-, z+ =
  * bits 0..5) a zero-flux face (ghost = the inside value), as on the sides of
  * the two-electrode problem of Sec. 4.3; the others are Dirichlet (values
@@ -105,6 +122,8 @@ typedef struct octmg_geom_desc {
     double lo[3];
     const double *lsf_params;
     int uniform_level, reserved;
+    octmg_lsf_fn lsf_fn;
+    void *lsf_user;
 } octmg_geom_desc;
 
 typedef struct octmg_geom_s *octmg_geom;
@@ -154,11 +173,21 @@ typedef struct octmg_solve_opts {
     double rtol;
 } octmg_solve_opts;
 
-/* Solve report (worst right-hand side of the state). */
+/* Solve report.  cycles, status, r0, r_final and history describe the
+ * state as a whole (the largest residual over its right-hand sides).  The
+ * four pointers are optional host arrays of n_rhs entries that the caller
+ * sets (NULL: not filled): per right-hand side its status (OCTMG_OK when it
+ * reached rtol, OCTMG_ERR_NOT_CONVERGED, OCTMG_ERR_NONFINITE), the cycles it
+ * received (a converged rhs is frozen), the max-norm residual of phi = 0 and
+ * the last residual. */
 typedef struct octmg_solve_report {
     int cycles, status;
     double r0, r_final;
     double history[64]; /* max-norm residual after each cycle */
+    int *rhs_status;
+    int *rhs_cycles;
+    double *rhs_r0;
+    double *rhs_r_final;
 } octmg_solve_report;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -244,11 +273,20 @@ octmg_status octmg_state_set_fused_levels(octmg_state s, int max_blocks);
  * redoing the setup). */
 octmg_status octmg_set_boundary(octmg_state s, const double *iface_vals, const double *domain_vals,
                                 int on_device, void *stream);
-/* rhs g at leaf cells, [n_rhs][n_leaf] in canonical leaf order. */
-octmg_status octmg_set_rhs(octmg_state s, const double *g, int on_device, void *stream);
-/* Initial guess / solution at leaf cells, [n_rhs][n_leaf]. */
-octmg_status octmg_set_solution(octmg_state s, const double *phi, int on_device, void *stream);
-octmg_status octmg_get_solution(octmg_state s, double *phi, int on_device, void *stream);
+/* Element type of the caller's rhs and solution buffers.  The solver
+ * works in FP64 (in MIXED precision the inner cycles run in FP32, the
+ * iterate is FP64); FP32 input is widened exactly, FP32 output is the FP64
+ * solution rounded to nearest. */
+enum { OCTMG_DTYPE_F64 = 0, OCTMG_DTYPE_F32 = 1 };
+/* rhs g at leaf cells, [n_rhs][n_leaf] in canonical leaf order, elements
+ * of type dtype.  OCTMG_ERR_NONFINITE if any value is NaN or Inf.
+ * Synchronises the stream (host buffers are staged through device memory
+ * that the call allocates and frees). */
+octmg_status octmg_set_rhs(octmg_state s, const void *g, int dtype, int on_device, void *stream);
+/* Initial guess / solution at leaf cells, [n_rhs][n_leaf], as for
+ * octmg_set_rhs.  get_solution synchronises the stream. */
+octmg_status octmg_set_solution(octmg_state s, const void *phi, int dtype, int on_device, void *stream);
+octmg_status octmg_get_solution(octmg_state s, void *phi, int dtype, int on_device, void *stream);
 octmg_status octmg_zero_solution(octmg_state s, void *stream);
 /* Exactly one cycle: OCTMG_CYCLE_V (FAS V-cycle, Sec. 2.2) or
  * OCTMG_CYCLE_FMG (have_guess = 0 starts by restricting the rhs). In MIXED

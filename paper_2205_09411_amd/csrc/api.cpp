@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <array>
 #include <chrono>
+#include <cstddef>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -589,10 +590,12 @@ octmg_status validate_desc(const octmg_geom_desc *d) {
     if (!d) return fail(OCTMG_ERR_INVALID, "null descriptor");
     if (!(d->eps_tol > 0.0 && d->eps_tol < 0.5)) return fail(OCTMG_ERR_INVALID, "eps_tol must be in (0, 0.5)");
     if (!(d->mask_factor > 0.0)) return fail(OCTMG_ERR_INVALID, "mask_factor must be > 0");
-    if (d->lsf_kind < OCTMG_LSF_NONE || d->lsf_kind > OCTMG_LSF_ELECTRODES) return fail(OCTMG_ERR_INVALID, "unknown lsf_kind");
+    if (d->lsf_kind < OCTMG_LSF_NONE || d->lsf_kind > OCTMG_LSF_CALLBACK) return fail(OCTMG_ERR_INVALID, "unknown lsf_kind");
+    if (d->lsf_kind == OCTMG_LSF_CALLBACK && !d->lsf_fn) return fail(OCTMG_ERR_INVALID, "lsf_fn is null");
     if (d->lsf_kind == OCTMG_LSF_SPHERES && (d->lsf_n < 1 || d->lsf_n > 100000))
         return fail(OCTMG_ERR_INVALID, "lsf_n out of range");
-    if (d->lsf_kind != OCTMG_LSF_NONE && !d->lsf_params) return fail(OCTMG_ERR_INVALID, "lsf_params is null");
+    if (d->lsf_kind != OCTMG_LSF_NONE && d->lsf_kind != OCTMG_LSF_CALLBACK && !d->lsf_params)
+        return fail(OCTMG_ERR_INVALID, "lsf_params is null");
     if (d->neumann_faces < 0 || d->neumann_faces >= (1 << (2 * d->dim)))
         return fail(OCTMG_ERR_INVALID, "neumann_faces has bits beyond the 2D faces");
     if (d->neumann_faces == (1 << (2 * d->dim)) - 1 && d->lsf_kind == OCTMG_LSF_NONE)
@@ -673,6 +676,8 @@ static octmg_status setup_geometry(octmg_geom_s *G, const octmg_geom_s *reuse, i
     const int nbisect = (int)std::ceil(-std::log(G->desc.eps_tol) / std::log(2.0));
     const int ngolden = (int)std::ceil(std::log(G->desc.eps_tol) / std::log(0.5 * (std::sqrt(5.0) - 1.0)));
 
+    // a level set given as a host function runs the setup passes on the host
+    const bool host_lsf = G->desc.lsf_kind == OCTMG_LSF_CALLBACK;
     long long leaf_base = 0, pt_base = 0;
     bool coarse_kept = false;  // level 0 unchanged: the coarse inverse carries over
     for (int il = 0; il < nlev; il++) {
@@ -739,6 +744,8 @@ static octmg_status setup_geometry(octmg_geom_s *G, const octmg_geom_s *reuse, i
         S.lsf_kind = G->desc.lsf_kind;
         S.lsf_n = G->desc.lsf_n;
         S.lsf_params = d_params;
+        S.lsf_fn = G->desc.lsf_fn;
+        S.lsf_user = G->desc.lsf_user;
         S.mask_L = G->desc.mask_factor * std::sqrt((double)D) * L.dx;
         S.w_min = G->desc.w_min;
         S.nbisect = nbisect;
@@ -768,12 +775,23 @@ static octmg_status setup_geometry(octmg_geom_s *G, const octmg_geom_s *reuse, i
         HIPCK(hipMalloc(&d_fresh, sizeof(int) * std::max<size_t>(1, fresh.size())));
         std::unique_ptr<int, void (*)(int *)> fresh_guard(d_fresh, [](int *p) { (void)hipFree(p); });
         std::vector<int> counts(2 * L.nblocks, 0);
+        SetupLevel H{};  // host view of S for a host level set
         if (!fresh.empty()) {
             HIPCK(hipMemcpy(d_fresh, fresh.data(), sizeof(int) * fresh.size(), hipMemcpyHostToDevice));
             S.blocks = (int)fresh.size() == L.nblocks ? nullptr : d_fresh;
             S.nlist = (int)fresh.size();
-            HIPCK(launch_setup_count(S, d_counts, nullptr));
-            HIPCK(hipMemcpy(counts.data(), d_counts, sizeof(int) * 2 * L.nblocks, hipMemcpyDeviceToHost));
+            if (host_lsf) {
+                H = S;
+                H.pos = pos4.data();
+                H.lut = T.lut.data();
+                H.leaf = leaf.data();
+                H.lsf_params = G->params.data();
+                H.blocks = S.blocks ? fresh.data() : nullptr;
+                host_setup_count(H, counts.data());
+            } else {
+                HIPCK(launch_setup_count(S, d_counts, nullptr));
+                HIPCK(hipMemcpy(counts.data(), d_counts, sizeof(int) * 2 * L.nblocks, hipMemcpyDeviceToHost));
+            }
         }
         for (int b = 0; b < L.nblocks; b++)
             if (old_of[b] >= 0) {
@@ -822,9 +840,27 @@ static octmg_status setup_geometry(octmg_geom_s *G, const octmg_geom_s *reuse, i
             HIPCK(G->pool.alloc(&L.d_rec8f, (size_t)8 * nrec));
             HIPCK(G->pool.alloc(&L.d_pts, (size_t)3 * std::max<long long>(1, npt)));
             HIPCK(G->pool.alloc(&L.d_inside, (size_t)nrec));
-            if (!fresh.empty())
+            if (!fresh.empty() && host_lsf) {
+                // records of the fresh blocks on the host, uploaded whole; the
+                // kept blocks' entries are filled in by the copy below
+                std::vector<int> map((size_t)nib * L.cpb, -1), meta((size_t)4 * nrec, 0), inside(nrec, 0);
+                std::vector<double> d6((size_t)6 * nrec, 0.0), cfull((size_t)6 * nrec, 0.0), rec8((size_t)8 * nrec, 0.0);
+                std::vector<float> rec8f((size_t)8 * nrec, 0.0f);
+                std::vector<double> pts((size_t)3 * std::max<long long>(1, npt), 0.0);
+                host_setup_emit(H, rec_off.data(), pt_off.data(), map_off.data(), map.data(), meta.data(), d6.data(),
+                                cfull.data(), rec8.data(), rec8f.data(), pts.data(), inside.data());
+                HIPCK(hipMemcpy(L.d_map, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice));
+                HIPCK(hipMemcpy(L.d_meta, meta.data(), sizeof(int) * meta.size(), hipMemcpyHostToDevice));
+                HIPCK(hipMemcpy(L.d_inside, inside.data(), sizeof(int) * inside.size(), hipMemcpyHostToDevice));
+                HIPCK(hipMemcpy(L.d_d6, d6.data(), sizeof(double) * d6.size(), hipMemcpyHostToDevice));
+                HIPCK(hipMemcpy(L.d_cfull, cfull.data(), sizeof(double) * cfull.size(), hipMemcpyHostToDevice));
+                HIPCK(hipMemcpy(L.d_rec8, rec8.data(), sizeof(double) * rec8.size(), hipMemcpyHostToDevice));
+                HIPCK(hipMemcpy(L.d_rec8f, rec8f.data(), sizeof(float) * rec8f.size(), hipMemcpyHostToDevice));
+                HIPCK(hipMemcpy(L.d_pts, pts.data(), sizeof(double) * pts.size(), hipMemcpyHostToDevice));
+            } else if (!fresh.empty()) {
                 HIPCK(launch_setup_emit(S, d_roff, d_poff, L.d_map_off, L.d_map, L.d_meta, L.d_d6, L.d_cfull, L.d_rec8,
                                         L.d_rec8f, L.d_pts, L.d_inside, nullptr));
+            }
             std::vector<ReuseBlock> keep;
             for (int b = 0; b < L.nblocks; b++) {
                 const int ob = old_of[b];
@@ -1265,13 +1301,35 @@ octmg_status octmg_set_boundary(octmg_state s, const double *iface_vals, const d
     return OCTMG_OK;
 }
 
-static octmg_status set_leaf_field(octmg_state s, const double *src, int on_device, hipStream_t st, int field) {
+// FP64 device copy of n caller values of type dtype (host or device)
+static octmg_status stage_in_typed(const void *src, int dtype, size_t n, int on_device, hipStream_t st, double **dev,
+                                   DevPool *tmp) {
+    if (dtype == OCTMG_DTYPE_F64) return stage_in((const double *)src, n, on_device, st, dev, tmp);
+    const float *f = (const float *)src;
+    if (!on_device) {
+        float *df = nullptr;
+        HIPCK(tmp->alloc(&df, n));
+        HIPCK(hipMemcpyAsync(df, src, n * sizeof(float), hipMemcpyHostToDevice, st));
+        f = df;
+    }
+    HIPCK(tmp->alloc(dev, n));
+    HIPCK(launch_copy_f2d(f, *dev, (long long)n, st));
+    return OCTMG_OK;
+}
+
+static octmg_status check_dtype(int dtype) {
+    if (dtype != OCTMG_DTYPE_F64 && dtype != OCTMG_DTYPE_F32) return fail(OCTMG_ERR_INVALID, "unknown dtype");
+    return OCTMG_OK;
+}
+
+static octmg_status set_leaf_field(octmg_state s, const void *src, int dtype, int on_device, hipStream_t st,
+                                   int field) {
     octmg_geom g = s->geom;
     HIPCK(hipSetDevice(g->device));
     DevPool tmp;
     double *dv = nullptr;
     const size_t n = (size_t)g->n_leaf * s->nrhs;
-    STCK(stage_in(src, n, on_device, st, &dv, &tmp));
+    STCK(stage_in_typed(src, dtype, n, on_device, st, &dv, &tmp));
     STCK(check_finite(s, dv, (long long)n, st));
     for (size_t il = 0; il < g->L.size(); il++) {
         const GeomLevel &L = g->L[il];
@@ -1282,32 +1340,44 @@ static octmg_status set_leaf_field(octmg_state s, const double *src, int on_devi
     return OCTMG_OK;
 }
 
-octmg_status octmg_set_rhs(octmg_state s, const double *gv, int on_device, void *stream) {
+octmg_status octmg_set_rhs(octmg_state s, const void *gv, int dtype, int on_device, void *stream) {
     if (!s || !gv) return fail(OCTMG_ERR_INVALID, "null argument");
+    STCK(check_dtype(dtype));
     s->r0_dirty = true;
-    return set_leaf_field(s, gv, on_device, (hipStream_t)stream, 1);
+    return set_leaf_field(s, gv, dtype, on_device, (hipStream_t)stream, 1);
 }
 
-octmg_status octmg_set_solution(octmg_state s, const double *phi, int on_device, void *stream) {
+octmg_status octmg_set_solution(octmg_state s, const void *phi, int dtype, int on_device, void *stream) {
     if (!s || !phi) return fail(OCTMG_ERR_INVALID, "null argument");
-    return set_leaf_field(s, phi, on_device, (hipStream_t)stream, 0);
+    STCK(check_dtype(dtype));
+    return set_leaf_field(s, phi, dtype, on_device, (hipStream_t)stream, 0);
 }
 
-octmg_status octmg_get_solution(octmg_state s, double *phi, int on_device, void *stream) {
+octmg_status octmg_get_solution(octmg_state s, void *phi, int dtype, int on_device, void *stream) {
     if (!s || !phi) return fail(OCTMG_ERR_INVALID, "null argument");
+    STCK(check_dtype(dtype));
     hipStream_t st = (hipStream_t)stream;
     octmg_geom g = s->geom;
     HIPCK(hipSetDevice(g->device));
     const size_t n = (size_t)g->n_leaf * s->nrhs;
     DevPool tmp;
-    double *dv = phi;
-    if (!on_device) HIPCK(tmp.alloc(&dv, n));
+    const bool f64 = dtype == OCTMG_DTYPE_F64;
+    double *dv = (double *)phi;
+    if (!on_device || !f64) HIPCK(tmp.alloc(&dv, n));
     for (size_t il = 0; il < g->L.size(); il++) {
         const GeomLevel &L = g->L[il];
         HIPCK(launch_gather_leaf(g->tree.D, L.Nb, lv64(s, (int)il), L.d_leaf_blocks, L.nleaf, dv, g->n_leaf,
                                  L.leaf_base, s->nrhs, st));
     }
-    if (!on_device) HIPCK(hipMemcpyAsync(phi, dv, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (f64) {
+        if (!on_device) HIPCK(hipMemcpyAsync(phi, dv, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    } else {
+        // rounded to FP32 on the device, then copied if the caller's buffer is on the host
+        float *df = (float *)phi;
+        if (!on_device) HIPCK(tmp.alloc(&df, n));
+        HIPCK(launch_copy_d2f(dv, df, (long long)n, st));
+        if (!on_device) HIPCK(hipMemcpyAsync(phi, df, n * sizeof(float), hipMemcpyDeviceToHost, st));
+    }
     HIPCK(hipStreamSynchronize(st));
     return OCTMG_OK;
 }
@@ -1504,10 +1574,22 @@ static void read_mapped(octmg_state s, std::vector<double> &out) {
 // graph_mode 0: eager launches; 1: each cycle replays one captured graph;
 // 2: the whole solve is one captured graph of max_cycles cycles, with the
 // convergence test on the device (no stall test in that mode).
-static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStream_t st, octmg_solve_report *rp) {
+// Outcome of each right-hand side of a solve: cycles it received, its last
+// residual norm, and whether it reached rtol.
+struct PerRhs {
+    std::vector<int> cycles, done;
+    std::vector<double> r0, r_final;
+};
+
+static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStream_t st, octmg_solve_report *rp,
+                               PerRhs &pr) {
     const int R = s->nrhs;
-    std::vector<double> r0(R), rk(R), cur(R, 0.0), prev(R, 0.0);
+    std::vector<double> r0(R), rk(R), prev(R, 0.0);
+    std::vector<double> &cur = pr.r_final;
     std::vector<int> act(R, 1);
+    cur.assign(R, 0.0);
+    pr.cycles.assign(R, 0);
+    pr.done.assign(R, 0);
     STCK(set_active(s, act, st));
     if (s->r0_dirty) {
         STCK(residual_norm_dev(s, 1, st));
@@ -1516,8 +1598,9 @@ static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStre
         s->r0_dirty = false;
     }
     r0 = s->r0_cache;
+    pr.r0 = r0;
     if (o->zero_start) STCK(octmg_zero_solution(s, st));
-    std::memset(rp, 0, sizeof(*rp));
+    std::memset(rp, 0, offsetof(octmg_solve_report, rhs_status));
     for (double v : r0) rp->r0 = std::max(rp->r0, v);
     // residual of the starting iterate
     if (s->precision == OCTMG_MIXED) {
@@ -1538,6 +1621,7 @@ static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStre
             th[r] = o->rtol * r0[r];
             if (!(rk[r] <= th[r])) all_done = false;
             act[r] = rk[r] <= th[r] ? 0 : 1;
+            pr.done[r] = 1 - act[r];
             rp->r_final = std::max(rp->r_final, rk[r]);
         }
         if (all_done) {
@@ -1571,8 +1655,9 @@ static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStre
             for (int r = 0; r < R; r++) {
                 if (!act[r]) continue;  // converged before this cycle
                 cur[r] = hist[(size_t)c * R + r];
+                pr.cycles[r] = c + 1;
                 if (!std::isfinite(cur[r])) nonfinite = true;
-                if (cur[r] <= th[r]) act[r] = 0;
+                if (cur[r] <= th[r]) act[r] = 0, pr.done[r] = 1;
                 any = true;
             }
             if (!any) break;
@@ -1601,8 +1686,10 @@ static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStre
             if (act[r]) cur[r] = rk[r];
             if (!std::isfinite(cur[r])) nonfinite = true;
             rmax = std::max(rmax, cur[r]);
+            if (act[r]) pr.cycles[r] = k;
             if (act[r] && cur[r] <= o->rtol * r0[r]) {
                 act[r] = 0;
+                pr.done[r] = 1;
                 changed = true;
             }
             if (act[r]) all_done = false;
@@ -1660,8 +1747,18 @@ octmg_status octmg_solve(octmg_state s, const octmg_solve_opts *o, void *stream,
         st = s->own_stream;
     }
     octmg_solve_report local{};
-    octmg_status res = solve_impl(s, o, st, rep ? rep : &local);
+    PerRhs pr;
+    octmg_status res = solve_impl(s, o, st, rep ? rep : &local, pr);
     std::string msg = g_last_error;
+    if (rep && (int)pr.r_final.size() == s->nrhs)
+        for (int r = 0; r < s->nrhs; r++) {
+            const bool finite = std::isfinite(pr.r_final[r]);
+            if (rep->rhs_status)
+                rep->rhs_status[r] = !finite ? OCTMG_ERR_NONFINITE : pr.done[r] ? OCTMG_OK : OCTMG_ERR_NOT_CONVERGED;
+            if (rep->rhs_cycles) rep->rhs_cycles[r] = pr.cycles[r];
+            if (rep->rhs_r0) rep->rhs_r0[r] = pr.r0.empty() ? 0.0 : pr.r0[r];
+            if (rep->rhs_r_final) rep->rhs_r_final[r] = pr.r_final[r];
+        }
     std::vector<int> all(s->nrhs, 1);
     STCK(set_active(s, all, st));
     if (res != OCTMG_OK) return fail(res, msg);

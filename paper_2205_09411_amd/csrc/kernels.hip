@@ -875,6 +875,10 @@ __global__ void k_copy_d2f(const double *s, float *d, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         d[i] = (float)s[i];
 }
+__global__ void k_copy_f2d(const float *s, double *d, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        d[i] = (double)s[i];
+}
 __global__ void k_check_finite(const double *p, long long n, int *flag) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         if (!isfinite(p[i])) atomicOr(flag, 1);
@@ -2712,6 +2716,11 @@ hipError_t launch_converge(const unsigned long long *norm, const double *thresh,
 hipError_t launch_copy_d2f(const double *src, float *dst, long long n, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_copy_d2f, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+hipError_t launch_copy_f2d(const float *src, double *dst, long long n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_f2d, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
     return hipGetLastError();
 }
 hipError_t launch_check_finite(const double *p, long long n, int *flag, hipStream_t s) {

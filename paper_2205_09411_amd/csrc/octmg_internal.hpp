@@ -50,7 +50,7 @@ bool build_tree(const octmg_geom_desc &d, Tree *out, std::string *err);
 // again.  The paper's setting: the mesh changes, the boundary does not.
 bool adapt_tree(const octmg_geom_desc &d, const Tree &old, const int8_t *flags, Tree *out, std::string *err);
 
-// Host evaluation of the built-in level sets (block-centre refinement test).
+// Host evaluation of the geometry's level set (block-centre refinement test).
 double lsf_host(const octmg_geom_desc &d, const double *params, const double *x);
 
 // ------------------------------------------------------- device views
@@ -184,6 +184,7 @@ hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long lon
 hipError_t launch_converge(const unsigned long long *norm, const double *thresh, int *active, double *hist, int c,
                            int nrhs, hipStream_t s);
 hipError_t launch_copy_d2f(const double *src, float *dst, long long n, hipStream_t s);
+hipError_t launch_copy_f2d(const float *src, double *dst, long long n, hipStream_t s);
 hipError_t launch_check_finite(const double *p, long long n, int *flag, hipStream_t s);
 // phi of one level's leaf blocks of an adapted tree from the levels of the
 // previous tree (Lold[nlev] and their block edges in device memory)
@@ -205,7 +206,9 @@ struct SetupLevel {
     const int *lut;
     const int *leaf;
     int lsf_kind, lsf_n;
-    const double *lsf_params;  // device copy
+    const double *lsf_params;  // device copy (host copy in the host passes)
+    octmg_lsf_fn lsf_fn;       // OCTMG_LSF_CALLBACK (host passes only)
+    void *lsf_user;
     double mask_L;             // mask_factor * sqrt(D) * dx
     double w_min;
     int nbisect, ngolden;
@@ -229,6 +232,11 @@ hipError_t launch_setup_count(const SetupLevel &S, int *counts /*[nblocks][2]*/,
 hipError_t launch_setup_emit(const SetupLevel &S, const int *rec_off, const int *pt_off, const int *map_off,
                              int *map, int *meta /*[nrec][4]*/, double *d6, double *cfull /*[nrec][6]*/,
                              double *rec8, float *rec8f, double *pts, int *inside /*[nrec]*/, hipStream_t s);
+// the same two passes on the host, for a level set given as a host function
+// (S holds host pointers; only the blocks of S.blocks if set)
+void host_setup_count(const SetupLevel &S, int *counts);
+void host_setup_emit(const SetupLevel &S, const int *rec_off, const int *pt_off, const int *map_off, int *map,
+                     int *meta, double *d6, double *cfull, double *rec8, float *rec8f, double *pts, int *inside);
 // coarsest grid: dense operator with domain ghosts folded in, then a
 // row-equilibrated Gauss-Jordan inverse M and scales S (A^-1 = M diag(S)).
 hipError_t launch_coarse_assemble(int D, int Nb, double dx, const int *map, const double *rec8, int neumann,

@@ -1,4 +1,4 @@
-// FP64 interface setup on the device.
+// FP64 interface setup.
 //
 // For every cell of a level: the boundary mask of eq. (boundary-mask), the
 // relative distances d of Sec. 3.2 (bisection when a link is bracketed,
@@ -8,117 +8,42 @@
 // side (Sec. 3.6.2).  The level-set decisions must not depend on rounding
 // shortcuts, so this file is compiled with -ffp-contract=off and uses only
 // + - * / sqrt and comparisons (all correctly rounded).
+//
+// The per-cell analysis is written once, for host and device: the built-in
+// level sets run it in the setup kernels, a level set given as a host
+// function runs it on the host (host_setup_count / host_setup_emit), with
+// the same results for the same f.
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
 
+#include "lsf.hpp"
 #include "octmg_internal.hpp"
 
 namespace octmg {
 namespace {
 
-// cube root of a >= 0 from + - * / alone: powers of 8 bring a into
-// [1/8, 1), six Newton steps from 3/4 on t^3 = m, powers of 2 scale back
-__device__ double cbrt_ops(double a) {
-    if (!(a > 0.0)) return 0.0;
-    int k = 0;
-    double m = a;
-    while (m >= 1.0) {
-        m = m * 0.125;
-        ++k;
-    }
-    while (m < 0.125) {
-        m = m * 8.0;
-        --k;
-    }
-    double t = 0.75;
-    for (int it = 0; it < 6; ++it) t = (2.0 * t + m / (t * t)) / 3.0;
-    for (; k > 0; --k) t = t * 2.0;
-    for (; k < 0; ++k) t = t * 0.5;
-    return t;
+__host__ __device__ inline Lsf lsf_of(const SetupLevel &S) {
+    return Lsf{S.lsf_kind, S.lsf_n, S.D, S.lsf_params, S.lsf_fn, S.lsf_user};
 }
 
-// sharp shapes of Sec. 4.2 on the (p, q) plane; params [cx, cy, cz, s]
-__device__ double shape_dev(const SetupLevel &S, const double *x) {
-    const double *c = S.lsf_params;
-    double p, q;
-    if (S.D == 2) {
-        p = c[3] * (x[0] - c[0]);
-        q = c[3] * (x[1] - c[1]);
-    } else {
-        const double ex = x[0] - c[0], ey = x[1] - c[1];
-        p = c[3] * __dsqrt_rn(ex * ex + ey * ey);
-        q = c[3] * (x[2] - c[2]);
-    }
-    if (S.lsf_kind == OCTMG_LSF_SPHEROID) return __dsqrt_rn(8.0 * p * p + q * q) - 1.0;
-    if (S.lsf_kind == OCTMG_LSF_RHOMBUS) return 8.0 * fabs(p) + fabs(q) - 1.5;
-    if (S.lsf_kind == OCTMG_LSF_HEART) {
-        const double h = q - cbrt_ops(p * p);
-        return p * p + h * h - 1.0;
-    }
-    return cbrt_ops(p * p) / 0.8 + cbrt_ops(q * q) / 1.5 - 0.8;
-}
-
-// rod (points within r_rod of segment a-b) and sphere, the nearer surface
-__device__ double electrodes_dev(const double *q, const double *x) {
-    double ab[3], t = 0.0, ll = 0.0;
-    for (int c = 0; c < 3; ++c) {
-        ab[c] = q[3 + c] - q[c];
-        t += (x[c] - q[c]) * ab[c];
-        ll += ab[c] * ab[c];
-    }
-    t = t / ll;
-    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-    double d2 = 0.0, s2 = 0.0;
-    for (int c = 0; c < 3; ++c) {
-        const double e = x[c] - (q[c] + t * ab[c]), f = x[c] - q[7 + c];
-        d2 += e * e;
-        s2 += f * f;
-    }
-    const double rod = __dsqrt_rn(d2) - q[6], sph = __dsqrt_rn(s2) - q[10];
-    return rod < sph ? rod : sph;
-}
-
-__device__ double lsf_dev(const SetupLevel &S, const double *x) {
-    const double *p = S.lsf_params;
-    if (S.lsf_kind == OCTMG_LSF_ELECTRODES) return electrodes_dev(p, x);
-    if (S.lsf_kind >= OCTMG_LSF_SPHEROID && S.lsf_kind <= OCTMG_LSF_ASTROID) return shape_dev(S, x);
-    if (S.lsf_kind == OCTMG_LSF_SPHERES) {
-        double best = 0.0;
-        for (int m = 0; m < S.lsf_n; m++) {
-            double ex = x[0] - p[4 * m], ey = x[1] - p[4 * m + 1];
-            double r2 = ex * ex + ey * ey;
-            if (S.D == 3) {
-                double ez = x[2] - p[4 * m + 2];
-                r2 = r2 + ez * ez;
-            }
-            double v = __dsqrt_rn(r2) - p[4 * m + 3];
-            if (m == 0 || v < best) best = v;
-        }
-        return best;
-    }
-    if (S.lsf_kind == OCTMG_LSF_CYLINDER_Z) {
-        double ex = x[0] - p[0], ey = x[1] - p[1];
-        return __dsqrt_rn(ex * ex + ey * ey) - p[2];
-    }
-    return 1.0;
-}
-
-__device__ inline double centre(const SetupLevel &S, int a, int gi) {
+__host__ __device__ inline double centre(const SetupLevel &S, int a, int gi) {
     return S.lo[a] + ((double)gi + 0.5) * S.dx;
 }
 
-__device__ inline void along(const double *a, const double *b, double t, double *x) {
+__host__ __device__ inline void along(const double *a, const double *b, double t, double *x) {
     for (int c = 0; c < 3; c++) x[c] = a[c] + t * (b[c] - a[c]);
 }
 
 // bisection on [0, thi] of a->b; sign test f(a) f(x) <= 0
-__device__ double bisect(const SetupLevel &S, const double *a, const double *b, double fa, double thi) {
+template <class F>
+__host__ __device__ double bisect(const SetupLevel &S, const F &f, const double *a, const double *b, double fa,
+                                  double thi) {
     double lo = 0.0, hi = thi, x[3];
     for (int it = 0; it < S.nbisect; it++) {
         double mid = 0.5 * (lo + hi);
         along(a, b, mid, x);
-        if (fa * lsf_dev(S, x) <= 0.0) hi = mid;
+        if (fa * f(x) <= 0.0) hi = mid;
         else lo = mid;
     }
     return 0.5 * (lo + hi);
@@ -126,19 +51,21 @@ __device__ double bisect(const SetupLevel &S, const double *a, const double *b, 
 
 // root of f on a->b (t in (0,1]); *hit = 0 when no bracket is found within
 // the golden-section evaluation budget
-__device__ double root_on_link(const SetupLevel &S, const double *a, const double *b, double fa, int *hit) {
+template <class F>
+__host__ __device__ double root_on_link(const SetupLevel &S, const F &f, const double *a, const double *b, double fa,
+                                        int *hit) {
     double x[3];
     *hit = 1;
-    if (fa * lsf_dev(S, b) <= 0.0) return bisect(S, a, b, fa, 1.0);
-    const double rho = 0.5 * (__dsqrt_rn(5.0) - 1.0);
+    if (fa * f(b) <= 0.0) return bisect(S, f, a, b, fa, 1.0);
+    const double rho = 0.5 * (sqrt_rn(5.0) - 1.0);
     double lo = 0.0, hi = 1.0;
     double t1 = hi - rho * (hi - lo), t2 = lo + rho * (hi - lo);
     along(a, b, t1, x);
-    double h1 = fa * lsf_dev(S, x);
-    if (h1 <= 0.0) return bisect(S, a, b, fa, t1);
+    double h1 = fa * f(x);
+    if (h1 <= 0.0) return bisect(S, f, a, b, fa, t1);
     along(a, b, t2, x);
-    double h2 = fa * lsf_dev(S, x);
-    if (h2 <= 0.0) return bisect(S, a, b, fa, t2);
+    double h2 = fa * f(x);
+    if (h2 <= 0.0) return bisect(S, f, a, b, fa, t2);
     for (int used = 2; used < S.ngolden; used++) {
         if (h1 < h2) {
             hi = t2;
@@ -146,16 +73,16 @@ __device__ double root_on_link(const SetupLevel &S, const double *a, const doubl
             h2 = h1;
             t1 = hi - rho * (hi - lo);
             along(a, b, t1, x);
-            h1 = fa * lsf_dev(S, x);
-            if (h1 <= 0.0) return bisect(S, a, b, fa, t1);
+            h1 = fa * f(x);
+            if (h1 <= 0.0) return bisect(S, f, a, b, fa, t1);
         } else {
             lo = t1;
             t1 = t2;
             h1 = h2;
             t2 = lo + rho * (hi - lo);
             along(a, b, t2, x);
-            h2 = fa * lsf_dev(S, x);
-            if (h2 <= 0.0) return bisect(S, a, b, fa, t2);
+            h2 = fa * f(x);
+            if (h2 <= 0.0) return bisect(S, f, a, b, fa, t2);
         }
     }
     *hit = 0;
@@ -163,8 +90,9 @@ __device__ double root_on_link(const SetupLevel &S, const double *a, const doubl
 }
 
 // Sec. 3.6.3: descent with step w_min towards f = 0, then a line search a->x.
-__device__ int unresolved_search(const SetupLevel &S, const double *a, double fa, double *dout, int *dir,
-                                 double *x0) {
+template <class F>
+__host__ __device__ int unresolved_search(const SetupLevel &S, const F &f, const double *a, double fa, double *dout,
+                                          int *dir, double *x0) {
     const double w = S.w_min;
     double x[3] = {a[0], a[1], a[2]};
     const double sgn = fa > 0.0 ? 1.0 : -1.0;
@@ -176,10 +104,10 @@ __device__ int unresolved_search(const SetupLevel &S, const double *a, double fa
             double xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
             xp[c] = x[c] + w;
             xm[c] = x[c] - w;
-            gr[c] = (lsf_dev(S, xp) - lsf_dev(S, xm)) / (2.0 * w);
+            gr[c] = (f(xp) - f(xm)) / (2.0 * w);
             n2 = n2 + gr[c] * gr[c];
         }
-        double nrm = __dsqrt_rn(n2);
+        double nrm = sqrt_rn(n2);
         if (!(nrm > 0.0)) break;
         bool leaves = false;
         for (int c = 0; c < S.D; c++) {
@@ -188,16 +116,16 @@ __device__ int unresolved_search(const SetupLevel &S, const double *a, double fa
             if (x[c] < S.lo[c] || x[c] > S.lo[c] + 1.0) leaves = true;
         }
         if (leaves) break;
-        if (fa * lsf_dev(S, x) <= 0.0) {
+        if (fa * f(x) <= 0.0) {
             hit = 1;
             break;
         }
     }
     if (!hit) return 0;
-    double t = bisect(S, a, x, fa, 1.0), p[3], s2 = 0.0;
+    double t = bisect(S, f, a, x, fa, 1.0), p[3], s2 = 0.0;
     along(a, x, t, p);
     for (int c = 0; c < S.D; c++) s2 = s2 + (p[c] - a[c]) * (p[c] - a[c]);
-    double d = __dsqrt_rn(s2) / S.dx;
+    double d = sqrt_rn(s2) / S.dx;
     if (!(d < 1.0)) return 0;
     double best = -1.0;
     int k = 0;
@@ -219,32 +147,33 @@ struct CellSetup {
 };
 
 // returns 1 if the cell carries a custom stencil (at least one cut link)
-__device__ int analyse_cell(const SetupLevel &S, int blk, int li, CellSetup &R) {
+template <class F>
+__host__ __device__ int analyse_cell(const SetupLevel &S, const F &f, int blk, int li, CellSetup &R) {
     const int4 p = S.pos[blk];
     int l[3] = {li % S.Nb, (li / S.Nb) % S.Nb, S.D == 3 ? li / (S.Nb * S.Nb) : 0};
     int g[3] = {p.x * S.Nb + l[0], p.y * S.Nb + l[1], S.D == 3 ? p.z * S.Nb + l[2] : 0};
     double a[3] = {0.0, 0.0, 0.0};
     for (int c = 0; c < S.D; c++) a[c] = centre(S, c, g[c]);
-    const double fa = lsf_dev(S, a);
+    const double fa = f(a);
     double n2 = 0.0;
     for (int c = 0; c < S.D; c++) {
         double xp[3] = {a[0], a[1], a[2]}, xm[3] = {a[0], a[1], a[2]};
         xp[c] = centre(S, c, g[c] + 1);
         xm[c] = centre(S, c, g[c] - 1);
-        double gc = (lsf_dev(S, xp) - lsf_dev(S, xm)) / (2.0 * S.dx);
+        double gc = (f(xp) - f(xm)) / (2.0 * S.dx);
         n2 = n2 + gc * gc;
     }
     R.cut = 0;
     R.inside = fa < 0.0;
     for (int k = 0; k < 6; k++) R.d[k] = 1.0;
-    if (!(fabs(fa) < S.mask_L * __dsqrt_rn(n2))) return 0;
+    if (!(fabs(fa) < S.mask_L * sqrt_rn(n2))) return 0;
     for (int k = 0; k < 2 * S.D; k++) {
         const int ax = k >> 1, s = (k & 1) ? 1 : -1;
         if (g[ax] + s < 0 || g[ax] + s >= S.n) continue;  // links leaving the domain
         double b[3] = {a[0], a[1], a[2]};
         b[ax] = centre(S, ax, g[ax] + s);
         int hit;
-        double t = root_on_link(S, a, b, fa, &hit);
+        double t = root_on_link(S, f, a, b, fa, &hit);
         if (hit) {
             R.d[k] = t;
             R.cut |= 1 << k;
@@ -254,7 +183,7 @@ __device__ int analyse_cell(const SetupLevel &S, int blk, int li, CellSetup &R) 
     if (!R.cut && !S.leaf[blk] && S.w_min > 0.0 && S.dx > S.w_min) {
         double d, x0[3];
         int k;
-        if (unresolved_search(S, a, fa, &d, &k, x0)) {
+        if (unresolved_search(S, f, a, fa, &d, &k, x0)) {
             R.d[k] = d;
             R.cut = 1 << k;
             for (int c = 0; c < 3; c++) R.x0[k][c] = x0[c];
@@ -263,10 +192,58 @@ __device__ int analyse_cell(const SetupLevel &S, int blk, int li, CellSetup &R) 
     return R.cut != 0;
 }
 
-__device__ inline int split_index(int D, int N, int li) {
+__host__ __device__ inline int split_index(int D, int N, int li) {
     const int i = li % N, j = (li / N) % N, k = D == 3 ? li / (N * N) : 0;
     const int half = (D == 3 ? N * N * N : N * N) / 2;
     return ((i + j + k) & 1) * half + (k * N + j) * (N / 2) + (i >> 1);
+}
+
+// Output arrays of the record pass (device or host memory).
+struct EmitOut {
+    const int *map_off;
+    int *map, *meta;
+    double *d6, *cfull, *rec8;
+    float *rec8f;
+    double *pts;
+    int *inside;
+};
+
+// The stencil of eqs. (lpl-1d-lsf)/(lpl-2d-lsf) of one analysed cell as
+// record r with its cut-link points from slot q on; returns the next slot.
+__host__ __device__ int emit_cell(const SetupLevel &S, const CellSetup &R, int blk, int li, int r, int q,
+                                  const EmitOut &o) {
+    const double dx2 = S.dx * S.dx;
+    double c[6] = {0, 0, 0, 0, 0, 0}, diag = 0.0;
+    for (int ax = 0; ax < S.D; ax++) {
+        double dm = R.d[2 * ax], dp = R.d[2 * ax + 1];
+        c[2 * ax] = 2.0 / ((dm + dp) * dm * dx2);
+        c[2 * ax + 1] = 2.0 / ((dm + dp) * dp * dx2);
+        diag = diag - c[2 * ax] - c[2 * ax + 1];
+    }
+    const int si = split_index(S.D, S.Nb, li);
+    o.meta[4 * r + 0] = blk;
+    o.meta[4 * r + 1] = si;
+    o.meta[4 * r + 2] = R.cut;
+    o.meta[4 * r + 3] = q;
+    o.inside[r] = R.inside;
+    for (int k = 0; k < 6; k++) {
+        o.d6[6 * r + k] = R.d[k];
+        o.cfull[6 * r + k] = c[k];
+        double hot = (R.cut >> k & 1) ? 0.0 : c[k];
+        o.rec8[8 * r + k] = hot;
+        o.rec8f[8 * r + k] = (float)hot;
+    }
+    o.rec8[8 * r + 6] = diag;
+    o.rec8[8 * r + 7] = 1.0 / diag;
+    o.rec8f[8 * r + 6] = (float)diag;
+    o.rec8f[8 * r + 7] = (float)(1.0 / diag);
+    o.map[o.map_off[blk] + si] = r;
+    for (int k = 0; k < 2 * S.D; k++) {
+        if (!(R.cut >> k & 1)) continue;
+        for (int cc = 0; cc < 3; cc++) o.pts[3 * q + cc] = R.x0[k][cc];
+        q++;
+    }
+    return q;
 }
 
 constexpr int kSetupThreads = 256;
@@ -274,12 +251,13 @@ constexpr int kSetupThreads = 256;
 __global__ __launch_bounds__(kSetupThreads) void k_setup_count(SetupLevel S, int *counts) {
     const int blk = S.blocks ? S.blocks[blockIdx.x] : (int)blockIdx.x;
     const int cpb = S.D == 3 ? S.Nb * S.Nb * S.Nb : S.Nb * S.Nb;
+    const Lsf f = lsf_of(S);
     int nrec = 0, npt = 0;
     CellSetup R;
     for (int li = threadIdx.x; li < cpb; li += blockDim.x) {
-        if (analyse_cell(S, blk, li, R)) {
+        if (analyse_cell(S, f, blk, li, R)) {
             nrec++;
-            npt += __popc(R.cut);
+            npt += __builtin_popcount(R.cut);
         }
     }
     __shared__ int sr[kSetupThreads], sp[kSetupThreads];
@@ -302,20 +280,19 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup_count(SetupLevel S, int
 // Records of a block in canonical (x-fastest) cell order: thread t owns the
 // contiguous cells [t*chunk, (t+1)*chunk); an exclusive scan over threads
 // gives every thread its first record and point slot.
-__global__ __launch_bounds__(kSetupThreads) void k_setup_emit(SetupLevel S, const int *rec_off,
-                                                               const int *pt_off, const int *map_off, int *map,
-                                                               int *meta, double *d6, double *cfull, double *rec8,
-                                                               float *rec8f, double *pts, int *inside) {
+__global__ __launch_bounds__(kSetupThreads) void k_setup_emit(SetupLevel S, const int *rec_off, const int *pt_off,
+                                                               EmitOut o) {
     const int blk = S.blocks ? S.blocks[blockIdx.x] : (int)blockIdx.x;
     const int cpb = S.D == 3 ? S.Nb * S.Nb * S.Nb : S.Nb * S.Nb;
     const int chunk = (cpb + blockDim.x - 1) / blockDim.x;
     const int c0 = threadIdx.x * chunk, c1 = min(cpb, c0 + chunk);
+    const Lsf f = lsf_of(S);
     CellSetup R;
     int nrec = 0, npt = 0;
     for (int li = c0; li < c1; li++)
-        if (analyse_cell(S, blk, li, R)) {
+        if (analyse_cell(S, f, blk, li, R)) {
             nrec++;
-            npt += __popc(R.cut);
+            npt += __builtin_popcount(R.cut);
         }
     __shared__ int sr[kSetupThreads], sp[kSetupThreads];
     sr[threadIdx.x] = nrec;
@@ -334,39 +311,9 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup_emit(SetupLevel S, cons
     __syncthreads();
     int r = rec_off[blk] + sr[threadIdx.x];
     int q = pt_off[blk] + sp[threadIdx.x];
-    const double dx2 = S.dx * S.dx;
     for (int li = c0; li < c1; li++) {
-        if (!analyse_cell(S, blk, li, R)) continue;
-        double c[6] = {0, 0, 0, 0, 0, 0}, diag = 0.0;
-        for (int ax = 0; ax < S.D; ax++) {
-            double dm = R.d[2 * ax], dp = R.d[2 * ax + 1];
-            c[2 * ax] = 2.0 / ((dm + dp) * dm * dx2);
-            c[2 * ax + 1] = 2.0 / ((dm + dp) * dp * dx2);
-            diag = diag - c[2 * ax] - c[2 * ax + 1];
-        }
-        const int si = split_index(S.D, S.Nb, li);
-        meta[4 * r + 0] = blk;
-        meta[4 * r + 1] = si;
-        meta[4 * r + 2] = R.cut;
-        meta[4 * r + 3] = q;
-        inside[r] = R.inside;
-        for (int k = 0; k < 6; k++) {
-            d6[6 * r + k] = R.d[k];
-            cfull[6 * r + k] = c[k];
-            double hot = (R.cut >> k & 1) ? 0.0 : c[k];
-            rec8[8 * r + k] = hot;
-            rec8f[8 * r + k] = (float)hot;
-        }
-        rec8[8 * r + 6] = diag;
-        rec8[8 * r + 7] = 1.0 / diag;
-        rec8f[8 * r + 6] = (float)diag;
-        rec8f[8 * r + 7] = (float)(1.0 / diag);
-        map[map_off[blk] + si] = r;
-        for (int k = 0; k < 2 * S.D; k++) {
-            if (!(R.cut >> k & 1)) continue;
-            for (int cc = 0; cc < 3; cc++) pts[3 * q + cc] = R.x0[k][cc];
-            q++;
-        }
+        if (!analyse_cell(S, f, blk, li, R)) continue;
+        q = emit_cell(S, R, blk, li, r, q, o);
         r++;
     }
 }
@@ -518,9 +465,48 @@ hipError_t launch_setup_emit(const SetupLevel &S, const int *rec_off, const int 
     if (S.nblocks == 0) return hipSuccess;
     const int grid = S.blocks ? S.nlist : S.nblocks;
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_setup_emit, dim3(grid), dim3(kSetupThreads), 0, s, S, rec_off, pt_off, map_off, map,
-                       meta, d6, cfull, rec8, rec8f, pts, inside);
+    const EmitOut o{map_off, map, meta, d6, cfull, rec8, rec8f, pts, inside};
+    hipLaunchKernelGGL(k_setup_emit, dim3(grid), dim3(kSetupThreads), 0, s, S, rec_off, pt_off, o);
     return hipGetLastError();
+}
+
+// Host passes for a level set given as a host function: the same cell
+// analysis and records as k_setup_count / k_setup_emit, one cell after the
+// other on the calling thread, into host arrays.
+void host_setup_count(const SetupLevel &S, int *counts) {
+    const int cpb = S.D == 3 ? S.Nb * S.Nb * S.Nb : S.Nb * S.Nb;
+    const Lsf f = lsf_of(S);
+    const int nb = S.blocks ? S.nlist : S.nblocks;
+    CellSetup R;
+    for (int i = 0; i < nb; i++) {
+        const int blk = S.blocks ? S.blocks[i] : i;
+        int nrec = 0, npt = 0;
+        for (int li = 0; li < cpb; li++)
+            if (analyse_cell(S, f, blk, li, R)) {
+                nrec++;
+                npt += __builtin_popcount(R.cut);
+            }
+        counts[2 * blk] = nrec;
+        counts[2 * blk + 1] = npt;
+    }
+}
+
+void host_setup_emit(const SetupLevel &S, const int *rec_off, const int *pt_off, const int *map_off, int *map,
+                     int *meta, double *d6, double *cfull, double *rec8, float *rec8f, double *pts, int *inside) {
+    const int cpb = S.D == 3 ? S.Nb * S.Nb * S.Nb : S.Nb * S.Nb;
+    const Lsf f = lsf_of(S);
+    const EmitOut o{map_off, map, meta, d6, cfull, rec8, rec8f, pts, inside};
+    const int nb = S.blocks ? S.nlist : S.nblocks;
+    CellSetup R;
+    for (int i = 0; i < nb; i++) {
+        const int blk = S.blocks ? S.blocks[i] : i;
+        int r = rec_off[blk], q = pt_off[blk];
+        for (int li = 0; li < cpb; li++) {
+            if (!analyse_cell(S, f, blk, li, R)) continue;
+            q = emit_cell(S, R, blk, li, r, q, o);
+            r++;
+        }
+    }
 }
 
 hipError_t launch_reuse_records(const ReuseBlock *list, int nlist, int cpb, const ReuseArrays &o,

@@ -7,93 +7,13 @@
 #include <cmath>
 #include <cstring>
 
+#include "lsf.hpp"
 #include "octmg_internal.hpp"
 
 namespace octmg {
 
-// cube root of a >= 0 with + - * / only (the device setup uses the same
-// steps, so refinement and interface decisions agree bit for bit)
-static double cbrt_ops_host(double a) {
-    if (!(a > 0.0)) return 0.0;
-    int k = 0;
-    double m = a;
-    while (m >= 1.0) {
-        m = m * 0.125;
-        ++k;
-    }
-    while (m < 0.125) {
-        m = m * 8.0;
-        --k;
-    }
-    double t = 0.75;
-    for (int it = 0; it < 6; ++it) t = (2.0 * t + m / (t * t)) / 3.0;
-    for (; k > 0; --k) t = t * 2.0;
-    for (; k < 0; ++k) t = t * 0.5;
-    return t;
-}
-
 double lsf_host(const octmg_geom_desc &d, const double *p, const double *x) {
-    if (d.lsf_kind == OCTMG_LSF_ELECTRODES) {
-        double ab[3], t = 0.0, ll = 0.0;
-        for (int c = 0; c < 3; ++c) {
-            ab[c] = p[3 + c] - p[c];
-            t += (x[c] - p[c]) * ab[c];
-            ll += ab[c] * ab[c];
-        }
-        t = t / ll;
-        t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-        double d2 = 0.0, s2 = 0.0;
-        for (int c = 0; c < 3; ++c) {
-            const double e = x[c] - (p[c] + t * ab[c]), f = x[c] - p[7 + c];
-            d2 += e * e;
-            s2 += f * f;
-        }
-        const double rod = std::sqrt(d2) - p[6], sph = std::sqrt(s2) - p[10];
-        return rod < sph ? rod : sph;
-    }
-    if (d.lsf_kind >= OCTMG_LSF_SPHEROID && d.lsf_kind <= OCTMG_LSF_ASTROID) {
-        double a, b;
-        if (d.dim == 2) {
-            a = p[3] * (x[0] - p[0]);
-            b = p[3] * (x[1] - p[1]);
-        } else {
-            const double ex = x[0] - p[0], ey = x[1] - p[1];
-            a = p[3] * std::sqrt(ex * ex + ey * ey);
-            b = p[3] * (x[2] - p[2]);
-        }
-        switch (d.lsf_kind) {
-            case OCTMG_LSF_SPHEROID: return std::sqrt(8.0 * a * a + b * b) - 1.0;
-            case OCTMG_LSF_RHOMBUS: return 8.0 * std::fabs(a) + std::fabs(b) - 1.5;
-            case OCTMG_LSF_HEART: {
-                const double h = b - cbrt_ops_host(a * a);
-                return a * a + h * h - 1.0;
-            }
-            default: return cbrt_ops_host(a * a) / 0.8 + cbrt_ops_host(b * b) / 1.5 - 0.8;
-        }
-    }
-    switch (d.lsf_kind) {
-        case OCTMG_LSF_SPHERES: {
-            double best = 0.0;
-            for (int m = 0; m < d.lsf_n; m++) {
-                const double *s = p + 4 * m;
-                double ex = x[0] - s[0], ey = x[1] - s[1];
-                double r2 = ex * ex + ey * ey;
-                if (d.dim == 3) {
-                    double ez = x[2] - s[2];
-                    r2 = r2 + ez * ez;
-                }
-                double v = std::sqrt(r2) - s[3];
-                if (m == 0 || v < best) best = v;
-            }
-            return best;
-        }
-        case OCTMG_LSF_CYLINDER_Z: {
-            double ex = x[0] - p[0], ey = x[1] - p[1];
-            return std::sqrt(ex * ex + ey * ey) - p[2];
-        }
-        default:
-            return 1.0;
-    }
+    return Lsf{d.lsf_kind, d.lsf_n, d.dim, p, d.lsf_fn, d.lsf_user}(x);
 }
 
 namespace {
@@ -136,7 +56,8 @@ bool check_desc(const octmg_geom_desc &d, std::string *err) {
     if (lmax < 1 || lmax > 14) { *err = "max_level out of range"; return false; }
     if (d.lsf_kind == OCTMG_LSF_SPHERES && (d.lsf_n < 1 || !d.lsf_params)) { *err = "spheres need lsf_n >= 1 and params"; return false; }
     if (d.lsf_kind == OCTMG_LSF_CYLINDER_Z && !d.lsf_params) { *err = "cylinder needs params"; return false; }
-    if (d.lsf_kind < OCTMG_LSF_NONE || d.lsf_kind > OCTMG_LSF_ELECTRODES) { *err = "unknown lsf_kind"; return false; }
+    if (d.lsf_kind < OCTMG_LSF_NONE || d.lsf_kind > OCTMG_LSF_CALLBACK) { *err = "unknown lsf_kind"; return false; }
+    if (d.lsf_kind == OCTMG_LSF_CALLBACK && !d.lsf_fn) { *err = "a callback level set needs lsf_fn"; return false; }
     if (d.lsf_kind == OCTMG_LSF_ELECTRODES && d.dim != 3) { *err = "the electrode level set is 3D"; return false; }
     if (d.refine_kind != OCTMG_REFINE_UNIFORM && d.refine_kind != OCTMG_REFINE_NEAR_INTERFACE) { *err = "unknown refine_kind"; return false; }
     if ((long)N << (lmax - 1) > (1L << 15)) { *err = "grid too large"; return false; }

@@ -8,8 +8,11 @@ passed by pointer (``tensor.data_ptr()``, ``torch.cuda.current_stream()``).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -19,8 +22,12 @@ LIB_PATH = os.path.join(_HERE, "liboctmg.so")
 OK = 0
 ERR_INVALID, ERR_OOM, ERR_HIP, ERR_NOT_CONVERGED, ERR_NONFINITE, ERR_GEOMETRY, ERR_BUDGET = -1, -2, -3, -4, -5, -6, -7
 LSF_NONE, LSF_SPHERES, LSF_CYLINDER_Z = 0, 1, 2
+LSF_CALLBACK = 8
+# double f(const double *x, void *user): a level set given as a host function
+LSF_FN = C.CFUNCTYPE(C.c_double, C.POINTER(C.c_double), C.c_void_p)
 REFINE_UNIFORM, REFINE_NEAR_INTERFACE = 0, 1
 FP64, MIXED = 0, 1
+DTYPE_F64, DTYPE_F32 = 0, 1
 CYCLE_V, CYCLE_FMG = 0, 1
 FIELD_PHI, FIELD_G, FIELD_OLD = 0, 1, 2
 STEP_HALF_SWEEP, STEP_SMOOTH, STEP_RESTRICT_FAS, STEP_PROLONG, STEP_COARSE_SOLVE, STEP_RESTRICT_RHS = range(6)
@@ -37,7 +44,7 @@ class GeomDesc(C.Structure):
                 ("lsf_kind", C.c_int), ("lsf_n", C.c_int), ("coarse_n", C.c_int), ("neumann_faces", C.c_int),
                 ("refine_width", C.c_double), ("eps_tol", C.c_double), ("mask_factor", C.c_double),
                 ("w_min", C.c_double), ("lo", C.c_double * 3), ("lsf_params", C.POINTER(C.c_double)),
-                ("uniform_level", C.c_int), ("reserved", C.c_int)]
+                ("uniform_level", C.c_int), ("reserved", C.c_int), ("lsf_fn", LSF_FN), ("lsf_user", C.c_void_p)]
 
 
 class SolveOpts(C.Structure):
@@ -55,7 +62,8 @@ class LaunchConfig(C.Structure):
 
 class SolveReport(C.Structure):
     _fields_ = [("cycles", C.c_int), ("status", C.c_int), ("r0", C.c_double), ("r_final", C.c_double),
-                ("history", C.c_double * 64)]
+                ("history", C.c_double * 64), ("rhs_status", C.POINTER(C.c_int)), ("rhs_cycles", C.POINTER(C.c_int)),
+                ("rhs_r0", C.POINTER(C.c_double)), ("rhs_r_final", C.POINTER(C.c_double))]
 
 
 class ServerOpts(C.Structure):
@@ -95,9 +103,9 @@ _SIGS = {
     "octmg_state_set_smoothing": (C.c_int, [_vp, C.c_int, C.c_int]),
     "octmg_state_set_fused_levels": (C.c_int, [_vp, C.c_int]),
     "octmg_set_boundary": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp]),
-    "octmg_set_rhs": (C.c_int, [_vp, _vp, C.c_int, _vp]),
-    "octmg_set_solution": (C.c_int, [_vp, _vp, C.c_int, _vp]),
-    "octmg_get_solution": (C.c_int, [_vp, _vp, C.c_int, _vp]),
+    "octmg_set_rhs": (C.c_int, [_vp, _vp, C.c_int, C.c_int, _vp]),
+    "octmg_set_solution": (C.c_int, [_vp, _vp, C.c_int, C.c_int, _vp]),
+    "octmg_get_solution": (C.c_int, [_vp, _vp, C.c_int, C.c_int, _vp]),
     "octmg_zero_solution": (C.c_int, [_vp, _vp]),
     "octmg_cycle": (C.c_int, [_vp, C.c_int, C.c_int, _vp]),
     "octmg_residual_norm": (C.c_int, [_vp, C.c_int, _dp, _vp]),
@@ -123,6 +131,36 @@ _SIGS = {
 }
 
 
+# Handles still open.  At interpreter exit they are closed in dependency
+# order (servers, then states, then geometries) by an atexit hook registered
+# when the library loads, so that no library object -- a server's worker
+# thread, captured graphs, pinned host memory -- is still alive when the HIP
+# runtime tears itself down after Python has finished; __del__ does nothing
+# from then on.
+_live = weakref.WeakSet()
+_shutting_down = False
+
+
+def close_all():
+    """Close every open handle (servers, states, geometries)."""
+    for kind in (Server, State, Geometry):
+        for obj in [o for o in list(_live) if isinstance(o, kind)]:
+            try:
+                obj.close()
+            except Exception:
+                pass
+
+
+def _at_exit():
+    global _shutting_down
+    close_all()
+    _shutting_down = True
+
+
+def _finalizing() -> bool:
+    return _shutting_down or sys.is_finalizing()
+
+
 def lib():
     """The loaded library; raises if it has not been built."""
     global _lib
@@ -135,6 +173,7 @@ def lib():
             f.restype = res
             f.argtypes = args
         _lib = L
+        atexit.register(_at_exit)
     return _lib
 
 
@@ -151,8 +190,15 @@ def _ptr(a: np.ndarray, ctype):
     return a.ctypes.data_as(C.POINTER(ctype))
 
 
+def lsf_callback(f):
+    """C level-set callback from a Python function f(x, y, z) -> float
+    (keep the returned object alive as long as the geometry)."""
+    return LSF_FN(lambda x, user: float(f(x[0], x[1], x[2])))
+
+
 def make_desc(geom) -> GeomDesc:
-    """GeomDesc from a workloads.Geometry-like object (keeps params alive)."""
+    """GeomDesc from a workloads.Geometry-like object (keeps params and a
+    level-set callback ``geom.lsf_fn`` alive)."""
     params = np.ascontiguousarray(np.asarray(geom.lsf_params, dtype=np.float64).reshape(-1))
     if params.size == 0:
         params = np.zeros(1)
@@ -167,6 +213,11 @@ def make_desc(geom) -> GeomDesc:
         d.lo[i] = geom.lo[i]
     d.lsf_params = _ptr(params, C.c_double)
     d._keep = params
+    fn = getattr(geom, "lsf_fn", None)
+    if fn is not None:
+        cb = fn if isinstance(fn, LSF_FN) else lsf_callback(fn)
+        d.lsf_fn = cb
+        d._keep_fn = cb
     return d
 
 
@@ -209,6 +260,7 @@ class Geometry:
         else:
             h = _handle
         self._h = h
+        _live.add(self)
         self.device = device
         self._refresh()
 
@@ -221,7 +273,9 @@ class Geometry:
         h = _vp()
         stats = np.zeros(4, dtype=np.int64)
         _check(lib().octmg_geom_adapt(self._h, f.ctypes.data, int(reuse), C.byref(h), _ptr(stats, C.c_int64)))
-        return Geometry(self.geom, self.device, _handle=h), stats
+        out = Geometry(self.geom, self.device, _handle=h)
+        out._parent_desc = self.desc  # the adapted geometry calls the same level-set callback
+        return out, stats
 
     def leaf_blocks(self):
         """(level, x, y, z) of every leaf block in canonical order."""
@@ -244,7 +298,8 @@ class Geometry:
             self._h = None
 
     def __del__(self):
-        self.close()
+        if not _finalizing():
+            self.close()
 
     def level_info(self, level: int) -> dict:
         out = np.zeros(8, dtype=np.int64)
@@ -297,6 +352,7 @@ class State:
         h = _vp()
         _check(lib().octmg_state_create(geometry._h, n_rhs, precision, C.byref(h)))
         self._h = h
+        _live.add(self)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -304,7 +360,8 @@ class State:
             self._h = None
 
     def __del__(self):
-        self.close()
+        if not _finalizing():
+            self.close()
 
     def set_smoothing(self, n_down: int, n_up: int):
         _check(lib().octmg_state_set_smoothing(self._h, n_down, n_up))
@@ -356,25 +413,43 @@ class State:
         q = g.domain_points()
         self.set_boundary(iface_fn(p) if len(p) else None, domain_fn(q), stream)
 
+    def _typed(self, a, n):
+        """(pointer, dtype code, on_device, keepalive) for float64 or float32
+        numpy arrays and torch tensors; other host arrays become float64."""
+        if hasattr(a, "data_ptr"):
+            dt = str(a.dtype)
+            assert dt in ("torch.float64", "torch.float32") and a.is_contiguous() and a.numel() == n, (dt, a.numel())
+            return a.data_ptr(), DTYPE_F32 if dt == "torch.float32" else DTYPE_F64, int(a.is_cuda), a
+        a = np.asarray(a)
+        arr = np.ascontiguousarray(a, dtype=np.float32 if a.dtype == np.float32 else np.float64).reshape(-1)
+        assert arr.size == n, (arr.size, n)
+        return arr.ctypes.data, DTYPE_F32 if arr.dtype == np.float32 else DTYPE_F64, 0, arr
+
     def set_rhs(self, g, stream=None):
-        p, od, keep = self._arr(g, self.geometry.n_leaf * self.n_rhs)
-        _check(lib().octmg_set_rhs(self._h, p, od, _stream_ptr(stream)))
+        p, dt, od, keep = self._typed(g, self.geometry.n_leaf * self.n_rhs)
+        _check(lib().octmg_set_rhs(self._h, p, dt, od, _stream_ptr(stream)))
 
     def remap_from(self, other: "State", stream=None):
         """phi carried over from a state of the geometry this one was adapted from."""
         _check(lib().octmg_state_remap(other._h, self._h, _stream_ptr(stream)))
 
     def set_solution(self, phi, stream=None):
-        p, od, keep = self._arr(phi, self.geometry.n_leaf * self.n_rhs)
-        _check(lib().octmg_set_solution(self._h, p, od, _stream_ptr(stream)))
+        p, dt, od, keep = self._typed(phi, self.geometry.n_leaf * self.n_rhs)
+        _check(lib().octmg_set_solution(self._h, p, dt, od, _stream_ptr(stream)))
 
-    def get_solution(self, out=None, stream=None) -> np.ndarray:
+    def get_solution(self, out=None, stream=None, dtype=np.float64) -> np.ndarray:
+        """Leaf values of phi; into `out` (a float64/float32 numpy array or
+        tensor) if given, else a new host array of `dtype`."""
         n = self.geometry.n_leaf * self.n_rhs
-        if out is not None and hasattr(out, "data_ptr"):
-            _check(lib().octmg_get_solution(self._h, out.data_ptr(), int(out.is_cuda), _stream_ptr(stream)))
+        if out is not None:
+            p, dt, od, keep = self._typed(out, n)
+            if not od and keep is not out and keep.base is not out:
+                raise ValueError("out must be a contiguous float64 or float32 array")
+            _check(lib().octmg_get_solution(self._h, p, dt, od, _stream_ptr(stream)))
             return out
-        a = np.zeros(n)
-        _check(lib().octmg_get_solution(self._h, a.ctypes.data, 0, _stream_ptr(stream)))
+        a = np.zeros(n, dtype=np.float32 if np.dtype(dtype) == np.float32 else np.float64)
+        _check(lib().octmg_get_solution(self._h, a.ctypes.data, DTYPE_F32 if a.dtype == np.float32 else DTYPE_F64, 0,
+                                        _stream_ptr(stream)))
         return a.reshape(self.n_rhs, -1) if self.n_rhs > 1 else a
 
     def zero_solution(self, stream=None):
@@ -407,7 +482,12 @@ class State:
         o.cycle_kind, o.max_cycles, o.zero_start, o.rtol = kind, max_cycles, int(zero_start), rtol
         o.graph_mode = graph_mode
         rep = SolveReport()
+        per = {"status": np.zeros(self.n_rhs, dtype=np.int32), "cycles": np.zeros(self.n_rhs, dtype=np.int32),
+               "r0": np.zeros(self.n_rhs), "r_final": np.zeros(self.n_rhs)}
+        rep.rhs_status, rep.rhs_cycles = _ptr(per["status"], C.c_int), _ptr(per["cycles"], C.c_int)
+        rep.rhs_r0, rep.rhs_r_final = _ptr(per["r0"], C.c_double), _ptr(per["r_final"], C.c_double)
         st = lib().octmg_solve(self._h, C.byref(o), _stream_ptr(stream), C.byref(rep))
+        rep.per_rhs = per  # per right-hand side: status, cycles, r0, r_final
         if raise_on_fail:
             _check(st)
         return rep
@@ -461,6 +541,7 @@ class Server:
         h = C.c_void_p()
         _check(lib().octmg_server_create(device, C.byref(o), C.byref(h)))
         self._h = h
+        _live.add(self)
         self._geoms = []
         self._held = {}
 
@@ -499,13 +580,14 @@ class Server:
         return {k: getattr(st, k) for k, _ in ServerStats._fields_}
 
     def close(self):
-        if self._h:
+        if getattr(self, "_h", None):
             lib().octmg_server_destroy(self._h)
             self._h = None
             self._held.clear()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        if not _finalizing():
+            try:
+                self.close()
+            except Exception:
+                pass

@@ -70,11 +70,41 @@ def test_adaptive_plan_is_adaptive():
 
 
 @pytest.mark.parametrize("field,value", [("dim", 4), ("block_n", 12), ("max_level", 0), ("coarse_n", 4),
-                                         ("eps_tol", 0.0), ("lsf_kind", 8), ("neumann_faces", 64),
+                                         ("eps_tol", 0.0), ("lsf_kind", 9), ("lsf_kind", 8), ("neumann_faces", 64),
                                          ("uniform_level", 9)])
 def test_invalid_descriptor_rejected(field, value):
+    """lsf_kind 8 is OCTMG_LSF_CALLBACK, invalid without a function."""
     geom = W.mms3d(max_level=2).geom
     setattr(geom, field, value)
     with pytest.raises(octmg.OctmgError) as e:
         octmg.plan_levels(geom)
     assert e.value.status == octmg.ERR_INVALID
+
+
+def test_callback_tree_matches_builtin(orc):
+    """A level set given as a host function (OCTMG_LSF_CALLBACK) that
+    restates a built-in union of spheres gives the same refined tree as the
+    built-in kind and the oracle (the refinement test evaluates f at block
+    centres on the host)."""
+    import copy
+    import math
+    geom = GEOMS["spheres_amr16"]()
+    P = [float(v) for v in geom.lsf_params]
+    calls = [0]
+
+    def f(x, y, z):
+        calls[0] += 1
+        best = 0.0
+        for m in range(len(P) // 4):
+            ex, ey, ez = x - P[4 * m], y - P[4 * m + 1], z - P[4 * m + 2]
+            v = math.sqrt(ex * ex + ey * ey + ez * ez) - P[4 * m + 3]
+            if m == 0 or v < best:
+                best = v
+        return best
+    g = copy.copy(geom)
+    g.lsf_kind, g.lsf_fn = octmg.LSF_CALLBACK, f
+    plan_cb, plan = octmg.plan_levels(g), octmg.plan_levels(geom)
+    assert calls[0] > 0 and plan_cb == plan
+    for il in range(len(plan)):
+        a, b = octmg.plan_blocks(g, il), octmg.plan_blocks(geom, il)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])

@@ -143,8 +143,8 @@ def test_vcycle_parity_from_zero(orc):
 
 def test_solve_fp64_and_mixed(orc):
     """FP64 solve to 1e-10 matches the oracle iterate for iterate (same number
-    of cycles); the mixed-precision solve reaches the same relative residual
-    and its error against the FP64 oracle is reported."""
+    of cycles); the mixed-precision solve reaches the same relative residual,
+    and both lie within the residual bound of the converged oracle solution."""
     w = CONFIGS["mms3d_b16_64"]()
     o, G, S = make_pair(orc, w)
     rep = S.solve(rtol=1e-10, max_cycles=40)
@@ -157,11 +157,19 @@ def test_solve_fp64_and_mixed(orc):
     repm = Sm.solve(rtol=1e-10, max_cycles=40)
     assert repm.status == 0 and repm.r_final <= 1e-10 * repm.r0
     o.solve(rtol=1e-13, max_cycles=40)
-    conv = o.get_solution()
-    err_m = rel(Sm.get_solution(), conv)
-    err_d = rel(S.get_solution(), conv)
-    print(f"FP64 cycles {rep.cycles} err {err_d:.2e}; mixed cycles {repm.cycles} err {err_m:.2e} (vs converged FP64 oracle)")
-    assert err_m < 10 * err_d + 1e-9
+    conv, r_o = o.get_solution(), o.residual_max()
+    # both solve the same discrete system A phi = g - b up to their leaf
+    # residuals: |phi - phi*| <= |A^-1| (|r| + |r_o|).  |A^-1|_inf <= 1/6 on the
+    # unit cube with Dirichlet data by the discrete maximum principle: the
+    # comparison function w = (3/4 - |x - c|^2)/6 is >= 0 on every boundary,
+    # the interface stencils reproduce quadratics exactly (-L w = 1 there), and
+    # a domain ghost 2 w(face) - w(in) adds h^2/12 per face to the stencil sum,
+    # so -L w >= 1 - 3/12 = 3/4 everywhere and max w / (3/4) = 1/6
+    for name, phi in (("FP64", S.get_solution()), ("mixed", Sm.get_solution())):
+        r = float(np.abs(o.leaf_residual(phi)).max())
+        err = float(np.abs(phi - conv).max())
+        print(f"{name}: |err| vs converged oracle {err:.2e}, bound {(r + r_o) / 6:.2e}")
+        assert err <= (r + r_o) / 6.0, name
     xyz, _ = o.leaf_coords()
     ex = w.exact(xyz)
     assert abs(np.abs(Sm.get_solution() - ex).max() / np.abs(ref - ex).max() - 1.0) < 1e-2

@@ -123,3 +123,82 @@ def test_invalid_server_arguments():
     with pytest.raises(octmg.OctmgError):
         server.submit(3, np.zeros(8), np.zeros(8), 1e-8)
     server.close()
+
+
+def inverse_norm(orc, w):
+    """|A^-1 1|_inf from the oracle (A u = 1, zero boundary data): |A^-1|_inf
+    of the M-matrix operator of a uniform tree."""
+    o = orc.Oracle(w.geom)
+    o.set_boundary(np.zeros(len(o.iface_points())), np.zeros(len(o.domain_points())))
+    o.set_rhs(np.ones(o.n_leaf))
+    o.solve(rtol=1e-12, max_cycles=60)
+    return float(np.abs(o.get_solution()).max())
+
+
+@pytest.mark.parametrize("precision", [octmg.FP64, octmg.MIXED])
+def test_served_results_against_oracle(orc, precision):
+    """Each served result against the oracle's converged solution of the same
+    rhs: its residual, recomputed by the oracle, meets the request's rtol, and
+    |phi - phi*|_inf <= 2 |A^-1|_inf (|r_served| + |r_oracle|) (both solve the
+    same discrete system up to their residuals; factor 2 as margin)."""
+    print("served results vs oracle, precision", precision, flush=True)
+    geoms = [geometry(1, 500, 2), geometry(5, 501, 3)]
+    server = octmg.Server(max_lanes=4, precision=precision)
+    slots = [server.add_geometry(G, w.iface_value(G.iface_points()), w.domain_value(G.domain_points()))
+             for w, G in geoms]
+    reqs = []
+    for i in range(6):
+        k = i % 2
+        w, G = geoms[k]
+        xyz, _ = G.leaf_coords()
+        g = W.gaussian_sources(xyz, 10000 + i)
+        out = np.full(G.n_leaf, np.nan)
+        reqs.append((server.submit(slots[k], g, out, 1e-8), k, g, out))
+    got = wait_all(server, [r[0] for r in reqs])
+    server.close()
+    ora = []
+    for w, G in geoms:
+        o = orc.Oracle(w.geom)
+        o.set_boundary(w.iface_value(o.iface_points()), w.domain_value(o.domain_points()))
+        ora.append((o, inverse_norm(orc, w)))
+    for rid, k, g, out in reqs:
+        o, ainv = ora[k]
+        assert got[rid]["status"] == 0
+        o.set_rhs(g)
+        o.zero_solution()
+        r0, _ = o.solve(rtol=1e-13, max_cycles=60)
+        ref, r_o = o.get_solution(), o.residual_max()
+        r_s = float(np.abs(o.leaf_residual(out)).max())
+        assert r_s <= 1.01e-8 * r0, (rid, r_s, r0)
+        err = float(np.abs(out - ref).max())
+        bound = 2.0 * ainv * (r_s + r_o)
+        print(f"  request {rid}: cycles {got[rid]['cycles']}, |err| {err:.2e}, bound {bound:.2e}")
+        assert err <= bound, (rid, err, bound)
+
+
+def test_exit_with_open_handles():
+    """A program that ends with a server (worker thread running), states with
+    captured graphs and geometries still open exits cleanly: the binding
+    closes them before the interpreter and the HIP runtime shut down."""
+    import os
+    import subprocess
+    import sys
+    code = (
+        "import numpy as np\n"
+        "from paper_2205_09411_amd import octmg, workloads as W\n"
+        "w = W.spheres(n_spheres=1, max_level=2, block_n=16, seed=500, adaptive=False)\n"
+        "G = octmg.Geometry(w.geom)\n"
+        "S = octmg.State(G, 2, octmg.MIXED)\n"
+        "S.set_boundary_fn(w.iface_value, w.domain_value)\n"
+        "xyz, _ = G.leaf_coords()\n"
+        "S.set_rhs(np.stack([W.gaussian_sources(xyz, 1), W.gaussian_sources(xyz, 2)]))\n"
+        "S.solve(rtol=1e-8, zero_start=True, graph_mode=1)\n"
+        "srv = octmg.Server(max_lanes=2)\n"
+        "slot = srv.add_geometry(G, w.iface_value(G.iface_points()), w.domain_value(G.domain_points()))\n"
+        "out = np.zeros(G.n_leaf)\n"
+        "srv.submit(slot, W.gaussian_sources(xyz, 3), out, 1e-8)\n"
+        "print('exiting with open handles', flush=True)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=100)
+    assert r.returncode == 0, (r.returncode, r.stdout[-2000:], r.stderr[-2000:])
+    assert "exiting with open handles" in r.stdout
