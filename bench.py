@@ -94,6 +94,30 @@ def timed_solves(S, n, stream, **kw):
     return (time.perf_counter() - t) / n, reps[-1]
 
 
+# set by main(): compare results with the FP64 oracle (host CPU) after the GPU work
+ORACLE_CHECKS = True
+
+
+def vs_oracle(o, phi, r0, cycles=3):
+    """A GPU result against the FP64 oracle on the same problem: the oracle's
+    leaf residual of the result (relative to the residual of phi = 0), then
+    `cycles` of the oracle's own V-cycles started from the result, and the
+    max difference between the result and that oracle iterate.  The oracle's
+    residual after its cycles is reported too: when it is far below the
+    result's, the difference is the result's error against the converged
+    FP64 oracle solution."""
+    t = time.perf_counter()
+    r = float(np.abs(o.leaf_residual(phi)).max())  # also sets the oracle's phi to the result
+    for _ in range(cycles):
+        o.vcycle()
+    ref = o.get_solution()
+    err = float(np.abs(phi - ref).max())
+    return {"oracle_rel_residual_of_result": r / r0, "oracle_rel_residual_after": o.residual_max() / r0,
+            "oracle_cycles_from_result": cycles, "max_abs_diff_vs_oracle": err,
+            "rel_diff_vs_oracle": err / max(float(np.abs(ref).max()), 1e-300),
+            "oracle_s": round(time.perf_counter() - t, 1)}
+
+
 def rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
@@ -107,9 +131,13 @@ def leg_mixed(G, w, phi64, t64, stream, steps, rtol):
     S.set_rhs(w.rhs(xyz))
     dt, rep = timed_solves(S, steps, stream, rtol=rtol, max_cycles=40, graph_mode=1)
     phi = S.get_solution()
+    MIXED_PHI["phi"] = phi
     return {"solves_per_s": round(1 / dt, 3), "ms_per_solve": round(dt * 1e3, 3), "speedup_vs_fp64": round(t64 / dt, 3),
             "outer_iterations": rep.cycles, "final_rel_residual": rep.r_final / rep.r0,
             "rel_diff_vs_fp64_solution": rel(phi, phi64), "max_err_vs_exact": float(np.abs(phi - w.exact(xyz)).max())}
+
+
+MIXED_PHI = {}  # the mixed leg's solution, compared with the oracle at the end
 
 
 def leg_batched(stream, rtol, reps=3, n_single=4):
@@ -125,17 +153,29 @@ def leg_batched(stream, rtol, reps=3, n_single=4):
     out = {"workload": f"{w.geom.name}: 128^3 in 16^3 blocks ({G.n_blocks} blocks), 64 rhs, phi=0 on cylinder and cube",
            "cells_all_levels_per_rhs": int(sum(G.level_info(i)["nblocks"] * G.level_info(i)["Nb"] ** 3
                                               for i in range(G.n_levels)))}
-    sols = {}
+    sols, r0s = {}, {}
     for name, prec in (("mixed", octmg.MIXED), ("fp64", octmg.FP64)):
         S = octmg.State(G, 64, prec)
         S.set_boundary(None, np.zeros(G.n_domain))
         S.set_rhs(g)
-        tuned, cand_ms = S.autotune(rtol=rtol, reps=1, stream=stream)
-        dt, rep = timed_solves(S, reps, stream, rtol=rtol, max_cycles=40, graph_mode=tuned["graph_mode"])
+        # the cycle count of this batch, so that the whole-solve graph
+        # candidates capture one cycle more than it needs
+        first = S.solve(rtol=rtol, max_cycles=40, zero_start=True, stream=stream)
+        mc = first.cycles + 1
+        tuned, cand_ms = S.autotune(rtol=rtol, max_cycles=mc, reps=1, stream=stream)
+        dt, rep = timed_solves(S, reps, stream, rtol=rtol, max_cycles=mc, graph_mode=tuned["graph_mode"])
         sols[name] = S.get_solution()
+        r0s[name] = rep.per_rhs["r0"].copy()
+        # candidates 0..13 launch cycle by cycle, the last two are the whole
+        # solve as one captured graph (512- and 256-thread kernels)
+        one = min(cand_ms[-2:])
+        other = min(cand_ms[:-2])
         out[name] = {"batch_ms": round(dt * 1e3, 3), "rhs_solves_per_s": round(64 / dt, 2), "cycles": rep.cycles,
                      "final_rel_residual": rep.r_final / rep.r0,
-                     "launch": {"chosen": tuned, "autotune_ms_per_batch": [round(v, 3) for v in cand_ms]}}
+                     "launch": {"chosen": tuned, "autotune_ms_per_batch": [round(v, 3) for v in cand_ms],
+                                "whole_solve_graph_ms": round(one, 3), "best_per_cycle_launch_ms": round(other, 3),
+                                "winner": "whole-solve graph" if one < other else "per-cycle launches",
+                                "whole_solve_graph_vs_best_other": round(other / one, 3)}}
         del S
     S1 = octmg.State(G, 1, octmg.FP64)
     S1.set_boundary(None, np.zeros(G.n_domain))
@@ -150,6 +190,16 @@ def leg_batched(stream, rtol, reps=3, n_single=4):
                               "sample": f"first {n_single} rhs, one at a time"}
     out["batched_fp64_vs_single_max_rel_diff"] = d1
     out["mixed_vs_fp64_max_rel_diff"] = rel(sols["mixed"], sols["fp64"])
+    if ORACLE_CHECKS:
+        import oracle
+        o = oracle.Oracle(w.geom)
+        o.set_boundary(np.zeros(len(o.iface_points())), np.zeros(len(o.domain_points())))
+        chk = {}
+        for lane in (0, 63):
+            o.set_rhs(g[lane])
+            for name in ("mixed", "fp64"):
+                chk[f"{name}_lane{lane}"] = vs_oracle(o, sols[name][lane], float(r0s[name][lane]))
+        out["vs_oracle"] = chk
     out["speedup_mixed_batch_vs_single_fp64"] = round(out["mixed"]["rhs_solves_per_s"] /
                                                       out["single_rhs_fp64"]["rhs_solves_per_s"], 2)
     return out
@@ -175,11 +225,17 @@ def leg_adaptive(stream, rtol, reps=3):
         S.set_rhs(g)
         dt, rep = timed_solves(S, reps, stream, rtol=rtol, max_cycles=40, graph_mode=1)
         sols[name] = S.get_solution()
+        r0 = rep.r0
         out[name] = {"ms_per_solve": round(dt * 1e3, 3), "solves_per_s": round(1 / dt, 3), "cycles": rep.cycles,
                      "final_rel_residual": rep.r_final / rep.r0,
                      "leaf_cell_solves_per_s_G": round(G.n_leaf / dt / 1e9, 3)}
         del S
     out["mixed_vs_fp64_max_rel_diff"] = rel(sols["mixed"], sols["fp64"])
+    if ORACLE_CHECKS:
+        import oracle
+        del G
+        o = oracle.setup_workload(w)
+        out["vs_oracle"] = {name: vs_oracle(o, sols[name], r0, cycles=2) for name in ("fp64", "mixed")}
     return out
 
 
@@ -496,10 +552,9 @@ def leg_2d(stream, steps=20):
             "max_err_vs_exact": float(np.abs(S.get_solution() - w.exact(xyz)).max())}
 
 
-def cpu_baseline(w, n_cycles):
-    import oracle
+def cpu_baseline(o, w, n_cycles):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    o = oracle.setup_workload(w)
+    o.zero_solution()
     o.vcycle()  # warm
     levels = [o.level_info(i) for i in range(o.n_levels)]
     t0 = time.perf_counter()
@@ -521,6 +576,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--cpu-cycles", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle", action="store_true",
+                    help="skip the comparisons of the results with the FP64 oracle (host CPU)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--block-order", type=int, default=None,
                     help="with --no-tune: block order of the 3D kernels (0 XCD ranges, 1 hardware, 2 octant walk)")
@@ -533,6 +590,8 @@ def main():
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
+    global ORACLE_CHECKS
+    ORACLE_CHECKS = not args.no_oracle
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is not built",
                           "n_gpus": args.gpus}))
@@ -675,8 +734,18 @@ def main():
         torch.cuda.empty_cache()
     if legs:
         out["legs"] = legs
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_cycles)
+    if ORACLE_CHECKS or not args.no_cpu_baseline:
+        import oracle
+        o = oracle.setup_workload(w)
+        if ORACLE_CHECKS:
+            r0 = reps[-1].r0
+            out["vs_oracle"] = {"fp64": vs_oracle(o, phi, r0)}
+            if "phi" in MIXED_PHI:
+                legs["mixed"]["vs_oracle"] = vs_oracle(o, MIXED_PHI["phi"], r0)
+            print("oracle comparisons done", file=sys.stderr, flush=True)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(o, w, args.cpu_cycles)
+        del o
     print(json.dumps(out), flush=True)
     octmg.close_all()  # release every device object before the interpreter exits
 

@@ -315,10 +315,12 @@ octmg_status octmg_solve(octmg_state s, const octmg_solve_opts *opts, void *stre
  * block orders x {separate, separate in a per-cycle graph, cooperative
  * bottom up to 8 and to 64 blocks (3D)}, with the 512-thread variants on
  * every level, plus block order 0 {separate, per-cycle graph} with them on
- * none), then keeps the fastest in the
- * state and returns it.  ms[i] (if not NULL, room for 14) receives the mean wall time
- * per solve of candidate i, *n_candidates their number.  Afterwards phi
- * holds the solution (the same under every candidate). */
+ * none (3D), plus block order 0 with the whole solve captured as one graph
+ * (graph_mode 2; opts.max_cycles cycles are captured) with the 512-thread
+ * variants on every level and (3D) on none), then keeps the fastest in the
+ * state and returns it.  ms[i] (if not NULL, room for 16) receives the mean
+ * wall time per solve of candidate i, *n_candidates their number.
+ * Afterwards phi holds the solution (the same under every candidate). */
 octmg_status octmg_autotune(octmg_state s, const octmg_solve_opts *opts, int reps, void *stream,
                             octmg_launch_config *best, double *ms, int *n_candidates);
 

@@ -1782,6 +1782,10 @@ octmg_status octmg_autotune(octmg_state s, const octmg_solve_opts *o, int reps, 
         cand.push_back({0, 0, 0, 0, 0});
         cand.push_back({0, 0, 0, 1, 0});
     }
+    // the whole solve as one captured launch (max_cycles cycles, convergence
+    // tested on the device), with the 512- and the 256-thread kernels
+    cand.push_back({0, 0, 0, 2, all});
+    if (s->geom->tree.D == 3) cand.push_back({0, 0, 0, 2, 0});
     if (n_candidates) *n_candidates = (int)cand.size();
     double best_ms = 0.0;
     int best_i = -1;

@@ -377,11 +377,12 @@ class State:
 
     def autotune(self, rtol: float = 1e-10, max_cycles: int = 40, kind: int = CYCLE_V, reps: int = 2, stream=None):
         """Time every candidate launch configuration; keep and return the
-        fastest, with the per-candidate mean ms per solve."""
+        fastest, with the per-candidate mean ms per solve.  The whole-solve
+        graph candidates capture max_cycles cycles."""
         o = SolveOpts()
         o.cycle_kind, o.max_cycles, o.zero_start, o.rtol = kind, max_cycles, 1, rtol
         best = LaunchConfig()
-        ms = np.zeros(14)
+        ms = np.zeros(16)
         n = C.c_int()
         _check(lib().octmg_autotune(self._h, C.byref(o), reps, _stream_ptr(stream), C.byref(best),
                                     _ptr(ms, C.c_double), C.byref(n)))
