@@ -127,7 +127,7 @@ def test_launch_configurations_and_autotune_identical():
         assert np.array_equal(S.get_solution(), ref), c
     best, ms = S.autotune(rtol=1e-10, reps=1)
     print("autotune", best, ms, flush=True)
-    assert len(ms) == 14 and all(m > 0 for m in ms)
+    assert len(ms) == 16 and all(m > 0 for m in ms)
     assert S.get_launch() == best
     assert np.array_equal(S.get_solution(), ref)
     with pytest.raises(octmg.OctmgError):
