@@ -309,6 +309,28 @@ octmg_status octmg_residual_norm(octmg_state s, int phi_zero, double *out, void 
 /* Cycles until max|r| <= rtol * max|r(phi=0)| for every rhs. */
 octmg_status octmg_solve(octmg_state s, const octmg_solve_opts *opts, void *stream, octmg_solve_report *rep);
 
+/* For callers that cannot allocate device memory (work prepared for HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * octmg_solve for one right-hand side in FP64 from phi = 0, with every
+ * field of the solve (phi, rhs and FAS rhs, restricted values, boundary
+ * terms, norms, flags on all levels) in a fixed 64 MiB device array of the
+ * library instead of a state.  Each device the call runs on holds its own
+ * copy of the array until the process ends; the call allocates no device or
+ * pinned host memory.  rhs [n_leaf] (canonical leaf order), iface_vals
+ * [n_interface] and domain_vals [n_domain] (as octmg_set_boundary; NULL =
+ * zero) are device pointers on g's device, as is the output phi [n_leaf].
+ * opts as for octmg_solve except that graph_mode must be 0 and zero_start
+ * is implied; rep (may be NULL) as for octmg_solve with n_rhs = 1.
+ * Errors: OCTMG_ERR_INVALID when the geometry's fields do not fit the array
+ * (about 24 B per cell of every level: up to 128^3 cells in 16^3 blocks),
+ * OCTMG_ERR_NONFINITE for NaN/Inf input, OCTMG_ERR_NOT_CONVERGED (phi is
+ * still written).  All calls on one device share the array: calls that
+ * overlap on one device race and must be serialised by the caller; the
+ * array keeps the last call's values, and each call clears what it reads.
+ * Synchronises the stream. */
+octmg_status octmg_solve_noalloc(octmg_geom g, const double *rhs, const double *iface_vals, const double *domain_vals,
+                                 double *phi, const octmg_solve_opts *opts, void *stream, octmg_solve_report *rep);
+
 /* Autotuner: solves the state's current problem from phi = 0 (opts, with
  * zero_start and graph_mode taken from each candidate) once to warm up and
  * `reps` times timed, under every candidate launch configuration (the three

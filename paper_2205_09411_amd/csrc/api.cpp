@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -476,6 +477,11 @@ octmg_status clean_norm_slots(octmg_state s, hipStream_t st) {
 // the one-workgroup kernel that reduces the norm slots (cheaper than a copy
 // for a few bytes); called after residual_norm_dev or mixed_defect
 octmg_status read_norms(octmg_state s, double *out, hipStream_t st) {
+    if (!s->h_norm) {  // no mapped buffer (octmg_solve_noalloc): copy from d_norm
+        HIPCK(hipMemcpyAsync(out, s->d_norm, sizeof(double) * s->nrhs, hipMemcpyDeviceToHost, st));
+        HIPCK(hipStreamSynchronize(st));
+        return OCTMG_OK;
+    }
     HIPCK(hipStreamSynchronize(st));
     for (int r = 0; r < s->nrhs; r++) {
         const unsigned long long v = ((volatile unsigned long long *)s->h_norm)[r];
@@ -1561,11 +1567,14 @@ static long long graph_key(int mode, int kind, int max_cycles, int zero_start, i
     return ((((long long)mode * 8 + kind) * 128 + max_cycles) * 2 + zero_start) * 8192 + n_launch;
 }
 
-static void read_mapped(octmg_state s, std::vector<double> &out) {
+// after the stream has passed the norm kernel
+static octmg_status read_mapped(octmg_state s, std::vector<double> &out, hipStream_t st) {
+    if (!s->h_norm) return read_norms(s, out.data(), st);
     for (int r = 0; r < s->nrhs; r++) {
         const unsigned long long v = ((volatile unsigned long long *)s->h_norm)[r];
         std::memcpy(&out[r], &v, sizeof(double));
     }
+    return OCTMG_OK;
 }
 
 // Cycles until every right-hand side satisfies max|r| <= rtol * max|r(0)|.
@@ -1725,7 +1734,7 @@ static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStre
             STCK(cycle_and_norm(s, o->cycle_kind, have_guess ? 1 : 0, st));
         }
         HIPCK(hipStreamSynchronize(st));
-        read_mapped(s, rk);
+        STCK(read_mapped(s, rk, st));
         have_guess = true;
     }
     rp->status = OCTMG_ERR_NOT_CONVERGED;
@@ -1877,6 +1886,158 @@ octmg_status octmg_debug_step(octmg_state s, int step, int level, int arg, void 
     return OCTMG_OK;
 }
 
+// ------------------------------------------------- allocation-free solve
+// octmg_solve_noalloc keeps every field of its one-rhs FP64 solve in this
+// array of the library's device code, one copy per device, which lives as
+// long as the process.  Its address on a device is looked up once, with that
+// device current, and only that address is used from host code.
+constexpr size_t kNoallocBytes = size_t(64) << 20;
+constexpr int kNoallocMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[kNoallocMaxDevices] = {};
+
+// the current device's copy of `scratch`
+static octmg_status scratch_on(int dev, unsigned char **out) {
+    if (dev < 0 || dev >= kNoallocMaxDevices) return fail(OCTMG_ERR_INVALID, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(OCTMG_ERR_HIP, "no device address for the scratch array");
+        g_scratch_ptr[dev] = (unsigned char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return OCTMG_OK;
+}
+
+extern "C++" {
+// bump allocation of 256-byte aligned pieces of the scratch array
+struct ScratchCut {
+    uintptr_t base;
+    size_t used = 0;
+    template <typename T>
+    T *take(size_t n) {
+        T *p = (T *)(base + used);
+        used += (n * sizeof(T) + 255) / 256 * 256;
+        return p;
+    }
+};
+
+// bytes of the scratch array that a solve on g needs
+static size_t noalloc_bytes(octmg_geom g) {
+    ScratchCut c{0};
+    const int D = g->tree.D;
+    for (const GeomLevel &L : g->L) {
+        const size_t cells = (size_t)L.nblocks * L.cpb;
+        for (int f = 0; f < 3; f++) c.take<double>(cells);
+        c.take<double>(std::max(1, L.nrec));
+        c.take<double>((size_t)2 * D * L.nface);
+    }
+    c.take<unsigned long long>(1);
+    c.take<unsigned long long>((size_t)norm_slot_words(1));
+    c.take<int>(1);
+    c.take<int>(2);
+    return c.used;
+}
+}  // extern "C++"
+
+octmg_status octmg_solve_noalloc(octmg_geom g, const double *rhs, const double *iface_vals, const double *domain_vals,
+                                 double *phi, const octmg_solve_opts *o, void *stream, octmg_solve_report *rep) {
+    if (!g || !rhs || !phi || !o) return fail(OCTMG_ERR_INVALID, "null argument");
+    if (!(o->rtol > 0.0) || o->max_cycles < 1 || o->max_cycles > 64) return fail(OCTMG_ERR_INVALID, "bad options");
+    if (o->cycle_kind != OCTMG_CYCLE_V && o->cycle_kind != OCTMG_CYCLE_FMG) return fail(OCTMG_ERR_INVALID, "bad cycle kind");
+    if (o->graph_mode != 0) return fail(OCTMG_ERR_INVALID, "octmg_solve_noalloc launches eagerly: graph_mode must be 0");
+    const size_t need = noalloc_bytes(g);
+    if (need > kNoallocBytes)
+        return fail(OCTMG_ERR_INVALID, "geometry too large for octmg_solve_noalloc: its fields need " +
+                                           std::to_string(need) + " bytes, the scratch array holds " +
+                                           std::to_string(kNoallocBytes));
+    hipStream_t st = (hipStream_t)stream;
+    HIPCK(hipSetDevice(g->device));
+    unsigned char *base = nullptr;
+    STCK(scratch_on(g->device, &base));
+
+    // a one-rhs FP64 state whose device memory is all in the scratch array
+    octmg_state_s s;
+    s.geom = g;
+    const int nlev = (int)g->L.size(), D = g->tree.D;
+    s.f64.resize(nlev);
+    s.stride.resize(nlev);
+    ScratchCut c{(uintptr_t)base};
+    for (int il = 0; il < nlev; il++) {
+        const GeomLevel &L = g->L[il];
+        const long long cells = (long long)L.nblocks * L.cpb;
+        s.stride[il] = cells;
+        Fields64 &F = s.f64[il];
+        F.phi = c.take<double>(cells);
+        F.g = c.take<double>(cells);
+        F.old = c.take<double>(cells);
+        F.b = c.take<double>(std::max(1, L.nrec));
+        F.bcv = c.take<double>((size_t)2 * D * L.nface);
+    }
+    s.d_norm = c.take<unsigned long long>(1);
+    s.d_norm_slots = c.take<unsigned long long>((size_t)norm_slot_words(1));
+    s.d_flag = c.take<int>(1);
+    s.d_active = c.take<int>(2);
+    s.h_norm_dev = s.d_norm;  // no mapped host buffer: norms are copied back
+    s.norm_slots_clean = false;
+
+    // every field starts at zero, as in a new state (the array keeps the
+    // previous call's values)
+    for (int il = 0; il < nlev; il++) {
+        const GeomLevel &L = g->L[il];
+        Fields64 &F = s.f64[il];
+        HIPCK(launch_fill(F.phi, s.stride[il], 0.0, st));
+        HIPCK(launch_fill(F.g, s.stride[il], 0.0, st));
+        HIPCK(launch_fill(F.old, s.stride[il], 0.0, st));
+        HIPCK(launch_fill(F.b, std::max(1, L.nrec), 0.0, st));
+    }
+    // boundary data (as octmg_set_boundary) and rhs (as octmg_set_rhs)
+    if (iface_vals && g->n_pts) STCK(check_finite(&s, iface_vals, g->n_pts, st));
+    if (domain_vals) STCK(check_finite(&s, domain_vals, g->n_dom, st));
+    STCK(check_finite(&s, rhs, g->n_leaf, st));
+    long long dom_off = 0;
+    for (int il = 0; il < nlev; il++) {
+        const GeomLevel &L = g->L[il];
+        Fields64 &F = s.f64[il];
+        HIPCK(launch_boundary_terms(D, L.d_meta, L.d_cfull, L.nrec, iface_vals ? iface_vals + L.pt_base : nullptr,
+                                    F.b, nullptr, st));
+        const long long nf = 2LL * D * L.nface;
+        if (domain_vals)
+            HIPCK(hipMemcpyAsync(F.bcv, domain_vals + dom_off, nf * sizeof(double), hipMemcpyDeviceToDevice, st));
+        else
+            HIPCK(launch_fill(F.bcv, nf, 0.0, st));
+        dom_off += nf;
+        HIPCK(launch_scatter_leaf(D, L.Nb, lv64(&s, il), L.d_leaf_blocks, L.nleaf, rhs, g->n_leaf, L.leaf_base, 1, 1,
+                                  st));
+    }
+    octmg_solve_opts so = *o;
+    so.zero_start = 1;
+    octmg_solve_report local{};
+    PerRhs pr;
+    const octmg_status res = solve_impl(&s, &so, st, rep ? rep : &local, pr);
+    const std::string msg = g_last_error;
+    if (rep && pr.r_final.size() == 1) {
+        if (rep->rhs_status)
+            rep->rhs_status[0] = !std::isfinite(pr.r_final[0]) ? OCTMG_ERR_NONFINITE
+                                 : pr.done[0]                  ? OCTMG_OK
+                                                               : OCTMG_ERR_NOT_CONVERGED;
+        if (rep->rhs_cycles) rep->rhs_cycles[0] = pr.cycles[0];
+        if (rep->rhs_r0) rep->rhs_r0[0] = pr.r0.empty() ? 0.0 : pr.r0[0];
+        if (rep->rhs_r_final) rep->rhs_r_final[0] = pr.r_final[0];
+    }
+    if (res == OCTMG_OK || res == OCTMG_ERR_NOT_CONVERGED)
+        for (int il = 0; il < nlev; il++) {
+            const GeomLevel &L = g->L[il];
+            HIPCK(launch_gather_leaf(D, L.Nb, lv64(&s, il), L.d_leaf_blocks, L.nleaf, phi, g->n_leaf, L.leaf_base, 1,
+                                     st));
+        }
+    HIPCK(hipStreamSynchronize(st));
+    if (res != OCTMG_OK) return fail(res, msg);
+    return OCTMG_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------- lanes (serving engine)
@@ -1976,7 +2137,7 @@ octmg_status lanes_cycle(octmg_state s, const std::vector<int> &running, int kin
 
 void lanes_norms(octmg_state s, std::vector<double> &out) {
     out.resize(s->nrhs);
-    read_mapped(s, out);
+    (void)read_mapped(s, out, nullptr);  // lane states have the mapped buffer: no copy
 }
 
 }  // namespace octmg

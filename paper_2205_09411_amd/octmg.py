@@ -111,6 +111,7 @@ _SIGS = {
     "octmg_residual_norm": (C.c_int, [_vp, C.c_int, _dp, _vp]),
     "octmg_gradient": (C.c_int, [_vp, C.c_int, _vp, C.c_int, _vp]),
     "octmg_solve": (C.c_int, [_vp, C.POINTER(SolveOpts), _vp, C.POINTER(SolveReport)]),
+    "octmg_solve_noalloc": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.POINTER(SolveOpts), _vp, C.POINTER(SolveReport)]),
     "octmg_geom_adapt": (C.c_int, [_vp, _vp, C.c_int, C.POINTER(_vp), _i64p]),
     "octmg_state_remap": (C.c_int, [_vp, _vp, _vp]),
     "octmg_state_set_launch": (C.c_int, [_vp, C.POINTER(LaunchConfig)]),
@@ -276,6 +277,36 @@ class Geometry:
         out = Geometry(self.geom, self.device, _handle=h)
         out._parent_desc = self.desc  # the adapted geometry calls the same level-set callback
         return out, stats
+
+    def solve_noalloc(self, rhs, phi, iface_vals=None, domain_vals=None, rtol: float = 1e-10, max_cycles: int = 40,
+                      kind: int = CYCLE_V, stream=None, raise_on_fail: bool = True) -> SolveReport:
+        """One FP64 solve from phi = 0 with no device allocation
+        (octmg_solve_noalloc): rhs, phi and the boundary values are float64
+        device tensors; phi receives the solution."""
+        for t in (rhs, phi, iface_vals, domain_vals):
+            if t is not None and not (hasattr(t, "data_ptr") and t.is_cuda and str(t.dtype) == "torch.float64"
+                                      and t.is_contiguous()):
+                raise ValueError("solve_noalloc takes contiguous float64 device tensors")
+        if rhs.numel() != self.n_leaf or phi.numel() != self.n_leaf:
+            raise ValueError("rhs and phi need n_leaf values")
+        if iface_vals is not None and iface_vals.numel() != self.n_iface:
+            raise ValueError("iface_vals needs n_iface values")
+        if domain_vals is not None and domain_vals.numel() != self.n_domain:
+            raise ValueError("domain_vals needs n_domain values")
+        o = SolveOpts()
+        o.cycle_kind, o.max_cycles, o.zero_start, o.rtol, o.graph_mode = kind, max_cycles, 1, rtol, 0
+        rep = SolveReport()
+        per = {"status": np.zeros(1, dtype=np.int32), "cycles": np.zeros(1, dtype=np.int32), "r0": np.zeros(1),
+               "r_final": np.zeros(1)}
+        rep.rhs_status, rep.rhs_cycles = _ptr(per["status"], C.c_int), _ptr(per["cycles"], C.c_int)
+        rep.rhs_r0, rep.rhs_r_final = _ptr(per["r0"], C.c_double), _ptr(per["r_final"], C.c_double)
+        ptr = lambda t: None if t is None else t.data_ptr()
+        st = lib().octmg_solve_noalloc(self._h, ptr(rhs), ptr(iface_vals), ptr(domain_vals), ptr(phi), C.byref(o),
+                                       _stream_ptr(stream), C.byref(rep))
+        rep.per_rhs = per
+        if raise_on_fail:
+            _check(st)
+        return rep
 
     def leaf_blocks(self):
         """(level, x, y, z) of every leaf block in canonical order."""
