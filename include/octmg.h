@@ -129,6 +129,31 @@ typedef struct octmg_geom_desc {
 typedef struct octmg_geom_s *octmg_geom;
 typedef struct octmg_state_s *octmg_state;
 
+/* Context: the device, an optional allocator for every device buffer of the
+ * geometries created in it and of their states (and of the temporaries of
+ * their calls), and an optional tune-cache file for octmg_autotune.
+ * alloc(bytes, device, user) returns device memory of at least `bytes` bytes
+ * on `device` aligned to 256 bytes, or NULL (reported as OCTMG_ERR_OOM);
+ * free(ptr, bytes, device, user) releases it; both may be called from the
+ * thread of any call on those objects (a server's worker thread included)
+ * and from octmg_*_destroy.  The callbacks must not call the library.
+ * Without an allocator the library uses hipMalloc/hipFree.  The tune cache
+ * is a text file of "<problem key> TAB <launch configuration> <ms>" lines
+ * that octmg_autotune reads before timing and appends to after; the key
+ * names the device, the tree's blocks per level, records, right-hand sides,
+ * precision and solve options.  A geometry keeps its context alive
+ * (reference counted): octmg_ctx_destroy may come before the geometries'
+ * own destroy calls. */
+typedef struct octmg_ctx_s *octmg_ctx;
+typedef struct octmg_allocator {
+    void *(*alloc)(size_t bytes, int device, void *user);
+    void (*free)(void *ptr, size_t bytes, int device, void *user);
+    void *user;
+} octmg_allocator;
+octmg_status octmg_ctx_create(int hip_device, const octmg_allocator *alloc_or_null, const char *tune_cache_path_or_null,
+                              octmg_ctx *out);
+void octmg_ctx_destroy(octmg_ctx c);
+
 /* Launch configuration of a state's cycles.  Every choice gives the same
  * iterates, bit for bit; only the speed differs.
  *   block_order: which workgroup handles which block in the 3D level
@@ -206,6 +231,10 @@ octmg_status octmg_plan_blocks(const octmg_geom_desc *d, int level, int *pos, in
  * boundaries Sec. 3.6.3, stencils eq. lpl-2d-lsf, Sec. 3.6.2) and factor the
  * coarsest grid.  *out receives a new handle. */
 octmg_status octmg_geom_create(const octmg_geom_desc *d, int hip_device, octmg_geom *out);
+/* The same in a context (its device; hip_device is ignored), whose
+ * allocator and tune cache serve the geometry, its states and the
+ * geometries adapted from it. */
+octmg_status octmg_geom_create_in(octmg_ctx ctx, const octmg_geom_desc *d, int hip_device, octmg_geom *out);
 void octmg_geom_destroy(octmg_geom g);
 /* info[0..7] = n_levels, n_leaf cells, n_interface points, n_domain face
  * points, custom-cell records (all levels), device bytes, tree blocks,
@@ -342,7 +371,11 @@ octmg_status octmg_solve_noalloc(octmg_geom g, const double *rhs, const double *
  * variants on every level and (3D) on none), then keeps the fastest in the
  * state and returns it.  ms[i] (if not NULL, room for 16) receives the mean
  * wall time per solve of candidate i, *n_candidates their number.
- * Afterwards phi holds the solution (the same under every candidate). */
+ * Afterwards phi holds the solution (the same under every candidate).
+ * When the state's geometry was created in a context with a tune cache
+ * that holds this problem's key, that configuration is applied without
+ * timing (*n_candidates = 0, ms untouched, phi unchanged); otherwise the
+ * winner is appended to the cache. */
 octmg_status octmg_autotune(octmg_state s, const octmg_solve_opts *opts, int reps, void *stream,
                             octmg_launch_config *best, double *ms, int *n_candidates);
 

@@ -43,22 +43,38 @@ octmg_status fail(octmg_status st, const std::string &msg) {
         if (s_ != OCTMG_OK) return s_;    \
     } while (0)
 
-// device allocation owned by a geometry or state
+// device allocation owned by a geometry, a state or a call: hipMalloc, or
+// the allocator of the geometry's context
 struct DevPool {
-    std::vector<void *> ptrs;
+    const octmg_allocator *a = nullptr;
+    int device = 0;
+    std::vector<std::pair<void *, size_t>> ptrs;
     size_t bytes = 0;
+    DevPool() = default;
+    DevPool(const octmg_allocator *alloc, int dev) : a(alloc), device(dev) {}
+    DevPool(const DevPool &) = delete;
+    DevPool &operator=(const DevPool &) = delete;
     ~DevPool() {
-        for (void *p : ptrs) (void)hipFree(p);
+        for (auto &p : ptrs) {
+            if (a) a->free(p.first, p.second, device, a->user);
+            else (void)hipFree(p.first);
+        }
     }
     template <typename T>
     hipError_t alloc(T **p, size_t n) {
         *p = nullptr;
         if (n == 0) return hipSuccess;
         void *q = nullptr;
-        hipError_t e = hipMalloc(&q, n * sizeof(T));
-        if (e != hipSuccess) return e;
-        ptrs.push_back(q);
-        bytes += n * sizeof(T);
+        const size_t nb = n * sizeof(T);
+        if (a) {
+            q = a->alloc(nb, device, a->user);
+            if (!q) return hipErrorOutOfMemory;
+        } else {
+            hipError_t e = hipMalloc(&q, nb);
+            if (e != hipSuccess) return e;
+        }
+        ptrs.push_back({q, nb});
+        bytes += nb;
         *p = (T *)q;
         return hipSuccess;
     }
@@ -82,7 +98,18 @@ struct GeomLevel {
 
 }  // namespace
 
+// device, allocator and tune cache shared by the geometries created in it
+struct octmg_ctx_s {
+    int device = 0;
+    octmg_allocator alloc{};
+    bool has_alloc = false;
+    std::string tune_path;
+    int refs = 1;
+    const octmg_allocator *allocator() const { return has_alloc ? &alloc : nullptr; }
+};
+
 struct octmg_geom_s {
+    octmg_ctx ctx = nullptr;  // may be null: hipMalloc, no tune cache
     octmg_geom_desc desc{};
     std::vector<double> params;
     int device = 0;
@@ -92,6 +119,7 @@ struct octmg_geom_s {
     double *d_M = nullptr, *d_S = nullptr;
     DevPool pool;
     int refs = 1;
+    const octmg_allocator *allocator() const { return ctx ? ctx->allocator() : nullptr; }
 };
 
 namespace {
@@ -176,11 +204,17 @@ namespace {
 
 int cells_per_block(int D, int Nb) { return D == 3 ? Nb * Nb * Nb : Nb * Nb; }
 
+void release_ctx(octmg_ctx c) {
+    if (c && --c->refs == 0) delete c;
+}
+
 void release_geom(octmg_geom g) {
     if (!g) return;
     if (--g->refs == 0) {
         (void)hipSetDevice(g->device);
-        delete g;
+        octmg_ctx c = g->ctx;
+        delete g;  // frees through the context's allocator
+        release_ctx(c);
     }
 }
 
@@ -775,11 +809,10 @@ static octmg_status setup_geometry(octmg_geom_s *G, const octmg_geom_s *reuse, i
             stats[1] += (long long)fresh.size();
         }
         if (il == 0) coarse_kept = reuse && fresh.empty();
+        DevPool tmp(G->allocator(), G->device);  // this level's temporaries
         int *d_counts = nullptr, *d_fresh = nullptr;
-        HIPCK(hipMalloc(&d_counts, sizeof(int) * 2 * L.nblocks));
-        std::unique_ptr<int, void (*)(int *)> counts_guard(d_counts, [](int *p) { (void)hipFree(p); });
-        HIPCK(hipMalloc(&d_fresh, sizeof(int) * std::max<size_t>(1, fresh.size())));
-        std::unique_ptr<int, void (*)(int *)> fresh_guard(d_fresh, [](int *p) { (void)hipFree(p); });
+        HIPCK(tmp.alloc(&d_counts, (size_t)2 * L.nblocks));
+        HIPCK(tmp.alloc(&d_fresh, std::max<size_t>(1, fresh.size())));
         std::vector<int> counts(2 * L.nblocks, 0);
         SetupLevel H{};  // host view of S for a host level set
         if (!fresh.empty()) {
@@ -831,10 +864,8 @@ static octmg_status setup_geometry(octmg_geom_s *G, const octmg_geom_s *reuse, i
         HIPCK(hipMemcpy(L.d_map_off, map_off.data(), sizeof(int) * L.nblocks, hipMemcpyHostToDevice));
         if (nrec) {
             int *d_roff = nullptr, *d_poff = nullptr;
-            HIPCK(hipMalloc(&d_roff, sizeof(int) * L.nblocks));
-            std::unique_ptr<int, void (*)(int *)> g1(d_roff, [](int *p) { (void)hipFree(p); });
-            HIPCK(hipMalloc(&d_poff, sizeof(int) * L.nblocks));
-            std::unique_ptr<int, void (*)(int *)> g2(d_poff, [](int *p) { (void)hipFree(p); });
+            HIPCK(tmp.alloc(&d_roff, (size_t)L.nblocks));
+            HIPCK(tmp.alloc(&d_poff, (size_t)L.nblocks));
             HIPCK(hipMemcpy(d_roff, rec_off.data(), sizeof(int) * L.nblocks, hipMemcpyHostToDevice));
             HIPCK(hipMemcpy(d_poff, pt_off.data(), sizeof(int) * L.nblocks, hipMemcpyHostToDevice));
             HIPCK(G->pool.alloc(&L.d_map, (size_t)nib * L.cpb));
@@ -878,8 +909,7 @@ static octmg_status setup_geometry(octmg_geom_s *G, const octmg_geom_s *reuse, i
                 for (const ReuseBlock &k : keep) stats[2] += k.nrec;
             if (!keep.empty()) {
                 ReuseBlock *d_keep = nullptr;
-                HIPCK(hipMalloc(&d_keep, sizeof(ReuseBlock) * keep.size()));
-                std::unique_ptr<ReuseBlock, void (*)(ReuseBlock *)> g3(d_keep, [](ReuseBlock *p) { (void)hipFree(p); });
+                HIPCK(tmp.alloc(&d_keep, keep.size()));
                 HIPCK(hipMemcpy(d_keep, keep.data(), sizeof(ReuseBlock) * keep.size(), hipMemcpyHostToDevice));
                 const ReuseArrays ra{Lo->d_map, Lo->d_meta, Lo->d_inside, Lo->d_d6, Lo->d_cfull, Lo->d_rec8,
                                      Lo->d_pts, Lo->d_rec8f};
@@ -900,12 +930,11 @@ static octmg_status setup_geometry(octmg_geom_s *G, const octmg_geom_s *reuse, i
         const GeomLevel &L0 = G->L[0];
         if (L0.nblocks != 1 || L0.Nb != 8) return fail(OCTMG_ERR_GEOMETRY, "coarsest level must be one 8^D block");
         const int n0 = L0.cpb;
+        DevPool tmp(G->allocator(), G->device);
         double *d_A = nullptr;
         int *d_fail = nullptr;
-        HIPCK(hipMalloc(&d_A, sizeof(double) * n0 * n0));
-        std::unique_ptr<double, void (*)(double *)> ga(d_A, [](double *p) { (void)hipFree(p); });
-        HIPCK(hipMalloc(&d_fail, sizeof(int)));
-        std::unique_ptr<int, void (*)(int *)> gf(d_fail, [](int *p) { (void)hipFree(p); });
+        HIPCK(tmp.alloc(&d_A, (size_t)n0 * n0));
+        HIPCK(tmp.alloc(&d_fail, 1));
         HIPCK(hipMemset(d_fail, 0, sizeof(int)));
         HIPCK(G->pool.alloc(&G->d_M, (size_t)n0 * n0));
         HIPCK(G->pool.alloc(&G->d_S, (size_t)n0));
@@ -928,15 +957,49 @@ static octmg_status setup_geometry(octmg_geom_s *G, const octmg_geom_s *reuse, i
     return OCTMG_OK;
 }
 
-octmg_status octmg_geom_create(const octmg_geom_desc *d, int hip_device, octmg_geom *out) {
-    STCK(validate_desc(d));
-    if (!out) return fail(OCTMG_ERR_INVALID, "null output");
-    *out = nullptr;
+static octmg_status check_device(int hip_device) {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(OCTMG_ERR_HIP, "no HIP device");
     if (hip_device < 0 || hip_device >= ndev) return fail(OCTMG_ERR_INVALID, "bad device index");
+    return OCTMG_OK;
+}
+
+octmg_status octmg_ctx_create(int hip_device, const octmg_allocator *alloc, const char *tune_cache_path,
+                              octmg_ctx *out) {
+    if (!out) return fail(OCTMG_ERR_INVALID, "null output");
+    *out = nullptr;
+    if (alloc && (!alloc->alloc || !alloc->free)) return fail(OCTMG_ERR_INVALID, "allocator needs alloc and free");
+    STCK(check_device(hip_device));
+    octmg_ctx c = new octmg_ctx_s();
+    c->device = hip_device;
+    if (alloc) {
+        c->alloc = *alloc;
+        c->has_alloc = true;
+    }
+    if (tune_cache_path) c->tune_path = tune_cache_path;
+    *out = c;
+    return OCTMG_OK;
+}
+
+void octmg_ctx_destroy(octmg_ctx c) { release_ctx(c); }
+
+octmg_status octmg_geom_create(const octmg_geom_desc *d, int hip_device, octmg_geom *out) {
+    return octmg_geom_create_in(nullptr, d, hip_device, out);
+}
+
+octmg_status octmg_geom_create_in(octmg_ctx ctx, const octmg_geom_desc *d, int hip_device, octmg_geom *out) {
+    STCK(validate_desc(d));
+    if (!out) return fail(OCTMG_ERR_INVALID, "null output");
+    *out = nullptr;
+    if (ctx) hip_device = ctx->device;
+    STCK(check_device(hip_device));
     HIPCK(hipSetDevice(hip_device));
     std::unique_ptr<octmg_geom_s> G(new octmg_geom_s());
+    if (ctx) {
+        G->ctx = ctx;  // referenced once the geometry exists (below)
+        G->pool.a = ctx->allocator();
+    }
+    G->pool.device = hip_device;
     G->desc = *d;
     G->params = copy_params(*d);
     G->desc.lsf_params = G->params.data();
@@ -944,6 +1007,7 @@ octmg_status octmg_geom_create(const octmg_geom_desc *d, int hip_device, octmg_g
     std::string err;
     if (!build_tree(G->desc, &G->tree, &err)) return fail(OCTMG_ERR_INVALID, err);
     STCK(setup_geometry(G.get(), nullptr, nullptr));
+    if (G->ctx) G->ctx->refs++;
     *out = G.release();
     return OCTMG_OK;
 }
@@ -953,6 +1017,11 @@ octmg_status octmg_geom_adapt(octmg_geom g, const int8_t *flags, int reuse, octm
     *out = nullptr;
     HIPCK(hipSetDevice(g->device));
     std::unique_ptr<octmg_geom_s> G(new octmg_geom_s());
+    if (g->ctx) {
+        G->ctx = g->ctx;
+        G->pool.a = g->ctx->allocator();
+    }
+    G->pool.device = g->device;
     G->desc = g->desc;
     G->params = g->params;
     G->desc.lsf_params = G->params.data();
@@ -962,6 +1031,7 @@ octmg_status octmg_geom_adapt(octmg_geom g, const int8_t *flags, int reuse, octm
     if (stats) std::memset(stats, 0, 4 * sizeof(int64_t));
     STCK(setup_geometry(G.get(), reuse ? g : nullptr, stats));
     if (stats) stats[3] -= stats[2];
+    if (G->ctx) G->ctx->refs++;
     *out = G.release();
     return OCTMG_OK;
 }
@@ -1101,6 +1171,8 @@ octmg_status octmg_state_create(octmg_geom g, int n_rhs, int precision, octmg_st
     HIPCK(hipSetDevice(g->device));
     std::unique_ptr<octmg_state_s> s(new octmg_state_s());
     s->geom = g;
+    s->pool.a = g->allocator();
+    s->pool.device = g->device;
     s->nrhs = n_rhs;
     s->precision = precision;
     const int nlev = (int)g->L.size(), D = g->tree.D;
@@ -1278,7 +1350,7 @@ octmg_status octmg_set_boundary(octmg_state s, const double *iface_vals, const d
     octmg_geom g = s->geom;
     HIPCK(hipSetDevice(g->device));
     const int D = g->tree.D;
-    DevPool tmp;
+    DevPool tmp(s->geom->allocator(), s->geom->device);
     double *dv_iface = nullptr, *dv_dom = nullptr;
     if (iface_vals && g->n_pts) {
         STCK(stage_in(iface_vals, g->n_pts, on_device, st, &dv_iface, &tmp));
@@ -1332,7 +1404,7 @@ static octmg_status set_leaf_field(octmg_state s, const void *src, int dtype, in
                                    int field) {
     octmg_geom g = s->geom;
     HIPCK(hipSetDevice(g->device));
-    DevPool tmp;
+    DevPool tmp(s->geom->allocator(), s->geom->device);
     double *dv = nullptr;
     const size_t n = (size_t)g->n_leaf * s->nrhs;
     STCK(stage_in_typed(src, dtype, n, on_device, st, &dv, &tmp));
@@ -1366,7 +1438,7 @@ octmg_status octmg_get_solution(octmg_state s, void *phi, int dtype, int on_devi
     octmg_geom g = s->geom;
     HIPCK(hipSetDevice(g->device));
     const size_t n = (size_t)g->n_leaf * s->nrhs;
-    DevPool tmp;
+    DevPool tmp(s->geom->allocator(), s->geom->device);
     const bool f64 = dtype == OCTMG_DTYPE_F64;
     double *dv = (double *)phi;
     if (!on_device || !f64) HIPCK(tmp.alloc(&dv, n));
@@ -1396,7 +1468,7 @@ octmg_status octmg_gradient(octmg_state s, int inside_zero, double *out, int on_
     Engine<double> e{s, st};
     STCK(e.sync_down());  // coarse copies of leaf values for refinement-boundary ghosts
     const size_t n = (size_t)3 * g->n_leaf * s->nrhs;
-    DevPool tmp;
+    DevPool tmp(s->geom->allocator(), s->geom->device);
     double *dv = out;
     if (!on_device) HIPCK(tmp.alloc(&dv, n));
     for (size_t il = 0; il < g->L.size(); il++) {
@@ -1435,7 +1507,7 @@ octmg_status octmg_state_remap(octmg_state from, octmg_state to, void *stream) {
         old[il].active = nullptr;
         nbo[il] = go->L[il].Nb;
     }
-    DevPool tmp;
+    DevPool tmp(to->geom->allocator(), to->geom->device);
     LV<double> *d_old = nullptr;
     int *d_nb = nullptr;
     HIPCK(tmp.alloc(&d_old, (size_t)nlev));
@@ -1774,9 +1846,62 @@ octmg_status octmg_solve(octmg_state s, const octmg_solve_opts *o, void *stream,
     return OCTMG_OK;
 }
 
+// Tune-cache key of a state's problem: everything the launch choice depends
+// on (device, tree shape, records, right-hand sides, precision, options).
+static std::string tune_key(octmg_state s, const octmg_solve_opts *o) {
+    hipDeviceProp_t prop{};
+    (void)hipGetDeviceProperties(&prop, s->geom->device);
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s cu%d D%d N%d rec%lld rhs%d prec%d kind%d rtol%.3e max%d", prop.gcnArchName,
+                  prop.multiProcessorCount, s->geom->tree.D, s->geom->tree.N, s->geom->n_rec, s->nrhs, s->precision,
+                  o->cycle_kind, o->rtol, o->max_cycles);
+    std::string k(buf);
+    for (const GeomLevel &L : s->geom->L) k += " " + std::to_string(L.nblocks) + "/" + std::to_string(L.nleaf);
+    return k;
+}
+
+static std::mutex g_tune_mu;  // one writer of a tune-cache file at a time in this process
+
+// the launch configuration recorded for `key` (the last such line wins)
+static bool tune_lookup(const std::string &path, const std::string &key, octmg_launch_config *c) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return false;
+    bool found = false;
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+        char *tab = std::strchr(line, '\t');
+        if (!tab || std::string(line, tab - line) != key) continue;
+        octmg_launch_config t{};
+        if (std::sscanf(tab + 1, "%d %d %d %d %d", &t.block_order, &t.bottom_kind, &t.bottom_max_blocks, &t.graph_mode,
+                        &t.pair_max_blocks) == 5) {
+            *c = t;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+static void tune_record(const std::string &path, const std::string &key, const octmg_launch_config &c, double ms) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE *f = std::fopen(path.c_str(), "a");
+    if (!f) return;  // an unwritable cache only costs the next tuning run
+    std::fprintf(f, "%s\t%d %d %d %d %d %.4f\n", key.c_str(), c.block_order, c.bottom_kind, c.bottom_max_blocks,
+                 c.graph_mode, c.pair_max_blocks, ms);
+    std::fclose(f);
+}
+
 octmg_status octmg_autotune(octmg_state s, const octmg_solve_opts *o, int reps, void *stream,
                             octmg_launch_config *best, double *ms, int *n_candidates) {
     if (!s || !o || !best || reps < 1) return fail(OCTMG_ERR_INVALID, "bad argument");
+    const octmg_ctx ctx = s->geom->ctx;
+    const bool cached = ctx && !ctx->tune_path.empty();
+    const std::string key = cached ? tune_key(s, o) : std::string();
+    if (cached && tune_lookup(ctx->tune_path, key, best)) {
+        if (n_candidates) *n_candidates = 0;
+        return octmg_state_set_launch(s, best);
+    }
     std::vector<octmg_launch_config> cand;
     constexpr int all = 1 << 30;
     for (int order = 0; order < 3; order++) {
@@ -1812,6 +1937,7 @@ octmg_status octmg_autotune(octmg_state s, const octmg_solve_opts *o, int reps, 
         if (best_i < 0 || t < best_ms) best_ms = t, best_i = (int)i;
     }
     *best = cand[best_i];
+    if (cached) tune_record(ctx->tune_path, key, *best, best_ms);
     return octmg_state_set_launch(s, best);
 }
 
@@ -1823,7 +1949,7 @@ octmg_status octmg_debug_get_field(octmg_state s, int level, int field, int rhs,
     const Fields64 &F = s->f64[level];
     double *src = (field == 0 ? F.phi : field == 1 ? F.g : F.old) + s->stride[level] * rhs;
     const size_t n = (size_t)L.nblocks * L.cpb;
-    DevPool tmp;
+    DevPool tmp(s->geom->allocator(), s->geom->device);
     double *canon = nullptr;
     HIPCK(tmp.alloc(&canon, n));
     HIPCK(launch_level_copy(s->geom->tree.D, L.Nb, src, canon, L.nblocks, 0, nullptr));
@@ -1839,7 +1965,7 @@ octmg_status octmg_debug_set_field(octmg_state s, int level, int field, int rhs,
     const Fields64 &F = s->f64[level];
     double *dst = (field == 0 ? F.phi : field == 1 ? F.g : F.old) + s->stride[level] * rhs;
     const size_t n = (size_t)L.nblocks * L.cpb;
-    DevPool tmp;
+    DevPool tmp(s->geom->allocator(), s->geom->device);
     double *canon = nullptr;
     HIPCK(tmp.alloc(&canon, n));
     HIPCK(hipMemcpy(canon, in, n * sizeof(double), hipMemcpyHostToDevice));
@@ -2070,7 +2196,7 @@ static LV<double> lv64_lane(const octmg_state_s *s, int il, int lane) {
 octmg_status lane_load(octmg_state s, int lane, const double *src, int on_device, hipStream_t st) {
     if (lane < 0 || lane >= s->nrhs) return fail(OCTMG_ERR_INVALID, "lane out of range");
     octmg_geom g = s->geom;
-    DevPool tmp;
+    DevPool tmp(s->geom->allocator(), s->geom->device);
     double *dv = nullptr;
     STCK(stage_in(src, (size_t)g->n_leaf, on_device, st, &dv, &tmp));
     STCK(check_finite(s, dv, g->n_leaf, st));
@@ -2091,7 +2217,7 @@ octmg_status lane_load(octmg_state s, int lane, const double *src, int on_device
 octmg_status lane_store(octmg_state s, int lane, double *dst, int on_device, hipStream_t st) {
     if (lane < 0 || lane >= s->nrhs) return fail(OCTMG_ERR_INVALID, "lane out of range");
     octmg_geom g = s->geom;
-    DevPool tmp;
+    DevPool tmp(s->geom->allocator(), s->geom->device);
     double *dv = dst;
     if (!on_device) HIPCK(tmp.alloc(&dv, (size_t)g->n_leaf));
     for (size_t il = 0; il < g->L.size(); il++) {

@@ -47,6 +47,14 @@ class GeomDesc(C.Structure):
                 ("uniform_level", C.c_int), ("reserved", C.c_int), ("lsf_fn", LSF_FN), ("lsf_user", C.c_void_p)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
 class SolveOpts(C.Structure):
     _fields_ = [("cycle_kind", C.c_int), ("max_cycles", C.c_int), ("zero_start", C.c_int),
                 ("graph_mode", C.c_int), ("rtol", C.c_double)]
@@ -89,7 +97,10 @@ _SIGS = {
     "octmg_version": (C.c_int, []),
     "octmg_plan_levels": (C.c_int, [C.POINTER(GeomDesc), _ip, _i64p]),
     "octmg_plan_blocks": (C.c_int, [C.POINTER(GeomDesc), C.c_int, _ip, _ip]),
+    "octmg_ctx_create": (C.c_int, [C.c_int, C.POINTER(Allocator), C.c_char_p, C.POINTER(_vp)]),
+    "octmg_ctx_destroy": (None, [_vp]),
     "octmg_geom_create": (C.c_int, [C.POINTER(GeomDesc), C.c_int, C.POINTER(_vp)]),
+    "octmg_geom_create_in": (C.c_int, [_vp, C.POINTER(GeomDesc), C.c_int, C.POINTER(_vp)]),
     "octmg_geom_destroy": (None, [_vp]),
     "octmg_geom_info": (C.c_int, [_vp, _i64p]),
     "octmg_geom_level_info": (C.c_int, [_vp, C.c_int, _i64p]),
@@ -144,7 +155,7 @@ _shutting_down = False
 
 def close_all():
     """Close every open handle (servers, states, geometries)."""
-    for kind in (Server, State, Geometry):
+    for kind in (Server, State, Geometry, Context):
         for obj in [o for o in list(_live) if isinstance(o, kind)]:
             try:
                 obj.close()
@@ -249,15 +260,73 @@ def _stream_ptr(stream):
     return stream.cuda_stream  # torch.cuda.Stream
 
 
-class Geometry:
-    """Tree, FP64 interface setup and coarse inverse on one HIP device."""
+class TorchAllocator:
+    """Device memory for the library from PyTorch's caching allocator (the
+    library's buffers then show up in torch's memory statistics).  The
+    callbacks may run on the library's worker threads."""
 
-    def __init__(self, geom, device: int = 0, _handle=None):
+    def __init__(self):
+        import threading
+        self._blocks = {}
+        self._lock = threading.Lock()
+
+        def alloc(nbytes, device, user):
+            import torch
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=f"cuda:{device}")
+            with self._lock:
+                self._blocks[t.data_ptr()] = t
+            return t.data_ptr()
+
+        def free(ptr, nbytes, device, user):
+            with self._lock:
+                self._blocks.pop(ptr, None)
+
+        self.c = Allocator(ALLOC_FN(alloc), FREE_FN(free), None)
+
+    def bytes_held(self) -> int:
+        with self._lock:
+            return sum(t.numel() for t in self._blocks.values())
+
+
+class Context:
+    """Device, optional allocator (e.g. TorchAllocator()) and optional
+    tune-cache file shared by the geometries created in it."""
+
+    def __init__(self, device: int = 0, allocator=None, tune_cache: str = None):
+        self.allocator = allocator  # kept alive for the callbacks
+        self.device = device
+        h = _vp()
+        _check(lib().octmg_ctx_create(device, C.byref(allocator.c) if allocator is not None else None,
+                                      tune_cache.encode() if tune_cache else None, C.byref(h)))
+        self._h = h
+        _live.add(self)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().octmg_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        if not _finalizing():
+            self.close()
+
+
+class Geometry:
+    """Tree, FP64 interface setup and coarse inverse on one HIP device (or in
+    a Context, whose allocator and tune cache it then uses)."""
+
+    def __init__(self, geom, device: int = 0, _handle=None, ctx: "Context" = None):
         self.desc = make_desc(geom)
         self.geom = geom
+        self.ctx = ctx  # a geometry keeps its context (and allocator callbacks) alive
+        if ctx is not None:
+            device = ctx.device
         if _handle is None:
             h = _vp()
-            _check(lib().octmg_geom_create(C.byref(self.desc), device, C.byref(h)))
+            if ctx is not None:
+                _check(lib().octmg_geom_create_in(ctx._h, C.byref(self.desc), device, C.byref(h)))
+            else:
+                _check(lib().octmg_geom_create(C.byref(self.desc), device, C.byref(h)))
         else:
             h = _handle
         self._h = h
@@ -274,7 +343,7 @@ class Geometry:
         h = _vp()
         stats = np.zeros(4, dtype=np.int64)
         _check(lib().octmg_geom_adapt(self._h, f.ctypes.data, int(reuse), C.byref(h), _ptr(stats, C.c_int64)))
-        out = Geometry(self.geom, self.device, _handle=h)
+        out = Geometry(self.geom, self.device, _handle=h, ctx=self.ctx)
         out._parent_desc = self.desc  # the adapted geometry calls the same level-set callback
         return out, stats
 
@@ -417,7 +486,7 @@ class State:
         n = C.c_int()
         _check(lib().octmg_autotune(self._h, C.byref(o), reps, _stream_ptr(stream), C.byref(best),
                                     _ptr(ms, C.c_double), C.byref(n)))
-        return best.as_dict(), ms[:n.value].tolist()
+        return best.as_dict(), ms[:n.value].tolist()  # no timings on a tune-cache hit
 
     def set_fused_levels(self, max_blocks: int):
         """Run levels with <= max_blocks blocks in one fused launch (0: off)."""
