@@ -419,8 +419,9 @@ def leg_sharp(stream, n_fmg=4, reps=5):
     import torch
     from paper_2205_09411_amd import octmg
     from paper_2205_09411_amd import workloads as W
-    out = {"workload": "sharp shapes of Sec. 4.2, p = 4(x-0.5), q = 4(y-0.5) (3D: p = 4 r, q = 4(z-0.5)), "
-                       "phi=1 on the shape, 0 on the domain boundary, FMG from phi=0"}
+    out = {"workload": "sharp shapes of Sec. 4.2, p = 4(x-0.5), q = 4(y-0.5) (3D, axisymmetric: "
+                       "p = 4(sqrt(x^2+y^2)-0.5), q = 4(z-0.5)), phi=1 on the shape, 0 on the domain boundary, "
+                       "FMG from phi=0"}
     for dim, lmax, bn, label in ((2, 8, 8, "1024^2"), (2, 9, 8, "2048^2"), (3, 5, 16, "256^3")):
         for shape in W.SHAPES:
             w = W.sharp_shape(shape, dim=dim, max_level=lmax, block_n=bn)

@@ -57,10 +57,11 @@ enum { OCTMG_LSF_NONE = 0,       /* no interface */
        OCTMG_LSF_SPHERES = 1,    /* union: f = min_m |x - c_m| - r_m; params [cx,cy,cz,r]*n */
        OCTMG_LSF_CYLINDER_Z = 2, /* f = |(x,y) - (cx,cy)| - r; params [cx,cy,r] */
        /* the sharp shapes of Sec. 4.2 (eqs. spheroid .. astroid) in
-        * coordinates 2D: p = s (x - cx), q = s (y - cy); 3D, rotated about the
-        * z axis through (cx, cy): p = s |(x - cx, y - cy)|, q = s (z - cz);
-        * params [cx, cy, cz, s]; |t|^(2/3) is evaluated as the cube root of
-        * t^2 computed with + - * / only (bit-reproducible) */
+        * coordinates 2D: p = s (x - cx), q = s (y - cy); 3D, axisymmetric
+        * about the z axis through (cx, cy): p = s (|(x - cx, y - cy)| - r0),
+        * q = s (z - cz); params [cx, cy, cz, s, r0] (r0 unused in 2D);
+        * |t|^(2/3) is evaluated as the cube root of t^2 computed with
+        * + - * / only (bit-reproducible) */
        OCTMG_LSF_SPHEROID = 3,   /* sqrt(8 p^2 + q^2) - 1 */
        OCTMG_LSF_RHOMBUS = 4,    /* 8 |p| + |q| - 1.5 */
        OCTMG_LSF_HEART = 5,      /* p^2 + (q - |p|^(2/3))^2 - 1 */

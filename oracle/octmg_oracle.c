@@ -155,10 +155,11 @@ static double cbrt_exact_ops(double a) {
 }
 
 /* The four shapes of Sec. 4.2 (eqs. spheroid .. astroid) in coordinates
- * (p, q): 2D p = s (x - cx), q = s (y - cy); 3D, rotated about the z axis
- * through (cx, cy): p = s |(x - cx, y - cy)|, q = s (z - cz); params
- * [cx, cy, cz, s].  The paper prints p = (x - 0.5)/4, which puts every
- * shape outside the unit square; the scale used is 4 (x - 0.5). */
+ * (p, q): 2D p = s (x - cx), q = s (y - cy); 3D, axisymmetric about the z
+ * axis through (cx, cy): p = s (|(x - cx, y - cy)| - r0), q = s (z - cz);
+ * params [cx, cy, cz, s, r0].  The paper prints p = (x - 0.5)/4, which puts
+ * every shape outside the unit square; the scale used is 4 (x - 0.5).  Its
+ * 3D form p = (sqrt(x^2 + y^2) - 0.5)/4 is cx = cy = 0, r0 = 0.5. */
 static double shape_lsf(int kind, int D, const double *prm, const double *x) {
     double p, q;
     if (D == 2) {
@@ -166,7 +167,7 @@ static double shape_lsf(int kind, int D, const double *prm, const double *x) {
         q = prm[3] * (x[1] - prm[1]);
     } else {
         double ex = x[0] - prm[0], ey = x[1] - prm[1];
-        p = prm[3] * sqrt(ex * ex + ey * ey);
+        p = prm[3] * (sqrt(ex * ex + ey * ey) - prm[4]);
         q = prm[3] * (x[2] - prm[2]);
     }
     switch (kind) {
@@ -971,7 +972,7 @@ void *orc_create(const orc_desc *d) {
     o->d = *d;
     o->D = d->dim;
     int np = d->lsf_kind == 1 ? 4 * d->lsf_n
-             : (d->lsf_kind == 2 ? 3 : (d->lsf_kind >= 3 && d->lsf_kind <= 6 ? 4 : (d->lsf_kind == 7 ? 11 : 0)));
+             : (d->lsf_kind == 2 ? 3 : (d->lsf_kind >= 3 && d->lsf_kind <= 6 ? 5 : (d->lsf_kind == 7 ? 11 : 0)));
     o->lsfp = xcalloc(np + 1, sizeof(double));
     if (np) memcpy(o->lsfp, d->lsf_params, np * sizeof(double));
     o->d.lsf_params = o->lsfp;

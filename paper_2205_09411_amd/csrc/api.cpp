@@ -649,7 +649,7 @@ std::vector<double> copy_params(const octmg_geom_desc &d) {
     int np = d.lsf_kind == OCTMG_LSF_SPHERES      ? 4 * d.lsf_n
              : d.lsf_kind == OCTMG_LSF_CYLINDER_Z   ? 3
              : d.lsf_kind == OCTMG_LSF_ELECTRODES   ? 11
-             : shape                                ? 4
+             : shape                                ? 5
                                                     : 0;
     std::vector<double> p(np + 1, 0.0);
     if (np && d.lsf_params) std::memcpy(p.data(), d.lsf_params, np * sizeof(double));

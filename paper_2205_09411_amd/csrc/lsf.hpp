@@ -54,7 +54,9 @@ struct Lsf {
     octmg_lsf_fn fn;
     void *user;
 
-    // the sharp shapes of Sec. 4.2 on the (p, q) plane; params [cx, cy, cz, s]
+    // the sharp shapes of Sec. 4.2 on the (p, q) plane; params
+    // [cx, cy, cz, s, r0], in 3D axisymmetric about the z axis through
+    // (cx, cy) with p = s (|(x - cx, y - cy)| - r0)
     __host__ __device__ double shape(const double *x) const {
         #pragma clang fp contract(off)
         const double *c = params;
@@ -64,7 +66,7 @@ struct Lsf {
             q = c[3] * (x[1] - c[1]);
         } else {
             const double ex = x[0] - c[0], ey = x[1] - c[1];
-            p = c[3] * sqrt_rn(ex * ex + ey * ey);
+            p = c[3] * (sqrt_rn(ex * ex + ey * ey) - c[4]);
             q = c[3] * (x[2] - c[2]);
         }
         if (kind == OCTMG_LSF_SPHEROID) return sqrt_rn(8.0 * p * p + q * q) - 1.0;

@@ -32,8 +32,8 @@ import numpy as np
 LSF_NONE = 0
 LSF_SPHERES = 1      # union of spheres/circles: params [cx, cy, cz, r] * n
 LSF_CYLINDER_Z = 2   # infinite cylinder along z: params [cx, cy, r]
-# the sharp shapes of Sec. 4.2, params [cx, cy, cz, s]: 2D p = s(x-cx),
-# q = s(y-cy); 3D p = s|(x-cx, y-cy)|, q = s(z-cz)
+# the sharp shapes of Sec. 4.2, params [cx, cy, cz, s, r0]: 2D p = s(x-cx),
+# q = s(y-cy); 3D p = s(|(x-cx, y-cy)| - r0), q = s(z-cz)
 LSF_SPHEROID, LSF_RHOMBUS, LSF_HEART, LSF_ASTROID = 3, 4, 5, 6
 SHAPES = {"spheroid": LSF_SPHEROID, "rhombus": LSF_RHOMBUS, "heart": LSF_HEART, "astroid": LSF_ASTROID}
 # two electrodes: rod around segment a-b plus a sphere, params
@@ -201,13 +201,22 @@ def sphere_f1(dim: int = 3, max_level: int = 4, R: float = 0.25, block_n: int = 
                     exact, exact=exact)
 
 
-def sharp_shape(shape: str, dim: int = 2, max_level: int = 4, block_n: int = 8) -> Workload:
+# 3D forms of the shapes: "ring" p = 4(sqrt(x^2 + y^2) - 0.5), q = 4(z - 0.5),
+# the printed axisymmetric transform with the same x4 scale as in 2D (axis on
+# the cube edge x = y = 0); "spindle" p = 4|(x, y) - (0.5, 0.5)|,
+# q = 4(z - 0.5), the shape revolved about the cube's vertical centre line
+SHAPE_3D = {"ring": [0.0, 0.0, 0.5, 4.0, 0.5], "spindle": [0.5, 0.5, 0.5, 4.0, 0.0]}
+
+
+def sharp_shape(shape: str, dim: int = 2, max_level: int = 4, block_n: int = 8, form3d: str = "ring") -> Workload:
     """Sec. 4.2: Laplace equation on the unit square/cube, phi = 1 on the
     shape's boundary, 0 on the domain boundary, uniform grid, w_min = 4e-3
-    (2D) or 8e-3 (3D); shapes centred at 0.5 with scale 4."""
+    (2D) or 8e-3 (3D); 2D shapes centred at 0.5 with scale 4, 3D forms as
+    in SHAPE_3D."""
+    prm = [0.5, 0.5, 0.5, 4.0, 0.0] if dim == 2 else SHAPE_3D[form3d]
     geom = Geometry(dim=dim, block_n=block_n, max_level=max_level, lsf_kind=SHAPES[shape],
-                    lsf_params=np.array([0.5, 0.5, 0.5, 4.0]), w_min=4e-3 if dim == 2 else 8e-3,
-                    name=f"{shape}_{dim}d_{block_n * (1 << (max_level - 1))}")
+                    lsf_params=np.array(prm), w_min=4e-3 if dim == 2 else 8e-3,
+                    name=f"{shape}_{dim}d_{block_n * (1 << (max_level - 1))}" + ("" if dim == 2 else f"_{form3d}"))
     return Workload(geom, lambda x: np.zeros(x.shape[0]), lambda x: np.ones(x.shape[0]),
                     lambda x: np.zeros(x.shape[0]))
 

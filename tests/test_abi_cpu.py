@@ -40,10 +40,10 @@ GEOMS = {
     # sharp shapes refined near the interface: the host refinement predicate
     # evaluates the shape (with its + - * / cube root) like the oracle
     "heart_amr2d": lambda: W.Geometry(dim=2, block_n=8, max_level=5, lsf_kind=W.LSF_HEART,
-                                      lsf_params=np.array([0.5, 0.5, 0.5, 4.0]), refine_kind=W.REFINE_NEAR_INTERFACE,
+                                      lsf_params=np.array([0.5, 0.5, 0.5, 4.0, 0.0]), refine_kind=W.REFINE_NEAR_INTERFACE,
                                       refine_width=2.0 + np.sqrt(3) / 2, w_min=4e-3),
     "astroid_amr3d": lambda: W.Geometry(dim=3, block_n=8, max_level=4, lsf_kind=W.LSF_ASTROID,
-                                        lsf_params=np.array([0.5, 0.5, 0.5, 4.0]),
+                                        lsf_params=np.array([0.0, 0.0, 0.5, 4.0, 0.5]),
                                         refine_kind=W.REFINE_NEAR_INTERFACE, refine_width=2.0 + np.sqrt(3) / 2,
                                         w_min=8e-3),
 }
