@@ -239,11 +239,12 @@ def leg_adaptive(stream, rtol, reps=3):
     return out
 
 
-def leg_serving(stream, n_requests=1000, pool=4, rtol=1e-8, budget_gb=64, max_lanes=16):
+def leg_serving(stream, n_requests=1000, rtol=1e-8, budget_gb=64, max_lanes=16):
     """Poisson arrivals over 4 sphere-union geometries x {64^3, 128^3, 256^3}
-    (16^3 blocks), Gaussian-source rhs resident in HBM, rtol 1e-8: the
-    batching server (mixed precision) against a plain FP64 one-at-a-time
-    loop on the same GPU, at 0.8x the plain loop's throughput and above."""
+    (16^3 blocks), each request its own Gaussian-source rhs (seed 10000 + i,
+    resident in HBM), rtol 1e-8: the batching server (mixed precision) against
+    a plain FP64 one-at-a-time loop on the same GPU, at 0.8x the plain loop's
+    throughput and above."""
     import torch
     from paper_2205_09411_amd import octmg
     from paper_2205_09411_amd import workloads as W
@@ -256,18 +257,23 @@ def leg_serving(stream, n_requests=1000, pool=4, rtol=1e-8, budget_gb=64, max_la
                               w_min=8e-3, name=f"serve_g{gid}_{16 << (lv - 1)}")
             G = octmg.Geometry(geom)
             xyz, _ = G.leaf_coords()
-            x = torch.tensor(xyz, device="cuda")
-            rhs = []
-            for j in range(pool):
-                amp, wid, cen = W.gaussian_params(10000 + j)
-                g = torch.zeros(G.n_leaf, dtype=torch.float64, device="cuda")
-                for a, w_, c in zip(amp, wid, cen):
-                    d2 = ((x - torch.tensor(c, device="cuda")) ** 2).sum(dim=1)
-                    g += a * torch.exp(-d2 / (2.0 * w_ * w_))
-                rhs.append(g)
-            pairs[(lv, gid)] = {"G": G, "rhs": rhs, "iface": np.ones(G.n_iface),
+            pairs[(lv, gid)] = {"G": G, "x": torch.tensor(xyz, device="cuda"), "iface": np.ones(G.n_iface),
                                 "dom": np.zeros(G.n_domain), "free": []}
-            del x
+
+    def sources(x, seed):  # workloads.gaussian_sources on the device
+        amp, wid, cen = W.gaussian_params(seed)
+        g = torch.zeros(x.shape[0], dtype=torch.float64, device="cuda")
+        for a, w_, c in zip(amp, wid, cen):
+            d2 = ((x - torch.tensor(c, device="cuda")) ** 2).sum(dim=1)
+            g += a * torch.exp(-d2 / (2.0 * w_ * w_))
+        return g
+
+    # every stream below draws the same (size, geometry, seed) per request
+    stream0 = W.serving_stream(n_requests, 1.0)
+    req_rhs = {seed: sources(pairs[(lv, gid)]["x"], seed) for (_, lv, gid, seed) in stream0}
+    for pr in pairs.values():
+        pr["warm"] = sources(pr["x"], 9999)  # warm-up and service-time probes
+        del pr["x"]
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t
 
@@ -280,7 +286,7 @@ def leg_serving(stream, n_requests=1000, pool=4, rtol=1e-8, budget_gb=64, max_la
         S = octmg.State(pr["G"], 1, octmg.FP64)
         S.set_boundary(pr["iface"], pr["dom"])
         pr["plain"] = S
-        S.set_rhs(pr["rhs"][0], stream=stream)
+        S.set_rhs(pr["warm"], stream=stream)
         S.solve(rtol=rtol, zero_start=True, stream=stream)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -299,7 +305,7 @@ def leg_serving(stream, n_requests=1000, pool=4, rtol=1e-8, budget_gb=64, max_la
                 time.sleep(ta - now)
             pr = pairs[(lv, gid)]
             S = pr["plain"]
-            S.set_rhs(pr["rhs"][seed % pool], stream=stream)
+            S.set_rhs(req_rhs[seed], stream=stream)
             S.solve(rtol=rtol, zero_start=True, stream=stream)
             lat.append(time.perf_counter() - t0 - ta)
         return np.array(lat), time.perf_counter() - t0
@@ -309,7 +315,7 @@ def leg_serving(stream, n_requests=1000, pool=4, rtol=1e-8, budget_gb=64, max_la
         slot = {key: srv.add_geometry(pr["G"], pr["iface"], pr["dom"]) for key, pr in pairs.items()}
         # warm-up: one request per geometry creates its resident state and
         # captures its cycle graph before the timed stream starts
-        warm = [srv.submit(slot[key], pr["rhs"][0], out_buf(pr), rtol) for key, pr in pairs.items()]
+        warm = [srv.submit(slot[key], pr["warm"], out_buf(pr), rtol) for key, pr in pairs.items()]
         while warm:
             for r in srv.poll():
                 warm.remove(r["id"])
@@ -324,7 +330,7 @@ def leg_serving(stream, n_requests=1000, pool=4, rtol=1e-8, budget_gb=64, max_la
                 ta, lv, gid, seed = reqs[i]
                 pr = pairs[(lv, gid)]
                 o = out_buf(pr)
-                rid = srv.submit(slot[(lv, gid)], pr["rhs"][seed % pool], o, rtol)
+                rid = srv.submit(slot[(lv, gid)], req_rhs[seed], o, rtol)
                 meta[rid] = (ta, pr, o)
                 i += 1
             for r in srv.poll():
@@ -344,7 +350,9 @@ def leg_serving(stream, n_requests=1000, pool=4, rtol=1e-8, budget_gb=64, max_la
                 "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3), "wall_s": round(wall, 2)}
 
     out = {"workload": "4 geometries (unions of 1/5/10/20 spheres, phi=1 on spheres, 0 on cube) x {64^3,128^3,256^3} "
-                       "in 16^3 blocks, Gaussian-source rhs resident in HBM, Poisson arrivals, rtol 1e-8",
+                       "in 16^3 blocks, one Gaussian-source rhs per request (seed 10000+i) resident in HBM, "
+                       "Poisson arrivals, rtol 1e-8",
+           "rhs_resident_gb": round(sum(v.numel() for v in req_rhs.values()) * 8 / 2 ** 30, 1),
            "requests": n_requests, "setup_s": round(setup_s, 2),
            "plain_fp64_service_ms": {f"{16 << (k[0] - 1)}^3/g{k[1]}": round(v * 1e3, 3) for k, v in plain.items()},
            "plain_fp64_capacity_solves_per_s": round(mu_plain, 1)}
@@ -362,6 +370,7 @@ def leg_serving(stream, n_requests=1000, pool=4, rtol=1e-8, budget_gb=64, max_la
         print(f"serving at {f}x done", file=sys.stderr, flush=True)
     for pr in pairs.values():
         del pr["plain"]
+    req_rhs.clear()
     return out
 
 

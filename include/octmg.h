@@ -410,9 +410,12 @@ octmg_status octmg_debug_step(octmg_state s, int step, int level, int arg, void 
  * of phi = 0, max_cycles, stall), and its result is identical to that of a
  * one-rhs octmg_solve of the same problem in the same precision.
  *
- * Device memory: lane fields (3 FP64 fields, plus 3 FP32 fields in MIXED
- * precision, per cell of every level) are held within hbm_budget_bytes; a
- * geometry's state gets as many lanes as the budget and max_lanes allow;
+ * Device memory: states are held within hbm_budget_bytes, each charged
+ * what it allocates: per lane 3 FP64 fields (plus 3 FP32 fields in MIXED
+ * precision) per cell of every level and its norm and control words, per
+ * state the boundary terms, face and interface values and one leaf-ordered
+ * staging buffer; a geometry's state gets as many lanes as the budget and
+ * max_lanes allow;
  * idle states of other geometries are released when a waiting geometry
  * needs room, and while one waits the others admit no new requests.  A request whose single lane
  * exceeds the budget completes with OCTMG_ERR_BUDGET.  Geometries are owned
@@ -422,8 +425,12 @@ octmg_status octmg_debug_step(octmg_state s, int step, int level, int arg, void 
  * solution (n_leaf values) must stay valid until the request's result has
  * been polled; on_device selects device or host memory.  The solution is
  * written before the result is published (also for NOT_CONVERGED; not for
- * NONFINITE or BUDGET).  Submit and poll are thread-safe and never block on
- * the GPU. */
+ * NONFINITE or BUDGET).  A rhs holding NaN or Inf completes with
+ * OCTMG_ERR_NONFINITE.  Submit and poll are thread-safe and never block on
+ * the GPU.  With device buffers the worker never waits for the GPU either
+ * (every step of a request is enqueued on its geometry's stream and
+ * completed through one polled event per geometry); host buffers are copied
+ * synchronously by the worker. */
 typedef struct octmg_server_s *octmg_server;
 typedef struct octmg_server_opts {
     size_t hbm_budget_bytes;

@@ -182,6 +182,13 @@ struct octmg_state_s {
     int n_launch = 1;                          // grid rows of every per-rhs launch
     unsigned long long *h_norm = nullptr;      // pinned, host-mapped copy of d_norm
     unsigned long long *h_norm_dev = nullptr;  // device view of h_norm
+    // serving lanes (lanes_prepare): pinned control uploads, two per pass of
+    // the server, and host-mapped norms of newly admitted lanes [2][nrhs]
+    // (residual of phi = 0, first defect)
+    int *h_ctrl = nullptr;
+    int ctrl_turn = 0;
+    unsigned long long *h_begin = nullptr;
+    unsigned long long *h_begin_dev = nullptr;
     std::vector<double> r0_cache;              // residual of phi = 0 (valid while !r0_dirty)
     bool r0_dirty = true;
     int block_order = 0;                       // LV::order of every level
@@ -480,7 +487,9 @@ hipError_t Engine<float>::fill(float *p, long long n) { return launch_fillf(p, n
 
 // synced: phi's coarse copies are already current (right after a cycle)
 // The norms land in d_norm and in the mapped host buffer.
-octmg_status residual_norm_dev(octmg_state s, int phi_zero, hipStream_t st, bool synced = false) {
+// mapped: host-mapped norm buffer to write (default: the state's h_norm)
+octmg_status residual_norm_dev(octmg_state s, int phi_zero, hipStream_t st, bool synced = false,
+                               unsigned long long *mapped = nullptr) {
     if (!s->norm_slots_clean) HIPCK(launch_fill_u64(s->d_norm_slots, norm_slot_words(s->nrhs), 0ull, st));
     s->norm_slots_clean = false;
     if (!phi_zero && !synced) {
@@ -494,7 +503,7 @@ octmg_status residual_norm_dev(octmg_state s, int phi_zero, hipStream_t st, bool
         HIPCK(launch_residual_max<double>(D, G.Nb, lv64(s, il), lv64(s, il - 1), phi_zero, s->d_norm_slots,
                                           s->n_launch, st));
     }
-    HIPCK(launch_norm_reduce(s->d_norm_slots, s->d_norm, s->h_norm_dev, s->nrhs, st));
+    HIPCK(launch_norm_reduce(s->d_norm_slots, s->d_norm, mapped ? mapped : s->h_norm_dev, s->nrhs, st));
     s->norm_slots_clean = true;
     return OCTMG_OK;
 }
@@ -526,7 +535,7 @@ octmg_status read_norms(octmg_state s, double *out, hipStream_t st) {
 
 // one outer step of the mixed-precision defect correction: FP64 defect on
 // the leaves (norm into d_norm), FP32 cycle on the correction, FP64 update
-octmg_status mixed_defect(octmg_state s, hipStream_t st) {
+octmg_status mixed_defect(octmg_state s, hipStream_t st, unsigned long long *mapped = nullptr) {
     Engine<double> e64{s, st};
     STCK(e64.sync_down());
     if (!s->norm_slots_clean) HIPCK(launch_fill_u64(s->d_norm_slots, norm_slot_words(s->nrhs), 0ull, st));
@@ -549,7 +558,7 @@ octmg_status mixed_defect(octmg_state s, hipStream_t st) {
         HIPCK(launch_defect(D, G.Nb, lv64(s, il), lv64(s, il - 1), lv32(s, il), G.d_leaf_blocks, G.nleaf,
                             s->d_norm_slots, s->n_launch, st));
     }
-    HIPCK(launch_norm_reduce(s->d_norm_slots, s->d_norm, s->h_norm_dev, s->nrhs, st));
+    HIPCK(launch_norm_reduce(s->d_norm_slots, s->d_norm, mapped ? mapped : s->h_norm_dev, s->nrhs, st));
     s->norm_slots_clean = true;
     return OCTMG_OK;
 }
@@ -931,9 +940,10 @@ static octmg_status setup_geometry(octmg_geom_s *G, const octmg_geom_s *reuse, i
         if (L0.nblocks != 1 || L0.Nb != 8) return fail(OCTMG_ERR_GEOMETRY, "coarsest level must be one 8^D block");
         const int n0 = L0.cpb;
         DevPool tmp(G->allocator(), G->device);
-        double *d_A = nullptr;
+        double *d_A = nullptr, *d_mult = nullptr;
         int *d_fail = nullptr;
         HIPCK(tmp.alloc(&d_A, (size_t)n0 * n0));
+        HIPCK(tmp.alloc(&d_mult, (size_t)n0));
         HIPCK(tmp.alloc(&d_fail, 1));
         HIPCK(hipMemset(d_fail, 0, sizeof(int)));
         HIPCK(G->pool.alloc(&G->d_M, (size_t)n0 * n0));
@@ -946,7 +956,7 @@ static octmg_status setup_geometry(octmg_geom_s *G, const octmg_geom_s *reuse, i
             HIPCK(hipMemcpy(&mo, L0.d_map_off, sizeof(int), hipMemcpyDeviceToHost));
             HIPCK(launch_coarse_assemble(D, L0.Nb, L0.dx, mo >= 0 ? L0.d_map + mo : nullptr, L0.d_rec8,
                                          G->desc.neumann_faces, d_A, nullptr));
-            HIPCK(launch_gauss_jordan(n0, d_A, G->d_M, G->d_S, d_fail, nullptr));
+            HIPCK(launch_gauss_jordan(n0, d_A, G->d_M, G->d_S, d_mult, d_fail, nullptr));
             int hf = 0;
             HIPCK(hipMemcpy(&hf, d_fail, sizeof(int), hipMemcpyDeviceToHost));
             if (hf) return fail(OCTMG_ERR_GEOMETRY, "coarse-grid operator is singular");
@@ -1238,6 +1248,8 @@ void octmg_state_destroy(octmg_state s) {
     (void)hipDeviceSynchronize();
     octmg_geom g = s->geom;
     if (s->h_norm) (void)hipHostFree(s->h_norm);
+    if (s->h_ctrl) (void)hipHostFree(s->h_ctrl);
+    if (s->h_begin) (void)hipHostFree(s->h_begin);
     for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
     if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
     delete s->prof;
@@ -1565,6 +1577,9 @@ octmg_status octmg_residual_norm(octmg_state s, int phi_zero, double *out, void 
 // iterating right-hand sides (grid y = their number), so finished or idle
 // ones cost no workgroups.  With none iterating the list keeps every rhs
 // (their kernels then exit at the flag) so that no launch is empty.
+// With the pinned control buffers of a lane state (lanes_prepare) the upload
+// is left in flight: the buffer it reads is not written again before the
+// server's next pass, which waits for the stream first.
 static octmg_status set_active(octmg_state s, const std::vector<int> &act, hipStream_t st) {
     std::vector<int> list;
     for (int r = 0; r < (int)act.size(); r++)
@@ -1577,6 +1592,13 @@ static octmg_status set_active(octmg_state s, const std::vector<int> &act, hipSt
     s->n_launch = (int)list.size();
     std::vector<int> ctrl(act);
     ctrl.insert(ctrl.end(), list.begin(), list.end());
+    if (s->h_ctrl) {
+        int *buf = s->h_ctrl + (size_t)s->ctrl_turn * 2 * s->nrhs;
+        s->ctrl_turn ^= 1;
+        std::memcpy(buf, ctrl.data(), sizeof(int) * ctrl.size());
+        HIPCK(hipMemcpyAsync(s->d_active, buf, sizeof(int) * ctrl.size(), hipMemcpyHostToDevice, st));
+        return OCTMG_OK;
+    }
     HIPCK(hipMemcpyAsync(s->d_active, ctrl.data(), sizeof(int) * ctrl.size(), hipMemcpyHostToDevice, st));
     HIPCK(hipStreamSynchronize(st));
     return OCTMG_OK;
@@ -2176,10 +2198,24 @@ octmg_status api_fail(octmg_status st, const std::string &msg) { return fail(st,
 
 int geom_device(octmg_geom g) { return g->device; }
 
+// what octmg_state_create allocates per right-hand side: phi, g, old on all
+// levels (plus their FP32 copies in MIXED precision), the norm, its slots,
+// the threshold, the graph history and two control words
 size_t lane_bytes(octmg_geom g, int precision) {
     size_t cells = 0;
     for (const GeomLevel &L : g->L) cells += (size_t)L.nblocks * L.cpb;
-    return cells * (3 * sizeof(double) + (precision == OCTMG_MIXED ? 3 * sizeof(float) : 0));
+    return cells * (3 * sizeof(double) + (precision == OCTMG_MIXED ? 3 * sizeof(float) : 0)) +
+           (1 + (size_t)norm_slot_words(1) + 1 + 64) * sizeof(double) + 2 * sizeof(int);
+}
+
+// and once per state: boundary terms, face values and interface values of
+// every level, the flag, plus one leaf-ordered staging buffer (a request
+// with host buffers is staged through it)
+size_t state_fixed_bytes(octmg_geom g) {
+    size_t n = 1;
+    for (const GeomLevel &L : g->L)
+        n += (size_t)std::max(1, L.nrec) + (size_t)2 * g->tree.D * L.nface + (size_t)std::max<long long>(1, L.npts);
+    return n * sizeof(double) + (size_t)g->n_leaf * sizeof(double);
 }
 
 static LV<double> lv64_lane(const octmg_state_s *s, int il, int lane) {
@@ -2193,13 +2229,21 @@ static LV<double> lv64_lane(const octmg_state_s *s, int il, int lane) {
     return v;
 }
 
+octmg_status lanes_prepare(octmg_state s) {
+    if (s->h_ctrl) return OCTMG_OK;
+    HIPCK(hipSetDevice(s->geom->device));
+    HIPCK(hipHostMalloc((void **)&s->h_ctrl, sizeof(int) * 4 * s->nrhs, hipHostMallocDefault));
+    HIPCK(hipHostMalloc((void **)&s->h_begin, sizeof(unsigned long long) * 2 * s->nrhs, hipHostMallocMapped));
+    HIPCK(hipHostGetDevicePointer((void **)&s->h_begin_dev, s->h_begin, 0));
+    return OCTMG_OK;
+}
+
 octmg_status lane_load(octmg_state s, int lane, const double *src, int on_device, hipStream_t st) {
     if (lane < 0 || lane >= s->nrhs) return fail(OCTMG_ERR_INVALID, "lane out of range");
     octmg_geom g = s->geom;
     DevPool tmp(s->geom->allocator(), s->geom->device);
     double *dv = nullptr;
     STCK(stage_in(src, (size_t)g->n_leaf, on_device, st, &dv, &tmp));
-    STCK(check_finite(s, dv, g->n_leaf, st));
     for (size_t il = 0; il < g->L.size(); il++) {
         const GeomLevel &L = g->L[il];
         const long long o = (long long)lane * s->stride[il];
@@ -2210,7 +2254,7 @@ octmg_status lane_load(octmg_state s, int lane, const double *src, int on_device
         HIPCK(launch_scatter_leaf(g->tree.D, L.Nb, v, L.d_leaf_blocks, L.nleaf, dv, g->n_leaf, L.leaf_base, 1, 1,
                                   st));
     }
-    HIPCK(hipStreamSynchronize(st));  // the staging buffer dies here
+    if (!on_device) HIPCK(hipStreamSynchronize(st));  // the staging buffer dies here
     return OCTMG_OK;
 }
 
@@ -2226,27 +2270,33 @@ octmg_status lane_store(octmg_state s, int lane, double *dst, int on_device, hip
         v.active = nullptr;
         HIPCK(launch_gather_leaf(g->tree.D, L.Nb, v, L.d_leaf_blocks, L.nleaf, dv, g->n_leaf, L.leaf_base, 1, st));
     }
-    if (!on_device) HIPCK(hipMemcpyAsync(dst, dv, sizeof(double) * g->n_leaf, hipMemcpyDeviceToHost, st));
-    HIPCK(hipStreamSynchronize(st));
+    if (!on_device) {
+        HIPCK(hipMemcpyAsync(dst, dv, sizeof(double) * g->n_leaf, hipMemcpyDeviceToHost, st));
+        HIPCK(hipStreamSynchronize(st));
+    }
     return OCTMG_OK;
 }
 
-// r0 (residual of phi = 0) and the first convergence norm of the lanes set
-// in `fresh`; lanes not in `fresh` keep their fields.
-octmg_status lanes_begin(octmg_state s, const std::vector<int> &fresh, hipStream_t st, std::vector<double> &r0,
-                         std::vector<double> &rk) {
-    r0.assign(s->nrhs, 0.0);
+// Residual of phi = 0 and the first convergence norm (FP64: the same; MIXED:
+// the first defect) of the lanes set in `fresh` into the state's begin
+// buffers; lanes not in `fresh` keep their fields.  Read with
+// lanes_begin_norms once the stream has passed.
+octmg_status lanes_begin(octmg_state s, const std::vector<int> &fresh, hipStream_t st) {
     STCK(set_active(s, fresh, st));
-    STCK(residual_norm_dev(s, 1, st));
-    STCK(read_norms(s, r0.data(), st));
-    if (s->precision == OCTMG_MIXED) {
-        STCK(mixed_defect(s, st));
-        rk.assign(s->nrhs, 0.0);
-        STCK(read_norms(s, rk.data(), st));
-    } else {
-        rk = r0;
-    }
+    STCK(residual_norm_dev(s, 1, st, false, s->h_begin_dev));
+    if (s->precision == OCTMG_MIXED) STCK(mixed_defect(s, st, s->h_begin_dev + s->nrhs));
     return OCTMG_OK;
+}
+
+void lanes_begin_norms(octmg_state s, std::vector<double> &r0, std::vector<double> &rk) {
+    r0.resize(s->nrhs);
+    rk.resize(s->nrhs);
+    for (int r = 0; r < s->nrhs; r++) {
+        const unsigned long long a = ((volatile unsigned long long *)s->h_begin)[r];
+        const unsigned long long b = ((volatile unsigned long long *)s->h_begin)[s->nrhs + r];
+        std::memcpy(&r0[r], &a, sizeof(double));
+        std::memcpy(&rk[r], s->precision == OCTMG_MIXED ? &b : &a, sizeof(double));
+    }
 }
 
 // Launch one cycle of the lanes set in `running` and the norms of the new

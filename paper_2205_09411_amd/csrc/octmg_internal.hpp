@@ -241,19 +241,26 @@ void host_setup_emit(const SetupLevel &S, const int *rec_off, const int *pt_off,
 // row-equilibrated Gauss-Jordan inverse M and scales S (A^-1 = M diag(S)).
 hipError_t launch_coarse_assemble(int D, int Nb, double dx, const int *map, const double *rec8, int neumann,
                                   double *A, hipStream_t s);
-hipError_t launch_gauss_jordan(int n, double *A, double *M, double *S, int *fail, hipStream_t s);
+// mult: n doubles of workspace; fail: 1 when the operator is singular
+hipError_t launch_gauss_jordan(int n, double *A, double *M, double *S, double *mult, int *fail, hipStream_t s);
 
-// ---- lanes of a multi-rhs state (api.cpp), used by the serving engine
+// ---- lanes of a multi-rhs state (api.cpp), used by the serving engine.
+// With device buffers these calls only enqueue work on `st`; the caller
+// waits for the stream (an event) before reading norms or results.
 octmg_status api_fail(octmg_status st, const std::string &msg);
 int geom_device(octmg_geom g);
-size_t lane_bytes(octmg_geom g, int precision);  // device bytes of one lane's fields
-// rhs of one lane from leaf-ordered values (host or device); zeroes its phi
+size_t lane_bytes(octmg_geom g, int precision);   // device bytes of one lane's fields
+size_t state_fixed_bytes(octmg_geom g);           // device bytes of a state besides its lanes
+// pinned control and mapped norm buffers of a lane state (once per state)
+octmg_status lanes_prepare(octmg_state s);
+// rhs of one lane from leaf-ordered values (host: staged and waited for;
+// device: enqueued); zeroes its phi
 octmg_status lane_load(octmg_state s, int lane, const double *src, int on_device, hipStream_t st);
-// leaf-ordered phi of one lane into dst (host or device); waits for the copy
+// leaf-ordered phi of one lane into dst (host: waited for; device: enqueued)
 octmg_status lane_store(octmg_state s, int lane, double *dst, int on_device, hipStream_t st);
-// r0 and first convergence norm of the lanes flagged in `fresh` (waits)
-octmg_status lanes_begin(octmg_state s, const std::vector<int> &fresh, hipStream_t st, std::vector<double> &r0,
-                         std::vector<double> &rk);
+// r0 and first convergence norm of the lanes flagged in `fresh`, enqueued
+octmg_status lanes_begin(octmg_state s, const std::vector<int> &fresh, hipStream_t st);
+void lanes_begin_norms(octmg_state s, std::vector<double> &r0, std::vector<double> &rk);
 // one V-cycle of the flagged lanes plus their norms, asynchronously
 octmg_status lanes_cycle(octmg_state s, const std::vector<int> &running, int kind, hipStream_t st);
 // norms written by the last lanes_cycle (after its stream has passed it)

@@ -63,6 +63,10 @@ struct Request {
 struct Lane {
     bool busy = false;
     bool running = false;  // admitted and not yet retired
+    bool fresh = false;    // admitted in the pass in flight: its first norms are pending
+    bool storing = false;  // finished: its solution is being copied out, published next pass
+    bool ran = false;      // cycled in the pass in flight
+    int status = OCTMG_OK;
     Request req;
     int cycles = 0, stall = 0;
     double r0 = 0.0, cur = 0.0, prev = 0.0;
@@ -133,10 +137,12 @@ struct octmg_server_s {
 
     // A state for S with as many lanes as the budget allows (up to
     // max_lanes), releasing idle states of other geometries first if that is
-    // what it takes to fit one lane.
+    // what it takes to fit one lane.  A state costs its fixed part plus
+    // lane_bytes per lane.
     octmg_status acquire(Slot &S, int idx, bool *rejected) {
         *rejected = false;
-        const size_t per = lane_bytes(S.geom, opts.precision);
+        const size_t lane = lane_bytes(S.geom, opts.precision), fixed = state_fixed_bytes(S.geom);
+        const size_t per = lane + fixed;  // the smallest state: one lane
         if (per > opts.hbm_budget_bytes) {
             *rejected = true;
             return OCTMG_OK;
@@ -163,18 +169,19 @@ struct octmg_server_s {
                 return OCTMG_OK;
             }
         }
-        const size_t fit = (opts.hbm_budget_bytes - used) / per;
+        const size_t fit = (opts.hbm_budget_bytes - used - fixed) / lane;
         const int n = (int)std::min<size_t>(fit, (size_t)opts.max_lanes);
         octmg_state st = nullptr;
         SSTCK(octmg_state_create(S.geom, n, opts.precision, &st));
         octmg_status r = octmg_set_boundary(st, S.iface.empty() ? nullptr : S.iface.data(), S.dom.data(), 0,
                                             S.stream);
+        if (r == OCTMG_OK) r = lanes_prepare(st);
         if (r != OCTMG_OK) {
             octmg_state_destroy(st);
             return r;
         }
         S.state = st;
-        S.bytes = per * (size_t)n;
+        S.bytes = fixed + lane * (size_t)n;
         used += S.bytes;
         S.lanes.assign(n, Lane{});
         if (starving == idx) starving = -1;
@@ -199,7 +206,19 @@ struct octmg_server_s {
         return false;
     }
 
-    // one pass over a slot; returns whether anything happened
+    // One pass over a slot; returns whether anything happened.  A pass only
+    // enqueues work on the slot's stream and records one event; the next
+    // pass, once the event has passed, reads what the work produced:
+    //   1. publish the lanes whose solutions were being copied out;
+    //   2. settle lanes admitted last pass on their first norms (cycle 0);
+    //   3. settle lanes that cycled on the cycle's norms;
+    //   4. copy out the lanes that finished, admit waiting requests into
+    //      free lanes (load rhs, first norms), launch the next cycle of the
+    //      running lanes, record the event.
+    // A lane admitted in a pass also cycles in it; a lane that had in fact
+    // converged before its first cycle (r0 = 0: phi = 0 is exact) is settled
+    // at cycle 0, and its cycle left phi = 0 unchanged.  Host buffers are
+    // staged synchronously (lane_load / lane_store wait for them).
     octmg_status service(Slot &S, int idx, bool *progress) {
         if (S.inflight) {
             const hipError_t q = hipEventQuery(S.done);
@@ -207,13 +226,28 @@ struct octmg_server_s {
             SHIP(q);
             S.inflight = false;
             *progress = true;
-            std::vector<double> nv;
+            std::vector<double> nv, r0, rk;
             lanes_norms(S.state, nv);
+            lanes_begin_norms(S.state, r0, rk);
             for (int i = 0; i < (int)S.lanes.size(); i++) {
                 Lane &l = S.lanes[i];
-                if (!l.running) continue;
-                l.cycles++;
-                SSTCK(step_lane(S, i, nv[i]));
+                if (l.storing) {
+                    finish(l.req, l.status, l.cycles, l.r0, l.cur);
+                    l = Lane{};
+                    continue;
+                }
+                bool done = false;
+                if (l.fresh) {
+                    l.fresh = false;
+                    l.r0 = r0[i];
+                    done = settle(l, rk[i], &l.status);
+                }
+                if (!done && l.ran) {
+                    l.cycles++;
+                    done = settle(l, nv[i], &l.status);
+                }
+                l.ran = false;
+                if (done) SSTCK(retire(S, i));
             }
         }
         if (!S.pending.empty() && !S.state) {
@@ -243,7 +277,7 @@ struct octmg_server_s {
                 continue;
             }
             l = Lane{};
-            l.busy = true;
+            l.busy = l.running = l.fresh = true;
             l.req = r;
             fresh[i] = 1;
             any_fresh = true;
@@ -251,42 +285,47 @@ struct octmg_server_s {
         }
         if (any_fresh) {
             *progress = true;
-            std::vector<double> r0, rk;
-            SSTCK(lanes_begin(S.state, fresh, S.stream, r0, rk));
-            for (int i = 0; i < (int)S.lanes.size(); i++) {
-                if (!fresh[i]) continue;
-                Lane &l = S.lanes[i];
-                l.r0 = r0[i];
-                l.running = true;
-                SSTCK(step_lane(S, i, rk[i]));
-            }
+            SSTCK(lanes_begin(S.state, fresh, S.stream));
         }
         std::vector<int> run(S.lanes.size(), 0);
-        bool any = false;
-        for (int i = 0; i < (int)S.lanes.size(); i++)
-            if (S.lanes[i].running) run[i] = 1, any = true;
+        bool any = false, storing = false;
+        for (int i = 0; i < (int)S.lanes.size(); i++) {
+            if (S.lanes[i].running) run[i] = 1, any = true, S.lanes[i].ran = true;
+            storing |= S.lanes[i].storing;
+        }
         if (any) {
             SSTCK(lanes_cycle(S.state, run, OCTMG_CYCLE_V, S.stream));
-            SHIP(hipEventRecord(S.done, S.stream));
-            S.inflight = true;
-            S.last_used = now();
             stats.cycles_launched++;
             int k = 0;
             for (int v : run) k += v;
             stats.lane_cycles += k;
         }
+        if (any || storing) {
+            SHIP(hipEventRecord(S.done, S.stream));
+            S.inflight = true;
+            S.last_used = now();
+        }
         return OCTMG_OK;
     }
 
-    // settle lane i with norm v; a finished lane stores its iterate (unless
-    // it is not finite) before its result is published
-    octmg_status step_lane(Slot &S, int i, double v) {
+    // lane i has its final status: copy its iterate out (unless it is not
+    // finite) and publish it once that copy has passed; a lane that is not
+    // copied is published now
+    octmg_status retire(Slot &S, int i) {
         Lane &l = S.lanes[i];
-        int status = OCTMG_OK;
-        if (!settle(l, v, &status)) return OCTMG_OK;
-        if (status != OCTMG_ERR_NONFINITE) SSTCK(lane_store(S.state, i, l.req.out, l.req.out_dev, S.stream));
-        finish(l.req, status, l.cycles, l.r0, v);
-        l = Lane{};
+        l.running = false;
+        if (l.status == OCTMG_ERR_NONFINITE) {
+            finish(l.req, l.status, l.cycles, l.r0, l.cur);
+            l = Lane{};
+            return OCTMG_OK;
+        }
+        SSTCK(lane_store(S.state, i, l.req.out, l.req.out_dev, S.stream));
+        if (l.req.out_dev) {
+            l.storing = true;
+        } else {  // copied and waited for already
+            finish(l.req, l.status, l.cycles, l.r0, l.cur);
+            l = Lane{};
+        }
         return OCTMG_OK;
     }
 

@@ -378,74 +378,88 @@ __global__ void k_coarse_assemble(int D, int Nb, double dx, const int *map, cons
     A[(long)row * n + row] += diag;
 }
 
-// Row-equilibrated Gauss-Jordan inverse with partial pivoting, one
-// workgroup: S_i = 1 / max_j |A_ij|, M = (diag(S) A)^-1, A^-1 = M diag(S).
-__global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double *A, double *M, double *S, int *fail) {
+// Row-equilibrated Gauss-Jordan inverse with partial pivoting:
+// S_i = 1 / max_j |A_ij|, M = (diag(S) A)^-1, A^-1 = M diag(S).  Step k runs
+// as two launches: k_gj_pivot (one workgroup) picks the pivot row of column
+// k (largest |A_rk|, r >= k, lowest r on ties), swaps it into row k, divides
+// row k of A and M by the pivot and records the column multipliers;
+// k_gj_eliminate (one thread per element) subtracts multiplier x row k from
+// every other row.  Each element sees the same operations in the same order
+// as in a one-workgroup elimination.
+__global__ __launch_bounds__(256) void k_gj_scale(int n, double *A, double *M, double *S) {
+    const int r = blockIdx.x;
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) m = fmax(m, fabs(A[(long)r * n + c]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    const double s = red[0] > 0.0 ? 1.0 / red[0] : 1.0;
+    if (threadIdx.x == 0) S[r] = s;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        A[(long)r * n + c] *= s;
+        M[(long)r * n + c] = r == c ? 1.0 : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_gj_pivot(int n, int k, double *A, double *M, double *mult, int *fail) {
     __shared__ double sval[1024];
     __shared__ int sidx[1024];
-    __shared__ double mult[512];
+    if (*fail) return;
     const int t = threadIdx.x, T = blockDim.x;
-    for (int r = t; r < n; r += T) {
-        double m = 0.0;
-        for (int c = 0; c < n; c++) m = fmax(m, fabs(A[(long)r * n + c]));
-        S[r] = m > 0.0 ? 1.0 / m : 1.0;
+    double best = -1.0;
+    int bi = k;
+    for (int r = k + t; r < n; r += T) {
+        const double v = fabs(A[(long)r * n + k]);
+        if (v > best) { best = v; bi = r; }
     }
+    sval[t] = best;
+    sidx[t] = bi;
     __syncthreads();
-    for (long e = t; e < (long)n * n; e += T) {
-        const int r = (int)(e / n), c = (int)(e % n);
-        A[e] *= S[r];
-        M[e] = r == c ? 1.0 : 0.0;
+    for (int w = T / 2; w > 0; w >>= 1) {
+        if (t < w && (sval[t + w] > sval[t] || (sval[t + w] == sval[t] && sidx[t + w] < sidx[t]))) {
+            sval[t] = sval[t + w];
+            sidx[t] = sidx[t + w];
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int k = 0; k < n; k++) {
-        double best = -1.0;
-        int bi = k;
-        for (int r = k + t; r < n; r += T) {
-            double v = fabs(A[(long)r * n + k]);
-            if (v > best) { best = v; bi = r; }
-        }
-        sval[t] = best;
-        sidx[t] = bi;
-        __syncthreads();
-        for (int w = T / 2; w > 0; w >>= 1) {
-            if (t < w && (sval[t + w] > sval[t] || (sval[t + w] == sval[t] && sidx[t + w] < sidx[t]))) {
-                sval[t] = sval[t + w];
-                sidx[t] = sidx[t + w];
-            }
-            __syncthreads();
-        }
-        const int p = sidx[0];
-        if (!(sval[0] > 0.0)) {
-            if (t == 0) *fail = 1;
-            return;
-        }
-        if (p != k)
-            for (int c = t; c < n; c += T) {
-                double x = A[(long)k * n + c], y = M[(long)k * n + c];
-                A[(long)k * n + c] = A[(long)p * n + c];
-                M[(long)k * n + c] = M[(long)p * n + c];
-                A[(long)p * n + c] = x;
-                M[(long)p * n + c] = y;
-            }
-        __syncthreads();
-        const double inv = 1.0 / A[(long)k * n + k];
-        __syncthreads();
+    const int p = sidx[0];
+    if (!(sval[0] > 0.0)) {
+        if (t == 0) *fail = 1;
+        return;
+    }
+    if (p != k)
         for (int c = t; c < n; c += T) {
-            A[(long)k * n + c] *= inv;
-            M[(long)k * n + c] *= inv;
+            const double x = A[(long)k * n + c], y = M[(long)k * n + c];
+            A[(long)k * n + c] = A[(long)p * n + c];
+            M[(long)k * n + c] = M[(long)p * n + c];
+            A[(long)p * n + c] = x;
+            M[(long)p * n + c] = y;
         }
-        __syncthreads();
-        for (int r = t; r < n; r += T) mult[r] = r == k ? 0.0 : A[(long)r * n + k];
-        __syncthreads();
-        for (long e = t; e < (long)n * n; e += T) {
-            const int r = (int)(e / n), c = (int)(e % n);
-            const double m = mult[r];
-            if (m != 0.0) {
-                A[e] -= m * A[(long)k * n + c];
-                M[e] -= m * M[(long)k * n + c];
-            }
-        }
-        __syncthreads();
+    __syncthreads();
+    const double inv = 1.0 / A[(long)k * n + k];
+    __syncthreads();
+    for (int c = t; c < n; c += T) {
+        A[(long)k * n + c] *= inv;
+        M[(long)k * n + c] *= inv;
+    }
+    __syncthreads();
+    for (int r = t; r < n; r += T) mult[r] = r == k ? 0.0 : A[(long)r * n + k];
+}
+
+__global__ __launch_bounds__(256) void k_gj_eliminate(int n, int k, double *A, double *M, const double *mult,
+                                                      const int *fail) {
+    if (*fail) return;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)n * n) return;
+    const int r = (int)(e / n), c = (int)(e % n);
+    const double m = mult[r];
+    if (m != 0.0) {
+        A[e] -= m * A[(long)k * n + c];
+        M[e] -= m * M[(long)k * n + c];
     }
 }
 
@@ -523,9 +537,15 @@ hipError_t launch_coarse_assemble(int D, int Nb, double dx, const int *map, cons
     return hipGetLastError();
 }
 
-hipError_t launch_gauss_jordan(int n, double *A, double *M, double *S, int *fail, hipStream_t s) {
-    if (n > 512) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s, n, A, M, S, fail);
+hipError_t launch_gauss_jordan(int n, double *A, double *M, double *S, double *mult, int *fail, hipStream_t s) {
+    if (n < 1 || n > 4096) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gj_scale, dim3(n), dim3(256), 0, s, n, A, M, S);
+    const long ne = (long)n * n;
+    for (int k = 0; k < n; k++) {
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, s, n, k, A, M, mult, fail);
+        hipLaunchKernelGGL(k_gj_eliminate, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, n, k, A, M, mult,
+                           (const int *)fail);
+    }
     return hipGetLastError();
 }
 
