@@ -152,6 +152,13 @@ __device__ __forceinline__ bool on_block_face(int i, int j, int k) {
 
 // right-hand side of this workgroup: grid y walks the launch's lane list
 // (the running right-hand sides), or all of them when there is none
+// |r| for the max-norm reductions, NaN as +Inf (fmax would drop a NaN, so a
+// non-finite residual must enter the max as +Inf)
+__device__ __forceinline__ double abs_nan_inf(double r) {
+    const double a = fabs(r);
+    return a == a ? a : __longlong_as_double(0x7ff0000000000000ll);
+}
+
 template <typename T>
 __device__ __forceinline__ int rhs_of(const LV<T> &L) {
     return L.lanes ? L.lanes[blockIdx.y] : (int)blockIdx.y;
@@ -602,7 +609,7 @@ __global__ __launch_bounds__((Blk<D, N>::THREADS)) void k_residual_max(LV<T> L, 
         const long long me = base + split_of<D, N>(i, j, k);
         const T own = ZERO ? T(0) : phi[me];
         const T lphi = apply_op<T, D, N, ZERO>(L, Lc, phi, phic, base, snb, P, smo, i, j, k, own);
-        m = fmax(m, fabs((double)(g[me] - lphi)));
+        m = fmax(m, abs_nan_inf((double)(g[me] - lphi)));
     }
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
     if (threadIdx.x % 64 == 0) wmax[threadIdx.x / 64] = m;
@@ -796,7 +803,7 @@ __global__ __launch_bounds__((Blk<D, N>::THREADS)) void k_defect(LV<double> L, L
         const long long me = base + split_of<D, N>(i, j, k);
         const double own = phi[me];
         const double r = g[me] - apply_op<double, D, N, false>(L, Lc, phi, phic, base, snb, P, smo, i, j, k, own);
-        m = fmax(m, fabs(r));
+        m = fmax(m, abs_nan_inf(r));
         g32[me] = (float)r;
         p32[me] = 0.0f;
     }
@@ -1984,7 +1991,7 @@ __global__ __launch_bounds__(2 * NTC) __attribute__((amdgpu_waves_per_eu(LATE ? 
     if (LATE) load_cells<T, PER, NTC, V2>(g + base, t, gv);
     double mx = 0.0;
 #pragma unroll
-    for (int m = 0; m < PER; m++) mx = fmax(mx, fabs((double)(gv[m] - lp[m])));
+    for (int m = 0; m < PER; m++) mx = fmax(mx, abs_nan_inf((double)(gv[m] - lp[m])));
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
     if (threadIdx.x % 64 == 0) wmax[threadIdx.x / 64] = mx;
     __syncthreads();
@@ -2039,7 +2046,7 @@ __global__ __launch_bounds__(256) void k_residual_max3(LV<T> L, LV<T> Lc, unsign
             }
         }
 #pragma unroll
-        for (int m = 0; m < PER; m++) mx = fmax(mx, fabs((double)(gv[m] - lp[m])));
+        for (int m = 0; m < PER; m++) mx = fmax(mx, abs_nan_inf((double)(gv[m] - lp[m])));
         __syncthreads();
     }
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
@@ -2154,7 +2161,7 @@ __global__ __launch_bounds__(256) void k_defect3(LV<double> L, LV<double> Lc, LV
         for (int m = 0; m < PER; m++) {
             const int s = c * B::HALF + threadIdx.x + 256 * m;
             const double r = gv[m] - lp[m];
-            mx = fmax(mx, fabs(r));
+            mx = fmax(mx, abs_nan_inf(r));
             g32[s] = (float)r;
             p32[s] = 0.0f;
         }
@@ -2210,7 +2217,7 @@ __global__ __launch_bounds__(2 * NTC) __attribute__((amdgpu_waves_per_eu(LATE ? 
 #pragma unroll
     for (int m = 0; m < PER; m++) {
         const double r = gv[m] - lp[m];
-        mx = fmax(mx, fabs(r));
+        mx = fmax(mx, abs_nan_inf(r));
         r32[m] = (float)r;
         z32[m] = 0.0f;
     }
