@@ -176,9 +176,12 @@ void octmg_ctx_destroy(octmg_ctx c);
  *     right-hand sides number at most pair_max_blocks, a level made of one
  *     16^3 block below the finest level also runs its steps of a V-cycle in
  *     one 1024-thread workgroup per rhs (one launch per leg).  0: never.
- *     Every value gives the same iterates.  Default 1 << 30 (every launch). */
+ *     Every value gives the same iterates.  Default 1 << 30 (every launch).
+ *   prolong_fused: 1 (default) runs the prolongation of a 3D V-cycle and
+ *     the red half sweep after it as one launch (the black values are
+ *     prolonged on the fly), 0 as two.  The same iterates either way. */
 typedef struct octmg_launch_config {
-    int block_order, bottom_kind, bottom_max_blocks, graph_mode, pair_max_blocks;
+    int block_order, bottom_kind, bottom_max_blocks, graph_mode, pair_max_blocks, prolong_fused;
 } octmg_launch_config;
 octmg_status octmg_state_set_launch(octmg_state s, const octmg_launch_config *c);
 octmg_status octmg_state_get_launch(octmg_state s, octmg_launch_config *c);

@@ -126,10 +126,12 @@ namespace {
 
 struct Fields64 {
     double *phi = nullptr, *g = nullptr, *old = nullptr, *b = nullptr, *bcv = nullptr;
+    double *bp = nullptr;  // prolonged black values of a fused prolongation (launch_prolong_gs)
     double *pb = nullptr;  // phi_b at the level's interface points (for the gradient)
 };
 struct Fields32 {
     float *phi = nullptr, *g = nullptr, *old = nullptr;
+    float *bp = nullptr;
 };
 
 }  // namespace
@@ -195,6 +197,7 @@ struct octmg_state_s {
     int tuned_graph = 0;                       // graph mode recommended by octmg_autotune
     int fused_max_blocks = 0;                  // levels with <= this many blocks run fused (0: off)
     int pair_max_blocks = 1 << 30;             // LV::pair_max of every level
+    int prolong_fused = 1;                     // V-cycle prolongation fused with the next red half sweep (3D)
     int fused_top = 0;                         // highest fused level (0: none)
     int fused_grid64 = 0, fused_grid32 = 0;    // co-resident workgroups of the fused kernel
     SmallLevels<double> *d_small64 = nullptr;  // device copies of the fused level tables
@@ -308,7 +311,11 @@ struct Engine {
     // group's time is shared evenly by its launches.
     // fas_first: the first red half sweep also forms the level's FAS
     // right-hand side (see restrict_only)
-    octmg_status smooth(int il, int steps, bool fas_first = false) {
+    // after_prolong: the first red half sweep has run inside the fused
+    // prolongation (prolong_fused); the first black one takes its cells' own
+    // values for the ghosts from the prolonged black values it left.  The
+    // timed group then holds the remaining 2 steps - 1 half sweeps.
+    octmg_status smooth(int il, int steps, bool fas_first = false, bool after_prolong = false) {
         Profile *P = s->prof;
         const bool timed = P && P->on && il == (int)s->geom->L.size() - 1 && steps > 0;
         hipEvent_t a = nullptr, b = nullptr;
@@ -319,11 +326,15 @@ struct Engine {
         }
         for (int k = 0; k < steps; k++)
             for (int color = 0; color < 2; color++) {
-                if (fas_first && k == 0 && color == 0)
+                if (after_prolong && k == 0 && color == 0) continue;
+                if (fas_first && k == 0 && color == 0) {
                     HIPCK(launch_fas_gs<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1),
                                            s->geom->tree.adaptive ? 1 : 0, s->n_launch, st));
-                else
-                    HIPCK(launch_gs_half<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1), color, s->n_launch, st));
+                } else {
+                    LV<T> v = lvT<T>(s, il);
+                    if (after_prolong && k == 0) v.own = bp_of(il);
+                    HIPCK(launch_gs_half<T>(D(), Nb(il), v, lvT<T>(s, il - 1), color, s->n_launch, st));
+                }
                 if (P && P->on) {
                     const GeomLevel &G = s->geom->L[il];
                     P->updates += 0.5 * (double)G.nblocks * G.cpb * s->n_launch;
@@ -332,7 +343,25 @@ struct Engine {
         if (timed) {
             HIPCK(hipEventRecord(b, st));
             P->pending.push_back({a, b});
-            P->launches.push_back(2 * steps);
+            P->launches.push_back(2 * steps - (after_prolong ? 1 : 0));
+        }
+        return OCTMG_OK;
+    }
+    T *bp_of(int il) const;
+    // the prolongation into il and its first red half sweep in one launch:
+    // 3D levels smoothed by separate launches, with post-smoothing
+    bool prolong_fusable(int il) const {
+        return D() == 3 && s->prolong_fused && s->n_up >= 1 && !single_block(il) && bp_of(il) != nullptr &&
+               (Nb(il) == 16 || (Nb(il) == 8 && Nb(il - 1) == 8));
+    }
+    octmg_status prolong_gs(int il) {
+        LV<T> v = lvT<T>(s, il);
+        v.own = bp_of(il);
+        HIPCK(launch_prolong_gs<T>(Nb(il), Nb(il - 1), v, lvT<T>(s, il - 1), s->n_launch, st));
+        Profile *P = s->prof;
+        if (P && P->on) {
+            const GeomLevel &G = s->geom->L[il];
+            P->updates += 0.5 * (double)G.nblocks * G.cpb * s->n_launch;
         }
         return OCTMG_OK;
     }
@@ -438,6 +467,11 @@ struct Engine {
         if (ft >= 1) STCK(fused(ft));
         else STCK(coarse_solve(fas_coarse && top >= 1 ? 1 : 0));
         for (int il = std::max(ft, 0) + 1; il <= top; il++) {
+            if (prolong_fusable(il)) {
+                STCK(prolong_gs(il));
+                STCK(smooth(il, s->n_up, false, true));
+                continue;
+            }
             STCK(prolong(il, 0));
             STCK(single_block(il) ? single_block_up(il) : smooth(il, s->n_up));
         }
@@ -480,6 +514,10 @@ octmg_status Engine<float>::fused(int top) {
     HIPCK(launch_small_vcycle<float>(s->d_small32, top, grid, st));
     return OCTMG_OK;
 }
+template <>
+double *Engine<double>::bp_of(int il) const { return s->f64[il].bp; }
+template <>
+float *Engine<float>::bp_of(int il) const { return s->f32.empty() ? nullptr : s->f32[il].bp; }
 template <>
 hipError_t Engine<double>::fill(double *p, long long n) { return launch_fill(p, n, 0.0, st); }
 template <>
@@ -1198,6 +1236,7 @@ octmg_status octmg_state_create(octmg_geom g, int n_rhs, int precision, octmg_st
         HIPCK(s->pool.alloc(&F.phi, n));
         HIPCK(s->pool.alloc(&F.g, n));
         HIPCK(s->pool.alloc(&F.old, n));
+        if (D == 3) HIPCK(s->pool.alloc(&F.bp, n));
         HIPCK(s->pool.alloc(&F.b, std::max(1, L.nrec)));
         HIPCK(s->pool.alloc(&F.bcv, (size_t)2 * D * L.nface));
         HIPCK(s->pool.alloc(&F.pb, (size_t)std::max<long long>(1, L.npts)));
@@ -1212,6 +1251,7 @@ octmg_status octmg_state_create(octmg_geom g, int n_rhs, int precision, octmg_st
             HIPCK(s->pool.alloc(&H.phi, n));
             HIPCK(s->pool.alloc(&H.g, n));
             HIPCK(s->pool.alloc(&H.old, n));
+            if (D == 3) HIPCK(s->pool.alloc(&H.bp, n));
             HIPCK(launch_fillf(H.phi, n, 0.0f, nullptr));
             HIPCK(launch_fillf(H.g, n, 0.0f, nullptr));
             HIPCK(launch_fillf(H.old, n, 0.0f, nullptr));
@@ -1315,8 +1355,10 @@ octmg_status octmg_state_set_launch(octmg_state s, const octmg_launch_config *c)
         return fail(OCTMG_ERR_INVALID, "bad launch configuration");
     if (c->bottom_kind == 1 && c->graph_mode != 0)
         return fail(OCTMG_ERR_INVALID, "the cooperative bottom launch cannot be captured");
+    if (c->prolong_fused != 0 && c->prolong_fused != 1) return fail(OCTMG_ERR_INVALID, "bad launch configuration");
     s->block_order = c->block_order;
     s->pair_max_blocks = c->pair_max_blocks;
+    s->prolong_fused = c->prolong_fused;
     s->tuned_graph = c->graph_mode;
     s->fused_max_blocks = c->bottom_kind ? c->bottom_max_blocks : 0;
     HIPCK(hipSetDevice(s->geom->device));
@@ -1330,6 +1372,7 @@ octmg_status octmg_state_get_launch(octmg_state s, octmg_launch_config *c) {
     c->bottom_max_blocks = s->fused_max_blocks;
     c->graph_mode = s->tuned_graph;
     c->pair_max_blocks = s->pair_max_blocks;
+    c->prolong_fused = s->prolong_fused;
     return OCTMG_OK;
 }
 
@@ -1895,8 +1938,8 @@ static bool tune_lookup(const std::string &path, const std::string &key, octmg_l
         char *tab = std::strchr(line, '\t');
         if (!tab || std::string(line, tab - line) != key) continue;
         octmg_launch_config t{};
-        if (std::sscanf(tab + 1, "%d %d %d %d %d", &t.block_order, &t.bottom_kind, &t.bottom_max_blocks, &t.graph_mode,
-                        &t.pair_max_blocks) == 5) {
+        if (std::sscanf(tab + 1, "%d %d %d %d %d %d", &t.block_order, &t.bottom_kind, &t.bottom_max_blocks,
+                        &t.graph_mode, &t.pair_max_blocks, &t.prolong_fused) == 6) {
             *c = t;
             found = true;
         }
@@ -1909,8 +1952,8 @@ static void tune_record(const std::string &path, const std::string &key, const o
     std::lock_guard<std::mutex> lk(g_tune_mu);
     FILE *f = std::fopen(path.c_str(), "a");
     if (!f) return;  // an unwritable cache only costs the next tuning run
-    std::fprintf(f, "%s\t%d %d %d %d %d %.4f\n", key.c_str(), c.block_order, c.bottom_kind, c.bottom_max_blocks,
-                 c.graph_mode, c.pair_max_blocks, ms);
+    std::fprintf(f, "%s\t%d %d %d %d %d %d %.4f\n", key.c_str(), c.block_order, c.bottom_kind, c.bottom_max_blocks,
+                 c.graph_mode, c.pair_max_blocks, c.prolong_fused, ms);
     std::fclose(f);
 }
 
@@ -1927,21 +1970,21 @@ octmg_status octmg_autotune(octmg_state s, const octmg_solve_opts *o, int reps, 
     std::vector<octmg_launch_config> cand;
     constexpr int all = 1 << 30;
     for (int order = 0; order < 3; order++) {
-        cand.push_back({order, 0, 0, 0, all});
-        cand.push_back({order, 0, 0, 1, all});
+        cand.push_back({order, 0, 0, 0, all, 1});
+        cand.push_back({order, 0, 0, 1, all, 1});
         if (s->geom->tree.D == 3) {
-            cand.push_back({order, 1, 8, 0, all});
-            cand.push_back({order, 1, 64, 0, all});
+            cand.push_back({order, 1, 8, 0, all, 1});
+            cand.push_back({order, 1, 64, 0, all, 1});
         }
     }
     if (s->geom->tree.D == 3) {
-        cand.push_back({0, 0, 0, 0, 0});
-        cand.push_back({0, 0, 0, 1, 0});
+        cand.push_back({0, 0, 0, 0, 0, 1});
+        cand.push_back({0, 0, 0, 1, 0, 1});
     }
     // the whole solve as one captured launch (max_cycles cycles, convergence
     // tested on the device), with the 512- and the 256-thread kernels
-    cand.push_back({0, 0, 0, 2, all});
-    if (s->geom->tree.D == 3) cand.push_back({0, 0, 0, 2, 0});
+    cand.push_back({0, 0, 0, 2, all, 1});
+    if (s->geom->tree.D == 3) cand.push_back({0, 0, 0, 2, 0, 1});
     if (n_candidates) *n_candidates = (int)cand.size();
     double best_ms = 0.0;
     int best_i = -1;
@@ -2204,7 +2247,8 @@ int geom_device(octmg_geom g) { return g->device; }
 size_t lane_bytes(octmg_geom g, int precision) {
     size_t cells = 0;
     for (const GeomLevel &L : g->L) cells += (size_t)L.nblocks * L.cpb;
-    return cells * (3 * sizeof(double) + (precision == OCTMG_MIXED ? 3 * sizeof(float) : 0)) +
+    const size_t nf = g->tree.D == 3 ? 4 : 3;  // phi, g, old (and bp in 3D)
+    return cells * (nf * sizeof(double) + (precision == OCTMG_MIXED ? nf * sizeof(float) : 0)) +
            (1 + (size_t)norm_slot_words(1) + 1 + 64) * sizeof(double) + 2 * sizeof(int);
 }
 

@@ -1123,15 +1123,17 @@ constexpr bool cell_pairs() {
 // NT threads stage the colour (t < NT); the faces take the first N*N.
 // With V2 a thread's cells come in adjacent pairs (slots of cell_of), the
 // staged interior loaded with one 2-element vector access per pair.
+// own: the reading colour's values for the domain ghosts (colour-compact,
+// (k N + j) N/2 + i/2; default: that colour of the block in phi).
 template <typename T, int N, bool ZERO, int NT = 256, bool V2 = false>
 __device__ __forceinline__ void stage_colour(T *tile, const LV<T> &L, const T *__restrict__ phi, int blk,
                                              const int *nbk, int4 P, int col, int t,
-                                             const T *interior = nullptr) {
+                                             const T *interior = nullptr, const T *own = nullptr) {
     using B = Blk<3, N>;
     using CT = ColTile<N>;
     constexpr int NH = N / 2, PER = B::HALF / NT;
     const int oc = col * B::HALF, uc = (1 - col) * B::HALF;
-    const T *__restrict__ own_col = phi + (long long)blk * B::CPB + uc;
+    const T *__restrict__ own_col = own ? own : phi + (long long)blk * B::CPB + uc;
     T r[PER];
     if (ZERO) {
         for (int e = t; e < CT::SIZE; e += NT) tile[e] = T(0);
@@ -1232,12 +1234,15 @@ __device__ __forceinline__ void gs_half3_body(const LV<T> &L, const LV<T> &Lc, i
     load_cells<T, PER, NT, V2, true>(gm, threadIdx.x, gv);
 #pragma unroll
     for (int m = 0; m < PER; m++) ri[m] = mo >= 0 ? L.map[mo + color * B::HALF + cell_of<NT, V2>(threadIdx.x, m)] : -1;
-    stage_colour<T, N, false, NT, V2>(tile, L, phi, blk, nbk, P, 1 - color, threadIdx.x);
+    // the cells' own values for their ghosts: phi, or after a fused
+    // prolongation and red half sweep (black) the prolonged values in L.own
+    const T *own = L.own ? L.own + (long long)rhs * L.fstride + base + color * B::HALF : nullptr;
+    stage_colour<T, N, false, NT, V2>(tile, L, phi, blk, nbk, P, 1 - color, threadIdx.x, nullptr, own);
     __syncthreads();
     T *__restrict__ dst = phi + base + color * B::HALF;
     if (any_coarser(nbk)) {
         const T *phic = Lc.phi ? Lc.phi + (long long)rhs * Lc.fstride : nullptr;
-        coarser_face_ghosts<T, N, NT>(tile, Lc, dst, phic, nbk, P, color, threadIdx.x);
+        coarser_face_ghosts<T, N, NT>(tile, Lc, own ? own : dst, phic, nbk, P, color, threadIdx.x);
         __syncthreads();
     }
     const T inv6 = T(1) / T(6);
@@ -2119,6 +2124,183 @@ __global__ __launch_bounds__(NT) void k_prolong3(LV<T> L, LV<T> Lc) {
     prolong3_body<T, N, NC, SOL, NT>(L, Lc, block_of(L), rhs_of(L), et);
 }
 
+// Prolongation of the coarse correction (as k_prolong3) fused with the red
+// half sweep that follows it (as k_gs_half3, colour 0), 3D.  The red cells'
+// prolonged values are only read where a cell forms its own ghost (domain
+// and refinement faces), and the black cells' prolonged values only by this
+// half sweep (as neighbours, the face halo included: the fine cells just
+// outside the block interpolate from the block's one-cell coarse halo) and
+// by the next black half sweep, for its own ghosts.  So the black values
+// are prolonged in LDS and not stored in phi (the next black half sweep
+// overwrites them); blocks with a domain or refinement face store them in
+// L.own, from where that black half sweep takes its own values.  Every
+// value is formed with the same operations in the same order as by the two
+// separate kernels.
+template <typename T, int N>
+__device__ __forceinline__ T prolonged(const T *et, int i, int j, int k) {
+    constexpr int E = N / 2 + 2;
+    const int ci = (i >> 1) + 1, cj = (j >> 1) + 1, ck = (k >> 1) + 1;
+    const int ox = (i & 1) ? 1 : -1, oy = (j & 1) ? 1 : -1, oz = (k & 1) ? 1 : -1;
+    T e = T(0);
+#pragma unroll
+    for (int dl = 0; dl < 8; dl++) {
+        const int ax = dl & 1, ay = (dl >> 1) & 1, az = (dl >> 2) & 1;
+        const T w = (ax ? T(0.25) : T(0.75)) * (ay ? T(0.25) : T(0.75)) * (az ? T(0.25) : T(0.75));
+        e = e + w * et[((ck + az * oz) * E + (cj + ay * oy)) * E + (ci + ax * ox)];
+    }
+    return e;
+}
+
+template <typename T, int N, int NC, int NT, bool V2>
+__device__ __forceinline__ void prolong_gs3_body(const LV<T> &L, const LV<T> &Lc, int blk, int rhs, T *tile, T *et,
+                                                 T *rp) {
+    using B = Blk<3, N>;
+    using CT = ColTile<N>;
+    constexpr int NH = N / 2, H = N / 2, E = H + 2, ESZ = E * E * E, PER = B::HALF / NT,
+                  EPER = (ESZ + NT - 1) / NT;
+    const int4 P = L.pos[blk];
+    int nbk[6];
+    face_ids<T, N>(L, blk, nbk);
+    const int mo = L.map_off ? L.map_off[blk] : -1;
+    const int act = L.active ? L.active[rhs] : 1;
+    tables_loaded(act, 1, P, nbk, mo);
+    if (!act) return;
+    bool ghosts = false;  // a domain or refinement face: cells form ghosts from their own values
+#pragma unroll
+    for (int d = 0; d < 6; d++) ghosts |= nbk[d] < 0;
+    T *__restrict__ phi = L.phi + (long long)rhs * L.fstride;
+    const long long base = (long long)blk * B::CPB;
+    const T *phic = Lc.phi + (long long)rhs * Lc.fstride;
+    const T *oldc = Lc.old + (long long)rhs * Lc.fstride;
+    const int t = threadIdx.x;
+    // loads: g of the red cells, record rows, the coarse correction with
+    // its one-cell halo, the red cells' values where ghosts need them
+    T gv[PER], ro[PER];
+    int ri[PER];
+    load_cells<T, PER, NT, V2, true>(L.g + (long long)rhs * L.fstride + base, t, gv);
+#pragma unroll
+    for (int m = 0; m < PER; m++) ri[m] = mo >= 0 ? L.map[mo + cell_of<NT, V2>(t, m)] : -1;
+    const int C0[3] = {P.x * H, P.y * H, P.z * H};
+    T ev[EPER];
+#pragma unroll
+    for (int m = 0; m < EPER; m++) {
+        const int e = t + NT * m;
+        if (e < ESZ) {
+            const int x = e % E, y = (e / E) % E, z = e / (E * E);
+            ev[m] = coarse_e<T, 3, NC, false>(Lc, phic, oldc, C0[0] + x - 1, C0[1] + y - 1, C0[2] + z - 1);
+        }
+    }
+    if (ghosts) load_cells<T, PER, NT, V2>(phi + base, t, ro);
+    // without ghosts the black colour and its halos are staged right away
+    // (their loads overlap the coarse ones); the own values are never read
+    if (!ghosts) stage_colour<T, N, false, NT, V2>(tile, L, phi, blk, nbk, P, 1, t);
+#pragma unroll
+    for (int m = 0; m < EPER; m++) {
+        const int e = t + NT * m;
+        if (e < ESZ) et[e] = ev[m];
+    }
+    __syncthreads();
+    if (ghosts) {
+        // prolonged red values, then the black colour staged with the domain
+        // ghosts of the red cells formed from them
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            int i, j, k;
+            const int q = cell_of<NT, V2>(t, m);
+            q_to_ijk<N>(0, q, i, j, k);
+            rp[q] = ro[m] + prolonged<T, N>(et, i, j, k);
+        }
+        __syncthreads();
+        stage_colour<T, N, false, NT, V2>(tile, L, phi, blk, nbk, P, 1, t, nullptr, rp);
+        __syncthreads();
+    }
+    // prolong the staged black values: the block's cells and the halo cells
+    // of same-level neighbours (domain ghosts are final; refinement-face
+    // slots are filled below)
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        int i, j, k;
+        const int q = cell_of<NT, V2>(t, m);
+        q_to_ijk<N>(1, q, i, j, k);
+        const int a = CT::at(k, j, q % NH);
+        tile[a] = tile[a] + prolonged<T, N>(et, i, j, k);
+    }
+    {
+        const int fh = t % NH, fr = t / NH;  // y/z face entries, as in stage_colour
+        if (t < N * NH) {
+            const int k = fr, jz = fr;
+            if (nbk[2] >= 0) {
+                const int a = CT::at(k, -1, fh);
+                tile[a] = tile[a] + prolonged<T, N>(et, 2 * fh + (k & 1), -1, k);
+            }
+            if (nbk[3] >= 0) {
+                const int a = CT::at(k, N, fh);
+                tile[a] = tile[a] + prolonged<T, N>(et, 2 * fh + ((N - 1 + k) & 1), N, k);
+            }
+            if (nbk[4] >= 0) {
+                const int a = CT::at(-1, jz, fh);
+                tile[a] = tile[a] + prolonged<T, N>(et, 2 * fh + (jz & 1), jz, -1);
+            }
+            if (nbk[5] >= 0) {
+                const int a = CT::at(N, jz, fh);
+                tile[a] = tile[a] + prolonged<T, N>(et, 2 * fh + ((jz + N - 1) & 1), jz, N);
+            }
+        }
+        const int xj = t % N, xk = t / N;  // x face entries
+        if (t < N * N) {
+            const int xp = (xj + xk) & 1, nbx = xp ? nbk[1] : nbk[0];
+            if (nbx >= 0) {
+                const int a = CT::at(xk, xj, xp ? NH : -1);
+                tile[a] = tile[a] + prolonged<T, N>(et, xp ? N : -1, xj, xk);
+            }
+        }
+    }
+    __syncthreads();
+    if (any_coarser(nbk)) {
+        coarser_face_ghosts<T, N, NT>(tile, Lc, rp, phic, nbk, P, 0, t);
+        __syncthreads();
+    }
+    // the red half sweep on the prolonged black values
+    const T inv6 = T(1) / T(6);
+    T nv[PER];
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        const int q = cell_of<NT, V2>(t, m);
+        int i, j, k;
+        T v[6];
+        tile_neighbours<T, N>(tile, 0, q, i, j, k, v);
+        if (ri[m] < 0) {
+            nv[m] = (((v[0] + v[1]) + (v[2] + v[3])) + (v[4] + v[5]) - L.dx2 * gv[m]) * inv6;
+        } else {
+            const T *r = L.rec + 8 * (long long)ri[m];
+            T sum = T(0);
+#pragma unroll
+            for (int d = 0; d < 6; d++) sum += r[d] * v[d];
+            const T bt = L.b ? L.b[ri[m]] : T(0);
+            nv[m] = (gv[m] - bt - sum) * r[7];
+        }
+    }
+    store_cells<T, PER, NT, V2>(phi + base, t, nv);
+    if (ghosts) {  // prolonged black values for the next black half sweep's ghosts
+        T bv[PER];
+#pragma unroll
+        for (int m = 0; m < PER; m++) {
+            const int q = cell_of<NT, V2>(t, m);
+            bv[m] = tile[CT::at(q / (NH * N), (q / NH) % N, q % NH)];
+        }
+        store_cells<T, PER, NT, V2>(L.own + (long long)rhs * L.fstride + base + B::HALF, t, bv);
+    }
+}
+
+template <typename T, int N, int NC, int NT, bool V2>
+__global__ __launch_bounds__(NT) void k_prolong_gs3(LV<T> L, LV<T> Lc) {
+    constexpr int E = N / 2 + 2;
+    __shared__ T tile[ColTile<N>::SIZE];
+    __shared__ T et[E * E * E];
+    __shared__ T rp[Blk<3, N>::HALF];
+    prolong_gs3_body<T, N, NC, NT, V2>(L, Lc, block_of(L), rhs_of(L), tile, et, rp);
+}
+
 // mixed precision defect (FP64): g32 = g - L phi on a leaf block, phi32 = 0
 template <int N>
 __global__ __launch_bounds__(256) void k_defect3(LV<double> L, LV<double> Lc, LV<float> L32, const int *lb,
@@ -2546,6 +2728,26 @@ hipError_t launch_prolong(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc,
 }
 
 template <typename T>
+hipError_t launch_prolong_gs(int N, int Nc, const LV<T> &L, const LV<T> &Lc, int nrhs, hipStream_t s) {
+    if (L.nblocks == 0) return hipSuccess;
+    if (!L.own) return hipErrorInvalidValue;
+    dim3 grid(L.nblocks, nrhs);
+    const bool wide = N == 16 && (long long)L.nblocks * nrhs <= L.pair_max;
+    if (N == 16 && Nc == 16) {
+        if (wide) hipLaunchKernelGGL((k_prolong_gs3<T, 16, 16, 512, cell_pairs<16>()>), grid, dim3(512), 0, s, L, Lc);
+        else hipLaunchKernelGGL((k_prolong_gs3<T, 16, 16, 256, false>), grid, dim3(256), 0, s, L, Lc);
+    } else if (N == 16 && Nc == 8) {
+        if (wide) hipLaunchKernelGGL((k_prolong_gs3<T, 16, 8, 512, cell_pairs<16>()>), grid, dim3(512), 0, s, L, Lc);
+        else hipLaunchKernelGGL((k_prolong_gs3<T, 16, 8, 256, false>), grid, dim3(256), 0, s, L, Lc);
+    } else if (N == 8 && Nc == 8) {
+        hipLaunchKernelGGL((k_prolong_gs3<T, 8, 8, 256, false>), grid, dim3(256), 0, s, L, Lc);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_coarse_solve(int D, const LV<T> &L0, const double *M, const double *S, int fas, int nrhs,
                                hipStream_t s) {
     if (D == 3) {
@@ -2746,6 +2948,7 @@ hipError_t launch_check_finite(const double *p, long long n, int *flag, hipStrea
     template hipError_t launch_fas_gs<T>(int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t);             \
     template hipError_t launch_single_block<T>(int, const LV<T> &, const LV<T> &, int, int, int, int, int, hipStream_t); \
     template hipError_t launch_prolong<T>(int, int, int, const LV<T> &, const LV<T> &, int, int, hipStream_t);      \
+    template hipError_t launch_prolong_gs<T>(int, int, const LV<T> &, const LV<T> &, int, hipStream_t);            \
     template hipError_t launch_coarse_solve<T>(int, const LV<T> &, const double *, const double *, int, int, hipStream_t); \
     template hipError_t launch_residual_max<T>(int, int, const LV<T> &, const LV<T> &, int, unsigned long long *, int, hipStream_t);
 OCTMG_INST(double)

@@ -71,6 +71,10 @@ struct LV {
     const T *b;          // [nrec] moved boundary term (nullptr: homogeneous)
     const T *bcv;        // [2D][nface] domain face values (nullptr: homogeneous)
     T *phi, *g, *old;
+    // prolonged black values that launch_prolong_gs leaves for the next
+    // black half sweep (which then forms its cells' ghosts from them); set on
+    // that sweep's view only (nullptr: ghosts from phi)
+    T *own;
     long long fstride;
     const int *active;   // [nrhs] nonzero = right-hand side still iterating (nullptr: all)
     const int *lanes;    // [grid y] right-hand side of each grid row (nullptr: row = rhs)
@@ -122,6 +126,13 @@ hipError_t launch_restrict_phi(int D, int N, int Nc, const LV<T> &L, const LV<T>
 template <typename T>
 hipError_t launch_prolong(int D, int N, int Nc, const LV<T> &L, const LV<T> &Lc, int solution_mode, int nrhs,
                           hipStream_t s);
+// 3D, V-cycle correction: launch_prolong (solution_mode 0) and the red half
+// sweep after it in one launch; the black values stay unprolonged in phi
+// and must be followed by launch_gs_half(colour 1) on a view with own = the
+// same L.own (blocks with domain or refinement faces store their prolonged
+// black values there).  Same results as the two separate launches.
+template <typename T>
+hipError_t launch_prolong_gs(int N, int Nc, const LV<T> &L, const LV<T> &Lc, int nrhs, hipStream_t s);
 template <typename T>
 // fas (3D): form the level's FAS right-hand side g + L phi from phi = old
 // inside the solve (after launch_restrict_fas without launch_fas_rhs)
