@@ -122,17 +122,20 @@ def rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-def leg_mixed(G, w, phi64, t64, stream, steps, rtol):
-    """Same problem, FP32 inner cycles inside FP64 defect correction."""
+def leg_mixed(G, w, phi64, t64, stream, steps, rtol, tune=True):
+    """Same problem, FP32 inner cycles inside FP64 defect correction, in the
+    launch configuration the autotuner picks for it."""
     from paper_2205_09411_amd import octmg
     S = octmg.State(G, 1, octmg.MIXED)
     S.set_boundary_fn(w.iface_value, w.domain_value)
     xyz, _ = G.leaf_coords()
     S.set_rhs(w.rhs(xyz))
-    dt, rep = timed_solves(S, steps, stream, rtol=rtol, max_cycles=40, graph_mode=1)
+    tuned, cand_ms = S.autotune(rtol=rtol, reps=2, stream=stream) if tune else (S.get_launch(), [])
+    dt, rep = timed_solves(S, steps, stream, rtol=rtol, max_cycles=40, graph_mode=tuned["graph_mode"])
     phi = S.get_solution()
     MIXED_PHI["phi"] = phi
     return {"solves_per_s": round(1 / dt, 3), "ms_per_solve": round(dt * 1e3, 3), "speedup_vs_fp64": round(t64 / dt, 3),
+            "launch": {"chosen": tuned, "autotune_ms_per_solve": [round(v, 3) for v in cand_ms]},
             "outer_iterations": rep.cycles, "final_rel_residual": rep.r_final / rep.r0,
             "rel_diff_vs_fp64_solution": rel(phi, phi64), "max_err_vs_exact": float(np.abs(phi - w.exact(xyz)).max())}
 
@@ -718,7 +721,7 @@ def main():
         t = time.perf_counter()
         try:
             if leg == "mixed":
-                legs[leg] = leg_mixed(G, w, phi, dt / args.steps, stream, args.steps, args.rtol)
+                legs[leg] = leg_mixed(G, w, phi, dt / args.steps, stream, args.steps, args.rtol, not args.no_tune)
             elif leg == "batched":
                 legs[leg] = leg_batched(stream, args.rtol)
             elif leg == "adaptive":

@@ -2292,8 +2292,10 @@ __device__ __forceinline__ void prolong_gs3_body(const LV<T> &L, const LV<T> &Lc
     }
 }
 
+// 512 threads: at most 80 VGPRs, three workgroups per CU (LDS allows three)
 template <typename T, int N, int NC, int NT, bool V2>
-__global__ __launch_bounds__(NT) void k_prolong_gs3(LV<T> L, LV<T> Lc) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 6 : 1))) void k_prolong_gs3(LV<T> L,
+                                                                                                           LV<T> Lc) {
     constexpr int E = N / 2 + 2;
     __shared__ T tile[ColTile<N>::SIZE];
     __shared__ T et[E * E * E];
@@ -2592,7 +2594,7 @@ hipError_t launch_gs_half(int D, int N, const LV<T> &L, const LV<T> &Lc, int col
         hipLaunchKernelGGL((k_gs_half3<T, 16, 512, cell_pairs<16>()>), grid, dim3(512), 0, s, L, Lc, color);
         return hipGetLastError();
     }
-#define GS3(N_) OCTMG_DN(3, N_, hipLaunchKernelGGL((k_gs_half3<T, N_, 256, false>), grid, dim3(256), 0, s, L, Lc, color))
+#define GS3(N_) OCTMG_DN(3, N_, hipLaunchKernelGGL((k_gs_half3<T, N_, 256, cell_pairs<N_>()>), grid, dim3(256), 0, s, L, Lc, color))
     GS3(16) GS3(8) GS(2, 8) GS(2, 16)
 #undef GS3
 #undef GS
@@ -2735,10 +2737,10 @@ hipError_t launch_prolong_gs(int N, int Nc, const LV<T> &L, const LV<T> &Lc, int
     const bool wide = N == 16 && (long long)L.nblocks * nrhs <= L.pair_max;
     if (N == 16 && Nc == 16) {
         if (wide) hipLaunchKernelGGL((k_prolong_gs3<T, 16, 16, 512, cell_pairs<16>()>), grid, dim3(512), 0, s, L, Lc);
-        else hipLaunchKernelGGL((k_prolong_gs3<T, 16, 16, 256, false>), grid, dim3(256), 0, s, L, Lc);
+        else hipLaunchKernelGGL((k_prolong_gs3<T, 16, 16, 256, cell_pairs<16>()>), grid, dim3(256), 0, s, L, Lc);
     } else if (N == 16 && Nc == 8) {
         if (wide) hipLaunchKernelGGL((k_prolong_gs3<T, 16, 8, 512, cell_pairs<16>()>), grid, dim3(512), 0, s, L, Lc);
-        else hipLaunchKernelGGL((k_prolong_gs3<T, 16, 8, 256, false>), grid, dim3(256), 0, s, L, Lc);
+        else hipLaunchKernelGGL((k_prolong_gs3<T, 16, 8, 256, cell_pairs<16>()>), grid, dim3(256), 0, s, L, Lc);
     } else if (N == 8 && Nc == 8) {
         hipLaunchKernelGGL((k_prolong_gs3<T, 8, 8, 256, false>), grid, dim3(256), 0, s, L, Lc);
     } else {
