@@ -131,11 +131,31 @@ def leg_mixed(G, w, phi64, t64, stream, steps, rtol, tune=True):
     xyz, _ = G.leaf_coords()
     S.set_rhs(w.rhs(xyz))
     tuned, cand_ms = S.autotune(rtol=rtol, reps=2, stream=stream) if tune else (S.get_launch(), [])
+    # FP32 finest-level half sweeps timed with HIP events (eager launches)
+    S.profile(True)
+    S.profile_read()
+    for _ in range(steps):
+        S.solve(rtol=rtol, max_cycles=40, zero_start=True, stream=stream)
+    prof = S.profile_read()
+    S.profile(False)
     dt, rep = timed_solves(S, steps, stream, rtol=rtol, max_cycles=40, graph_mode=tuned["graph_mode"])
     phi = S.get_solution()
     MIXED_PHI["phi"] = phi
+    top = G.level_info(G.n_levels - 1)
+    ncell = top["nblocks"] * top["Nb"] ** 3
+    # algorithmic bytes of one FP32 half sweep: 6 B per cell of the level
+    # (other colour's phi, g and the written phi of half the cells, 4 B
+    # each) plus the FP32 stencil record (32 B) and boundary term (4 B) of
+    # the custom cells of that colour
+    b32 = 6.0 * ncell + 18.0 * top["nrec"]
+    ms32 = prof["finest_half_sweep_ms"] / max(1, prof["finest_half_sweeps"])
+    a32 = b32 / (ms32 * 1e-3) / 1e9
     return {"solves_per_s": round(1 / dt, 3), "ms_per_solve": round(dt * 1e3, 3), "speedup_vs_fp64": round(t64 / dt, 3),
             "launch": {"chosen": tuned, "autotune_ms_per_solve": [round(v, 3) for v in cand_ms]},
+            "sweep_roofline_fp32": {"bound": "hbm", "achieved": round(a32, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": round(a32 / HBM_PEAK_GBS, 4), "kernel": "k_gs_half3<float,16> (finest level)",
+                                    "bytes_per_launch": b32, "mean_launch_ms": round(ms32, 5),
+                                    "launches_timed": prof["finest_half_sweeps"]},
             "outer_iterations": rep.cycles, "final_rel_residual": rep.r_final / rep.r0,
             "rel_diff_vs_fp64_solution": rel(phi, phi64), "max_err_vs_exact": float(np.abs(phi - w.exact(xyz)).max())}
 
@@ -565,8 +585,21 @@ def leg_2d(stream, steps=20):
             "max_err_vs_exact": float(np.abs(S.get_solution() - w.exact(xyz)).max())}
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(o, w, n_cycles):
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    """The oracle as it stands, timed on the host: n_cycles V-cycles with
+    the OpenMP threads it runs with, then one V-cycle on one thread."""
+    import oracle as orc
+    threads = orc.get_threads()
     o.zero_solution()
     o.vcycle()  # warm
     levels = [o.level_info(i) for i in range(o.n_levels)]
@@ -574,10 +607,18 @@ def cpu_baseline(o, w, n_cycles):
     for _ in range(n_cycles):
         o.vcycle()
     dt = time.perf_counter() - t0
-    upd = smoother_updates_per_vcycle(levels) * n_cycles
-    return {"value": upd / dt / 1e6, "unit": "Mcell-updates/s", "cores": threads, "kind": "oracle",
+    upd = smoother_updates_per_vcycle(levels)
+    orc.set_threads(1)
+    t1 = time.perf_counter()
+    o.vcycle()
+    dt1 = time.perf_counter() - t1
+    orc.set_threads(threads)
+    return {"value": upd * n_cycles / dt / 1e6, "unit": "Mcell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_cycles} FAS V(2,2) cycles of the same {w.geom.name} problem (setup excluded), "
-                      f"{dt:.1f} s, smoother updates on all levels / wall time"}
+                      f"{dt:.1f} s, smoother updates on all levels / wall time; then 1 cycle on 1 thread, "
+                      f"{dt1:.1f} s",
+            "one_thread_value": upd / dt1 / 1e6, "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count(),
+            "oracle_build": "gcc -O3 -ffp-contract=off -fopenmp"}
 
 
 def main():

@@ -25,7 +25,7 @@ _LIB = os.path.join(_HERE, "liboctmg_oracle.so")
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no FMA contraction, OpenMP for timing)."""
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
+        cmd = ["gcc", "-O3", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
                "-o", _LIB + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
@@ -91,6 +91,8 @@ def lib():
             "orc_cbrt": (C.c_double, [C.c_double]),
             "orc_gradient": (None, [vp, dp, C.c_int]),
             "orc_coarse_search": (C.c_int, [C.POINTER(_Desc), dp, C.c_double, dp, ip, dp]),
+            "orc_set_threads": (None, [C.c_int]),
+            "orc_get_threads": (C.c_int, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -302,6 +304,16 @@ class Oracle:
             if hist[-1] <= rtol * r0:
                 break
         return r0, hist
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's loops (timing only; results do not
+    depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
 
 
 def setup_workload(w, n_down: int = 2, n_up: int = 2, rhs_index=None) -> Oracle:

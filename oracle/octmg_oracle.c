@@ -78,6 +78,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <omp.h>
+
 #define MAXLEV 20
 
 typedef struct {
@@ -1320,3 +1322,8 @@ int orc_coarse_search(const orc_desc *d, const double *a, double dx, double *dou
     L.dx = dx;
     return coarse_search(&o, &L, a, lsf(&o, a), dout, dir, x0);
 }
+
+/* OpenMP threads of the oracle's parallel loops (timing only: every loop
+ * writes disjoint cells, so the results do not depend on the count) */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
