@@ -938,6 +938,14 @@ __device__ __forceinline__ int block_of(const LV<T> &L) {
     return xcd_block();
 }
 
+// position in a leaf-block list of this workgroup (a launch over the list):
+// the list holds the level's leaf blocks in Morton order, so the same
+// XCD-contiguous ranges as block_of keep face halos in one XCD's L2
+template <typename T>
+__device__ __forceinline__ int leaf_slot(const LV<T> &L) {
+    return L.order == 1 ? (int)blockIdx.x : xcd_block();
+}
+
 // one colour of a block with halo: (N+2) x (N+2) x (N/2+2), index (k, j, h)
 template <int N>
 struct ColTile {
@@ -2312,7 +2320,7 @@ __global__ __launch_bounds__(256) void k_defect3(LV<double> L, LV<double> Lc, LV
     __shared__ double tile[ColTile<N>::SIZE];
     __shared__ double wmax[4];
     const int rhs = rhs_of(L);
-    const int blk = lb[blockIdx.x];
+    const int blk = lb[leaf_slot(L)];
     const int4 P = L.pos[blk];
     int nbk[6];
     face_ids<double, N>(L, blk, nbk);
@@ -2373,7 +2381,7 @@ __global__ __launch_bounds__(2 * NTC) __attribute__((amdgpu_waves_per_eu(LATE ? 
     __shared__ double tiles[PairTiles<double, N>::SIZE];
     __shared__ double wmax[2 * NTC / 64];
     const int rhs = rhs_of(L);
-    const int blk = lb[blockIdx.x];
+    const int blk = lb[leaf_slot(L)];
     const int c = threadIdx.x / NTC, t = threadIdx.x % NTC;
     const int4 P = L.pos[blk];
     int nbk[6];
