@@ -397,7 +397,7 @@ def leg_serving(stream, n_requests=1000, rtol=1e-8, budget_gb=64, max_lanes=16):
     return out
 
 
-def leg_table1(stream, n_fmg=10):
+def leg_table1(stream, n_fmg=40):
     """The Sec. 4.1 sphere (R = 1/4, domain [-1/2,1/2]^3, exact solution on
     the domain boundary) on a uniform 512^3 grid, FP64: time per FMG cycle
     over n_fmg consecutive FMG cycles, for 8^3 and 16^3 blocks, beside the
@@ -579,10 +579,15 @@ def leg_2d(stream, steps=20):
     dt, rep = timed_solves(S, steps, stream, rtol=1e-10, max_cycles=40, graph_mode=1)
     hist = [rep.r0] + list(rep.history[:rep.cycles])
     factors = [hist[i + 1] / hist[i] for i in range(len(hist) - 1)]
-    return {"workload": "2D unit square 64^2 in 8^2 blocks, circle r=0.25, phi=sin(2 pi x)cos(3 pi y)+x^2",
-            "ms_per_solve": round(dt * 1e3, 3), "cycles": rep.cycles,
-            "residual_factor_per_cycle": [round(f, 4) for f in factors],
-            "max_err_vs_exact": float(np.abs(S.get_solution() - w.exact(xyz)).max())}
+    phi = S.get_solution()
+    out = {"workload": "2D unit square 64^2 in 8^2 blocks, circle r=0.25, phi=sin(2 pi x)cos(3 pi y)+x^2",
+           "ms_per_solve": round(dt * 1e3, 3), "cycles": rep.cycles,
+           "residual_factor_per_cycle": [round(f, 4) for f in factors],
+           "max_err_vs_exact": float(np.abs(phi - w.exact(xyz)).max())}
+    if ORACLE_CHECKS:
+        import oracle
+        out["vs_oracle"] = vs_oracle(oracle.setup_workload(w), phi, rep.r0, cycles=10)
+    return out
 
 
 def cpu_model():
