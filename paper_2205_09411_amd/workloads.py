@@ -181,6 +181,30 @@ def cylinder(max_level: int = 4, block_n: int = 16, n_rhs: int = 64, seed0: int 
     return Workload(geom, rhs, z, z, extra={"n_rhs": n_rhs, "seed0": seed0})
 
 
+def no_interface(max_level: int = 3, block_n: int = 16) -> Workload:
+    """The 3D manufactured problem without any interface (no level set):
+    Dirichlet data on the cube only, standard stencils everywhere."""
+    geom = Geometry(dim=3, block_n=block_n, max_level=max_level, lsf_kind=LSF_NONE, lsf_params=np.zeros(1),
+                    name=f"no_interface_{block_n * (1 << (max_level - 1))}")
+    return Workload(geom, _mms3d_g, _mms3d_phi, _mms3d_phi, exact=_mms3d_phi)
+
+
+def through_centres(max_level: int = 3, block_n: int = 16, a: int = 12, b: int = 5) -> Workload:
+    """Degenerate interface: a cylinder along z through (1/2, 1/2) whose
+    radius is the distance of the finest-level cell centre (1/2 + (a + 1/2)
+    dx, 1/2 + (b + 1/2) dx) from the axis, computed with the same operations
+    as the level set, so that f = 0 exactly at the centres of that cell and
+    its seven mirror images in every z layer; phi = 1 on the cylinder and 0 on
+    the cube, Gaussian sources as rhs (seed 7)."""
+    n = block_n * (1 << (max_level - 1))
+    ex, ey = (a + 0.5) / n, (b + 0.5) / n
+    r = float(np.sqrt(ex * ex + ey * ey))
+    geom = Geometry(dim=3, block_n=block_n, max_level=max_level, lsf_kind=LSF_CYLINDER_Z,
+                    lsf_params=np.array([0.5, 0.5, r]), w_min=8e-3, name=f"through_centres_{n}")
+    return Workload(geom, lambda x: gaussian_sources(x, 7), lambda x: np.ones(x.shape[0]),
+                    lambda x: np.zeros(x.shape[0]), extra={"radius": r, "on_interface": (a, b)})
+
+
 def sphere_f1(dim: int = 3, max_level: int = 4, R: float = 0.25, block_n: int = 8,
               phi_b: float = 0.0, a: float = 1.0) -> Workload:
     """Sec. 4.1 convergence test: Laplace equation, f = |x| - R on a domain of

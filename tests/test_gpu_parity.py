@@ -32,6 +32,10 @@ CONFIGS = {
     # zero-flux side faces (Sec. 4.3)
     "electrodes_small": lambda: W.two_electrodes(max_level=5, uniform_level=3),
     "neumann_2d": lambda: W.neumann2d(max_level=5),
+    # degenerate inputs: no interface at all; an interface exactly through
+    # finest-level cell centres (f = 0 there, d = 2^-28 on their links)
+    "no_interface_64": lambda: W.no_interface(),
+    "through_centres_64": lambda: W.through_centres(),
 }
 
 
@@ -191,6 +195,49 @@ def test_batched_rhs_equal_single(orc):
         S1.set_rhs(g[i])
         S1.solve(rtol=1e-10)
         assert rel(batched[i], S1.get_solution()) <= 1e-14
+
+
+def test_cells_on_the_interface_take_the_boundary_value(orc):
+    """Cells whose centre lies exactly on the interface have every link cut
+    at d = 2^-28: after a V-cycle and an FMG their value is the boundary
+    value exactly, on the GPU as in the oracle."""
+    w = CONFIGS["through_centres_64"]()
+    o, G, S = make_pair(orc, w)
+    xyz, _ = G.leaf_coords()
+    on = (np.sqrt((xyz[:, 0] - 0.5) ** 2 + (xyz[:, 1] - 0.5) ** 2) - w.extra["radius"]) == 0
+    assert on.sum() == 512
+    S.vcycle()
+    assert np.all(S.get_solution()[on] == 1.0)
+    S.fmg(have_guess=True)
+    assert np.all(S.get_solution()[on] == 1.0)
+
+
+def _f1_error(max_level):
+    w = W.sphere_f1(dim=3, max_level=max_level, block_n=16)
+    G = octmg.Geometry(w.geom)
+    S = octmg.State(G)
+    S.set_boundary_fn(w.iface_value, w.domain_value)
+    xyz, _ = G.leaf_coords()
+    S.set_rhs(np.zeros(G.n_leaf))
+    S.fmg(have_guess=False)
+    S.fmg(have_guess=True)
+    S.fmg(have_guess=True)
+    outside = np.sqrt((xyz ** 2).sum(axis=1)) > 0.25
+    return float(np.abs(S.get_solution()[outside] - w.exact(xyz)[outside]).max())
+
+
+def test_largest_grid_second_order():
+    """The largest configuration timed, the Sec. 4.1 sphere on a uniform
+    512^3 grid in 16^3 blocks (37 450 blocks, 153M cells on all levels), is
+    checked through a property that holds at any size: after three FMG
+    cycles the error against the exact solution (eq. solution-sphere, cells
+    outside the sphere) is the discretisation error, which falls about four
+    times from 256^3 (second order, Sec. 4.1)."""
+    print("second order 256^3 -> 512^3", flush=True)
+    e256 = _f1_error(5)
+    e512 = _f1_error(6)
+    print("errors", e256, e512, flush=True)
+    assert 3.5 < e256 / e512 < 4.6, (e256, e512)
 
 
 def test_nonfinite_rhs_rejected():
