@@ -858,6 +858,7 @@ static octmg_status setup_geometry(octmg_geom_s *G, const octmg_geom_s *reuse, i
         if (il == 0) coarse_kept = reuse && fresh.empty();
         DevPool tmp(G->allocator(), G->device);  // this level's temporaries
         int *d_counts = nullptr, *d_fresh = nullptr;
+        unsigned char *d_flags = nullptr;  // per cell: custom-cell flag of the count pass
         HIPCK(tmp.alloc(&d_counts, (size_t)2 * L.nblocks));
         HIPCK(tmp.alloc(&d_fresh, std::max<size_t>(1, fresh.size())));
         std::vector<int> counts(2 * L.nblocks, 0);
@@ -875,7 +876,9 @@ static octmg_status setup_geometry(octmg_geom_s *G, const octmg_geom_s *reuse, i
                 H.blocks = S.blocks ? fresh.data() : nullptr;
                 host_setup_count(H, counts.data());
             } else {
-                HIPCK(launch_setup_count(S, d_counts, nullptr));
+                HIPCK(tmp.alloc(&d_flags, (size_t)L.nblocks * L.cpb));
+                HIPCK(hipMemset(d_counts, 0, sizeof(int) * 2 * L.nblocks));
+                HIPCK(launch_setup_count(S, d_counts, d_flags, nullptr));
                 HIPCK(hipMemcpy(counts.data(), d_counts, sizeof(int) * 2 * L.nblocks, hipMemcpyDeviceToHost));
             }
         }
@@ -942,8 +945,8 @@ static octmg_status setup_geometry(octmg_geom_s *G, const octmg_geom_s *reuse, i
                 HIPCK(hipMemcpy(L.d_rec8f, rec8f.data(), sizeof(float) * rec8f.size(), hipMemcpyHostToDevice));
                 HIPCK(hipMemcpy(L.d_pts, pts.data(), sizeof(double) * pts.size(), hipMemcpyHostToDevice));
             } else if (!fresh.empty()) {
-                HIPCK(launch_setup_emit(S, d_roff, d_poff, L.d_map_off, L.d_map, L.d_meta, L.d_d6, L.d_cfull, L.d_rec8,
-                                        L.d_rec8f, L.d_pts, L.d_inside, nullptr));
+                HIPCK(launch_setup_emit(S, d_flags, d_roff, d_poff, L.d_map_off, L.d_map, L.d_meta, L.d_d6, L.d_cfull,
+                                        L.d_rec8, L.d_rec8f, L.d_pts, L.d_inside, nullptr));
             }
             std::vector<ReuseBlock> keep;
             for (int b = 0; b < L.nblocks; b++) {

@@ -237,12 +237,16 @@ struct ReuseArrays {
 };
 hipError_t launch_reuse_records(const ReuseBlock *list, int nlist, int cpb, const ReuseArrays &o,
                                 const ReuseArrays &n, hipStream_t s);
-// pass 1: per block, the number of custom cells and of cut links
-hipError_t launch_setup_count(const SetupLevel &S, int *counts /*[nblocks][2]*/, hipStream_t s);
-// pass 2: records in canonical order at the given per-block offsets
-hipError_t launch_setup_emit(const SetupLevel &S, const int *rec_off, const int *pt_off, const int *map_off,
-                             int *map, int *meta /*[nrec][4]*/, double *d6, double *cfull /*[nrec][6]*/,
-                             double *rec8, float *rec8f, double *pts, int *inside /*[nrec]*/, hipStream_t s);
+// pass 1: per block, the number of custom cells and of cut links (added to
+// counts, which start at zero), and per cell a flag byte (0x80 | cut links
+// for a custom cell, else 0; [nblocks][cells per block])
+hipError_t launch_setup_count(const SetupLevel &S, int *counts /*[nblocks][2]*/, unsigned char *flags, hipStream_t s);
+// pass 2: records in canonical order at the given per-block offsets; only
+// the cells flagged by pass 1 are analysed again
+hipError_t launch_setup_emit(const SetupLevel &S, const unsigned char *flags, const int *rec_off, const int *pt_off,
+                             const int *map_off, int *map, int *meta /*[nrec][4]*/, double *d6,
+                             double *cfull /*[nrec][6]*/, double *rec8, float *rec8f, double *pts,
+                             int *inside /*[nrec]*/, hipStream_t s);
 // the same two passes on the host, for a level set given as a host function
 // (S holds host pointers; only the blocks of S.blocks if set)
 void host_setup_count(const SetupLevel &S, int *counts);

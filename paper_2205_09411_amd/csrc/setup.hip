@@ -248,17 +248,28 @@ __host__ __device__ int emit_cell(const SetupLevel &S, const CellSetup &R, int b
 
 constexpr int kSetupThreads = 256;
 
-__global__ __launch_bounds__(kSetupThreads) void k_setup_count(SetupLevel S, int *counts) {
-    const int blk = S.blocks ? S.blocks[blockIdx.x] : (int)blockIdx.x;
+// The cells of a block are analysed by `split` workgroups, each taking one
+// contiguous range of them, so that levels with few blocks still occupy the
+// GPU (cell ranges never cross blocks: split divides the cells per block).
+__global__ __launch_bounds__(kSetupThreads) void k_setup_count(SetupLevel S, int split, int *counts,
+                                                                unsigned char *flags) {
+    const int bi = (int)blockIdx.x / split, part = (int)blockIdx.x % split;
+    const int blk = S.blocks ? S.blocks[bi] : bi;
     const int cpb = S.D == 3 ? S.Nb * S.Nb * S.Nb : S.Nb * S.Nb;
+    const int span = cpb / split, c0 = part * span;
+    unsigned char *fb = flags + (long long)blk * cpb;
     const Lsf f = lsf_of(S);
     int nrec = 0, npt = 0;
     CellSetup R;
-    for (int li = threadIdx.x; li < cpb; li += blockDim.x) {
+    for (int li = c0 + (int)threadIdx.x; li < c0 + span; li += blockDim.x) {
+        unsigned char fl = 0;
         if (analyse_cell(S, f, blk, li, R)) {
+            const int pc = __builtin_popcount(R.cut);
             nrec++;
-            npt += __builtin_popcount(R.cut);
+            npt += pc;
+            fl = (unsigned char)(0x80 | pc);
         }
+        fb[li] = fl;
     }
     __shared__ int sr[kSetupThreads], sp[kSetupThreads];
     sr[threadIdx.x] = nrec;
@@ -272,47 +283,66 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup_count(SetupLevel S, int
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        counts[2 * blk] = sr[0];
-        counts[2 * blk + 1] = sp[0];
+        atomicAdd(&counts[2 * blk], sr[0]);
+        atomicAdd(&counts[2 * blk + 1], sp[0]);
     }
 }
 
-// Records of a block in canonical (x-fastest) cell order: thread t owns the
-// contiguous cells [t*chunk, (t+1)*chunk); an exclusive scan over threads
-// gives every thread its first record and point slot.
-__global__ __launch_bounds__(kSetupThreads) void k_setup_emit(SetupLevel S, const int *rec_off, const int *pt_off,
-                                                               EmitOut o) {
-    const int blk = S.blocks ? S.blocks[blockIdx.x] : (int)blockIdx.x;
+// Records of a block in canonical (x-fastest) cell order.  Within its cell
+// range a workgroup gives thread t the contiguous cells
+// [t*chunk, (t+1)*chunk); the flags of pass 1 give every thread its first
+// record and point slot (the records and points of the block's cells before
+// the range, plus an exclusive scan over the threads), and only the flagged
+// cells are analysed again.
+__global__ __launch_bounds__(kSetupThreads) void k_setup_emit(SetupLevel S, int split, const unsigned char *flags,
+                                                               const int *rec_off, const int *pt_off, EmitOut o) {
+    const int bi = (int)blockIdx.x / split, part = (int)blockIdx.x % split;
+    const int blk = S.blocks ? S.blocks[bi] : bi;
     const int cpb = S.D == 3 ? S.Nb * S.Nb * S.Nb : S.Nb * S.Nb;
-    const int chunk = (cpb + blockDim.x - 1) / blockDim.x;
-    const int c0 = threadIdx.x * chunk, c1 = min(cpb, c0 + chunk);
-    const Lsf f = lsf_of(S);
-    CellSetup R;
-    int nrec = 0, npt = 0;
-    for (int li = c0; li < c1; li++)
-        if (analyse_cell(S, f, blk, li, R)) {
-            nrec++;
-            npt += __builtin_popcount(R.cut);
+    const int span = cpb / split, c0 = part * span;
+    const unsigned char *fb = flags + (long long)blk * cpb;
+    const int chunk = (span + blockDim.x - 1) / blockDim.x;
+    const int a0 = min(c0 + span, c0 + (int)threadIdx.x * chunk), a1 = min(c0 + span, a0 + chunk);
+    int before_r = 0, before_p = 0;  // this thread's share of the cells before the range
+    for (int li = threadIdx.x; li < c0; li += blockDim.x)
+        if (fb[li]) {
+            before_r++;
+            before_p += fb[li] & 0x7f;
         }
-    __shared__ int sr[kSetupThreads], sp[kSetupThreads];
+    int nrec = 0, npt = 0;
+    for (int li = a0; li < a1; li++)
+        if (fb[li]) {
+            nrec++;
+            npt += fb[li] & 0x7f;
+        }
+    __shared__ int sr[kSetupThreads], sp[kSetupThreads], br[kSetupThreads], bp[kSetupThreads];
     sr[threadIdx.x] = nrec;
     sp[threadIdx.x] = npt;
+    br[threadIdx.x] = before_r;
+    bp[threadIdx.x] = before_p;
     __syncthreads();
-    if (threadIdx.x == 0) {  // exclusive scan (setup only, 256 entries)
-        int a = 0, b = 0;
+    if (threadIdx.x == 0) {  // exclusive scan of the chunks, total before the range (setup only)
+        int a = 0, b = 0, c = 0, d = 0;
         for (int t = 0; t < (int)blockDim.x; t++) {
-            int x = sr[t], y = sp[t];
+            const int x = sr[t], y = sp[t];
             sr[t] = a;
             sp[t] = b;
             a += x;
             b += y;
+            c += br[t];
+            d += bp[t];
         }
+        br[0] = c;
+        bp[0] = d;
     }
     __syncthreads();
-    int r = rec_off[blk] + sr[threadIdx.x];
-    int q = pt_off[blk] + sp[threadIdx.x];
-    for (int li = c0; li < c1; li++) {
-        if (!analyse_cell(S, f, blk, li, R)) continue;
+    int r = rec_off[blk] + br[0] + sr[threadIdx.x];
+    int q = pt_off[blk] + bp[0] + sp[threadIdx.x];
+    const Lsf f = lsf_of(S);
+    CellSetup R;
+    for (int li = a0; li < a1; li++) {
+        if (!fb[li]) continue;
+        analyse_cell(S, f, blk, li, R);
         q = emit_cell(S, R, blk, li, r, q, o);
         r++;
     }
@@ -465,22 +495,34 @@ __global__ __launch_bounds__(256) void k_gj_eliminate(int n, int k, double *A, d
 
 }  // namespace
 
-hipError_t launch_setup_count(const SetupLevel &S, int *counts, hipStream_t s) {
+// workgroups per block: doubled while the launch has fewer than 32768
+// workgroups and each keeps at least a cell per thread
+static int setup_split(const SetupLevel &S, int nb) {
+    const int cpb = S.D == 3 ? S.Nb * S.Nb * S.Nb : S.Nb * S.Nb;
+    int split = 1;
+    while (2 * split * kSetupThreads <= cpb && (long long)nb * split < 32768) split *= 2;
+    return split;
+}
+
+hipError_t launch_setup_count(const SetupLevel &S, int *counts, unsigned char *flags, hipStream_t s) {
     if (S.nblocks == 0) return hipSuccess;
-    const int grid = S.blocks ? S.nlist : S.nblocks;
-    if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_setup_count, dim3(grid), dim3(kSetupThreads), 0, s, S, counts);
+    const int nb = S.blocks ? S.nlist : S.nblocks;
+    if (nb == 0) return hipSuccess;
+    const int split = setup_split(S, nb);
+    hipLaunchKernelGGL(k_setup_count, dim3(nb * split), dim3(kSetupThreads), 0, s, S, split, counts, flags);
     return hipGetLastError();
 }
 
-hipError_t launch_setup_emit(const SetupLevel &S, const int *rec_off, const int *pt_off, const int *map_off,
-                             int *map, int *meta, double *d6, double *cfull, double *rec8, float *rec8f,
-                             double *pts, int *inside, hipStream_t s) {
+hipError_t launch_setup_emit(const SetupLevel &S, const unsigned char *flags, const int *rec_off, const int *pt_off,
+                             const int *map_off, int *map, int *meta, double *d6, double *cfull, double *rec8,
+                             float *rec8f, double *pts, int *inside, hipStream_t s) {
     if (S.nblocks == 0) return hipSuccess;
-    const int grid = S.blocks ? S.nlist : S.nblocks;
-    if (grid == 0) return hipSuccess;
+    const int nb = S.blocks ? S.nlist : S.nblocks;
+    if (nb == 0) return hipSuccess;
+    const int split = setup_split(S, nb);
     const EmitOut o{map_off, map, meta, d6, cfull, rec8, rec8f, pts, inside};
-    hipLaunchKernelGGL(k_setup_emit, dim3(grid), dim3(kSetupThreads), 0, s, S, rec_off, pt_off, o);
+    hipLaunchKernelGGL(k_setup_emit, dim3(nb * split), dim3(kSetupThreads), 0, s, S, split, flags, rec_off, pt_off,
+                       o);
     return hipGetLastError();
 }
 
