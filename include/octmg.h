@@ -179,9 +179,14 @@ void octmg_ctx_destroy(octmg_ctx c);
  *     Every value gives the same iterates.  Default 1 << 30 (every launch).
  *   prolong_fused: 1 (default) runs the prolongation of a 3D V-cycle and
  *     the red half sweep after it as one launch (the black values are
- *     prolonged on the fly), 0 as two.  The same iterates either way. */
+ *     prolonged on the fly), 0 as two.  The same iterates either way.
+ *   red_preset: 1 (default) lets the mixed-precision defect of a 3D tree
+ *     whose leaves are all on the finest level write the FP32 correction's
+ *     red cells as the first red half sweep from zero leaves them, so the
+ *     FP32 V-cycle starts with the black half sweep; 0 zeroes the
+ *     correction and runs that half sweep.  The same iterates either way. */
 typedef struct octmg_launch_config {
-    int block_order, bottom_kind, bottom_max_blocks, graph_mode, pair_max_blocks, prolong_fused;
+    int block_order, bottom_kind, bottom_max_blocks, graph_mode, pair_max_blocks, prolong_fused, red_preset;
 } octmg_launch_config;
 octmg_status octmg_state_set_launch(octmg_state s, const octmg_launch_config *c);
 octmg_status octmg_state_get_launch(octmg_state s, octmg_launch_config *c);

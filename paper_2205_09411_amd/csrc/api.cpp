@@ -198,6 +198,7 @@ struct octmg_state_s {
     int fused_max_blocks = 0;                  // levels with <= this many blocks run fused (0: off)
     int pair_max_blocks = 1 << 30;             // LV::pair_max of every level
     int prolong_fused = 1;                     // V-cycle prolongation fused with the next red half sweep (3D)
+    int red_preset = 1;                        // mixed precision: first red half sweep inside the defect (3D)
     int fused_top = 0;                         // highest fused level (0: none)
     int fused_grid64 = 0, fused_grid32 = 0;    // co-resident workgroups of the fused kernel
     SmallLevels<double> *d_small64 = nullptr;  // device copies of the fused level tables
@@ -315,7 +316,10 @@ struct Engine {
     // prolongation (prolong_fused); the first black one takes its cells' own
     // values for the ghosts from the prolonged black values it left.  The
     // timed group then holds the remaining 2 steps - 1 half sweeps.
-    octmg_status smooth(int il, int steps, bool fas_first = false, bool after_prolong = false) {
+    // red_preset: the first red half sweep has run inside the mixed-precision
+    // defect (the correction starts from zero there); it is skipped.
+    octmg_status smooth(int il, int steps, bool fas_first = false, bool after_prolong = false,
+                        bool red_preset = false) {
         Profile *P = s->prof;
         const bool timed = P && P->on && il == (int)s->geom->L.size() - 1 && steps > 0;
         hipEvent_t a = nullptr, b = nullptr;
@@ -326,7 +330,7 @@ struct Engine {
         }
         for (int k = 0; k < steps; k++)
             for (int color = 0; color < 2; color++) {
-                if (after_prolong && k == 0 && color == 0) continue;
+                if ((after_prolong || red_preset) && k == 0 && color == 0) continue;
                 if (fas_first && k == 0 && color == 0) {
                     HIPCK(launch_fas_gs<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1),
                                            s->geom->tree.adaptive ? 1 : 0, s->n_launch, st));
@@ -343,7 +347,7 @@ struct Engine {
         if (timed) {
             HIPCK(hipEventRecord(b, st));
             P->pending.push_back({a, b});
-            P->launches.push_back(2 * steps - (after_prolong ? 1 : 0));
+            P->launches.push_back(2 * steps - (after_prolong || red_preset ? 1 : 0));
         }
         return OCTMG_OK;
     }
@@ -453,14 +457,17 @@ struct Engine {
     octmg_status fused(int top);
     // FAS V-cycle with top level `top` (Sec. 2.2).  Levels up to fused_top
     // (few blocks each) run in one cooperative launch with the same steps.
-    octmg_status vcycle(int top) {
+    // top_red_preset: the top level's first red half sweep has already run
+    // (inside the mixed-precision defect, see mixed_red_preset)
+    octmg_status vcycle(int top, bool top_red_preset = false) {
         const int ft = std::min(top, s->fused_top);
         bool fas_pending = false;
         // the coarsest level's FAS right-hand side is formed inside the solve (3D)
         const bool fas_coarse = ft == 0 && D() == 3;
         for (int il = top; il > ft; il--) {
             const bool sb = single_block(il);
-            STCK(sb ? single_block_down(il, fas_pending) : smooth(il, s->n_down, fas_pending));
+            STCK(sb ? single_block_down(il, fas_pending)
+                    : smooth(il, s->n_down, fas_pending, false, top_red_preset && il == top));
             fas_pending = fas_in_sweep(il - 1, ft);
             STCK(fas_pending || (il == 1 && fas_coarse) ? restrict_only(il, sb) : restrict_fas(il, sb));
         }
@@ -491,9 +498,9 @@ struct Engine {
     }
     // sync: leave the coarse copies of leaf values current (not needed when
     // the iterate is a correction that only the leaves pass on)
-    octmg_status cycle(int kind, int have_guess, bool sync = true) {
+    octmg_status cycle(int kind, int have_guess, bool sync = true, bool red_preset = false) {
         const int top = (int)s->geom->L.size() - 1;
-        STCK(kind == OCTMG_CYCLE_FMG ? fmg(have_guess) : vcycle(top));
+        STCK(kind == OCTMG_CYCLE_FMG ? fmg(have_guess) : vcycle(top, red_preset));
         return sync ? sync_down() : OCTMG_OK;
     }
 };
@@ -571,9 +578,22 @@ octmg_status read_norms(octmg_state s, double *out, hipStream_t st) {
     return OCTMG_OK;
 }
 
+// The FP32 V-cycle on the correction starts from zero, so its first red half
+// sweep on the finest level needs nothing but the FP32 right-hand side of
+// each red cell: the defect kernel writes it there directly (3D trees whose
+// leaves all lie on the finest level, smoothed by separate launches with at
+// least one pre-smoothing step).  The same bits as the half sweep.
+static bool mixed_red_preset(const octmg_state_s *s) {
+    const int top = (int)s->geom->L.size() - 1;
+    return s->red_preset && s->geom->tree.D == 3 && !s->geom->tree.adaptive && top >= 1 && s->fused_top < top &&
+           s->n_down >= 1;
+}
+
 // one outer step of the mixed-precision defect correction: FP64 defect on
-// the leaves (norm into d_norm), FP32 cycle on the correction, FP64 update
-octmg_status mixed_defect(octmg_state s, hipStream_t st, unsigned long long *mapped = nullptr) {
+// the leaves (norm into d_norm), FP32 cycle on the correction, FP64 update.
+// next_v: the correction that follows is a V-cycle (mixed_red_preset applies)
+octmg_status mixed_defect(octmg_state s, hipStream_t st, bool next_v, unsigned long long *mapped = nullptr) {
+    const int red = next_v && mixed_red_preset(s) ? 1 : 0;
     Engine<double> e64{s, st};
     STCK(e64.sync_down());
     if (!s->norm_slots_clean) HIPCK(launch_fill_u64(s->d_norm_slots, norm_slot_words(s->nrhs), 0ull, st));
@@ -594,7 +614,7 @@ octmg_status mixed_defect(octmg_state s, hipStream_t st, unsigned long long *map
         const GeomLevel &G = s->geom->L[il];
         if (G.nleaf == 0) continue;
         HIPCK(launch_defect(D, G.Nb, lv64(s, il), lv64(s, il - 1), lv32(s, il), G.d_leaf_blocks, G.nleaf,
-                            s->d_norm_slots, s->n_launch, st));
+                            s->d_norm_slots, s->n_launch, st, red));
     }
     HIPCK(launch_norm_reduce(s->d_norm_slots, s->d_norm, mapped ? mapped : s->h_norm_dev, s->nrhs, st));
     s->norm_slots_clean = true;
@@ -603,7 +623,9 @@ octmg_status mixed_defect(octmg_state s, hipStream_t st, unsigned long long *map
 
 octmg_status mixed_correct(octmg_state s, int kind, hipStream_t st) {
     Engine<float> e32{s, st};
-    STCK(e32.cycle(kind, kind == OCTMG_CYCLE_FMG ? 0 : 1, false));  // only leaf values are passed on
+    // only leaf values are passed on; the defect before a V-cycle has done
+    // its first red half sweep
+    STCK(e32.cycle(kind, kind == OCTMG_CYCLE_FMG ? 0 : 1, false, kind == OCTMG_CYCLE_V && mixed_red_preset(s)));
     const int D = s->geom->tree.D;
     for (int il = 0; il < (int)s->geom->L.size(); il++) {
         const GeomLevel &G = s->geom->L[il];
@@ -1358,10 +1380,12 @@ octmg_status octmg_state_set_launch(octmg_state s, const octmg_launch_config *c)
         return fail(OCTMG_ERR_INVALID, "bad launch configuration");
     if (c->bottom_kind == 1 && c->graph_mode != 0)
         return fail(OCTMG_ERR_INVALID, "the cooperative bottom launch cannot be captured");
-    if (c->prolong_fused != 0 && c->prolong_fused != 1) return fail(OCTMG_ERR_INVALID, "bad launch configuration");
+    if ((c->prolong_fused != 0 && c->prolong_fused != 1) || (c->red_preset != 0 && c->red_preset != 1))
+        return fail(OCTMG_ERR_INVALID, "bad launch configuration");
     s->block_order = c->block_order;
     s->pair_max_blocks = c->pair_max_blocks;
     s->prolong_fused = c->prolong_fused;
+    s->red_preset = c->red_preset;
     s->tuned_graph = c->graph_mode;
     s->fused_max_blocks = c->bottom_kind ? c->bottom_max_blocks : 0;
     HIPCK(hipSetDevice(s->geom->device));
@@ -1376,6 +1400,7 @@ octmg_status octmg_state_get_launch(octmg_state s, octmg_launch_config *c) {
     c->graph_mode = s->tuned_graph;
     c->pair_max_blocks = s->pair_max_blocks;
     c->prolong_fused = s->prolong_fused;
+    c->red_preset = s->red_preset;
     return OCTMG_OK;
 }
 
@@ -1604,7 +1629,7 @@ octmg_status octmg_cycle(octmg_state s, int kind, int have_guess, void *stream) 
     hipStream_t st = (hipStream_t)stream;
     HIPCK(hipSetDevice(s->geom->device));
     if (s->precision == OCTMG_MIXED) {
-        STCK(mixed_defect(s, st));
+        STCK(mixed_defect(s, st, kind == OCTMG_CYCLE_V));
         return mixed_correct(s, kind, st);
     }
     Engine<double> e{s, st};
@@ -1656,7 +1681,7 @@ static octmg_status set_active(octmg_state s, const std::vector<int> &act, hipSt
 static octmg_status cycle_and_norm(octmg_state s, int kind, int have_guess, hipStream_t st) {
     if (s->precision == OCTMG_MIXED) {
         STCK(mixed_correct(s, kind, st));
-        STCK(mixed_defect(s, st));
+        STCK(mixed_defect(s, st, kind == OCTMG_CYCLE_V));
     } else {
         Engine<double> e{s, st};
         STCK(e.cycle(kind, have_guess));
@@ -1753,7 +1778,7 @@ static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStre
     for (double v : r0) rp->r0 = std::max(rp->r0, v);
     // residual of the starting iterate
     if (s->precision == OCTMG_MIXED) {
-        STCK(mixed_defect(s, st));
+        STCK(mixed_defect(s, st, o->cycle_kind == OCTMG_CYCLE_V));
         STCK(read_norms(s, rk.data(), st));
     } else if (o->zero_start) {
         rk = r0;  // the residual of phi = 0 is r0 itself
@@ -1941,8 +1966,8 @@ static bool tune_lookup(const std::string &path, const std::string &key, octmg_l
         char *tab = std::strchr(line, '\t');
         if (!tab || std::string(line, tab - line) != key) continue;
         octmg_launch_config t{};
-        if (std::sscanf(tab + 1, "%d %d %d %d %d %d", &t.block_order, &t.bottom_kind, &t.bottom_max_blocks,
-                        &t.graph_mode, &t.pair_max_blocks, &t.prolong_fused) == 6) {
+        if (std::sscanf(tab + 1, "%d %d %d %d %d %d %d", &t.block_order, &t.bottom_kind, &t.bottom_max_blocks,
+                        &t.graph_mode, &t.pair_max_blocks, &t.prolong_fused, &t.red_preset) == 7) {
             *c = t;
             found = true;
         }
@@ -1955,8 +1980,8 @@ static void tune_record(const std::string &path, const std::string &key, const o
     std::lock_guard<std::mutex> lk(g_tune_mu);
     FILE *f = std::fopen(path.c_str(), "a");
     if (!f) return;  // an unwritable cache only costs the next tuning run
-    std::fprintf(f, "%s\t%d %d %d %d %d %d %.4f\n", key.c_str(), c.block_order, c.bottom_kind, c.bottom_max_blocks,
-                 c.graph_mode, c.pair_max_blocks, c.prolong_fused, ms);
+    std::fprintf(f, "%s\t%d %d %d %d %d %d %d %.4f\n", key.c_str(), c.block_order, c.bottom_kind,
+                 c.bottom_max_blocks, c.graph_mode, c.pair_max_blocks, c.prolong_fused, c.red_preset, ms);
     std::fclose(f);
 }
 
@@ -1973,21 +1998,21 @@ octmg_status octmg_autotune(octmg_state s, const octmg_solve_opts *o, int reps, 
     std::vector<octmg_launch_config> cand;
     constexpr int all = 1 << 30;
     for (int order = 0; order < 3; order++) {
-        cand.push_back({order, 0, 0, 0, all, 1});
-        cand.push_back({order, 0, 0, 1, all, 1});
+        cand.push_back({order, 0, 0, 0, all, 1, 1});
+        cand.push_back({order, 0, 0, 1, all, 1, 1});
         if (s->geom->tree.D == 3) {
-            cand.push_back({order, 1, 8, 0, all, 1});
-            cand.push_back({order, 1, 64, 0, all, 1});
+            cand.push_back({order, 1, 8, 0, all, 1, 1});
+            cand.push_back({order, 1, 64, 0, all, 1, 1});
         }
     }
     if (s->geom->tree.D == 3) {
-        cand.push_back({0, 0, 0, 0, 0, 1});
-        cand.push_back({0, 0, 0, 1, 0, 1});
+        cand.push_back({0, 0, 0, 0, 0, 1, 1});
+        cand.push_back({0, 0, 0, 1, 0, 1, 1});
     }
     // the whole solve as one captured launch (max_cycles cycles, convergence
     // tested on the device), with the 512- and the 256-thread kernels
-    cand.push_back({0, 0, 0, 2, all, 1});
-    if (s->geom->tree.D == 3) cand.push_back({0, 0, 0, 2, 0, 1});
+    cand.push_back({0, 0, 0, 2, all, 1, 1});
+    if (s->geom->tree.D == 3) cand.push_back({0, 0, 0, 2, 0, 1, 1});
     if (n_candidates) *n_candidates = (int)cand.size();
     double best_ms = 0.0;
     int best_i = -1;
@@ -2331,7 +2356,7 @@ octmg_status lane_store(octmg_state s, int lane, double *dst, int on_device, hip
 octmg_status lanes_begin(octmg_state s, const std::vector<int> &fresh, hipStream_t st) {
     STCK(set_active(s, fresh, st));
     STCK(residual_norm_dev(s, 1, st, false, s->h_begin_dev));
-    if (s->precision == OCTMG_MIXED) STCK(mixed_defect(s, st, s->h_begin_dev + s->nrhs));
+    if (s->precision == OCTMG_MIXED) STCK(mixed_defect(s, st, true, s->h_begin_dev + s->nrhs));
     return OCTMG_OK;
 }
 

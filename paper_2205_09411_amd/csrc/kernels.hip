@@ -2311,10 +2311,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 
     prolong_gs3_body<T, N, NC, NT, V2>(L, Lc, block_of(L), rhs_of(L), tile, et, rp);
 }
 
-// mixed precision defect (FP64): g32 = g - L phi on a leaf block, phi32 = 0
+// The FP32 correction's first red half sweep when the correction is zero
+// everywhere (every neighbour and ghost value is +0): the arithmetic of
+// gs_half3_body with those zeros, so the value is the same bits.  r32: the
+// cell's FP32 right-hand side; ri its record (-1: standard stencil).
+__device__ __forceinline__ float zero_start_red(const LV<float> &L32, float r32, int ri) {
+    if (ri < 0) {
+        const float inv6 = 1.0f / 6.0f;
+        return (0.0f - L32.dx2 * r32) * inv6;
+    }
+    return r32 * L32.rec[8 * (long long)ri + 7];
+}
+
+// mixed precision defect (FP64): g32 = g - L phi on a leaf block, phi32 = 0,
+// or with red_preset the red cells' phi32 after the correction's first red
+// half sweep from zero (zero_start_red)
 template <int N>
 __global__ __launch_bounds__(256) void k_defect3(LV<double> L, LV<double> Lc, LV<float> L32, const int *lb,
-                                                  unsigned long long *out) {
+                                                  unsigned long long *out, int red_preset) {
     using B = Blk<3, N>;
     constexpr int PER = Per<N>::PER;
     __shared__ double tile[ColTile<N>::SIZE];
@@ -2355,7 +2369,7 @@ __global__ __launch_bounds__(256) void k_defect3(LV<double> L, LV<double> Lc, LV
             const double r = gv[m] - lp[m];
             mx = fmax(mx, abs_nan_inf(r));
             g32[s] = (float)r;
-            p32[s] = 0.0f;
+            p32[s] = red_preset && c == 0 ? zero_start_red(L32, (float)r, ri[m]) : 0.0f;
         }
         __syncthreads();
     }
@@ -2374,7 +2388,7 @@ __global__ __launch_bounds__(256) void k_defect3(LV<double> L, LV<double> Lc, LV
 // LATE as in the restriction
 template <int N, int NTC, bool LATE>
 __global__ __launch_bounds__(2 * NTC) __attribute__((amdgpu_waves_per_eu(LATE ? 6 : 1))) void k_defect3_pair(
-    LV<double> L, LV<double> Lc, LV<float> L32, const int *lb, unsigned long long *out) {
+    LV<double> L, LV<double> Lc, LV<float> L32, const int *lb, unsigned long long *out, int red_preset) {
     using B = Blk<3, N>;
     constexpr int PER = B::HALF / NTC;
     constexpr bool V2 = cell_pairs<N>();
@@ -2411,7 +2425,7 @@ __global__ __launch_bounds__(2 * NTC) __attribute__((amdgpu_waves_per_eu(LATE ? 
         const double r = gv[m] - lp[m];
         mx = fmax(mx, abs_nan_inf(r));
         r32[m] = (float)r;
-        z32[m] = 0.0f;
+        z32[m] = red_preset && c == 0 ? zero_start_red(L32, r32[m], ri[m]) : 0.0f;
     }
     store_cells<float, PER, NTC, V2>(g32, t, r32);
     store_cells<float, PER, NTC, V2>(p32, t, z32);
@@ -2874,16 +2888,16 @@ hipError_t launch_level_copy(int D, int N, double *split, double *canon, int nbl
 }
 
 hipError_t launch_defect(int D, int N, const LV<double> &L, const LV<double> &Lc, LV<float> L32, const int *lb,
-                         int nlb, unsigned long long *out, int nrhs, hipStream_t s) {
+                         int nlb, unsigned long long *out, int nrhs, hipStream_t s, int red_preset) {
     if (nlb == 0) return hipSuccess;
     dim3 grid(nlb, nrhs);
 #define DF(D_, N_) OCTMG_DN(D_, N_, hipLaunchKernelGGL((k_defect<D_, N_>), grid, dim3(Blk<D_, N_>::THREADS), 0, s, L, Lc, L32, lb, out))
     const bool pair = (long long)nlb * nrhs <= L.pair_max, late = (long long)nlb * nrhs > kLateMin;
 #define DF3(N_)                                                                                                    \
     OCTMG_DN(3, N_,                                                                                                \
-             if (pair && late) hipLaunchKernelGGL((k_defect3_pair<N_, 256, true>), grid, dim3(512), 0, s, L, Lc, L32, lb, out); \
-             else if (pair) hipLaunchKernelGGL((k_defect3_pair<N_, 256, false>), grid, dim3(512), 0, s, L, Lc, L32, lb, out); \
-             else hipLaunchKernelGGL((k_defect3<N_>), grid, dim3(256), 0, s, L, Lc, L32, lb, out))
+             if (pair && late) hipLaunchKernelGGL((k_defect3_pair<N_, 256, true>), grid, dim3(512), 0, s, L, Lc, L32, lb, out, red_preset); \
+             else if (pair) hipLaunchKernelGGL((k_defect3_pair<N_, 256, false>), grid, dim3(512), 0, s, L, Lc, L32, lb, out, red_preset); \
+             else hipLaunchKernelGGL((k_defect3<N_>), grid, dim3(256), 0, s, L, Lc, L32, lb, out, red_preset))
     DF3(16) DF3(8) DF(2, 8) DF(2, 16)
 #undef DF3
 #undef DF

@@ -180,8 +180,11 @@ hipError_t launch_level_copy(int D, int N, double *split, double *canon, int nbl
 // mixed precision: r64 = g - L phi on leaf blocks -> g32 = (float)r64,
 // phi32 = 0 there, max |r64| into the norm slots `out`; and phi64 += phi32
 // on leaf blocks.
+// red_preset (3D): the red cells' FP32 correction is written as its first
+// red half sweep from zero would leave it (the next FP32 V-cycle then starts
+// with the black half sweep); otherwise the correction is zeroed
 hipError_t launch_defect(int D, int N, const LV<double> &L, const LV<double> &Lc, LV<float> L32, const int *lb,
-                         int nlb, unsigned long long *out, int nrhs, hipStream_t s);
+                         int nlb, unsigned long long *out, int nrhs, hipStream_t s, int red_preset = 0);
 hipError_t launch_update(int D, int N, const LV<double> &L, LV<float> L32, const int *lb, int nlb, int nrhs,
                          hipStream_t s);
 // b_i = sum over cut links of c_link * phi_b(point)
