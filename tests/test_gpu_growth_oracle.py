@@ -171,3 +171,33 @@ def test_full_size_mixed_against_oracle(orc):
     bound = 2.0 * (r_gpu + o.residual_max()) / 6.0
     print("mixed 256^3 vs oracle", err, bound, flush=True)
     assert err <= bound, (err, bound)
+
+
+@pytest.mark.parametrize("name", ["mms2d_64", "heart_2d", "neumann_2d"])
+def test_mixed_2d_within_residual_bound_of_oracle(orc, name):
+    """Mixed precision in 2D (uniform tree with a circle, a sharp shape of
+    Sec. 4.2, an adaptive quadtree with zero-flux faces): the solve reaches
+    1e-10 and lies within 2 |A^-1 1|_inf (|r| + |r_oracle|) of the oracle's
+    converged solution."""
+    w = {"mms2d_64": lambda: W.mms2d(max_level=4),
+         "heart_2d": lambda: W.sharp_shape("heart", dim=2, max_level=4),
+         "neumann_2d": lambda: W.neumann2d(max_level=5)}[name]()
+    print("mixed 2D", name, flush=True)
+    G = octmg.Geometry(w.geom)
+    S = octmg.State(G, 1, octmg.MIXED)
+    S.set_boundary_fn(w.iface_value, w.domain_value)
+    xyz, _ = G.leaf_coords()
+    S.set_rhs(w.rhs(xyz))
+    rep = S.solve(rtol=1e-10, zero_start=True)
+    assert rep.status == 0 and rep.r_final <= 1e-10 * rep.r0
+    phi = S.get_solution()
+    o = orc.Oracle(w.geom)
+    o.set_boundary_fn(w.iface_value, w.domain_value)
+    o.set_rhs(w.rhs(xyz))
+    r_gpu = float(np.abs(o.leaf_residual(phi)).max())
+    o.zero_solution()
+    o.solve(rtol=1e-13, max_cycles=60)
+    err = float(np.abs(phi - o.get_solution()).max())
+    bound = 2.0 * inverse_norm(orc, w) * (r_gpu + o.residual_max())
+    print(f"  |err| {err:.2e}, bound {bound:.2e}", flush=True)
+    assert err <= bound, (err, bound)
