@@ -36,6 +36,12 @@ CONFIGS = {
     # finest-level cell centres (f = 0 there, d = 2^-28 on their links)
     "no_interface_64": lambda: W.no_interface(),
     "through_centres_64": lambda: W.through_centres(),
+    # the smallest trees: the 8^D coarse grid alone (the V-cycle is the
+    # direct solve), and one 16^D block above it
+    "tiny_3d_8": lambda: W.mms3d(max_level=1, block_n=8),
+    "tiny_3d_16": lambda: W.mms3d(max_level=1, block_n=16),
+    "tiny_2d_8": lambda: W.mms2d(max_level=1, block_n=8),
+    "tiny_2d_16": lambda: W.mms2d(max_level=1, block_n=16),
 }
 
 
@@ -238,6 +244,21 @@ def test_largest_grid_second_order():
     e512 = _f1_error(6)
     print("errors", e256, e512, flush=True)
     assert 3.5 < e256 / e512 < 4.6, (e256, e512)
+
+
+@pytest.mark.parametrize("name", ["tiny_3d_8", "tiny_3d_16", "tiny_2d_8", "tiny_2d_16"])
+def test_smallest_trees_solve(orc, name):
+    """Solves on the smallest trees: FP64 in the oracle's cycles and equal to
+    its iterate, mixed precision to the same relative residual."""
+    w = CONFIGS[name]()
+    o, G, S = make_pair(orc, w)
+    rep = S.solve(rtol=1e-10, max_cycles=40)
+    _, hist = o.solve(rtol=1e-10, max_cycles=40)
+    assert rep.status == 0 and rep.cycles == len(hist) - 1
+    assert rel(S.get_solution(), o.get_solution()) < 1e-10
+    _, _, Sm = make_pair(orc, w, precision=octmg.MIXED)
+    repm = Sm.solve(rtol=1e-10, max_cycles=40)
+    assert repm.status == 0 and repm.r_final <= 1e-10 * repm.r0
 
 
 def test_nonfinite_rhs_rejected():
