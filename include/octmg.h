@@ -196,9 +196,12 @@ octmg_status octmg_state_get_launch(octmg_state s, octmg_launch_config *c);
  * solve stops with OCTMG_ERR_NOT_CONVERGED after max_cycles, or when the
  * residual ratio of successive cycles stays above 0.95 for 3 cycles.
  * graph_mode: 0 launches every kernel; 1 captures one cycle (with its
- * residual norm) in a HIP graph and replays it each cycle; 2 captures the
- * whole solve (max_cycles cycles, convergence tested on the device, no stall
- * test) and launches it once.  Results are identical in all modes.  Graph
+ * residual norm) in a HIP graph and replays it each cycle; 2 captures a
+ * chunk of cycles (all max_cycles of them when that is at most 16, else 8),
+ * each followed by a convergence test on the device that stops the rhs it
+ * concerns (no stall test), and replays the chunk until no rhs runs (the
+ * host reads the running flags between replays).  Results are identical in
+ * all modes.  Graph
  * modes capture on `stream` (or an internal stream if NULL) and need the
  * fused levels off; graphs are cached per state and rebuilt when the
  * smoothing counts or fused levels change. */

@@ -208,6 +208,7 @@ struct octmg_state_s {
     hipStream_t own_stream = nullptr;          // capture stream when the caller passes NULL
     double *d_thresh = nullptr;                // [nrhs] rtol * r0 for device-side convergence
     double *d_hist = nullptr;                  // [64][nrhs] residual history of a graph solve
+    int *d_cbase = nullptr;                    // first cycle number of the chunk a graph solve replays
     DevPool pool;
 };
 
@@ -1298,6 +1299,7 @@ octmg_status octmg_state_create(octmg_geom g, int n_rhs, int precision, octmg_st
     HIPCK(hipHostGetDevicePointer((void **)&s->h_norm_dev, s->h_norm, 0));
     HIPCK(s->pool.alloc(&s->d_thresh, n_rhs));
     HIPCK(s->pool.alloc(&s->d_hist, (size_t)64 * n_rhs));
+    HIPCK(s->pool.alloc(&s->d_cbase, 1));
     STCK(setup_fused(s.get()));
     // the fills ran on the legacy default stream; other streams' work (a
     // server's running batches) need not be waited for
@@ -1729,7 +1731,7 @@ static octmg_status graph_for(octmg_state s, long long key, hipStream_t st, F &&
 // cache key of a captured graph: what it was captured for, including the
 // number of grid rows of its launches
 static long long graph_key(int mode, int kind, int max_cycles, int zero_start, int n_launch) {
-    return ((((long long)mode * 8 + kind) * 128 + max_cycles) * 2 + zero_start) * 8192 + n_launch;
+    return ((((long long)mode * 8 + kind) * 128 + max_cycles) * 4 + zero_start) * 8192 + n_launch;
 }
 
 // after the stream has passed the norm kernel
@@ -1804,21 +1806,39 @@ static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStre
         }
         STCK(set_active(s, act, st));
         HIPCK(hipMemcpyAsync(s->d_thresh, th.data(), sizeof(double) * R, hipMemcpyHostToDevice, st));
-        const long long key = graph_key(2, o->cycle_kind, o->max_cycles, o->zero_start ? 1 : 0, s->n_launch);
-        hipGraphExec_t exec = nullptr;
-        STCK(graph_for(s, key, st, [&]() -> octmg_status {
-            for (int c = 0; c < o->max_cycles; c++) {
-                STCK(cycle_and_norm(s, o->cycle_kind, (c > 0 || !o->zero_start) ? 1 : 0, st));
-                HIPCK(launch_converge(s->d_norm, s->d_thresh, s->d_active, s->d_hist, c, R, st));
-            }
-            return OCTMG_OK;
-        }, &exec));
-        STCK(clean_norm_slots(s, st));
-        HIPCK(hipGraphLaunch(exec, st));
-        std::vector<double> hist((size_t)o->max_cycles * R);
+        // The cycles run as replays of one captured chunk of K cycles (all
+        // max_cycles of them when that is at most 16), each cycle followed by
+        // its convergence test; the host looks at the running flags after
+        // each replay and stops once none runs.  The cycles of a chunk after
+        // every rhs has stopped launch and exit at once.
+        const int K = o->max_cycles <= 16 ? o->max_cycles : 8;
+        HIPCK(hipMemsetAsync(s->d_cbase, 0, sizeof(int), st));  // outside the graphs
         std::vector<int> act_after(R);
+        for (int launched = 0; launched < o->max_cycles; launched += K) {
+            const bool first = launched == 0;
+            // the first chunk starts from the caller's iterate (an FMG's
+            // first cycle without a guess when zero_start); later ones go on
+            const long long key =
+                graph_key(2, o->cycle_kind, o->max_cycles, first ? (o->zero_start ? 1 : 0) : 2, s->n_launch);
+            hipGraphExec_t exec = nullptr;
+            STCK(graph_for(s, key, st, [&]() -> octmg_status {
+                for (int c = 0; c < K; c++) {
+                    STCK(cycle_and_norm(s, o->cycle_kind, (c > 0 || !first || !o->zero_start) ? 1 : 0, st));
+                    HIPCK(launch_converge(s->d_norm, s->d_thresh, s->d_active, s->d_hist, c, R, s->d_cbase,
+                                          o->max_cycles, c == K - 1 ? K : 0, st));
+                }
+                return OCTMG_OK;
+            }, &exec));
+            STCK(clean_norm_slots(s, st));
+            HIPCK(hipGraphLaunch(exec, st));
+            HIPCK(hipMemcpyAsync(act_after.data(), s->d_active, sizeof(int) * R, hipMemcpyDeviceToHost, st));
+            HIPCK(hipStreamSynchronize(st));
+            bool running = false;
+            for (int r = 0; r < R; r++) running |= act_after[r] != 0;
+            if (!running) break;
+        }
+        std::vector<double> hist((size_t)o->max_cycles * R);
         HIPCK(hipMemcpyAsync(hist.data(), s->d_hist, sizeof(double) * hist.size(), hipMemcpyDeviceToHost, st));
-        HIPCK(hipMemcpyAsync(act_after.data(), s->d_active, sizeof(int) * R, hipMemcpyDeviceToHost, st));
         HIPCK(hipStreamSynchronize(st));
         s->active_host = act_after;
         int cycles = 0;

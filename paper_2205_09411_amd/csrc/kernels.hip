@@ -869,14 +869,21 @@ __global__ void k_norm_reduce(unsigned long long *slots, unsigned long long *nor
         mapped[r] = m;
     }
 }
+// cycle number cbase + c of a graph solve: record each running rhs's norm,
+// stop it when converged, non-finite, or at the last of max_cycles cycles;
+// the last launch of a chunk of `advance` cycles moves cbase on by it
 __global__ void k_converge(const unsigned long long *norm, const double *thresh, int *active, double *hist, int c,
-                           int nrhs) {
-    for (int r = threadIdx.x; r < nrhs; r += blockDim.x) {
-        if (!active[r]) continue;
-        const double v = __longlong_as_double((long long)norm[r]);
-        hist[(long long)c * nrhs + r] = v;
-        if (v <= thresh[r] || !(v == v)) active[r] = 0;
-    }
+                           int nrhs, int *cbase, int max_cycles, int advance) {
+    const int cc = c + *cbase;
+    if (cc < max_cycles)
+        for (int r = threadIdx.x; r < nrhs; r += blockDim.x) {
+            if (!active[r]) continue;
+            const double v = __longlong_as_double((long long)norm[r]);
+            hist[(long long)cc * nrhs + r] = v;
+            if (v <= thresh[r] || !(v == v) || cc + 1 >= max_cycles) active[r] = 0;
+        }
+    __syncthreads();
+    if (advance && threadIdx.x == 0) *cbase = cc - c + advance;
 }
 __global__ void k_copy_d2f(const double *s, float *d, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -2942,8 +2949,9 @@ hipError_t launch_norm_reduce(unsigned long long *slots, unsigned long long *nor
     return hipGetLastError();
 }
 hipError_t launch_converge(const unsigned long long *norm, const double *thresh, int *active, double *hist, int c,
-                           int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL(k_converge, dim3(1), dim3(256), 0, s, norm, thresh, active, hist, c, nrhs);
+                           int nrhs, int *cbase, int max_cycles, int advance, hipStream_t s) {
+    hipLaunchKernelGGL(k_converge, dim3(1), dim3(256), 0, s, norm, thresh, active, hist, c, nrhs, cbase, max_cycles,
+                       advance);
     return hipGetLastError();
 }
 hipError_t launch_copy_d2f(const double *src, float *dst, long long n, hipStream_t s) {

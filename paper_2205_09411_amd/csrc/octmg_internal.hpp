@@ -193,10 +193,13 @@ hipError_t launch_boundary_terms(int D, const int *meta, const double *cfull, in
 hipError_t launch_fill(double *p, long long n, double v, hipStream_t s);
 hipError_t launch_fillf(float *p, long long n, float v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long long v, hipStream_t s);
-// device-side convergence test of cycle c: for every active rhs record its
-// norm in hist[c][rhs] and freeze it once the norm is <= thresh[rhs]
+// device-side convergence test of cycle *cbase + c of a graph solve: for
+// every active rhs record its norm in hist[cycle][rhs] and freeze it once the
+// norm is <= thresh[rhs] (or not finite, or at cycle max_cycles - 1); with
+// advance > 0 (the last test of a chunk of that many cycles) *cbase then
+// moves on by advance.  Cycles at or beyond max_cycles record nothing.
 hipError_t launch_converge(const unsigned long long *norm, const double *thresh, int *active, double *hist, int c,
-                           int nrhs, hipStream_t s);
+                           int nrhs, int *cbase, int max_cycles, int advance, hipStream_t s);
 hipError_t launch_copy_d2f(const double *src, float *dst, long long n, hipStream_t s);
 hipError_t launch_copy_f2d(const float *src, double *dst, long long n, hipStream_t s);
 hipError_t launch_check_finite(const double *p, long long n, int *flag, hipStream_t s);

@@ -157,3 +157,23 @@ def test_thread_variants_identical_adaptive(precision):
                 ref, ref_cycles = sol, r.cycles
             assert r.cycles == ref_cycles, p
             assert np.array_equal(sol, ref), p
+
+
+@pytest.mark.parametrize("max_cycles", [17, 40])
+def test_whole_solve_graph_in_chunks(max_cycles):
+    """Graph mode 2 replays a captured chunk of 8 cycles when max_cycles is
+    above 16: the same cycles, norms and solution bits as eager launches,
+    also when the solve stops at max_cycles inside a chunk (rtol out of
+    reach)."""
+    print("graph mode 2 in chunks, max_cycles", max_cycles, flush=True)
+    _, S = state(W.cylinder(max_level=3), n_rhs=3)
+    for rtol in (1e-10, 1e-14):
+        ra = S.solve(rtol=rtol, max_cycles=max_cycles, zero_start=True, graph_mode=0, raise_on_fail=False)
+        a = S.get_solution()
+        rb = S.solve(rtol=rtol, max_cycles=max_cycles, zero_start=True, graph_mode=2, raise_on_fail=False)
+        b = S.get_solution()
+        if ra.status == octmg.ERR_NOT_CONVERGED and ra.cycles < max_cycles:
+            continue  # the eager loop's stall test stopped it (graph mode 2 has none)
+        assert ra.status == rb.status and ra.cycles == rb.cycles, (rtol, ra.cycles, rb.cycles)
+        assert ra.r_final == rb.r_final
+        assert np.array_equal(a, b), rtol
