@@ -2188,13 +2188,12 @@ __device__ __forceinline__ void prolong_gs3_body(const LV<T> &L, const LV<T> &Lc
     const T *phic = Lc.phi + (long long)rhs * Lc.fstride;
     const T *oldc = Lc.old + (long long)rhs * Lc.fstride;
     const int t = threadIdx.x;
-    // loads: g of the red cells, record rows, the coarse correction with
-    // its one-cell halo, the red cells' values where ghosts need them
+    // loads: the coarse correction with its one-cell halo, the red cells'
+    // values where ghosts need them (g of the red cells and their record
+    // rows are loaded after the prolongation, which keeps them out of the
+    // registers live across it)
     T gv[PER], ro[PER];
     int ri[PER];
-    load_cells<T, PER, NT, V2, true>(L.g + (long long)rhs * L.fstride + base, t, gv);
-#pragma unroll
-    for (int m = 0; m < PER; m++) ri[m] = mo >= 0 ? L.map[mo + cell_of<NT, V2>(t, m)] : -1;
     const int C0[3] = {P.x * H, P.y * H, P.z * H};
     T ev[EPER];
 #pragma unroll
@@ -2270,6 +2269,9 @@ __device__ __forceinline__ void prolong_gs3_body(const LV<T> &L, const LV<T> &Lc
             }
         }
     }
+    load_cells<T, PER, NT, V2, true>(L.g + (long long)rhs * L.fstride + base, t, gv);
+#pragma unroll
+    for (int m = 0; m < PER; m++) ri[m] = mo >= 0 ? L.map[mo + cell_of<NT, V2>(t, m)] : -1;
     __syncthreads();
     if (any_coarser(nbk)) {
         coarser_face_ghosts<T, N, NT>(tile, Lc, rp, phic, nbk, P, 0, t);
