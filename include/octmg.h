@@ -184,9 +184,14 @@ void octmg_ctx_destroy(octmg_ctx c);
  *     whose leaves are all on the finest level write the FP32 correction's
  *     red cells as the first red half sweep from zero leaves them, so the
  *     FP32 V-cycle starts with the black half sweep; 0 zeroes the
- *     correction and runs that half sweep.  The same iterates either way. */
+ *     correction and runs that half sweep.  The same iterates either way.
+ *   update_fused: 1 (default) lets the last (black) half sweep of the
+ *     mixed-precision FP32 V-cycle on such a tree also add the correction
+ *     to the FP64 solution (phi += e, both colours), in place of a separate
+ *     update launch; 0 runs the two apart.  The same iterates either way. */
 typedef struct octmg_launch_config {
-    int block_order, bottom_kind, bottom_max_blocks, graph_mode, pair_max_blocks, prolong_fused, red_preset;
+    int block_order, bottom_kind, bottom_max_blocks, graph_mode, pair_max_blocks, prolong_fused, red_preset,
+        update_fused;
 } octmg_launch_config;
 octmg_status octmg_state_set_launch(octmg_state s, const octmg_launch_config *c);
 octmg_status octmg_state_get_launch(octmg_state s, octmg_launch_config *c);

@@ -199,6 +199,7 @@ struct octmg_state_s {
     int pair_max_blocks = 1 << 30;             // LV::pair_max of every level
     int prolong_fused = 1;                     // V-cycle prolongation fused with the next red half sweep (3D)
     int red_preset = 1;                        // mixed precision: first red half sweep inside the defect (3D)
+    int update_fused = 1;                      // mixed precision: FP64 update inside the last black half sweep (3D)
     int fused_top = 0;                         // highest fused level (0: none)
     int fused_grid64 = 0, fused_grid32 = 0;    // co-resident workgroups of the fused kernel
     SmallLevels<double> *d_small64 = nullptr;  // device copies of the fused level tables
@@ -319,10 +320,14 @@ struct Engine {
     // timed group then holds the remaining 2 steps - 1 half sweeps.
     // red_preset: the first red half sweep has run inside the mixed-precision
     // defect (the correction starts from zero there); it is skipped.
+    // update_last (FP32 correction of a mixed-precision solve, upd set): the
+    // last (black) half sweep also adds the correction to the FP64 solution
+    // (k_gs_half3_update); it stays outside the timed group.
     octmg_status smooth(int il, int steps, bool fas_first = false, bool after_prolong = false,
-                        bool red_preset = false) {
+                        bool red_preset = false, bool update_last = false) {
         Profile *P = s->prof;
-        const bool timed = P && P->on && il == (int)s->geom->L.size() - 1 && steps > 0;
+        const int plain = 2 * steps - (after_prolong || red_preset ? 1 : 0) - (update_last && steps > 0 ? 1 : 0);
+        const bool timed = P && P->on && il == (int)s->geom->L.size() - 1 && plain > 0;
         hipEvent_t a = nullptr, b = nullptr;
         if (timed) {
             a = P->get();
@@ -332,13 +337,20 @@ struct Engine {
         for (int k = 0; k < steps; k++)
             for (int color = 0; color < 2; color++) {
                 if ((after_prolong || red_preset) && k == 0 && color == 0) continue;
+                const bool upd_here = update_last && k == steps - 1 && color == 1;
+                if (upd_here && timed) HIPCK(hipEventRecord(b, st));
                 if (fas_first && k == 0 && color == 0) {
                     HIPCK(launch_fas_gs<T>(D(), Nb(il), lvT<T>(s, il), lvT<T>(s, il - 1),
                                            s->geom->tree.adaptive ? 1 : 0, s->n_launch, st));
                 } else {
                     LV<T> v = lvT<T>(s, il);
                     if (after_prolong && k == 0) v.own = bp_of(il);
-                    HIPCK(launch_gs_half<T>(D(), Nb(il), v, lvT<T>(s, il - 1), color, s->n_launch, st));
+                    if (upd_here) {
+                        HIPCK(sweep_update(il, v));
+                        upd_done = true;
+                    } else {
+                        HIPCK(launch_gs_half<T>(D(), Nb(il), v, lvT<T>(s, il - 1), color, s->n_launch, st));
+                    }
                 }
                 if (P && P->on) {
                     const GeomLevel &G = s->geom->L[il];
@@ -346,12 +358,17 @@ struct Engine {
                 }
             }
         if (timed) {
-            HIPCK(hipEventRecord(b, st));
+            if (!(update_last && steps > 0)) HIPCK(hipEventRecord(b, st));
             P->pending.push_back({a, b});
-            P->launches.push_back(2 * steps - (after_prolong || red_preset ? 1 : 0));
+            P->launches.push_back(plain);
         }
         return OCTMG_OK;
     }
+    // FP32 correction of a mixed-precision solve: the FP64 finest level that
+    // the last half sweep updates (mixed_correct sets it), and whether it did
+    const LV<double> *upd = nullptr;
+    bool upd_done = false;
+    hipError_t sweep_update(int il, const LV<T> &v);
     T *bp_of(int il) const;
     // the prolongation into il and its first red half sweep in one launch:
     // 3D levels smoothed by separate launches, with post-smoothing
@@ -475,13 +492,15 @@ struct Engine {
         if (ft >= 1) STCK(fused(ft));
         else STCK(coarse_solve(fas_coarse && top >= 1 ? 1 : 0));
         for (int il = std::max(ft, 0) + 1; il <= top; il++) {
+            // the finest level's last half sweep may carry the FP64 update
+            const bool ul = upd != nullptr && il == (int)s->geom->L.size() - 1 && !single_block(il);
             if (prolong_fusable(il)) {
                 STCK(prolong_gs(il));
-                STCK(smooth(il, s->n_up, false, true));
+                STCK(smooth(il, s->n_up, false, true, false, ul));
                 continue;
             }
             STCK(prolong(il, 0));
-            STCK(single_block(il) ? single_block_up(il) : smooth(il, s->n_up));
+            STCK(single_block(il) ? single_block_up(il) : smooth(il, s->n_up, false, false, false, ul));
         }
         return OCTMG_OK;
     }
@@ -521,6 +540,12 @@ octmg_status Engine<float>::fused(int top) {
     const int grid = std::max(1, std::min(s->fused_grid32, most * s->nrhs));
     HIPCK(launch_small_vcycle<float>(s->d_small32, top, grid, st));
     return OCTMG_OK;
+}
+template <>
+hipError_t Engine<double>::sweep_update(int, const LV<double> &) { return hipErrorInvalidValue; }
+template <>
+hipError_t Engine<float>::sweep_update(int il, const LV<float> &v) {
+    return launch_gs_half_update(Nb(il), v, lvT<float>(s, il - 1), *upd, s->n_launch, st);
 }
 template <>
 double *Engine<double>::bp_of(int il) const { return s->f64[il].bp; }
@@ -622,15 +647,31 @@ octmg_status mixed_defect(octmg_state s, hipStream_t st, bool next_v, unsigned l
     return OCTMG_OK;
 }
 
+// The FP64 update phi += e can ride on the correction's last black half
+// sweep of the finest level when every leaf block lies there (3D trees with
+// a separate finest level and post-smoothing): k_gs_half3_update.
+static bool mixed_update_fused(const octmg_state_s *s) {
+    const int top = (int)s->geom->L.size() - 1;
+    const int nb = s->geom->L[top].Nb;
+    return s->update_fused && s->geom->tree.D == 3 && !s->geom->tree.adaptive && top >= 1 && s->fused_top < top &&
+           s->n_up >= 1 && (nb == 8 || nb == 16);
+}
+
 octmg_status mixed_correct(octmg_state s, int kind, hipStream_t st) {
     Engine<float> e32{s, st};
+    const int top = (int)s->geom->L.size() - 1;
+    LV<double> u64;
+    if (mixed_update_fused(s)) {
+        u64 = lv64(s, top);
+        e32.upd = &u64;
+    }
     // only leaf values are passed on; the defect before a V-cycle has done
     // its first red half sweep
     STCK(e32.cycle(kind, kind == OCTMG_CYCLE_FMG ? 0 : 1, false, kind == OCTMG_CYCLE_V && mixed_red_preset(s)));
     const int D = s->geom->tree.D;
     for (int il = 0; il < (int)s->geom->L.size(); il++) {
         const GeomLevel &G = s->geom->L[il];
-        if (G.nleaf == 0) continue;
+        if (G.nleaf == 0 || (il == top && e32.upd_done)) continue;
         HIPCK(launch_update(D, G.Nb, lv64(s, il), lv32(s, il), G.d_leaf_blocks, G.nleaf, s->n_launch, st));
     }
     return OCTMG_OK;
@@ -1382,12 +1423,14 @@ octmg_status octmg_state_set_launch(octmg_state s, const octmg_launch_config *c)
         return fail(OCTMG_ERR_INVALID, "bad launch configuration");
     if (c->bottom_kind == 1 && c->graph_mode != 0)
         return fail(OCTMG_ERR_INVALID, "the cooperative bottom launch cannot be captured");
-    if ((c->prolong_fused != 0 && c->prolong_fused != 1) || (c->red_preset != 0 && c->red_preset != 1))
+    if ((c->prolong_fused != 0 && c->prolong_fused != 1) || (c->red_preset != 0 && c->red_preset != 1) ||
+        (c->update_fused != 0 && c->update_fused != 1))
         return fail(OCTMG_ERR_INVALID, "bad launch configuration");
     s->block_order = c->block_order;
     s->pair_max_blocks = c->pair_max_blocks;
     s->prolong_fused = c->prolong_fused;
     s->red_preset = c->red_preset;
+    s->update_fused = c->update_fused;
     s->tuned_graph = c->graph_mode;
     s->fused_max_blocks = c->bottom_kind ? c->bottom_max_blocks : 0;
     HIPCK(hipSetDevice(s->geom->device));
@@ -1403,6 +1446,7 @@ octmg_status octmg_state_get_launch(octmg_state s, octmg_launch_config *c) {
     c->pair_max_blocks = s->pair_max_blocks;
     c->prolong_fused = s->prolong_fused;
     c->red_preset = s->red_preset;
+    c->update_fused = s->update_fused;
     return OCTMG_OK;
 }
 
@@ -1986,8 +2030,8 @@ static bool tune_lookup(const std::string &path, const std::string &key, octmg_l
         char *tab = std::strchr(line, '\t');
         if (!tab || std::string(line, tab - line) != key) continue;
         octmg_launch_config t{};
-        if (std::sscanf(tab + 1, "%d %d %d %d %d %d %d", &t.block_order, &t.bottom_kind, &t.bottom_max_blocks,
-                        &t.graph_mode, &t.pair_max_blocks, &t.prolong_fused, &t.red_preset) == 7) {
+        if (std::sscanf(tab + 1, "%d %d %d %d %d %d %d %d", &t.block_order, &t.bottom_kind, &t.bottom_max_blocks,
+                        &t.graph_mode, &t.pair_max_blocks, &t.prolong_fused, &t.red_preset, &t.update_fused) == 8) {
             *c = t;
             found = true;
         }
@@ -2000,8 +2044,9 @@ static void tune_record(const std::string &path, const std::string &key, const o
     std::lock_guard<std::mutex> lk(g_tune_mu);
     FILE *f = std::fopen(path.c_str(), "a");
     if (!f) return;  // an unwritable cache only costs the next tuning run
-    std::fprintf(f, "%s\t%d %d %d %d %d %d %d %.4f\n", key.c_str(), c.block_order, c.bottom_kind,
-                 c.bottom_max_blocks, c.graph_mode, c.pair_max_blocks, c.prolong_fused, c.red_preset, ms);
+    std::fprintf(f, "%s\t%d %d %d %d %d %d %d %d %.4f\n", key.c_str(), c.block_order, c.bottom_kind,
+                 c.bottom_max_blocks, c.graph_mode, c.pair_max_blocks, c.prolong_fused, c.red_preset, c.update_fused,
+                 ms);
     std::fclose(f);
 }
 
@@ -2018,21 +2063,21 @@ octmg_status octmg_autotune(octmg_state s, const octmg_solve_opts *o, int reps, 
     std::vector<octmg_launch_config> cand;
     constexpr int all = 1 << 30;
     for (int order = 0; order < 3; order++) {
-        cand.push_back({order, 0, 0, 0, all, 1, 1});
-        cand.push_back({order, 0, 0, 1, all, 1, 1});
+        cand.push_back({order, 0, 0, 0, all, 1, 1, 1});
+        cand.push_back({order, 0, 0, 1, all, 1, 1, 1});
         if (s->geom->tree.D == 3) {
-            cand.push_back({order, 1, 8, 0, all, 1, 1});
-            cand.push_back({order, 1, 64, 0, all, 1, 1});
+            cand.push_back({order, 1, 8, 0, all, 1, 1, 1});
+            cand.push_back({order, 1, 64, 0, all, 1, 1, 1});
         }
     }
     if (s->geom->tree.D == 3) {
-        cand.push_back({0, 0, 0, 0, 0, 1, 1});
-        cand.push_back({0, 0, 0, 1, 0, 1, 1});
+        cand.push_back({0, 0, 0, 0, 0, 1, 1, 1});
+        cand.push_back({0, 0, 0, 1, 0, 1, 1, 1});
     }
     // the whole solve as one captured launch (max_cycles cycles, convergence
     // tested on the device), with the 512- and the 256-thread kernels
-    cand.push_back({0, 0, 0, 2, all, 1, 1});
-    if (s->geom->tree.D == 3) cand.push_back({0, 0, 0, 2, 0, 1, 1});
+    cand.push_back({0, 0, 0, 2, all, 1, 1, 1});
+    if (s->geom->tree.D == 3) cand.push_back({0, 0, 0, 2, 0, 1, 1, 1});
     if (n_candidates) *n_candidates = (int)cand.size();
     double best_ms = 0.0;
     int best_i = -1;

@@ -1227,9 +1227,13 @@ __device__ __forceinline__ void tile_neighbours(const T *tile, int col, int q, i
     v[5] = tile[CT::at(k + 1, j, h)];
 }
 
-// red-black half sweep, NT threads per block (V2: cells in adjacent pairs)
+// red-black half sweep, NT threads per block (V2: cells in adjacent pairs).
+// U (FP32 sweeps only): the FP64 level of a mixed-precision solve; the
+// block's FP64 values take the update phi += e from the swept colour's new
+// values and the other colour's staged ones (k_gs_half3_update)
 template <typename T, int N, int NT = 256, bool V2 = false>
-__device__ __forceinline__ void gs_half3_body(const LV<T> &L, const LV<T> &Lc, int color, int blk, int rhs, T *tile) {
+__device__ __forceinline__ void gs_half3_body(const LV<T> &L, const LV<T> &Lc, int color, int blk, int rhs, T *tile,
+                                              const LV<double> *U = nullptr) {
     using B = Blk<3, N>;
     constexpr int PER = B::HALF / NT;
     const int4 P = L.pos[blk];
@@ -1279,13 +1283,45 @@ __device__ __forceinline__ void gs_half3_body(const LV<T> &L, const LV<T> &Lc, i
             nv[m] = (gv[m] - bt - s) * r[7];
         }
     }
-    store_cells<T, PER, NT, V2>(dst, threadIdx.x, nv);
+    if (!U) {
+        store_cells<T, PER, NT, V2>(dst, threadIdx.x, nv);
+        return;
+    }
+    // phi += e on both colours, in FP64 (k_update's arithmetic); the swept
+    // colour's e is not stored
+    constexpr int NH = N / 2;
+    using CT = ColTile<N>;
+    double *p64 = U->phi + (long long)rhs * U->fstride + base;
+    double sw[PER], ot[PER];
+    load_cells<double, PER, NT, V2, true>(p64 + color * B::HALF, threadIdx.x, sw);
+    load_cells<double, PER, NT, V2, true>(p64 + (1 - color) * B::HALF, threadIdx.x, ot);
+#pragma unroll
+    for (int m = 0; m < PER; m++) {
+        const int q = cell_of<NT, V2>(threadIdx.x, m);
+        sw[m] += (double)nv[m];
+        ot[m] += (double)tile[CT::at(q / (NH * N), (q / NH) % N, q % NH)];
+    }
+    store_cells<double, PER, NT, V2>(p64 + color * B::HALF, threadIdx.x, sw);
+    store_cells<double, PER, NT, V2>(p64 + (1 - color) * B::HALF, threadIdx.x, ot);
 }
 
 template <typename T, int N, int NT, bool V2>
 __global__ __launch_bounds__(NT) void k_gs_half3(LV<T> L, LV<T> Lc, int color) {
     __shared__ T tile[ColTile<N>::SIZE];
     gs_half3_body<T, N, NT, V2>(L, Lc, color, block_of(L), rhs_of(L), tile);
+}
+
+// The last half sweep (black) of the FP32 correction's V-cycle on a level
+// whose blocks are all leaves, fused with the FP64 update phi += e that
+// follows the cycle (k_update): the black cells add their new values, the
+// red cells the values staged for the sweep, which it does not change.  The
+// black correction values themselves are not stored: the next defect
+// overwrites the correction on every leaf cell before anything reads it.
+// Same FP64 bits as the half sweep followed by k_update.
+template <int N, int NT, bool V2>
+__global__ __launch_bounds__(NT) void k_gs_half3_update(LV<float> L, LV<float> Lc, LV<double> U) {
+    __shared__ float tile[ColTile<N>::SIZE];
+    gs_half3_body<float, N, NT, V2>(L, Lc, 1, block_of(L), rhs_of(L), tile, &U);
 }
 
 // L phi at the PER cells of colour `col` owned by this thread, from the
@@ -2630,6 +2666,21 @@ hipError_t launch_gs_half(int D, int N, const LV<T> &L, const LV<T> &Lc, int col
 #undef GS3
 #undef GS
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_gs_half_update(int N, const LV<float> &L, const LV<float> &Lc, const LV<double> &U, int nrhs,
+                                 hipStream_t s) {
+    if (L.nblocks == 0) return hipSuccess;
+    dim3 grid(L.nblocks, nrhs);
+    if (N == 16 && (long long)L.nblocks * nrhs <= L.pair_max)
+        hipLaunchKernelGGL((k_gs_half3_update<16, 512, cell_pairs<16>()>), grid, dim3(512), 0, s, L, Lc, U);
+    else if (N == 16)
+        hipLaunchKernelGGL((k_gs_half3_update<16, 256, cell_pairs<16>()>), grid, dim3(256), 0, s, L, Lc, U);
+    else if (N == 8)
+        hipLaunchKernelGGL((k_gs_half3_update<8, 256, cell_pairs<8>()>), grid, dim3(256), 0, s, L, Lc, U);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 #define OCTMG_DNC(D_, N_, NC_, CALL) \

@@ -63,7 +63,7 @@ class SolveOpts(C.Structure):
 class LaunchConfig(C.Structure):
     _fields_ = [("block_order", C.c_int), ("bottom_kind", C.c_int), ("bottom_max_blocks", C.c_int),
                 ("graph_mode", C.c_int), ("pair_max_blocks", C.c_int), ("prolong_fused", C.c_int),
-                ("red_preset", C.c_int)]
+                ("red_preset", C.c_int), ("update_fused", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -468,9 +468,9 @@ class State:
         _check(lib().octmg_state_set_smoothing(self._h, n_down, n_up))
 
     def set_launch(self, block_order=0, bottom_kind=0, bottom_max_blocks=0, graph_mode=0, pair_max_blocks=1 << 30,
-                   prolong_fused=1, red_preset=1):
+                   prolong_fused=1, red_preset=1, update_fused=1):
         c = LaunchConfig(block_order, bottom_kind, bottom_max_blocks, graph_mode, pair_max_blocks, prolong_fused,
-                         red_preset)
+                         red_preset, update_fused)
         _check(lib().octmg_state_set_launch(self._h, C.byref(c)))
 
     def get_launch(self) -> dict:

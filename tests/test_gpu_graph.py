@@ -115,14 +115,15 @@ def test_launch_configurations_and_autotune_identical():
     ref_rep = S.solve(rtol=1e-10, zero_start=True)
     ref = S.get_solution()
     configs = [dict(block_order=o, bottom_kind=b, bottom_max_blocks=m, graph_mode=g, pair_max_blocks=1 << 30,
-                    prolong_fused=1, red_preset=1)
+                    prolong_fused=1, red_preset=1, update_fused=1)
                for o in (0, 1, 2) for (b, m, g) in ((0, 0, 0), (0, 0, 1), (0, 0, 2), (1, 8, 0), (1, 64, 0))]
     # the 512-thread kernels on no level, on the levels of at most 64 blocks;
     # prolongation and red half sweep as separate launches; the mixed
-    # defect without the first red half sweep
+    # defect without the first red half sweep; the FP64 update apart from
+    # the last black half sweep
     configs += [dict(block_order=0, bottom_kind=0, bottom_max_blocks=0, graph_mode=g, pair_max_blocks=p,
-                     prolong_fused=f, red_preset=r)
-                for p in (0, 64) for g in (0, 2) for f in (0, 1) for r in (0, 1)]
+                     prolong_fused=f, red_preset=r, update_fused=u)
+                for p in (0, 64) for g in (0, 2) for f in (0, 1) for (r, u) in ((0, 0), (1, 1), (1, 0))]
     for c in configs:
         S.set_launch(**c)
         assert S.get_launch() == c

@@ -1,11 +1,18 @@
-"""The mixed-precision defect that leaves the FP32 correction's red cells as
-its first red half sweep from zero would (launch option red_preset, the
-default) gives the same iterates bit for bit as zeroing the correction and
-running that half sweep: uniform 3D trees with 16^3 and 8^3 blocks, an
+"""Two launch fusions of the mixed-precision solve give the same iterates
+bit for bit as the separate launches they replace:
+
+* red_preset: the FP64 defect leaves the FP32 correction's red cells as its
+  first red half sweep from zero would, instead of zeroing the correction
+  and running that half sweep;
+* update_fused: the correction's last black half sweep on the finest level
+  adds the correction to the FP64 solution, instead of a separate update
+  launch after the cycle.
+
+Uniform 3D trees with 16^3 (512- and 256-lane kernels) and 8^3 blocks, an
 interface through cell centres, zero-flux faces, several right-hand sides,
-pre-smoothing counts 1 to 3, eager launches and graphs, V-cycles and solves;
-where it does not apply (adaptive trees, FMG corrections) the two settings
-run the same launches."""
+smoothing counts (1..3, 1..2), eager launches and graphs, V-cycles, FMG
+corrections and solves; where a fusion does not apply (adaptive trees, FMG
+corrections for red_preset) the settings run the same launches."""
 import numpy as np
 import pytest
 
@@ -24,9 +31,9 @@ CASES = {
 }
 
 
-def state(w, G, preset, n_rhs, n_down, n_up):
+def state(w, G, launch, n_rhs, n_down, n_up):
     S = octmg.State(G, n_rhs, octmg.MIXED)
-    S.set_launch(red_preset=preset)
+    S.set_launch(**launch)
     S.set_smoothing(n_down, n_up)
     S.set_boundary_fn(w.iface_value, w.domain_value)
     xyz, _ = G.leaf_coords()
@@ -35,14 +42,10 @@ def state(w, G, preset, n_rhs, n_down, n_up):
     return S
 
 
-@pytest.mark.parametrize("name", sorted(CASES))
-def test_red_preset_bitwise(name):
-    w = CASES[name]()
-    print("red preset", name, flush=True)
-    G = octmg.Geometry(w.geom)
+def compare(w, G, fused, apart):
     for n_down, n_up, n_rhs in ((2, 2, 1), (1, 2, 3), (3, 1, 1)):
-        a = state(w, G, 1, n_rhs, n_down, n_up)
-        b = state(w, G, 0, n_rhs, n_down, n_up)
+        a = state(w, G, fused, n_rhs, n_down, n_up)
+        b = state(w, G, apart, n_rhs, n_down, n_up)
         for k in range(2):
             a.vcycle()
             b.vcycle()
@@ -55,3 +58,26 @@ def test_red_preset_bitwise(name):
             rb = b.solve(rtol=1e-10, max_cycles=30, zero_start=True, graph_mode=gm, raise_on_fail=False)
             assert ra.cycles == rb.cycles and ra.r_final == rb.r_final, (n_down, n_up, gm)
             assert np.array_equal(a.get_solution(), b.get_solution()), (n_down, n_up, "solve", gm)
+
+
+@pytest.mark.parametrize("option", ["red_preset", "update_fused"])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_fusion_bitwise(name, option):
+    w = CASES[name]()
+    print("mixed fusion", option, name, flush=True)
+    G = octmg.Geometry(w.geom)
+    compare(w, G, {}, {option: 0})
+
+
+@pytest.mark.parametrize("option", ["red_preset", "update_fused"])
+def test_fusion_bitwise_256_lanes(option):
+    """16^3 blocks with the 256-lane kernels on every level."""
+    w = CASES["mms3d_b16_64"]()
+    G = octmg.Geometry(w.geom)
+    compare(w, G, {"pair_max_blocks": 0}, {"pair_max_blocks": 0, option: 0})
+
+
+def test_both_fusions_off():
+    w = CASES["cylinder_64"]()
+    G = octmg.Geometry(w.geom)
+    compare(w, G, {}, {"red_preset": 0, "update_fused": 0})
