@@ -322,7 +322,8 @@ struct Engine {
     // defect (the correction starts from zero there); it is skipped.
     // update_last (FP32 correction of a mixed-precision solve, upd set): the
     // last (black) half sweep also adds the correction to the FP64 solution
-    // (k_gs_half3_update); it stays outside the timed group.
+    // on the level's leaf blocks (k_gs_half3_update); it stays outside the
+    // timed group.
     octmg_status smooth(int il, int steps, bool fas_first = false, bool after_prolong = false,
                         bool red_preset = false, bool update_last = false) {
         Profile *P = s->prof;
@@ -347,7 +348,7 @@ struct Engine {
                     if (after_prolong && k == 0) v.own = bp_of(il);
                     if (upd_here) {
                         HIPCK(sweep_update(il, v));
-                        upd_done = true;
+                        upd_levels |= 1ull << il;
                     } else {
                         HIPCK(launch_gs_half<T>(D(), Nb(il), v, lvT<T>(s, il - 1), color, s->n_launch, st));
                     }
@@ -364,10 +365,11 @@ struct Engine {
         }
         return OCTMG_OK;
     }
-    // FP32 correction of a mixed-precision solve: the FP64 finest level that
-    // the last half sweep updates (mixed_correct sets it), and whether it did
-    const LV<double> *upd = nullptr;
-    bool upd_done = false;
+    // FP32 correction of a mixed-precision solve: the last half sweep of each
+    // level with leaves in the final V-cycle adds the correction to the FP64
+    // solution there (mixed_correct sets upd); upd_levels: the levels it did
+    bool upd = false;
+    unsigned long long upd_levels = 0;
     hipError_t sweep_update(int il, const LV<T> &v);
     T *bp_of(int il) const;
     // the prolongation into il and its first red half sweep in one launch:
@@ -491,9 +493,13 @@ struct Engine {
         }
         if (ft >= 1) STCK(fused(ft));
         else STCK(coarse_solve(fas_coarse && top >= 1 ? 1 : 0));
+        // in the final V-cycle (top = the finest level) each level's leaf
+        // values are final after its post-smoothing: its last half sweep may
+        // carry the FP64 update
+        const bool last = upd && top == (int)s->geom->L.size() - 1;
         for (int il = std::max(ft, 0) + 1; il <= top; il++) {
-            // the finest level's last half sweep may carry the FP64 update
-            const bool ul = upd != nullptr && il == (int)s->geom->L.size() - 1 && !single_block(il);
+            const bool ul = last && s->geom->L[il].nleaf > 0 && !single_block(il) && il < 64 &&
+                            (Nb(il) == 8 || Nb(il) == 16);
             if (prolong_fusable(il)) {
                 STCK(prolong_gs(il));
                 STCK(smooth(il, s->n_up, false, true, false, ul));
@@ -545,7 +551,8 @@ template <>
 hipError_t Engine<double>::sweep_update(int, const LV<double> &) { return hipErrorInvalidValue; }
 template <>
 hipError_t Engine<float>::sweep_update(int il, const LV<float> &v) {
-    return launch_gs_half_update(Nb(il), v, lvT<float>(s, il - 1), *upd, s->n_launch, st);
+    const int keep = s->geom->tree.adaptive ? 1 : 0;
+    return launch_gs_half_update(Nb(il), v, lvT<float>(s, il - 1), lv64(s, il), keep, s->n_launch, st);
 }
 template <>
 double *Engine<double>::bp_of(int il) const { return s->f64[il].bp; }
@@ -648,30 +655,23 @@ octmg_status mixed_defect(octmg_state s, hipStream_t st, bool next_v, unsigned l
 }
 
 // The FP64 update phi += e can ride on the correction's last black half
-// sweep of the finest level when every leaf block lies there (3D trees with
-// a separate finest level and post-smoothing): k_gs_half3_update.
+// sweep of each level with leaves (3D, with post-smoothing): those levels
+// that the final V-cycle smooths by separate launches (k_gs_half3_update);
+// the others take k_update.
 static bool mixed_update_fused(const octmg_state_s *s) {
-    const int top = (int)s->geom->L.size() - 1;
-    const int nb = s->geom->L[top].Nb;
-    return s->update_fused && s->geom->tree.D == 3 && !s->geom->tree.adaptive && top >= 1 && s->fused_top < top &&
-           s->n_up >= 1 && (nb == 8 || nb == 16);
+    return s->update_fused && s->geom->tree.D == 3 && s->n_up >= 1;
 }
 
 octmg_status mixed_correct(octmg_state s, int kind, hipStream_t st) {
     Engine<float> e32{s, st};
-    const int top = (int)s->geom->L.size() - 1;
-    LV<double> u64;
-    if (mixed_update_fused(s)) {
-        u64 = lv64(s, top);
-        e32.upd = &u64;
-    }
+    e32.upd = mixed_update_fused(s);
     // only leaf values are passed on; the defect before a V-cycle has done
     // its first red half sweep
     STCK(e32.cycle(kind, kind == OCTMG_CYCLE_FMG ? 0 : 1, false, kind == OCTMG_CYCLE_V && mixed_red_preset(s)));
     const int D = s->geom->tree.D;
     for (int il = 0; il < (int)s->geom->L.size(); il++) {
         const GeomLevel &G = s->geom->L[il];
-        if (G.nleaf == 0 || (il == top && e32.upd_done)) continue;
+        if (G.nleaf == 0 || (il < 64 && (e32.upd_levels >> il) & 1)) continue;
         HIPCK(launch_update(D, G.Nb, lv64(s, il), lv32(s, il), G.d_leaf_blocks, G.nleaf, s->n_launch, st));
     }
     return OCTMG_OK;

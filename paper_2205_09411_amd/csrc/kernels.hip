@@ -1230,10 +1230,12 @@ __device__ __forceinline__ void tile_neighbours(const T *tile, int col, int q, i
 // red-black half sweep, NT threads per block (V2: cells in adjacent pairs).
 // U (FP32 sweeps only): the FP64 level of a mixed-precision solve; the
 // block's FP64 values take the update phi += e from the swept colour's new
-// values and the other colour's staged ones (k_gs_half3_update)
+// values and the other colour's staged ones (k_gs_half3_update).  keep: the
+// swept colour is stored as well and only leaf blocks are updated (levels
+// of adaptive trees, whose values finer levels still read as ghosts)
 template <typename T, int N, int NT = 256, bool V2 = false>
 __device__ __forceinline__ void gs_half3_body(const LV<T> &L, const LV<T> &Lc, int color, int blk, int rhs, T *tile,
-                                              const LV<double> *U = nullptr) {
+                                              const LV<double> *U = nullptr, int keep = 0) {
     using B = Blk<3, N>;
     constexpr int PER = B::HALF / NT;
     const int4 P = L.pos[blk];
@@ -1241,7 +1243,8 @@ __device__ __forceinline__ void gs_half3_body(const LV<T> &L, const LV<T> &Lc, i
     face_ids<T, N>(L, blk, nbk);
     const int mo = L.map_off ? L.map_off[blk] : -1;
     const int act = L.active ? L.active[rhs] : 1;
-    tables_loaded(act, 1, P, nbk, mo);
+    const int leaf = U && keep ? L.leaf[blk] : 1;
+    tables_loaded(act, leaf, P, nbk, mo);
     if (!act) return;
     T *__restrict__ phi = L.phi + (long long)rhs * L.fstride;
     const long long base = (long long)blk * B::CPB;
@@ -1283,12 +1286,10 @@ __device__ __forceinline__ void gs_half3_body(const LV<T> &L, const LV<T> &Lc, i
             nv[m] = (gv[m] - bt - s) * r[7];
         }
     }
-    if (!U) {
-        store_cells<T, PER, NT, V2>(dst, threadIdx.x, nv);
-        return;
-    }
-    // phi += e on both colours, in FP64 (k_update's arithmetic); the swept
-    // colour's e is not stored
+    if (!U || keep) store_cells<T, PER, NT, V2>(dst, threadIdx.x, nv);
+    if (!U || !leaf) return;
+    // phi += e on both colours, in FP64 (k_update's arithmetic); without
+    // keep the swept colour's e is not stored
     constexpr int NH = N / 2;
     using CT = ColTile<N>;
     double *p64 = U->phi + (long long)rhs * U->fstride + base;
@@ -1311,17 +1312,19 @@ __global__ __launch_bounds__(NT) void k_gs_half3(LV<T> L, LV<T> Lc, int color) {
     gs_half3_body<T, N, NT, V2>(L, Lc, color, block_of(L), rhs_of(L), tile);
 }
 
-// The last half sweep (black) of the FP32 correction's V-cycle on a level
-// whose blocks are all leaves, fused with the FP64 update phi += e that
-// follows the cycle (k_update): the black cells add their new values, the
-// red cells the values staged for the sweep, which it does not change.  The
-// black correction values themselves are not stored: the next defect
-// overwrites the correction on every leaf cell before anything reads it.
-// Same FP64 bits as the half sweep followed by k_update.
+// The last half sweep (black) of a level in the FP32 correction's final
+// V-cycle, fused with the FP64 update phi += e of the level's leaf blocks
+// that follows the cycle (k_update): the black cells add their new values,
+// the red cells the values staged for the sweep, which it does not change.
+// keep = 0 (every block a leaf, no finer level): the black correction values
+// themselves are not stored, since the next defect overwrites the correction
+// on every leaf cell before anything reads it; keep = 1 (adaptive trees):
+// they are stored, parent blocks and finer levels' ghosts read them.  Same
+// FP64 bits as the half sweep followed by k_update.
 template <int N, int NT, bool V2>
-__global__ __launch_bounds__(NT) void k_gs_half3_update(LV<float> L, LV<float> Lc, LV<double> U) {
+__global__ __launch_bounds__(NT) void k_gs_half3_update(LV<float> L, LV<float> Lc, LV<double> U, int keep) {
     __shared__ float tile[ColTile<N>::SIZE];
-    gs_half3_body<float, N, NT, V2>(L, Lc, 1, block_of(L), rhs_of(L), tile, &U);
+    gs_half3_body<float, N, NT, V2>(L, Lc, 1, block_of(L), rhs_of(L), tile, &U, keep);
 }
 
 // L phi at the PER cells of colour `col` owned by this thread, from the
@@ -2668,16 +2671,16 @@ hipError_t launch_gs_half(int D, int N, const LV<T> &L, const LV<T> &Lc, int col
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_gs_half_update(int N, const LV<float> &L, const LV<float> &Lc, const LV<double> &U, int nrhs,
-                                 hipStream_t s) {
+hipError_t launch_gs_half_update(int N, const LV<float> &L, const LV<float> &Lc, const LV<double> &U, int keep,
+                                 int nrhs, hipStream_t s) {
     if (L.nblocks == 0) return hipSuccess;
     dim3 grid(L.nblocks, nrhs);
     if (N == 16 && (long long)L.nblocks * nrhs <= L.pair_max)
-        hipLaunchKernelGGL((k_gs_half3_update<16, 512, cell_pairs<16>()>), grid, dim3(512), 0, s, L, Lc, U);
+        hipLaunchKernelGGL((k_gs_half3_update<16, 512, cell_pairs<16>()>), grid, dim3(512), 0, s, L, Lc, U, keep);
     else if (N == 16)
-        hipLaunchKernelGGL((k_gs_half3_update<16, 256, cell_pairs<16>()>), grid, dim3(256), 0, s, L, Lc, U);
+        hipLaunchKernelGGL((k_gs_half3_update<16, 256, cell_pairs<16>()>), grid, dim3(256), 0, s, L, Lc, U, keep);
     else if (N == 8)
-        hipLaunchKernelGGL((k_gs_half3_update<8, 256, cell_pairs<8>()>), grid, dim3(256), 0, s, L, Lc, U);
+        hipLaunchKernelGGL((k_gs_half3_update<8, 256, cell_pairs<8>()>), grid, dim3(256), 0, s, L, Lc, U, keep);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -90,11 +90,12 @@ struct LV {
 // block edge.  Return hipSuccess or the launch error.
 template <typename T>
 hipError_t launch_gs_half(int D, int N, const LV<T> &L, const LV<T> &Lc, int color, int nrhs, hipStream_t s);
-// 3D FP32 black half sweep of a level whose blocks are all leaves, with the
-// mixed-precision update U.phi += e of every cell of its blocks (both
-// colours) in place of storing the black values; N = 8 or 16
-hipError_t launch_gs_half_update(int N, const LV<float> &L, const LV<float> &Lc, const LV<double> &U, int nrhs,
-                                 hipStream_t s);
+// 3D FP32 black half sweep with the mixed-precision update U.phi += e of
+// every cell (both colours) of the level's leaf blocks.  keep = 0: every
+// block is a leaf and the black values are not stored; keep = 1: they are
+// stored and blocks with L.leaf[blk] = 0 are not updated.  N = 8 or 16
+hipError_t launch_gs_half_update(int N, const LV<float> &L, const LV<float> &Lc, const LV<double> &U, int keep,
+                                 int nrhs, hipStream_t s);
 // phi_c is written to Lc.phi, or to Lc.old when `into_old` (adaptive trees:
 // refinement-boundary ghosts of the fine level still read Lc.phi); then
 // launch_copy_parents moves it to phi on parent blocks (and copies phi to

@@ -4,15 +4,18 @@ bit for bit as the separate launches they replace:
 * red_preset: the FP64 defect leaves the FP32 correction's red cells as its
   first red half sweep from zero would, instead of zeroing the correction
   and running that half sweep;
-* update_fused: the correction's last black half sweep on the finest level
-  adds the correction to the FP64 solution, instead of a separate update
-  launch after the cycle.
+* update_fused: in the correction's final V-cycle the last black half sweep
+  of each level with leaf blocks adds the correction to the FP64 solution
+  there, instead of a separate update launch after the cycle (on adaptive
+  trees the black correction is stored as well and only leaf blocks are
+  updated).
 
-Uniform 3D trees with 16^3 (512- and 256-lane kernels) and 8^3 blocks, an
-interface through cell centres, zero-flux faces, several right-hand sides,
-smoothing counts (1..3, 1..2), eager launches and graphs, V-cycles, FMG
-corrections and solves; where a fusion does not apply (adaptive trees, FMG
-corrections for red_preset) the settings run the same launches."""
+Uniform 3D trees with 16^3 (512- and 256-lane kernels) and 8^3 blocks,
+adaptive trees with 16^3 and 8^3 blocks, an interface through cell centres,
+zero-flux faces, several right-hand sides, smoothing counts (1..3, 1..2),
+eager launches and graphs, V-cycles, FMG corrections and solves; where a
+fusion does not apply (red_preset on adaptive trees and FMG corrections)
+the settings run the same launches."""
 import numpy as np
 import pytest
 
@@ -28,6 +31,7 @@ CASES = {
     "through_centres_64": lambda: W.through_centres(),
     "electrodes_uniform": lambda: W.two_electrodes(max_level=4, uniform_level=4),
     "spheres_amr16": lambda: W.spheres(n_spheres=8, max_level=5, block_n=16, seed=12),
+    "spheres_amr8": lambda: W.spheres(n_spheres=5, max_level=5, block_n=8, seed=9),
 }
 
 
