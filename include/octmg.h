@@ -185,10 +185,11 @@ void octmg_ctx_destroy(octmg_ctx c);
  *     red cells as the first red half sweep from zero leaves them, so the
  *     FP32 V-cycle starts with the black half sweep; 0 zeroes the
  *     correction and runs that half sweep.  The same iterates either way.
- *   update_fused: 1 (default) lets the last (black) half sweep of the
- *     mixed-precision FP32 V-cycle on such a tree also add the correction
- *     to the FP64 solution (phi += e, both colours), in place of a separate
- *     update launch; 0 runs the two apart.  The same iterates either way. */
+ *   update_fused: 1 (default) lets the last (black) half sweep of each 3D
+ *     level with leaf blocks in the mixed-precision FP32 correction's final
+ *     V-cycle also add the correction to the FP64 solution on those blocks
+ *     (phi += e, both colours), in place of a separate update launch; 0
+ *     runs the two apart.  The same iterates either way. */
 typedef struct octmg_launch_config {
     int block_order, bottom_kind, bottom_max_blocks, graph_mode, pair_max_blocks, prolong_fused, red_preset,
         update_fused;
