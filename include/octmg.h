@@ -181,10 +181,10 @@ void octmg_ctx_destroy(octmg_ctx c);
  *     the red half sweep after it as one launch (the black values are
  *     prolonged on the fly), 0 as two.  The same iterates either way.
  *   red_preset: 1 (default) lets the mixed-precision defect of a 3D tree
- *     whose leaves are all on the finest level write the FP32 correction's
- *     red cells as the first red half sweep from zero leaves them, so the
- *     FP32 V-cycle starts with the black half sweep; 0 zeroes the
- *     correction and runs that half sweep.  The same iterates either way.
+ *     write the FP32 correction's red cells on the finest level as the
+ *     first red half sweep from zero leaves them, so the FP32 V-cycle starts
+ *     there with the black half sweep; 0 zeroes the correction and runs that
+ *     half sweep.  The same iterates either way.
  *   update_fused: 1 (default) lets the last (black) half sweep of each 3D
  *     level with leaf blocks in the mixed-precision FP32 correction's final
  *     V-cycle also add the correction to the FP64 solution on those blocks

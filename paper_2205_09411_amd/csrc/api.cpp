@@ -611,15 +611,15 @@ octmg_status read_norms(octmg_state s, double *out, hipStream_t st) {
     return OCTMG_OK;
 }
 
-// The FP32 V-cycle on the correction starts from zero, so its first red half
-// sweep on the finest level needs nothing but the FP32 right-hand side of
-// each red cell: the defect kernel writes it there directly (3D trees whose
-// leaves all lie on the finest level, smoothed by separate launches with at
-// least one pre-smoothing step).  The same bits as the half sweep.
+// The FP32 V-cycle on the correction starts from zero (every level, so the
+// refinement-boundary ghosts of adaptive trees are zero too), so its first
+// red half sweep on the finest level needs nothing but the FP32 right-hand
+// side of each red cell: the defect kernel writes it there directly (3D
+// trees whose finest level is smoothed by separate launches with at least
+// one pre-smoothing step).  The same bits as the half sweep.
 static bool mixed_red_preset(const octmg_state_s *s) {
     const int top = (int)s->geom->L.size() - 1;
-    return s->red_preset && s->geom->tree.D == 3 && !s->geom->tree.adaptive && top >= 1 && s->fused_top < top &&
-           s->n_down >= 1;
+    return s->red_preset && s->geom->tree.D == 3 && top >= 1 && s->fused_top < top && s->n_down >= 1;
 }
 
 // one outer step of the mixed-precision defect correction: FP64 defect on
@@ -627,6 +627,7 @@ static bool mixed_red_preset(const octmg_state_s *s) {
 // next_v: the correction that follows is a V-cycle (mixed_red_preset applies)
 octmg_status mixed_defect(octmg_state s, hipStream_t st, bool next_v, unsigned long long *mapped = nullptr) {
     const int red = next_v && mixed_red_preset(s) ? 1 : 0;
+    const int top = (int)s->geom->L.size() - 1;
     Engine<double> e64{s, st};
     STCK(e64.sync_down());
     if (!s->norm_slots_clean) HIPCK(launch_fill_u64(s->d_norm_slots, norm_slot_words(s->nrhs), 0ull, st));
@@ -647,7 +648,7 @@ octmg_status mixed_defect(octmg_state s, hipStream_t st, bool next_v, unsigned l
         const GeomLevel &G = s->geom->L[il];
         if (G.nleaf == 0) continue;
         HIPCK(launch_defect(D, G.Nb, lv64(s, il), lv64(s, il - 1), lv32(s, il), G.d_leaf_blocks, G.nleaf,
-                            s->d_norm_slots, s->n_launch, st, red));
+                            s->d_norm_slots, s->n_launch, st, il == top ? red : 0));
     }
     HIPCK(launch_norm_reduce(s->d_norm_slots, s->d_norm, mapped ? mapped : s->h_norm_dev, s->nrhs, st));
     s->norm_slots_clean = true;

@@ -1,9 +1,10 @@
 """Two launch fusions of the mixed-precision solve give the same iterates
 bit for bit as the separate launches they replace:
 
-* red_preset: the FP64 defect leaves the FP32 correction's red cells as its
-  first red half sweep from zero would, instead of zeroing the correction
-  and running that half sweep;
+* red_preset: the FP64 defect leaves the FP32 correction's red cells on the
+  finest level as its first red half sweep from zero would, instead of
+  zeroing the correction and running that half sweep (on adaptive trees the
+  coarser leaf levels are zeroed as before);
 * update_fused: in the correction's final V-cycle the last black half sweep
   of each level with leaf blocks adds the correction to the FP64 solution
   there, instead of a separate update launch after the cycle (on adaptive
@@ -14,8 +15,8 @@ Uniform 3D trees with 16^3 (512- and 256-lane kernels) and 8^3 blocks,
 adaptive trees with 16^3 and 8^3 blocks, an interface through cell centres,
 zero-flux faces, several right-hand sides, smoothing counts (1..3, 1..2),
 eager launches and graphs, V-cycles, FMG corrections and solves; where a
-fusion does not apply (red_preset on adaptive trees and FMG corrections)
-the settings run the same launches."""
+fusion does not apply (red_preset before FMG corrections) the settings run
+the same launches."""
 import numpy as np
 import pytest
 
@@ -32,6 +33,7 @@ CASES = {
     "electrodes_uniform": lambda: W.two_electrodes(max_level=4, uniform_level=4),
     "spheres_amr16": lambda: W.spheres(n_spheres=8, max_level=5, block_n=16, seed=12),
     "spheres_amr8": lambda: W.spheres(n_spheres=5, max_level=5, block_n=8, seed=9),
+    "electrodes_amr": lambda: W.two_electrodes(max_level=5, uniform_level=3),
 }
 
 
