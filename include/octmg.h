@@ -202,12 +202,13 @@ octmg_status octmg_state_get_launch(octmg_state s, octmg_launch_config *c);
  * solve stops with OCTMG_ERR_NOT_CONVERGED after max_cycles, or when the
  * residual ratio of successive cycles stays above 0.95 for 3 cycles.
  * graph_mode: 0 launches every kernel; 1 captures one cycle (with its
- * residual norm) in a HIP graph and replays it each cycle; 2 captures a
- * chunk of cycles (all max_cycles of them when that is at most 16, else 8),
- * each followed by a convergence test on the device that stops the rhs it
- * concerns (no stall test), and replays the chunk until no rhs runs (the
- * host reads the running flags between replays).  Results are identical in
- * all modes.  Graph
+ * residual norm) in a HIP graph and replays it each cycle; 2 runs the
+ * cycles as captured chunks, each cycle followed by a convergence test on
+ * the device that stops the rhs it concerns (no stall test): a first chunk
+ * of as many cycles as the state's previous solve took (on its first solve
+ * all max_cycles of them when that is at most 16, else 8), then chunks of
+ * one cycle until no rhs runs (the host reads the running flags between
+ * chunks).  Results are identical in all modes.  Graph
  * modes capture on `stream` (or an internal stream if NULL) and need the
  * fused levels off; graphs are cached per state and rebuilt when the
  * smoothing counts or fused levels change. */
@@ -384,8 +385,8 @@ octmg_status octmg_solve_noalloc(octmg_geom g, const double *rhs, const double *
  * block orders x {separate, separate in a per-cycle graph, cooperative
  * bottom up to 8 and to 64 blocks (3D)}, with the 512-thread variants on
  * every level, plus block order 0 {separate, per-cycle graph} with them on
- * none (3D), plus block order 0 with the whole solve captured as one graph
- * (graph_mode 2; opts.max_cycles cycles are captured) with the 512-thread
+ * none (3D), plus block order 0 with the solve replayed as captured chunks
+ * of cycles (graph_mode 2) with the 512-thread
  * variants on every level and (3D) on none), then keeps the fastest in the
  * state and returns it.  ms[i] (if not NULL, room for 16) receives the mean
  * wall time per solve of candidate i, *n_candidates their number.

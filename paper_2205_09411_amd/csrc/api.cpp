@@ -200,6 +200,7 @@ struct octmg_state_s {
     int prolong_fused = 1;                     // V-cycle prolongation fused with the next red half sweep (3D)
     int red_preset = 1;                        // mixed precision: first red half sweep inside the defect (3D)
     int update_fused = 1;                      // mixed precision: FP64 update inside the last black half sweep (3D)
+    int cycle_hint = 0;                        // cycles of the last solve (first chunk of graph_mode 2), 0: none
     int fused_top = 0;                         // highest fused level (0: none)
     int fused_grid64 = 0, fused_grid32 = 0;    // co-resident workgroups of the fused kernel
     SmallLevels<double> *d_small64 = nullptr;  // device copies of the fused level tables
@@ -1776,6 +1777,7 @@ static octmg_status graph_for(octmg_state s, long long key, hipStream_t st, F &&
 // cache key of a captured graph: what it was captured for, including the
 // number of grid rows of its launches
 static long long graph_key(int mode, int kind, int max_cycles, int zero_start, int n_launch) {
+    // (graph_mode 2 appends its chunk length: key * 128 + K)
     return ((((long long)mode * 8 + kind) * 128 + max_cycles) * 4 + zero_start) * 8192 + n_launch;
 }
 
@@ -1851,20 +1853,23 @@ static octmg_status solve_impl(octmg_state s, const octmg_solve_opts *o, hipStre
         }
         STCK(set_active(s, act, st));
         HIPCK(hipMemcpyAsync(s->d_thresh, th.data(), sizeof(double) * R, hipMemcpyHostToDevice, st));
-        // The cycles run as replays of one captured chunk of K cycles (all
-        // max_cycles of them when that is at most 16), each cycle followed by
-        // its convergence test; the host looks at the running flags after
-        // each replay and stops once none runs.  The cycles of a chunk after
-        // every rhs has stopped launch and exit at once.
-        const int K = o->max_cycles <= 16 ? o->max_cycles : 8;
+        // The cycles run as replays of captured chunks of cycles, each cycle
+        // followed by its convergence test; the host looks at the running
+        // flags after each chunk and stops once none runs.  The first chunk
+        // has as many cycles as the state's last solve took (else all
+        // max_cycles of them when that is at most 16, else 8), the later
+        // ones one cycle each.  The cycles of a chunk after every rhs has
+        // stopped launch and exit at once.
+        const int K1 = std::min(o->max_cycles, s->cycle_hint > 0 ? s->cycle_hint
+                                                                 : (o->max_cycles <= 16 ? o->max_cycles : 8));
         HIPCK(hipMemsetAsync(s->d_cbase, 0, sizeof(int), st));  // outside the graphs
         std::vector<int> act_after(R);
-        for (int launched = 0; launched < o->max_cycles; launched += K) {
+        for (int launched = 0, K = K1; launched < o->max_cycles; launched += K, K = 1) {
             const bool first = launched == 0;
             // the first chunk starts from the caller's iterate (an FMG's
             // first cycle without a guess when zero_start); later ones go on
             const long long key =
-                graph_key(2, o->cycle_kind, o->max_cycles, first ? (o->zero_start ? 1 : 0) : 2, s->n_launch);
+                graph_key(2, o->cycle_kind, o->max_cycles, first ? (o->zero_start ? 1 : 0) : 2, s->n_launch) * 128 + K;
             hipGraphExec_t exec = nullptr;
             STCK(graph_for(s, key, st, [&]() -> octmg_status {
                 for (int c = 0; c < K; c++) {
@@ -1989,6 +1994,8 @@ octmg_status octmg_solve(octmg_state s, const octmg_solve_opts *o, void *stream,
     PerRhs pr;
     octmg_status res = solve_impl(s, o, st, rep ? rep : &local, pr);
     std::string msg = g_last_error;
+    // the next solve's first graph chunk (graph_mode 2) covers as many cycles
+    s->cycle_hint = (rep ? rep : &local)->cycles;
     if (rep && (int)pr.r_final.size() == s->nrhs)
         for (int r = 0; r < s->nrhs; r++) {
             const bool finite = std::isfinite(pr.r_final[r]);

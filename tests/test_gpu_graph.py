@@ -178,3 +178,22 @@ def test_whole_solve_graph_in_chunks(max_cycles):
         assert ra.status == rb.status and ra.cycles == rb.cycles, (rtol, ra.cycles, rb.cycles)
         assert ra.r_final == rb.r_final
         assert np.array_equal(a, b), rtol
+
+
+def test_graph_chunk_from_previous_solve():
+    """Graph mode 2's first chunk has as many cycles as the state's previous
+    solve: too few (a looser rtol before a tighter one: one-cycle chunks
+    follow) and too many (a tighter rtol before a looser one: the extra
+    cycles exit at once) give the cycles, norms and bits of eager launches
+    on another state, for three rhs that converge at different cycles."""
+    print("graph mode 2 chunk from the previous solve", flush=True)
+    w = W.cylinder(max_level=3)
+    _, A = state(w, n_rhs=3)
+    _, B = state(w, n_rhs=3)
+    for rtol in (1e-5, 1e-11, 1e-5, 1e-8):
+        ra = A.solve(rtol=rtol, max_cycles=30, zero_start=True, graph_mode=0)
+        rb = B.solve(rtol=rtol, max_cycles=30, zero_start=True, graph_mode=2)
+        assert ra.cycles == rb.cycles and ra.r_final == rb.r_final, (rtol, ra.cycles, rb.cycles)
+        assert np.array_equal(ra.per_rhs["cycles"], rb.per_rhs["cycles"]), rtol
+        assert np.array_equal(ra.per_rhs["r_final"], rb.per_rhs["r_final"]), rtol
+        assert np.array_equal(A.get_solution(), B.get_solution()), rtol
