@@ -552,7 +552,9 @@ template <>
 hipError_t Engine<double>::sweep_update(int, const LV<double> &) { return hipErrorInvalidValue; }
 template <>
 hipError_t Engine<float>::sweep_update(int il, const LV<float> &v) {
-    const int keep = s->geom->tree.adaptive ? 1 : 0;
+    // below the finest level of an adaptive tree parent blocks and finer
+    // levels' refinement ghosts still read the black correction
+    const int keep = s->geom->tree.adaptive && il + 1 < (int)s->geom->L.size() ? 1 : 0;
     return launch_gs_half_update(Nb(il), v, lvT<float>(s, il - 1), lv64(s, il), keep, s->n_launch, st);
 }
 template <>

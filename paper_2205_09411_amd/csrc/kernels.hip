@@ -1316,11 +1316,12 @@ __global__ __launch_bounds__(NT) void k_gs_half3(LV<T> L, LV<T> Lc, int color) {
 // V-cycle, fused with the FP64 update phi += e of the level's leaf blocks
 // that follows the cycle (k_update): the black cells add their new values,
 // the red cells the values staged for the sweep, which it does not change.
-// keep = 0 (every block a leaf, no finer level): the black correction values
-// themselves are not stored, since the next defect overwrites the correction
-// on every leaf cell before anything reads it; keep = 1 (adaptive trees):
-// they are stored, parent blocks and finer levels' ghosts read them.  Same
-// FP64 bits as the half sweep followed by k_update.
+// keep = 0 (the finest level: every block a leaf, no finer level): the
+// black correction values themselves are not stored, since the next defect
+// overwrites the correction on every leaf cell before anything reads it;
+// keep = 1 (coarser levels of adaptive trees): they are stored, parent
+// blocks and finer levels' ghosts read them.  Same FP64 bits as the half
+// sweep followed by k_update.
 template <int N, int NT, bool V2>
 __global__ __launch_bounds__(NT) void k_gs_half3_update(LV<float> L, LV<float> Lc, LV<double> U, int keep) {
     __shared__ float tile[ColTile<N>::SIZE];
