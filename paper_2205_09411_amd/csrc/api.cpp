@@ -1997,7 +1997,9 @@ octmg_status octmg_solve(octmg_state s, const octmg_solve_opts *o, void *stream,
     octmg_status res = solve_impl(s, o, st, rep ? rep : &local, pr);
     std::string msg = g_last_error;
     // the next solve's first graph chunk (graph_mode 2) covers as many cycles
-    s->cycle_hint = (rep ? rep : &local)->cycles;
+    // as this one took, if it converged (else the default chunk: a solve cut
+    // off at max_cycles would make the next one launch that many)
+    s->cycle_hint = res == OCTMG_OK ? (rep ? rep : &local)->cycles : 0;
     if (rep && (int)pr.r_final.size() == s->nrhs)
         for (int r = 0; r < s->nrhs; r++) {
             const bool finite = std::isfinite(pr.r_final[r]);
