@@ -205,8 +205,8 @@ octmg_status octmg_state_get_launch(octmg_state s, octmg_launch_config *c);
  * residual norm) in a HIP graph and replays it each cycle; 2 runs the
  * cycles as captured chunks, each cycle followed by a convergence test on
  * the device that stops the rhs it concerns (no stall test): a first chunk
- * of as many cycles as the state's previous solve took (on its first solve
- * all max_cycles of them when that is at most 16, else 8), then chunks of
+ * of as many cycles as the state's previous solve took if that converged
+ * (else all max_cycles of them when that is at most 16, else 8), then chunks of
  * one cycle until no rhs runs (the host reads the running flags between
  * chunks).  Results are identical in all modes.  Graph
  * modes capture on `stream` (or an internal stream if NULL) and need the
