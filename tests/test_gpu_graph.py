@@ -185,7 +185,8 @@ def test_graph_chunk_from_previous_solve():
     solve: too few (a looser rtol before a tighter one: one-cycle chunks
     follow) and too many (a tighter rtol before a looser one: the extra
     cycles exit at once) give the cycles, norms and bits of eager launches
-    on another state, for three rhs that converge at different cycles."""
+    on another state, for three distinct rhs; a solve cut off at max_cycles
+    sets no hint."""
     print("graph mode 2 chunk from the previous solve", flush=True)
     w = W.cylinder(max_level=3)
     _, A = state(w, n_rhs=3)
@@ -197,3 +198,13 @@ def test_graph_chunk_from_previous_solve():
         assert np.array_equal(ra.per_rhs["cycles"], rb.per_rhs["cycles"]), rtol
         assert np.array_equal(ra.per_rhs["r_final"], rb.per_rhs["r_final"]), rtol
         assert np.array_equal(A.get_solution(), B.get_solution()), rtol
+    # a solve cut off at max_cycles leaves no hint: the next one starts with
+    # the default chunk
+    ra = A.solve(rtol=1e-11, max_cycles=3, zero_start=True, graph_mode=0, raise_on_fail=False)
+    rb = B.solve(rtol=1e-11, max_cycles=3, zero_start=True, graph_mode=2, raise_on_fail=False)
+    assert ra.status == rb.status == octmg.ERR_NOT_CONVERGED and ra.cycles == rb.cycles == 3
+    assert ra.r_final == rb.r_final and np.array_equal(A.get_solution(), B.get_solution())
+    ra = A.solve(rtol=1e-8, max_cycles=30, zero_start=True, graph_mode=0)
+    rb = B.solve(rtol=1e-8, max_cycles=30, zero_start=True, graph_mode=2)
+    assert ra.cycles == rb.cycles and ra.r_final == rb.r_final
+    assert np.array_equal(A.get_solution(), B.get_solution())
