@@ -76,9 +76,12 @@ def test_fusion_bitwise(name, option):
 
 
 @pytest.mark.parametrize("option", ["red_preset", "update_fused"])
-def test_fusion_bitwise_256_lanes(option):
-    """16^3 blocks with the 256-lane kernels on every level."""
-    w = CASES["mms3d_b16_64"]()
+@pytest.mark.parametrize("name", ["mms3d_b16_64", "spheres_amr16"])
+def test_fusion_bitwise_256_lanes(name, option):
+    """16^3 blocks with the 256-lane kernels on every level (uniform and
+    adaptive trees)."""
+    print("mixed fusion, 256 lanes", option, name, flush=True)
+    w = CASES[name]()
     G = octmg.Geometry(w.geom)
     compare(w, G, {"pair_max_blocks": 0}, {"pair_max_blocks": 0, option: 0})
 
