@@ -90,3 +90,18 @@ def test_both_fusions_off():
     w = CASES["cylinder_64"]()
     G = octmg.Geometry(w.geom)
     compare(w, G, {}, {"red_preset": 0, "update_fused": 0})
+
+
+def test_fusion_options_validated():
+    """The two options take 0 or 1; anything else is refused and leaves the
+    configuration as it was."""
+    w = CASES["mms3d_b16_64"]()
+    G = octmg.Geometry(w.geom)
+    S = octmg.State(G, 1, octmg.MIXED)
+    before = S.get_launch()
+    for bad in ({"red_preset": 2}, {"update_fused": -1}, {"update_fused": 2}):
+        with pytest.raises(octmg.OctmgError):
+            S.set_launch(**bad)
+        assert S.get_launch() == before, bad
+    S.set_launch(update_fused=0)
+    assert S.get_launch()["update_fused"] == 0
