@@ -757,6 +757,9 @@ def main():
         "solve_ms_p10_p50_p90": [round(float(np.percentile(solve_ms, q)), 3) for q in (10, 50, 90)],
         "launch": {"chosen": tuned, "autotune_ms_per_solve": [round(v, 3) for v in cand_ms]},
         "cycles_per_solve": int(np.mean([r.cycles for r in reps])),
+        # a V-cycle with its residual norm: the solve's time over its cycles
+        # (the residual of phi = 0 that the test starts from is cached)
+        "ms_per_vcycle": round(dt / sum(r.cycles for r in reps) * 1e3, 4),
         "final_rel_residual": max(r.r_final / r.r0 for r in reps),
         "max_err_vs_exact": err,
         "sweep_kernel_mcups": round(ncell / 2 / (mean_ms * 1e-3) / 1e6, 1),
