@@ -305,6 +305,28 @@ def test_full_size_mms3d_256(orc):
     assert abs(S.residual_norm(phi_zero=True)[0] - r0) <= 1e-12 * r0
 
 
+def test_full_size_solve_in_every_graph_mode():
+    """The 256^3 benchmark solve to 1e-10 in the launch forms the autotuner
+    picks from: eager launches, one captured cycle per cycle, and captured
+    chunks (twice, the second sized by the first) give the same cycles,
+    residuals and solution bits, in FP64 and mixed precision."""
+    w = W.mms3d(max_level=5, block_n=16)
+    print("full size 256^3 in every graph mode", flush=True)
+    G = octmg.Geometry(w.geom)
+    xyz, _ = G.leaf_coords()
+    for prec in (octmg.FP64, octmg.MIXED):
+        S = octmg.State(G, 1, prec)
+        S.set_boundary(w.iface_value(G.iface_points()), w.domain_value(G.domain_points()))
+        S.set_rhs(w.rhs(xyz))
+        ref = S.solve(rtol=1e-10, max_cycles=40, zero_start=True, graph_mode=0)
+        a = S.get_solution()
+        for gm in (1, 2, 2):
+            r = S.solve(rtol=1e-10, max_cycles=40, zero_start=True, graph_mode=gm)
+            assert r.cycles == ref.cycles and r.r_final == ref.r_final, (prec, gm)
+            assert np.array_equal(S.get_solution(), a), (prec, gm)
+        S.close()
+
+
 @pytest.mark.parametrize("name", ["mms3d_b16_64", "spheres_amr16", "cylinder_64", "sphere_f1_3d"])
 def test_fused_bottom_equals_separate_launches(name):
     """The bottom of the V-cycle run in one cooperative launch gives the same
