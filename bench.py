@@ -189,8 +189,9 @@ def leg_batched(stream, rtol, reps=3, n_single=4):
         dt, rep = timed_solves(S, reps, stream, rtol=rtol, max_cycles=mc, graph_mode=tuned["graph_mode"])
         sols[name] = S.get_solution()
         r0s[name] = rep.per_rhs["r0"].copy()
-        # candidates 0..13 launch cycle by cycle, the last two are the whole
-        # solve as one captured graph (512- and 256-thread kernels)
+        # candidates 0..13 launch cycle by cycle, the last two run the solve
+        # as captured chunks of cycles (512- and 256-thread kernels): one
+        # graph launch once the first chunk is sized by the previous solve
         one = min(cand_ms[-2:])
         other = min(cand_ms[:-2])
         out[name] = {"batch_ms": round(dt * 1e3, 3), "rhs_solves_per_s": round(64 / dt, 2), "cycles": rep.cycles,
