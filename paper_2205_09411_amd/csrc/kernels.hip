@@ -2311,7 +2311,8 @@ __device__ __forceinline__ void prolong_gs3_body(const LV<T> &L, const LV<T> &Lc
             }
         }
     }
-    load_cells<T, PER, NT, V2, true>(L.g + (long long)rhs * L.fstride + base, t, gv);
+    // (non-temporal in FP64 only, as in the sweep)
+    load_cells<T, PER, NT, V2, sizeof(T) == 8>(L.g + (long long)rhs * L.fstride + base, t, gv);
 #pragma unroll
     for (int m = 0; m < PER; m++) ri[m] = mo >= 0 ? L.map[mo + cell_of<NT, V2>(t, m)] : -1;
     __syncthreads();
